@@ -1,0 +1,385 @@
+"""Adaptive multigrid for A = D^H D, written out step by step in FP64 (oracle).
+
+Every function cites the passage of the paper it follows.  The operators are scipy
+sparse matrices, so each level's operator is literally the matrix the paper
+writes down: the fine A = D^H D (Introduction), the coarse A^(l+1) = P^H A^(l) P
+(Eq. 2).  Nothing here is blocked, fused or reordered for speed.
+
+Readings of the paper taken here (the paper is silent or garbled at these points):
+
+* Eq. (3) is printed with "+ R A R^dagger"; only "- R A R^dagger" reproduces the
+  five V-cycle steps listed above it, so the V-cycle follows the steps.
+* Step 5 of the V-cycle is read as x <- x + R (b - A x) (the correction is added).
+* The relaxation used inside the setup (Eq. 4) is the solve smoother itself:
+  the frozen minimal-residual polynomial, so I - R A = prod_k (I - c_k A).
+* An aggregate is all degrees of freedom of a bx x bt block of sites (4x4 in the
+  paper), so a coarse site carries M = Nv degrees of freedom.
+* The setup's V-cycle on level l is the two-level cycle on the current P with the
+  coarse system solved exactly (sparse direct solve here).
+
+Vectors at level l are complex128, index ((t*lx_l + x)*dof_l + d).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+class SetupError(RuntimeError):
+    """Raised when an aggregate's candidate vectors are linearly dependent."""
+
+
+def dot(a: np.ndarray, b: np.ndarray) -> complex:
+    """<a, b> = sum conj(a_i) b_i."""
+    return complex(np.vdot(a, b))
+
+
+def norm(a: np.ndarray) -> float:
+    return float(np.linalg.norm(a))
+
+
+# ---------------------------------------------------------------------------
+# Smoother (Results section: degree-nu polynomial from nu under-relaxed minimal
+# residual steps, coefficients then frozen, so R = R^dagger).
+# ---------------------------------------------------------------------------
+
+def mr_coefficients(A, b: np.ndarray, nu: int, omega: float) -> List[float]:
+    """Run nu minimal-residual steps on A x = b from x = 0, damping each by omega.
+
+    The MR step length is alpha = <A r, r> / <A r, A r> (real for Hermitian A); the
+    frozen coefficient is c_k = omega * alpha_k.
+    """
+    r = np.array(b, dtype=np.complex128, copy=True)
+    coefs = []
+    for _ in range(nu):
+        q = A @ r
+        alpha = dot(q, r).real / dot(q, q).real
+        ck = omega * alpha
+        coefs.append(ck)
+        r = r - ck * q
+    return coefs
+
+
+def smoother_apply(A, coefs: Sequence[float], b: np.ndarray) -> np.ndarray:
+    """R b for the frozen polynomial: the nu MR updates replayed with fixed c_k from x = 0.
+
+    x_k = x_{k-1} + c_k r_{k-1},  r_k = r_{k-1} - c_k A r_{k-1}.
+    """
+    x = np.zeros_like(b)
+    r = np.array(b, copy=True)
+    for k, ck in enumerate(coefs):
+        x = x + ck * r
+        if k + 1 < len(coefs):
+            r = r - ck * (A @ r)
+    return x
+
+
+def smoother_matrix(A_dense: np.ndarray, coefs: Sequence[float]) -> np.ndarray:
+    """Dense R, built from the identity I - R A = prod_k (I - c_k A) (test helper)."""
+    n = A_dense.shape[0]
+    E = np.eye(n, dtype=np.complex128)
+    for ck in coefs:
+        E = (np.eye(n) - ck * A_dense) @ E
+    # R A = I - E  =>  R = (I - E) A^{-1}
+    return np.linalg.solve(A_dense.T, (np.eye(n) - E).T).T
+
+
+# ---------------------------------------------------------------------------
+# Aggregates S_j and the prolongator (Adaptive Multigrid section, Eqs. 5 and the
+# M-vector form that follows it).
+# ---------------------------------------------------------------------------
+
+def aggregate_gather(shape, block) -> np.ndarray:
+    """G[J, i]: fine-vector index of the i-th variable of aggregate J.
+
+    shape = (lx, lt, dof) of the fine side, block = (bx, bt).  Aggregate J =
+    Jt*(lx/bx) + Jx holds the sites x in [Jx*bx, Jx*bx+bx), t in [Jt*bt, Jt*bt+bt)
+    with all dof components; within it i = ((t % bt)*bx + (x % bx))*dof + d.
+    """
+    lx, lt, dof = shape
+    bx, bt = block
+    if lx % bx or lt % bt:
+        raise ValueError("lattice extent not divisible by the block extent")
+    cx, ct = lx // bx, lt // bt
+    Jt, Jx, ty, tx, d = np.meshgrid(
+        np.arange(ct), np.arange(cx), np.arange(bt), np.arange(bx), np.arange(dof), indexing="ij"
+    )
+    fine = ((Jt * bt + ty) * lx + (Jx * bx + tx)) * dof + d
+    return fine.reshape(ct * cx, bt * bx * dof)
+
+
+def block_gram_schmidt(vectors: np.ndarray, gather: np.ndarray, tol: float = 1e-12) -> np.ndarray:
+    """Block-orthonormalise candidate vectors (Adaptive Multigrid section).
+
+    vectors[k] is the k-th near-null candidate on the fine side.  For every
+    aggregate J the restrictions v_k|_J are taken in order, made orthogonal to the
+    earlier ones (modified Gram-Schmidt, two passes) and normalised to 1.
+    Returns U[J, k, i], the columns of P on aggregate J.
+    """
+    nv = vectors.shape[0]
+    nJ, nagg = gather.shape
+    U = np.zeros((nJ, nv, nagg), dtype=np.complex128)
+    # The same arithmetic is done for every aggregate, so the aggregates form the
+    # leading array axis; the loops over k and j are the Gram-Schmidt order itself.
+    for k in range(nv):
+        w = vectors[k][gather]                                  # [J, i]
+        ref = np.linalg.norm(w, axis=1)
+        for _ in range(2):
+            for j in range(k):
+                proj = np.sum(np.conj(U[:, j, :]) * w, axis=1)  # <u_j, w> per aggregate
+                w = w - proj[:, None] * U[:, j, :]
+        nw = np.linalg.norm(w, axis=1)
+        bad = ~(nw > tol * ref)
+        if np.any(bad):
+            raise SetupError(f"aggregate {int(np.argmax(bad))}: candidate {k} is linearly dependent")
+        U[:, k, :] = w / nw[:, None]
+    return U
+
+
+def prolongator(U: np.ndarray, gather: np.ndarray, n_fine: int) -> sp.csr_matrix:
+    """P with P[gather[J, i], J*Nv + k] = U[J, k, i] (coarse index (K*Nv + k))."""
+    nJ, nv, nagg = U.shape
+    rows = np.broadcast_to(gather[:, None, :], (nJ, nv, nagg)).ravel()
+    cols = np.broadcast_to((np.arange(nJ)[:, None] * nv + np.arange(nv)[None, :])[:, :, None],
+                           (nJ, nv, nagg)).ravel()
+    return sp.coo_matrix((U.ravel(), (rows, cols)), shape=(n_fine, nJ * nv)).tocsr()
+
+
+def galerkin(A, P) -> sp.csr_matrix:
+    """Eq. (2): A^(l+1) = P^H A^(l) P."""
+    return (P.conj().T @ (A @ P)).tocsr()
+
+
+# ---------------------------------------------------------------------------
+# Krylov solvers (Multigrid section: the V-cycle preconditions conjugate gradients).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SolveInfo:
+    converged: bool
+    iterations: int
+    fine_applies: int          # applications of A on the level solved (2 D/D^H each)
+    relres: float              # true relative residual ||rhs - A x|| / ||rhs||
+    history: List[float] = field(default_factory=list)
+
+
+def cg(A, rhs: np.ndarray, tol: float, maxiter: int = 100000) -> (np.ndarray, SolveInfo):
+    """Plain conjugate gradients on HPD A from x = 0, stopping on the true residual."""
+    return pcg(A, rhs, None, tol, maxiter)
+
+
+def pcg(A, rhs: np.ndarray, precond: Optional[Callable], tol: float, maxiter: int = 100000):
+    """Preconditioned CG, z = M r with M = precond (identity when None).
+
+    Stops when the recursive residual reaches tol and the recomputed true residual
+    ||rhs - A x|| / ||rhs|| also does; otherwise the residual is replaced by the
+    true one and the iteration continues.
+    """
+    bnorm = norm(rhs)
+    x = np.zeros_like(rhs)
+    if bnorm == 0.0:
+        return x, SolveInfo(True, 0, 0, 0.0)
+    applies = 0
+    r = np.array(rhs, copy=True)
+    z = precond(r) if precond else r.copy()
+    p = z.copy()
+    rz = dot(r, z).real
+    hist = []
+    for it in range(1, maxiter + 1):
+        q = A @ p
+        applies += 1
+        pq = dot(p, q).real
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rel = norm(r) / bnorm
+        hist.append(rel)
+        if rel <= tol:
+            rt = rhs - A @ x
+            applies += 1
+            true_rel = norm(rt) / bnorm
+            if true_rel <= tol:
+                return x, SolveInfo(True, it, applies, true_rel, hist)
+            r = rt
+        z = precond(r) if precond else r.copy()
+        rz_new = dot(r, z).real
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    true_rel = norm(rhs - A @ x) / bnorm
+    return x, SolveInfo(False, maxiter, applies + 1, true_rel, hist)
+
+
+# ---------------------------------------------------------------------------
+# Hierarchy and V-cycle (Multigrid section, steps 1-5; Eq. 3 with the sign reading).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Level:
+    A: sp.csr_matrix
+    shape: tuple                    # (lx, lt, dof)
+    coefs: List[float] = field(default_factory=list)
+    block: Optional[tuple] = None   # (bx, bt) towards the next level
+    U: Optional[np.ndarray] = None  # [J, k, i] prolongator columns
+    P: Optional[sp.csr_matrix] = None
+    gather: Optional[np.ndarray] = None
+
+
+@dataclass
+class Hierarchy:
+    levels: List[Level]
+    coarsest: str = "cholesky"      # "cholesky" (exact) or "cg"
+    coarsest_tol: float = 1e-12
+    _chol: object = None
+
+    def factor_coarsest(self):
+        if self.coarsest == "cholesky":
+            Ad = self.levels[-1].A.toarray()
+            self._chol = sla.cho_factor(Ad, lower=True)
+        return self
+
+    def coarse_solve(self, b: np.ndarray) -> np.ndarray:
+        """Exact solve on the coarsest level (Results: 'solved exactly')."""
+        A = self.levels[-1].A
+        if self.coarsest == "cholesky":
+            if self._chol is None:
+                self.factor_coarsest()
+            return sla.cho_solve(self._chol, b)
+        x, _ = cg(A, b, self.coarsest_tol)
+        return x
+
+
+def vcycle(h: Hierarchy, l: int, b: np.ndarray, counter: Optional[list] = None) -> np.ndarray:
+    """One V-cycle V^(l) b, following steps 1-5 of the Multigrid section.
+
+    1. x = R^H b                       (pre-relaxation; R^H = R here)
+    2. r_c = P^H (b - A x)             (restrict the residual)
+    3. e = V^(l+1) r_c                 (recurse; the coarsest level is exact)
+    4. x = x + P e                     (coarse-grid correction)
+    5. x = x + R (b - A x)             (post-relaxation)
+    """
+    lev = h.levels[l]
+    if l == len(h.levels) - 1:
+        return h.coarse_solve(b)
+    A = lev.A
+    x = smoother_apply(A, lev.coefs, b)
+    rc = lev.P.conj().T @ (b - A @ x)
+    e = vcycle(h, l + 1, rc, counter)
+    x = x + lev.P @ e
+    x = x + smoother_apply(A, lev.coefs, b - A @ x)
+    if counter is not None and l == 0:
+        counter[0] += 1
+    return x
+
+
+def mg_cg(h: Hierarchy, rhs: np.ndarray, tol: float, maxiter: int = 10000):
+    """MG-CG: CG on the fine A with the V-cycle as preconditioner (Results section)."""
+    return pcg(h.levels[0].A, rhs, lambda r: vcycle(h, 0, r), tol, maxiter)
+
+
+# ---------------------------------------------------------------------------
+# Building a hierarchy.
+# ---------------------------------------------------------------------------
+
+def coarsen(level: Level, vectors: np.ndarray, block) -> (Level, Level):
+    """Given candidate vectors on `level`, form P (block Gram-Schmidt) and A_c = P^H A P."""
+    gather = aggregate_gather(level.shape, block)
+    U = block_gram_schmidt(vectors, gather)
+    P = prolongator(U, gather, level.A.shape[0])
+    level.block, level.U, level.P, level.gather = tuple(block), U, P, gather
+    lx, lt, _ = level.shape
+    nv = vectors.shape[0]
+    nxt = Level(A=galerkin(level.A, P), shape=(lx // block[0], lt // block[1], nv))
+    return level, nxt
+
+
+def hierarchy_from_vectors(A, shape, blocks, vectors_per_level, calib_per_level, nu, omega,
+                           coarsest="cholesky", coarsest_tol=1e-12) -> Hierarchy:
+    """Hierarchy from given near-null vectors (no adaptive iteration).
+
+    vectors_per_level[l] is [Nv_l, n_l]; calib_per_level[l] starts the MR
+    calibration of level l.
+    """
+    levels = [Level(A=A, shape=tuple(shape))]
+    for l, block in enumerate(blocks):
+        cur = levels[-1]
+        cur.coefs = mr_coefficients(cur.A, calib_per_level[l], nu, omega)
+        cur, nxt = coarsen(cur, np.asarray(vectors_per_level[l]), block)
+        levels.append(nxt)
+    return Hierarchy(levels, coarsest, coarsest_tol).factor_coarsest()
+
+
+def _two_level_exact(level: Level, Ac) -> Callable:
+    """Two-level V-cycle on `level` with the coarse system solved by a sparse direct solve."""
+    # Symmetric fill-reducing ordering; Ac is Hermitian positive definite.
+    lu = spla.splu(Ac.tocsc(), permc_spec="MMD_AT_PLUS_A", options=dict(SymmetricMode=True))
+    A, P, c = level.A, level.P, level.coefs
+
+    def V(b):
+        x = smoother_apply(A, c, b)
+        e = lu.solve(P.conj().T @ (b - A @ x))
+        x = x + P @ e
+        return x + smoother_apply(A, c, b - A @ x)
+
+    return V
+
+
+def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_iters: int,
+                   coarsest="cholesky", coarsest_tol=1e-12, log: Optional[list] = None) -> Hierarchy:
+    """Adaptive setup (Adaptive Multigrid section), level by level.
+
+    For each coarsening l with random starts randoms[l] ([1 + Nv, n_l]):
+      * freeze the smoother from MR steps on randoms[l][0];
+      * candidate 1: relax A e = 0 from randoms[l][1], e <- (I - R A) e, setup_iters
+        times (Eq. 4 with the frozen polynomial), renormalising each pass;
+      * candidates k = 2..Nv: from randoms[l][k], apply the current two-level V-cycle
+        as an error propagator, e <- (I - V A) e, setup_iters times; the surviving
+        error is restricted to the aggregates, orthonormalised against the earlier
+        vectors and appended, and A_c is rebuilt;
+      * the finished A_c is the next level's operator (the procedure recurses).
+    """
+    levels = [Level(A=A, shape=tuple(shape))]
+    for l, block in enumerate(blocks):
+        cur = levels[-1]
+        R = randoms[l]
+        cur.coefs = mr_coefficients(cur.A, R[0], nu, omega)
+        e = np.array(R[1], copy=True)
+        for _ in range(setup_iters):
+            e = e - smoother_apply(cur.A, cur.coefs, cur.A @ e)
+            e = e / norm(e)
+        vecs = [e]
+        cur, nxt = coarsen(cur, np.array(vecs), block)
+        for k in range(1, nvs[l]):
+            V = _two_level_exact(cur, nxt.A)
+            e = np.array(R[1 + k], copy=True)
+            for _ in range(setup_iters):
+                e = e - V(cur.A @ e)
+                e = e / norm(e)
+            vecs.append(e)
+            cur, nxt = coarsen(cur, np.array(vecs), block)
+        if log is not None:
+            log.append({"level": l, "coefs": list(cur.coefs)})
+        levels.append(nxt)
+    return Hierarchy(levels, coarsest, coarsest_tol).factor_coarsest()
+
+
+def set_mass(h: Hierarchy, A_fine, calib_per_level, nu: int, omega: float) -> Hierarchy:
+    """Reuse the prolongators at a new mass (Results: setup at the lightest mass,
+    vectors reused for heavier masses): rebuild every A^(l) by Eq. (2) and
+    recalibrate the smoothers."""
+    levels = []
+    A = A_fine
+    for l, lev in enumerate(h.levels):
+        new = Level(A=A, shape=lev.shape, block=lev.block, U=lev.U, P=lev.P, gather=lev.gather)
+        if lev.P is not None:
+            new.coefs = mr_coefficients(A, calib_per_level[l], nu, omega)
+            A = galerkin(A, lev.P)
+        levels.append(new)
+    return Hierarchy(levels, h.coarsest, h.coarsest_tol).factor_coarsest()
