@@ -1,0 +1,203 @@
+/*
+ * smg.h -- adaptive multigrid for the 2D U(1) Wilson-Dirac normal equations on MI355X.
+ *
+ * C ABI of libsmg.so.  The library solves the normal equations
+ *
+ *     A x = rhs,   A = D^H D,
+ *
+ * of the Wilson-Dirac operator D (Introduction of Brannick, Brower, Clark, Osborn,
+ * Rebbi, "Adaptive Multigrid Algorithm for the QCD Dirac-Wilson Operator",
+ * arXiv:0710.3612) with conjugate gradients preconditioned by an adaptive
+ * multigrid V-cycle (Multigrid and Adaptive Multigrid sections, Eqs. 2-5).
+ * A caller who wants D psi = chi passes rhs = D^H chi (formed with smg_apply_D,
+ * dagger = 1) and gets psi = x.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice     lx * lt sites, site s = t*lx + x, periodic; direction mu = 0 is x,
+ *             mu = 1 is t.  gamma_x = sigma1, gamma_t = sigma2 (2 spins per site).
+ * Operator    D psi_s = (2 + m) psi_s - 1/2 sum_mu [ (1 - gamma_mu) U_s^mu psi_{s+mu}
+ *                        + (1 + gamma_mu) conj(U_{s-mu}^mu) psi_{s-mu} ].
+ *             The diagonal is (d + m) with d = 2 (standard Wilson normalisation: the
+ *             free operator at zero momentum is m); the paper prints (2d + m),
+ *             which is this operator at mass m + 2.
+ * Fermion BC  periodic in x; antiperiodic in t when params.t_antiperiodic != 0.
+ * Vectors     complex128, real and imaginary parts interleaved.  A batch of
+ *             nrhs fine vectors is [nrhs][lt][lx][2]; a batch of vectors on
+ *             multigrid level l >= 1 is [nrhs][lt_l][lx_l][nv_{l-1}].
+ * Gauge       complex128 [2][lt][lx]: gauge[mu][t][x] = U_{(x,t)}^mu, |U| = 1.
+ * Pointers    "device" pointers are HIP device memory of the current device
+ *             (for example the data pointer of a torch CUDA tensor); "host"
+ *             pointers are ordinary host memory.  The caller owns every pointer
+ *             it passes; the library never frees or retains them beyond the call.
+ * Streams     `stream` is a hipStream_t (NULL = the null stream).  Everything is
+ *             enqueued on it.  Calls marked ASYNC return before the work is done;
+ *             all other calls synchronise the stream before returning.
+ *             One handle may be used by one stream at a time.
+ * Errors      every int-returning call returns SMG_OK (0), a negative error code
+ *             or SMG_NOTCONV (+1, a warning).  smg_strerror() names a code and
+ *             smg_last_error() describes the most recent failure of this thread.
+ *             On error the outputs are unspecified and the handle stays valid.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMG_MAXLEV 6
+
+enum {
+  SMG_OK = 0,
+  SMG_NOTCONV = 1,      /* solve stopped at maxiter; x holds the last iterate */
+  SMG_EINVAL = -1,      /* invalid argument or parameter */
+  SMG_ESHAPE = -2,      /* lattice extents not divisible by the block extents */
+  SMG_ENOMEM = -3,      /* device allocation failed */
+  SMG_EDEVICE = -4,     /* a HIP runtime call failed */
+  SMG_EBREAKDOWN = -5,  /* NaN/Inf, or <p, A p> <= 0 in a Krylov iteration */
+  SMG_ESETUP = -6       /* degenerate aggregate in Gram-Schmidt, or coarsest factorisation failed */
+};
+
+enum { SMG_COARSEST_DIRECT = 0, SMG_COARSEST_CG = 1 };
+enum { SMG_FP64 = 0, SMG_MIXED = 1 };
+
+typedef struct smg_ctx* smg_handle;
+
+typedef struct {
+  int32_t lx, lt;                 /* fine extents, even, divisible by the product of blocks */
+  double mass;                    /* m of the operator above */
+  int32_t levels;                 /* L >= 1 grid levels; 1 = no coarsening (plain CG) */
+  int32_t block[SMG_MAXLEV][2];   /* aggregate extents (bx, bt) of coarsening l -> l+1 */
+  int32_t nv[SMG_MAXLEV];         /* near-null vectors of coarsening l (the paper's M) */
+  int32_t setup_iters;            /* relaxation / V-cycle passes per candidate vector */
+  int32_t smoother_steps;         /* nu: degree of the frozen minimal-residual polynomial */
+  double smoother_omega;          /* under-relaxation of the MR steps (paper: 0.8) */
+  int32_t t_antiperiodic;         /* 1: antiperiodic fermion BC in t */
+  int32_t coarsest;               /* SMG_COARSEST_DIRECT (dense inverse) or SMG_COARSEST_CG */
+  double coarsest_tol;            /* relative residual of the coarsest CG (and setup cycles) */
+  int32_t coarsest_maxiter;       /* iteration cap of every coarsest CG */
+  double inner_tol;               /* mixed precision: relative residual of each inner FP32 solve */
+  uint64_t seed;                  /* random starts of the setup when none are passed in */
+} smg_params;
+
+typedef struct {
+  int32_t status;                 /* SMG_OK or SMG_NOTCONV for this right-hand side */
+  int32_t iterations;             /* outer Krylov iterations (summed over refinements) */
+  int32_t refinements;            /* defect-correction cycles (1 for SMG_FP64) */
+  int32_t vcycles;                /* V-cycles applied */
+  int64_t fine_applies;           /* applications of A on the fine lattice (2 of D/D^H each) */
+  double true_relres;             /* ||rhs - A x|| / ||rhs|| recomputed in FP64 at exit */
+  double seconds;                 /* wall time of the whole call */
+} smg_stats;
+
+/* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
+ * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
+ * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1. */
+void smg_default_params(smg_params* p);
+
+/* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
+ * gauge: device, complex128 [2][lt][lx] (copied; not retained).
+ * randoms: device or NULL.  When given, the random starts of every coarsening,
+ *   concatenated over l = 0..levels-2, each block complex128 [1 + nv[l]][n_l] with
+ *   n_l the vector length of level l: row 0 starts the smoother calibration and
+ *   rows 1..nv[l] start the candidate vectors.  When NULL they are drawn from
+ *   params.seed by the library.
+ * On success *out is a new handle owning all device memory of the hierarchy.
+ * Errors: SMG_EINVAL, SMG_ESHAPE, SMG_ENOMEM, SMG_EDEVICE, SMG_ESETUP. */
+int smg_setup(const double* gauge, const smg_params* params, const double* randoms,
+              void* stream, smg_handle* out);
+
+/* Hierarchy from given near-null vectors, skipping the adaptive iteration (block
+ * Gram-Schmidt of the Adaptive Multigrid section, then Eq. 2 on every level).
+ * vectors: device, concatenated over coarsenings, block l complex128 [nv[l]][n_l].
+ * calib: device, concatenated over coarsenings, block l complex128 [n_l]; starts
+ *   the smoother calibration of level l.
+ * Errors as smg_setup. */
+int smg_setup_from_vectors(const double* gauge, const smg_params* params, const double* vectors,
+                           const double* calib, void* stream, smg_handle* out);
+
+/* Change the mass, reusing the prolongators (Results: the setup is done at the
+ * lightest mass and its vectors are reused for heavier masses).  Rebuilds every
+ * coarse operator by Eq. 2 and recalibrates the smoothers from the stored
+ * calibration starts.  Errors: SMG_EINVAL, SMG_EDEVICE. */
+int smg_set_mass(smg_handle h, double mass, void* stream);
+
+/* y = D x (dagger = 0) or y = D^H x (dagger = 1) on the fine lattice (Introduction).
+ * x, y: device, complex128 [nrhs][lt][lx][2], must not overlap.  ASYNC.
+ * Errors: SMG_EINVAL. */
+int smg_apply_D(smg_handle h, const double* x, double* y, int32_t nrhs, int32_t dagger, void* stream);
+
+/* y = A x = D^H D x on the fine lattice (the operator of the normal equations).
+ * x, y: device, complex128 [nrhs][lt][lx][2], must not overlap.  ASYNC. */
+int smg_apply_A(smg_handle h, const double* x, double* y, int32_t nrhs, void* stream);
+
+/* y = A^(l) x on level l (0 = fine A; l >= 1 the Galerkin operator of Eq. 2).
+ * x, y: device, complex128 level-l batches, must not overlap.  ASYNC. */
+int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
+                    void* stream);
+
+/* y = P^H x: restriction from level l to level l+1 (V-cycle step 2).  ASYNC. */
+int smg_restrict(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
+                 void* stream);
+
+/* y = P x: prolongation from level l+1 to level l (V-cycle step 4).  ASYNC. */
+int smg_prolong(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
+                void* stream);
+
+/* x = R b on level l < levels-1: the frozen minimal-residual polynomial smoother
+ * (Results section; R = R^H).  ASYNC. */
+int smg_smooth(smg_handle h, int32_t level, const double* b, double* x, int32_t nrhs,
+               void* stream);
+
+/* x = V b, one V-cycle from the finest level (Multigrid section, steps 1-5; Eq. 3
+ * with the sign of its R A R^H term taken from those steps).  FP64.  ASYNC. */
+int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream);
+
+/* Solve A x = rhs for nrhs independent right-hand sides with MG-CG (Results
+ * section).  precision SMG_FP64: FP64 throughout.  SMG_MIXED: FP32 operators,
+ * smoother and coarse levels inside FP64 defect correction (the true residual and
+ * the solution update are FP64; Gram-Schmidt and the coarsest solve stay FP64).
+ * rhs, x: device complex128 [nrhs][lt][lx][2]; x is overwritten (start from 0).
+ * stats: host array of nrhs entries or NULL.
+ * Returns SMG_OK when every column reached tol, SMG_NOTCONV when some did not,
+ * SMG_EBREAKDOWN on NaN/Inf or loss of positive definiteness. */
+int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol,
+              int32_t maxiter, int32_t precision, void* stream, smg_stats* stats);
+
+/* Plain CG on the fine A (the paper's comparison solver).  Arguments as smg_solve. */
+int smg_cg(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol, int32_t maxiter,
+           void* stream, smg_stats* stats);
+
+/* Shape of level l: extents and degrees of freedom per site. */
+int smg_level_info(smg_handle h, int32_t level, int32_t* lx, int32_t* lt, int32_t* dof);
+
+/* Copy out the prolongator of coarsening l: device complex128 [J][k][i] with J the
+ * coarse site, k < nv[l] the vector and i = ((t%bt)*bx + x%bx)*dof_l + d the
+ * variable inside the aggregate.  Synchronous. */
+int smg_get_prolongator(smg_handle h, int32_t level, double* out, void* stream);
+
+/* Copy out the Galerkin operator of level l >= 1 as 9 link blocks per coarse site:
+ * device complex128 [K][9][nc][nc], block index (dt+1)*3 + (dx+1) for the
+ * neighbour K + (dx, dt), row = output component: (A v)_K = sum_D L[K][D] v_{K+D}.
+ * Synchronous. */
+int smg_get_coarse_links(smg_handle h, int32_t level, double* out, void* stream);
+
+/* Host copy of the nu smoother coefficients c_k of level l. */
+int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out);
+
+/* Device bytes held by the handle. */
+int smg_memory_bytes(smg_handle h, size_t* bytes);
+
+void smg_destroy(smg_handle h);
+const char* smg_strerror(int code);
+const char* smg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMG_H */

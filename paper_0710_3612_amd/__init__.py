@@ -1,0 +1,350 @@
+"""Adaptive multigrid for the 2D U(1) Wilson-Dirac normal equations on MI355X.
+
+Thin Python binding of ``libsmg.so`` (declared in ``include/smg.h``).  Every
+numerical step runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch supplies device memory and streams: vectors are complex128
+CUDA tensors whose data pointers are handed to the C ABI.
+
+Method: Brannick, Brower, Clark, Osborn and Rebbi, "Adaptive Multigrid Algorithm
+for the QCD Dirac-Wilson Operator", arXiv:0710.3612 (Multigrid and Adaptive
+Multigrid sections; Results for the smoother, the 4x4 blocks and MG-CG).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+from typing import Optional, Sequence
+
+__all__ = [
+    "load_library",
+    "Params",
+    "Stats",
+    "Solver",
+    "SmgError",
+    "FP64",
+    "MIXED",
+    "COARSEST_DIRECT",
+    "COARSEST_CG",
+    "library_path",
+]
+
+MAXLEV = 6
+FP64 = 0
+MIXED = 1
+COARSEST_DIRECT = 0
+COARSEST_CG = 1
+
+OK = 0
+NOTCONV = 1
+
+_HERE = Path(__file__).resolve().parent
+
+
+def library_path() -> Path:
+    return Path(os.environ.get("SMG_LIBRARY", _HERE / "libsmg.so"))
+
+
+class Params(ctypes.Structure):
+    """Mirror of smg_params."""
+
+    _fields_ = [
+        ("lx", ctypes.c_int32),
+        ("lt", ctypes.c_int32),
+        ("mass", ctypes.c_double),
+        ("levels", ctypes.c_int32),
+        ("block", (ctypes.c_int32 * 2) * MAXLEV),
+        ("nv", ctypes.c_int32 * MAXLEV),
+        ("setup_iters", ctypes.c_int32),
+        ("smoother_steps", ctypes.c_int32),
+        ("smoother_omega", ctypes.c_double),
+        ("t_antiperiodic", ctypes.c_int32),
+        ("coarsest", ctypes.c_int32),
+        ("coarsest_tol", ctypes.c_double),
+        ("coarsest_maxiter", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class Stats(ctypes.Structure):
+    """Mirror of smg_stats."""
+
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("refinements", ctypes.c_int32),
+        ("vcycles", ctypes.c_int32),
+        ("fine_applies", ctypes.c_int64),
+        ("true_relres", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"smg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not path.exists():
+        raise RuntimeError(
+            f"{path} not found: build it with `python -m paper_0710_3612_amd.build` "
+            "(or __graft_entry__.build())"
+        )
+    lib = ctypes.CDLL(str(path))
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    h = ctypes.c_void_p
+    sig = {
+        "smg_default_params": (None, [ctypes.POINTER(Params)]),
+        "smg_setup": (i32, [P, ctypes.POINTER(Params), P, P, ctypes.POINTER(h)]),
+        "smg_setup_from_vectors": (i32, [P, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(h)]),
+        "smg_set_mass": (i32, [h, ctypes.c_double, P]),
+        "smg_apply_D": (i32, [h, P, P, i32, i32, P]),
+        "smg_apply_A": (i32, [h, P, P, i32, P]),
+        "smg_apply_level": (i32, [h, i32, P, P, i32, P]),
+        "smg_restrict": (i32, [h, i32, P, P, i32, P]),
+        "smg_prolong": (i32, [h, i32, P, P, i32, P]),
+        "smg_smooth": (i32, [h, i32, P, P, i32, P]),
+        "smg_vcycle": (i32, [h, P, P, i32, P]),
+        "smg_solve": (i32, [h, P, P, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(Stats)]),
+        "smg_cg": (i32, [h, P, P, i32, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
+        "smg_level_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "smg_get_prolongator": (i32, [h, i32, P, P]),
+        "smg_get_coarse_links": (i32, [h, i32, P, P]),
+        "smg_get_smoother_coefs": (i32, [h, i32, ctypes.POINTER(ctypes.c_double)]),
+        "smg_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_destroy": (None, [h]),
+        "smg_strerror": (ctypes.c_char_p, [i32]),
+        "smg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, allow_notconv: bool = False) -> int:
+    if code == OK or (allow_notconv and code == NOTCONV):
+        return code
+    lib = load_library()
+    raise SmgError(code, f"{lib.smg_strerror(code).decode()}: {lib.smg_last_error().decode()}")
+
+
+def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence = ((4, 4),),
+                nv: Sequence[int] = (8,), setup_iters: int = 5, smoother_steps: int = 4,
+                smoother_omega: float = 0.8, t_antiperiodic: bool = True, coarsest: int = COARSEST_DIRECT,
+                coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
+                seed: int = 1) -> Params:
+    lib = load_library()
+    p = Params()
+    lib.smg_default_params(ctypes.byref(p))
+    p.lx, p.lt, p.mass, p.levels = lx, lt, mass, levels
+    for l in range(levels - 1):
+        p.block[l][0], p.block[l][1] = blocks[l]
+        p.nv[l] = nv[l]
+    p.setup_iters = setup_iters
+    p.smoother_steps = smoother_steps
+    p.smoother_omega = smoother_omega
+    p.t_antiperiodic = int(bool(t_antiperiodic))
+    p.coarsest = coarsest
+    p.coarsest_tol = coarsest_tol
+    p.coarsest_maxiter = coarsest_maxiter
+    p.inner_tol = inner_tol
+    p.seed = seed
+    return p
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError("expected a contiguous complex128 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Adaptive-MG hierarchy for one gauge field (handle of the C library).
+
+    gauge: complex128 CUDA tensor [2, lt, lx].  Either run the adaptive setup
+    (optionally from given random starts, a complex128 CUDA tensor holding the
+    per-level blocks [1 + nv_l, n_l] concatenated) or build the hierarchy from
+    given near-null vectors (`vectors` and `calib`, see smg_setup_from_vectors).
+    """
+
+    def __init__(self, gauge, params: Params, randoms=None, vectors=None, calib=None, stream=None):
+        import torch
+
+        self.lib = load_library()
+        self.params = params
+        self.handle = ctypes.c_void_p()
+        g = gauge.contiguous()
+        if tuple(g.shape) != (2, params.lt, params.lx):
+            raise ValueError(f"gauge must have shape (2, {params.lt}, {params.lx})")
+        st = _stream(stream)
+        if vectors is not None:
+            code = self.lib.smg_setup_from_vectors(_ptr(g), ctypes.byref(params), _ptr(vectors.contiguous()),
+                                                   _ptr(calib.contiguous()), st, ctypes.byref(self.handle))
+        else:
+            rp = _ptr(randoms.contiguous()) if randoms is not None else ctypes.c_void_p()
+            code = self.lib.smg_setup(_ptr(g), ctypes.byref(params), rp, st, ctypes.byref(self.handle))
+        _check(code)
+        self._torch = torch
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.smg_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- shapes -----------------------------------------------------------------
+    def level_info(self, level: int):
+        lx, lt, dof = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.smg_level_info(self.handle, level, ctypes.byref(lx), ctypes.byref(lt), ctypes.byref(dof)))
+        return lx.value, lt.value, dof.value
+
+    def level_size(self, level: int) -> int:
+        lx, lt, dof = self.level_info(level)
+        return lx * lt * dof
+
+    def _new(self, n, like):
+        return self._torch.empty(n, dtype=self._torch.complex128, device=like.device)
+
+    @staticmethod
+    def _nrhs(x, n):
+        if x.numel() % n:
+            raise ValueError(f"vector length {x.numel()} is not a multiple of {n}")
+        return x.numel() // n
+
+    # -- operators ----------------------------------------------------------------
+    def set_mass(self, mass: float, stream=None):
+        _check(self.lib.smg_set_mass(self.handle, float(mass), _stream(stream)))
+        self.params.mass = mass
+
+    def apply_D(self, x, dagger: bool = False, stream=None):
+        x = x.contiguous()
+        nr = self._nrhs(x, self.level_size(0))
+        y = self._new(x.shape, x)
+        _check(self.lib.smg_apply_D(self.handle, _ptr(x), _ptr(y), nr, int(dagger), _stream(stream)))
+        return y
+
+    def apply_A(self, x, stream=None):
+        return self.apply_level(0, x, stream)
+
+    def apply_level(self, level: int, x, stream=None):
+        x = x.contiguous()
+        nr = self._nrhs(x, self.level_size(level))
+        y = self._new(x.shape, x)
+        _check(self.lib.smg_apply_level(self.handle, level, _ptr(x), _ptr(y), nr, _stream(stream)))
+        return y
+
+    def restrict(self, level: int, x, stream=None):
+        x = x.contiguous()
+        nr = self._nrhs(x, self.level_size(level))
+        y = self._new(nr * self.level_size(level + 1), x)
+        _check(self.lib.smg_restrict(self.handle, level, _ptr(x), _ptr(y), nr, _stream(stream)))
+        return y
+
+    def prolong(self, level: int, e, stream=None):
+        e = e.contiguous()
+        nr = self._nrhs(e, self.level_size(level + 1))
+        y = self._new(nr * self.level_size(level), e)
+        _check(self.lib.smg_prolong(self.handle, level, _ptr(e), _ptr(y), nr, _stream(stream)))
+        return y
+
+    def smooth(self, level: int, b, stream=None):
+        b = b.contiguous()
+        nr = self._nrhs(b, self.level_size(level))
+        x = self._new(b.shape, b)
+        _check(self.lib.smg_smooth(self.handle, level, _ptr(b), _ptr(x), nr, _stream(stream)))
+        return x
+
+    def vcycle(self, b, stream=None):
+        b = b.contiguous()
+        nr = self._nrhs(b, self.level_size(0))
+        x = self._new(b.shape, b)
+        _check(self.lib.smg_vcycle(self.handle, _ptr(b), _ptr(x), nr, _stream(stream)))
+        return x
+
+    # -- solvers ------------------------------------------------------------------
+    def solve(self, rhs, tol: float = 1e-10, maxiter: int = 10000, precision: int = FP64, out=None, stream=None):
+        """Solve A x = rhs; returns (x, [per-column stats dicts], status)."""
+        rhs = rhs.contiguous()
+        nr = self._nrhs(rhs, self.level_size(0))
+        x = out if out is not None else self._new(rhs.shape, rhs)
+        st = (Stats * nr)()
+        code = self.lib.smg_solve(self.handle, _ptr(rhs), _ptr(x), nr, float(tol), int(maxiter), int(precision),
+                                  _stream(stream), st)
+        _check(code, allow_notconv=True)
+        return x, [s.as_dict() for s in st], code
+
+    def cg(self, rhs, tol: float = 1e-10, maxiter: int = 100000, stream=None):
+        rhs = rhs.contiguous()
+        nr = self._nrhs(rhs, self.level_size(0))
+        x = self._new(rhs.shape, rhs)
+        st = (Stats * nr)()
+        code = self.lib.smg_cg(self.handle, _ptr(rhs), _ptr(x), nr, float(tol), int(maxiter), _stream(stream), st)
+        _check(code, allow_notconv=True)
+        return x, [s.as_dict() for s in st], code
+
+    # -- introspection -------------------------------------------------------------
+    def prolongator(self, level: int, stream=None):
+        """P of coarsening `level` as a [J, nv, nagg] complex128 tensor."""
+        lx, lt, dof = self.level_info(level)
+        cx, ct, nc = self.level_info(level + 1)
+        nagg = (lx // cx) * (lt // ct) * dof
+        out = self._torch.empty((cx * ct, nc, nagg), dtype=self._torch.complex128, device="cuda")
+        _check(self.lib.smg_get_prolongator(self.handle, level, _ptr(out), _stream(stream)))
+        return out
+
+    def coarse_links(self, level: int, stream=None):
+        """Links of level >= 1 as [K, 9, nc, nc] complex128 (block (dt+1)*3+(dx+1))."""
+        cx, ct, nc = self.level_info(level)
+        out = self._torch.empty((cx * ct, 9, nc, nc), dtype=self._torch.complex128, device="cuda")
+        _check(self.lib.smg_get_coarse_links(self.handle, level, _ptr(out), _stream(stream)))
+        return out
+
+    def smoother_coefs(self, level: int):
+        buf = (ctypes.c_double * 64)()
+        _check(self.lib.smg_get_smoother_coefs(self.handle, level, buf))
+        return [buf[i] for i in range(self.params.smoother_steps)]
+
+    def memory_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(self.lib.smg_memory_bytes(self.handle, ctypes.byref(b)))
+        return b.value

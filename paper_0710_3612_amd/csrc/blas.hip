@@ -1,0 +1,283 @@
+// Level-1 vector kernels for the Krylov solvers (Multigrid section: conjugate
+// gradients preconditioned by the V-cycle) and the smoother calibration.
+//
+// Reductions are deterministic and batch invariant: every column of a batch is
+// reduced by the same fixed number of blocks (a function of the column length
+// only), each block sums in a fixed order with wavefront shuffles, and a second
+// pass adds the block partials in a fixed order.  Sums are accumulated in FP64
+// for FP32 vectors too.  Krylov scalars live on the device, so the CG loop needs
+// no host round trip except the convergence check.
+#include "common.h"
+
+namespace smg {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block (kThreads) sum of two doubles; result valid in thread 0.
+__device__ inline void block_sum2(double& a, double& b) {
+  __shared__ double sa[kThreads / 64], sb[kThreads / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { sa[w] = a; sb[w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0; b = 0;
+    for (int i = 0; i < kThreads / 64; ++i) { a += sa[i]; b += sb[i]; }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_dot_partial(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b,
+                                                          size_t n, int nb, double* __restrict__ partial) {
+  const size_t off = (size_t)blockIdx.y * n;
+  double re = 0, im = 0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)nb * kThreads) {
+    const cpx<R> u = a[off + i], v = b[off + i];
+    re += (double)u.re * v.re + (double)u.im * v.im;
+    im += (double)u.re * v.im - (double)u.im * v.re;
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    partial[2 * ((size_t)blockIdx.y * nb + blockIdx.x)] = re;
+    partial[2 * ((size_t)blockIdx.y * nb + blockIdx.x) + 1] = im;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_final(const double* __restrict__ partial, int nb,
+                                                           double* __restrict__ out) {
+  double re = 0, im = 0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    re += partial[2 * ((size_t)blockIdx.x * nb + i)];
+    im += partial[2 * ((size_t)blockIdx.x * nb + i) + 1];
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = re;
+    out[2 * blockIdx.x + 1] = im;
+  }
+}
+
+// x += alpha p ; r -= alpha q ; partial |r|^2
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_axpy_update(cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
+                                                          const cpx<R>* __restrict__ p, const cpx<R>* __restrict__ q,
+                                                          const double* __restrict__ alpha, size_t n, int nb,
+                                                          double* __restrict__ partial) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const R a = (R)alpha[blockIdx.y];
+  double rr = 0, dummy = 0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)nb * kThreads) {
+    const size_t j = off + i;
+    x[j] = x[j] + a * p[j];
+    const cpx<R> rn = r[j] - a * q[j];
+    r[j] = rn;
+    rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+  }
+  block_sum2(rr, dummy);
+  if (threadIdx.x == 0) {
+    partial[2 * ((size_t)blockIdx.y * nb + blockIdx.x)] = rr;
+    partial[2 * ((size_t)blockIdx.y * nb + blockIdx.x) + 1] = 0;
+  }
+}
+
+template <typename R>
+__global__ void k_xpay(const cpx<R>* __restrict__ z, cpx<R>* __restrict__ p, const double* __restrict__ beta,
+                       size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const R b = (R)beta[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[off + i] = z[off + i] + b * p[off + i];
+}
+
+template <typename R>
+__global__ void k_axpy_const(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, R a, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[off + i] = y[off + i] + a * x[off + i];
+}
+
+template <typename R>
+__global__ void k_sub(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, cpx<R>* __restrict__ y, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[off + i] = a[off + i] - b[off + i];
+}
+
+template <typename R>
+__global__ void k_scale_cols(cpx<R>* __restrict__ x, const double* __restrict__ s, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const R a = (R)s[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[off + i] = a * x[off + i];
+}
+
+template <typename R>
+__global__ void k_scale_const(cpx<R>* x, R a, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[off + i] = a * x[off + i];
+}
+
+template <typename Ro, typename Ri>
+__global__ void k_convert(const cpx<Ri>* __restrict__ in, cpx<Ro>* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = cvt<Ro>(in[i]);
+}
+
+__global__ void k_scale_down(const z64* __restrict__ in, z32* __restrict__ out, const double* __restrict__ s,
+                             size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const double a = s[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[off + i] = cvt<float>(a * in[off + i]);
+}
+
+__global__ void k_scale_up_add(z64* __restrict__ x, const z32* __restrict__ e, const double* __restrict__ s,
+                               size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const double a = s[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[off + i] = x[off + i] + a * cvt<double>(e[off + i]);
+}
+
+// alpha = <r,z> / <p,Ap>; a column that is frozen or breaks down gets alpha = 0.
+__global__ void k_cg_alpha(const double* __restrict__ rz, const double* __restrict__ pq, double* __restrict__ alpha,
+                           const int* __restrict__ active, int* __restrict__ bad, int nrhs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double a = 0;
+  if (active[j]) {
+    const double num = rz[2 * j], den = pq[2 * j];
+    if (!isfinite(num) || !isfinite(den)) {
+      bad[j] = 1;
+    } else if (num == 0) {
+      a = 0;  // residual is exactly zero: nothing left to do in this column
+    } else if (!(den > 0)) {
+      bad[j] = 1;
+    } else {
+      a = num / den;
+    }
+  }
+  alpha[j] = a;
+}
+
+// beta = <r,z>_new / <r,z>_old ; rz_old <- rz_new.
+__global__ void k_cg_beta(const double* __restrict__ rz_new, double* __restrict__ rz, double* __restrict__ beta,
+                          const int* __restrict__ active, int nrhs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double b = 0;
+  if (active[j] && rz[2 * j] != 0) b = rz_new[2 * j] / rz[2 * j];
+  beta[j] = b;
+  if (active[j]) {
+    rz[2 * j] = rz_new[2 * j];
+    rz[2 * j + 1] = rz_new[2 * j + 1];
+  }
+}
+
+inline dim3 ew_grid(size_t n, int nrhs) {
+  size_t g = (n + kThreads - 1) / kThreads;
+  if (g > 4096) g = 4096;
+  return dim3((unsigned)g, nrhs);
+}
+
+}  // namespace
+
+template <typename R>
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, double* partial, double* out,
+                hipStream_t st) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, a, b, n, nb, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs), dim3(kThreads), 0, st, partial, nb, out);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
+                        int nrhs, double* partial, double* rr, hipStream_t st) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_axpy_update<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, alpha, n, nb, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs), dim3(kThreads), 0, st, partial, nb, rr);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_xpay<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, z, p, beta, n);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_axpy_const(cpx<R>* y, const cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_const<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, y, x, (R)a, n);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_sub(const cpx<R>* a, const cpx<R>* b, cpx<R>* y, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_sub<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, a, b, y, n);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_scale_cols(cpx<R>* x, const double* s, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_cols<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, x, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_scale_const(cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_const<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, x, (R)a, n);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename Ro, typename Ri>
+void launch_convert(const cpx<Ri>* in, cpx<Ro>* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Ro, Ri>), ew_grid(n, 1), dim3(kThreads), 0, st, in, out, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_down, ew_grid(n, nrhs), dim3(kThreads), 0, st, in, out, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_scale_up_add(z64* x, const z32* e, const double* s, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_up_add, ew_grid(n, nrhs), dim3(kThreads), 0, st, x, e, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_cg_alpha(const double* rz, const double* pq, double* alpha, const int* active, int* bad, int nrhs,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, st, rz, pq, alpha, active, bad, nrhs);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* active, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta, dim3((nrhs + 63) / 64), dim3(64), 0, st, rz_new, rz, beta, active, nrhs);
+  HIPCHECK(hipGetLastError());
+}
+
+#define INST(R)                                                                                              \
+  template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, double*, double*, hipStream_t);       \
+  template void launch_axpy_update<R>(cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double*, size_t,  \
+                                      int, double*, double*, hipStream_t);                                    \
+  template void launch_xpay<R>(const cpx<R>*, cpx<R>*, const double*, size_t, int, hipStream_t);              \
+  template void launch_axpy_const<R>(cpx<R>*, const cpx<R>*, double, size_t, int, hipStream_t);              \
+  template void launch_sub<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, size_t, int, hipStream_t);              \
+  template void launch_scale_cols<R>(cpx<R>*, const double*, size_t, int, hipStream_t);               \
+  template void launch_scale_const<R>(cpx<R>*, double, size_t, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+template void launch_convert<float, double>(const z64*, z32*, size_t, hipStream_t);
+template void launch_convert<double, float>(const z32*, z64*, size_t, hipStream_t);
+template void launch_convert<double, double>(const z64*, z64*, size_t, hipStream_t);
+
+}  // namespace smg

@@ -1,0 +1,185 @@
+// Internal definitions shared by the HIP kernels and the host driver of libsmg.
+//
+// Storage conventions (all device arrays are plain interleaved complex numbers):
+//   fine vector batch     [nrhs][t][x][spin]        spin in {0,1}
+//   level-l vector batch  [nrhs][t][x][dof]         dof = nv of the coarsening above
+//   fine links            [mu][t][x]                fermion BC sign folded into mu=1, t=lt-1
+//   prolongator           [J][k][i]                 J coarse site, k vector, i aggregate variable
+//   coarse links (device) [D][col][K][row]          D = (dt+1)*3 + (dx+1); "site-major" so that
+//                                                   threads (K,row) read consecutive words
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace smg {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ inline cpx<R> mk(R a, R b) { cpx<R> z; z.re = a; z.im = b; return z; }
+template <typename R>
+__host__ __device__ inline cpx<R> operator+(cpx<R> a, cpx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ inline cpx<R> operator-(cpx<R> a, cpx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ inline cpx<R> operator*(cpx<R> a, cpx<R> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ inline cpx<R> operator*(R s, cpx<R> a) { return mk(s * a.re, s * a.im); }
+template <typename R>
+__host__ __device__ inline cpx<R> cj(cpx<R> a) { return mk(a.re, -a.im); }
+// conj(a) * b
+template <typename R>
+__host__ __device__ inline cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+// i * a
+template <typename R>
+__host__ __device__ inline cpx<R> imul(cpx<R> a) { return mk(-a.im, a.re); }
+template <typename R>
+__host__ __device__ inline void fma_acc(cpx<R>& acc, cpx<R> a, cpx<R> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+template <typename R>
+__host__ __device__ inline void fma_acc_conj(cpx<R>& acc, cpx<R> a, cpx<R> b) {  // acc += conj(a) b
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+template <typename Ro, typename Ri>
+__host__ __device__ inline cpx<Ro> cvt(cpx<Ri> a) { return mk((Ro)a.re, (Ro)a.im); }
+
+using z64 = cpx<double>;
+using z32 = cpx<float>;
+
+// Error raised inside the library and turned into a return code at the C boundary.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPCHECK(call) ::smg::hip_check((call), #call, __FILE__, __LINE__)
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(size_t n, int threads = kThreads, size_t cap = 1u << 20) {
+  size_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// Deterministic reductions use a partial count that depends only on the vector
+// length, never on the batch size or on which columns are active.
+inline int red_blocks(size_t n) {
+  size_t b = (n + 4 * kThreads - 1) / (4 * kThreads);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All are asynchronous on `st`.
+// ---------------------------------------------------------------------------
+
+// Fine Wilson operator, links U [2][V] with the fermion BC sign already folded in.
+template <typename R>
+void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs,
+                   bool dagger, hipStream_t st);
+
+// Fine normal operator with an epilogue.  mode:
+//   0: y = A x
+//   1: smoother step   xacc += c * x ;  y = x - c * A x
+//   2: residual        y = b - A x           (b = aux)
+// A x = D^H (D x); `tmp` holds D x ([nrhs][V][2]).
+template <typename R>
+void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
+                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+
+// Coarse 9-point operator on level with extents (cx, ct), nc dof; links [9][nc][K][nc].
+template <typename R>
+void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+                   double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+
+// Transfer between level (lx, lt, dof) and its aggregates of (bx, bt) sites.
+// P is [J][ldk][nagg] (ldk >= nc vectors stored per aggregate).
+template <typename R>
+void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt,
+                     int nc, int ldk, int nrhs, hipStream_t st);
+// mode 0: y = P e ; mode 1: y += P e
+template <typename R>
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt,
+                    int nc, int ldk, int nrhs, int mode, hipStream_t st);
+
+// Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
+void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+                      int* fail, hipStream_t st);
+
+// Galerkin helpers: X = sum over aggregates J of colour (cxc, ctc) of P[J][k] (zero elsewhere).
+void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+                          int cxc, int ctc, hipStream_t st);
+// links[D(K)][k][K][:] = P_K^H (Y restricted to K), D(K) the offset of the colour's aggregate.
+void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int nc,
+                          int ldk, int k, int cxc, int ctc, hipStream_t st);
+int colors_along(int extent);
+
+// Dense coarsest operator and its inverse (FP64).
+void launch_coarse_to_dense(const z64* L, z64* M, int cx, int ct, int nc, hipStream_t st);
+void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hipStream_t st);
+template <typename R>
+void launch_dense_apply(const z64* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
+
+// Level-1 BLAS (batched over nrhs columns of length n).
+template <typename R>
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, double* partial, double* out,
+                hipStream_t st);  // out[2*rhs] = <a,b> (complex)
+template <typename R>
+void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
+                        int nrhs, double* partial, double* rr, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2
+template <typename R>
+void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
+template <typename R>
+void launch_axpy_const(cpx<R>* y, const cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st);
+template <typename R>
+void launch_sub(const cpx<R>* a, const cpx<R>* b, cpx<R>* y, size_t n, int nrhs, hipStream_t st);  // y = a-b
+template <typename R>
+void launch_scale_cols(cpx<R>* x, const double* s, size_t n, int nrhs, hipStream_t st);  // x *= s[rhs]
+template <typename R>
+void launch_scale_const(cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st);  // x *= a
+template <typename Ro, typename Ri>
+void launch_convert(const cpx<Ri>* in, cpx<Ro>* out, size_t n, hipStream_t st);
+// out32 = in64 * s[rhs]   (defect-correction right-hand side)
+void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st);
+// x64 += s[rhs] * e32     (defect-correction update)
+void launch_scale_up_add(z64* x, const z32* e, const double* s, size_t n, int nrhs, hipStream_t st);
+
+// Scalar steps of CG, one thread per column; `active[rhs] == 0` freezes a column.
+void launch_cg_alpha(const double* rz, const double* pq, double* alpha, const int* active, int* bad, int nrhs,
+                     hipStream_t st);
+void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* active, int nrhs, hipStream_t st);
+
+// Gauge relayout: U[mu][t][x] -> fermion links with the antiperiodic sign folded in.
+template <typename R>
+void launch_prepare_links(const z64* gauge, cpx<R>* U, int lx, int lt, int antiperiodic, hipStream_t st);
+
+// Counter-based Gaussian vectors (when the caller supplies no random starts).
+void launch_random_gaussian(z64* v, size_t n, uint64_t seed, uint64_t stream_id, hipStream_t st);
+
+// Layout conversions of the coarse links: device [D][col][K][row] <-> export [K][D][row][col].
+void launch_links_export(const z64* L, z64* out, int nK, int nc, hipStream_t st);
+template <typename Ro>
+void launch_links_convert(const z64* L, cpx<Ro>* out, size_t n, hipStream_t st);
+// out = C2 + m*C1 + m^2 * I(D = centre)  (mass-affine coarse links)
+void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int nK, int nc, hipStream_t st);
+
+}  // namespace smg

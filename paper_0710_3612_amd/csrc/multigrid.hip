@@ -1,0 +1,567 @@
+// Multigrid kernels: transfer (restriction P^H and prolongation P), the 9-point
+// Galerkin coarse operator, block Gram-Schmidt, the Galerkin build and the dense
+// coarsest solve (Multigrid section, Eq. 2; Adaptive Multigrid section).
+//
+// Aggregates (Adaptive Multigrid section): the lattice of level l is cut into
+// bx x bt blocks of sites; aggregate J holds every degree of freedom of its block,
+// so its variables are i = ((t % bt) * bx + x % bx) * dof + d.  Column (J, k) of P
+// is the k-th block-orthonormal near-null vector restricted to J.
+//
+// The coarse operator A_c = P^H A P couples a coarse site only to the 3x3 box
+// around it (A has reach one site in each direction and the blocks are at least
+// two sites wide), so it is stored as 9 dense nc x nc link blocks per coarse site.
+#include "common.h"
+
+namespace smg {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fine index of variable i of aggregate J.
+__device__ inline int agg_index(int J, int i, int lx, int dof, int bx, int bt, int cx) {
+  const int Jt = J / cx, Jx = J - Jt * cx;
+  const int site = i / dof, d = i - site * dof;
+  const int ty = site / bx, tx = site - ty * bx;
+  return ((Jt * bt + ty) * lx + (Jx * bx + tx)) * dof + d;
+}
+
+// ---------------------------------------------------------------------------
+// Restriction y[K][k] = sum_i conj(P[K][k][i]) x[agg(K,i)]: one wavefront per
+// aggregate; the lanes walk the aggregate's variables (coalesced P rows) and the
+// nc inner products are reduced across the wavefront one after the other.
+// The result goes to out[k * ostride_k] (plain restriction or a column of the
+// Galerkin links).
+// ---------------------------------------------------------------------------
+template <typename R, int NCH>
+__device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x, int K, int lx,
+                                    int dof, int bx, int bt, int cx, int nc, int ldk, cpx<R>* __restrict__ out,
+                                    size_t ostride_k) {
+  const int lane = threadIdx.x & 63;
+  const int nagg = bx * bt * dof;
+  cpx<R> xv[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = lane + 64 * c;
+    xv[c] = (i < nagg) ? x[agg_index(K, i, lx, dof, bx, bt, cx)] : mk<R>(0, 0);
+  }
+  const cpx<R>* PK = P + (size_t)K * ldk * nagg;
+  for (int k = 0; k < nc; ++k) {
+    double re = 0, im = 0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int i = lane + 64 * c;
+      if (i < nagg) {
+        const cpx<R> p = PK[(size_t)k * nagg + i];
+        re += (double)p.re * xv[c].re + (double)p.im * xv[c].im;
+        im += (double)p.re * xv[c].im - (double)p.im * xv[c].re;
+      }
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) out[(size_t)k * ostride_k] = mk<R>((R)re, (R)im);
+  }
+}
+
+template <typename R, int NCH>
+__global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x,
+                                                       cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
+                                                       int bt, int nc, int ldk) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (K >= nK) return;
+  const size_t n = (size_t)lx * lt * dof;
+  const int rhs = blockIdx.y;
+  restrict_one<R, NCH>(P, x + rhs * n, K, lx, dof, bx, bt, cx, nc, ldk, y + (size_t)rhs * nK * nc + (size_t)K * nc,
+                       1);
+}
+
+// y[agg(K,i)] (+)= sum_k P[K][k][i] e[K][k]; one thread per fine variable.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ e,
+                                                      cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx, int bt,
+                                                      int nc, int ldk) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int nagg = bx * bt * dof;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nK * nagg) return;
+  const int K = tid / nagg, i = tid - K * nagg;
+  const size_t n = (size_t)lx * lt * dof;
+  const int rhs = blockIdx.y;
+  const cpx<R>* PK = P + (size_t)K * ldk * nagg + i;
+  const cpx<R>* eK = e + (size_t)rhs * nK * nc + (size_t)K * nc;
+  cpx<R> acc = mk<R>(0, 0);
+  for (int k = 0; k < nc; ++k) fma_acc(acc, PK[(size_t)k * nagg], eK[k]);
+  const size_t o = rhs * n + agg_index(K, i, lx, dof, bx, bt, cx);
+  if (MODE == 0)
+    y[o] = acc;
+  else
+    y[o] = y[o] + acc;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse 9-point operator: y_K = sum_D L_{K,D} v_{K+D}.  Links are stored
+// [D][col][K][row]: thread (K,row) reads consecutive words for each (D, col).
+// ---------------------------------------------------------------------------
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ L, const cpx<R>* __restrict__ v,
+                                                     cpx<R>* __restrict__ y, int cx, int ct, int nc, R c,
+                                                     cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux) {
+  const int nK = cx * ct;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nK * nc) return;
+  const int K = tid / nc;
+  const int Kt = K / cx, Kx = K - Kt * cx;
+  const size_t n = (size_t)nK * nc;
+  const size_t off = (size_t)blockIdx.y * n;
+  const cpx<R>* vb = v + off;
+  cpx<R> acc = mk<R>(0, 0);
+  for (int D = 0; D < 9; ++D) {
+    const int dt = D / 3 - 1, dx = D % 3 - 1;
+    int nx = Kx + dx, nt = Kt + dt;
+    nx = nx < 0 ? nx + cx : (nx >= cx ? nx - cx : nx);
+    nt = nt < 0 ? nt + ct : (nt >= ct ? nt - ct : nt);
+    const cpx<R>* vn = vb + (size_t)(nt * cx + nx) * nc;
+    const cpx<R>* LD = L + (size_t)D * nc * n + tid;
+    for (int col = 0; col < nc; ++col) fma_acc(acc, LD[(size_t)col * n], vn[col]);
+  }
+  const size_t o = off + tid;
+  if (MODE == 0) {
+    y[o] = acc;
+  } else if (MODE == 1) {
+    const cpx<R> vi = v[o];
+    xacc[o] = xacc[o] + c * vi;
+    y[o] = vi - c * acc;
+  } else {
+    y[o] = aux[o] - acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block Gram-Schmidt (FP64): append candidate v as vector k of every aggregate.
+// One workgroup per aggregate; two passes of modified Gram-Schmidt against the
+// earlier vectors, then normalisation to 1 (Adaptive Multigrid section).
+// ---------------------------------------------------------------------------
+__device__ inline void block_allreduce2(double& a, double& b, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();  // earlier readers of sh are done
+  if (l == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  __syncthreads();
+  a = 0; b = 0;
+  for (int i = 0; i < kThreads / 64; ++i) { a += sh[2 * i]; b += sh[2 * i + 1]; }
+}
+
+template <int NCH>
+__global__ void __launch_bounds__(kThreads) k_gs_append(z64* __restrict__ P, const z64* __restrict__ v, int lx,
+                                                        int dof, int bx, int bt, int cx, int k, int ldk,
+                                                        int* __restrict__ fail) {
+  __shared__ double sh[2 * (kThreads / 64)];
+  const int J = blockIdx.x;
+  const int nagg = bx * bt * dof;
+  z64* PJ = P + (size_t)J * ldk * nagg;
+  z64 w[NCH];
+  double ref = 0, dummy = 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = threadIdx.x + kThreads * c;
+    w[c] = (i < nagg) ? v[agg_index(J, i, lx, dof, bx, bt, cx)] : mk(0.0, 0.0);
+    ref += w[c].re * w[c].re + w[c].im * w[c].im;
+  }
+  block_allreduce2(ref, dummy, sh);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < k; ++j) {
+      const z64* u = PJ + (size_t)j * nagg;
+      double re = 0, im = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int i = threadIdx.x + kThreads * c;
+        if (i < nagg) {
+          const z64 a = u[i];
+          re += a.re * w[c].re + a.im * w[c].im;
+          im += a.re * w[c].im - a.im * w[c].re;
+        }
+      }
+      block_allreduce2(re, im, sh);
+      const z64 proj = mk(re, im);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int i = threadIdx.x + kThreads * c;
+        if (i < nagg) w[c] = w[c] - proj * u[i];
+      }
+    }
+  }
+  double nrm = 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) nrm += w[c].re * w[c].re + w[c].im * w[c].im;
+  block_allreduce2(nrm, dummy, sh);
+  nrm = sqrt(nrm);
+  ref = sqrt(ref);
+  if (!(nrm > 1e-12 * ref)) {
+    if (threadIdx.x == 0) fail[0] = 1;
+    nrm = 1.0;
+  }
+  const double inv = 1.0 / nrm;
+  z64* out = PJ + (size_t)k * nagg;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = threadIdx.x + kThreads * c;
+    if (i < nagg) out[i] = inv * w[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin build by colouring.  Aggregates of one colour are at least three
+// blocks apart (with wrap-around), so A applied to the sum of their k-th
+// columns never mixes two of them on any aggregate: restricting that image to
+// aggregate K gives column k of the link block L_{K, J-K} for the unique J of the
+// colour within K's 3x3 box.  colour(j) = j mod 3 on the first 3*floor(c/3)
+// blocks of an extent c, and a colour of its own for each remaining block.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int color_of(int j, int c) {
+  if (c < 3) return j;
+  const int base = 3 * (c / 3);
+  return j < base ? j % 3 : 3 + (j - base);
+}
+
+// Offset d in {0,-1,+1} of the block of colour `col` next to block j (extent c),
+// or 2 if there is none.  For c <= 2 several offsets name the same block; the
+// first one found receives the whole coupling and the apply sums them.
+__device__ inline int pick_offset(int j, int c, int col) {
+  const int ds[3] = {0, -1, 1};
+  for (int q = 0; q < 3; ++q) {
+    int n = j + ds[q];
+    n = n < 0 ? n + c : (n >= c ? n - c : n);
+    if (color_of(n, c) == col) return ds[q];
+  }
+  return 2;
+}
+
+__global__ void k_color_scatter(const z64* __restrict__ P, z64* __restrict__ X, int lx, int lt, int dof, int bx,
+                                int bt, int k, int ldk, int cxc, int ctc) {
+  const size_t n = (size_t)lx * lt * dof;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
+  const int t = site / lx, x = site - t * lx;
+  const int cx = lx / bx, ct = lt / bt;
+  const int Jx = x / bx, Jt = t / bt;
+  z64 val = mk(0.0, 0.0);
+  if (color_of(Jx, cx) == cxc && color_of(Jt, ct) == ctc) {
+    const int nagg = bx * bt * dof;
+    const int i = ((t - Jt * bt) * bx + (x - Jx * bx)) * dof + d;
+    val = P[((size_t)(Jt * cx + Jx) * ldk + k) * nagg + i];
+  }
+  X[idx] = val;
+}
+
+template <int NCH>
+__global__ void __launch_bounds__(kThreads) k_color_project(const z64* __restrict__ P, const z64* __restrict__ Y,
+                                                            z64* __restrict__ L, int lx, int lt, int dof, int bx,
+                                                            int bt, int nc, int ldk, int k, int cxc, int ctc) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (K >= nK) return;
+  const int Kt = K / cx, Kx = K - Kt * cx;
+  const int dx = pick_offset(Kx, cx, cxc), dt = pick_offset(Kt, ct, ctc);
+  if (dx == 2 || dt == 2) return;
+  const int D = (dt + 1) * 3 + (dx + 1);
+  const size_t n = (size_t)nK * nc;
+  // L[D][k][K][row]: row stride 1, so out = &L[D][k][K][0]
+  restrict_one<double, NCH>(P, Y, K, lx, dof, bx, bt, cx, nc, ldk, L + ((size_t)D * nc + k) * n + (size_t)K * nc, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Dense coarsest operator and its inverse by Gauss-Jordan elimination (FP64).
+// A^(L) is Hermitian positive definite, so no pivoting is needed.
+// ---------------------------------------------------------------------------
+__global__ void k_coarse_to_dense(const z64* __restrict__ L, z64* __restrict__ M, int cx, int ct, int nc) {
+  const int nK = cx * ct;
+  const size_t n = (size_t)nK * nc;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+  const int K = i / nc, row = i - K * nc, Kn = j / nc, col = j - Kn * nc;
+  const int Kt = K / cx, Kx = K - Kt * cx;
+  z64 acc = mk(0.0, 0.0);
+  for (int D = 0; D < 9; ++D) {
+    const int dt = D / 3 - 1, dx = D % 3 - 1;
+    int nx = Kx + dx, nt = Kt + dt;
+    nx = nx < 0 ? nx + cx : (nx >= cx ? nx - cx : nx);
+    nt = nt < 0 ? nt + ct : (nt >= ct ? nt - ct : nt);
+    if (nt * cx + nx == Kn) acc = acc + L[((size_t)D * nc + col) * n + (size_t)K * nc + row];
+  }
+  M[idx] = acc;
+}
+
+// Step k, part 1: save column k, record the pivot, scale row k.
+__global__ void k_gj_pivot(z64* __restrict__ M, int n, int k, z64* __restrict__ colk, double* __restrict__ piv,
+                           int* __restrict__ fail) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double p = M[(size_t)k * n + k].re;
+  if (j == 0) {
+    piv[0] = p;
+    if (!(p > 0) || !isfinite(p)) fail[0] = 1;
+  }
+  colk[j] = M[(size_t)j * n + k];
+  if (j != k) M[(size_t)k * n + j] = (1.0 / p) * M[(size_t)k * n + j];
+}
+
+// Step k, part 2: eliminate column k from every other row.
+__global__ void k_gj_update(z64* __restrict__ M, int n, int k, const z64* __restrict__ colk,
+                            const double* __restrict__ piv) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+  const double p = piv[0];
+  if (i == k) {
+    if (j == k) M[idx] = mk(1.0 / p, 0.0);
+    return;
+  }
+  if (j == k) {
+    M[idx] = (-1.0 / p) * colk[i];
+  } else {
+    M[idx] = M[idx] - colk[i] * M[(size_t)k * n + j];
+  }
+}
+
+// y = M x for every column; one wavefront per row.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_dense_apply(const z64* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                          cpx<R>* __restrict__ y, int n) {
+  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const cpx<R>* xb = x + (size_t)blockIdx.y * n;
+  const z64* Mr = M + (size_t)row * n;
+  double re = 0, im = 0;
+  for (int j = lane; j < n; j += 64) {
+    const z64 m = Mr[j];
+    const cpx<R> v = xb[j];
+    re += m.re * v.re - m.im * v.im;
+    im += m.re * v.im + m.im * v.re;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)re, (R)im);
+}
+
+// ---------------------------------------------------------------------------
+// Utilities.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// Complex Gaussian with Re, Im ~ N(0, 1/2): Box-Muller on two counter-based uniforms.
+__global__ void k_random_gaussian(z64* __restrict__ v, size_t n, uint64_t seed, uint64_t sid) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = splitmix64(seed ^ splitmix64(sid));
+  const uint64_t a = splitmix64(key + 2 * i), b = splitmix64(key + 2 * i + 1);
+  const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740992.0);  // (0, 1]
+  const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);          // [0, 1)
+  const double r = sqrt(-log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  v[i] = mk(r * c, r * s);
+}
+
+__global__ void k_links_export(const z64* __restrict__ L, z64* __restrict__ out, int nK, int nc) {
+  const size_t total = (size_t)nK * 9 * nc * nc;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  // out index = ((K*9 + D)*nc + row)*nc + col
+  const int col = (int)(idx % nc);
+  size_t r = idx / nc;
+  const int row = (int)(r % nc);
+  r /= nc;
+  const int D = (int)(r % 9);
+  const int K = (int)(r / 9);
+  const size_t n = (size_t)nK * nc;
+  out[idx] = L[((size_t)D * nc + col) * n + (size_t)K * nc + row];
+}
+
+__global__ void k_links_affine(const z64* __restrict__ C2, const z64* __restrict__ C1, z64* __restrict__ out,
+                               double m, int nK, int nc) {
+  const size_t n = (size_t)nK * nc;
+  const size_t total = 9 * (size_t)nc * n;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  z64 v = C2[idx] + m * C1[idx];
+  // centre block D = 4, diagonal col == row
+  const size_t Dc = idx / ((size_t)nc * n);
+  const int col = (int)((idx / n) % nc);
+  const int row = (int)(idx % nc);
+  if (Dc == 4 && col == row) v.re += m * m;
+  out[idx] = v;
+}
+
+template <typename Ro>
+__global__ void k_copy_convert(const z64* __restrict__ in, cpx<Ro>* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = cvt<Ro>(in[i]);
+}
+
+template <int N>
+struct IntC {
+  static constexpr int v = N;
+};
+
+// Dispatch on the number of 64-lane (or 256-thread) chunks covering an aggregate.
+template <typename F>
+void dispatch_chunks(int chunks, F&& f) {
+  if (chunks <= 1) f(IntC<1>{});
+  else if (chunks <= 2) f(IntC<2>{});
+  else if (chunks <= 3) f(IntC<3>{});
+  else if (chunks <= 4) f(IntC<4>{});
+  else if (chunks <= 8) f(IntC<8>{});
+  else if (chunks <= 16) f(IntC<16>{});
+  else throw Error(-1, "aggregate too large (more than 1024 variables)");
+}
+
+}  // namespace
+
+int colors_along(int extent) { return extent < 3 ? extent : 3 + (extent - 3 * (extent / 3)); }
+
+template <typename R>
+void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int nc,
+                     int ldk, int nrhs, hipStream_t st) {
+  const int nK = (lx / bx) * (lt / bt);
+  const int nagg = bx * bt * dof;
+  dim3 grid((nK + 3) / 4, nrhs);
+  dispatch_chunks((nagg + 63) / 64, [&](auto c) {
+    hipLaunchKernelGGL((k_restrict<R, decltype(c)::v>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt,
+                       nc, ldk);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int nc,
+                    int ldk, int nrhs, int mode, hipStream_t st) {
+  const size_t total = (size_t)lx * lt * dof;
+  dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_prolong<R, 0>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, nc, ldk);
+  else
+    hipLaunchKernelGGL((k_prolong<R, 1>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, nc, ldk);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                   cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  const size_t total = (size_t)cx * ct * nc;
+  dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarse<R, 0>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_coarse<R, 1>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
+  else
+    hipLaunchKernelGGL((k_coarse<R, 2>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int* fail,
+                      hipStream_t st) {
+  const int cx = lx / bx, nK = cx * (lt / bt);
+  const int nagg = bx * bt * dof;
+  dispatch_chunks((nagg + kThreads - 1) / kThreads, [&](auto c) {
+    hipLaunchKernelGGL((k_gs_append<decltype(c)::v>), dim3(nK), dim3(kThreads), 0, st, (z64*)P, v, lx, dof, bx, bt,
+                       cx, k, ldk, fail);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int cxc,
+                          int ctc, hipStream_t st) {
+  const size_t n = (size_t)lx * lt * dof;
+  hipLaunchKernelGGL(k_color_scatter, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, P, X,
+                     lx, lt, dof, bx, bt, k, ldk, cxc, ctc);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int nc,
+                          int ldk, int k, int cxc, int ctc, hipStream_t st) {
+  const int nK = (lx / bx) * (lt / bt);
+  const int nagg = bx * bt * dof;
+  dispatch_chunks((nagg + 63) / 64, [&](auto c) {
+    hipLaunchKernelGGL((k_color_project<decltype(c)::v>), dim3((nK + 3) / 4), dim3(kThreads), 0, st, P, Y, L, lx,
+                       lt, dof, bx, bt, nc, ldk, k, cxc, ctc);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_coarse_to_dense(const z64* L, z64* M, int cx, int ct, int nc, hipStream_t st) {
+  const size_t n = (size_t)cx * ct * nc;
+  hipLaunchKernelGGL(k_coarse_to_dense, dim3((unsigned)((n * n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                     L, M, cx, ct, nc);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, M, n, k, colk, piv,
+                     fail);
+  const size_t nn = (size_t)n * n;
+  hipLaunchKernelGGL(k_gj_update, dim3((unsigned)((nn + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, M, n, k,
+                     colk, piv);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_dense_apply(const z64* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_dense_apply<R>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_random_gaussian(z64* v, size_t n, uint64_t seed, uint64_t stream_id, hipStream_t st) {
+  hipLaunchKernelGGL(k_random_gaussian, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, v, n,
+                     seed, stream_id);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_links_export(const z64* L, z64* out, int nK, int nc, hipStream_t st) {
+  const size_t total = (size_t)nK * 9 * nc * nc;
+  hipLaunchKernelGGL(k_links_export, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, L,
+                     out, nK, nc);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename Ro>
+void launch_links_convert(const z64* L, cpx<Ro>* out, size_t n, hipStream_t st) {
+  size_t g = (n + kThreads - 1) / kThreads;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL((k_copy_convert<Ro>), dim3((unsigned)g), dim3(kThreads), 0, st, L, out, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int nK, int nc, hipStream_t st) {
+  const size_t total = 9 * (size_t)nc * nc * nK;
+  hipLaunchKernelGGL(k_links_affine, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, C2,
+                     C1, out, m, nK, nc);
+  HIPCHECK(hipGetLastError());
+}
+
+#define INST(R)                                                                                                  \
+  template void launch_restrict<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int, \
+                                   hipStream_t);                                                                 \
+  template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int,  \
+                                  int, hipStream_t);                                                             \
+  template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
+                                 const cpx<R>*, hipStream_t);                                                    \
+  template void launch_dense_apply<R>(const z64*, const cpx<R>*, cpx<R>*, int, int, hipStream_t);                \
+  template void launch_links_convert<R>(const z64*, cpx<R>*, size_t, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace smg

@@ -1,0 +1,1120 @@
+// Host driver of libsmg: the multigrid hierarchy, the V-cycle, the Krylov
+// solvers, the adaptive setup and the C entry points declared in smg.h.
+//
+// Paper map (Brannick, Brower, Clark, Osborn, Rebbi, arXiv:0710.3612):
+//   V-cycle        Multigrid section, steps 1-5 and Eq. 3 (read with -R A R^H)
+//   Galerkin       Eq. 2, A^(l+1) = P^H A^(l) P
+//   Setup          Adaptive Multigrid section: relaxation of a random vector
+//                  (Eq. 4), then V-cycles on further random vectors, each
+//                  survivor block-orthonormalised and appended; recursion.
+//   Smoother       Results section: frozen nu-step under-relaxed MR polynomial
+//   Outer solver   Results section: MG-CG, the V-cycle preconditions CG
+//   Mass reuse     Results section: setup at one mass, vectors reused
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/smg.h"
+#include "common.h"
+
+namespace smg {
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e != hipSuccess) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    throw Error(e == hipErrorOutOfMemory ? SMG_ENOMEM : SMG_EDEVICE, buf);
+  }
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------
+// Device memory owned by a context; everything is released with the context.
+// ---------------------------------------------------------------------------
+struct Pool {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  ~Pool() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+// One grid level in one precision.
+template <typename R>
+struct Level {
+  int lx = 0, lt = 0, dof = 0;
+  size_t n = 0;                     // vector length per right-hand side
+  bool fine = false;
+  const cpx<R>* U = nullptr;        // fine links (fine level only)
+  double diag = 0;                  // 2 + m (fine level only)
+  cpx<R>* L = nullptr;              // coarse links [9][dof][K][dof] (coarse levels)
+  // transfer to the next level
+  int bx = 0, bt = 0, nc = 0, ldk = 0;
+  cpx<R>* P = nullptr;              // [J][ldk][nagg]
+  std::vector<double> coefs;        // smoother polynomial
+  // work vectors, `cap` columns each
+  int cap = 0;
+  cpx<R>*b = nullptr, *x = nullptr, *r = nullptr, *t = nullptr, *tmp = nullptr;
+};
+
+struct Scal {
+  double *bb = nullptr, *rz = nullptr, *pq = nullptr, *ab = nullptr, *rr = nullptr, *tt = nullptr;
+  int *active = nullptr, *bad = nullptr;
+};
+
+template <typename R>
+struct KVecs {
+  cpx<R>*r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *t = nullptr;
+  size_t cap = 0;                   // elements per vector
+};
+
+struct Ctx {
+  smg_params prm{};
+  int nlev = 0;
+  hipStream_t st = nullptr;
+  Pool pool;
+  z64* U64 = nullptr;
+  z32* U32 = nullptr;
+  std::vector<Level<double>> L64;
+  std::vector<Level<float>> L32;
+  bool f32_ready = false;
+  std::vector<z64*> calib;          // smoother calibration start per coarsening
+  // dense inverse of the coarsest operator
+  z64* Minv = nullptr;
+  z64* colk = nullptr;
+  double* piv = nullptr;
+  // per-column scalars on the device: one set per CG nesting depth (the outer
+  // solve and a coarsest-level CG running inside its V-cycle)
+  int scal_cap = 0;
+  double* partial = nullptr;
+  Scal sc[2];
+  double *dc_down = nullptr, *dc_up = nullptr;
+  int* fail = nullptr;
+  double* h_scal = nullptr;         // pinned host mirrors
+  int* h_int = nullptr;
+  // Krylov vectors
+  KVecs<double> f64, c64;
+  KVecs<float> f32, c32;
+  z64* r64 = nullptr;               // defect-correction residual
+  z32 *b32 = nullptr, *e32 = nullptr;
+  size_t dc_cap = 0;
+  // setup scratch
+  z64 *gX = nullptr, *gY = nullptr, *se = nullptr, *st_ = nullptr, *sz = nullptr;
+  // counters
+  int64_t fine_applies = 0;
+  int64_t vcycles = 0;
+
+  ~Ctx() {
+    if (h_scal) (void)hipHostFree(h_scal);
+    if (h_int) (void)hipHostFree(h_int);
+  }
+};
+
+template <typename R>
+std::vector<Level<R>>& levels_of(Ctx& c);
+template <>
+std::vector<Level<double>>& levels_of<double>(Ctx& c) { return c.L64; }
+template <>
+std::vector<Level<float>>& levels_of<float>(Ctx& c) { return c.L32; }
+
+void sync(Ctx& c) { HIPCHECK(hipStreamSynchronize(c.st)); }
+void zero(void* p, size_t bytes, hipStream_t st) { HIPCHECK(hipMemsetAsync(p, 0, bytes, st)); }
+
+void ensure_scalars(Ctx& c, int nrhs) {
+  if (nrhs <= c.scal_cap) return;
+  const int cap = std::max(nrhs, 8);
+  const int nb = red_blocks(c.L64[0].n);
+  c.partial = c.pool.alloc<double>((size_t)2 * nb * cap);
+  for (auto& s : c.sc) {
+    s.bb = c.pool.alloc<double>(2 * cap);
+    s.rz = c.pool.alloc<double>(2 * cap);
+    s.pq = c.pool.alloc<double>(2 * cap);
+    s.ab = c.pool.alloc<double>(2 * cap);
+    s.rr = c.pool.alloc<double>(2 * cap);
+    s.tt = c.pool.alloc<double>(2 * cap);
+    s.active = c.pool.alloc<int>(cap);
+    s.bad = c.pool.alloc<int>(cap);
+  }
+  c.dc_down = c.pool.alloc<double>(cap);
+  c.dc_up = c.pool.alloc<double>(cap);
+  if (c.h_scal) (void)hipHostFree(c.h_scal);
+  if (c.h_int) (void)hipHostFree(c.h_int);
+  c.h_scal = nullptr;
+  c.h_int = nullptr;
+  HIPCHECK(hipHostMalloc((void**)&c.h_scal, sizeof(double) * 4 * cap, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&c.h_int, sizeof(int) * 2 * cap, hipHostMallocDefault));
+  c.scal_cap = cap;
+}
+
+template <typename R>
+void ensure_level_work(Ctx& c, int nrhs) {
+  for (auto& lv : levels_of<R>(c)) {
+    if (lv.cap >= nrhs) continue;
+    lv.cap = nrhs;
+    lv.b = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+    lv.x = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+    lv.r = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+    lv.t = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+    if (lv.fine) lv.tmp = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+  }
+}
+
+template <typename R>
+void ensure_kvecs(Ctx& c, KVecs<R>& v, size_t elems) {
+  if (v.cap >= elems) return;
+  v.r = c.pool.alloc<cpx<R>>(elems);
+  v.p = c.pool.alloc<cpx<R>>(elems);
+  v.q = c.pool.alloc<cpx<R>>(elems);
+  v.z = c.pool.alloc<cpx<R>>(elems);
+  v.t = c.pool.alloc<cpx<R>>(elems);
+  v.cap = elems;
+}
+
+// ---------------------------------------------------------------------------
+// Operators.
+// ---------------------------------------------------------------------------
+template <typename R>
+void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mode, double coef, cpx<R>* xacc,
+              const cpx<R>* aux) {
+  if (lv.fine) {
+    launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st);
+    c.fine_applies += nrhs;
+  } else {
+    launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+  }
+}
+
+template <typename R>
+void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
+  launch_restrict<R>(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.nc, lv.ldk, nrhs, c.st);
+}
+
+template <typename R>
+void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, int mode) {
+  launch_prolong<R>(lv.P, e, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.nc, lv.ldk, nrhs, mode, c.st);
+}
+
+// x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).
+template <typename R>
+void smooth(Ctx& c, Level<R>& lv, const cpx<R>* b, cpx<R>* x, int nrhs) {
+  zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  const int nu = (int)lv.coefs.size();
+  const cpx<R>* cur = b;
+  cpx<R>* bufs[2] = {lv.r, lv.t};
+  for (int k = 0; k < nu; ++k) {
+    if (k + 1 < nu) {
+      cpx<R>* nxt = bufs[k & 1];
+      apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
+      cur = nxt;
+    } else {
+      launch_axpy_const<R>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
+    }
+  }
+}
+
+template <typename R>
+void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter);
+
+// Coarsest solve: dense inverse (exact) or CG to coarsest_tol.
+template <typename R>
+void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool use_cg) {
+  auto& lv = levels_of<R>(c)[l];
+  if (!use_cg && c.Minv && l == c.nlev - 1)
+    launch_dense_apply<R>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
+  else
+    coarse_cg<R>(c, l, b, x, nrhs, c.prm.coarsest_tol, c.prm.coarsest_maxiter);
+}
+
+// One V-cycle on level l (steps 1-5 of the Multigrid section); `last` is the level
+// solved exactly.  b is read only; x receives V b.
+template <typename R>
+void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool use_cg) {
+  auto& Ls = levels_of<R>(c);
+  if (l == last) {
+    coarsest_solve<R>(c, l, b, x, nrhs, use_cg);
+    return;
+  }
+  Level<R>& lv = Ls[l];
+  Level<R>& nx = Ls[l + 1];
+  const int nu = (int)lv.coefs.size();
+  // 1. x = R^H b (= R b: the polynomial is real), tracking r = b - A x
+  zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  const cpx<R>* cur = b;
+  cpx<R>* bufs[2] = {lv.r, lv.t};
+  for (int k = 0; k < nu; ++k) {
+    cpx<R>* nxt = bufs[k & 1];
+    apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
+    cur = nxt;
+  }
+  // 2. r_c = P^H (b - A x)
+  restrict_to<R>(c, lv, cur, nx.b, nrhs);
+  // 3. e = V^(l+1) r_c
+  vcycle<R>(c, l + 1, last, nx.b, nx.x, nrhs, use_cg);
+  // 4. x = x + P e
+  prolong_from<R>(c, lv, nx.x, x, nrhs, 1);
+  // 5. x = x + R (b - A x)
+  apply_op<R>(c, lv, x, lv.r, nrhs, 2, 0.0, nullptr, b);
+  cur = lv.r;
+  cpx<R>* pb[2] = {lv.t, lv.r};
+  for (int k = 0; k < nu; ++k) {
+    if (k + 1 < nu) {
+      cpx<R>* nxt = pb[k & 1];
+      apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
+      cur = nxt;
+    } else {
+      launch_axpy_const<R>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
+    }
+  }
+  if (l == 0) c.vcycles += nrhs;
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients with per-column scalars on the device.  The host reads
+// the residual norms for the convergence test (every iteration, or every 8th
+// for the coarsest CG) and confirms convergence on the recomputed residual.
+// ---------------------------------------------------------------------------
+struct ColStats {
+  std::vector<int> iters, status;
+  std::vector<double> relres;
+};
+
+template <typename R>
+void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter, bool precond, KVecs<R>& v,
+         ColStats* cs, int check_interval, int depth) {
+  auto& lv = levels_of<R>(c)[l];
+  Scal& S = c.sc[depth];
+  const size_t n = lv.n;
+  ensure_scalars(c, nrhs);
+  const size_t bytes = (size_t)nrhs * n * sizeof(cpx<R>);
+  launch_dot<R>(b, b, n, nrhs, c.partial, S.bb, c.st);
+  HIPCHECK(hipMemcpyAsync(c.h_scal, S.bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
+  sync(c);
+  std::vector<double> hbb(nrhs), rel(nrhs, 0.0);
+  std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
+  for (int j = 0; j < nrhs; ++j) {
+    hbb[j] = c.h_scal[2 * j];
+    if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
+    if (!(hbb[j] > 0)) {
+      act[j] = 0;
+      stat[j] = SMG_OK;
+    }
+  }
+  int nact = 0;
+  for (int j = 0; j < nrhs; ++j) nact += act[j];
+  auto upload_active = [&]() {
+    for (int j = 0; j < nrhs; ++j) c.h_int[j] = act[j];
+    HIPCHECK(hipMemcpyAsync(S.active, c.h_int, sizeof(int) * nrhs, hipMemcpyHostToDevice, c.st));
+    sync(c);
+  };
+  zero(x, bytes, c.st);
+  HIPCHECK(hipMemcpyAsync(v.r, b, bytes, hipMemcpyDeviceToDevice, c.st));
+  zero(S.bad, sizeof(int) * nrhs, c.st);
+  upload_active();
+  auto precondition = [&](const cpx<R>* r, cpx<R>* z) {
+    if (precond)
+      vcycle<R>(c, l, c.nlev - 1, r, z, nrhs, c.prm.coarsest == SMG_COARSEST_CG);
+    else
+      HIPCHECK(hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, c.st));
+  };
+  if (nact > 0) {
+    precondition(v.r, v.z);
+    HIPCHECK(hipMemcpyAsync(v.p, v.z, bytes, hipMemcpyDeviceToDevice, c.st));
+    launch_dot<R>(v.r, v.z, n, nrhs, c.partial, S.rz, c.st);
+  }
+  for (int it = 1; it <= maxiter && nact > 0; ++it) {
+    apply_op<R>(c, lv, v.p, v.q, nrhs, 0, 0.0, nullptr, nullptr);
+    launch_dot<R>(v.p, v.q, n, nrhs, c.partial, S.pq, c.st);
+    launch_cg_alpha(S.rz, S.pq, S.ab, S.active, S.bad, nrhs, c.st);
+    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.partial, S.rr, c.st);
+    for (int j = 0; j < nrhs; ++j) its[j] += act[j];
+    if (it % check_interval == 0 || it == maxiter) {
+      HIPCHECK(hipMemcpyAsync(c.h_scal, S.rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
+      HIPCHECK(hipMemcpyAsync(c.h_int + nrhs, S.bad, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c.st));
+      sync(c);
+      std::vector<int> cand(nrhs, 0);
+      bool any_cand = false;
+      for (int j = 0; j < nrhs; ++j) {
+        if (!act[j]) continue;
+        if (c.h_int[nrhs + j])
+          throw Error(SMG_EBREAKDOWN, "CG breakdown (<p,Ap> <= 0 or NaN) in column " + std::to_string(j));
+        const double r2 = c.h_scal[2 * j];
+        if (!std::isfinite(r2)) throw Error(SMG_EBREAKDOWN, "CG residual is NaN/Inf");
+        if (r2 <= tol * tol * hbb[j]) {
+          cand[j] = 1;
+          any_cand = true;
+        }
+      }
+      if (any_cand) {
+        // confirm on the true residual t = b - A x
+        apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
+        launch_dot<R>(v.t, v.t, n, nrhs, c.partial, S.tt, c.st);
+        HIPCHECK(hipMemcpyAsync(c.h_scal, S.tt, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
+        sync(c);
+        bool changed = false;
+        for (int j = 0; j < nrhs; ++j) {
+          if (!cand[j]) continue;
+          const double tr = std::sqrt(c.h_scal[2 * j] / hbb[j]);
+          if (tr <= tol) {
+            act[j] = 0;
+            stat[j] = SMG_OK;
+            rel[j] = tr;
+            changed = true;
+          } else {  // replace the recursive residual by the true one and continue
+            HIPCHECK(hipMemcpyAsync(v.r + (size_t)j * n, v.t + (size_t)j * n, n * sizeof(cpx<R>),
+                                    hipMemcpyDeviceToDevice, c.st));
+          }
+        }
+        if (changed) {
+          nact = 0;
+          for (int j = 0; j < nrhs; ++j) nact += act[j];
+          upload_active();
+        }
+        if (nact == 0) break;
+      }
+    }
+    precondition(v.r, v.z);
+    launch_dot<R>(v.r, v.z, n, nrhs, c.partial, S.pq, c.st);
+    launch_cg_beta(S.pq, S.rz, S.ab, S.active, nrhs, c.st);
+    launch_xpay<R>(v.z, v.p, S.ab, n, nrhs, c.st);
+  }
+  if (nact > 0) {  // true residual of the columns that did not converge
+    apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
+    launch_dot<R>(v.t, v.t, n, nrhs, c.partial, S.tt, c.st);
+    HIPCHECK(hipMemcpyAsync(c.h_scal, S.tt, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
+    sync(c);
+    for (int j = 0; j < nrhs; ++j)
+      if (act[j]) rel[j] = std::sqrt(c.h_scal[2 * j] / hbb[j]);
+  }
+  if (cs) {
+    cs->iters = its;
+    cs->status = stat;
+    cs->relres = rel;
+  }
+}
+
+template <typename R>
+KVecs<R>& coarse_kvecs(Ctx& c);
+template <>
+KVecs<double>& coarse_kvecs<double>(Ctx& c) { return c.c64; }
+template <>
+KVecs<float>& coarse_kvecs<float>(Ctx& c) { return c.c32; }
+
+template <typename R>
+void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter) {
+  auto& lv = levels_of<R>(c)[l];
+  KVecs<R>& v = coarse_kvecs<R>(c);
+  ensure_kvecs<R>(c, v, (size_t)nrhs * lv.n);
+  ColStats cs;
+  pcg<R>(c, l, b, x, nrhs, tol, maxiter, false, v, &cs, 8, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchy construction (FP64).
+// ---------------------------------------------------------------------------
+double dev_dot_re(Ctx& c, const z64* a, const z64* b, size_t n) {
+  ensure_scalars(c, 1);
+  launch_dot<double>(a, b, n, 1, c.partial, c.sc[1].tt, c.st);
+  HIPCHECK(hipMemcpyAsync(c.h_scal, c.sc[1].tt, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  sync(c);
+  return c.h_scal[0];
+}
+
+// Smoother calibration (Results section): nu MR steps from the stored start
+// vector, alpha_k = <A r, r> / <A r, A r>, frozen as c_k = omega * alpha_k.
+void calibrate(Ctx& c, int l) {
+  auto& lv = c.L64[l];
+  lv.coefs.clear();
+  HIPCHECK(hipMemcpyAsync(lv.r, c.calib[l], lv.n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  for (int k = 0; k < c.prm.smoother_steps; ++k) {
+    apply_op<double>(c, lv, lv.r, lv.t, 1, 0, 0.0, nullptr, nullptr);
+    const double qr = dev_dot_re(c, lv.t, lv.r, lv.n);
+    const double qq = dev_dot_re(c, lv.t, lv.t, lv.n);
+    if (!(qq > 0) || !std::isfinite(qr)) throw Error(SMG_ESETUP, "smoother calibration broke down");
+    const double ck = c.prm.smoother_omega * qr / qq;
+    lv.coefs.push_back(ck);
+    launch_axpy_const<double>(lv.r, lv.t, -ck, lv.n, 1, c.st);
+  }
+}
+
+// Set the number of vectors in use between level l and l+1.
+void set_nc(Ctx& c, int l, int nc) {
+  c.L64[l].nc = nc;
+  auto& nx = c.L64[l + 1];
+  nx.dof = nc;
+  nx.n = (size_t)nx.lx * nx.lt * nc;
+}
+
+// Eq. 2 by colouring: for each colour and vector k, apply A^(l) to the sum of the
+// k-th prolongator columns of that colour and restrict the image aggregate by
+// aggregate; each restriction is column k of one link block.
+void galerkin(Ctx& c, int l) {
+  auto& lv = c.L64[l];
+  auto& nx = c.L64[l + 1];
+  const int nc = lv.nc;
+  const int cx = lv.lx / lv.bx, ct = lv.lt / lv.bt;
+  const size_t nK = (size_t)cx * ct;
+  zero(nx.L, 9 * nK * nc * nc * sizeof(z64), c.st);
+  const int ncx = colors_along(cx), nct = colors_along(ct);
+  for (int a = 0; a < ncx; ++a)
+    for (int bcol = 0; bcol < nct; ++bcol)
+      for (int k = 0; k < nc; ++k) {
+        launch_color_scatter(lv.P, c.gX, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, a, bcol, c.st);
+        apply_op<double>(c, lv, c.gX, c.gY, 1, 0, 0.0, nullptr, nullptr);
+        launch_color_project(lv.P, c.gY, nx.L, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, nc, lv.ldk, k, a, bcol, c.st);
+      }
+}
+
+void check_fail(Ctx& c, const char* what) {
+  HIPCHECK(hipMemcpyAsync(c.h_int, c.fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  sync(c);
+  if (c.h_int[0]) throw Error(SMG_ESETUP, what);
+}
+
+void gs_append(Ctx& c, int l, const z64* v, int k) {
+  auto& lv = c.L64[l];
+  zero(c.fail, sizeof(int), c.st);
+  launch_gs_append((double*)lv.P, v, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, c.fail, c.st);
+  check_fail(c, "block Gram-Schmidt: candidate vector is degenerate on an aggregate");
+}
+
+// Dense inverse of the coarsest operator by Gauss-Jordan elimination (FP64).
+void build_coarsest_inverse(Ctx& c) {
+  if (c.nlev < 2 || c.prm.coarsest != SMG_COARSEST_DIRECT) return;
+  auto& lv = c.L64[c.nlev - 1];
+  const int n = (int)lv.n;
+  if (!c.Minv) {
+    c.Minv = c.pool.alloc<z64>((size_t)n * n);
+    c.colk = c.pool.alloc<z64>(n);
+    c.piv = c.pool.alloc<double>(1);
+  }
+  launch_coarse_to_dense(lv.L, c.Minv, lv.lx, lv.lt, lv.dof, c.st);
+  zero(c.fail, sizeof(int), c.st);
+  for (int k = 0; k < n; ++k) launch_gj_step(c.Minv, n, k, c.colk, c.piv, c.fail, c.st);
+  check_fail(c, "coarsest operator is not positive definite");
+}
+
+void scale_to_unit(Ctx& c, z64* e, size_t n) {
+  const double nrm = std::sqrt(dev_dot_re(c, e, e, n));
+  if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(SMG_ESETUP, "candidate vector vanished or is not finite");
+  launch_scale_const<double>(e, 1.0 / nrm, n, 1, c.st);
+}
+
+// Adaptive setup of coarsening l (Adaptive Multigrid section).  rnd holds the
+// 1 + nv random starts of this level (row 0 was used for the calibration).
+void adaptive_level(Ctx& c, int l, const z64* rnd) {
+  auto& lv = c.L64[l];
+  const int nv = c.prm.nv[l];
+  const size_t n = lv.n;
+  // first candidate: relaxation alone on A e = 0 (Eq. 4 with the frozen smoother)
+  HIPCHECK(hipMemcpyAsync(c.se, rnd + n, n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  for (int it = 0; it < c.prm.setup_iters; ++it) {
+    apply_op<double>(c, lv, c.se, c.st_, 1, 0, 0.0, nullptr, nullptr);
+    smooth<double>(c, lv, c.st_, c.sz, 1);
+    launch_axpy_const<double>(c.se, c.sz, -1.0, n, 1, c.st);
+    scale_to_unit(c, c.se, n);
+  }
+  set_nc(c, l, 1);
+  gs_append(c, l, c.se, 0);
+  galerkin(c, l);
+  // further candidates: the current two-level V-cycle as error propagator
+  for (int k = 1; k < nv; ++k) {
+    HIPCHECK(hipMemcpyAsync(c.se, rnd + (size_t)(1 + k) * n, n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+    for (int it = 0; it < c.prm.setup_iters; ++it) {
+      apply_op<double>(c, lv, c.se, c.st_, 1, 0, 0.0, nullptr, nullptr);
+      vcycle<double>(c, l, l + 1, c.st_, c.sz, 1, true);
+      launch_axpy_const<double>(c.se, c.sz, -1.0, n, 1, c.st);
+      scale_to_unit(c, c.se, n);
+    }
+    gs_append(c, l, c.se, k);
+    set_nc(c, l, k + 1);
+    galerkin(c, l);
+  }
+}
+
+void validate(const smg_params& p) {
+  if (p.lx <= 0 || p.lt <= 0) throw Error(SMG_EINVAL, "lattice extents must be positive");
+  if (p.levels < 1 || p.levels > SMG_MAXLEV) throw Error(SMG_EINVAL, "levels must be in [1, SMG_MAXLEV]");
+  if (p.smoother_steps < 1 || p.smoother_steps > 64) throw Error(SMG_EINVAL, "smoother_steps must be in [1, 64]");
+  if (!(p.smoother_omega > 0)) throw Error(SMG_EINVAL, "smoother_omega must be positive");
+  if (p.setup_iters < 0) throw Error(SMG_EINVAL, "setup_iters must be >= 0");
+  if (!(p.coarsest_tol > 0) || p.coarsest_maxiter < 1) throw Error(SMG_EINVAL, "bad coarsest CG settings");
+  if (!std::isfinite(p.mass)) throw Error(SMG_EINVAL, "mass must be finite");
+  if (p.coarsest != SMG_COARSEST_DIRECT && p.coarsest != SMG_COARSEST_CG) throw Error(SMG_EINVAL, "bad coarsest");
+  int lx = p.lx, lt = p.lt, dof = 2;
+  for (int l = 0; l + 1 < p.levels; ++l) {
+    const int bx = p.block[l][0], bt = p.block[l][1];
+    if (bx < 1 || bt < 1) throw Error(SMG_EINVAL, "block extents must be positive");
+    if (lx % bx || lt % bt) throw Error(SMG_ESHAPE, "lattice extent not divisible by the block extent");
+    const int nv = p.nv[l];
+    if (nv < 1 || nv > 64) throw Error(SMG_EINVAL, "nv must be in [1, 64]");
+    if (nv > bx * bt * dof) throw Error(SMG_EINVAL, "nv exceeds the variables of an aggregate");
+    if (bx * bt * dof > 1024) throw Error(SMG_EINVAL, "aggregates larger than 1024 variables are not supported");
+    lx /= bx;
+    lt /= bt;
+    dof = nv;
+  }
+  if ((size_t)p.lx * p.lt * 2 > (size_t)1 << 30) throw Error(SMG_EINVAL, "lattice too large");
+}
+
+Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st) {
+  if (!gauge || !prm) throw Error(SMG_EINVAL, "null gauge or params");
+  validate(*prm);
+  Ctx* c = new Ctx();
+  try {
+    c->prm = *prm;
+    c->st = st;
+    c->nlev = prm->levels;
+    const int lx = prm->lx, lt = prm->lt;
+    const size_t V = (size_t)lx * lt;
+    c->U64 = c->pool.alloc<z64>(2 * V);
+    launch_prepare_links<double>((const z64*)gauge, c->U64, lx, lt, prm->t_antiperiodic, st);
+    c->L64.resize(c->nlev);
+    c->L64[0].lx = lx;
+    c->L64[0].lt = lt;
+    c->L64[0].dof = 2;
+    c->L64[0].n = 2 * V;
+    c->L64[0].fine = true;
+    c->L64[0].U = c->U64;
+    c->L64[0].diag = 2.0 + prm->mass;
+    size_t maxn = 2 * V;
+    for (int l = 1; l < c->nlev; ++l) {
+      auto& pv = c->L64[l - 1];
+      auto& lv = c->L64[l];
+      lv.lx = pv.lx / prm->block[l - 1][0];
+      lv.lt = pv.lt / prm->block[l - 1][1];
+      lv.dof = prm->nv[l - 1];
+      lv.n = (size_t)lv.lx * lv.lt * lv.dof;
+      lv.L = c->pool.alloc<z64>(9 * (size_t)lv.lx * lv.lt * lv.dof * lv.dof);
+      pv.bx = prm->block[l - 1][0];
+      pv.bt = prm->block[l - 1][1];
+      pv.nc = lv.dof;
+      pv.ldk = lv.dof;
+      pv.P = c->pool.alloc<z64>((size_t)lv.lx * lv.lt * lv.dof * pv.bx * pv.bt * pv.dof);
+    }
+    c->fail = c->pool.alloc<int>(4);
+    ensure_scalars(*c, 1);
+    ensure_level_work<double>(*c, 1);
+    if (c->nlev > 1) {
+      c->gX = c->pool.alloc<z64>(maxn);
+      c->gY = c->pool.alloc<z64>(maxn);
+      c->se = c->pool.alloc<z64>(maxn);
+      c->st_ = c->pool.alloc<z64>(maxn);
+      c->sz = c->pool.alloc<z64>(maxn);
+    }
+    return c;
+  } catch (...) {
+    delete c;
+    throw;
+  }
+}
+
+// FP32 copy of the hierarchy for the mixed-precision inner solves.
+void ensure_f32(Ctx& c) {
+  if (c.f32_ready) return;
+  const bool fresh = c.L32.empty();
+  if (fresh) {
+    c.L32.resize(c.nlev);
+    c.U32 = c.pool.alloc<z32>(c.L64[0].n);  // 2 links per site, as many as vector entries
+  }
+  launch_links_convert<float>(c.U64, c.U32, c.L64[0].n, c.st);  // 2V links == n entries
+  for (int l = 0; l < c.nlev; ++l) {
+    auto& a = c.L64[l];
+    auto& b = c.L32[l];
+    b.lx = a.lx; b.lt = a.lt; b.dof = a.dof; b.n = a.n; b.fine = a.fine; b.diag = a.diag;
+    b.bx = a.bx; b.bt = a.bt; b.nc = a.nc; b.ldk = a.ldk; b.coefs = a.coefs;
+    if (a.fine) b.U = c.U32;
+    if (a.L) {
+      const size_t nl = 9 * (size_t)a.lx * a.lt * a.dof * a.dof;
+      if (fresh) b.L = c.pool.alloc<z32>(nl);
+      launch_links_convert<float>(a.L, b.L, nl, c.st);
+    }
+    if (a.P) {
+      const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * a.bx * a.bt * a.dof;
+      if (fresh) b.P = c.pool.alloc<z32>(np);
+      launch_links_convert<float>(a.P, b.P, np, c.st);
+    }
+  }
+  c.f32_ready = true;
+}
+
+void finish_setup(Ctx& c) {
+  build_coarsest_inverse(c);
+  c.f32_ready = false;
+  sync(c);
+}
+
+size_t level_offset_randoms(const Ctx& c, int l, bool with_calib) {
+  size_t off = 0;
+  for (int q = 0; q < l; ++q) off += (size_t)(c.prm.nv[q] + (with_calib ? 1 : 0)) * c.L64[q].n;
+  return off;
+}
+
+size_t level_offset_plain(const Ctx& c, int l) {
+  size_t off = 0;
+  for (int q = 0; q < l; ++q) off += c.L64[q].n;
+  return off;
+}
+
+// Stable C-side view of stats.
+void fill_stats(smg_stats* s, int nrhs, const ColStats& cs, int refinements, int64_t applies, int64_t vcyc,
+                double secs) {
+  if (!s) return;
+  for (int j = 0; j < nrhs; ++j) {
+    s[j].status = cs.status.empty() ? SMG_OK : cs.status[j];
+    s[j].iterations = cs.iters.empty() ? 0 : cs.iters[j];
+    s[j].refinements = refinements;
+    s[j].vcycles = (int32_t)(vcyc / std::max(nrhs, 1));
+    s[j].fine_applies = applies / std::max(nrhs, 1);
+    s[j].true_relres = cs.relres.empty() ? 0.0 : cs.relres[j];
+    s[j].seconds = secs;
+  }
+}
+
+int fail_code(const Error& e) {
+  g_last_error = e.what();
+  return e.code;
+}
+
+Ctx* H(smg_handle h) {
+  if (!h) throw Error(SMG_EINVAL, "null handle");
+  return reinterpret_cast<Ctx*>(h);
+}
+
+int check_level(Ctx* c, int level) {
+  if (level < 0 || level >= c->nlev) throw Error(SMG_EINVAL, "level out of range");
+  return level;
+}
+
+void check_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 4096) throw Error(SMG_EINVAL, "nrhs must be in [1, 4096]");
+}
+
+}  // namespace
+}  // namespace smg
+
+using namespace smg;
+
+#define API_BEGIN try {
+#define API_END                                   \
+  }                                               \
+  catch (const Error& e) {                        \
+    return fail_code(e);                          \
+  }                                               \
+  catch (const std::exception& e) {               \
+    g_last_error = e.what();                      \
+    return SMG_EINVAL;                            \
+  }
+
+extern "C" {
+
+void smg_default_params(smg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->lx = 32;
+  p->lt = 32;
+  p->mass = 0.1;
+  p->levels = 2;
+  for (int l = 0; l < SMG_MAXLEV; ++l) {
+    p->block[l][0] = 4;
+    p->block[l][1] = 4;
+    p->nv[l] = 8;
+  }
+  p->setup_iters = 5;
+  p->smoother_steps = 4;
+  p->smoother_omega = 0.8;
+  p->t_antiperiodic = 1;
+  p->coarsest = SMG_COARSEST_DIRECT;
+  p->coarsest_tol = 1e-12;
+  p->coarsest_maxiter = 10000;
+  p->inner_tol = 1e-5;
+  p->seed = 1;
+}
+
+int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
+              smg_handle* out) {
+  API_BEGIN
+  if (!out) throw Error(SMG_EINVAL, "null output handle");
+  hipStream_t st = (hipStream_t)stream;
+  Ctx* c = create(gauge, params, st);
+  try {
+    c->calib.resize(c->nlev);
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      const size_t n = c->L64[l].n;
+      const int nv = c->prm.nv[l];
+      z64* rnd = c->pool.alloc<z64>((1 + (size_t)nv) * n);
+      if (randoms) {
+        HIPCHECK(hipMemcpyAsync(rnd, (const z64*)randoms + level_offset_randoms(*c, l, true),
+                                (1 + (size_t)nv) * n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      } else {
+        for (int row = 0; row <= nv; ++row)
+          launch_random_gaussian(rnd + (size_t)row * n, n, c->prm.seed, (uint64_t)l * 4096 + row, st);
+      }
+      c->calib[l] = rnd;  // row 0
+      calibrate(*c, l);
+      adaptive_level(*c, l, rnd);
+    }
+    finish_setup(*c);
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  *out = reinterpret_cast<smg_handle>(c);
+  return SMG_OK;
+  API_END
+}
+
+int smg_setup_from_vectors(const double* gauge, const smg_params* params, const double* vectors, const double* calib,
+                           void* stream, smg_handle* out) {
+  API_BEGIN
+  if (!out || !vectors || !calib) throw Error(SMG_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  Ctx* c = create(gauge, params, st);
+  try {
+    c->calib.resize(c->nlev);
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      const size_t n = c->L64[l].n;
+      const int nv = c->prm.nv[l];
+      z64* cb = c->pool.alloc<z64>(n);
+      HIPCHECK(hipMemcpyAsync(cb, (const z64*)calib + level_offset_plain(*c, l), n * sizeof(z64),
+                              hipMemcpyDeviceToDevice, st));
+      c->calib[l] = cb;
+      calibrate(*c, l);
+      const z64* vl = (const z64*)vectors + level_offset_randoms(*c, l, false);
+      for (int k = 0; k < nv; ++k) gs_append(*c, l, vl + (size_t)k * n, k);
+      set_nc(*c, l, nv);
+      galerkin(*c, l);
+    }
+    finish_setup(*c);
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  *out = reinterpret_cast<smg_handle>(c);
+  return SMG_OK;
+  API_END
+}
+
+int smg_set_mass(smg_handle h, double mass, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  if (!std::isfinite(mass)) throw Error(SMG_EINVAL, "mass must be finite");
+  c->st = (hipStream_t)stream;
+  c->prm.mass = mass;
+  c->L64[0].diag = 2.0 + mass;
+  for (int l = 0; l + 1 < c->nlev; ++l) {
+    calibrate(*c, l);
+    galerkin(*c, l);
+  }
+  finish_setup(*c);
+  return SMG_OK;
+  API_END
+}
+
+int smg_apply_D(smg_handle h, const double* x, double* y, int32_t nrhs, int32_t dagger, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!x || !y) throw Error(SMG_EINVAL, "null vector");
+  auto& lv = c->L64[0];
+  launch_wilson<double>(lv.U, (const z64*)x, (z64*)y, lv.lx, lv.lt, lv.diag, nrhs, dagger != 0, (hipStream_t)stream);
+  return SMG_OK;
+  API_END
+}
+
+int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (!x || !y) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  ensure_level_work<double>(*c, nrhs);
+  apply_op<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs, 0, 0.0, nullptr, nullptr);
+  return SMG_OK;
+  API_END
+}
+
+int smg_apply_A(smg_handle h, const double* x, double* y, int32_t nrhs, void* stream) {
+  return smg_apply_level(h, 0, x, y, nrhs, stream);
+}
+
+int smg_restrict(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no coarser level");
+  if (!x || !y) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  restrict_to<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs);
+  return SMG_OK;
+  API_END
+}
+
+int smg_prolong(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no coarser level");
+  if (!x || !y) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  prolong_from<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs, 0);
+  return SMG_OK;
+  API_END
+}
+
+int smg_smooth(smg_handle h, int32_t level, const double* b, double* x, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "the coarsest level has no smoother");
+  if (!x || !b) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  ensure_level_work<double>(*c, nrhs);
+  smooth<double>(*c, c->L64[level], (const z64*)b, (z64*)x, nrhs);
+  return SMG_OK;
+  API_END
+}
+
+int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!x || !b) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  ensure_level_work<double>(*c, nrhs);
+  vcycle<double>(*c, 0, c->nlev - 1, (const z64*)b, (z64*)x, nrhs, c->prm.coarsest == SMG_COARSEST_CG);
+  return SMG_OK;
+  API_END
+}
+
+int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol, int32_t maxiter,
+              int32_t precision, void* stream, smg_stats* stats) {
+  API_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!rhs || !x) throw Error(SMG_EINVAL, "null vector");
+  if (!(tol > 0) || maxiter < 1) throw Error(SMG_EINVAL, "tol must be > 0 and maxiter >= 1");
+  if (precision != SMG_FP64 && precision != SMG_MIXED) throw Error(SMG_EINVAL, "bad precision");
+  c->st = (hipStream_t)stream;
+  const int64_t fa0 = c->fine_applies, vc0 = c->vcycles;
+  const bool mg = c->nlev > 1;
+  auto& lv = c->L64[0];
+  const size_t n = lv.n;
+  ColStats cs;
+  int refinements = 1;
+  if (precision == SMG_FP64) {
+    ensure_level_work<double>(*c, nrhs);
+    ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * n);
+    pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, mg, c->f64, &cs, 1, 0);
+  } else {
+    // FP64 defect correction around FP32 MG-CG.
+    ensure_f32(*c);
+    ensure_level_work<float>(*c, nrhs);
+    ensure_level_work<double>(*c, nrhs);
+    ensure_kvecs<float>(*c, c->f32, (size_t)nrhs * n);
+    ensure_scalars(*c, nrhs);
+    if (c->dc_cap < (size_t)nrhs * n) {
+      c->r64 = c->pool.alloc<z64>((size_t)nrhs * n);
+      c->b32 = c->pool.alloc<z32>((size_t)nrhs * n);
+      c->e32 = c->pool.alloc<z32>((size_t)nrhs * n);
+      c->dc_cap = (size_t)nrhs * n;
+    }
+    const size_t bytes = (size_t)nrhs * n * sizeof(z64);
+    const z64* b = (const z64*)rhs;
+    z64* xx = (z64*)x;
+    zero(xx, bytes, c->st);
+    HIPCHECK(hipMemcpyAsync(c->r64, b, bytes, hipMemcpyDeviceToDevice, c->st));
+    launch_dot<double>(b, b, n, nrhs, c->partial, c->sc[1].bb, c->st);
+    HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
+    sync(*c);
+    std::vector<double> hbb(nrhs), rel(nrhs, 0.0), down(nrhs), up(nrhs);
+    std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
+    for (int j = 0; j < nrhs; ++j) {
+      hbb[j] = c->h_scal[2 * j];
+      if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
+      if (!(hbb[j] > 0)) { act[j] = 0; stat[j] = SMG_OK; }
+    }
+    refinements = 0;
+    int used = 0;
+    while (true) {
+      launch_dot<double>(c->r64, c->r64, n, nrhs, c->partial, c->sc[1].rr, c->st);
+      HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
+      sync(*c);
+      int nact = 0;
+      for (int j = 0; j < nrhs; ++j) {
+        if (!act[j]) { down[j] = 0; up[j] = 0; continue; }
+        const double rr = c->h_scal[2 * j];
+        if (!std::isfinite(rr)) throw Error(SMG_EBREAKDOWN, "defect correction residual is NaN/Inf");
+        rel[j] = std::sqrt(rr / hbb[j]);
+        if (rel[j] <= tol) { act[j] = 0; stat[j] = SMG_OK; down[j] = 0; up[j] = 0; continue; }
+        down[j] = 1.0 / std::sqrt(rr);
+        up[j] = std::sqrt(rr);
+        ++nact;
+      }
+      if (nact == 0 || used >= maxiter) break;
+      for (int j = 0; j < nrhs; ++j) {
+        c->h_scal[j] = down[j];
+        c->h_scal[nrhs + j] = up[j];
+      }
+      HIPCHECK(hipMemcpyAsync(c->dc_down, c->h_scal, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->st));
+      HIPCHECK(hipMemcpyAsync(c->dc_up, c->h_scal + nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->st));
+      launch_scale_down(c->r64, c->b32, c->dc_down, n, nrhs, c->st);
+      sync(*c);
+      ColStats inner;
+      // The inner solve's own convergence test uses inner_tol; its limit is what is
+      // left of maxiter.
+      pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0);
+      int maxit = 0;
+      for (int j = 0; j < nrhs; ++j) {
+        if (down[j] != 0) its[j] += inner.iters[j];
+        maxit = std::max(maxit, inner.iters[j]);
+      }
+      used += std::max(maxit, 1);
+      launch_scale_up_add(xx, c->e32, c->dc_up, n, nrhs, c->st);
+      apply_op<double>(*c, lv, xx, c->r64, nrhs, 2, 0.0, nullptr, b);
+      ++refinements;
+    }
+    cs.iters = its;
+    cs.status = stat;
+    cs.relres = rel;
+  }
+  sync(*c);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(stats, nrhs, cs, refinements, c->fine_applies - fa0, c->vcycles - vc0, secs);
+  for (int j = 0; j < nrhs; ++j)
+    if (cs.status[j] != SMG_OK) return SMG_NOTCONV;
+  return SMG_OK;
+  API_END
+}
+
+int smg_cg(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol, int32_t maxiter, void* stream,
+           smg_stats* stats) {
+  API_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!rhs || !x) throw Error(SMG_EINVAL, "null vector");
+  if (!(tol > 0) || maxiter < 1) throw Error(SMG_EINVAL, "tol must be > 0 and maxiter >= 1");
+  c->st = (hipStream_t)stream;
+  const int64_t fa0 = c->fine_applies;
+  ensure_level_work<double>(*c, nrhs);
+  ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * c->L64[0].n);
+  ColStats cs;
+  pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, false, c->f64, &cs, 1, 0);
+  sync(*c);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(stats, nrhs, cs, 1, c->fine_applies - fa0, 0, secs);
+  for (int j = 0; j < nrhs; ++j)
+    if (cs.status[j] != SMG_OK) return SMG_NOTCONV;
+  return SMG_OK;
+  API_END
+}
+
+int smg_level_info(smg_handle h, int32_t level, int32_t* lx, int32_t* lt, int32_t* dof) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  if (lx) *lx = c->L64[level].lx;
+  if (lt) *lt = c->L64[level].lt;
+  if (dof) *dof = c->L64[level].dof;
+  return SMG_OK;
+  API_END
+}
+
+int smg_get_prolongator(smg_handle h, int32_t level, double* out, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no prolongator below the coarsest level");
+  if (!out) throw Error(SMG_EINVAL, "null output");
+  auto& a = c->L64[level];
+  const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * a.bx * a.bt * a.dof;
+  HIPCHECK(hipMemcpyAsync(out, a.P, np * sizeof(z64), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  return SMG_OK;
+  API_END
+}
+
+int smg_get_coarse_links(smg_handle h, int32_t level, double* out, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  if (level < 1) throw Error(SMG_EINVAL, "level 0 has no coarse links");
+  if (!out) throw Error(SMG_EINVAL, "null output");
+  auto& a = c->L64[level];
+  launch_links_export(a.L, (z64*)out, a.lx * a.lt, a.dof, (hipStream_t)stream);
+  HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  return SMG_OK;
+  API_END
+}
+
+int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  if (!out) throw Error(SMG_EINVAL, "null output");
+  auto& a = c->L64[level];
+  for (size_t k = 0; k < a.coefs.size(); ++k) out[k] = a.coefs[k];
+  return SMG_OK;
+  API_END
+}
+
+int smg_memory_bytes(smg_handle h, size_t* bytes) {
+  API_BEGIN
+  Ctx* c = H(h);
+  if (!bytes) throw Error(SMG_EINVAL, "null output");
+  *bytes = c->pool.bytes;
+  return SMG_OK;
+  API_END
+}
+
+void smg_destroy(smg_handle h) {
+  if (!h) return;
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+}
+
+const char* smg_strerror(int code) {
+  switch (code) {
+    case SMG_OK: return "success";
+    case SMG_NOTCONV: return "not converged within maxiter";
+    case SMG_EINVAL: return "invalid argument";
+    case SMG_ESHAPE: return "lattice extents not divisible by the block extents";
+    case SMG_ENOMEM: return "device out of memory";
+    case SMG_EDEVICE: return "HIP runtime error";
+    case SMG_EBREAKDOWN: return "numerical breakdown (NaN/Inf or loss of positive definiteness)";
+    case SMG_ESETUP: return "setup failed (degenerate aggregate or coarsest factorisation)";
+    default: return "unknown error code";
+  }
+}
+
+const char* smg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

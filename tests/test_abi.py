@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed): the shared library loads and
+exports every entry point that include/smg.h declares, the ctypes mirrors of the
+parameter and statistics structs have the C layout, and error codes map to text."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"^(?:int|void|const char\*)\s+(smg_\w+)\s*\(", text, re.M)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("smg_setup", "smg_solve", "smg_apply_A", "smg_apply_D", "smg_set_mass", "smg_vcycle",
+                     "smg_restrict", "smg_prolong", "smg_smooth", "smg_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"missing exports: {missing}"
+
+
+def test_struct_layouts_match_c():
+    """Offsets of the ctypes mirrors equal the C layout (natural alignment)."""
+    import paper_0710_3612_amd as smg
+
+    p = smg.Params
+    assert p.mass.offset == 8
+    assert p.block.offset == 20
+    assert p.nv.offset == 20 + 6 * 2 * 4
+    assert ctypes.sizeof(p) % 8 == 0
+    s = smg.Stats
+    assert s.fine_applies.offset == 16
+    assert ctypes.sizeof(s) == 40
+
+
+def test_default_params_and_strerror():
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    p = smg.Params()
+    lib.smg_default_params(ctypes.byref(p))
+    assert (p.levels, p.smoother_steps, p.setup_iters) == (2, 4, 5)
+    assert abs(p.smoother_omega - 0.8) < 1e-15
+    assert p.block[0][0] == 4 and p.nv[0] == 8
+    assert lib.smg_strerror(-2).decode().startswith("lattice extents")
+    assert lib.smg_strerror(1).decode().startswith("not converged")
+
+
+def test_setup_rejects_bad_shapes_without_touching_the_device():
+    """Parameter validation happens before any device call."""
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    p = smg.make_params(30, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[8])
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -2
+    assert "divisible" in lib.smg_last_error().decode()
+    p = smg.make_params(32, 32, 0.1, levels=2, blocks=[(2, 2)], nv=[9])
+    assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    p = smg.make_params(32, 32, float("nan"))
+    assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert lib.smg_setup(None, ctypes.byref(p), None, None, ctypes.byref(h)) == -1

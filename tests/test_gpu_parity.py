@@ -1,0 +1,301 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+FP64 operator applications must agree to 1e-12 relative (max-norm over the
+output); solves must reach a true residual <= 1e-10 recomputed by the oracle's own
+sparse A on the downloaded solution.  Lattices are small enough for the oracle to
+finish in seconds but span several thread blocks and end on a ragged tail.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import multigrid as mg
+from oracle.wilson import dirac_matrix, normal_matrix
+
+pytestmark = pytest.mark.gpu
+
+TOL_APPLY = 1e-12
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def field(lx, lt, seed, beta=3.0, sweeps=20):
+    return synth.links_from_angles(synth.metropolis_u1(lx, lt, beta, sweeps, seed))
+
+
+def smg_mod():
+    import paper_0710_3612_amd as smg
+
+    return smg
+
+
+def hierarchy_inputs(lx, lt, blocks, nvs, seed):
+    """Near-null vectors and calibration starts per level, shared by both sides."""
+    shapes = synth.level_shapes(lx, lt, blocks, nvs)
+    vecs, calib = [], []
+    for l, nv in enumerate(nvs):
+        cx, ct, dof = shapes[l]
+        n = cx * ct * dof
+        vecs.append(synth.gaussian((nv, n), seed * 100 + l))
+        calib.append(synth.gaussian(n, seed * 100 + 50 + l))
+    return vecs, calib
+
+
+def links_from_sparse(Ac, cx, ct, nc):
+    """Oracle coarse matrix -> [K, 9, nc, nc] link blocks (coarse extents >= 3)."""
+    A = Ac.toarray()
+    out = np.zeros((cx * ct, 9, nc, nc), dtype=np.complex128)
+    for K in range(cx * ct):
+        kt, kx = divmod(K, cx)
+        for D in range(9):
+            dt, dx = D // 3 - 1, D % 3 - 1
+            Kn = ((kt + dt) % ct) * cx + (kx + dx) % cx
+            out[K, D] = A[K * nc:(K + 1) * nc, Kn * nc:(Kn + 1) * nc]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Fine operators
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lx,lt,nrhs", [(30, 26, 3), (64, 48, 1), (8, 4, 2)])
+def test_apply_D_and_A(cuda, lx, lt, nrhs):
+    smg = smg_mod()
+    U = field(lx, lt, seed=lx + lt)
+    m = 0.07
+    p = smg.make_params(lx, lt, m, levels=1)
+    s = smg.Solver(dev(U), p)
+    x = synth.gaussian((nrhs, 2 * lx * lt), 3)
+    D = dirac_matrix(U, m)
+    A = normal_matrix(U, m)
+    yd = host(s.apply_D(dev(x))).reshape(nrhs, -1)
+    yh = host(s.apply_D(dev(x), dagger=True)).reshape(nrhs, -1)
+    ya = host(s.apply_A(dev(x))).reshape(nrhs, -1)
+    for j in range(nrhs):
+        assert rel_err(yd[j], D @ x[j]) <= TOL_APPLY
+        assert rel_err(yh[j], D.conj().T @ x[j]) <= TOL_APPLY
+        assert rel_err(ya[j], A @ x[j]) <= TOL_APPLY
+    s.close()
+
+
+def test_apply_periodic_bc(cuda):
+    smg = smg_mod()
+    lx, lt = 16, 12
+    U = field(lx, lt, seed=5)
+    p = smg.make_params(lx, lt, -0.3, levels=1, t_antiperiodic=False)
+    s = smg.Solver(dev(U), p)
+    x = synth.gaussian(2 * lx * lt, 4)
+    assert rel_err(host(s.apply_D(dev(x))), dirac_matrix(U, -0.3, antiperiodic_t=False) @ x) <= TOL_APPLY
+
+
+# ---------------------------------------------------------------------------
+# Hierarchy from given vectors: every step of the V-cycle
+# ---------------------------------------------------------------------------
+
+CASES = [
+    # lx, lt, blocks, nvs, mass
+    (32, 24, [(4, 4), (2, 2)], [6, 5], 0.05),
+    (24, 24, [(4, 4)], [8], 0.1),
+    (40, 24, [(4, 2), (2, 3)], [4, 4], 0.2),
+]
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)))
+def pair(request):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    smg = smg_mod()
+    lx, lt, blocks, nvs, m = CASES[request.param]
+    U = field(lx, lt, seed=request.param + 1)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, request.param + 7)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8)
+    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs)
+    s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])),
+                   calib=dev(np.concatenate(calib)))
+    yield dict(U=U, A=A, h=h, s=s, lx=lx, lt=lt, blocks=blocks, nvs=nvs, m=m, calib=calib)
+    s.close()
+
+
+def test_smoother_coefficients(pair):
+    h, s = pair["h"], pair["s"]
+    for l in range(len(pair["blocks"])):
+        np.testing.assert_allclose(s.smoother_coefs(l), h.levels[l].coefs, rtol=1e-12)
+
+
+def test_prolongator(pair):
+    h, s = pair["h"], pair["s"]
+    for l in range(len(pair["blocks"])):
+        assert rel_err(host(s.prolongator(l)), h.levels[l].U) <= 1e-12
+
+
+def test_coarse_links(pair):
+    h, s = pair["h"], pair["s"]
+    for l in range(1, len(pair["blocks"]) + 1):
+        cx, ct, nc = s.level_info(l)
+        ref = links_from_sparse(h.levels[l].A, cx, ct, nc)
+        assert rel_err(host(s.coarse_links(l)), ref) <= 1e-12
+
+
+def test_transfer_and_coarse_apply(pair):
+    h, s = pair["h"], pair["s"]
+    for l in range(len(pair["blocks"])):
+        n = s.level_size(l)
+        nc = s.level_size(l + 1)
+        P = h.levels[l].P
+        x = synth.gaussian((2, n), 11 + l)
+        e = synth.gaussian((2, nc), 13 + l)
+        r = host(s.restrict(l, dev(x))).reshape(2, -1)
+        pe = host(s.prolong(l, dev(e))).reshape(2, -1)
+        Al = h.levels[l].A
+        ya = host(s.apply_level(l, dev(x))).reshape(2, -1)
+        rb = host(s.smooth(l, dev(x))).reshape(2, -1)
+        for j in range(2):
+            assert rel_err(r[j], P.conj().T @ x[j]) <= 1e-12
+            assert rel_err(pe[j], P @ e[j]) <= 1e-12
+            assert rel_err(ya[j], Al @ x[j]) <= 1e-12
+            assert rel_err(rb[j], mg.smoother_apply(Al, h.levels[l].coefs, x[j])) <= 1e-11
+        Ac = h.levels[l + 1].A
+        yc = host(s.apply_level(l + 1, dev(e))).reshape(2, -1)
+        for j in range(2):
+            assert rel_err(yc[j], Ac @ e[j]) <= 1e-12
+
+
+def test_vcycle(pair):
+    h, s = pair["h"], pair["s"]
+    n = s.level_size(0)
+    b = synth.gaussian((3, n), 17)
+    x = host(s.vcycle(dev(b))).reshape(3, -1)
+    for j in range(3):
+        assert rel_err(x[j], mg.vcycle(h, 0, b[j])) <= 1e-11
+
+
+def test_mgcg_solve_fp64_and_mixed(pair):
+    smg = smg_mod()
+    U, A, s, m = pair["U"], pair["A"], pair["s"], pair["m"]
+    n = s.level_size(0)
+    b = synth.gaussian((2, n), 19)
+    Dm = dirac_matrix(U, m)
+    rhs = np.stack([Dm.conj().T @ b[j] for j in range(2)])
+    xo = [mg.mg_cg(pair["h"], rhs[j], 1e-10)[0] for j in range(2)]
+    for prec in (smg.FP64, smg.MIXED):
+        x, stats, code = s.solve(dev(rhs), tol=1e-10, maxiter=500, precision=prec)
+        assert code == 0
+        xh = host(x).reshape(2, -1)
+        for j in range(2):
+            res = np.linalg.norm(rhs[j] - A @ xh[j]) / np.linalg.norm(rhs[j])
+            assert res <= 1e-10, (prec, j, res)
+            assert stats[j]["true_relres"] <= 1e-10
+            # forward error vs the oracle's MG-CG solution
+            assert np.linalg.norm(xh[j] - xo[j]) / np.linalg.norm(xo[j]) < 1e-6
+
+
+def test_set_mass_rebuilds_coarse_operators(pair):
+    """Setup reuse across masses: P kept, A_c(m) rebuilt by Eq. 2, smoothers recalibrated."""
+    U, h, s = pair["U"], pair["h"], pair["s"]
+    m2 = pair["m"] + 0.13
+    s.set_mass(m2)
+    try:
+        h2 = mg.set_mass(h, normal_matrix(U, m2), pair["calib"], 4, 0.8)
+        for l in range(1, len(pair["blocks"]) + 1):
+            cx, ct, nc = s.level_info(l)
+            assert rel_err(host(s.coarse_links(l)), links_from_sparse(h2.levels[l].A, cx, ct, nc)) <= 1e-12
+        for l in range(len(pair["blocks"])):
+            np.testing.assert_allclose(s.smoother_coefs(l), h2.levels[l].coefs, rtol=1e-12)
+    finally:
+        s.set_mass(pair["m"])
+
+
+# ---------------------------------------------------------------------------
+# Adaptive setup and the c1 workload (32^2, beta 3, m 0.1, 2 levels, Nv 8)
+# ---------------------------------------------------------------------------
+
+def c1_inputs():
+    lx = lt = 32
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 200, 1000))
+    R = synth.setup_randoms(lx, lt, [(4, 4)], [8], 1)
+    b = synth.gaussian(2 * lx * lt, 0)
+    return U, R, b
+
+
+def test_adaptive_setup_and_solve_c1(cuda):
+    smg = smg_mod()
+    U, R, b = c1_inputs()
+    lx = lt = 32
+    m = 0.1
+    A = normal_matrix(U, m)
+    rhs = dirac_matrix(U, m).conj().T @ b
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [8], R, nu=4, omega=0.8, setup_iters=5, coarsest="cg")
+    xo, io = mg.mg_cg(h, rhs, 1e-10)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=[(4, 4)], nv=[8], coarsest=smg.COARSEST_CG)
+    s = smg.Solver(dev(U), p, randoms=dev(np.concatenate([r.ravel() for r in R])))
+    # setup parity: smoother exactly, prolongator up to rounding amplified by the
+    # setup iterations, compared through the per-aggregate projectors P_J P_J^H
+    np.testing.assert_allclose(s.smoother_coefs(0), h.levels[0].coefs, rtol=1e-12)
+    Pg = host(s.prolongator(0))
+    Po = h.levels[0].U
+    proj_g = np.einsum("jki,jkl->jil", Pg, Pg.conj())
+    proj_o = np.einsum("jki,jkl->jil", Po, Po.conj())
+    assert np.max(np.abs(proj_g - proj_o)) <= 1e-8
+    for prec in (smg.FP64, smg.MIXED):
+        x, st, code = s.solve(dev(rhs), tol=1e-10, maxiter=500, precision=prec)
+        assert code == 0
+        xh = host(x)
+        res = np.linalg.norm(rhs - A @ xh) / np.linalg.norm(rhs)
+        assert res <= 1e-10
+        assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) < 1e-7
+        if prec == smg.FP64:
+            assert abs(st[0]["iterations"] - io.iterations) <= 1
+    # plain CG agrees with the oracle's CG iteration count
+    xc, stc, code = s.cg(dev(rhs), tol=1e-10)
+    _, ic = mg.cg(A, rhs, 1e-10)
+    assert code == 0 and abs(stc[0]["iterations"] - ic.iterations) <= 2
+    s.close()
+
+
+def test_batch_invariance_and_edge_cases(cuda):
+    """A column's result is bitwise the same alone and in a batch; a zero column
+    returns zero; NaN input is reported as a breakdown; maxiter too small is
+    reported as not converged."""
+    smg = smg_mod()
+    lx = lt = 24
+    U = field(lx, lt, seed=3, sweeps=50)
+    p = smg.make_params(lx, lt, 0.05, levels=2, blocks=[(4, 4)], nv=[6], seed=9)
+    s = smg.Solver(dev(U), p)
+    n = 2 * lx * lt
+    B = synth.gaussian((4, n), 23)
+    B[2] = 0.0
+    xb, stb, code = s.solve(dev(B), tol=1e-10)
+    assert code == 0
+    xb = host(xb).reshape(4, -1)
+    assert np.all(xb[2] == 0)
+    for j in (0, 1, 3):
+        xa, _, _ = s.solve(dev(B[j]), tol=1e-10)
+        assert np.array_equal(host(xa), xb[j])
+    _, st, code = s.solve(dev(B[0]), tol=1e-10, maxiter=1)
+    assert code == smg.NOTCONV and st[0]["status"] == smg.NOTCONV
+    bad = B[0].copy()
+    bad[5] = np.nan
+    with pytest.raises(smg.SmgError) as ei:
+        s.solve(dev(bad), tol=1e-10)
+    assert ei.value.code == -5
+    s.close()
