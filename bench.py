@@ -1,0 +1,336 @@
+#!/usr/bin/env python3
+"""Benchmark of the adaptive-MG hot path on one MI355X.
+
+Workload (the precision configuration): 256x256 lattice, quenched U(1) fields at
+beta = 6 (500 Metropolis sweeps, 4 fields, seeds 2000-2003), 5 masses per field at
+lambda_min(A)/lambda_max(A) = 1e-2, 3e-3, 1e-3, 3e-4, 1e-4 (tuned offline, stored in
+workloads/c2_masses.json), 3 levels of 4x4 aggregates with Nv = 12, nu = 4 MR
+smoother (omega 0.8), 5 setup iterations, dense FP64 coarsest inverse, one Gaussian
+right-hand side per field (rhs = D^H b), true residual 1e-10.
+
+The adaptive setup runs once per field at its lightest mass; the heavier masses
+reuse its near-null vectors (their coarse operators are rebuilt) -- both are timed
+separately as setup.  One step solves all 20 (field, mass) systems.  `value` is
+mixed-precision (FP32 inner, FP64 defect correction) solves/s; the plain FP64
+GPU MG is timed on the same hierarchies and reported beside it.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build uses one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L = 256
+BETA = 6.0
+SWEEPS = 500
+SEEDS = [2000, 2001, 2002, 2003]
+BLOCKS = [(4, 4), (4, 4)]
+NV = [12, 12]
+NU = 4
+OMEGA = 0.8
+SETUP_ITERS = 5
+TOL = 1e-10
+DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_masses():
+    with open(os.path.join(ROOT, "workloads", "c2_masses.json")) as f:
+        data = json.load(f)
+    out = {}
+    for fld in data["fields"]:
+        assert fld["L"] == L and fld["beta"] == BETA and fld["sweeps"] == SWEEPS
+        out[fld["seed"]] = [m["mass"] for m in fld["masses"]]
+    return out
+
+
+def make_field(seed):
+    import synth
+
+    return synth.links_from_angles(synth.metropolis_u1(L, L, BETA, SWEEPS, seed))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample (child process, one thread)
+# ---------------------------------------------------------------------------
+
+def cpu_baseline_leg():
+    """Oracle MG-CG on field 2000: adaptive setup at the lightest mass (not in the
+    rate), then solves at the lightest and the heaviest mass (timed)."""
+    import numpy as np
+
+    import synth
+    from oracle import multigrid as mg
+    from oracle.wilson import dirac_matrix, normal_matrix
+
+    seed = SEEDS[0]
+    masses = load_masses()[seed]
+    U = make_field(seed)
+    m_light = min(masses)
+    R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
+    t0 = time.perf_counter()
+    h = mg.adaptive_setup(normal_matrix(U, m_light), (L, L, 2), BLOCKS, NV, R, nu=NU, omega=OMEGA,
+                          setup_iters=SETUP_ITERS)
+    setup_s = time.perf_counter() - t0
+    b = synth.gaussian(2 * L * L, 10000 * 2 + 0)
+    solve_s, iters, res = [], [], []
+    for m in (m_light, max(masses)):
+        hm = h if m == m_light else mg.set_mass(h, normal_matrix(U, m), [r[0] for r in R], NU, OMEGA)
+        rhs = dirac_matrix(U, m).conj().T @ b
+        t0 = time.perf_counter()
+        x, info = mg.mg_cg(hm, rhs, TOL)
+        solve_s.append(time.perf_counter() - t0)
+        iters.append(info.iterations)
+        res.append(info.relres)
+    return dict(setup_s=setup_s, solve_s=solve_s, iterations=iters, relres=res)
+
+
+def start_cpu_baseline():
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-leg"], env=env,
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+# GPU
+# ---------------------------------------------------------------------------
+
+def timed_events(fn, reps, stream):
+    """Average duration of fn() over reps launches, HIP events on `stream`."""
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        fn()
+        start.record(stream)
+        for _ in range(reps):
+            fn()
+        stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) * 1e-3 / reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--dslash-reps", type=int, default=200)
+    args = ap.parse_args()
+
+    if args.cpu_baseline_leg:
+        print(json.dumps(cpu_baseline_leg()))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        return 2
+
+    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline()
+
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+
+    masses = load_masses()
+    log("generating gauge fields")
+    with ProcessPoolExecutor(max_workers=len(SEEDS)) as ex:
+        fields = list(ex.map(make_field, SEEDS))
+
+    import torch
+
+    import paper_0710_3612_amd as smg
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(dev)
+
+    # ---- setup (timed separately) ---------------------------------------------
+    systems = []     # (solver, rhs tensor)
+    setup_s, remass_s = [], []
+    keep = []
+    for seed, U in zip(SEEDS, fields):
+        ms = masses[seed]
+        m_light = min(ms)
+        p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=NV, setup_iters=SETUP_ITERS,
+                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed)
+        R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
+        g = T(U)
+        rnd = T(np.concatenate([r.ravel() for r in R]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s0 = smg.Solver(g, p, randoms=rnd)
+        torch.cuda.synchronize()
+        setup_s.append(time.perf_counter() - t0)
+        b = T(synth.gaussian(2 * L * L, 10000 * 2 + SEEDS.index(seed)))
+        keep.append(s0)
+        for m in ms:
+            t0 = time.perf_counter()
+            s = s0 if m == m_light else s0.derive(m)
+            torch.cuda.synchronize()
+            if m != m_light:
+                remass_s.append(time.perf_counter() - t0)
+            rhs = s.apply_D(b, dagger=True)
+            systems.append((s, rhs, seed, m))
+            keep.append(s)
+        log(f"field {seed}: setup {setup_s[-1]:.2f}s")
+    xs = [torch.empty_like(rhs) for _, rhs, _, _ in systems]
+
+    records = {}
+
+    def step(prec, rec=None):
+        for k, (s, rhs, seed, m) in enumerate(systems):
+            x, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=xs[k])
+            if code != 0 or st[0]["true_relres"] > TOL:
+                raise RuntimeError(f"solve did not converge: field {seed} mass {m} {st[0]}")
+            if rec is not None:
+                rec.append(dict(seed=seed, mass=m, iterations=st[0]["iterations"],
+                                refinements=st[0]["refinements"], fine_applies=st[0]["fine_applies"],
+                                relres=st[0]["true_relres"]))
+
+    results = {}
+    for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
+        rec = []
+        step(prec, rec)                       # also the first warmup
+        for _ in range(max(args.warmup - 1, 0)):
+            step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        results[name] = dict(seconds=dt, solves=len(systems) * args.steps, records=rec)
+        log(f"{name}: {len(systems) * args.steps / dt:.1f} solves/s")
+
+    # ---- dominant-kernel roofline: level-2 coarse operator of the mixed solve --------
+    # (measured with HIP events on the solver's stream)
+    s = systems[0][0]
+    cx, ct, nc = s.level_info(1)
+    v1 = T(synth.gaussian(cx * ct * nc, 5))
+    y1 = torch.empty_like(v1)
+    lib = smg.load_library()
+    import ctypes
+
+    h = s.handle
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    px, py = ctypes.c_void_p(v1.data_ptr()), ctypes.c_void_p(y1.data_ptr())
+    dur_c = timed_events(lambda: lib.smg_apply_level(h, 1, px, py, 1, sp), args.dslash_reps, stream)
+    coarse_bytes = 9 * nc * nc * 16 * cx * ct + 2 * cx * ct * nc * 16    # FP64 links + in/out vectors
+    coarse_gbs = coarse_bytes / dur_c / 1e9
+
+    # ---- fine D^H D at 2048^2 (HBM-bound working set) -----------------------------
+    th = np.random.default_rng(5000).uniform(-math.pi, math.pi, size=(2, DSLASH_L, DSLASH_L))
+    gbig = T(np.exp(1j * th))
+    pbig = smg.make_params(DSLASH_L, DSLASH_L, 0.01, levels=1)
+    sbig = smg.Solver(gbig, pbig)
+    xb = T(synth.gaussian(2 * DSLASH_L * DSLASH_L, 6))
+    yb = torch.empty_like(xb)
+    hb = sbig.handle
+    pxb, pyb = ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr())
+    dur_a = timed_events(lambda: lib.smg_apply_A(hb, pxb, pyb, 1, sp), args.dslash_reps, stream)
+    V = DSLASH_L * DSLASH_L
+    a_bytes = V * (32 + 32 + 32)          # psi in, A psi out, 2 links per site (FP64)
+    a_gbs = a_bytes / dur_a / 1e9
+
+    cpu = None
+    if cpu_proc is not None:
+        out, err = cpu_proc.communicate(timeout=1800)
+        if cpu_proc.returncode == 0:
+            leg = json.loads(out.strip().splitlines()[-1])
+            per_solve = sum(leg["solve_s"]) / len(leg["solve_s"])
+            cpu = dict(value=1.0 / per_solve, unit="solves/s", cores=1, kind="oracle",
+                       sample=(f"FP64 oracle (scipy sparse, 1 thread, {cpu_model()}) MG-CG on field {SEEDS[0]} at its "
+                               f"lightest and heaviest mass ({len(leg['solve_s'])} solves, "
+                               f"{sum(leg['solve_s']):.1f}s); its adaptive setup took {leg['setup_s']:.1f}s "
+                               f"(not in the rate); iterations {leg['iterations']}"))
+        else:
+            log("cpu baseline failed: " + err[-2000:])
+
+    mixed = results["mixed"]
+    fp64 = results["fp64"]
+    value = mixed["solves"] / mixed["seconds"]
+    line = {
+        "metric": "MG solves/s to 1e-10 residual (mixed vs FP64); D†D HBM GB/s; p99 latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 inner / f64 outer",
+        "data": "synthetic",
+        "config": {
+            "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
+                        "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10",
+            "systems_per_step": len(systems),
+            "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
+            "mixed_over_fp64": (mixed["solves"] / mixed["seconds"]) / (fp64["solves"] / fp64["seconds"]),
+            "setup_s_per_field": setup_s,
+            "remass_s_mean": sum(remass_s) / max(len(remass_s), 1),
+            "mean_iterations_mixed": sum(r["iterations"] for r in mixed["records"]) / len(mixed["records"]),
+            "mean_iterations_fp64": sum(r["iterations"] for r in fp64["records"]) / len(fp64["records"]),
+            "max_relres": max(r["relres"] for r in mixed["records"] + fp64["records"]),
+        },
+        "roofline": {
+            "kernel": "coarse 9-point operator, level 2 (64x64, nc=12, FP64), single RHS",
+            "bound": "hbm",
+            "achieved": coarse_gbs,
+            "peak": 8000.0,
+            "unit": "GB/s",
+            "frac": coarse_gbs / 8000.0,
+            "traffic": None,
+            "avg_launch_us": dur_c * 1e6,
+            "bytes_per_launch": coarse_bytes,
+        },
+        "dslash": {
+            "kernel": f"fine A = D^H D, {DSLASH_L}x{DSLASH_L}, FP64, single RHS",
+            "bound": "hbm",
+            "achieved": a_gbs,
+            "peak": 8000.0,
+            "unit": "GB/s",
+            "frac": a_gbs / 8000.0,
+            "avg_launch_us": dur_a * 1e6,
+            "bytes_per_launch": a_bytes,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

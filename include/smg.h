@@ -82,6 +82,11 @@ typedef struct {
   int32_t coarsest_maxiter;       /* iteration cap of every coarsest CG */
   double inner_tol;               /* mixed precision: relative residual of each inner FP32 solve */
   uint64_t seed;                  /* random starts of the setup when none are passed in */
+  double sa_scale;                /* smoothed aggregation: P = (I - w A) P_t with
+                                     w = sa_scale / lambda_max(A) (20 power iterations from
+                                     the calibration start); 0 = plain aggregation.  Applied
+                                     where both block extents are >= 4 and both coarse
+                                     extents >= 2 (the coarse operator stays 9-point). */
 } smg_params;
 
 typedef struct {
@@ -96,7 +101,7 @@ typedef struct {
 
 /* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
- * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1. */
+ * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
@@ -125,6 +130,13 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
  * coarse operator by Eq. 2 and recalibrates the smoothers from the stored
  * calibration starts.  Errors: SMG_EINVAL, SMG_EDEVICE. */
 int smg_set_mass(smg_handle h, double mass, void* stream);
+
+/* New handle for the same gauge field at another mass, reusing the prolongators of
+ * h (Results section: vectors from the setup at the lightest mass serve every
+ * heavier mass).  The new handle owns copies of P and of the calibration starts;
+ * its coarse operators and smoothers are rebuilt for `mass`.  h is unchanged and
+ * may be destroyed independently.  Errors: SMG_EINVAL, SMG_ENOMEM, SMG_EDEVICE. */
+int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out);
 
 /* y = D x (dagger = 0) or y = D^H x (dagger = 1) on the fine lattice (Introduction).
  * x, y: device, complex128 [nrhs][lt][lx][2], must not overlap.  ASYNC.
@@ -175,10 +187,19 @@ int smg_cg(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol,
 /* Shape of level l: extents and degrees of freedom per site. */
 int smg_level_info(smg_handle h, int32_t level, int32_t* lx, int32_t* lt, int32_t* dof);
 
-/* Copy out the prolongator of coarsening l: device complex128 [J][k][i] with J the
- * coarse site, k < nv[l] the vector and i = ((t%bt)*bx + x%bx)*dof_l + d the
- * variable inside the aggregate.  Synchronous. */
-int smg_get_prolongator(smg_handle h, int32_t level, double* out, void* stream);
+/* Copy out the prolongator of coarsening l (Adaptive Multigrid section).
+ * smoothed = 0: the tentative block-orthonormal P_t, device complex128 [J][k][i]
+ *   with J the coarse site, k < nv[l] the vector and i = (wy*bx + wx)*dof_l + d for
+ *   the site (Jx*bx + wx, Jt*bt + wy) of the aggregate.
+ * smoothed = 1: the prolongator the V-cycle uses, [J][k][i] over the window of
+ *   (bx + 2h) x (bt + 2h) sites, i = (wy*(bx+2h) + wx)*dof_l + d for the site
+ *   (Jx*bx + wx - h, Jt*bt + wy - h) (periodic), h from smg_transfer_info.
+ * Synchronous. */
+int smg_get_prolongator(smg_handle h, int32_t level, int32_t smoothed, double* out, void* stream);
+
+/* Halo h (0 or 1) of the V-cycle prolongator of coarsening l and its smoothed-
+ * aggregation weight w (0 when P = P_t). */
+int smg_transfer_info(smg_handle h, int32_t level, int32_t* halo, double* sa_weight);
 
 /* Copy out the Galerkin operator of level l >= 1 as 9 link blocks per coarse site:
  * device complex128 [K][9][nc][nc], block index (dt+1)*3 + (dx+1) for the

@@ -16,6 +16,14 @@ Readings of the paper taken here (the paper is silent or garbled at these points
   paper), so a coarse site carries M = Nv degrees of freedom.
 * The setup's V-cycle on level l is the two-level cycle on the current P with the
   coarse system solved exactly (sparse direct solve here).
+* Smoothed aggregation (Adaptive Multigrid section): the block-orthonormal
+  tentative prolongator P_t is smoothed by one Richardson step, P = (I - w A) P_t.
+  The paper picks w to minimise the coarse condition number without a formula;
+  here w = s / lambda_max with s = 4/3 (the usual smoothed-aggregation weight) and
+  lambda_max the Rayleigh quotient after 20 power iterations of A from the level's
+  calibration start vector.  Smoothing is applied only where both block extents
+  are >= 4 and both coarse extents >= 2 (then A_c stays a 9-point stencil), and
+  the smoothed P is kept when the mass changes.
 
 Vectors at level l are complex128, index ((t*lx_l + x)*dof_l + d).
 """
@@ -227,9 +235,11 @@ class Level:
     shape: tuple                    # (lx, lt, dof)
     coefs: List[float] = field(default_factory=list)
     block: Optional[tuple] = None   # (bx, bt) towards the next level
-    U: Optional[np.ndarray] = None  # [J, k, i] prolongator columns
-    P: Optional[sp.csr_matrix] = None
+    U: Optional[np.ndarray] = None  # [J, k, i] tentative (block-orthonormal) columns
+    P: Optional[sp.csr_matrix] = None  # prolongator used by the V-cycle (smoothed or tentative)
+    P_t: Optional[sp.csr_matrix] = None
     gather: Optional[np.ndarray] = None
+    sa_weight: float = 0.0
 
 
 @dataclass
@@ -288,30 +298,59 @@ def mg_cg(h: Hierarchy, rhs: np.ndarray, tol: float, maxiter: int = 10000):
 # Building a hierarchy.
 # ---------------------------------------------------------------------------
 
-def coarsen(level: Level, vectors: np.ndarray, block) -> (Level, Level):
-    """Given candidate vectors on `level`, form P (block Gram-Schmidt) and A_c = P^H A P."""
+def power_lambda_max(A, start: np.ndarray, iters: int = 20) -> float:
+    """Rayleigh quotient after `iters` power iterations of A from `start`."""
+    v = np.array(start, dtype=np.complex128, copy=True)
+    lam = 0.0
+    for _ in range(iters):
+        w = A @ v
+        lam = dot(v, w).real / dot(v, v).real
+        v = w / norm(w)
+    return lam
+
+
+def sa_applies(shape, block) -> bool:
+    lx, lt, _ = shape
+    bx, bt = block
+    return bx >= 4 and bt >= 4 and lx // bx >= 2 and lt // bt >= 2
+
+
+def coarsen(level: Level, vectors: np.ndarray, block, sa_weight: float = 0.0) -> (Level, Level):
+    """Given candidate vectors on `level`, form P (block Gram-Schmidt, then the
+    smoothed-aggregation step when sa_weight > 0) and A_c = P^H A P (Eq. 2)."""
     gather = aggregate_gather(level.shape, block)
     U = block_gram_schmidt(vectors, gather)
-    P = prolongator(U, gather, level.A.shape[0])
-    level.block, level.U, level.P, level.gather = tuple(block), U, P, gather
+    P_t = prolongator(U, gather, level.A.shape[0])
+    P = P_t
+    if sa_weight > 0:
+        P = (P_t - sa_weight * (level.A @ P_t)).tocsr()
+    level.block, level.U, level.P, level.P_t, level.gather = tuple(block), U, P, P_t, gather
+    level.sa_weight = sa_weight
     lx, lt, _ = level.shape
     nv = vectors.shape[0]
     nxt = Level(A=galerkin(level.A, P), shape=(lx // block[0], lt // block[1], nv))
     return level, nxt
 
 
+def level_sa_weight(level: Level, block, calib: np.ndarray, sa_scale: float) -> float:
+    if sa_scale <= 0 or not sa_applies(level.shape, block):
+        return 0.0
+    return sa_scale / power_lambda_max(level.A, calib)
+
+
 def hierarchy_from_vectors(A, shape, blocks, vectors_per_level, calib_per_level, nu, omega,
-                           coarsest="cholesky", coarsest_tol=1e-12) -> Hierarchy:
+                           coarsest="cholesky", coarsest_tol=1e-12, sa_scale: float = 0.0) -> Hierarchy:
     """Hierarchy from given near-null vectors (no adaptive iteration).
 
     vectors_per_level[l] is [Nv_l, n_l]; calib_per_level[l] starts the MR
-    calibration of level l.
+    calibration (and the lambda_max estimate) of level l.
     """
     levels = [Level(A=A, shape=tuple(shape))]
     for l, block in enumerate(blocks):
         cur = levels[-1]
         cur.coefs = mr_coefficients(cur.A, calib_per_level[l], nu, omega)
-        cur, nxt = coarsen(cur, np.asarray(vectors_per_level[l]), block)
+        wsa = level_sa_weight(cur, block, calib_per_level[l], sa_scale)
+        cur, nxt = coarsen(cur, np.asarray(vectors_per_level[l]), block, wsa)
         levels.append(nxt)
     return Hierarchy(levels, coarsest, coarsest_tol).factor_coarsest()
 
@@ -332,7 +371,8 @@ def _two_level_exact(level: Level, Ac) -> Callable:
 
 
 def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_iters: int,
-                   coarsest="cholesky", coarsest_tol=1e-12, log: Optional[list] = None) -> Hierarchy:
+                   coarsest="cholesky", coarsest_tol=1e-12, log: Optional[list] = None,
+                   sa_scale: float = 0.0) -> Hierarchy:
     """Adaptive setup (Adaptive Multigrid section), level by level.
 
     For each coarsening l with random starts randoms[l] ([1 + Nv, n_l]):
@@ -344,18 +384,20 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
         error is restricted to the aggregates, orthonormalised against the earlier
         vectors and appended, and A_c is rebuilt;
       * the finished A_c is the next level's operator (the procedure recurses).
+    With sa_scale > 0 every prolongator is the smoothed one (see the module notes).
     """
     levels = [Level(A=A, shape=tuple(shape))]
     for l, block in enumerate(blocks):
         cur = levels[-1]
         R = randoms[l]
         cur.coefs = mr_coefficients(cur.A, R[0], nu, omega)
+        wsa = level_sa_weight(cur, block, R[0], sa_scale)
         e = np.array(R[1], copy=True)
         for _ in range(setup_iters):
             e = e - smoother_apply(cur.A, cur.coefs, cur.A @ e)
             e = e / norm(e)
         vecs = [e]
-        cur, nxt = coarsen(cur, np.array(vecs), block)
+        cur, nxt = coarsen(cur, np.array(vecs), block, wsa)
         for k in range(1, nvs[l]):
             V = _two_level_exact(cur, nxt.A)
             e = np.array(R[1 + k], copy=True)
@@ -363,7 +405,7 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
                 e = e - V(cur.A @ e)
                 e = e / norm(e)
             vecs.append(e)
-            cur, nxt = coarsen(cur, np.array(vecs), block)
+            cur, nxt = coarsen(cur, np.array(vecs), block, wsa)
         if log is not None:
             log.append({"level": l, "coefs": list(cur.coefs)})
         levels.append(nxt)
@@ -377,7 +419,8 @@ def set_mass(h: Hierarchy, A_fine, calib_per_level, nu: int, omega: float) -> Hi
     levels = []
     A = A_fine
     for l, lev in enumerate(h.levels):
-        new = Level(A=A, shape=lev.shape, block=lev.block, U=lev.U, P=lev.P, gather=lev.gather)
+        new = Level(A=A, shape=lev.shape, block=lev.block, U=lev.U, P=lev.P, P_t=lev.P_t, gather=lev.gather,
+                    sa_weight=lev.sa_weight)
         if lev.P is not None:
             new.coefs = mr_coefficients(A, calib_per_level[l], nu, omega)
             A = galerkin(A, lev.P)

@@ -65,6 +65,7 @@ class Params(ctypes.Structure):
         ("coarsest_maxiter", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("sa_scale", ctypes.c_double),
     ]
 
 
@@ -114,6 +115,7 @@ def load_library():
         "smg_setup": (i32, [P, ctypes.POINTER(Params), P, P, ctypes.POINTER(h)]),
         "smg_setup_from_vectors": (i32, [P, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(h)]),
         "smg_set_mass": (i32, [h, ctypes.c_double, P]),
+        "smg_derive": (i32, [h, ctypes.c_double, P, ctypes.POINTER(h)]),
         "smg_apply_D": (i32, [h, P, P, i32, i32, P]),
         "smg_apply_A": (i32, [h, P, P, i32, P]),
         "smg_apply_level": (i32, [h, i32, P, P, i32, P]),
@@ -124,7 +126,8 @@ def load_library():
         "smg_solve": (i32, [h, P, P, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(Stats)]),
         "smg_cg": (i32, [h, P, P, i32, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
         "smg_level_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
-        "smg_get_prolongator": (i32, [h, i32, P, P]),
+        "smg_get_prolongator": (i32, [h, i32, i32, P, P]),
+        "smg_transfer_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "smg_get_coarse_links": (i32, [h, i32, P, P]),
         "smg_get_smoother_coefs": (i32, [h, i32, ctypes.POINTER(ctypes.c_double)]),
         "smg_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
@@ -151,7 +154,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 nv: Sequence[int] = (8,), setup_iters: int = 5, smoother_steps: int = 4,
                 smoother_omega: float = 0.8, t_antiperiodic: bool = True, coarsest: int = COARSEST_DIRECT,
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
-                seed: int = 1) -> Params:
+                seed: int = 1, sa_scale: float = 4.0 / 3.0) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -168,6 +171,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.coarsest_maxiter = coarsest_maxiter
     p.inner_tol = inner_tol
     p.seed = seed
+    p.sa_scale = sa_scale
     return p
 
 
@@ -256,6 +260,19 @@ class Solver:
         _check(self.lib.smg_set_mass(self.handle, float(mass), _stream(stream)))
         self.params.mass = mass
 
+    def derive(self, mass: float, stream=None) -> "Solver":
+        """New Solver at another mass sharing this setup's near-null vectors."""
+        import copy
+
+        other = Solver.__new__(Solver)
+        other.lib = self.lib
+        other.params = copy.copy(self.params)
+        other.params.mass = mass
+        other.handle = ctypes.c_void_p()
+        other._torch = self._torch
+        _check(self.lib.smg_derive(self.handle, float(mass), _stream(stream), ctypes.byref(other.handle)))
+        return other
+
     def apply_D(self, x, dagger: bool = False, stream=None):
         x = x.contiguous()
         nr = self._nrhs(x, self.level_size(0))
@@ -323,13 +340,23 @@ class Solver:
         return x, [s.as_dict() for s in st], code
 
     # -- introspection -------------------------------------------------------------
-    def prolongator(self, level: int, stream=None):
-        """P of coarsening `level` as a [J, nv, nagg] complex128 tensor."""
+    def transfer_info(self, level: int):
+        """(halo, smoothed-aggregation weight) of the prolongator of coarsening `level`."""
+        h, w = ctypes.c_int32(), ctypes.c_double()
+        _check(self.lib.smg_transfer_info(self.handle, level, ctypes.byref(h), ctypes.byref(w)))
+        return h.value, w.value
+
+    def prolongator(self, level: int, smoothed: bool = False, stream=None):
+        """P of coarsening `level` as [J, nv, nw] complex128: the tentative one
+        (smoothed=False, nw = bx*bt*dof) or the one the V-cycle uses (windows of
+        (bx+2h)(bt+2h) sites)."""
         lx, lt, dof = self.level_info(level)
         cx, ct, nc = self.level_info(level + 1)
-        nagg = (lx // cx) * (lt // ct) * dof
-        out = self._torch.empty((cx * ct, nc, nagg), dtype=self._torch.complex128, device="cuda")
-        _check(self.lib.smg_get_prolongator(self.handle, level, _ptr(out), _stream(stream)))
+        bx, bt = lx // cx, lt // ct
+        hh = self.transfer_info(level)[0] if smoothed else 0
+        nw = (bx + 2 * hh) * (bt + 2 * hh) * dof
+        out = self._torch.empty((cx * ct, nc, nw), dtype=self._torch.complex128, device="cuda")
+        _check(self.lib.smg_get_prolongator(self.handle, level, int(bool(smoothed)), _ptr(out), _stream(stream)))
         return out
 
     def coarse_links(self, level: int, stream=None):

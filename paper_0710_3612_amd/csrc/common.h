@@ -4,7 +4,7 @@
 //   fine vector batch     [nrhs][t][x][spin]        spin in {0,1}
 //   level-l vector batch  [nrhs][t][x][dof]         dof = nv of the coarsening above
 //   fine links            [mu][t][x]                fermion BC sign folded into mu=1, t=lt-1
-//   prolongator           [J][k][i]                 J coarse site, k vector, i aggregate variable
+//   prolongator           [J][k][i]                 J coarse site, k vector, i window variable
 //   coarse links (device) [D][col][K][row]          D = (dt+1)*3 + (dx+1); "site-major" so that
 //                                                   threads (K,row) read consecutive words
 #pragma once
@@ -112,13 +112,14 @@ void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, 
                    double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
 
 // Transfer between level (lx, lt, dof) and its aggregates of (bx, bt) sites.
-// P is [J][ldk][nagg] (ldk >= nc vectors stored per aggregate).
+// P is [J][ldk][nw] (ldk >= nc vectors stored per aggregate) over windows of
+// (bx + 2h) x (bt + 2h) sites: h = 0 tentative, h = 1 smoothed prolongator.
 template <typename R>
-void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt,
+void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                      int nc, int ldk, int nrhs, hipStream_t st);
 // mode 0: y = P e ; mode 1: y += P e
 template <typename R>
-void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt,
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                     int nc, int ldk, int nrhs, int mode, hipStream_t st);
 
 // Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
@@ -126,11 +127,14 @@ void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, 
                       int* fail, hipStream_t st);
 
 // Galerkin helpers: X = sum over aggregates J of colour (cxc, ctc) of P[J][k] (zero elsewhere).
-void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int h, int k, int ldk,
                           int cxc, int ctc, hipStream_t st);
-// links[D(K)][k][K][:] = P_K^H (Y restricted to K), D(K) the offset of the colour's aggregate.
-void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int nc,
-                          int ldk, int k, int cxc, int ctc, hipStream_t st);
+// links[D(K)][k][K][:] = P_K^H (Y restricted to K's window), D(K) the offset of the colour's aggregate.
+void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int h,
+                          int nc, int ldk, int k, int cxc, int ctc, hipStream_t st);
+// Smoothed aggregation: P[J][k] = (X - w Y) on the windows of colour (cxc, ctc).
+void launch_sa_extract(const z64* X, const z64* Y, z64* P, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+                       int cxc, int ctc, double w, hipStream_t st);
 int colors_along(int extent);
 
 // Dense coarsest operator and its inverse (FP64).

@@ -4,8 +4,10 @@
 //
 // Aggregates (Adaptive Multigrid section): the lattice of level l is cut into
 // bx x bt blocks of sites; aggregate J holds every degree of freedom of its block,
-// so its variables are i = ((t % bt) * bx + x % bx) * dof + d.  Column (J, k) of P
-// is the k-th block-orthonormal near-null vector restricted to J.
+// so its variables are i = ((t % bt) * bx + x % bx) * dof + d.  Column (J, k) of the
+// tentative P is the k-th block-orthonormal near-null vector restricted to J; the
+// smoothed P (smoothed aggregation, same section) is (I - w A) applied to it and
+// lives on the block plus a one-site ring.
 //
 // The coarse operator A_c = P^H A P couples a coarse site only to the 3x3 box
 // around it (A has reach one site in each direction and the blocks are at least
@@ -21,12 +23,34 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Fine index of variable i of aggregate J.
-__device__ inline int agg_index(int J, int i, int lx, int dof, int bx, int bt, int cx) {
+// Aggregate windows.  Column (J, k) of the prolongator lives on the block of J
+// (halo h = 0, the tentative P) or on the block plus a one-site ring (h = 1, the
+// smoothed P).  Window variable i = ((wy * (bx + 2h)) + wx) * dof + d with
+// wx in [0, bx + 2h) standing for x = Jx * bx + wx - h (periodic).
+__device__ inline int win_index(int J, int i, int lx, int lt, int dof, int bx, int bt, int cx, int h) {
   const int Jt = J / cx, Jx = J - Jt * cx;
+  const int wxw = bx + 2 * h;
   const int site = i / dof, d = i - site * dof;
-  const int ty = site / bx, tx = site - ty * bx;
-  return ((Jt * bt + ty) * lx + (Jx * bx + tx)) * dof + d;
+  const int wy = site / wxw, wx = site - wy * wxw;
+  int x = Jx * bx + wx - h, t = Jt * bt + wy - h;
+  x = x < 0 ? x + lx : (x >= lx ? x - lx : x);
+  t = t < 0 ? t + lt : (t >= lt ? t - lt : t);
+  return (t * lx + x) * dof + d;
+}
+
+__device__ inline int agg_index(int J, int i, int lx, int dof, int bx, int bt, int cx) {
+  return win_index(J, i, lx, 1 << 30, dof, bx, bt, cx, 0);
+}
+
+// Offsets o of fine coordinate c inside the window of block j (extent L, block b,
+// halo h): o = c - j*b (mod L) within [-h, b + h).  At most one for h <= 1 when
+// the coarse extent is at least 2 (no window covers the lattice twice).
+__device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
+  int v = c - j * b;
+  v = ((v % L) + L) % L;           // [0, L)
+  if (v < b + h) { o = v; return true; }
+  if (v >= L - h) { o = v - L; return true; }
+  return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -38,15 +62,15 @@ __device__ inline int agg_index(int J, int i, int lx, int dof, int bx, int bt, i
 // ---------------------------------------------------------------------------
 template <typename R, int NCH>
 __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x, int K, int lx,
-                                    int dof, int bx, int bt, int cx, int nc, int ldk, cpx<R>* __restrict__ out,
-                                    size_t ostride_k) {
+                                    int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
+                                    cpx<R>* __restrict__ out, size_t ostride_k) {
   const int lane = threadIdx.x & 63;
-  const int nagg = bx * bt * dof;
+  const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
   cpx<R> xv[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = lane + 64 * c;
-    xv[c] = (i < nagg) ? x[agg_index(K, i, lx, dof, bx, bt, cx)] : mk<R>(0, 0);
+    xv[c] = (i < nagg) ? x[win_index(K, i, lx, lt, dof, bx, bt, cx, h)] : mk<R>(0, 0);
   }
   const cpx<R>* PK = P + (size_t)K * ldk * nagg;
   for (int k = 0; k < nc; ++k) {
@@ -69,33 +93,57 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* 
 template <typename R, int NCH>
 __global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                       int bt, int nc, int ldk) {
+                                                       int bt, int h, int nc, int ldk) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
   const int rhs = blockIdx.y;
-  restrict_one<R, NCH>(P, x + rhs * n, K, lx, dof, bx, bt, cx, nc, ldk, y + (size_t)rhs * nK * nc + (size_t)K * nc,
-                       1);
+  restrict_one<R, NCH>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                       y + (size_t)rhs * nK * nc + (size_t)K * nc, 1);
 }
 
-// y[agg(K,i)] (+)= sum_k P[K][k][i] e[K][k]; one thread per fine variable.
+// y (+)= P e; one thread per fine variable, gathering over the (at most 2 x 2)
+// aggregate windows that contain it.
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ e,
                                                       cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx, int bt,
-                                                      int nc, int ldk) {
+                                                      int h, int nc, int ldk) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
-  const int nagg = bx * bt * dof;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nK * nagg) return;
-  const int K = tid / nagg, i = tid - K * nagg;
+  const int wxw = bx + 2 * h;
+  const int nw = wxw * (bt + 2 * h) * dof;
   const size_t n = (size_t)lx * lt * dof;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
   const int rhs = blockIdx.y;
-  const cpx<R>* PK = P + (size_t)K * ldk * nagg + i;
-  const cpx<R>* eK = e + (size_t)rhs * nK * nc + (size_t)K * nc;
+  const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
+  const int t = site / lx, x = site - t * lx;
+  const cpx<R>* eb = e + (size_t)rhs * nK * nc;
   cpx<R> acc = mk<R>(0, 0);
-  for (int k = 0; k < nc; ++k) fma_acc(acc, PK[(size_t)k * nagg], eK[k]);
-  const size_t o = rhs * n + agg_index(K, i, lx, dof, bx, bt, cx);
+  int jts[3], njt = 0, jxs[3], njx = 0;
+  for (int q = -h; q <= h; ++q) {  // distinct candidate blocks
+    int jt = (t / bt + q + ct) % ct, jx = (x / bx + q + cx) % cx;
+    bool dup = false;
+    for (int a = 0; a < njt; ++a) dup |= (jts[a] == jt);
+    if (!dup) jts[njt++] = jt;
+    dup = false;
+    for (int a = 0; a < njx; ++a) dup |= (jxs[a] == jx);
+    if (!dup) jxs[njx++] = jx;
+  }
+  for (int a = 0; a < njt; ++a) {
+    int ot;
+    if (!win_offset(t, jts[a], bt, lt, h, ot)) continue;
+    for (int b = 0; b < njx; ++b) {
+      int ox;
+      if (!win_offset(x, jxs[b], bx, lx, h, ox)) continue;
+      const int J = jts[a] * cx + jxs[b];
+      const int i = ((ot + h) * wxw + (ox + h)) * dof + d;
+      const cpx<R>* PJ = P + (size_t)J * ldk * nw + i;
+      const cpx<R>* eJ = eb + (size_t)J * nc;
+      for (int k = 0; k < nc; ++k) fma_acc(acc, PJ[(size_t)k * nw], eJ[k]);
+    }
+  }
+  const size_t o = (size_t)rhs * n + idx;
   if (MODE == 0)
     y[o] = acc;
   else
@@ -241,20 +289,31 @@ __device__ inline int pick_offset(int j, int c, int col) {
   return 2;
 }
 
+// X = sum over aggregates J of colour (cxc, ctc) of column k of P (window halo h).
+// Windows of one colour are disjoint, so each fine variable takes at most one value.
 __global__ void k_color_scatter(const z64* __restrict__ P, z64* __restrict__ X, int lx, int lt, int dof, int bx,
-                                int bt, int k, int ldk, int cxc, int ctc) {
+                                int bt, int h, int k, int ldk, int cxc, int ctc) {
   const size_t n = (size_t)lx * lt * dof;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
   const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
   const int t = site / lx, x = site - t * lx;
   const int cx = lx / bx, ct = lt / bt;
-  const int Jx = x / bx, Jt = t / bt;
+  const int wxw = bx + 2 * h;
+  const int nw = wxw * (bt + 2 * h) * dof;
   z64 val = mk(0.0, 0.0);
-  if (color_of(Jx, cx) == cxc && color_of(Jt, ct) == ctc) {
-    const int nagg = bx * bt * dof;
-    const int i = ((t - Jt * bt) * bx + (x - Jx * bx)) * dof + d;
-    val = P[((size_t)(Jt * cx + Jx) * ldk + k) * nagg + i];
+  bool done = false;
+  for (int qt = -h; qt <= h && !done; ++qt) {
+    const int jt = (t / bt + qt + ct) % ct;
+    int ot;
+    if (color_of(jt, ct) != ctc || !win_offset(t, jt, bt, lt, h, ot)) continue;
+    for (int qx = -h; qx <= h && !done; ++qx) {
+      const int jx = (x / bx + qx + cx) % cx;
+      int ox;
+      if (color_of(jx, cx) != cxc || !win_offset(x, jx, bx, lx, h, ox)) continue;
+      val = P[((size_t)(jt * cx + jx) * ldk + k) * nw + ((ot + h) * wxw + (ox + h)) * dof + d];
+      done = true;
+    }
   }
   X[idx] = val;
 }
@@ -262,7 +321,7 @@ __global__ void k_color_scatter(const z64* __restrict__ P, z64* __restrict__ X, 
 template <int NCH>
 __global__ void __launch_bounds__(kThreads) k_color_project(const z64* __restrict__ P, const z64* __restrict__ Y,
                                                             z64* __restrict__ L, int lx, int lt, int dof, int bx,
-                                                            int bt, int nc, int ldk, int k, int cxc, int ctc) {
+                                                            int bt, int h, int nc, int ldk, int k, int cxc, int ctc) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (K >= nK) return;
@@ -272,7 +331,23 @@ __global__ void __launch_bounds__(kThreads) k_color_project(const z64* __restric
   const int D = (dt + 1) * 3 + (dx + 1);
   const size_t n = (size_t)nK * nc;
   // L[D][k][K][row]: row stride 1, so out = &L[D][k][K][0]
-  restrict_one<double, NCH>(P, Y, K, lx, dof, bx, bt, cx, nc, ldk, L + ((size_t)D * nc + k) * n + (size_t)K * nc, 1);
+  restrict_one<double, NCH>(P, Y, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                            L + ((size_t)D * nc + k) * n + (size_t)K * nc, 1);
+}
+
+// Smoothed aggregation: column k of P = (I - w A) P_t on the windows of colour
+// (cxc, ctc), from X = the tentative columns of that colour and Y = A X.
+__global__ void k_sa_extract(const z64* __restrict__ X, const z64* __restrict__ Y, z64* __restrict__ P, int lx,
+                             int lt, int dof, int bx, int bt, int k, int ldk, int cxc, int ctc, double w) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int nw = (bx + 2) * (bt + 2) * dof;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nK * nw) return;
+  const int J = (int)(idx / nw), i = (int)(idx - (size_t)J * nw);
+  const int Jt = J / cx, Jx = J - Jt * cx;
+  if (color_of(Jx, cx) != cxc || color_of(Jt, ct) != ctc) return;
+  const int f = win_index(J, i, lx, lt, dof, bx, bt, cx, 1);
+  P[((size_t)J * ldk + k) * nw + i] = X[f] - w * Y[f];
 }
 
 // ---------------------------------------------------------------------------
@@ -433,27 +508,27 @@ void dispatch_chunks(int chunks, F&& f) {
 int colors_along(int extent) { return extent < 3 ? extent : 3 + (extent - 3 * (extent / 3)); }
 
 template <typename R>
-void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int nc,
-                     int ldk, int nrhs, hipStream_t st) {
+void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
+                     int nc, int ldk, int nrhs, hipStream_t st) {
   const int nK = (lx / bx) * (lt / bt);
-  const int nagg = bx * bt * dof;
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   dim3 grid((nK + 3) / 4, nrhs);
-  dispatch_chunks((nagg + 63) / 64, [&](auto c) {
-    hipLaunchKernelGGL((k_restrict<R, decltype(c)::v>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt,
+  dispatch_chunks((nw + 63) / 64, [&](auto c) {
+    hipLaunchKernelGGL((k_restrict<R, decltype(c)::v>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h,
                        nc, ldk);
   });
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
-void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int nc,
-                    int ldk, int nrhs, int mode, hipStream_t st) {
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
+                    int nc, int ldk, int nrhs, int mode, hipStream_t st) {
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
   if (mode == 0)
-    hipLaunchKernelGGL((k_prolong<R, 0>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, nc, ldk);
+    hipLaunchKernelGGL((k_prolong<R, 0>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, h, nc, ldk);
   else
-    hipLaunchKernelGGL((k_prolong<R, 1>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, nc, ldk);
+    hipLaunchKernelGGL((k_prolong<R, 1>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, h, nc, ldk);
   HIPCHECK(hipGetLastError());
 }
 
@@ -482,22 +557,30 @@ void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, 
   HIPCHECK(hipGetLastError());
 }
 
-void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int cxc,
-                          int ctc, hipStream_t st) {
+void launch_color_scatter(const z64* P, z64* X, int lx, int lt, int dof, int bx, int bt, int h, int k, int ldk,
+                          int cxc, int ctc, hipStream_t st) {
   const size_t n = (size_t)lx * lt * dof;
   hipLaunchKernelGGL(k_color_scatter, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, P, X,
-                     lx, lt, dof, bx, bt, k, ldk, cxc, ctc);
+                     lx, lt, dof, bx, bt, h, k, ldk, cxc, ctc);
   HIPCHECK(hipGetLastError());
 }
 
-void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int nc,
+void launch_color_project(const z64* P, const z64* Y, z64* L, int lx, int lt, int dof, int bx, int bt, int h, int nc,
                           int ldk, int k, int cxc, int ctc, hipStream_t st) {
   const int nK = (lx / bx) * (lt / bt);
-  const int nagg = bx * bt * dof;
-  dispatch_chunks((nagg + 63) / 64, [&](auto c) {
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  dispatch_chunks((nw + 63) / 64, [&](auto c) {
     hipLaunchKernelGGL((k_color_project<decltype(c)::v>), dim3((nK + 3) / 4), dim3(kThreads), 0, st, P, Y, L, lx,
-                       lt, dof, bx, bt, nc, ldk, k, cxc, ctc);
+                       lt, dof, bx, bt, h, nc, ldk, k, cxc, ctc);
   });
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_sa_extract(const z64* X, const z64* Y, z64* P, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+                       int cxc, int ctc, double w, hipStream_t st) {
+  const size_t total = (size_t)(lx / bx) * (lt / bt) * (bx + 2) * (bt + 2) * dof;
+  hipLaunchKernelGGL(k_sa_extract, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, X, Y,
+                     P, lx, lt, dof, bx, bt, k, ldk, cxc, ctc, w);
   HIPCHECK(hipGetLastError());
 }
 
@@ -553,9 +636,9 @@ void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int n
 
 #define INST(R)                                                                                                  \
   template void launch_restrict<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int, \
-                                   hipStream_t);                                                                 \
+                                   int, hipStream_t);                                                            \
   template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int,  \
-                                  int, hipStream_t);                                                             \
+                                  int, int, hipStream_t);                                                        \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
                                  const cpx<R>*, hipStream_t);                                                    \
   template void launch_dense_apply<R>(const z64*, const cpx<R>*, cpx<R>*, int, int, hipStream_t);                \

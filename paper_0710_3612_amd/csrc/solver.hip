@@ -72,7 +72,10 @@ struct Level {
   cpx<R>* L = nullptr;              // coarse links [9][dof][K][dof] (coarse levels)
   // transfer to the next level
   int bx = 0, bt = 0, nc = 0, ldk = 0;
-  cpx<R>* P = nullptr;              // [J][ldk][nagg]
+  int halo = 0;                     // 1: smoothed prolongator on block + one-site ring
+  double sa_w = 0;                  // smoothed-aggregation weight w of P = (I - w A) P_t
+  cpx<R>* P = nullptr;              // prolongator of the V-cycle, [J][ldk][nw]
+  cpx<R>* Pt = nullptr;             // tentative block-orthonormal prolongator [J][ldk][nagg]
   std::vector<double> coefs;        // smoother polynomial
   // work vectors, `cap` columns each
   int cap = 0;
@@ -208,12 +211,12 @@ void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mo
 
 template <typename R>
 void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
-  launch_restrict<R>(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.nc, lv.ldk, nrhs, c.st);
+  launch_restrict<R>(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
 }
 
 template <typename R>
 void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, int mode) {
-  launch_prolong<R>(lv.P, e, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.nc, lv.ldk, nrhs, mode, c.st);
+  launch_prolong<R>(lv.P, e, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st);
 }
 
 // x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).
@@ -301,8 +304,12 @@ struct ColStats {
 };
 
 template <typename R>
+// true_check: confirm convergence on the recomputed residual b - A x.  The inner
+// FP32 solves of defect correction stop on the recursive residual instead: in FP32
+// the recomputed residual of an ill-conditioned system has a rounding floor above
+// the inner tolerance, and the outer FP64 loop checks the true residual anyway.
 void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter, bool precond, KVecs<R>& v,
-         ColStats* cs, int check_interval, int depth) {
+         ColStats* cs, int check_interval, int depth, bool true_check = true) {
   auto& lv = levels_of<R>(c)[l];
   Scal& S = c.sc[depth];
   const size_t n = lv.n;
@@ -366,7 +373,18 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
           any_cand = true;
         }
       }
-      if (any_cand) {
+      if (any_cand && !true_check) {
+        for (int j = 0; j < nrhs; ++j)
+          if (cand[j]) {
+            act[j] = 0;
+            stat[j] = SMG_OK;
+            rel[j] = std::sqrt(c.h_scal[2 * j] / hbb[j]);
+          }
+        nact = 0;
+        for (int j = 0; j < nrhs; ++j) nact += act[j];
+        upload_active();
+        if (nact == 0) break;
+      } else if (any_cand) {
         // confirm on the true residual t = b - A x
         apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
         launch_dot<R>(v.t, v.t, n, nrhs, c.partial, S.tt, c.st);
@@ -480,9 +498,10 @@ void galerkin(Ctx& c, int l) {
   for (int a = 0; a < ncx; ++a)
     for (int bcol = 0; bcol < nct; ++bcol)
       for (int k = 0; k < nc; ++k) {
-        launch_color_scatter(lv.P, c.gX, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, a, bcol, c.st);
+        launch_color_scatter(lv.P, c.gX, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, k, lv.ldk, a, bcol, c.st);
         apply_op<double>(c, lv, c.gX, c.gY, 1, 0, 0.0, nullptr, nullptr);
-        launch_color_project(lv.P, c.gY, nx.L, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, nc, lv.ldk, k, a, bcol, c.st);
+        launch_color_project(lv.P, c.gY, nx.L, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, nc, lv.ldk, k, a, bcol,
+                             c.st);
       }
 }
 
@@ -492,11 +511,44 @@ void check_fail(Ctx& c, const char* what) {
   if (c.h_int[0]) throw Error(SMG_ESETUP, what);
 }
 
+// Smoothed aggregation for column k: P[.][k] = (I - w A) P_t[.][k], by colouring
+// (the windows of one colour are disjoint, as are the supports of A P_t on them).
+void smooth_column(Ctx& c, int l, int k) {
+  auto& lv = c.L64[l];
+  if (!lv.halo) return;
+  const int ncx = colors_along(lv.lx / lv.bx), nct = colors_along(lv.lt / lv.bt);
+  for (int a = 0; a < ncx; ++a)
+    for (int b = 0; b < nct; ++b) {
+      launch_color_scatter(lv.Pt, c.gX, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, 0, k, lv.ldk, a, b, c.st);
+      apply_op<double>(c, lv, c.gX, c.gY, 1, 0, 0.0, nullptr, nullptr);
+      launch_sa_extract(c.gX, c.gY, lv.P, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, a, b, lv.sa_w, c.st);
+    }
+}
+
 void gs_append(Ctx& c, int l, const z64* v, int k) {
   auto& lv = c.L64[l];
   zero(c.fail, sizeof(int), c.st);
-  launch_gs_append((double*)lv.P, v, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, c.fail, c.st);
+  launch_gs_append((double*)lv.Pt, v, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, c.fail, c.st);
   check_fail(c, "block Gram-Schmidt: candidate vector is degenerate on an aggregate");
+  smooth_column(c, l, k);
+}
+
+// Smoothed-aggregation weight of level l: w = sa_scale / lambda, lambda the Rayleigh
+// quotient after 20 power iterations of A^(l) from the calibration start.
+void sa_weight(Ctx& c, int l) {
+  auto& lv = c.L64[l];
+  if (!lv.halo) return;
+  HIPCHECK(hipMemcpyAsync(lv.r, c.calib[l], lv.n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  double lam = 0;
+  for (int it = 0; it < 20; ++it) {
+    apply_op<double>(c, lv, lv.r, lv.t, 1, 0, 0.0, nullptr, nullptr);
+    lam = dev_dot_re(c, lv.r, lv.t, lv.n) / dev_dot_re(c, lv.r, lv.r, lv.n);
+    const double nt = std::sqrt(dev_dot_re(c, lv.t, lv.t, lv.n));
+    if (!(nt > 0) || !std::isfinite(lam)) throw Error(SMG_ESETUP, "power iteration for lambda_max broke down");
+    HIPCHECK(hipMemcpyAsync(lv.r, lv.t, lv.n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+    launch_scale_const<double>(lv.r, 1.0 / nt, lv.n, 1, c.st);
+  }
+  lv.sa_w = c.prm.sa_scale / lam;
 }
 
 // Dense inverse of the coarsest operator by Gauss-Jordan elimination (FP64).
@@ -562,6 +614,7 @@ void validate(const smg_params& p) {
   if (!(p.coarsest_tol > 0) || p.coarsest_maxiter < 1) throw Error(SMG_EINVAL, "bad coarsest CG settings");
   if (!std::isfinite(p.mass)) throw Error(SMG_EINVAL, "mass must be finite");
   if (p.coarsest != SMG_COARSEST_DIRECT && p.coarsest != SMG_COARSEST_CG) throw Error(SMG_EINVAL, "bad coarsest");
+  if (!(p.sa_scale >= 0) || !std::isfinite(p.sa_scale)) throw Error(SMG_EINVAL, "sa_scale must be >= 0");
   int lx = p.lx, lt = p.lt, dof = 2;
   for (int l = 0; l + 1 < p.levels; ++l) {
     const int bx = p.block[l][0], bt = p.block[l][1];
@@ -578,8 +631,10 @@ void validate(const smg_params& p) {
   if ((size_t)p.lx * p.lt * 2 > (size_t)1 << 30) throw Error(SMG_EINVAL, "lattice too large");
 }
 
-Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st) {
-  if (!gauge || !prm) throw Error(SMG_EINVAL, "null gauge or params");
+// New context with every device array allocated.  The fermion links come from
+// `gauge` (ABI layout) or are copied from `src_links` (already prepared).
+Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z64* src_links = nullptr) {
+  if ((!gauge && !src_links) || !prm) throw Error(SMG_EINVAL, "null gauge or params");
   validate(*prm);
   Ctx* c = new Ctx();
   try {
@@ -589,7 +644,10 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st) {
     const int lx = prm->lx, lt = prm->lt;
     const size_t V = (size_t)lx * lt;
     c->U64 = c->pool.alloc<z64>(2 * V);
-    launch_prepare_links<double>((const z64*)gauge, c->U64, lx, lt, prm->t_antiperiodic, st);
+    if (src_links)
+      HIPCHECK(hipMemcpyAsync(c->U64, src_links, 2 * V * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    else
+      launch_prepare_links<double>((const z64*)gauge, c->U64, lx, lt, prm->t_antiperiodic, st);
     c->L64.resize(c->nlev);
     c->L64[0].lx = lx;
     c->L64[0].lt = lt;
@@ -611,7 +669,13 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st) {
       pv.bt = prm->block[l - 1][1];
       pv.nc = lv.dof;
       pv.ldk = lv.dof;
-      pv.P = c->pool.alloc<z64>((size_t)lv.lx * lv.lt * lv.dof * pv.bx * pv.bt * pv.dof);
+      pv.Pt = c->pool.alloc<z64>((size_t)lv.lx * lv.lt * lv.dof * pv.bx * pv.bt * pv.dof);
+      // smoothed aggregation where the 9-point coarse stencil survives it
+      pv.halo = (prm->sa_scale > 0 && pv.bx >= 4 && pv.bt >= 4 && lv.lx >= 2 && lv.lt >= 2) ? 1 : 0;
+      if (pv.halo)
+        pv.P = c->pool.alloc<z64>((size_t)lv.lx * lv.lt * lv.dof * (pv.bx + 2) * (pv.bt + 2) * pv.dof);
+      else
+        pv.P = pv.Pt;
     }
     c->fail = c->pool.alloc<int>(4);
     ensure_scalars(*c, 1);
@@ -643,7 +707,7 @@ void ensure_f32(Ctx& c) {
     auto& a = c.L64[l];
     auto& b = c.L32[l];
     b.lx = a.lx; b.lt = a.lt; b.dof = a.dof; b.n = a.n; b.fine = a.fine; b.diag = a.diag;
-    b.bx = a.bx; b.bt = a.bt; b.nc = a.nc; b.ldk = a.ldk; b.coefs = a.coefs;
+    b.bx = a.bx; b.bt = a.bt; b.nc = a.nc; b.ldk = a.ldk; b.coefs = a.coefs; b.halo = a.halo; b.sa_w = a.sa_w;
     if (a.fine) b.U = c.U32;
     if (a.L) {
       const size_t nl = 9 * (size_t)a.lx * a.lt * a.dof * a.dof;
@@ -651,7 +715,7 @@ void ensure_f32(Ctx& c) {
       launch_links_convert<float>(a.L, b.L, nl, c.st);
     }
     if (a.P) {
-      const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * a.bx * a.bt * a.dof;
+      const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * a.halo) * (a.bt + 2 * a.halo) * a.dof;
       if (fresh) b.P = c.pool.alloc<z32>(np);
       launch_links_convert<float>(a.P, b.P, np, c.st);
     }
@@ -750,6 +814,7 @@ void smg_default_params(smg_params* p) {
   p->coarsest_maxiter = 10000;
   p->inner_tol = 1e-5;
   p->seed = 1;
+  p->sa_scale = 4.0 / 3.0;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
@@ -773,6 +838,7 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
       }
       c->calib[l] = rnd;  // row 0
       calibrate(*c, l);
+      sa_weight(*c, l);
       adaptive_level(*c, l, rnd);
     }
     finish_setup(*c);
@@ -801,6 +867,7 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
                               hipMemcpyDeviceToDevice, st));
       c->calib[l] = cb;
       calibrate(*c, l);
+      sa_weight(*c, l);
       const z64* vl = (const z64*)vectors + level_offset_randoms(*c, l, false);
       for (int k = 0; k < nv; ++k) gs_append(*c, l, vl + (size_t)k * n, k);
       set_nc(*c, l, nv);
@@ -828,6 +895,47 @@ int smg_set_mass(smg_handle h, double mass, void* stream) {
     galerkin(*c, l);
   }
   finish_setup(*c);
+  return SMG_OK;
+  API_END
+}
+
+int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
+  API_BEGIN
+  Ctx* src = H(h);
+  if (!out) throw Error(SMG_EINVAL, "null output handle");
+  if (!std::isfinite(mass)) throw Error(SMG_EINVAL, "mass must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(hipStreamSynchronize(src->st));
+  smg_params prm = src->prm;
+  prm.mass = mass;
+  Ctx* c = create(nullptr, &prm, st, src->U64);
+  try {
+    c->calib.resize(c->nlev);
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      auto& a = src->L64[l];
+      auto& b = c->L64[l];
+      const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * a.bx * a.bt * a.dof;
+      HIPCHECK(hipMemcpyAsync(b.Pt, a.Pt, np * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      if (a.halo) {
+        const size_t nw = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2) * (a.bt + 2) * a.dof;
+        HIPCHECK(hipMemcpyAsync(b.P, a.P, nw * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      }
+      b.sa_w = a.sa_w;
+      z64* cb = c->pool.alloc<z64>(a.n);
+      HIPCHECK(hipMemcpyAsync(cb, src->calib[l], a.n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      c->calib[l] = cb;
+    }
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      set_nc(*c, l, c->prm.nv[l]);
+      calibrate(*c, l);
+      galerkin(*c, l);
+    }
+    finish_setup(*c);
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  *out = reinterpret_cast<smg_handle>(c);
   return SMG_OK;
   API_END
 }
@@ -989,7 +1097,8 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
       ColStats inner;
       // The inner solve's own convergence test uses inner_tol; its limit is what is
       // left of maxiter.
-      pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0);
+      pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0,
+                 false);
       int maxit = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (down[j] != 0) its[j] += inner.iters[j];
@@ -1047,16 +1156,29 @@ int smg_level_info(smg_handle h, int32_t level, int32_t* lx, int32_t* lt, int32_
   API_END
 }
 
-int smg_get_prolongator(smg_handle h, int32_t level, double* out, void* stream) {
+int smg_get_prolongator(smg_handle h, int32_t level, int32_t smoothed, double* out, void* stream) {
   API_BEGIN
   Ctx* c = H(h);
   check_level(c, level);
   if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no prolongator below the coarsest level");
   if (!out) throw Error(SMG_EINVAL, "null output");
   auto& a = c->L64[level];
-  const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * a.bx * a.bt * a.dof;
-  HIPCHECK(hipMemcpyAsync(out, a.P, np * sizeof(z64), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  const int hh = smoothed ? a.halo : 0;
+  const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * hh) * (a.bt + 2 * hh) * a.dof;
+  HIPCHECK(hipMemcpyAsync(out, smoothed ? a.P : a.Pt, np * sizeof(z64), hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
   HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  return SMG_OK;
+  API_END
+}
+
+int smg_transfer_info(smg_handle h, int32_t level, int32_t* halo, double* sa_weight) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no prolongator below the coarsest level");
+  if (halo) *halo = c->L64[level].halo;
+  if (sa_weight) *sa_weight = c->L64[level].sa_w;
   return SMG_OK;
   API_END
 }

@@ -124,6 +124,204 @@ __global__ void __launch_bounds__(kThreads) k_normal2(const cpx<R>* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused A = D^H D (one pass over memory).
+//
+// A workgroup owns a TX x TT tile.  psi on the tile plus a one-site halo (corners
+// included) is staged in LDS.  Phase 1 computes phi = D psi on the tile and, on the
+// halo ring, only the spin projection that D^H will use there: for the ring site
+// beyond the tile in direction +mu, D^H needs (1 + gamma_mu) phi, which annihilates
+// the (1 - gamma_mu) hop of D from that site further out, so that hop (the only
+// one reaching past the halo) is skipped.  Phase 2 applies D^H on the tile.  Each
+// thread keeps its sites' links and phi in registers between the phases, so the
+// algorithmic traffic is psi in + links + y out per site.
+//
+// Tiles are ordered so that the workgroups that land on one XCD (dispatch is
+// round-robin over the 8 XCDs) cover a contiguous band of the lattice; the halos
+// they share then hit the same L2.
+// ---------------------------------------------------------------------------
+// Hop directions for the skip argument.
+enum { kSkipNone = -1, kSkipXp = 0, kSkipXm = 1, kSkipTp = 2, kSkipTm = 3 };
+
+template <typename R, bool DAG>
+__device__ inline void hop_acc(cpx<R>& s0, cpx<R>& s1, int dir, cpx<R> u, cpx<R> p0, cpx<R> p1) {
+  // dir 0: +x (1 -+ s1), 1: -x (1 +- s1), 2: +t (1 -+ s2), 3: -t (1 +- s2); upper sign for D.
+  const bool minus = ((dir & 1) == 0) != DAG;  // projector (1 - gamma) ?
+  if (dir < 2) {
+    if (minus) { cpx<R> h = u * (p0 - p1); s0 = s0 + h; s1 = s1 - h; }
+    else       { cpx<R> h = u * (p0 + p1); s0 = s0 + h; s1 = s1 + h; }
+  } else {
+    if (minus) { cpx<R> h = u * (p0 + imul(p1)); s0 = s0 + h; s1 = s1 - imul(h); }
+    else       { cpx<R> h = u * (p0 - imul(p1)); s0 = s0 + h; s1 = s1 + imul(h); }
+  }
+}
+
+__device__ inline int fused_tile(int b, int nb) {
+  // XCD-aware order: block b runs on XCD b % 8; give XCD k the k-th eighth of the tiles.
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename R, int TX, int TT, int MODE, bool NT>
+__global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const cpx<R>* __restrict__ x,
+                                                           cpx<R>* __restrict__ y, int lx, int lt, R diag, R c,
+                                                           cpx<R>* __restrict__ xacc,
+                                                           const cpx<R>* __restrict__ aux) {
+  constexpr int HX = TX + 2, HT = TT + 2;
+  constexpr int RG = kThreads / TX;          // row groups
+  constexpr int PER = TX * TT / kThreads;    // sites per thread
+  static_assert(PER >= 1 && TX * TT % kThreads == 0, "tile shape");
+  __shared__ cpx<R> sp[HT * HX * 2];           // psi, halo included: [ht][hx][spin]
+  __shared__ cpx<R> sf[TT * TX * 2];           // phi on the tile
+  __shared__ cpx<R> sr[2 * TX + 2 * TT];       // projected phi on the ring: xm[TT] xp[TT] tm[TX] tp[TX]
+
+  const int V = lx * lt;
+  const int ntx = lx / TX;
+  const int tile = fused_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
+  const size_t off = (size_t)blockIdx.y * 2 * V;
+  const cpx<R>* __restrict__ xb = x + off;
+
+  // ---- stage psi (tile + halo) ----------------------------------------------
+  for (int i = threadIdx.x; i < HT * HX * 2; i += kThreads) {
+    const int comp = i & 1, site = i >> 1;
+    const int ht = site / HX, hx = site - ht * HX;
+    int gx = x0 + hx - 1, gt = t0 + ht - 1;
+    gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
+    gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
+    sp[i] = xb[2 * (gt * lx + gx) + comp];
+  }
+  __syncthreads();
+
+  auto P = [&](int ht, int hx, int comp) -> cpx<R> { return sp[(ht * HX + hx) * 2 + comp]; };
+  const R half = (R)0.5;
+
+  // D (or a projection of it) at halo coordinates (hx, ht), global (gx, gt).
+  auto d_at = [&](int hx, int ht, int gx, int gt, int skip, cpx<R> u0, cpx<R> u1, cpx<R> u0m, cpx<R> u1m,
+                  cpx<R>& o0, cpx<R>& o1) {
+    cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
+    if (skip != kSkipXp) hop_acc<R, false>(s0, s1, 0, u0, P(ht, hx + 1, 0), P(ht, hx + 1, 1));
+    if (skip != kSkipXm) hop_acc<R, false>(s0, s1, 1, cj(u0m), P(ht, hx - 1, 0), P(ht, hx - 1, 1));
+    if (skip != kSkipTp) hop_acc<R, false>(s0, s1, 2, u1, P(ht + 1, hx, 0), P(ht + 1, hx, 1));
+    if (skip != kSkipTm) hop_acc<R, false>(s0, s1, 3, cj(u1m), P(ht - 1, hx, 0), P(ht - 1, hx, 1));
+    o0 = diag * P(ht, hx, 0) - half * s0;
+    o1 = diag * P(ht, hx, 1) - half * s1;
+  };
+
+  // ---- phase 1: phi on the tile ------------------------------------------------
+  const int lxi = threadIdx.x % TX, lti = threadIdx.x / TX;
+  cpx<R> ku0[PER], ku1[PER], ku0m[PER], ku1m[PER], f0[PER], f1[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int r = lti + k * RG;
+    const int gx = x0 + lxi, gt = t0 + r;
+    const int s = gt * lx + gx;
+    const int sxm = gt * lx + (gx == 0 ? lx - 1 : gx - 1);
+    const int stm = (gt == 0 ? lt - 1 : gt - 1) * lx + gx;
+    ku0[k] = U[s];
+    ku1[k] = U[V + s];
+    ku0m[k] = U[sxm];
+    ku1m[k] = U[V + stm];
+    d_at(lxi + 1, r + 1, gx, gt, kSkipNone, ku0[k], ku1[k], ku0m[k], ku1m[k], f0[k], f1[k]);
+    sf[(r * TX + lxi) * 2] = f0[k];
+    sf[(r * TX + lxi) * 2 + 1] = f1[k];
+  }
+  // ---- phase 1b: projected phi on the ring -------------------------------------
+  for (int i = threadIdx.x; i < 2 * TX + 2 * TT; i += kThreads) {
+    int hx, ht, skip;
+    if (i < TT) { hx = 0; ht = i + 1; skip = kSkipXm; }                       // x = x0 - 1
+    else if (i < 2 * TT) { hx = TX + 1; ht = i - TT + 1; skip = kSkipXp; }    // x = x0 + TX
+    else if (i < 2 * TT + TX) { hx = i - 2 * TT + 1; ht = 0; skip = kSkipTm; }  // t = t0 - 1
+    else { hx = i - 2 * TT - TX + 1; ht = TT + 1; skip = kSkipTp; }            // t = t0 + TT
+    int gx = x0 + hx - 1, gt = t0 + ht - 1;
+    gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
+    gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
+    const int s = gt * lx + gx;
+    const int sxm = gt * lx + (gx == 0 ? lx - 1 : gx - 1);
+    const int stm = (gt == 0 ? lt - 1 : gt - 1) * lx + gx;
+    const cpx<R> z = mk<R>(0, 0);
+    const cpx<R> u0 = skip == kSkipXp ? z : U[s];
+    const cpx<R> u0m = skip == kSkipXm ? z : U[sxm];
+    const cpx<R> u1 = skip == kSkipTp ? z : U[V + s];
+    const cpx<R> u1m = skip == kSkipTm ? z : U[V + stm];
+    cpx<R> o0, o1;
+    d_at(hx, ht, gx, gt, skip, u0, u1, u0m, u1m, o0, o1);
+    // D^H at the neighbouring tile site uses: from x0-1 (its -x hop) (1 - s1) -> o0 - o1;
+    // from x0+TX (+x hop) (1 + s1) -> o0 + o1; from t0-1 (1 - s2) -> o0 + i o1;
+    // from t0+TT (1 + s2) -> o0 - i o1.
+    cpx<R> h;
+    if (skip == kSkipXm) h = o0 - o1;
+    else if (skip == kSkipXp) h = o0 + o1;
+    else if (skip == kSkipTm) h = o0 + imul(o1);
+    else h = o0 - imul(o1);
+    sr[i] = h;
+  }
+  __syncthreads();
+
+  // ---- phase 2: D^H phi on the tile ---------------------------------------------
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int r = lti + k * RG;
+    const int gx = x0 + lxi, gt = t0 + r;
+    const int s = gt * lx + gx;
+    cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
+    // +x neighbour: (1 + s1) U0_s phi_{s+x}
+    {
+      cpx<R> h;
+      if (lxi + 1 < TX) h = sf[(r * TX + lxi + 1) * 2] + sf[(r * TX + lxi + 1) * 2 + 1];
+      else h = sr[TT + r];
+      h = ku0[k] * h;
+      s0 = s0 + h; s1 = s1 + h;
+    }
+    // -x neighbour: (1 - s1) conj(U0_{s-x}) phi_{s-x}
+    {
+      cpx<R> h;
+      if (lxi > 0) h = sf[(r * TX + lxi - 1) * 2] - sf[(r * TX + lxi - 1) * 2 + 1];
+      else h = sr[r];
+      h = cj(ku0m[k]) * h;
+      s0 = s0 + h; s1 = s1 - h;
+    }
+    // +t neighbour: (1 + s2) U1_s phi_{s+t}: h = phi0 - i phi1, spread (1, i)
+    {
+      cpx<R> h;
+      if (r + 1 < TT) h = sf[((r + 1) * TX + lxi) * 2] - imul(sf[((r + 1) * TX + lxi) * 2 + 1]);
+      else h = sr[2 * TT + TX + lxi];
+      h = ku1[k] * h;
+      s0 = s0 + h; s1 = s1 + imul(h);
+    }
+    // -t neighbour: (1 - s2) conj(U1_{s-t}) phi_{s-t}: h = phi0 + i phi1, spread (1, -i)
+    {
+      cpx<R> h;
+      if (r > 0) h = sf[((r - 1) * TX + lxi) * 2] + imul(sf[((r - 1) * TX + lxi) * 2 + 1]);
+      else h = sr[2 * TT + lxi];
+      h = cj(ku1m[k]) * h;
+      s0 = s0 + h; s1 = s1 - imul(h);
+    }
+    const cpx<R> o0 = diag * f0[k] - half * s0;
+    const cpx<R> o1 = diag * f1[k] - half * s1;
+    const size_t i0 = off + 2 * (size_t)s, i1 = i0 + 1;
+    if (MODE == 0) {
+      if (NT) {  // streaming output: keep it out of the caches
+        __builtin_nontemporal_store(o0.re, &y[i0].re);
+        __builtin_nontemporal_store(o0.im, &y[i0].im);
+        __builtin_nontemporal_store(o1.re, &y[i1].re);
+        __builtin_nontemporal_store(o1.im, &y[i1].im);
+      } else {
+        y[i0] = o0; y[i1] = o1;
+      }
+    } else if (MODE == 1) {
+      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+      xacc[i0] = xacc[i0] + c * v0;
+      xacc[i1] = xacc[i1] + c * v1;
+      y[i0] = v0 - c * o0;
+      y[i1] = v1 - c * o1;
+    } else {
+      y[i0] = aux[i0] - o0;
+      y[i1] = aux[i1] - o1;
+    }
+  }
+}
+
 template <typename R>
 __global__ void k_prepare_links(const z64* __restrict__ g, cpx<R>* __restrict__ U, int lx, int lt, int anti) {
   const int V = lx * lt;
@@ -149,9 +347,76 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
   HIPCHECK(hipGetLastError());
 }
 
+template <typename R, int TX, int TT, bool NT>
+void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs, int mode,
+                  double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  dim3 grid((lx / TX) * (lt / TT), nrhs);
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 0, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
+                         (R)c, xacc, aux);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 1, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
+                         (R)c, xacc, aux);
+      break;
+    default:
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 2, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
+                         (R)c, xacc, aux);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+// Tile shape of the fused kernel, from measurements on MI355X at 2048^2 and 4096^2:
+//   FP64 with a working set (psi + links + y = 96 B/site) beyond the 256 MB
+//   Infinity Cache: 64x4; smaller FP64 lattices: 64x8 with non-temporal output
+//   stores; FP32: 32x16 with non-temporal output stores.
+// Shapes that do not divide the lattice fall back to the next one that does;
+// kTileNone means no tile fits and A is applied as D followed by D^H.
+enum { kTileNone = 0, kT64x4, kT64x8nt, kT32x16nt, kT32x8, kT16x16 };
+
+template <typename R>
+int fused_shape(int lx, int lt) {
+  const double ws = 96.0 * (sizeof(R) / 8.0) * lx * lt;
+  const bool big = ws > 256.0 * (1 << 20);
+  int pref[4];
+  if (sizeof(R) == 8) {
+    pref[0] = big ? kT64x4 : kT64x8nt;
+    pref[1] = big ? kT64x8nt : kT64x4;
+    pref[2] = kT32x16nt;
+    pref[3] = kT32x8;
+  } else {
+    pref[0] = kT32x16nt;
+    pref[1] = kT64x8nt;
+    pref[2] = kT64x4;
+    pref[3] = kT32x8;
+  }
+  auto fits = [&](int sh) {
+    switch (sh) {
+      case kT64x4: return lx % 64 == 0 && lt % 4 == 0;
+      case kT64x8nt: return lx % 64 == 0 && lt % 8 == 0;
+      case kT32x16nt: return lx % 32 == 0 && lt % 16 == 0;
+      case kT32x8: return lx % 32 == 0 && lt % 8 == 0;
+      case kT16x16: return lx % 16 == 0 && lt % 16 == 0;
+    }
+    return false;
+  };
+  for (int sh : pref)
+    if (fits(sh)) return sh;
+  return fits(kT16x16) ? kT16x16 : kTileNone;
+}
+
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
                    int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  switch (fused_shape<R>(lx, lt)) {
+    case kT64x4: launch_fused<R, 64, 4, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    case kT64x8nt: launch_fused<R, 64, 8, true>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    case kT32x16nt: launch_fused<R, 32, 16, true>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    case kT32x8: launch_fused<R, 32, 8, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    case kT16x16: launch_fused<R, 16, 16, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    default: break;
+  }
   launch_wilson<R>(U, x, tmp, lx, lt, diag, nrhs, false, st);
   const int V = lx * lt;
   dim3 grid((V + kThreads - 1) / kThreads, nrhs);

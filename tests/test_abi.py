@@ -40,7 +40,8 @@ def test_struct_layouts_match_c():
     assert p.mass.offset == 8
     assert p.block.offset == 20
     assert p.nv.offset == 20 + 6 * 2 * 4
-    assert ctypes.sizeof(p) % 8 == 0
+    assert p.seed.offset % 8 == 0 and p.sa_scale.offset == p.seed.offset + 8
+    assert ctypes.sizeof(p) == p.sa_scale.offset + 8
     s = smg.Stats
     assert s.fine_applies.offset == 16
     assert ctypes.sizeof(s) == 40
@@ -55,6 +56,7 @@ def test_default_params_and_strerror():
     assert (p.levels, p.smoother_steps, p.setup_iters) == (2, 4, 5)
     assert abs(p.smoother_omega - 0.8) < 1e-15
     assert p.block[0][0] == 4 and p.nv[0] == 8
+    assert abs(p.sa_scale - 4.0 / 3.0) < 1e-15
     assert lib.smg_strerror(-2).decode().startswith("lattice extents")
     assert lib.smg_strerror(1).decode().startswith("not converged")
 

@@ -75,7 +75,9 @@ def links_from_sparse(Ac, cx, ct, nc):
 # Fine operators
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("lx,lt,nrhs", [(30, 26, 3), (64, 48, 1), (8, 4, 2)])
+@pytest.mark.parametrize("lx,lt,nrhs", [(30, 26, 3), (64, 48, 1), (8, 4, 2), (128, 64, 2), (32, 32, 1),
+                                        (16, 64, 3), (192, 40, 1), (64, 12, 2), (256, 128, 1),
+                                        (96, 24, 1)])
 def test_apply_D_and_A(cuda, lx, lt, nrhs):
     smg = smg_mod()
     U = field(lx, lt, seed=lx + lt)
@@ -109,12 +111,37 @@ def test_apply_periodic_bc(cuda):
 # Hierarchy from given vectors: every step of the V-cycle
 # ---------------------------------------------------------------------------
 
+SA = 4.0 / 3.0
 CASES = [
-    # lx, lt, blocks, nvs, mass
-    (32, 24, [(4, 4), (2, 2)], [6, 5], 0.05),
-    (24, 24, [(4, 4)], [8], 0.1),
-    (40, 24, [(4, 2), (2, 3)], [4, 4], 0.2),
+    # lx, lt, blocks, nvs, mass, sa_scale
+    (32, 24, [(4, 4), (2, 2)], [6, 5], 0.05, SA),   # smoothed level 1, plain level 2
+    (24, 24, [(4, 4)], [8], 0.1, 0.0),              # plain aggregation
+    (40, 24, [(4, 2), (2, 3)], [4, 4], 0.2, SA),    # blocks too small to smooth
+    (64, 64, [(4, 4), (4, 4)], [6, 6], 0.03, SA),   # fused fine kernel, smoothed on both levels
+    (32, 32, [(4, 4), (4, 4)], [4, 4], 0.1, SA),    # coarse extents 8 -> 2 (two colours)
 ]
+
+
+def windowed(P, shape, block, nv, halo):
+    """Oracle sparse P -> [J, k, nw] over the (bx+2h) x (bt+2h) windows."""
+    lx, lt, dof = shape
+    bx, bt = block
+    cx, ct = lx // bx, lt // bt
+    wx, wy = bx + 2 * halo, bt + 2 * halo
+    Pd = P.tocsc()
+    out = np.zeros((cx * ct, nv, wx * wy * dof), dtype=np.complex128)
+    for J in range(cx * ct):
+        jt, jx = divmod(J, cx)
+        for a in range(wy):
+            for b in range(wx):
+                t = (jt * bt + a - halo) % lt
+                x = (jx * bx + b - halo) % lx
+                for d in range(dof):
+                    f = (t * lx + x) * dof + d
+                    i = (a * wx + b) * dof + d
+                    for k in range(nv):
+                        out[J, k, i] = Pd[f, J * nv + k]
+    return out
 
 
 @pytest.fixture(scope="module", params=range(len(CASES)))
@@ -124,12 +151,12 @@ def pair(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     smg = smg_mod()
-    lx, lt, blocks, nvs, m = CASES[request.param]
+    lx, lt, blocks, nvs, m, sa = CASES[request.param]
     U = field(lx, lt, seed=request.param + 1)
     vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, request.param + 7)
     A = normal_matrix(U, m)
-    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8)
-    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=sa)
+    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, sa_scale=sa)
     s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])),
                    calib=dev(np.concatenate(calib)))
     yield dict(U=U, A=A, h=h, s=s, lx=lx, lt=lt, blocks=blocks, nvs=nvs, m=m, calib=calib)
@@ -143,17 +170,40 @@ def test_smoother_coefficients(pair):
 
 
 def test_prolongator(pair):
+    """Tentative P_t (block Gram-Schmidt) and the smoothed P = (I - w A) P_t."""
     h, s = pair["h"], pair["s"]
     for l in range(len(pair["blocks"])):
-        assert rel_err(host(s.prolongator(l)), h.levels[l].U) <= 1e-12
+        lev = h.levels[l]
+        assert rel_err(host(s.prolongator(l)), lev.U) <= 1e-12
+        halo, w = s.transfer_info(l)
+        assert halo == (1 if lev.sa_weight > 0 else 0)
+        if halo:
+            assert abs(w - lev.sa_weight) <= 1e-12 * lev.sa_weight
+        ref = windowed(lev.P, lev.shape, lev.block, lev.U.shape[1], halo)
+        assert rel_err(host(s.prolongator(l, smoothed=True)), ref) <= 1e-12
+
+
+def dense_from_links(Lk, cx, ct, nc):
+    """[K, 9, nc, nc] link blocks -> dense coarse matrix (offsets naming the same
+    neighbour on extents <= 2 are summed, as the coarse apply does)."""
+    A = np.zeros((cx * ct * nc, cx * ct * nc), dtype=np.complex128)
+    for K in range(cx * ct):
+        kt, kx = divmod(K, cx)
+        for D in range(9):
+            dt, dx = D // 3 - 1, D % 3 - 1
+            Kn = ((kt + dt) % ct) * cx + (kx + dx) % cx
+            A[K * nc:(K + 1) * nc, Kn * nc:(Kn + 1) * nc] += Lk[K, D]
+    return A
 
 
 def test_coarse_links(pair):
     h, s = pair["h"], pair["s"]
     for l in range(1, len(pair["blocks"]) + 1):
         cx, ct, nc = s.level_info(l)
-        ref = links_from_sparse(h.levels[l].A, cx, ct, nc)
-        assert rel_err(host(s.coarse_links(l)), ref) <= 1e-12
+        links = host(s.coarse_links(l))
+        if min(cx, ct) >= 3:
+            assert rel_err(links, links_from_sparse(h.levels[l].A, cx, ct, nc)) <= 1e-12
+        assert rel_err(dense_from_links(links, cx, ct, nc), h.levels[l].A.toarray()) <= 1e-12
 
 
 def test_transfer_and_coarse_apply(pair):
@@ -218,7 +268,7 @@ def test_set_mass_rebuilds_coarse_operators(pair):
         h2 = mg.set_mass(h, normal_matrix(U, m2), pair["calib"], 4, 0.8)
         for l in range(1, len(pair["blocks"]) + 1):
             cx, ct, nc = s.level_info(l)
-            assert rel_err(host(s.coarse_links(l)), links_from_sparse(h2.levels[l].A, cx, ct, nc)) <= 1e-12
+            assert rel_err(dense_from_links(host(s.coarse_links(l)), cx, ct, nc), h2.levels[l].A.toarray()) <= 1e-12
         for l in range(len(pair["blocks"])):
             np.testing.assert_allclose(s.smoother_coefs(l), h2.levels[l].coefs, rtol=1e-12)
     finally:
@@ -244,9 +294,10 @@ def test_adaptive_setup_and_solve_c1(cuda):
     m = 0.1
     A = normal_matrix(U, m)
     rhs = dirac_matrix(U, m).conj().T @ b
-    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [8], R, nu=4, omega=0.8, setup_iters=5, coarsest="cg")
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [8], R, nu=4, omega=0.8, setup_iters=5, coarsest="cg",
+                          sa_scale=4 / 3)
     xo, io = mg.mg_cg(h, rhs, 1e-10)
-    p = smg.make_params(lx, lt, m, levels=2, blocks=[(4, 4)], nv=[8], coarsest=smg.COARSEST_CG)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=[(4, 4)], nv=[8], coarsest=smg.COARSEST_CG, sa_scale=4 / 3)
     s = smg.Solver(dev(U), p, randoms=dev(np.concatenate([r.ravel() for r in R])))
     # setup parity: smoother exactly, prolongator up to rounding amplified by the
     # setup iterations, compared through the per-aggregate projectors P_J P_J^H
@@ -256,6 +307,7 @@ def test_adaptive_setup_and_solve_c1(cuda):
     proj_g = np.einsum("jki,jkl->jil", Pg, Pg.conj())
     proj_o = np.einsum("jki,jkl->jil", Po, Po.conj())
     assert np.max(np.abs(proj_g - proj_o)) <= 1e-8
+    assert abs(s.transfer_info(0)[1] - h.levels[0].sa_weight) <= 1e-12 * h.levels[0].sa_weight
     for prec in (smg.FP64, smg.MIXED):
         x, st, code = s.solve(dev(rhs), tol=1e-10, maxiter=500, precision=prec)
         assert code == 0

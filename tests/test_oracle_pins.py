@@ -440,3 +440,98 @@ def test_topological_charge_is_integer_and_gauge_invariant():
     th2[1] = th[1] + a - np.roll(a, -1, axis=0)
     assert abs(synth.topological_charge(th2) - q) < 1e-9
     np.testing.assert_allclose(synth.mean_plaquette(th2), synth.mean_plaquette(th), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Smoothed aggregation (Adaptive Multigrid section)
+# ---------------------------------------------------------------------------
+
+def test_sa_free_field_closed_form():
+    """Free field, periodic BC, constant candidates: A 1 = m^2 1, so the smoothed
+    prolongator maps the coarse constant to (1 - w m^2) times the fine constant
+    and the coarse operator has eigenvalue m^2 (1 - w m^2)^2 on it."""
+    lx, lt, m, w = 8, 8, 0.3, 0.07
+    U = np.ones((2, lt, lx), dtype=np.complex128)
+    A = normal_matrix(U, m, antiperiodic_t=False)
+    V = np.zeros((2, 2 * lx * lt), dtype=np.complex128)
+    V[0, 0::2] = 1.0
+    V[1, 1::2] = 1.0
+    lev = mg.Level(A=A, shape=(lx, lt, 2))
+    lev, nxt = mg.coarsen(lev, V, (4, 4), sa_weight=w)
+    e = np.ones(nxt.A.shape[0], dtype=np.complex128)
+    np.testing.assert_allclose(nxt.A @ e, m * m * (1 - w * m * m) ** 2 * e, atol=1e-13)
+    np.testing.assert_allclose(lev.P @ e, (1 - w * m * m) * (lev.P_t @ e), atol=1e-14)
+
+
+def test_sa_columns_live_on_block_plus_ring_and_stencil_stays_nine_point():
+    lx = lt = 16
+    U = hot_field(lx, lt, seed=51, sweeps=10)
+    A = normal_matrix(U, 0.1)
+    R = synth.setup_randoms(lx, lt, [(4, 4)], [3], 5)
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [3], R, nu=2, omega=0.8, setup_iters=2, sa_scale=4 / 3)
+    lev = h.levels[0]
+    assert lev.sa_weight > 0
+    P = lev.P.toarray()
+    for J in range(16):
+        jt, jx = divmod(J, 4)
+        rows = np.nonzero(np.abs(P[:, J * 3:(J + 1) * 3]).sum(axis=1))[0]
+        for row in rows:
+            t, x = divmod(row // 2, lx)
+            dx = (x - jx * 4 + 1) % lx
+            dt = (t - jt * 4 + 1) % lt
+            assert dx <= 5 and dt <= 5, "smoothed column leaves the block plus one ring"
+    Ac = h.levels[1].A.toarray()
+    assert np.allclose(Ac, Ac.conj().T, atol=1e-14)
+    for K in range(16):
+        kt, kx = divmod(K, 4)
+        for Kn in range(16):
+            nt, nx = divmod(Kn, 4)
+            near = min((nx - kx) % 4, (kx - nx) % 4) <= 1 and min((nt - kt) % 4, (kt - nt) % 4) <= 1
+            if not near:
+                assert np.max(np.abs(Ac[K * 3:(K + 1) * 3, Kn * 3:(Kn + 1) * 3])) == 0.0
+
+
+def test_sa_weight_from_power_iteration_and_applicability():
+    lx = lt = 16
+    U = hot_field(lx, lt, seed=52, sweeps=10)
+    A = normal_matrix(U, 0.1)
+    start = synth.gaussian(2 * lx * lt, 3)
+    lam = mg.power_lambda_max(A, start, 200)
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev[-1] * 0.97 <= lam <= ev[-1] * (1 + 1e-12)
+    assert mg.sa_applies((16, 16, 2), (4, 4))
+    assert not mg.sa_applies((16, 16, 2), (2, 4))
+    assert not mg.sa_applies((4, 16, 2), (4, 4))
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_sa_vcycle_error_propagator_and_projector(levels):
+    """The V-cycle identity and the A-orthogonal coarse projector hold with the
+    smoothed prolongator (Galerkin with any full-rank P)."""
+    lx = lt = 16 if levels == 2 else 32
+    U = hot_field(lx, lt, seed=53, sweeps=10)
+    A = normal_matrix(U, 0.2)
+    blocks = [(4, 4)] * (levels - 1)
+    nvs = [3] * (levels - 1)
+    R = synth.setup_randoms(lx, lt, blocks, nvs, 6)
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, nu=2, omega=0.8, setup_iters=2, sa_scale=4 / 3)
+    assert h.levels[0].sa_weight > 0
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    lev = h.levels[0]
+    P = lev.P.toarray()
+    if levels == 2:
+        Ac = h.levels[1].A.toarray()
+        E = np.eye(n) - P @ np.linalg.solve(Ac, P.conj().T @ Ad)
+        np.testing.assert_allclose(E @ E, E, atol=1e-10)
+        np.testing.assert_allclose(Ad @ E, (Ad @ E).conj().T, atol=1e-10)
+    nc = P.shape[1]
+    b = synth.gaussian(n, 8)
+    # apply both sides of I - V A = (I - R A)(I - P V_c P^H A)(I - R A) to one vector
+    def R_(v):
+        return mg.smoother_apply(A, lev.coefs, v)
+    lhs = b - mg.vcycle(h, 0, A @ b)
+    v1 = b - R_(A @ b)
+    v2 = v1 - P @ mg.vcycle(h, 1, P.conj().T @ (A @ v1))
+    rhs = v2 - R_(A @ v2)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.linalg.norm(b))

@@ -1,0 +1,140 @@
+"""Write masses at prescribed spectral ratios lambda_min(A)/lambda_max(A) (offline).
+
+The paper sweeps the mass gap m - m_crit towards zero (Results section) but does
+not give m_crit.  The benchmark instead fixes, per gauge field, the masses at which
+the condition number of A = D^H D reaches given ratios.  This script finds them
+with the FP64 oracle's sparse D and A:
+
+  * lambda_min(A(m)) = sigma_min(D(m))^2 by shift-invert Lanczos, with
+    A^{-1} = D^{-1} D^{-H} from a sparse LU of D;
+  * lambda_max(A(m)) by 60 power iterations (about 1% accurate, enough for a ratio);
+  1. scan lambda_min on a grid, refine the minimiser m* by golden section;
+  2. for each target ratio r, bisect on m > m* for lambda_min/lambda_max = r; if
+     the field is gapped and r is out of reach, m* is used and the reached ratio
+     is recorded.
+
+Usage: python -m workloads.make_masses  (writes workloads/c2_masses.json)
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle.wilson import dirac_matrix  # noqa: E402
+
+C2 = dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
+          ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4])
+
+_FIELDS = {}
+
+
+def field(L, beta, sweeps, seed):
+    key = (L, beta, sweeps, seed)
+    if key not in _FIELDS:
+        _FIELDS[key] = synth.metropolis_u1(L, L, beta, sweeps, seed)
+    return _FIELDS[key]
+
+
+def extremes(U, m):
+    """(lambda_min, lambda_max) of A(m) = D(m)^H D(m)."""
+    D = dirac_matrix(U, m).tocsc()
+    A = (D.conj().T @ D).tocsr()
+    n = D.shape[0]
+    lu = spla.splu(D, permc_spec="MMD_AT_PLUS_A")
+    op = spla.LinearOperator((n, n), dtype=np.complex128,
+                             matvec=lambda v: lu.solve(lu.solve(np.asarray(v, np.complex128), trans="H")))
+    lmin = spla.eigsh(A, k=1, sigma=0.0, which="LM", OPinv=op, tol=1e-6, return_eigenvectors=False)[0]
+    v = np.random.default_rng(0).standard_normal(n) + 0j
+    lmax = 0.0
+    for _ in range(60):
+        w = A @ v
+        lmax = np.vdot(v, w).real / np.vdot(v, v).real
+        v = w / np.linalg.norm(w)
+    return float(lmin), float(lmax)
+
+
+def find_mstar(args):
+    L, beta, sweeps, seed = args
+    th = field(L, beta, sweeps, seed)
+    U = synth.links_from_angles(th)
+    cache = {}
+
+    def lmin(m):
+        if m not in cache:
+            cache[m] = extremes(U, m)[0]
+        return cache[m]
+
+    grid = np.linspace(-0.3, 0.1, 9)
+    vals = [lmin(float(m)) for m in grid]
+    i = int(np.argmin(vals))
+    a, b = float(grid[max(i - 1, 0)]), float(grid[min(i + 1, len(grid) - 1)])
+    g = (math.sqrt(5) - 1) / 2
+    c, d = b - g * (b - a), a + g * (b - a)
+    for _ in range(12):
+        if lmin(c) < lmin(d):
+            b = d
+        else:
+            a = c
+        c, d = b - g * (b - a), a + g * (b - a)
+    mstar = 0.5 * (a + b)
+    lo_min, lo_max = extremes(U, mstar)
+    return dict(seed=seed, m_star=mstar, lambda_min=lo_min, lambda_max=lo_max,
+                plaquette=synth.mean_plaquette(th), topological_charge=round(synth.topological_charge(th)))
+
+
+def bisect_target(args):
+    L, beta, sweeps, seed, mstar, r0, target = args
+    U = synth.links_from_angles(field(L, beta, sweeps, seed))
+    if r0 >= target:
+        return dict(target=target, mass=mstar, ratio=r0, reached=False)
+    lo, hi = mstar, mstar + 0.05
+    while True:
+        mn, mx = extremes(U, hi)
+        if mn / mx > target:
+            break
+        lo, hi = hi, hi + 0.05
+    for _ in range(14):
+        mid = 0.5 * (lo + hi)
+        mn, mx = extremes(U, mid)
+        if mn / mx > target:
+            hi = mid
+        else:
+            lo = mid
+    mn, mx = extremes(U, hi)
+    return dict(target=target, mass=hi, ratio=mn / mx, reached=True)
+
+
+def main():
+    cfg = C2
+    t0 = time.time()
+    base = [(cfg["L"], cfg["beta"], cfg["sweeps"], s) for s in cfg["seeds"]]
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        stars = list(ex.map(find_mstar, base))
+        jobs = [(cfg["L"], cfg["beta"], cfg["sweeps"], st["seed"], st["m_star"], st["lambda_min"] / st["lambda_max"], r)
+                for st in stars for r in cfg["ratios"]]
+        res = list(ex.map(bisect_target, jobs))
+    fields = []
+    for k, st in enumerate(stars):
+        fld = dict(st, L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
+        fld["masses"] = res[k * len(cfg["ratios"]):(k + 1) * len(cfg["ratios"])]
+        fields.append(fld)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_masses.json")
+    with open(path, "w") as f:
+        json.dump(dict(config=cfg, fields=fields, seconds=time.time() - t0), f, indent=1)
+    print(path)
+
+
+if __name__ == "__main__":
+    main()
