@@ -39,6 +39,7 @@ NV = [12, 12]
 NU = 4
 OMEGA = 0.8
 SETUP_ITERS = 5
+SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
 
@@ -83,7 +84,7 @@ def cpu_baseline_leg():
     R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
     t0 = time.perf_counter()
     h = mg.adaptive_setup(normal_matrix(U, m_light), (L, L, 2), BLOCKS, NV, R, nu=NU, omega=OMEGA,
-                          setup_iters=SETUP_ITERS)
+                          setup_iters=SETUP_ITERS, sa_scale=SA_SCALE)
     setup_s = time.perf_counter() - t0
     b = synth.gaussian(2 * L * L, 10000 * 2 + 0)
     solve_s, iters, res = [], [], []
@@ -134,6 +135,76 @@ def timed_events(fn, reps, stream):
     return start.elapsed_time(stop) * 1e-3 / reps
 
 
+COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f32_level1_256_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size), or None when
+    the kernel source changed since they were taken."""
+    import hashlib
+
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    vals = dict(line.split(" = ", 1) for line in text.splitlines() if " = " in line and line[:1].isalpha())
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256", "").strip() != src:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
+    """Average launch time of the FP32 coarse operator on level 1 (the kernel that
+    dominates the mixed-precision V-cycle), and its algorithmic bytes: 9 link
+    blocks of nc x nc complex64 per coarse site plus the input and output vector."""
+    import ctypes
+
+    cx, ct, nc = s.level_info(1)
+    v = torch.randn(cx * ct * nc, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(v)
+    px, py = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    dur = timed_events(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
+    nbytes = 9 * nc * nc * 8 * cx * ct + 2 * cx * ct * nc * 8
+    gbs = nbytes / dur / 1e9
+    return dict(kernel=f"k_coarse<float,0,1>: FP32 coarse 9-point operator, level 1 ({cx}x{ct} sites, nc={nc}), "
+                       "single RHS", bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
+                traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes)
+
+
+def kernel_probe(reps):
+    """Launch only the roofline kernel and a plain copy of known size (for PMC runs)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_0710_3612_amd as smg
+    import synth
+
+    dev = torch.device("cuda:0")
+    U = synth.links_from_angles(synth.metropolis_u1(L, L, BETA, 20, SEEDS[0]))
+    p = smg.make_params(L, L, 0.0, levels=3, blocks=BLOCKS, nv=NV, setup_iters=0, smoother_steps=NU,
+                        smoother_omega=OMEGA, seed=SEEDS[0], sa_scale=SA_SCALE)
+    s = smg.Solver(torch.from_numpy(U).to(dev), p)
+    lib = smg.load_library()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    roof = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev)
+    # calibration: an elementwise FP32 kernel that reads and writes 64 MiB each
+    a = torch.ones(16 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.add(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(roofline=roof, copy_read_bytes=a.numel() * 4, copy_write_bytes=b.numel() * 4)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,7 +213,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=200)
+    ap.add_argument("--streams", type=int, default=8, help="concurrent solve streams")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only launch the roofline kernel and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
+    if args.kernel_probe:
+        kernel_probe(args.dslash_reps)
+        return 0
 
     if args.cpu_baseline_leg:
         print(json.dumps(cpu_baseline_leg()))
@@ -183,7 +260,7 @@ def main():
         ms = masses[seed]
         m_light = min(ms)
         p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=NV, setup_iters=SETUP_ITERS,
-                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed)
+                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE)
         R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
         g = T(U)
         rnd = T(np.concatenate([r.ravel() for r in R]))
@@ -206,17 +283,32 @@ def main():
         log(f"field {seed}: setup {setup_s[-1]:.2f}s")
     xs = [torch.empty_like(rhs) for _, rhs, _, _ in systems]
 
-    records = {}
+    # The systems are independent: worker threads, each with its own stream, keep
+    # several solves in flight (ctypes releases the GIL during library calls).
+    from concurrent.futures import ThreadPoolExecutor
+
+    nwork = max(1, min(args.streams, len(systems)))
+    streams = [torch.cuda.Stream(dev) for _ in range(nwork)]
+    torch.cuda.synchronize()
+
+    def run_share(w, prec, rec):
+        with torch.cuda.stream(streams[w]):
+            for k in range(w, len(systems), nwork):
+                s, rhs, seed, m = systems[k]
+                x, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=xs[k], stream=streams[w])
+                if code != 0 or st[0]["true_relres"] > TOL:
+                    raise RuntimeError(f"solve did not converge: field {seed} mass {m} {st[0]}")
+                if rec is not None:
+                    rec.append(dict(seed=seed, mass=m, iterations=st[0]["iterations"],
+                                    refinements=st[0]["refinements"], fine_applies=st[0]["fine_applies"],
+                                    relres=st[0]["true_relres"], seconds=st[0]["seconds"]))
+
+    pool = ThreadPoolExecutor(max_workers=nwork)
 
     def step(prec, rec=None):
-        for k, (s, rhs, seed, m) in enumerate(systems):
-            x, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=xs[k])
-            if code != 0 or st[0]["true_relres"] > TOL:
-                raise RuntimeError(f"solve did not converge: field {seed} mass {m} {st[0]}")
-            if rec is not None:
-                rec.append(dict(seed=seed, mass=m, iterations=st[0]["iterations"],
-                                refinements=st[0]["refinements"], fine_applies=st[0]["fine_applies"],
-                                relres=st[0]["true_relres"]))
+        futs = [pool.submit(run_share, w, prec, rec) for w in range(nwork)]
+        for f in futs:
+            f.result()
 
     results = {}
     for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
@@ -232,36 +324,36 @@ def main():
         dt = time.perf_counter() - t0
         results[name] = dict(seconds=dt, solves=len(systems) * args.steps, records=rec)
         log(f"{name}: {len(systems) * args.steps / dt:.1f} solves/s")
+    pool.shutdown()
 
-    # ---- dominant-kernel roofline: level-2 coarse operator of the mixed solve --------
-    # (measured with HIP events on the solver's stream)
-    s = systems[0][0]
-    cx, ct, nc = s.level_info(1)
-    v1 = T(synth.gaussian(cx * ct * nc, 5))
-    y1 = torch.empty_like(v1)
-    lib = smg.load_library()
+    # ---- dominant-kernel roofline: the FP32 level-2 coarse operator of the mixed solve
+    # (64x64 coarse sites, nc = 12), measured with HIP events on the solver's stream
     import ctypes
 
-    h = s.handle
+    lib = smg.load_library()
     sp = ctypes.c_void_p(stream.cuda_stream)
-    px, py = ctypes.c_void_p(v1.data_ptr()), ctypes.c_void_p(y1.data_ptr())
-    dur_c = timed_events(lambda: lib.smg_apply_level(h, 1, px, py, 1, sp), args.dslash_reps, stream)
-    coarse_bytes = 9 * nc * nc * 16 * cx * ct + 2 * cx * ct * nc * 16    # FP64 links + in/out vectors
-    coarse_gbs = coarse_bytes / dur_c / 1e9
+    s = systems[0][0]
+    roof = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev)
 
-    # ---- fine D^H D at 2048^2 (HBM-bound working set) -----------------------------
-    th = np.random.default_rng(5000).uniform(-math.pi, math.pi, size=(2, DSLASH_L, DSLASH_L))
-    gbig = T(np.exp(1j * th))
-    pbig = smg.make_params(DSLASH_L, DSLASH_L, 0.01, levels=1)
-    sbig = smg.Solver(gbig, pbig)
-    xb = T(synth.gaussian(2 * DSLASH_L * DSLASH_L, 6))
-    yb = torch.empty_like(xb)
-    hb = sbig.handle
-    pxb, pyb = ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr())
-    dur_a = timed_events(lambda: lib.smg_apply_A(hb, pxb, pyb, 1, sp), args.dslash_reps, stream)
-    V = DSLASH_L * DSLASH_L
-    a_bytes = V * (32 + 32 + 32)          # psi in, A psi out, 2 links per site (FP64)
-    a_gbs = a_bytes / dur_a / 1e9
+    # ---- fine D^H D at 2048^2 and 4096^2 (working sets beyond the caches) ------------
+    def dslash(Ld):
+        th = np.random.default_rng(5000 + Ld).uniform(-math.pi, math.pi, size=(2, Ld, Ld))
+        sbig = smg.Solver(T(np.exp(1j * th)), smg.make_params(Ld, Ld, 0.01, levels=1))
+        xb = T(synth.gaussian(2 * Ld * Ld, 6))
+        yb = torch.empty_like(xb)
+        hb = sbig.handle
+        pxb, pyb = ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr())
+        dur = timed_events(lambda: lib.smg_apply_A(hb, pxb, pyb, 1, sp), args.dslash_reps, stream)
+        nbytes = Ld * Ld * (32 + 32 + 32)     # psi in, A psi out, 2 links per site (FP64)
+        sbig.close()
+        del xb, yb
+        torch.cuda.empty_cache()
+        return dict(kernel=f"fine A = D^H D, {Ld}x{Ld}, FP64, single RHS", bound="hbm",
+                    achieved=nbytes / dur / 1e9, peak=8000.0, unit="GB/s", frac=nbytes / dur / 1e9 / 8000.0,
+                    avg_launch_us=dur * 1e6, bytes_per_launch=nbytes)
+
+    dslash_2048 = dslash(DSLASH_L)
+    dslash_4096 = dslash(2 * DSLASH_L)
 
     cpu = None
     if cpu_proc is not None:
@@ -297,6 +389,7 @@ def main():
             "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
                         "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10",
             "systems_per_step": len(systems),
+            "concurrent_streams": nwork,
             "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
             "mixed_over_fp64": (mixed["solves"] / mixed["seconds"]) / (fp64["solves"] / fp64["seconds"]),
             "setup_s_per_field": setup_s,
@@ -305,27 +398,9 @@ def main():
             "mean_iterations_fp64": sum(r["iterations"] for r in fp64["records"]) / len(fp64["records"]),
             "max_relres": max(r["relres"] for r in mixed["records"] + fp64["records"]),
         },
-        "roofline": {
-            "kernel": "coarse 9-point operator, level 2 (64x64, nc=12, FP64), single RHS",
-            "bound": "hbm",
-            "achieved": coarse_gbs,
-            "peak": 8000.0,
-            "unit": "GB/s",
-            "frac": coarse_gbs / 8000.0,
-            "traffic": None,
-            "avg_launch_us": dur_c * 1e6,
-            "bytes_per_launch": coarse_bytes,
-        },
-        "dslash": {
-            "kernel": f"fine A = D^H D, {DSLASH_L}x{DSLASH_L}, FP64, single RHS",
-            "bound": "hbm",
-            "achieved": a_gbs,
-            "peak": 8000.0,
-            "unit": "GB/s",
-            "frac": a_gbs / 8000.0,
-            "avg_launch_us": dur_a * 1e6,
-            "bytes_per_launch": a_bytes,
-        },
+        "roofline": roof,
+        "dslash": dslash_2048,
+        "dslash_4096": dslash_4096,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

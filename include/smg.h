@@ -152,6 +152,11 @@ int smg_apply_A(smg_handle h, const double* x, double* y, int32_t nrhs, void* st
 int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
                     void* stream);
 
+/* y = A^(l) x with the FP32 copy of the level-l operator that the mixed-precision
+ * solves use (the same operator as smg_apply_level, links rounded to FP32).
+ * x, y: device, complex64 (interleaved float) level-l batches.  ASYNC. */
+int smg_apply_level_f32(smg_handle h, int32_t level, const float* x, float* y, int32_t nrhs, void* stream);
+
 /* y = P^H x: restriction from level l to level l+1 (V-cycle step 2).  ASYNC. */
 int smg_restrict(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
                  void* stream);

@@ -119,6 +119,7 @@ def load_library():
         "smg_apply_D": (i32, [h, P, P, i32, i32, P]),
         "smg_apply_A": (i32, [h, P, P, i32, P]),
         "smg_apply_level": (i32, [h, i32, P, P, i32, P]),
+        "smg_apply_level_f32": (i32, [h, i32, P, P, i32, P]),
         "smg_restrict": (i32, [h, i32, P, P, i32, P]),
         "smg_prolong": (i32, [h, i32, P, P, i32, P]),
         "smg_smooth": (i32, [h, i32, P, P, i32, P]),
@@ -288,6 +289,19 @@ class Solver:
         nr = self._nrhs(x, self.level_size(level))
         y = self._new(x.shape, x)
         _check(self.lib.smg_apply_level(self.handle, level, _ptr(x), _ptr(y), nr, _stream(stream)))
+        return y
+
+    def apply_level_f32(self, level: int, x, stream=None):
+        """A^(l) x with the FP32 operator of the mixed-precision solver (complex64 in/out)."""
+        import torch
+
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
+            raise TypeError("expected a complex64 CUDA tensor")
+        x = x.contiguous()
+        nr = self._nrhs(x, self.level_size(level))
+        y = torch.empty_like(x)
+        _check(self.lib.smg_apply_level_f32(self.handle, level, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(y.data_ptr()), nr, _stream(stream)))
         return y
 
     def restrict(self, level: int, x, stream=None):

@@ -117,10 +117,10 @@ void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, 
 template <typename R>
 void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                      int nc, int ldk, int nrhs, hipStream_t st);
-// mode 0: y = P e ; mode 1: y += P e
+// mode 0: y = P e ; mode 1: y += P e.  wbuf holds nrhs * nK * nw scratch values.
 template <typename R>
-void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
-                    int nc, int ldk, int nrhs, int mode, hipStream_t st);
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
 
 // Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk,

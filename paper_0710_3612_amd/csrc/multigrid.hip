@@ -63,7 +63,7 @@ __device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
 template <typename R, int NCH>
 __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x, int K, int lx,
                                     int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
-                                    cpx<R>* __restrict__ out, size_t ostride_k) {
+                                    cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1) {
   const int lane = threadIdx.x & 63;
   const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
   cpx<R> xv[NCH];
@@ -73,7 +73,7 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* 
     xv[c] = (i < nagg) ? x[win_index(K, i, lx, lt, dof, bx, bt, cx, h)] : mk<R>(0, 0);
   }
   const cpx<R>* PK = P + (size_t)K * ldk * nagg;
-  for (int k = 0; k < nc; ++k) {
+  for (int k = kbeg; k < nc; k += kstep) {
     double re = 0, im = 0;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -90,25 +90,42 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* 
   }
 }
 
+// One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...
 template <typename R, int NCH>
 __global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
                                                        int bt, int h, int nc, int ldk) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
-  const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int K = blockIdx.x;
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
   const int rhs = blockIdx.y;
   restrict_one<R, NCH>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
-                       y + (size_t)rhs * nK * nc + (size_t)K * nc, 1);
+                       y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
 }
 
-// y (+)= P e; one thread per fine variable, gathering over the (at most 2 x 2)
-// aggregate windows that contain it.
+// Prolongation y (+)= P e in two deterministic phases.
+// Phase 1: per aggregate window, w[K][i] = sum_k P[K][k][i] e[K][k] (lanes walk the
+// window variables, so P rows are read coalesced and e is a broadcast).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_prolong_win(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ e,
+                                                          cpx<R>* __restrict__ wbuf, int nK, int nw, int nc, int ldk) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nK * nw) return;
+  const int K = (int)(idx / nw), i = (int)(idx - (size_t)K * nw);
+  const int rhs = blockIdx.y;
+  const cpx<R>* PK = P + (size_t)K * ldk * nw + i;
+  const cpx<R>* eK = e + ((size_t)rhs * nK + K) * nc;
+  cpx<R> acc = mk<R>(0, 0);
+  for (int k = 0; k < nc; ++k) fma_acc(acc, PK[(size_t)k * nw], eK[k]);
+  wbuf[(size_t)rhs * nK * nw + idx] = acc;
+}
+
+// Phase 2: every fine variable sums the window values that cover it (one window
+// for the tentative P, up to 2 x 2 for the smoothed one), in a fixed order.
 template <typename R, int MODE>
-__global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ e,
-                                                      cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx, int bt,
-                                                      int h, int nc, int ldk) {
+__global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __restrict__ wbuf, cpx<R>* __restrict__ y,
+                                                             int lx, int lt, int dof, int bx, int bt, int h) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int wxw = bx + 2 * h;
   const int nw = wxw * (bt + 2 * h) * dof;
@@ -118,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__
   const int rhs = blockIdx.y;
   const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
   const int t = site / lx, x = site - t * lx;
-  const cpx<R>* eb = e + (size_t)rhs * nK * nc;
+  const cpx<R>* wb = wbuf + (size_t)rhs * nK * nw;
   cpx<R> acc = mk<R>(0, 0);
   int jts[3], njt = 0, jxs[3], njx = 0;
   for (int q = -h; q <= h; ++q) {  // distinct candidate blocks
@@ -136,11 +153,7 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__
     for (int b = 0; b < njx; ++b) {
       int ox;
       if (!win_offset(x, jxs[b], bx, lx, h, ox)) continue;
-      const int J = jts[a] * cx + jxs[b];
-      const int i = ((ot + h) * wxw + (ox + h)) * dof + d;
-      const cpx<R>* PJ = P + (size_t)J * ldk * nw + i;
-      const cpx<R>* eJ = eb + (size_t)J * nc;
-      for (int k = 0; k < nc; ++k) fma_acc(acc, PJ[(size_t)k * nw], eJ[k]);
+      acc = acc + wb[(size_t)(jts[a] * cx + jxs[b]) * nw + ((ot + h) * wxw + (ox + h)) * dof + d];
     }
   }
   const size_t o = (size_t)rhs * n + idx;
@@ -152,39 +165,65 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const cpx<R>* __restrict__
 
 // ---------------------------------------------------------------------------
 // Coarse 9-point operator: y_K = sum_D L_{K,D} v_{K+D}.  Links are stored
-// [D][col][K][row]: thread (K,row) reads consecutive words for each (D, col).
+// [D][col][K][row], so for a fixed (D, col) consecutive outputs (K, row) read
+// consecutive words.  A workgroup owns 64 consecutive outputs; its four
+// wavefronts each sum a quarter of the columns for all nine link blocks and the
+// partial sums meet in LDS.  Up to NR right-hand sides share every link load.
 // ---------------------------------------------------------------------------
-template <typename R, int MODE>
+template <typename R, int MODE, int NR>
 __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ L, const cpx<R>* __restrict__ v,
-                                                     cpx<R>* __restrict__ y, int cx, int ct, int nc, R c,
+                                                     cpx<R>* __restrict__ y, int cx, int ct, int nc, int nrhs, R c,
                                                      cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux) {
+  __shared__ cpx<R> part[3][NR][64];
   const int nK = cx * ct;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nK * nc) return;
-  const int K = tid / nc;
-  const int Kt = K / cx, Kx = K - Kt * cx;
   const size_t n = (size_t)nK * nc;
-  const size_t off = (size_t)blockIdx.y * n;
-  const cpx<R>* vb = v + off;
-  cpx<R> acc = mk<R>(0, 0);
-  for (int D = 0; D < 9; ++D) {
-    const int dt = D / 3 - 1, dx = D % 3 - 1;
-    int nx = Kx + dx, nt = Kt + dt;
-    nx = nx < 0 ? nx + cx : (nx >= cx ? nx - cx : nx);
-    nt = nt < 0 ? nt + ct : (nt >= ct ? nt - ct : nt);
-    const cpx<R>* vn = vb + (size_t)(nt * cx + nx) * nc;
-    const cpx<R>* LD = L + (size_t)D * nc * n + tid;
-    for (int col = 0; col < nc; ++col) fma_acc(acc, LD[(size_t)col * n], vn[col]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = blockIdx.x * 64 + lane;  // output index (K, row)
+  const int rhs0 = blockIdx.y * NR;
+  const bool live = tid < (int)n;
+  const int q = (nc + 3) / 4;
+  const int c0 = w * q, c1 = min(nc, c0 + q);
+  cpx<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = mk<R>(0, 0);
+  if (live) {
+    const int K = tid / nc;
+    const int Kt = K / cx, Kx = K - Kt * cx;
+    for (int D = 0; D < 9; ++D) {
+      const int dt = D / 3 - 1, dx = D % 3 - 1;
+      int nx = Kx + dx, nt = Kt + dt;
+      nx = nx < 0 ? nx + cx : (nx >= cx ? nx - cx : nx);
+      nt = nt < 0 ? nt + ct : (nt >= ct ? nt - ct : nt);
+      const size_t vn = (size_t)(nt * cx + nx) * nc;
+      const cpx<R>* LD = L + (size_t)D * nc * n + tid;
+      for (int col = c0; col < c1; ++col) {
+        const cpx<R> l = LD[(size_t)col * n];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (rhs0 + r < nrhs) fma_acc(acc[r], l, v[(size_t)(rhs0 + r) * n + vn + col]);
+      }
+    }
   }
-  const size_t o = off + tid;
-  if (MODE == 0) {
-    y[o] = acc;
-  } else if (MODE == 1) {
-    const cpx<R> vi = v[o];
-    xacc[o] = xacc[o] + c * vi;
-    y[o] = vi - c * acc;
-  } else {
-    y[o] = aux[o] - acc;
+  if (w > 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) part[w - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (w != 0 || !live) return;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (rhs0 + r >= nrhs) break;
+    const cpx<R> sum = acc[r] + part[0][r][lane] + part[1][r][lane] + part[2][r][lane];
+    const size_t o = (size_t)(rhs0 + r) * n + tid;
+    if (MODE == 0) {
+      y[o] = sum;
+    } else if (MODE == 1) {
+      const cpx<R> vi = v[o];
+      xacc[o] = xacc[o] + c * vi;
+      y[o] = vi - c * sum;
+    } else {
+      y[o] = aux[o] - sum;
+    }
   }
 }
 
@@ -512,7 +551,7 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
                      int nc, int ldk, int nrhs, hipStream_t st) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
-  dim3 grid((nK + 3) / 4, nrhs);
+  dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
     hipLaunchKernelGGL((k_restrict<R, decltype(c)::v>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h,
                        nc, ldk);
@@ -521,29 +560,50 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
 }
 
 template <typename R>
-void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
-                    int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+  const int nK = (lx / bx) * (lt / bt);
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  const size_t nkw = (size_t)nK * nw;
+  hipLaunchKernelGGL((k_prolong_win<R>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs), dim3(kThreads), 0,
+                     st, P, e, wbuf, nK, nw, nc, ldk);
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
   if (mode == 0)
-    hipLaunchKernelGGL((k_prolong<R, 0>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, h, nc, ldk);
+    hipLaunchKernelGGL((k_prolong_gather<R, 0>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt, h);
   else
-    hipLaunchKernelGGL((k_prolong<R, 1>), grid, dim3(kThreads), 0, st, P, e, y, lx, lt, dof, bx, bt, h, nc, ldk);
+    hipLaunchKernelGGL((k_prolong_gather<R, 1>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt, h);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R, int NR>
+void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+                      double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  const size_t total = (size_t)cx * ct * nc;
+  dim3 grid((unsigned)((total + 63) / 64), (nrhs + NR - 1) / NR);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarse<R, 0, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+                       aux);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_coarse<R, 1, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+                       aux);
+  else
+    hipLaunchKernelGGL((k_coarse<R, 2, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+                       aux);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                    cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
-  const size_t total = (size_t)cx * ct * nc;
-  dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_coarse<R, 0>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse<R, 1>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
+  if (nrhs == 1)
+    launch_coarse_nr<R, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else if (nrhs <= 2)
+    launch_coarse_nr<R, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else if (nrhs <= 4)
+    launch_coarse_nr<R, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
   else
-    hipLaunchKernelGGL((k_coarse<R, 2>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, xacc, aux);
-  HIPCHECK(hipGetLastError());
+    launch_coarse_nr<R, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
 }
 
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int* fail,
@@ -637,8 +697,8 @@ void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int n
 #define INST(R)                                                                                                  \
   template void launch_restrict<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int, \
                                    int, hipStream_t);                                                            \
-  template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int,  \
-                                  int, int, hipStream_t);                                                        \
+  template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int, int, int, int, int,  \
+                                  int, int, int, int, hipStream_t);                                              \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
                                  const cpx<R>*, hipStream_t);                                                    \
   template void launch_dense_apply<R>(const z64*, const cpx<R>*, cpx<R>*, int, int, hipStream_t);                \

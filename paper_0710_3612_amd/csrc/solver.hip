@@ -80,6 +80,8 @@ struct Level {
   // work vectors, `cap` columns each
   int cap = 0;
   cpx<R>*b = nullptr, *x = nullptr, *r = nullptr, *t = nullptr, *tmp = nullptr;
+  cpx<R>* wbuf = nullptr;           // prolongation scratch, cap * nK * nw values
+  size_t nkw() const { return bx ? (size_t)(lx / bx) * (lt / bt) * (bx + 2 * halo) * (bt + 2 * halo) * dof : 0; }
 };
 
 struct Scal {
@@ -181,6 +183,7 @@ void ensure_level_work(Ctx& c, int nrhs) {
     lv.r = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
     lv.t = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
     if (lv.fine) lv.tmp = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
+    if (lv.bx) lv.wbuf = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.nkw());
   }
 }
 
@@ -216,7 +219,7 @@ void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
 
 template <typename R>
 void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, int mode) {
-  launch_prolong<R>(lv.P, e, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st);
+  launch_prolong<R>(lv.P, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st);
 }
 
 // x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).
@@ -964,6 +967,20 @@ int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int
   API_END
 }
 
+int smg_apply_level_f32(smg_handle h, int32_t level, const float* x, float* y, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (!x || !y) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  ensure_f32(*c);
+  ensure_level_work<float>(*c, nrhs);
+  apply_op<float>(*c, c->L32[level], (const z32*)x, (z32*)y, nrhs, 0, 0.0, nullptr, nullptr);
+  return SMG_OK;
+  API_END
+}
+
 int smg_apply_A(smg_handle h, const double* x, double* y, int32_t nrhs, void* stream) {
   return smg_apply_level(h, 0, x, y, nrhs, stream);
 }
@@ -989,6 +1006,7 @@ int smg_prolong(smg_handle h, int32_t level, const double* x, double* y, int32_t
   if (level >= c->nlev - 1) throw Error(SMG_EINVAL, "no coarser level");
   if (!x || !y) throw Error(SMG_EINVAL, "null vector");
   c->st = (hipStream_t)stream;
+  ensure_level_work<double>(*c, nrhs);
   prolong_from<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs, 0);
   return SMG_OK;
   API_END

@@ -368,9 +368,9 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
 }
 
 // Tile shape of the fused kernel, from measurements on MI355X at 2048^2 and 4096^2:
-//   FP64 with a working set (psi + links + y = 96 B/site) beyond the 256 MB
-//   Infinity Cache: 64x4; smaller FP64 lattices: 64x8 with non-temporal output
-//   stores; FP32: 32x16 with non-temporal output stores.
+//   FP64 with a working set (psi + links + y = 96 B/site) above 1 GB: 64x4;
+//   smaller FP64 lattices: 64x8 with non-temporal output stores; FP32: 32x16
+//   with non-temporal output stores.
 // Shapes that do not divide the lattice fall back to the next one that does;
 // kTileNone means no tile fits and A is applied as D followed by D^H.
 enum { kTileNone = 0, kT64x4, kT64x8nt, kT32x16nt, kT32x8, kT16x16 };
@@ -378,7 +378,7 @@ enum { kTileNone = 0, kT64x4, kT64x8nt, kT32x16nt, kT32x8, kT16x16 };
 template <typename R>
 int fused_shape(int lx, int lt) {
   const double ws = 96.0 * (sizeof(R) / 8.0) * lx * lt;
-  const bool big = ws > 256.0 * (1 << 20);
+  const bool big = ws > 1024.0 * (1 << 20);
   int pref[4];
   if (sizeof(R) == 8) {
     pref[0] = big ? kT64x4 : kT64x8nt;

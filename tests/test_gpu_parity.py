@@ -119,6 +119,7 @@ CASES = [
     (40, 24, [(4, 2), (2, 3)], [4, 4], 0.2, SA),    # blocks too small to smooth
     (64, 64, [(4, 4), (4, 4)], [6, 6], 0.03, SA),   # fused fine kernel, smoothed on both levels
     (32, 32, [(4, 4), (4, 4)], [4, 4], 0.1, SA),    # coarse extents 8 -> 2 (two colours)
+    (20, 20, [(4, 4)], [5], 0.1, SA),               # odd coarse vector length (5 x 5 x 5)
 ]
 
 
@@ -351,3 +352,21 @@ def test_batch_invariance_and_edge_cases(cuda):
         s.solve(dev(bad), tol=1e-10)
     assert ei.value.code == -5
     s.close()
+
+
+def test_fp32_operators(pair):
+    """The FP32 copies of every level's operator (used inside the mixed-precision
+    solves) against the FP64 oracle.  Inputs and links are rounded to FP32 (unit
+    roundoff 6e-8) and each output sums at most 9 * nc * 4 products, so 2e-5 of the
+    output max-norm bounds the error with a wide margin."""
+    import torch
+
+    h, s = pair["h"], pair["s"]
+    for l in range(len(pair["blocks"]) + 1):
+        n = s.level_size(l)
+        x = synth.gaussian((2, n), 29 + l)
+        y = s.apply_level_f32(l, torch.from_numpy(x.astype(np.complex64)).to("cuda")).cpu().numpy()
+        y = y.reshape(2, -1).astype(np.complex128)
+        Al = h.levels[l].A
+        for j in range(2):
+            assert rel_err(y[j], Al @ x[j]) <= 2e-5
