@@ -43,6 +43,18 @@ SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
 
+# Serving workload: Poisson stream of requests over 8 seeded fields per lattice size,
+# beta cycling over the fields, 4 masses per beta, 1-16 Gaussian right-hand sides,
+# admission under a 200 GB HBM budget.
+SERVE_SIZES = [64, 128, 256, 512]
+SERVE_BETAS = [3.0, 6.0, 10.0]
+SERVE_FIELDS_PER_SIZE = 8
+SERVE_SWEEPS = 200
+SERVE_MASSES = {3.0: [0.02, 0.05, 0.1, 0.2], 6.0: [0.01, 0.03, 0.06, 0.1], 10.0: [0.005, 0.02, 0.05, 0.1]}
+SERVE_NV = 8
+SERVE_BUDGET = 200 * 10**9
+SERVE_CAPACITY = 16
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -118,6 +130,88 @@ def cpu_model():
 # ---------------------------------------------------------------------------
 # GPU
 # ---------------------------------------------------------------------------
+
+def serve_field(spec):
+    import synth
+
+    L, beta, seed = spec
+    return synth.links_from_angles(synth.metropolis_u1(L, L, beta, SERVE_SWEEPS, seed))
+
+
+def serving_leg(args, torch, smg, dev):
+    """The request loop on a warm setup cache; returns the serving summary."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    from paper_0710_3612_amd import serve
+
+    specs = [(L, SERVE_BETAS[i % len(SERVE_BETAS)], 3000 + 100 * si + i)
+             for si, L in enumerate(SERVE_SIZES) for i in range(SERVE_FIELDS_PER_SIZE)]
+    log(f"serving: generating {len(specs)} gauge fields")
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=16) as ex:
+        links = list(ex.map(serve_field, specs))
+    gen_s = time.perf_counter() - t0
+    fields, masses = {}, {}
+    for (L, beta, seed), U in zip(specs, links):
+        lv = serve.levels_for(L)
+        p = smg.make_params(L, L, 0.0, levels=lv, blocks=[(4, 4)] * (lv - 1), nv=[SERVE_NV] * (lv - 1),
+                            setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=seed,
+                            sa_scale=SA_SCALE)
+        fields[seed] = (torch.from_numpy(np.ascontiguousarray(U)).to(dev), p)
+        masses[seed] = SERVE_MASSES[beta]
+    torch.cuda.synchronize()
+    backend = serve.DeviceBackend(fields, mixed=True)
+    srv = serve.Server(backend, SERVE_BUDGET, capacity=SERVE_CAPACITY, tol=TOL, maxiter=2000,
+                       precision=smg.MIXED, max_lanes=args.serve_lanes)
+    keys = [(f, m) for f in fields for m in masses[f]]
+    t0 = time.perf_counter()
+    srv.warm(keys, workers=8)
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    log(f"serving: warmed {len(keys)} hierarchies in {warm_s:.1f}s ({srv.cache.used / 1e9:.1f} GB)")
+    trace = serve.poisson_trace(args.serve_requests, args.serve_rate, list(fields), masses, (1, 16), seed=7)
+    reqs = []
+    for i, (t, f, m, k, sd) in enumerate(trace):
+        n = 2 * fields[f][1].lx * fields[f][1].lt
+        reqs.append(serve.Request(i, f, m, (lambda n=n, sd=sd, k=k: synth.gaussian_device(n, sd, "cuda", k)), k, t))
+    results = srv.run_trace(reqs, timeout=1200)
+    summ = serve.latency_summary(results)
+    bad = [r for r in results if not r.ok or max(r.true_relres) > TOL]
+    if bad:
+        raise RuntimeError(f"{len(bad)} served requests failed, first: {bad[0].error} {bad[0].status} "
+                           f"{bad[0].true_relres}")
+    by_size = {}
+    for r in results:
+        L = fields[r.field][1].lx
+        by_size.setdefault(L, []).append(r)
+    iters = [i for r in results for i in r.iterations]
+    summ.update(
+        offered_rate_rps=args.serve_rate,
+        warm_s=warm_s,
+        field_generation_s=gen_s,
+        resident_gb=srv.cache.used / 1e9,
+        hierarchies=len(srv.cache.entries),
+        setups=srv.cache.setups,
+        derives=srv.cache.derives,
+        evictions=srv.cache.evictions,
+        lanes=args.serve_lanes,
+        lanes_started=srv.lanes_started,
+        mean_iterations=float(np.mean(iters)),
+        max_relres=max(max(r.true_relres) for r in results),
+        p50_ms_by_size={str(L): serve.latency_summary(rs)["p50_ms"] for L, rs in sorted(by_size.items())},
+        p99_ms_by_size={str(L): serve.latency_summary(rs)["p99_ms"] for L, rs in sorted(by_size.items())},
+        workload=(f"{args.serve_requests} Poisson requests at {args.serve_rate:g}/s over {len(fields)} fields "
+                  f"({'/'.join(map(str, SERVE_SIZES))}^2 x {SERVE_FIELDS_PER_SIZE}, beta 3/6/10, "
+                  f"{SERVE_SWEEPS} sweeps), 4 masses per beta, 1-16 Gaussian RHS each, 4x4 blocks, "
+                  f"Nv={SERVE_NV}, mixed precision, {SERVE_CAPACITY}-slot batches, "
+                  f"budget {SERVE_BUDGET / 1e9:.0f} GB, tol {TOL:g}"),
+    )
+    srv.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return summ
 
 def timed_events(fn, reps, stream):
     """Average duration of fn() over reps launches, HIP events on `stream`."""
@@ -214,6 +308,11 @@ def main():
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--streams", type=int, default=8, help="concurrent solve streams")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="offered requests/s of the serving trace")
+    ap.add_argument("--serve-lanes", type=int, default=8, help="concurrent (field, mass) lanes")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the roofline kernel and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
@@ -228,6 +327,14 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
         return 2
+
+    if args.serve_only:
+        import torch
+
+        import paper_0710_3612_amd as smg
+
+        print(json.dumps(serving_leg(args, torch, smg, torch.device("cuda:0"))))
+        return 0
 
     cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline()
 
@@ -354,6 +461,14 @@ def main():
 
     dslash_2048 = dslash(DSLASH_L)
     dslash_4096 = dslash(2 * DSLASH_L)
+    n_systems = len(systems)
+    del systems, xs, s
+    for s_ in keep:
+        s_.close()
+    keep.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    serving = None if args.no_serve else serving_leg(args, torch, smg, dev)
 
     cpu = None
     if cpu_proc is not None:
@@ -388,7 +503,7 @@ def main():
         "config": {
             "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
                         "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10",
-            "systems_per_step": len(systems),
+            "systems_per_step": n_systems,
             "concurrent_streams": nwork,
             "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
             "mixed_over_fp64": (mixed["solves"] / mixed["seconds"]) / (fp64["solves"] / fp64["seconds"]),
@@ -402,6 +517,7 @@ def main():
         "dslash": dslash_2048,
         "dslash_4096": dslash_4096,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line))
     return 0

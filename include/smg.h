@@ -59,13 +59,15 @@ enum {
   SMG_ENOMEM = -3,      /* device allocation failed */
   SMG_EDEVICE = -4,     /* a HIP runtime call failed */
   SMG_EBREAKDOWN = -5,  /* NaN/Inf, or <p, A p> <= 0 in a Krylov iteration */
-  SMG_ESETUP = -6       /* degenerate aggregate in Gram-Schmidt, or coarsest factorisation failed */
+  SMG_ESETUP = -6,      /* degenerate aggregate in Gram-Schmidt, or coarsest factorisation failed */
+  SMG_EBUSY = -7        /* no free slot in a batch */
 };
 
 enum { SMG_COARSEST_DIRECT = 0, SMG_COARSEST_CG = 1 };
 enum { SMG_FP64 = 0, SMG_MIXED = 1 };
 
 typedef struct smg_ctx* smg_handle;
+typedef struct smg_batch_s* smg_batch;
 
 typedef struct {
   int32_t lx, lt;                 /* fine extents, even, divisible by the product of blocks */
@@ -214,6 +216,52 @@ int smg_get_coarse_links(smg_handle h, int32_t level, double* out, void* stream)
 
 /* Host copy of the nu smoother coefficients c_k of level l. */
 int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out);
+
+/* ------------------------------------------------------------------------------
+ * Continuous batching (serving).  A batch is a set of max_rhs column slots that run
+ * MG-CG on the operator of handle h (Results section: the V-cycle preconditions
+ * CG; the setup is amortised over many right-hand sides).  Right-hand sides are
+ * admitted into free slots at any time, all running slots advance together, and
+ * finished slots are harvested and reused.  Each slot keeps its own Krylov
+ * scalars and is frozen on the device when it converges, so its result is bitwise
+ * the same alone and in any mix.  precision SMG_FP64: FP64 MG-CG; SMG_MIXED: FP64
+ * flexible CG preconditioned by the FP32 V-cycle.  A batch uses the work buffers
+ * of h: while it exists, h must not run other solves concurrently.
+ * ------------------------------------------------------------------------------ */
+
+/* New batch of max_rhs (1..256) slots with relative tolerance tol (true residual)
+ * and per-slot iteration cap maxiter.  Errors: SMG_EINVAL, SMG_ENOMEM. */
+int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter, int32_t precision, void* stream,
+                     smg_batch* out);
+
+/* Copy rhs (device, complex128 [lt][lx][2]) into a free slot, start its MG-CG and
+ * return the slot.  Synchronous.  Errors: SMG_EBUSY (no free slot), SMG_EBREAKDOWN
+ * (NaN/Inf in rhs). */
+int smg_batch_admit(smg_batch b, const double* rhs, int32_t* slot, void* stream);
+
+/* Advance every running slot by `iters` MG-CG iterations (slots that converge,
+ * break down or reach maxiter stop).  Synchronous. */
+int smg_batch_step(smg_batch b, int32_t iters, void* stream);
+
+/* Per slot (host arrays of max_rhs entries, either may be NULL): done[j] = 1 when
+ * slot j holds a finished right-hand side; stats[j] its status, iterations and
+ * true relative residual. */
+int smg_batch_poll(smg_batch b, uint8_t* done, smg_stats* stats);
+
+/* Number of occupied and of still-running slots. */
+int smg_batch_active(smg_batch b, int32_t* used, int32_t* running);
+
+/* Copy the solution of finished slot `slot` to x (device complex128, or NULL to
+ * drop it) and free the slot.  Synchronous.  Errors: SMG_EINVAL. */
+int smg_batch_harvest(smg_batch b, int32_t slot, double* x, void* stream);
+
+/* Free a slot whether or not it has finished (the other slots are unaffected). */
+int smg_batch_cancel(smg_batch b, int32_t slot, void* stream);
+
+/* Device bytes held by the batch (in addition to its handle). */
+int smg_batch_memory_bytes(smg_batch b, size_t* bytes);
+
+void smg_batch_destroy(smg_batch b);
 
 /* Device bytes held by the handle. */
 int smg_memory_bytes(smg_handle h, size_t* bytes);

@@ -22,6 +22,7 @@ __all__ = [
     "Params",
     "Stats",
     "Solver",
+    "Batch",
     "SmgError",
     "FP64",
     "MIXED",
@@ -38,6 +39,8 @@ COARSEST_CG = 1
 
 OK = 0
 NOTCONV = 1
+EBREAKDOWN = -5
+EBUSY = -7
 
 _HERE = Path(__file__).resolve().parent
 
@@ -132,6 +135,15 @@ def load_library():
         "smg_get_coarse_links": (i32, [h, i32, P, P]),
         "smg_get_smoother_coefs": (i32, [h, i32, ctypes.POINTER(ctypes.c_double)]),
         "smg_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_batch_create": (i32, [h, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(h)]),
+        "smg_batch_admit": (i32, [h, P, ctypes.POINTER(i32), P]),
+        "smg_batch_step": (i32, [h, i32, P]),
+        "smg_batch_poll": (i32, [h, P, ctypes.POINTER(Stats)]),
+        "smg_batch_active": (i32, [h, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "smg_batch_harvest": (i32, [h, i32, P, P]),
+        "smg_batch_cancel": (i32, [h, i32, P]),
+        "smg_batch_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_batch_destroy": (None, [h]),
         "smg_destroy": (None, [h]),
         "smg_strerror": (ctypes.c_char_p, [i32]),
         "smg_last_error": (ctypes.c_char_p, []),
@@ -388,4 +400,90 @@ class Solver:
     def memory_bytes(self) -> int:
         b = ctypes.c_size_t()
         _check(self.lib.smg_memory_bytes(self.handle, ctypes.byref(b)))
+        return b.value
+
+
+class Batch:
+    """Continuous batch of MG-CG solves on one Solver (smg_batch_* of the C ABI).
+
+    `capacity` column slots; right-hand sides are admitted into free slots at any
+    time, `step(k)` advances every running slot by k iterations, finished slots
+    are harvested and reused.  A slot's result does not depend on what else runs
+    in the batch.  While the batch exists its Solver must not run other solves.
+    """
+
+    def __init__(self, solver: Solver, capacity: int, tol: float = 1e-10, maxiter: int = 10000,
+                 precision: int = FP64, stream=None):
+        self.lib = solver.lib
+        self.solver = solver
+        self.capacity = int(capacity)
+        self.n = solver.level_size(0)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.smg_batch_create(solver.handle, self.capacity, float(tol), int(maxiter), int(precision),
+                                         _stream(stream), ctypes.byref(self.handle)))
+        self._stats = (Stats * self.capacity)()
+        self._done = (ctypes.c_uint8 * self.capacity)()
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.smg_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def admit(self, rhs, stream=None) -> Optional[int]:
+        """Start solving A x = rhs (complex128, n entries); returns the slot, or
+        None when every slot is occupied."""
+        rhs = rhs.contiguous()
+        if rhs.numel() != self.n:
+            raise ValueError(f"rhs must have {self.n} entries")
+        slot = ctypes.c_int32()
+        code = self.lib.smg_batch_admit(self.handle, _ptr(rhs), ctypes.byref(slot), _stream(stream))
+        if code == EBUSY:
+            return None
+        _check(code)
+        return slot.value
+
+    def step(self, iters: int = 1, stream=None):
+        _check(self.lib.smg_batch_step(self.handle, int(iters), _stream(stream)))
+
+    def poll(self):
+        """[(slot, stats dict)] of the finished, not yet harvested slots."""
+        _check(self.lib.smg_batch_poll(self.handle, self._done, self._stats))
+        return [(j, self._stats[j].as_dict()) for j in range(self.capacity) if self._done[j]]
+
+    def stats(self, slot: int) -> dict:
+        _check(self.lib.smg_batch_poll(self.handle, None, self._stats))
+        return self._stats[slot].as_dict()
+
+    def counts(self):
+        """(occupied slots, running slots)."""
+        u, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.smg_batch_active(self.handle, ctypes.byref(u), ctypes.byref(r)))
+        return u.value, r.value
+
+    def harvest(self, slot: int, out=None, stream=None):
+        """Solution of a finished slot (a new tensor, or `out`); frees the slot."""
+        import torch
+
+        x = out if out is not None else torch.empty(self.n, dtype=torch.complex128, device="cuda")
+        _check(self.lib.smg_batch_harvest(self.handle, int(slot), _ptr(x), _stream(stream)))
+        return x
+
+    def cancel(self, slot: int, stream=None):
+        _check(self.lib.smg_batch_cancel(self.handle, int(slot), _stream(stream)))
+
+    def memory_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(self.lib.smg_batch_memory_bytes(self.handle, ctypes.byref(b)))
         return b.value

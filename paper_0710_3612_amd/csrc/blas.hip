@@ -181,6 +181,21 @@ __global__ void k_cg_beta(const double* __restrict__ rz_new, double* __restrict_
   }
 }
 
+// Flexible (Polak-Ribiere) beta = (<r,z>_new - <r_new, z_old>) / <r,z>_old; rz_old <- rz_new.
+__global__ void k_cg_beta_flex(const double* __restrict__ rz_new, const double* __restrict__ rzo,
+                               double* __restrict__ rz, double* __restrict__ beta, const int* __restrict__ active,
+                               int nrhs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double b = 0;
+  if (active[j] && rz[2 * j] != 0) b = (rz_new[2 * j] - rzo[2 * j]) / rz[2 * j];
+  beta[j] = b;
+  if (active[j]) {
+    rz[2 * j] = rz_new[2 * j];
+    rz[2 * j + 1] = rz_new[2 * j + 1];
+  }
+}
+
 inline dim3 ew_grid(size_t n, int nrhs) {
   size_t g = (n + kThreads - 1) / kThreads;
   if (g > 4096) g = 4096;
@@ -256,6 +271,12 @@ void launch_scale_up_add(z64* x, const z32* e, const double* s, size_t n, int nr
 void launch_cg_alpha(const double* rz, const double* pq, double* alpha, const int* active, int* bad, int nrhs,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_cg_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, st, rz, pq, alpha, active, bad, nrhs);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_cg_beta_flex(const double* rz_new, const double* rzo, double* rz, double* beta, const int* active,
+                         int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta_flex, dim3((nrhs + 63) / 64), dim3(64), 0, st, rz_new, rzo, rz, beta, active, nrhs);
   HIPCHECK(hipGetLastError());
 }
 

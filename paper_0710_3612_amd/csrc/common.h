@@ -171,6 +171,8 @@ void launch_scale_up_add(z64* x, const z32* e, const double* s, size_t n, int nr
 void launch_cg_alpha(const double* rz, const double* pq, double* alpha, const int* active, int* bad, int nrhs,
                      hipStream_t st);
 void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* active, int nrhs, hipStream_t st);
+void launch_cg_beta_flex(const double* rz_new, const double* rzo, double* rz, double* beta, const int* active,
+                         int nrhs, hipStream_t st);
 
 // Gauge relayout: U[mu][t][x] -> fermion links with the antiperiodic sign folded in.
 template <typename R>

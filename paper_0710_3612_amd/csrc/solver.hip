@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -778,6 +779,159 @@ void check_nrhs(int nrhs) {
   if (nrhs < 1 || nrhs > 4096) throw Error(SMG_EINVAL, "nrhs must be in [1, 4096]");
 }
 
+// ---------------------------------------------------------------------------
+// Continuous batching: MG-CG over a fixed set of column slots of one handle.
+// Every column keeps its own Krylov scalars and is frozen on the device when it
+// converges, so a column's iterates do not depend on which other slots are busy
+// or when they were admitted.  FP64: MG-CG as in smg_solve.  Mixed: FP64 flexible
+// CG preconditioned by the FP32 V-cycle (defect correction's restarts do not fit
+// admission at any time).
+// ---------------------------------------------------------------------------
+struct Batch {
+  Ctx* c = nullptr;
+  int cap = 0;
+  double tol = 1e-10;
+  int maxiter = 0;
+  int prec = SMG_FP64;
+  size_t n = 0;
+  Pool pool;
+  z64 *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zo = nullptr,
+      *t = nullptr;
+  z32 *r32 = nullptr, *z32v = nullptr;
+  double* partial = nullptr;
+  Scal S;
+  double* rzo = nullptr;
+  double* h = nullptr;  // pinned host scratch
+  int* hi_ = nullptr;
+  std::vector<int> used, act, its, stat, bad;
+  std::vector<double> bb, rel;
+  int64_t applies0 = 0;
+  ~Batch() {
+    if (h) (void)hipHostFree(h);
+    if (hi_) (void)hipHostFree(hi_);
+  }
+  int hi() const {
+    int m = 0;
+    for (int j = 0; j < cap; ++j)
+      if (used[j]) m = j + 1;
+    return m;
+  }
+};
+
+void batch_upload_active(Batch& B, hipStream_t st) {
+  for (int j = 0; j < B.cap; ++j) B.hi_[j] = B.act[j];
+  HIPCHECK(hipMemcpyAsync(B.S.active, B.hi_, sizeof(int) * B.cap, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
+// z = M r on columns [j0, j0 + cnt) (the V-cycle; FP32 for mixed).
+void batch_precondition(Batch& B, int j0, int cnt, hipStream_t st) {
+  Ctx& c = *B.c;
+  c.st = st;
+  const size_t off = (size_t)j0 * B.n;
+  if (c.nlev < 2) {
+    HIPCHECK(hipMemcpyAsync(B.z + off, B.r + off, (size_t)cnt * B.n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    return;
+  }
+  const bool cg = c.prm.coarsest == SMG_COARSEST_CG;
+  if (B.prec == SMG_FP64) {
+    vcycle<double>(c, 0, c.nlev - 1, B.r + off, B.z + off, cnt, cg);
+  } else {
+    launch_convert<float, double>(B.r + off, B.r32 + off, (size_t)cnt * B.n, st);
+    vcycle<float>(c, 0, c.nlev - 1, B.r32 + off, B.z32v + off, cnt, cg);
+    launch_convert<double, float>(B.z32v + off, B.z + off, (size_t)cnt * B.n, st);
+  }
+}
+
+// A slot that stops running keeps x; its r, z and p are cleared so that the
+// shared V-cycle sees a zero (finite) column there.
+void batch_clear(Batch& B, int j, hipStream_t st) {
+  const size_t off = (size_t)j * B.n, bytes = B.n * sizeof(z64);
+  zero(B.r + off, bytes, st);
+  zero(B.z + off, bytes, st);
+  zero(B.p + off, bytes, st);
+  if (B.zo) zero(B.zo + off, bytes, st);
+}
+
+// One MG-CG iteration per step of the loop, ordered so that a fresh slot joins
+// without work of its own: z = M r, beta (0 for a fresh slot, whose <r,z>_old is
+// 0), p = z + beta p, q = A p, alpha, x/r update, convergence check.
+void batch_step(Batch& B, int iters, hipStream_t st) {
+  Ctx& c = *B.c;
+  c.st = st;
+  auto& lv = c.L64[0];
+  const size_t n = B.n;
+  for (int it = 0; it < iters; ++it) {
+    const int hi = B.hi();
+    int nact = 0;
+    for (int j = 0; j < hi; ++j) nact += B.act[j];
+    if (nact == 0) return;
+    if (B.prec == SMG_MIXED)
+      HIPCHECK(hipMemcpyAsync(B.zo, B.z, (size_t)hi * n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    batch_precondition(B, 0, hi, st);
+    launch_dot<double>(B.r, B.z, n, hi, B.partial, B.S.pq, st);
+    if (B.prec == SMG_MIXED) {
+      launch_dot<double>(B.r, B.zo, n, hi, B.partial, B.rzo, st);
+      launch_cg_beta_flex(B.S.pq, B.rzo, B.S.rz, B.S.ab, B.S.active, hi, st);
+    } else {
+      launch_cg_beta(B.S.pq, B.S.rz, B.S.ab, B.S.active, hi, st);
+    }
+    launch_xpay<double>(B.z, B.p, B.S.ab, n, hi, st);
+    apply_op<double>(c, lv, B.p, B.q, hi, 0, 0.0, nullptr, nullptr);
+    launch_dot<double>(B.p, B.q, n, hi, B.partial, B.S.pq, st);
+    launch_cg_alpha(B.S.rz, B.S.pq, B.S.ab, B.S.active, B.S.bad, hi, st);
+    launch_axpy_update<double>(B.x, B.r, B.p, B.q, B.S.ab, n, hi, B.partial, B.S.rr, st);
+    HIPCHECK(hipMemcpyAsync(B.h, B.S.rr, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(B.hi_, B.S.bad, sizeof(int) * hi, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    bool changed = false, any_cand = false;
+    std::vector<int> cand(hi, 0);
+    auto stop = [&](int j, int status, double rel) {
+      B.act[j] = 0;
+      B.stat[j] = status;
+      B.rel[j] = rel;
+      batch_clear(B, j, st);
+      changed = true;
+    };
+    for (int j = 0; j < hi; ++j) {
+      if (!B.act[j]) continue;
+      B.its[j] += 1;
+      const double r2 = B.h[2 * j];
+      if (B.hi_[j] || !std::isfinite(r2)) {
+        stop(j, SMG_EBREAKDOWN, std::numeric_limits<double>::quiet_NaN());
+        continue;
+      }
+      if (r2 <= B.tol * B.tol * B.bb[j]) {
+        cand[j] = 1;
+        any_cand = true;
+      }
+    }
+    if (any_cand) {  // confirm on the true residual t = b - A x
+      apply_op<double>(c, lv, B.x, B.t, hi, 2, 0.0, nullptr, B.b);
+      launch_dot<double>(B.t, B.t, n, hi, B.partial, B.S.tt, st);
+      HIPCHECK(hipMemcpyAsync(B.h, B.S.tt, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      for (int j = 0; j < hi; ++j) {
+        if (!cand[j]) continue;
+        const double tr = std::sqrt(B.h[2 * j] / B.bb[j]);
+        if (tr <= B.tol)
+          stop(j, SMG_OK, tr);
+        else
+          HIPCHECK(hipMemcpyAsync(B.r + (size_t)j * n, B.t + (size_t)j * n, n * sizeof(z64), hipMemcpyDeviceToDevice,
+                                  st));
+      }
+    }
+    for (int j = 0; j < hi; ++j)
+      if (B.act[j] && B.its[j] >= B.maxiter) stop(j, SMG_NOTCONV, std::sqrt(B.h[2 * j] / B.bb[j]));
+    if (changed) batch_upload_active(B, st);
+  }
+}
+
+Batch* BH(smg_batch b) {
+  if (!b) throw Error(SMG_EINVAL, "null batch");
+  return reinterpret_cast<Batch*>(b);
+}
+
 }  // namespace
 }  // namespace smg
 
@@ -1234,6 +1388,205 @@ int smg_memory_bytes(smg_handle h, size_t* bytes) {
   API_END
 }
 
+int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter, int32_t precision, void* stream,
+                     smg_batch* out) {
+  API_BEGIN
+  Ctx* c = H(h);
+  if (!out) throw Error(SMG_EINVAL, "null output");
+  if (max_rhs < 1 || max_rhs > 256) throw Error(SMG_EINVAL, "max_rhs must be in [1, 256]");
+  if (!(tol > 0) || maxiter < 1) throw Error(SMG_EINVAL, "tol must be > 0 and maxiter >= 1");
+  if (precision != SMG_FP64 && precision != SMG_MIXED) throw Error(SMG_EINVAL, "bad precision");
+  hipStream_t st = (hipStream_t)stream;
+  c->st = st;
+  Batch* B = new Batch();
+  try {
+    B->c = c;
+    B->cap = max_rhs;
+    B->tol = tol;
+    B->maxiter = maxiter;
+    B->prec = precision;
+    B->n = c->L64[0].n;
+    const size_t e = (size_t)max_rhs * B->n;
+    B->b = B->pool.alloc<z64>(e);
+    B->x = B->pool.alloc<z64>(e);
+    B->r = B->pool.alloc<z64>(e);
+    B->p = B->pool.alloc<z64>(e);
+    B->q = B->pool.alloc<z64>(e);
+    B->z = B->pool.alloc<z64>(e);
+    B->t = B->pool.alloc<z64>(e);
+    if (precision == SMG_MIXED) {
+      B->zo = B->pool.alloc<z64>(e);
+      B->r32 = B->pool.alloc<z32>(e);
+      B->z32v = B->pool.alloc<z32>(e);
+      B->rzo = B->pool.alloc<double>(2 * max_rhs);
+      ensure_f32(*c);
+      ensure_level_work<float>(*c, max_rhs);
+    }
+    B->partial = B->pool.alloc<double>((size_t)2 * red_blocks(B->n) * max_rhs);
+    B->S.bb = B->pool.alloc<double>(2 * max_rhs);
+    B->S.rz = B->pool.alloc<double>(2 * max_rhs);
+    B->S.pq = B->pool.alloc<double>(2 * max_rhs);
+    B->S.ab = B->pool.alloc<double>(2 * max_rhs);
+    B->S.rr = B->pool.alloc<double>(2 * max_rhs);
+    B->S.tt = B->pool.alloc<double>(2 * max_rhs);
+    B->S.active = B->pool.alloc<int>(max_rhs);
+    B->S.bad = B->pool.alloc<int>(max_rhs);
+    HIPCHECK(hipHostMalloc((void**)&B->h, sizeof(double) * 2 * max_rhs, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&B->hi_, sizeof(int) * max_rhs, hipHostMallocDefault));
+    B->used.assign(max_rhs, 0);
+    B->act.assign(max_rhs, 0);
+    B->its.assign(max_rhs, 0);
+    B->stat.assign(max_rhs, SMG_OK);
+    B->bb.assign(max_rhs, 0.0);
+    B->rel.assign(max_rhs, 0.0);
+    zero(B->S.bad, sizeof(int) * max_rhs, st);
+    zero(B->x, e * sizeof(z64), st);
+    zero(B->p, e * sizeof(z64), st);
+    zero(B->r, e * sizeof(z64), st);
+    zero(B->z, e * sizeof(z64), st);
+    zero(B->S.rz, sizeof(double) * 2 * max_rhs, st);
+    ensure_level_work<double>(*c, max_rhs);
+    batch_upload_active(*B, st);
+  } catch (...) {
+    delete B;
+    throw;
+  }
+  *out = reinterpret_cast<smg_batch>(B);
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_admit(smg_batch b, const double* rhs, int32_t* slot, void* stream) {
+  API_BEGIN
+  Batch* B = BH(b);
+  if (!rhs || !slot) throw Error(SMG_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int s = -1;
+  for (int j = 0; j < B->cap; ++j)
+    if (!B->used[j]) {
+      s = j;
+      break;
+    }
+  if (s < 0) throw Error(SMG_EBUSY, "no free slot in the batch");
+  const size_t n = B->n, off = (size_t)s * n;
+  HIPCHECK(hipMemcpyAsync(B->b + off, rhs, n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(hipMemcpyAsync(B->r + off, rhs, n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  zero(B->x + off, n * sizeof(z64), st);
+  zero(B->p + off, n * sizeof(z64), st);
+  zero(B->S.rz + 2 * s, sizeof(double) * 2, st);
+  zero(B->S.bad + s, sizeof(int), st);
+  launch_dot<double>(B->b + off, B->b + off, n, 1, B->partial, B->S.bb + 2 * s, st);
+  HIPCHECK(hipMemcpyAsync(B->h, B->S.bb + 2 * s, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  const double bb = B->h[0];
+  if (!std::isfinite(bb)) {  // leave the free slot finite for the shared V-cycle
+    batch_clear(*B, s, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
+  }
+  B->used[s] = 1;
+  B->its[s] = 0;
+  B->rel[s] = 0.0;
+  B->bb[s] = bb;
+  if (!(bb > 0)) {  // zero right-hand side: x = 0, done
+    B->act[s] = 0;
+    B->stat[s] = SMG_OK;
+    zero(B->r + off, n * sizeof(z64), st);
+  } else {  // joins at the next step with beta = 0 (<r,z>_old = 0)
+    B->act[s] = 1;
+    B->stat[s] = SMG_NOTCONV;
+  }
+  batch_upload_active(*B, st);
+  *slot = s;
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_step(smg_batch b, int32_t iters, void* stream) {
+  API_BEGIN
+  Batch* B = BH(b);
+  if (iters < 1) throw Error(SMG_EINVAL, "iters must be >= 1");
+  batch_step(*B, iters, (hipStream_t)stream);
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_poll(smg_batch b, uint8_t* done, smg_stats* stats) {
+  API_BEGIN
+  Batch* B = BH(b);
+  for (int j = 0; j < B->cap; ++j) {
+    if (done) done[j] = (B->used[j] && !B->act[j]) ? 1 : 0;
+    if (stats) {
+      stats[j].status = B->used[j] ? B->stat[j] : SMG_OK;
+      stats[j].iterations = B->its[j];
+      stats[j].refinements = 1;
+      stats[j].vcycles = B->its[j];
+      stats[j].fine_applies = 0;
+      stats[j].true_relres = B->rel[j];
+      stats[j].seconds = 0;
+    }
+  }
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_active(smg_batch b, int32_t* used, int32_t* running) {
+  API_BEGIN
+  Batch* B = BH(b);
+  int u = 0, a = 0;
+  for (int j = 0; j < B->cap; ++j) {
+    u += B->used[j];
+    a += B->act[j];
+  }
+  if (used) *used = u;
+  if (running) *running = a;
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_harvest(smg_batch b, int32_t slot, double* x, void* stream) {
+  API_BEGIN
+  Batch* B = BH(b);
+  if (slot < 0 || slot >= B->cap || !B->used[slot]) throw Error(SMG_EINVAL, "slot is not in use");
+  if (B->act[slot]) throw Error(SMG_EINVAL, "slot is still running");
+  hipStream_t st = (hipStream_t)stream;
+  if (x)
+    HIPCHECK(hipMemcpyAsync(x, B->x + (size_t)slot * B->n, B->n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  batch_clear(*B, slot, st);
+  HIPCHECK(hipStreamSynchronize(st));
+  B->used[slot] = 0;
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_cancel(smg_batch b, int32_t slot, void* stream) {
+  API_BEGIN
+  Batch* B = BH(b);
+  if (slot < 0 || slot >= B->cap || !B->used[slot]) throw Error(SMG_EINVAL, "slot is not in use");
+  B->used[slot] = 0;
+  B->act[slot] = 0;
+  batch_clear(*B, slot, (hipStream_t)stream);
+  batch_upload_active(*B, (hipStream_t)stream);
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_memory_bytes(smg_batch b, size_t* bytes) {
+  API_BEGIN
+  Batch* B = BH(b);
+  if (!bytes) throw Error(SMG_EINVAL, "null output");
+  *bytes = B->pool.bytes;
+  return SMG_OK;
+  API_END
+}
+
+void smg_batch_destroy(smg_batch b) {
+  if (!b) return;
+  Batch* B = reinterpret_cast<Batch*>(b);
+  (void)hipStreamSynchronize(B->c->st);
+  delete B;
+}
+
 void smg_destroy(smg_handle h) {
   if (!h) return;
   Ctx* c = reinterpret_cast<Ctx*>(h);
@@ -1251,6 +1604,7 @@ const char* smg_strerror(int code) {
     case SMG_EDEVICE: return "HIP runtime error";
     case SMG_EBREAKDOWN: return "numerical breakdown (NaN/Inf or loss of positive definiteness)";
     case SMG_ESETUP: return "setup failed (degenerate aggregate or coarsest factorisation)";
+    case SMG_EBUSY: return "no free slot in the batch";
     default: return "unknown error code";
   }
 }

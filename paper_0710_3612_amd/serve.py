@@ -1,0 +1,704 @@
+"""Serving: a continuous-batching request loop over the adaptive-MG library.
+
+The paper separates the adaptive setup from the solves and reuses one setup for
+many right-hand sides and for other masses (Results section).  A server that
+answers solve requests for many gauge fields therefore keeps each field's setup
+resident on the device and sends every right-hand side through a batch of column
+slots of that setup:
+
+* ``SetupCache`` holds hierarchies keyed by (field, mass) under an HBM budget,
+  evicting the least recently used idle one when a new one does not fit.  The
+  first mass of a field runs the full adaptive setup; another mass of a field
+  with a resident hierarchy is derived from it (same near-null vectors, new
+  Galerkin operators), as the paper does when it changes the mass.
+* A ``Lane`` serves one (field, mass) key on its own stream and host thread.  It
+  owns a ``Batch`` (``smg_batch_*``): right-hand sides are admitted into free
+  slots whenever they arrive, all running slots advance together, and finished
+  slots are harvested and refilled.  Lanes of different keys run at the same
+  time, so their kernels overlap on the device.
+* ``Server`` routes requests (each 1..k right-hand sides) to lanes, limits the
+  number of live lanes, and records arrival, admission and completion times.
+
+All numerical work is in the library; this module only schedules it.  The cache,
+lanes and server accept any backend object with the methods used here, which
+lets the host logic be tested without a GPU.
+"""
+
+from __future__ import annotations
+
+import collections
+import contextlib
+import dataclasses
+import math
+import threading
+import time
+from typing import Callable, Dict, Hashable, List, Optional, Sequence, Tuple
+
+__all__ = [
+    "Request",
+    "Result",
+    "SetupCache",
+    "Server",
+    "estimate_bytes",
+    "poisson_trace",
+    "latency_summary",
+    "levels_for",
+]
+
+Z64, Z32 = 16, 8
+
+
+def levels_for(l: int, block: int = 4, max_coarse: int = 8) -> int:
+    """Number of levels for an l x l lattice with block x block aggregates: coarsen
+    while the coarse extent stays >= 4 and the coarse lattice exceeds max_coarse."""
+    levels, c = 1, l
+    while c % block == 0 and c // block >= 4 and c > max_coarse:
+        c //= block
+        levels += 1
+    return levels
+
+
+def estimate_bytes(lx: int, lt: int, blocks: Sequence, nv: Sequence[int], capacity: int = 1,
+                   mixed: bool = True, full_setup: bool = True, smoothed: bool = True,
+                   coarsest_direct: bool = True) -> int:
+    """Device bytes of one hierarchy plus one batch of `capacity` slots (an upper
+    estimate of what the library allocates for them)."""
+    shapes = [(lx, lt, 2)]
+    for (bx, bt), k in zip(blocks, nv):
+        cx, ct, _ = shapes[-1]
+        shapes.append((cx // bx, ct // bt, k))
+    n = [a * b * c for a, b, c in shapes]
+    tot = 2 * lx * lt * Z64  # links
+    work = 0
+    for l in range(len(shapes) - 1):
+        bx, bt = blocks[l]
+        cx, ct, k = shapes[l + 1]
+        dof = shapes[l][2]
+        K = cx * ct
+        halo = 1 if (smoothed and bx >= 4 and bt >= 4 and cx >= 2 and ct >= 2) else 0
+        links = 9 * K * k * k
+        pt = K * k * bx * bt * dof
+        pw = K * k * (bx + 2 * halo) * (bt + 2 * halo) * dof
+        tot += (links + pt + (pw if halo else 0)) * Z64
+        tot += n[l] * Z64  # calibration vector
+        if full_setup:
+            tot += (1 + k) * n[l] * Z64  # random starts
+        if mixed:
+            tot += (links + pw) * Z32
+        work += K * (bx + 2 * halo) * (bt + 2 * halo) * dof  # window buffer per column
+    nlev = len(shapes)
+    if nlev > 1:
+        tot += 5 * n[0] * Z64  # setup scratch
+        if coarsest_direct:
+            tot += (n[-1] * n[-1] + n[-1]) * Z64
+    cols = capacity + 1  # level work grows from 1 column to the batch width
+    per_col64 = sum(4 * m for m in n) + n[0] + work
+    tot += cols * per_col64 * Z64
+    if mixed:
+        tot += n[0] * Z32 + cols * per_col64 * Z32
+    # the batch itself: b x r p q z t (+ z_old, FP32 r and z)
+    tot += capacity * n[0] * (7 + (1 if mixed else 0)) * Z64 + (2 * capacity * n[0] * Z32 if mixed else 0)
+    return int(tot * 1.05) + (1 << 20)
+
+
+@dataclasses.dataclass
+class Request:
+    """A solve request: A(field, mass) x_i = b_i for its k right-hand sides.
+
+    `rhs` is a [k, n] complex128 device tensor or a callable returning one (called
+    on the serving lane's stream when the request is first admitted)."""
+
+    rid: int
+    field: Hashable
+    mass: float
+    rhs: object
+    k: int
+    arrival: float = 0.0
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    field: Hashable
+    mass: float
+    k: int
+    arrival: float
+    admitted: float = math.nan
+    finished: float = math.nan
+    x: object = None
+    status: List[int] = dataclasses.field(default_factory=list)
+    iterations: List[int] = dataclasses.field(default_factory=list)
+    true_relres: List[float] = dataclasses.field(default_factory=list)
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+    @property
+    def ok(self) -> bool:
+        return self.error is None and all(s == 0 for s in self.status)
+
+
+class BudgetExceeded(RuntimeError):
+    pass
+
+
+@dataclasses.dataclass
+class _Entry:
+    solver: object
+    bytes: int
+    pins: int = 0
+    batch: object = None  # the key's slot batch, kept with the hierarchy
+    ready: threading.Event = dataclasses.field(default_factory=threading.Event)
+    failed: Optional[BaseException] = None
+
+
+class SetupCache:
+    """Resident hierarchies keyed by (field, mass), least recently used first out.
+
+    backend.setup(field, mass, stream) -> solver   full adaptive setup
+    backend.derive(solver, mass, stream) -> solver  another mass, same vectors
+    backend.estimate(field, capacity) -> bytes      before allocating
+    solver.memory_bytes(), solver.close()
+
+    Setups run outside the cache lock (other keys stay available meanwhile); a
+    second request for a key being built waits for it.
+    """
+
+    def __init__(self, backend, budget_bytes: int):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.entries: "collections.OrderedDict[Tuple, _Entry]" = collections.OrderedDict()
+        self.used = 0
+        self.lock = threading.RLock()
+        self.setups = 0
+        self.derives = 0
+        self.evictions = 0
+
+    def _evict_for(self, need: int) -> bool:
+        for key in list(self.entries.keys()):
+            if self.used + need <= self.budget:
+                break
+            e = self.entries[key]
+            if e.pins == 0 and e.ready.is_set():
+                if e.batch is not None:
+                    e.batch.close()
+                if e.solver is not None:
+                    e.solver.close()
+                self.used -= e.bytes
+                del self.entries[key]
+                self.evictions += 1
+        return self.used + need <= self.budget
+
+    def entry(self, field, mass: float) -> Optional[_Entry]:
+        with self.lock:
+            return self.entries.get((field, float(mass)))
+
+    def acquire(self, field, mass: float, capacity: int, stream=None):
+        """Pinned solver for (field, mass); None while the budget cannot make room
+        (every resident hierarchy is in use).  Raises BudgetExceeded when it could
+        never fit, and what the setup raised when it failed."""
+        key = (field, float(mass))
+        with self.lock:
+            e = self.entries.get(key)
+            if e is not None:
+                self.entries.move_to_end(key)
+                e.pins += 1
+                build = False
+            else:
+                need = self.backend.estimate(field, capacity)
+                if need > self.budget:
+                    raise BudgetExceeded(f"{key}: {need} bytes exceed the budget of {self.budget}")
+                if not self._evict_for(need):
+                    return None
+                src = next((k for k, v in reversed(self.entries.items())
+                            if k[0] == field and v.ready.is_set() and v.solver is not None), None)
+                if src is not None:
+                    self.entries[src].pins += 1
+                e = _Entry(None, need, pins=1)
+                self.entries[key] = e
+                self.used += need
+                build = True
+        if not build:
+            e.ready.wait()
+            if e.failed is not None:
+                self.release(field, mass)
+                raise e.failed
+            return e.solver
+        try:
+            if src is not None:
+                solver = self.backend.derive(self.entries[src].solver, float(mass), stream)
+            else:
+                solver = self.backend.setup(field, float(mass), stream)
+        except BaseException as exc:
+            with self.lock:
+                e.failed = exc
+                self.used -= e.bytes
+                e.bytes = 0
+                if self.entries.get(key) is e:
+                    del self.entries[key]
+                if src is not None:
+                    self.entries[src].pins -= 1
+            e.ready.set()
+            raise
+        with self.lock:
+            e.solver = solver
+            if src is not None:
+                self.entries[src].pins -= 1
+                self.derives += 1
+            else:
+                self.setups += 1
+        e.ready.set()
+        return solver
+
+    def settle(self, field, mass: float, actual: int):
+        """Replace the estimate of a resident entry by its measured bytes."""
+        with self.lock:
+            e = self.entries.get((field, float(mass)))
+            if e is not None:
+                self.used += int(actual) - e.bytes
+                e.bytes = int(actual)
+
+    def release(self, field, mass: float):
+        with self.lock:
+            e = self.entries.get((field, float(mass)))
+            if e is not None and e.pins > 0:
+                e.pins -= 1
+
+    def close(self):
+        with self.lock:
+            for e in self.entries.values():
+                if e.batch is not None:
+                    e.batch.close()
+                if e.solver is not None:
+                    e.solver.close()
+            self.entries.clear()
+            self.used = 0
+
+
+class _Lane:
+    """One (field, mass) key: a batch of slots on its own stream and thread."""
+
+    def __init__(self, server: "Server", field, mass: float):
+        self.server = server
+        self.field = field
+        self.mass = float(mass)
+        self.pending: "collections.deque[Tuple[Result, Request, int]]" = collections.deque()
+        self.slots: Dict[int, Tuple[Result, int]] = {}
+        self.remaining: Dict[int, int] = {}
+        self.cv = threading.Condition()
+        self.stop = False
+        self.last_busy = time.perf_counter()
+        self.thread = threading.Thread(target=self._run, daemon=True, name=f"lane-{field}-{mass}")
+        self.solver = None
+        self.batch = None
+        self.stream = server._take_stream()
+
+    def push(self, res: Result, req: Request):
+        with self.cv:
+            for j in range(req.k):
+                self.pending.append((res, req, j))
+            self.remaining[res.rid] = req.k
+            self.last_busy = time.perf_counter()
+            self.cv.notify()
+
+    def idle(self) -> bool:
+        with self.cv:
+            return not self.pending and not self.slots
+
+    def _fail(self, msg: str):
+        srv = self.server
+        with self.cv:
+            items = list(self.pending)
+            self.pending.clear()
+            held = list(self.slots.values())
+            self.slots.clear()
+        done = set()
+        for res, _req, _j in items:
+            if res.rid not in done:
+                res.error = msg
+                done.add(res.rid)
+                srv._complete(res)
+        for res, _j in held:
+            if res.rid not in done:
+                res.error = msg
+                done.add(res.rid)
+                srv._complete(res)
+
+    def _run(self):
+        srv = self.server
+        be = srv.backend
+        ctx = be.stream_context(self.stream)
+        with ctx:
+            try:
+                while True:
+                    self.solver = srv.cache.acquire(self.field, self.mass, srv.capacity, self.stream)
+                    if self.solver is not None:
+                        break
+                    if self.stop:
+                        return
+                    time.sleep(srv.poll_sleep)
+                ent = srv.cache.entry(self.field, self.mass)
+                if ent.batch is None:  # first lane of this key: the batch stays with the hierarchy
+                    ent.batch = be.new_batch(self.solver, srv.capacity, srv.tol, srv.maxiter, srv.precision,
+                                             self.stream)
+                    srv.cache.settle(self.field, self.mass, self.solver.memory_bytes() + ent.batch.memory_bytes())
+                self.batch = ent.batch
+            except Exception as exc:  # setup failed: fail what is queued here
+                self._fail(f"setup: {exc}")
+                if self.solver is not None:
+                    srv.cache.release(self.field, self.mass)
+                    self.solver = None
+                srv._lane_done(self)
+                return
+            try:
+                self._serve()
+            except Exception as exc:
+                self._fail(f"solve: {exc}")
+                # the batch's slots are in an unknown state: drop it with the lane
+                ent = srv.cache.entry(self.field, self.mass)
+                if ent is not None and ent.batch is self.batch:
+                    ent.batch = None
+                try:
+                    self.batch.close()
+                except Exception:
+                    pass
+            finally:
+                self.batch = None
+                srv.cache.release(self.field, self.mass)
+                self.solver = None
+                srv._lane_done(self)
+
+    def _serve(self):
+        srv = self.server
+        be = srv.backend
+        while True:
+            with self.cv:
+                if not self.pending and not self.slots and not self.stop:
+                    self.cv.wait(timeout=srv.poll_sleep * 10)
+                has_work = bool(self.pending or self.slots)
+                stop = self.stop
+                todo = []
+                free = srv.capacity - len(self.slots)
+                while self.pending and len(todo) < free:
+                    todo.append(self.pending.popleft())
+            if not has_work:
+                if stop or srv._want_retire(self):  # takes the server lock: never under self.cv
+                    return
+                continue
+            for i, (res, req, j) in enumerate(todo):
+                if res.x is None:
+                    rhs = req.rhs() if callable(req.rhs) else req.rhs
+                    req.rhs = rhs
+                    res.x = be.new_output(rhs)
+                    res.status = [1] * req.k
+                    res.iterations = [0] * req.k
+                    res.true_relres = [math.nan] * req.k
+                if math.isnan(res.admitted):
+                    res.admitted = srv.now()
+                slot = self.batch.admit(req.rhs[j], self.stream)
+                if slot is None:  # cannot happen while slots are counted; keep the columns
+                    with self.cv:
+                        self.pending.extendleft(reversed(todo[i:]))
+                    break
+                self.slots[slot] = (res, j)
+            if self.slots:
+                self.batch.step(srv.iters_per_step, self.stream)
+                for slot, st in self.batch.poll():
+                    res, j = self.slots.pop(slot)
+                    self.batch.harvest(slot, res.x[j], self.stream)
+                    res.status[j] = st["status"]
+                    res.iterations[j] = st["iterations"]
+                    res.true_relres[j] = st["true_relres"]
+                    self.remaining[res.rid] -= 1
+                    if self.remaining[res.rid] == 0:
+                        del self.remaining[res.rid]
+                        res.finished = srv.now()
+                        srv._complete(res)
+                self.last_busy = time.perf_counter()
+
+
+class Server:
+    """Routes requests to per-(field, mass) lanes; at most `max_lanes` are live.
+
+    backend: new_stream(), stream_context(stream), new_batch(solver, capacity, tol,
+    maxiter, precision, stream), new_output(rhs), plus the SetupCache methods.
+    """
+
+    def __init__(self, backend, budget_bytes: int, capacity: int = 16, tol: float = 1e-10, maxiter: int = 5000,
+                 precision: int = 1, max_lanes: int = 8, iters_per_step: int = 1, poll_sleep: float = 0.0005,
+                 linger: float = 0.5):
+        self.backend = backend
+        self.cache = SetupCache(backend, budget_bytes)
+        self.capacity = int(capacity)
+        self.tol = float(tol)
+        self.maxiter = int(maxiter)
+        self.precision = int(precision)
+        self.max_lanes = int(max_lanes)
+        self.iters_per_step = int(iters_per_step)
+        self.poll_sleep = float(poll_sleep)
+        self.linger = float(linger)
+        self.lanes: Dict[Tuple, _Lane] = {}
+        self.waiting: "collections.deque[Tuple[Result, Request]]" = collections.deque()
+        self.lock = threading.RLock()
+        self.done_cv = threading.Condition(self.lock)
+        self.results: Dict[int, Result] = {}
+        self.open = 0
+        self.t0 = time.perf_counter()
+        self.lanes_started = 0
+        self.streams: list = []
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # -- routing ---------------------------------------------------------------
+    def submit(self, req: Request, arrival: Optional[float] = None) -> Result:
+        res = Result(req.rid, req.field, float(req.mass), req.k, self.now() if arrival is None else arrival)
+        with self.lock:
+            self.results[req.rid] = res
+            self.open += 1
+            self._route(res, req)
+        return res
+
+    def _route(self, res: Result, req: Request):
+        key = (req.field, float(req.mass))
+        lane = self.lanes.get(key)
+        if lane is None:
+            if len(self.lanes) >= self.max_lanes:
+                self.waiting.append((res, req))
+                return
+            lane = _Lane(self, req.field, req.mass)
+            self.lanes[key] = lane
+            self.lanes_started += 1
+            lane.push(res, req)
+            lane.thread.start()
+            return
+        lane.push(res, req)
+
+    def _want_retire(self, lane: _Lane) -> bool:
+        """An idle lane leaves when others wait for a lane or it lingered long."""
+        with self.lock:
+            if lane.pending or lane.slots:
+                return False
+            if self.waiting or time.perf_counter() - lane.last_busy > self.linger:
+                key = (lane.field, lane.mass)
+                if self.lanes.get(key) is lane:
+                    del self.lanes[key]
+                return True
+            return False
+
+    def _take_stream(self):
+        with self.lock:
+            return self.streams.pop() if self.streams else self.backend.new_stream()
+
+    def _lane_done(self, lane: _Lane):
+        with self.lock:
+            self.streams.append(lane.stream)
+            key = (lane.field, lane.mass)
+            if self.lanes.get(key) is lane:
+                del self.lanes[key]
+            # requests routed to the lane after it decided to retire
+            with lane.cv:
+                left = list(lane.pending)
+                lane.pending.clear()
+            seen = set()
+            for res, req, _j in left:
+                if res.rid not in seen:
+                    seen.add(res.rid)
+                    self.waiting.appendleft((res, req))
+            self._drain_waiting()
+
+    def _drain_waiting(self):
+        keep = collections.deque()
+        while self.waiting:
+            res, req = self.waiting.popleft()
+            key = (req.field, float(req.mass))
+            if key in self.lanes or len(self.lanes) < self.max_lanes:
+                self._route(res, req)
+            else:
+                keep.append((res, req))
+        self.waiting = keep
+
+    def _complete(self, res: Result):
+        with self.lock:
+            if math.isnan(res.finished):
+                res.finished = self.now()
+            self.open -= 1
+            self.done_cv.notify_all()
+
+    # -- warm-up -----------------------------------------------------------------
+    def warm(self, keys: Sequence[Tuple], workers: int = 4):
+        """Build the hierarchy and batch of each (field, mass) key before serving
+        (fields in parallel; the masses of one field in order, so that the first
+        one runs the adaptive setup and the others derive from it)."""
+        by_field: Dict = collections.OrderedDict()
+        for f, m in keys:
+            by_field.setdefault(f, []).append(float(m))
+        items = list(by_field.items())
+        errors: list = []
+
+        def work(i):
+            stream = self._take_stream()
+            try:
+                with self.backend.stream_context(stream):
+                    for f, ms in items[i::workers]:
+                        for m in ms:
+                            solver = self.cache.acquire(f, m, self.capacity, stream)
+                            if solver is None:
+                                raise BudgetExceeded(f"no room to warm {(f, m)}")
+                            ent = self.cache.entry(f, m)
+                            if ent.batch is None:
+                                ent.batch = self.backend.new_batch(solver, self.capacity, self.tol, self.maxiter,
+                                                                   self.precision, stream)
+                                self.cache.settle(f, m, solver.memory_bytes() + ent.batch.memory_bytes())
+                            self.cache.release(f, m)
+            except BaseException as exc:
+                errors.append(exc)
+            finally:
+                with self.lock:
+                    self.streams.append(stream)
+
+        threads = [threading.Thread(target=work, args=(i,)) for i in range(min(workers, len(items)))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+
+    # -- driving ---------------------------------------------------------------
+    def run_trace(self, requests: Sequence[Request], timeout: float = 600.0) -> List[Result]:
+        """Submit each request at its arrival time (seconds from now) and wait for
+        all of them; returns the results in request order."""
+        self.t0 = time.perf_counter()
+        order = sorted(requests, key=lambda r: r.arrival)
+        for req in order:
+            dt = req.arrival - self.now()
+            if dt > 0:
+                time.sleep(dt)
+            self.submit(req, arrival=req.arrival)
+            with self.lock:
+                self._drain_waiting()
+        self.wait(timeout)
+        return [self.results[r.rid] for r in requests]
+
+    def wait(self, timeout: float = 600.0):
+        end = time.perf_counter() + timeout
+        with self.lock:
+            while self.open > 0:
+                self._drain_waiting()
+                left = end - time.perf_counter()
+                if left <= 0:
+                    raise TimeoutError(f"{self.open} requests still open")
+                self.done_cv.wait(timeout=min(left, 0.01))
+
+    def close(self):
+        with self.lock:
+            lanes = list(self.lanes.values())
+        for lane in lanes:
+            with lane.cv:
+                lane.stop = True
+                lane.cv.notify()
+        for lane in lanes:
+            lane.thread.join(timeout=60)
+        self.cache.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# -- workloads -------------------------------------------------------------------
+def poisson_trace(n_requests: int, rate: float, fields: Sequence, masses: Dict, k_range=(1, 16),
+                  seed: int = 0) -> List[Tuple[float, object, float, int, int]]:
+    """(arrival, field, mass, k, rhs_seed) for a Poisson stream of `rate`
+    requests/s; field uniform over `fields`, mass uniform over masses[field], k
+    uniform over k_range (inclusive)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n_requests):
+        f = fields[int(rng.integers(len(fields)))]
+        ms = masses[f]
+        m = float(ms[int(rng.integers(len(ms)))])
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        out.append((float(t[i]), f, m, k, int(rng.integers(1 << 31))))
+    return out
+
+
+def latency_summary(results: Sequence[Result]) -> dict:
+    import numpy as np
+
+    lat = np.array([r.latency for r in results if r.ok], dtype=np.float64)
+    solves = sum(r.k for r in results if r.ok)
+    span = max(r.finished for r in results) - min(r.arrival for r in results) if results else 0.0
+    if lat.size == 0:
+        return {"requests": len(results), "ok": 0}
+    return {
+        "requests": len(results),
+        "ok": int(sum(r.ok for r in results)),
+        "solves": int(solves),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "max_ms": float(lat.max() * 1e3),
+        "span_s": float(span),
+        "solves_per_s": float(solves / span) if span > 0 else math.nan,
+    }
+
+
+class DeviceBackend:
+    """The library on the GPU: one torch stream per lane.
+
+    fields: {key: (gauge tensor [2, lt, lx] on the device, Params template)}."""
+
+    def __init__(self, fields: Dict, mixed: bool = True):
+        import torch
+
+        from . import Batch, Solver
+
+        self.torch = torch
+        self.Solver = Solver
+        self.Batch = Batch
+        self.fields = fields
+        self.mixed = mixed
+
+    def estimate(self, field, capacity: int) -> int:
+        g, p = self.fields[field]
+        blocks = [(p.block[l][0], p.block[l][1]) for l in range(p.levels - 1)]
+        nv = [p.nv[l] for l in range(p.levels - 1)]
+        return estimate_bytes(p.lx, p.lt, blocks, nv, capacity, mixed=self.mixed,
+                              smoothed=p.sa_scale > 0, coarsest_direct=p.coarsest == 0)
+
+    def setup(self, field, mass: float, stream):
+        g, p = self.fields[field]
+        q = type(p)()
+        ctypes_copy(q, p)
+        q.mass = mass
+        return self.Solver(g, q, stream=stream)
+
+    def derive(self, solver, mass: float, stream):
+        return solver.derive(mass, stream=stream)
+
+    def new_stream(self):
+        return self.torch.cuda.Stream()
+
+    def stream_context(self, stream):
+        return self.torch.cuda.stream(stream)
+
+    def new_batch(self, solver, capacity, tol, maxiter, precision, stream):
+        return self.Batch(solver, capacity, tol=tol, maxiter=maxiter, precision=precision, stream=stream)
+
+    def new_output(self, rhs):
+        return self.torch.empty_like(rhs)
+
+
+def ctypes_copy(dst, src):
+    import ctypes
+
+    ctypes.memmove(ctypes.addressof(dst), ctypes.addressof(src), ctypes.sizeof(src))

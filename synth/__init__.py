@@ -7,7 +7,7 @@ the CPU oracle can both consume its outputs without sharing any method code.
 """
 
 from .gauge import metropolis_u1, plaquette_angles, mean_plaquette, topological_charge, links_from_angles
-from .vectors import gaussian, z2_noise, point_source, setup_randoms, level_shapes
+from .vectors import gaussian, gaussian_device, z2_noise, point_source, setup_randoms, level_shapes
 
 __all__ = [
     "metropolis_u1",
@@ -16,6 +16,7 @@ __all__ = [
     "topological_charge",
     "links_from_angles",
     "gaussian",
+    "gaussian_device",
     "z2_noise",
     "point_source",
     "setup_randoms",

@@ -65,3 +65,19 @@ def setup_randoms(lx: int, lt: int, blocks, nvs, seed: int):
         cx, ct, dof = shapes[lvl]
         out.append(gaussian((1 + nv, cx * ct * dof), seed * 1000 + lvl))
     return out
+
+
+def gaussian_device(n: int, seed: int, device="cuda", count: int = 1):
+    """`count` complex Gaussian vectors (Re, Im ~ N(0, 1/2)) drawn by torch's
+    generator on `device` from `seed`: [count, n] complex128.
+
+    For request streams whose right-hand sides are too many to draw on the host;
+    the values differ from ``gaussian(n, seed)`` (another generator) but are
+    reproducible for a given device type and seed.
+    """
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    z = torch.randn((count, n, 2), generator=g, device=device, dtype=torch.float64) * math.sqrt(0.5)
+    return torch.view_as_complex(z)

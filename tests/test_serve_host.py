@@ -1,0 +1,257 @@
+"""Host logic of the serving loop (setup cache, lanes, routing) on the CPU.
+
+A fake backend stands in for the library: its "solver" of key (field, mass)
+returns x = b / (f + m) after a number of steps that depends on b, so a result
+routed to the wrong key, column or slot shows up as a wrong value.
+"""
+
+import contextlib
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_0710_3612_amd import serve
+
+
+class FakeSolver:
+    def __init__(self, be, field, mass, derived_from=None):
+        self.be, self.field, self.mass = be, field, mass
+        self.derived_from = derived_from
+        self.closed = False
+
+    def memory_bytes(self):
+        return self.be.bytes_per_solver
+
+    def derive(self, mass, stream=None):
+        return FakeSolver(self.be, self.field, mass, derived_from=self)
+
+    def close(self):
+        assert not self.closed
+        self.closed = True
+        self.be.closed += 1
+
+
+class FakeBatch:
+    def __init__(self, be, solver, capacity):
+        self.be, self.solver, self.cap = be, solver, capacity
+        self.slots = [None] * capacity  # [rhs, steps left, done]
+        self.closed = False
+
+    def memory_bytes(self):
+        return self.be.bytes_per_batch
+
+    def admit(self, rhs, stream=None):
+        assert not self.solver.closed
+        for j in range(self.cap):
+            if self.slots[j] is None:
+                steps = 1 + int(abs(rhs[0].real) * 3) % 4
+                self.slots[j] = [np.array(rhs), steps, False]
+                return j
+        return None
+
+    def step(self, iters=1, stream=None):
+        with self.be.lock:
+            self.be.stepping += 1
+            self.be.max_stepping = max(self.be.max_stepping, self.be.stepping)
+        time.sleep(0.0005)
+        for s in self.slots:
+            if s is not None and not s[2]:
+                s[1] -= iters
+                if s[1] <= 0:
+                    s[2] = True
+        with self.be.lock:
+            self.be.stepping -= 1
+
+    def poll(self):
+        return [(j, {"status": 0, "iterations": 3, "true_relres": 1e-11})
+                for j, s in enumerate(self.slots) if s is not None and s[2]]
+
+    def harvest(self, slot, out, stream=None):
+        rhs = self.slots[slot][0]
+        out[:] = rhs / (self.solver.field + self.solver.mass)
+        self.slots[slot] = None
+
+    def close(self):
+        self.closed = True
+
+
+class FakeBackend:
+    def __init__(self, est=100, bytes_per_solver=80, bytes_per_batch=20, fail_fields=(), setup_delay=0.0):
+        self.est = est
+        self.bytes_per_solver = bytes_per_solver
+        self.bytes_per_batch = bytes_per_batch
+        self.fail_fields = set(fail_fields)
+        self.setup_delay = setup_delay
+        self.setups = []
+        self.derives = []
+        self.closed = 0
+        self.lock = threading.Lock()
+        self.stepping = 0
+        self.max_stepping = 0
+        self.cache_ref = None
+        self.max_used = 0
+
+    def _watch(self):
+        if self.cache_ref is not None:
+            self.max_used = max(self.max_used, self.cache_ref.used)
+
+    def estimate(self, field, capacity):
+        return self.est
+
+    def setup(self, field, mass, stream):
+        time.sleep(self.setup_delay)
+        if field in self.fail_fields:
+            raise RuntimeError("setup failed")
+        self.setups.append((field, mass))
+        self._watch()
+        return FakeSolver(self, field, mass)
+
+    def derive(self, solver, mass, stream):
+        self.derives.append((solver.field, mass))
+        self._watch()
+        return solver.derive(mass)
+
+    def new_stream(self):
+        return object()
+
+    def stream_context(self, stream):
+        return contextlib.nullcontext()
+
+    def new_batch(self, solver, capacity, tol, maxiter, precision, stream):
+        return FakeBatch(self, solver, capacity)
+
+    def new_output(self, rhs):
+        return np.zeros_like(rhs)
+
+
+def make_requests(spec, n=6, seed=0):
+    """spec: list of (field, mass, k, arrival)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (f, m, k, t) in enumerate(spec):
+        rhs = rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n))
+        out.append(serve.Request(i, f, m, rhs, k, t))
+    return out
+
+
+def check_results(reqs, results):
+    for req, res in zip(reqs, results):
+        assert res.ok, res.error
+        np.testing.assert_array_equal(res.x, req.rhs / (req.field + req.mass))
+        assert res.admitted >= res.arrival - 1e-9
+        assert res.finished >= res.admitted
+        assert len(res.status) == req.k
+
+
+def test_all_requests_complete_and_route_correctly():
+    be = FakeBackend()
+    spec = [(f, m, k, 0.002 * i) for i, (f, m, k) in enumerate(
+        [(1, 0.1, 3), (2, 0.1, 1), (1, 0.2, 5), (1, 0.1, 2), (3, 0.05, 16), (2, 0.3, 4)] * 3)]
+    reqs = make_requests(spec)
+    with serve.Server(be, budget_bytes=10_000, capacity=4, max_lanes=3) as srv:
+        results = srv.run_trace(reqs, timeout=30)
+        # first mass of a field is a full setup, the others derive from it
+        assert sorted(set(f for f, _ in be.setups)) == [1, 2, 3]
+        assert len(be.setups) == 3
+        assert len(be.derives) == 2
+    check_results(reqs, results)
+    assert be.max_stepping <= 3
+
+
+def test_request_wider_than_the_batch_streams_through_slots():
+    be = FakeBackend()
+    reqs = make_requests([(1, 0.0, 11, 0.0)])
+    with serve.Server(be, budget_bytes=10_000, capacity=2, max_lanes=1) as srv:
+        results = srv.run_trace(reqs, timeout=30)
+    check_results(reqs, results)
+
+
+def test_budget_evicts_least_recently_used_idle_setups():
+    be = FakeBackend(est=100, bytes_per_solver=80, bytes_per_batch=20)
+    spec = [(f, 0.0, 2, 0.0) for f in (1, 2, 3, 1, 4, 2)]
+    reqs = make_requests(spec)
+    with serve.Server(be, budget_bytes=250, capacity=4, max_lanes=1, linger=0.0) as srv:
+        be.cache_ref = srv.cache
+        results = srv.run_trace(reqs, timeout=30)
+        assert srv.cache.used <= 250
+        assert srv.cache.evictions >= 2
+        assert be.max_used <= 250
+    check_results(reqs, results)
+    assert be.closed >= 2
+
+
+def test_pinned_setups_are_not_evicted_and_waiters_proceed():
+    # room for one hierarchy: the second key waits for the first lane to retire
+    be = FakeBackend(est=100)
+    reqs = make_requests([(1, 0.0, 3, 0.0), (2, 0.0, 3, 0.0), (1, 0.5, 2, 0.0)])
+    with serve.Server(be, budget_bytes=150, capacity=2, max_lanes=3, linger=0.0) as srv:
+        results = srv.run_trace(reqs, timeout=30)
+    check_results(reqs, results)
+
+
+def test_over_budget_and_failed_setups_fail_only_their_requests():
+    be = FakeBackend(est=100, fail_fields={7})
+    reqs = make_requests([(7, 0.0, 2, 0.0), (1, 0.0, 2, 0.0)])
+    with serve.Server(be, budget_bytes=1000, capacity=2, max_lanes=2) as srv:
+        results = srv.run_trace(reqs, timeout=30)
+    assert results[0].error and "setup failed" in results[0].error
+    check_results(reqs[1:], results[1:])
+
+    be2 = FakeBackend(est=5000)
+    reqs2 = make_requests([(1, 0.0, 1, 0.0)])
+    with serve.Server(be2, budget_bytes=1000, capacity=2) as srv:
+        res = srv.run_trace(reqs2, timeout=30)
+    assert res[0].error and "exceed the budget" in res[0].error
+
+
+def test_concurrent_requests_for_a_key_share_one_setup():
+    be = FakeBackend(setup_delay=0.05)
+    reqs = make_requests([(1, 0.0, 1, 0.0)] * 6)
+    with serve.Server(be, budget_bytes=10_000, capacity=8, max_lanes=4) as srv:
+        results = srv.run_trace(reqs, timeout=30)
+    assert len(be.setups) == 1 and not be.derives
+    check_results(reqs, results)
+
+
+def test_poisson_trace_and_summary():
+    fields = ["a", "b"]
+    masses = {"a": [0.1, 0.2], "b": [0.3]}
+    tr = serve.poisson_trace(4000, rate=200.0, fields=fields, masses=masses, k_range=(1, 16), seed=3)
+    t = np.array([x[0] for x in tr])
+    assert t[0] == 0.0 and np.all(np.diff(t) >= 0)
+    assert abs(np.mean(np.diff(t)) - 1 / 200.0) < 0.1 / 200.0
+    ks = np.array([x[3] for x in tr])
+    assert ks.min() == 1 and ks.max() == 16
+    for _, f, m, _, _ in tr:
+        assert m in masses[f]
+    assert tr == serve.poisson_trace(4000, 200.0, fields, masses, (1, 16), seed=3)
+    res = [serve.Result(i, "a", 0.1, 2, arrival=0.0, admitted=0.0, finished=0.01 * (i + 1), status=[0, 0])
+           for i in range(100)]
+    s = serve.latency_summary(res)
+    assert s["ok"] == 100 and s["solves"] == 200
+    assert abs(s["p50_ms"] - 505.0) < 1e-9 and abs(s["p99_ms"] - 990.1) < 1e-9  # linear interpolation at rank 98.01
+
+
+def test_levels_for_and_estimate():
+    assert serve.levels_for(64) == 3  # 64 -> 16 -> 4
+    assert serve.levels_for(128) == 3  # 128 -> 32 -> 8
+    assert serve.levels_for(256) == 4  # 256 -> 64 -> 16 -> 4
+    assert serve.levels_for(512) == 4  # 512 -> 128 -> 32 -> 8
+    a = serve.estimate_bytes(256, 256, [(4, 4)] * 2, [12, 12], capacity=16)
+    b = serve.estimate_bytes(256, 256, [(4, 4)] * 2, [12, 12], capacity=1)
+    assert a > b > 0
+
+
+def test_warm_builds_every_key_once():
+    be = FakeBackend()
+    keys = [(f, m) for f in (1, 2, 3) for m in (0.1, 0.2)]
+    with serve.Server(be, budget_bytes=10_000, capacity=4) as srv:
+        srv.warm(keys, workers=2)
+        assert len(be.setups) == 3 and len(be.derives) == 3
+        assert all(srv.cache.entry(f, m).batch is not None for f, m in keys)
+        reqs = make_requests([(f, m, 2, 0.0) for f, m in keys])
+        results = srv.run_trace(reqs, timeout=30)
+        assert len(be.setups) == 3 and len(be.derives) == 3  # served from the warm cache
+    check_results(reqs, results)
