@@ -89,6 +89,10 @@ typedef struct {
                                      the calibration start); 0 = plain aggregation.  Applied
                                      where both block extents are >= 4 and both coarse
                                      extents >= 2 (the coarse operator stays 9-point). */
+  int32_t mfma_min_rhs;           /* FP32 coarse applies of at least this many right-hand
+                                     sides run on the matrix cores (MFMA FP32, levels with
+                                     nc <= 16); 1 = always, 0 = never.  Results differ from
+                                     the vector-ALU path by FP32 rounding only. */
 } smg_params;
 
 typedef struct {
@@ -103,7 +107,8 @@ typedef struct {
 
 /* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
- * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3. */
+ * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
+ * mfma_min_rhs = 16. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
@@ -158,6 +163,15 @@ int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int
  * solves use (the same operator as smg_apply_level, links rounded to FP32).
  * x, y: device, complex64 (interleaved float) level-l batches.  ASYNC. */
 int smg_apply_level_f32(smg_handle h, int32_t level, const float* x, float* y, int32_t nrhs, void* stream);
+
+/* FP32 operator of level `level` with the epilogues the V-cycle uses (Multigrid
+ * section, steps 1-5; Results for the smoother): mode 0: y = A_l x; mode 1 (one
+ * frozen MR step): xacc += coef x and y = x - coef A_l x; mode 2 (residual):
+ * y = aux - A_l x.  Vectors are complex64 device arrays [nrhs][n_l] (xacc, aux
+ * may be NULL where unused).  Coarse levels with nc <= 16 and
+ * nrhs >= mfma_min_rhs run on the matrix cores.  Errors: SMG_EINVAL. */
+int smg_level_op_f32(smg_handle h, int32_t level, int32_t mode, double coef, const float* x, float* y, float* xacc,
+                     const float* aux, int32_t nrhs, void* stream);
 
 /* y = P^H x: restriction from level l to level l+1 (V-cycle step 2).  ASYNC. */
 int smg_restrict(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,

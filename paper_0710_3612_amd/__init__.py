@@ -69,6 +69,7 @@ class Params(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("sa_scale", ctypes.c_double),
+        ("mfma_min_rhs", ctypes.c_int32),
     ]
 
 
@@ -123,6 +124,7 @@ def load_library():
         "smg_apply_A": (i32, [h, P, P, i32, P]),
         "smg_apply_level": (i32, [h, i32, P, P, i32, P]),
         "smg_apply_level_f32": (i32, [h, i32, P, P, i32, P]),
+        "smg_level_op_f32": (i32, [h, i32, i32, ctypes.c_double, P, P, P, P, i32, P]),
         "smg_restrict": (i32, [h, i32, P, P, i32, P]),
         "smg_prolong": (i32, [h, i32, P, P, i32, P]),
         "smg_smooth": (i32, [h, i32, P, P, i32, P]),
@@ -167,7 +169,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 nv: Sequence[int] = (8,), setup_iters: int = 5, smoother_steps: int = 4,
                 smoother_omega: float = 0.8, t_antiperiodic: bool = True, coarsest: int = COARSEST_DIRECT,
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
-                seed: int = 1, sa_scale: float = 4.0 / 3.0) -> Params:
+                seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -185,6 +187,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.inner_tol = inner_tol
     p.seed = seed
     p.sa_scale = sa_scale
+    p.mfma_min_rhs = mfma_min_rhs
     return p
 
 
@@ -314,6 +317,22 @@ class Solver:
         y = torch.empty_like(x)
         _check(self.lib.smg_apply_level_f32(self.handle, level, ctypes.c_void_p(x.data_ptr()),
                                             ctypes.c_void_p(y.data_ptr()), nr, _stream(stream)))
+        return y
+
+    def level_op_f32(self, level: int, x, mode: int = 0, coef: float = 0.0, xacc=None, aux=None, stream=None):
+        """FP32 level operator with the V-cycle's epilogues (smg_level_op_f32);
+        complex64 tensors; returns y (xacc is updated in place for mode 1)."""
+        def p32(t):
+            if t is None:
+                return ctypes.c_void_p()
+            if not t.is_cuda or t.dtype != self._torch.complex64 or not t.is_contiguous():
+                raise TypeError("expected a contiguous complex64 CUDA tensor")
+            return ctypes.c_void_p(t.data_ptr())
+
+        nr = self._nrhs(x, self.level_size(level))
+        y = self._torch.empty_like(x)
+        _check(self.lib.smg_level_op_f32(self.handle, level, int(mode), float(coef), p32(x), p32(y), p32(xacc),
+                                         p32(aux), nr, _stream(stream)))
         return y
 
     def restrict(self, level: int, x, stream=None):

@@ -110,6 +110,9 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                    double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+// Matrix-core (MFMA FP32) coarse apply for 1 <= nc <= 16, any number of right-hand sides.
+void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                        z32* xacc, const z32* aux, hipStream_t st);
 
 // Transfer between level (lx, lt, dof) and its aggregates of (bx, bt) sites.
 // P is [J][ldk][nw] (ldk >= nc vectors stored per aggregate) over windows of

@@ -593,6 +593,148 @@ void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int c
   HIPCHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Multi-RHS FP32 coarse operator on the matrix cores (Eq. 2 applied to 32
+// right-hand sides at once).  For one coarse site K and one link direction D the
+// complex product Y += L_{K,D} V_{K+D} (nc x nc times nc x 32) is the real GEMM
+//   [Yr; Yi] += [[Lr, -Li], [Li, Lr]] [Vr; Vi]      (rows and K index padded to 32)
+// done with v_mfma_f32_32x32x2f32: each instruction takes two link columns c, c+1
+// (one per half-wave) against the matching rows of V; the Re half of the K index
+// pairs Lr|Li with Vr, the Im half pairs -Li|Lr with Vi.  Per site that is
+// 9 * 2 * ceil(nc/2) instructions of 4096 flops.  Lane layout (checked on the
+// device): A[i][k] from lane i + 32k, B[k][j] from lane j + 32k, and accumulator
+// r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32.
+//
+// V is staged per workgroup for a TX x TT tile of sites plus a one-site ring,
+// transposed to [site][c][rhs] (rows padded to 33 entries against bank
+// conflicts), so the B operand is one conflict-free 8-byte LDS read per lane.
+// Links stream from HBM once.  Waves take the tile's sites in turn.
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaRS = 33;  // padded LDS row (32 right-hand sides + 1)
+
+__device__ inline int xcd_tile(int b, int nb) {
+  // block b runs on XCD b % 8: hand XCD k the k-th eighth of the tiles
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <int MODE, int TX, int TT, int NW>
+__global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__ L, const z32* __restrict__ v,
+                                                        z32* __restrict__ y, int cx, int ct, int nc, int nrhs,
+                                                        float c, z32* __restrict__ xacc,
+                                                        const z32* __restrict__ aux) {
+  constexpr int HX = TX + 2, HT = TT + 2, NS = HX * HT;
+  __shared__ float2 vs[NS * 16 * kMfmaRS];
+  const int nK = cx * ct;
+  const size_t n = (size_t)nK * nc;
+  const int rhs0 = blockIdx.y * 32;
+  const int ntx = (cx + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
+  const int S = (nc + 1) >> 1;  // instruction pairs per link direction
+  const int nc2 = 2 * S;        // staged rows (a zero row pads odd nc)
+
+  // ---- stage V (tile + ring), [site][c][rhs] --------------------------------
+  const int per_rhs = NS * nc2;
+  for (int e = threadIdx.x; e < per_rhs * 32; e += NW * 64) {
+    const int j = e / per_rhs;
+    const int rest = e - j * per_rhs;
+    const int site = rest / nc2, cc = rest - site * nc2;
+    const int ht = site / HX, hx = site - ht * HX;
+    // periodic wrap; the ring of a ragged tile may reach past one period when an
+    // extent is smaller than the tile
+    const int gx = ((x0 + hx - 1) % cx + cx) % cx, gt = ((t0 + ht - 1) % ct + ct) % ct;
+    float2 val = make_float2(0.f, 0.f);
+    if (cc < nc && rhs0 + j < nrhs) {
+      const z32 t = v[(size_t)(rhs0 + j) * n + (size_t)(gt * cx + gx) * nc + cc];
+      val = make_float2(t.re, t.im);
+    }
+    vs[(site * 16 + cc) * kMfmaRS + j] = val;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int row = i & 15;
+  const bool upper = i >= 16;
+  const bool row_ok = row < nc;
+  for (int s = w; s < TX * TT; s += NW) {
+    const int ox = s % TX, ot = s / TX;
+    const int Kx = x0 + ox, Kt = t0 + ot;
+    if (Kx >= cx || Kt >= ct) continue;  // ragged tile edge (wave-uniform)
+    const size_t Kbase = (size_t)(Kt * cx + Kx) * nc;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int D = 0; D < 9; ++D) {
+      const int dt = D / 3 - 1, dx = D % 3 - 1;
+      const int ls = (ot + 1 + dt) * HX + (ox + 1 + dx);
+      const z32* LD = L + (size_t)D * nc * n + Kbase + row;
+      const float2* VB = vs + (size_t)ls * 16 * kMfmaRS + i;
+#pragma unroll
+      for (int sp = 0; sp < 8; ++sp) {
+        if (sp < S) {
+          const int cc = 2 * sp + h;
+          z32 l = mk<float>(0.f, 0.f);
+          if (row_ok && cc < nc) l = LD[(size_t)cc * n];
+          const float2 b = VB[cc * kMfmaRS];
+          const float a_re = upper ? l.im : l.re;
+          const float a_im = upper ? l.re : -l.im;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b.y, acc, 0, 0, 0);
+        }
+      }
+    }
+    // ---- epilogue: lane holds rhs j = i, dofs 8(r/4) + 4h + r%4 (Re in r, Im in r + 8)
+    const int j = i;
+    if (rhs0 + j >= nrhs) continue;
+    const size_t ob = (size_t)(rhs0 + j) * n + Kbase;
+    const int lsc = (ot + 1) * HX + (ox + 1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int dof = 8 * (r >> 2) + 4 * h + (r & 3);
+      if (dof >= nc) continue;
+      const z32 sum = mk<float>(acc[r], acc[r + 8]);
+      const size_t o = ob + dof;
+      if (MODE == 0) {
+        y[o] = sum;
+      } else if (MODE == 1) {
+        const float2 t = vs[(lsc * 16 + dof) * kMfmaRS + j];
+        const z32 vi = mk<float>(t.x, t.y);
+        xacc[o] = xacc[o] + c * vi;
+        y[o] = vi - c * sum;
+      } else {
+        y[o] = aux[o] - sum;
+      }
+    }
+  }
+}
+
+template <int TX, int TT, int NW>
+void launch_coarse_mfma_t(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                          z32* xacc, const z32* aux, hipStream_t st) {
+  const int tiles = ((cx + TX - 1) / TX) * ((ct + TT - 1) / TT);
+  dim3 grid((unsigned)tiles, (unsigned)((nrhs + 31) / 32));
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarse_mfma<0, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_coarse_mfma<1, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux);
+  else
+    hipLaunchKernelGGL((k_coarse_mfma<2, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                        z32* xacc, const z32* aux, hipStream_t st) {
+  if (nc < 1 || nc > 16) throw Error(-1, "matrix-core coarse apply needs 1 <= nc <= 16");
+  launch_coarse_mfma_t<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+}
+
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                    cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {

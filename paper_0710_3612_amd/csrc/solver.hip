@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/smg.h"
@@ -99,6 +100,7 @@ struct KVecs {
 struct Ctx {
   smg_params prm{};
   int nlev = 0;
+  int mfma_pin = -1;                // -1: by mfma_min_rhs; 0 / 1: vector ALU / matrix cores
   hipStream_t st = nullptr;
   Pool pool;
   z64* U64 = nullptr;
@@ -202,15 +204,30 @@ void ensure_kvecs(Ctx& c, KVecs<R>& v, size_t elems) {
 // ---------------------------------------------------------------------------
 // Operators.
 // ---------------------------------------------------------------------------
+// FP32 coarse applies of many right-hand sides go to the matrix cores.  A batch
+// pins the choice for all its V-cycles (mfma_pin), so that a column's rounding
+// does not depend on how many other columns run beside it.
+bool use_mfma(const Ctx& c, int nc, int nrhs) {
+  if (nc > 16) return false;
+  if (c.mfma_pin >= 0) return c.mfma_pin == 1;
+  return c.prm.mfma_min_rhs > 0 && nrhs >= c.prm.mfma_min_rhs;
+}
+
 template <typename R>
 void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mode, double coef, cpx<R>* xacc,
               const cpx<R>* aux) {
   if (lv.fine) {
     launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st);
     c.fine_applies += nrhs;
-  } else {
-    launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+    return;
   }
+  if constexpr (std::is_same<R, float>::value) {
+    if (use_mfma(c, lv.dof, nrhs)) {
+      launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+      return;
+    }
+  }
+  launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
 }
 
 template <typename R>
@@ -837,6 +854,11 @@ void batch_precondition(Batch& B, int j0, int cnt, hipStream_t st) {
   if (B.prec == SMG_FP64) {
     vcycle<double>(c, 0, c.nlev - 1, B.r + off, B.z + off, cnt, cg);
   } else {
+    struct Pin {  // restored on every exit path
+      Ctx& c;
+      ~Pin() { c.mfma_pin = -1; }
+    } pin{c};
+    c.mfma_pin = (c.prm.mfma_min_rhs > 0 && B.cap >= c.prm.mfma_min_rhs) ? 1 : 0;
     launch_convert<float, double>(B.r + off, B.r32 + off, (size_t)cnt * B.n, st);
     vcycle<float>(c, 0, c.nlev - 1, B.r32 + off, B.z32v + off, cnt, cg);
     launch_convert<double, float>(B.z32v + off, B.z + off, (size_t)cnt * B.n, st);
@@ -972,6 +994,7 @@ void smg_default_params(smg_params* p) {
   p->inner_tol = 1e-5;
   p->seed = 1;
   p->sa_scale = 4.0 / 3.0;
+  p->mfma_min_rhs = 16;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
@@ -1131,6 +1154,23 @@ int smg_apply_level_f32(smg_handle h, int32_t level, const float* x, float* y, i
   ensure_f32(*c);
   ensure_level_work<float>(*c, nrhs);
   apply_op<float>(*c, c->L32[level], (const z32*)x, (z32*)y, nrhs, 0, 0.0, nullptr, nullptr);
+  return SMG_OK;
+  API_END
+}
+
+int smg_level_op_f32(smg_handle h, int32_t level, int32_t mode, double coef, const float* x, float* y, float* xacc,
+                     const float* aux, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (mode < 0 || mode > 2) throw Error(SMG_EINVAL, "mode must be 0, 1 or 2");
+  if (!x || !y || (mode == 1 && !xacc) || (mode == 2 && !aux)) throw Error(SMG_EINVAL, "null vector");
+  if (!std::isfinite(coef)) throw Error(SMG_EINVAL, "coef must be finite");
+  c->st = (hipStream_t)stream;
+  ensure_f32(*c);
+  ensure_level_work<float>(*c, nrhs);
+  apply_op<float>(*c, c->L32[level], (const z32*)x, (z32*)y, nrhs, mode, coef, (z32*)xacc, (const z32*)aux);
   return SMG_OK;
   API_END
 }

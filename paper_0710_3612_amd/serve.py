@@ -640,12 +640,18 @@ def latency_summary(results: Sequence[Result]) -> dict:
     span = max(r.finished for r in results) - min(r.arrival for r in results) if results else 0.0
     if lat.size == 0:
         return {"requests": len(results), "ok": 0}
+    wait = np.array([r.admitted - r.arrival for r in results if r.ok], dtype=np.float64)
+    service = np.array([r.finished - r.admitted for r in results if r.ok], dtype=np.float64)
     return {
         "requests": len(results),
         "ok": int(sum(r.ok for r in results)),
         "solves": int(solves),
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "wait_p50_ms": float(np.percentile(wait, 50) * 1e3),
+        "wait_p99_ms": float(np.percentile(wait, 99) * 1e3),
+        "service_p50_ms": float(np.percentile(service, 50) * 1e3),
+        "service_p99_ms": float(np.percentile(service, 99) * 1e3),
         "max_ms": float(lat.max() * 1e3),
         "span_s": float(span),
         "solves_per_s": float(solves / span) if span > 0 else math.nan,

@@ -32,19 +32,44 @@ def test_library_exports_every_declared_symbol():
     assert not missing, f"missing exports: {missing}"
 
 
+def c_layout():
+    """Offsets and sizes of the ABI structs as the C compiler lays them out."""
+    import json
+    import subprocess
+    import tempfile
+
+    fields = {
+        "smg_params": ["lx", "lt", "mass", "levels", "block", "nv", "setup_iters", "smoother_steps",
+                       "smoother_omega", "t_antiperiodic", "coarsest", "coarsest_tol", "coarsest_maxiter",
+                       "inner_tol", "seed", "sa_scale", "mfma_min_rhs"],
+        "smg_stats": ["status", "iterations", "refinements", "vcycles", "fine_applies", "true_relres", "seconds"],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {", 'printf("{");']
+    first = True
+    for st, fs in fields.items():
+        for f in fs:
+            sep = "" if first else ","
+            first = False
+            lines.append(f'printf("{sep}\\"{st}.{f}\\": %zu", offsetof({st}, {f}));')
+        lines.append(f'printf(",\\"{st}\\": %zu", sizeof({st}));')
+    lines += ['printf("}\\n");', "return 0; }"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", src, "-o", exe], check=True)
+        return json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout), fields
+
+
 def test_struct_layouts_match_c():
-    """Offsets of the ctypes mirrors equal the C layout (natural alignment)."""
+    """Offsets and sizes of the ctypes mirrors equal the C compiler's."""
     import paper_0710_3612_amd as smg
 
-    p = smg.Params
-    assert p.mass.offset == 8
-    assert p.block.offset == 20
-    assert p.nv.offset == 20 + 6 * 2 * 4
-    assert p.seed.offset % 8 == 0 and p.sa_scale.offset == p.seed.offset + 8
-    assert ctypes.sizeof(p) == p.sa_scale.offset + 8
-    s = smg.Stats
-    assert s.fine_applies.offset == 16
-    assert ctypes.sizeof(s) == 40
+    lay, fields = c_layout()
+    for st, cls in (("smg_params", smg.Params), ("smg_stats", smg.Stats)):
+        assert [f for f, _ in cls._fields_] == fields[st]
+        for f in fields[st]:
+            assert getattr(cls, f).offset == lay[f"{st}.{f}"], (st, f)
+        assert ctypes.sizeof(cls) == lay[st]
 
 
 def test_default_params_and_strerror():
@@ -57,6 +82,7 @@ def test_default_params_and_strerror():
     assert abs(p.smoother_omega - 0.8) < 1e-15
     assert p.block[0][0] == 4 and p.nv[0] == 8
     assert abs(p.sa_scale - 4.0 / 3.0) < 1e-15
+    assert p.mfma_min_rhs == 16
     assert lib.smg_strerror(-2).decode().startswith("lattice extents")
     assert lib.smg_strerror(1).decode().startswith("not converged")
 

@@ -1,0 +1,131 @@
+"""GPU: the matrix-core (MFMA FP32) coarse operator against the FP64 oracle.
+
+The coarse operator of Eq. 2 applied to many right-hand sides runs on
+v_mfma_f32_32x32x2f32 for levels with nc <= 16.  Each mode (plain apply, one
+frozen MR smoother step, residual) is compared with the oracle's sparse coarse
+matrix in FP64 on the same FP32-rounded inputs, and with the vector-ALU path.
+Inputs and links are rounded to FP32 (unit roundoff 6e-8) and an output sums at
+most 9 * 16 complex products, so 2e-5 of the column's largest entry bounds the
+difference with a wide margin.  Cases cover nc = 16, 12 and an odd nc = 5, tiles
+cut by the lattice edge (coarse extents not multiples of the 4 x 4 tile), and
+right-hand-side counts that are not multiples of 32.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import multigrid as mg
+from oracle.wilson import normal_matrix
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 2e-5
+
+CASES = [
+    # lx, lt, blocks, nvs, mass
+    (32, 32, [(4, 4), (2, 2)], [16, 16], 0.05),   # levels 8x8x16 and 4x4x16
+    (40, 24, [(4, 4)], [12], 0.1),                # 10x6x12: tiles cut at both edges
+    (20, 20, [(4, 4)], [5], 0.2),                 # 5x5x5: odd nc
+    (24, 24, [(4, 4)], [16], 0.03),               # 6x6x16: tiles cut at both edges
+    (16, 16, [(4, 4), (2, 2)], [8, 16], 0.1),     # 2x2x16: the ring wraps more than once
+]
+
+
+def dev(x, dtype=np.complex128):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def colerr(a, b):
+    """Largest per-column max-norm difference relative to the column's max |b|."""
+    a = a.reshape(b.shape)
+    return max(float(np.max(np.abs(a[j] - b[j])) / np.max(np.abs(b[j]))) for j in range(b.shape[0]))
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)))
+def hier(request):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0710_3612_amd as smg
+
+    lx, lt, blocks, nvs, m = CASES[request.param]
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 20, 70 + request.param))
+    shapes = synth.level_shapes(lx, lt, blocks, nvs)
+    vecs, calib = [], []
+    for l, nv in enumerate(nvs):
+        cx, ct, dof = shapes[l]
+        n = cx * ct * dof
+        vecs.append(synth.gaussian((nv, n), 900 + 10 * request.param + l))
+        calib.append(synth.gaussian(n, 950 + 10 * request.param + l))
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=4 / 3)
+    vv = dev(np.concatenate([v.ravel() for v in vecs]))
+    cc = dev(np.concatenate(calib))
+    out = {}
+    for name, mmin in (("mfma", 1), ("valu", 0)):
+        p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, mfma_min_rhs=mmin)
+        out[name] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    yield dict(h=h, A=A, U=U, m=m, nlev=len(blocks) + 1, **out)
+    for s in (out["mfma"], out["valu"]):
+        s.close()
+
+
+@pytest.mark.parametrize("nrhs", [32, 45, 1])
+def test_mfma_coarse_modes(hier, nrhs):
+    import torch
+
+    for level in range(1, hier["nlev"]):
+        Ac = hier["h"].levels[level].A
+        n = Ac.shape[0]
+        rng = np.random.default_rng(level * 100 + nrhs)
+        x = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        aux = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        acc0 = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        coef = 0.37
+        x64 = x.astype(np.complex128)
+        Ax = np.stack([Ac @ x64[j] for j in range(nrhs)])
+        got = {}
+        for name in ("mfma", "valu"):
+            s = hier[name]
+            xt = dev(x, np.complex64)
+            y0 = host(s.level_op_f32(level, xt, mode=0)).reshape(nrhs, n)
+            xacc = dev(acc0, np.complex64)
+            y1 = host(s.level_op_f32(level, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
+            a1 = host(xacc).reshape(nrhs, n)
+            y2 = host(s.level_op_f32(level, xt, mode=2, aux=dev(aux, np.complex64))).reshape(nrhs, n)
+            torch.cuda.synchronize()
+            assert colerr(y0, Ax) <= TOL32, (name, level, "mode 0")
+            assert colerr(y1, x64 - coef * Ax) <= TOL32, (name, level, "mode 1")
+            assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (name, level, "mode 1 acc")
+            assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL32, (name, level, "mode 2")
+            got[name] = y0
+        assert colerr(got["mfma"], got["valu"].astype(np.complex128)) <= TOL32
+
+
+def test_mfma_mixed_solve_many_rhs(hier):
+    """Mixed-precision MG-CG of 40 right-hand sides with the matrix-core coarse
+    operator: every column reaches 1e-10 against the oracle's A, and the solution
+    agrees with the vector-ALU path to the accuracy both reached."""
+    import paper_0710_3612_amd as smg
+
+    A = hier["A"]
+    n = A.shape[0]
+    B = synth.gaussian((40, n), 4242)
+    xs = {}
+    for name in ("mfma", "valu"):
+        x, st, code = hier[name].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.MIXED)
+        assert code == 0
+        xh = host(x).reshape(40, n)
+        for j in range(0, 40, 7):
+            assert np.linalg.norm(B[j] - A @ xh[j]) / np.linalg.norm(B[j]) <= 1e-10
+        xs[name] = xh
+    d = np.linalg.norm(xs["mfma"] - xs["valu"], axis=1) / np.linalg.norm(xs["valu"], axis=1)
+    assert d.max() < 1e-6
