@@ -620,12 +620,16 @@ __device__ inline int xcd_tile(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <int MODE, int TX, int TT, int NW>
+template <int MODE, int TX, int TT, int NW, int S>
 __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__ L, const z32* __restrict__ v,
                                                         z32* __restrict__ y, int cx, int ct, int nc, int nrhs,
                                                         float c, z32* __restrict__ xacc,
-                                                        const z32* __restrict__ aux) {
+                                                        const z32* __restrict__ aux, int pairs) {
+  // S = ceil(nc / 2): MFMA pairs per link direction and staged column pairs.  It is
+  // a compile-time constant so that the loads below are straight-line code (loads
+  // under branches make the compiler drain every outstanding load before an MFMA).
   constexpr int HX = TX + 2, HT = TT + 2, NS = HX * HT;
+  constexpr int NT = NW * 64;
   __shared__ float2 vs[NS * 16 * kMfmaRS];
   const int nK = cx * ct;
   const size_t n = (size_t)nK * nc;
@@ -633,25 +637,50 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   const int ntx = (cx + TX - 1) / TX;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
-  const int S = (nc + 1) >> 1;  // instruction pairs per link direction
-  const int nc2 = 2 * S;        // staged rows (a zero row pads odd nc)
 
-  // ---- stage V (tile + ring), [site][c][rhs] --------------------------------
-  const int per_rhs = NS * nc2;
-  for (int e = threadIdx.x; e < per_rhs * 32; e += NW * 64) {
-    const int j = e / per_rhs;
-    const int rest = e - j * per_rhs;
-    const int site = rest / nc2, cc = rest - site * nc2;
-    const int ht = site / HX, hx = site - ht * HX;
-    // periodic wrap; the ring of a ragged tile may reach past one period when an
-    // extent is smaller than the tile
-    const int gx = ((x0 + hx - 1) % cx + cx) % cx, gt = ((t0 + ht - 1) % ct + ct) % ct;
-    float2 val = make_float2(0.f, 0.f);
-    if (cc < nc && rhs0 + j < nrhs) {
-      const z32 t = v[(size_t)(rhs0 + j) * n + (size_t)(gt * cx + gx) * nc + cc];
-      val = make_float2(t.re, t.im);
+  // ---- stage V (tile + ring) as [site][c][rhs]: item = (rhs, row, site in row, column pair),
+  // consecutive items are consecutive 16-byte pairs of one right-hand side's row.  Out of
+  // range items load a clamped (valid) address and are masked afterwards.
+  {
+    constexpr int U = 18;  // loads in flight per thread (a 4x4 tile of 16 columns: all of them)
+    constexpr int items = 32 * NS * S;
+    const int jmax = nrhs - rhs0 - 1;
+    for (int base = threadIdx.x; base < items; base += NT * U) {
+      float4 buf[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e0 = base + u * NT;
+        const int e = e0 < items ? e0 : items - 1;
+        const int pr = e % S;
+        const int rest = e / S;
+        const int site = rest % NS, j = rest / NS;
+        const int ht = site / HX, hx = site - ht * HX;
+        // periodic wrap; the ring of a ragged tile may reach past one period when an
+        // extent is smaller than the tile
+        const int gx = ((x0 + hx - 1) % cx + cx) % cx, gt = ((t0 + ht - 1) % ct + ct) % ct;
+        const int jc = j <= jmax ? j : jmax;
+        const z32* src = v + (size_t)(rhs0 + jc) * n + (size_t)(gt * cx + gx) * nc;
+        float4 t;
+        if (pairs) {
+          t = *reinterpret_cast<const float4*>(src + 2 * pr);
+        } else {
+          const z32 a0 = src[2 * pr];
+          const z32 a1 = src[min(2 * pr + 1, nc - 1)];
+          t = make_float4(a0.re, a0.im, a1.re, a1.im);
+        }
+        const bool live = j <= jmax;
+        const bool hi_ok = live && (2 * pr + 1 < nc);
+        buf[u] = make_float4(live ? t.x : 0.f, live ? t.y : 0.f, hi_ok ? t.z : 0.f, hi_ok ? t.w : 0.f);
+        dst[u] = e0 < items ? (site * 16 + 2 * pr) * kMfmaRS + j : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (dst[u] < 0) continue;
+        vs[dst[u]] = make_float2(buf[u].x, buf[u].y);
+        vs[dst[u] + kMfmaRS] = make_float2(buf[u].z, buf[u].w);
+      }
     }
-    vs[(site * 16 + cc) * kMfmaRS + j] = val;
   }
   __syncthreads();
 
@@ -659,44 +688,84 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   const int i = lane & 31, h = lane >> 5;
   const int row = i & 15;
   const bool upper = i >= 16;
+  const int rowc = row < nc ? row : nc - 1;  // clamped: every lane loads a valid address
   const bool row_ok = row < nc;
-  for (int s = w; s < TX * TT; s += NW) {
-    const int ox = s % TX, ot = s / TX;
-    const int Kx = x0 + ox, Kt = t0 + ot;
-    if (Kx >= cx || Kt >= ct) continue;  // ragged tile edge (wave-uniform)
-    const size_t Kbase = (size_t)(Kt * cx + Kx) * nc;
-    floatx16 acc;
+  // this wave's sites: valid sites of the tile, round robin over the waves
+  const int vx = min(TX, cx - x0), vt = min(TT, ct - t0);
+  const int nvalid = vx * vt;
+  const int mine = nvalid > w ? (nvalid - w + NW - 1) / NW : 0;
+  if (mine == 0) return;  // wave-uniform, and no barrier follows
+  auto load_links = [&](int k, int D, z32* dst) {
+    const int idx = w + k * NW;
+    const int ox = idx % vx, ot = idx / vx;
+    const z32* LD = L + (size_t)D * nc * n + (size_t)((t0 + ot) * cx + x0 + ox) * nc + rowc;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int sp = 0; sp < S; ++sp) {
+      const int cc = 2 * sp + h;
+      dst[sp] = LD[(size_t)(cc < nc ? cc : nc - 1) * n];  // masked where used, not here
+    }
+  };
+  // Links stream through a ring of three link directions held in registers, two
+  // ahead of the MFMAs (occupancy is set by the LDS tile, so registers are free).
+  // The sites of a wave and their nine directions are unrolled and their results
+  // stay in registers until every site is done: the loop is straight-line code
+  // with compile-time ring slots and no stores, so the compiler can wait for
+  // exactly the loads each step needs.
+  constexpr int MAXS = (TX * TT + NW - 1) / NW;
+  const int last = 9 * mine - 1;
+  auto load_step = [&](int q, z32* dst) {
+    q = min(q, last);
+    load_links(q / 9, q - 9 * (q / 9), dst);
+  };
+  z32 lb[3][S];
+  load_step(0, lb[0]);
+  load_step(1, lb[1]);
+  load_step(2, lb[2]);
+  floatx16 acc[MAXS];
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+    if (k >= mine) continue;  // wave-uniform
+    const int idx = w + k * NW;
+    const int ox = idx % vx, ot = idx / vx;
+#pragma unroll
     for (int D = 0; D < 9; ++D) {
       const int dt = D / 3 - 1, dx = D % 3 - 1;
       const int ls = (ot + 1 + dt) * HX + (ox + 1 + dx);
-      const z32* LD = L + (size_t)D * nc * n + Kbase + row;
       const float2* VB = vs + (size_t)ls * 16 * kMfmaRS + i;
+      float2 b[S];
 #pragma unroll
-      for (int sp = 0; sp < 8; ++sp) {
-        if (sp < S) {
-          const int cc = 2 * sp + h;
-          z32 l = mk<float>(0.f, 0.f);
-          if (row_ok && cc < nc) l = LD[(size_t)cc * n];
-          const float2 b = VB[cc * kMfmaRS];
-          const float a_re = upper ? l.im : l.re;
-          const float a_im = upper ? l.re : -l.im;
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b.x, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b.y, acc, 0, 0, 0);
-        }
+      for (int sp = 0; sp < S; ++sp) b[sp] = VB[(2 * sp + h) * kMfmaRS];
+#pragma unroll
+      for (int sp = 0; sp < S; ++sp) {
+        const z32 l = lb[D % 3][sp];
+        const bool ok = row_ok && (2 * sp + h < nc);
+        const float a_re = ok ? (upper ? l.im : l.re) : 0.f;
+        const float a_im = ok ? (upper ? l.re : -l.im) : 0.f;
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b[sp].x, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b[sp].y, acc[k], 0, 0, 0);
       }
+      load_step(9 * k + D + 3, lb[D % 3]);  // refill the slot just consumed
+      // keep the refill here: the scheduler would otherwise sink it next to its use
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // ---- epilogue: lane holds rhs j = i, dofs 8(r/4) + 4h + r%4 (Re in r, Im in r + 8)
-    const int j = i;
-    if (rhs0 + j >= nrhs) continue;
-    const size_t ob = (size_t)(rhs0 + j) * n + Kbase;
+  }
+  // ---- epilogue: lane holds rhs j = i, dofs 8(r/4) + 4h + r%4 (Re in r, Im in r + 8)
+  const int j = i;
+  if (rhs0 + j >= nrhs) return;
+#pragma unroll
+  for (int k = 0; k < MAXS; ++k) {
+    if (k >= mine) break;
+    const int idx = w + k * NW;
+    const int ox = idx % vx, ot = idx / vx;
+    const size_t ob = (size_t)(rhs0 + j) * n + (size_t)((t0 + ot) * cx + x0 + ox) * nc;
     const int lsc = (ot + 1) * HX + (ox + 1);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int dof = 8 * (r >> 2) + 4 * h + (r & 3);
       if (dof >= nc) continue;
-      const z32 sum = mk<float>(acc[r], acc[r + 8]);
+      const z32 sum = mk<float>(acc[k][r], acc[k][r + 8]);
       const size_t o = ob + dof;
       if (MODE == 0) {
         y[o] = sum;
@@ -712,27 +781,38 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   }
 }
 
-template <int TX, int TT, int NW>
+template <int TX, int TT, int NW, int S>
 void launch_coarse_mfma_t(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                           z32* xacc, const z32* aux, hipStream_t st) {
   const int tiles = ((cx + TX - 1) / TX) * ((ct + TT - 1) / TT);
   dim3 grid((unsigned)tiles, (unsigned)((nrhs + 31) / 32));
+  // 16-byte loads of column pairs need an even nc and a 16-byte aligned input
+  const int pairs = (nc % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
   if (mode == 0)
-    hipLaunchKernelGGL((k_coarse_mfma<0, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux);
+    hipLaunchKernelGGL((k_coarse_mfma<0, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux, pairs);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse_mfma<1, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux);
+    hipLaunchKernelGGL((k_coarse_mfma<1, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux, pairs);
   else
-    hipLaunchKernelGGL((k_coarse_mfma<2, TX, TT, NW>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux);
+    hipLaunchKernelGGL((k_coarse_mfma<2, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux, pairs);
   HIPCHECK(hipGetLastError());
 }
 
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                         z32* xacc, const z32* aux, hipStream_t st) {
   if (nc < 1 || nc > 16) throw Error(-1, "matrix-core coarse apply needs 1 <= nc <= 16");
-  launch_coarse_mfma_t<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  switch ((nc + 1) / 2) {
+    case 1: launch_coarse_mfma_t<4, 4, 8, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 2: launch_coarse_mfma_t<4, 4, 8, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 3: launch_coarse_mfma_t<4, 4, 8, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 4: launch_coarse_mfma_t<4, 4, 8, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 5: launch_coarse_mfma_t<4, 4, 8, 5>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 6: launch_coarse_mfma_t<4, 4, 8, 6>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 7: launch_coarse_mfma_t<4, 4, 8, 7>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    default: launch_coarse_mfma_t<4, 4, 8, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+  }
 }
 
 template <typename R>
