@@ -143,8 +143,9 @@ int colors_along(int extent);
 // Dense coarsest operator and its inverse (FP64).
 void launch_coarse_to_dense(const z64* L, z64* M, int cx, int ct, int nc, hipStream_t st);
 void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hipStream_t st);
-template <typename R>
-void launch_dense_apply(const z64* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
+// Y = M X, M dense row-major n x n in precision RM, X and Y [nrhs][n].
+template <typename RM, typename R>
+void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
 
 // Level-1 BLAS (batched over nrhs columns of length n).
 template <typename R>

@@ -444,25 +444,74 @@ __global__ void k_gj_update(z64* __restrict__ M, int n, int k, const z64* __rest
   }
 }
 
-// y = M x for every column; one wavefront per row.
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_dense_apply(const z64* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                          cpx<R>* __restrict__ y, int n) {
-  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const cpx<R>* xb = x + (size_t)blockIdx.y * n;
-  const z64* Mr = M + (size_t)row * n;
-  double re = 0, im = 0;
-  for (int j = lane; j < n; j += 64) {
-    const z64 m = Mr[j];
-    const cpx<R> v = xb[j];
-    re += m.re * v.re - m.im * v.im;
-    im += m.re * v.im + m.im * v.re;
+// Y = M X for nrhs columns (M dense row-major n x n, X and Y [nrhs][n]): the
+// coarsest solve with the explicit inverse.  A workgroup computes a 64-row x
+// 32-column tile; tiles of M (64 x 16) and X (32 x 16) pass through LDS, so M is
+// read once per 32 columns and X once per 64 rows.  Every output accumulates its
+// products in the order j = 0, 1, ..., n-1 with explicit FMAs, so a column's
+// result does not depend on nrhs or on the other columns.
+constexpr int kGemmTR = 64, kGemmTC = 32, kGemmTJ = 16;
+
+template <typename RM, typename R>
+__global__ void __launch_bounds__(kThreads) k_dense_gemm(const cpx<RM>* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                         cpx<R>* __restrict__ y, int n, int nrhs) {
+  __shared__ cpx<RM> Ms[kGemmTJ][kGemmTR + 1];
+  __shared__ cpx<RM> Xs[kGemmTJ][kGemmTC + 1];
+  const int r0 = blockIdx.x * kGemmTR, c0 = blockIdx.y * kGemmTC;
+  const int t = threadIdx.x;
+  const int tr = t & 31, tc = t >> 5;  // rows tr, tr + 32; columns tc + 8k
+  RM are[2][4], aim[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) are[a][k] = aim[a][k] = 0;
+  for (int j0 = 0; j0 < n; j0 += kGemmTJ) {
+#pragma unroll
+    for (int q = 0; q < kGemmTR * kGemmTJ / kThreads; ++q) {
+      const int e = t + q * kThreads;
+      const int row = e / kGemmTJ, jj = e % kGemmTJ;
+      const int gr = r0 + row, gj = j0 + jj;
+      Ms[jj][row] = (gr < n && gj < n) ? M[(size_t)gr * n + gj] : mk<RM>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < kGemmTC * kGemmTJ / kThreads; ++q) {
+      const int e = t + q * kThreads;
+      const int col = e / kGemmTJ, jj = e % kGemmTJ;
+      const int gc = c0 + col, gj = j0 + jj;
+      cpx<RM> v = mk<RM>(0, 0);
+      if (gc < nrhs && gj < n) {
+        const cpx<R> u = x[(size_t)gc * n + gj];
+        v = mk<RM>((RM)u.re, (RM)u.im);
+      }
+      Xs[jj][col] = v;
+    }
+    __syncthreads();
+    const int jn = min(kGemmTJ, n - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      cpx<RM> m[2], v[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) m[a] = Ms[jj][tr + 32 * a];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = Xs[jj][tc + 8 * k];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          are[a][k] = fma(m[a].re, v[k].re, are[a][k]);
+          are[a][k] = fma(-m[a].im, v[k].im, are[a][k]);
+          aim[a][k] = fma(m[a].re, v[k].im, aim[a][k]);
+          aim[a][k] = fma(m[a].im, v[k].re, aim[a][k]);
+        }
+    }
+    __syncthreads();
   }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)re, (R)im);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int gr = r0 + tr + 32 * a, gc = c0 + tc + 8 * k;
+      if (gr < n && gc < nrhs) y[(size_t)gc * n + gr] = mk<R>((R)are[a][k], (R)aim[a][k]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -882,9 +931,10 @@ void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hip
   HIPCHECK(hipGetLastError());
 }
 
-template <typename R>
-void launch_dense_apply(const z64* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_dense_apply<R>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n);
+template <typename RM, typename R>
+void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
+  hipLaunchKernelGGL((k_dense_gemm<RM, R>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs);
   HIPCHECK(hipGetLastError());
 }
 
@@ -923,10 +973,11 @@ void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int n
                                   int, int, int, int, hipStream_t);                                              \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
                                  const cpx<R>*, hipStream_t);                                                    \
-  template void launch_dense_apply<R>(const z64*, const cpx<R>*, cpx<R>*, int, int, hipStream_t);                \
   template void launch_links_convert<R>(const z64*, cpx<R>*, size_t, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
+template void launch_dense_apply<double, double>(const z64*, const z64*, z64*, int, int, hipStream_t);
+template void launch_dense_apply<float, float>(const z32*, const z32*, z32*, int, int, hipStream_t);
 
 }  // namespace smg

@@ -11,6 +11,7 @@
 //   Outer solver   Results section: MG-CG, the V-cycle preconditions CG
 //   Mass reuse     Results section: setup at one mass, vectors reused
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -101,6 +102,7 @@ struct Ctx {
   smg_params prm{};
   int nlev = 0;
   int mfma_pin = -1;                // -1: by mfma_min_rhs; 0 / 1: vector ALU / matrix cores
+  rocblas_handle blas = nullptr;    // GEMMs of the blocked coarsest inversion (setup only)
   hipStream_t st = nullptr;
   Pool pool;
   z64* U64 = nullptr;
@@ -111,6 +113,7 @@ struct Ctx {
   std::vector<z64*> calib;          // smoother calibration start per coarsening
   // dense inverse of the coarsest operator
   z64* Minv = nullptr;
+  z32* Minv32 = nullptr;            // FP32 copy for the mixed solve's V-cycles
   z64* colk = nullptr;
   double* piv = nullptr;
   // per-column scalars on the device: one set per CG nesting depth (the outer
@@ -135,6 +138,7 @@ struct Ctx {
   int64_t vcycles = 0;
 
   ~Ctx() {
+    if (blas) (void)rocblas_destroy_handle(blas);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_int) (void)hipHostFree(h_int);
   }
@@ -265,9 +269,12 @@ void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, 
 template <typename R>
 void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool use_cg) {
   auto& lv = levels_of<R>(c)[l];
-  if (!use_cg && c.Minv && l == c.nlev - 1)
-    launch_dense_apply<R>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
-  else
+  if (!use_cg && c.Minv && l == c.nlev - 1) {
+    if constexpr (std::is_same<R, float>::value)
+      launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st);
+    else
+      launch_dense_apply<double, double>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
+  } else
     coarse_cg<R>(c, l, b, x, nrhs, c.prm.coarsest_tol, c.prm.coarsest_maxiter);
 }
 
@@ -460,13 +467,23 @@ KVecs<double>& coarse_kvecs<double>(Ctx& c) { return c.c64; }
 template <>
 KVecs<float>& coarse_kvecs<float>(Ctx& c) { return c.c32; }
 
+// Relative residual of the coarsest CG inside FP32 V-cycles.
+constexpr double kCoarseTolF32 = 1e-6;
+
 template <typename R>
 void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter) {
   auto& lv = levels_of<R>(c)[l];
   KVecs<R>& v = coarse_kvecs<R>(c);
   ensure_kvecs<R>(c, v, (size_t)nrhs * lv.n);
   ColStats cs;
-  pcg<R>(c, l, b, x, nrhs, tol, maxiter, false, v, &cs, 8, 1);
+  if (std::is_same<R, float>::value) {
+    // Inside the FP32 V-cycle of the mixed solve: FP32 cannot confirm a true
+    // residual below ~1e-7, so stop on the recursive residual at a reachable
+    // tolerance (the outer FP64 iteration corrects what the preconditioner misses).
+    pcg<R>(c, l, b, x, nrhs, std::max(tol, kCoarseTolF32), maxiter, false, v, &cs, 8, 1, false);
+  } else {
+    pcg<R>(c, l, b, x, nrhs, tol, maxiter, false, v, &cs, 8, 1);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -572,6 +589,63 @@ void sa_weight(Ctx& c, int l) {
   lv.sa_w = c.prm.sa_scale / lam;
 }
 
+// In-place inversion of a Hermitian positive definite n x n matrix by blocked
+// Gauss-Jordan elimination without pivoting.  The buffer is taken column-major
+// (B = M^T for the row-major M; inverting B gives inv(M)^T, i.e. inv(M) row-major).
+// Per block column k (width m): P = inv(B_kk) (unblocked steps), R = P B_k*,
+// B -= C R with C = B_*k and its block k zeroed, then row block k = R, column
+// block k = -C P and B_kk = P.  The three products are plain GEMMs (rocBLAS).
+constexpr int kGJBlock = 512;
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  ~DevBuf() { (void)hipFree(p); }
+};
+
+void blas_check(rocblas_status s) {
+  if (s != rocblas_status_success) throw Error(SMG_EDEVICE, std::string("rocBLAS: ") + rocblas_status_to_string(s));
+}
+
+void blocked_gauss_jordan(Ctx& c, z64* B, int n) {
+  if (!c.blas) blas_check(rocblas_create_handle(&c.blas));
+  blas_check(rocblas_set_stream(c.blas, c.st));
+  const int nb = kGJBlock;
+  DevBuf Cb((size_t)n * nb * sizeof(z64)), Rb((size_t)n * nb * sizeof(z64)), Pb((size_t)nb * nb * sizeof(z64));
+  z64* C = static_cast<z64*>(Cb.p);
+  z64* R = static_cast<z64*>(Rb.p);
+  z64* P = static_cast<z64*>(Pb.p);
+  const size_t zs = sizeof(z64);
+  const rocblas_double_complex one = {1.0, 0.0}, mone = {-1.0, 0.0}, zer = {0.0, 0.0};
+  auto zc = [](z64* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
+  for (int kb = 0; kb < n; kb += nb) {
+    const int m = std::min(nb, n - kb);
+    // C = B[:, kb:kb+m] (contiguous columns), P = its diagonal block, then zero that block of C
+    HIPCHECK(hipMemcpyAsync(C, B + (size_t)kb * n, (size_t)n * m * zs, hipMemcpyDeviceToDevice, c.st));
+    HIPCHECK(hipMemcpy2DAsync(P, m * zs, C + kb, (size_t)n * zs, m * zs, m, hipMemcpyDeviceToDevice, c.st));
+    HIPCHECK(hipMemset2DAsync(C + kb, (size_t)n * zs, 0, m * zs, m, c.st));
+    for (int k = 0; k < m; ++k) launch_gj_step(P, m, k, c.colk, c.piv, c.fail, c.st);
+    // R = P B[kb:kb+m, :]
+    blas_check(rocblas_zgemm(c.blas, rocblas_operation_none, rocblas_operation_none, m, n, m, &one, zc(P), m,
+                             zc(B + kb), n, &zer, zc(R), m));
+    // B -= C R (row block kb is untouched: C is zero there)
+    blas_check(rocblas_zgemm(c.blas, rocblas_operation_none, rocblas_operation_none, n, n, m, &mone, zc(C), n,
+                             zc(R), m, &one, zc(B), n));
+    HIPCHECK(hipMemcpy2DAsync(B + kb, (size_t)n * zs, R, m * zs, m * zs, n, hipMemcpyDeviceToDevice, c.st));
+    // B[:, kb:kb+m] = -C P, then its diagonal block = P
+    blas_check(rocblas_zgemm(c.blas, rocblas_operation_none, rocblas_operation_none, n, m, m, &mone, zc(C), n,
+                             zc(P), m, &zer, zc(B + (size_t)kb * n), n));
+    HIPCHECK(hipMemcpy2DAsync(B + (size_t)kb * n + kb, (size_t)n * zs, P, m * zs, m * zs, m, hipMemcpyDeviceToDevice,
+                              c.st));
+  }
+  HIPCHECK(hipStreamSynchronize(c.st));  // the scratch buffers are freed on return
+}
+
 // Dense inverse of the coarsest operator by Gauss-Jordan elimination (FP64).
 void build_coarsest_inverse(Ctx& c) {
   if (c.nlev < 2 || c.prm.coarsest != SMG_COARSEST_DIRECT) return;
@@ -584,7 +658,10 @@ void build_coarsest_inverse(Ctx& c) {
   }
   launch_coarse_to_dense(lv.L, c.Minv, lv.lx, lv.lt, lv.dof, c.st);
   zero(c.fail, sizeof(int), c.st);
-  for (int k = 0; k < n; ++k) launch_gj_step(c.Minv, n, k, c.colk, c.piv, c.fail, c.st);
+  if (n <= kGJBlock)
+    for (int k = 0; k < n; ++k) launch_gj_step(c.Minv, n, k, c.colk, c.piv, c.fail, c.st);
+  else
+    blocked_gauss_jordan(c, c.Minv, n);
   check_fail(c, "coarsest operator is not positive definite");
 }
 
@@ -740,6 +817,11 @@ void ensure_f32(Ctx& c) {
       if (fresh) b.P = c.pool.alloc<z32>(np);
       launch_links_convert<float>(a.P, b.P, np, c.st);
     }
+  }
+  if (c.Minv) {
+    const size_t nn = c.L64[c.nlev - 1].n * c.L64[c.nlev - 1].n;
+    if (!c.Minv32) c.Minv32 = c.pool.alloc<z32>(nn);
+    launch_links_convert<float>(c.Minv, c.Minv32, nn, c.st);
   }
   c.f32_ready = true;
 }

@@ -120,6 +120,8 @@ CASES = [
     (64, 64, [(4, 4), (4, 4)], [6, 6], 0.03, SA),   # fused fine kernel, smoothed on both levels
     (32, 32, [(4, 4), (4, 4)], [4, 4], 0.1, SA),    # coarse extents 8 -> 2 (two colours)
     (20, 20, [(4, 4)], [5], 0.1, SA),               # odd coarse vector length (5 x 5 x 5)
+    (64, 64, [(4, 4)], [8], 0.1, SA),               # coarsest 2048: blocked Gauss-Jordan, 4 blocks
+    (48, 48, [(4, 4)], [7], 0.1, SA),               # coarsest 1008: blocked, ragged last block
 ]
 
 
