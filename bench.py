@@ -4,7 +4,7 @@
 Workload (the precision configuration): 256x256 lattice, quenched U(1) fields at
 beta = 6 (500 Metropolis sweeps, 4 fields, seeds 2000-2003), 5 masses per field at
 lambda_min(A)/lambda_max(A) = 1e-2, 3e-3, 1e-3, 3e-4, 1e-4 (tuned offline, stored in
-workloads/c2_masses.json), 3 levels of 4x4 aggregates with Nv = 12, nu = 4 MR
+workloads/masses_256_beta6.json), 3 levels of 4x4 aggregates with Nv = 12, nu = 4 MR
 smoother (omega 0.8), 5 setup iterations, dense FP64 coarsest inverse, one Gaussian
 right-hand side per field (rhs = D^H b), true residual 1e-10.
 
@@ -55,13 +55,22 @@ SERVE_NV = 8
 SERVE_BUDGET = 200 * 10**9
 SERVE_CAPACITY = 16
 
+# Multi-RHS workload: 32 Z2-noise sources on one 512x512 field at beta = 6 (500
+# sweeps, seed 5000) at the mass where lambda_min(A)/lambda_max(A) = 1e-3, 3 levels of
+# 4x4 aggregates with Nv = 16 (coarse links 16x16 on the matrix cores, dense inverse
+# of the 16384-variable coarsest operator).
+MRHS_L = 512
+MRHS_SEED = 5000
+MRHS_NRHS = 32
+MRHS_NV = [16, 16]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def load_masses():
-    with open(os.path.join(ROOT, "workloads", "c2_masses.json")) as f:
+    with open(os.path.join(ROOT, "workloads", "masses_256_beta6.json")) as f:
         data = json.load(f)
     out = {}
     for fld in data["fields"]:
@@ -136,6 +145,87 @@ def serve_field(spec):
 
     L, beta, seed = spec
     return synth.links_from_angles(synth.metropolis_u1(L, L, beta, SERVE_SWEEPS, seed))
+
+
+def mrhs_field(_=None):
+    import synth
+
+    return synth.links_from_angles(synth.metropolis_u1(MRHS_L, MRHS_L, BETA, SWEEPS, MRHS_SEED))
+
+
+def mrhs_mass():
+    with open(os.path.join(ROOT, "workloads", "masses_512_beta6.json")) as f:
+        data = json.load(f)
+    fld = data["fields"][0]
+    assert fld["L"] == MRHS_L and fld["seed"] == MRHS_SEED and fld["sweeps"] == SWEEPS
+    return fld["masses"][0]["mass"], fld["masses"][0]["ratio"]
+
+
+def mrhs_leg(args, torch, smg, dev, U):
+    """32 right-hand sides on one 512^2 field: mixed (FP32 MG-CG with the matrix-core
+    coarse operator, FP64 defect correction) against plain FP64 MG-CG."""
+    import ctypes
+
+    import numpy as np
+
+    import synth
+
+    mass, ratio = mrhs_mass()
+    n = 2 * MRHS_L * MRHS_L
+    p = smg.make_params(MRHS_L, MRHS_L, mass, levels=3, blocks=[(4, 4), (4, 4)], nv=MRHS_NV,
+                        setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=MRHS_SEED,
+                        sa_scale=SA_SCALE, mfma_min_rhs=16)
+    g = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = smg.Solver(g, p)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    eta = torch.from_numpy(synth.z2_noise((MRHS_NRHS, n), MRHS_SEED + 1)).to(dev)
+    rhs = s.apply_D(eta, dagger=True)
+    x = torch.empty_like(rhs)
+    out = {}
+    for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
+        _, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=x)
+        if code != 0 or max(q["true_relres"] for q in st) > TOL:
+            raise RuntimeError(f"multi-RHS {name} solve did not converge: {st[0]}")
+        torch.cuda.synchronize()
+        reps = max(1, args.mrhs_steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = dict(solves_per_s=MRHS_NRHS / dt, seconds_per_batch=dt,
+                         mean_iterations=float(np.mean([q["iterations"] for q in st])),
+                         max_relres=max(q["true_relres"] for q in st))
+        log(f"multi-RHS {name}: {MRHS_NRHS / dt:.1f} solves/s ({dt * 1e3:.1f} ms per {MRHS_NRHS} RHS)")
+    # matrix-core utilisation of the level-1 coarse operator (128^2 sites, nc = 16, 32 RHS),
+    # HIP events on the stream the kernel runs on
+    cx, ct, nc = s.level_info(1)
+    nl = cx * ct * nc
+    v32 = torch.randn(MRHS_NRHS * nl, dtype=torch.complex64, device=dev)
+    y32 = torch.empty_like(v32)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    lib = smg.load_library()
+    h = s.handle
+    px, py = ctypes.c_void_p(v32.data_ptr()), ctypes.c_void_p(y32.data_ptr())
+    nul = ctypes.c_void_p()
+    dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), 100, stream)
+    flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
+    mfma = dict(kernel=f"coarse operator on the matrix cores (k_coarse_mfma), {cx}x{ct} sites, nc={nc}, "
+                       f"{MRHS_NRHS} RHS, FP32", bound="mfma", achieved=flops / dur / 1e12, peak=157.3,
+                unit="TFLOP/s", frac=flops / dur / 1e12 / 157.3, avg_launch_us=dur * 1e6, flops_per_launch=flops)
+    s.close()
+    del g, eta, rhs, x, v32, y32
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return dict(workload=(f"{MRHS_L}x{MRHS_L} U(1) beta={BETA:g} ({SWEEPS} sweeps, seed {MRHS_SEED}), mass {mass:.5f} "
+                          f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
+                          f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}"),
+                setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
+                mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
 
 
 def serving_leg(args, torch, smg, dev):
@@ -313,6 +403,9 @@ def main():
     ap.add_argument("--serve-lanes", type=int, default=8, help="concurrent (field, mass) lanes")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
+    ap.add_argument("--no-mrhs", action="store_true")
+    ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
+    ap.add_argument("--mrhs-steps", type=int, default=3)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the roofline kernel and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
@@ -336,6 +429,15 @@ def main():
         print(json.dumps(serving_leg(args, torch, smg, torch.device("cuda:0"))))
         return 0
 
+    if args.mrhs_only:
+        import torch
+
+        import paper_0710_3612_amd as smg
+
+        U = mrhs_field()
+        print(json.dumps(mrhs_leg(args, torch, smg, torch.device("cuda:0"), U)))
+        return 0
+
     cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline()
 
     import numpy as np
@@ -345,8 +447,10 @@ def main():
 
     masses = load_masses()
     log("generating gauge fields")
-    with ProcessPoolExecutor(max_workers=len(SEEDS)) as ex:
+    with ProcessPoolExecutor(max_workers=len(SEEDS) + 1) as ex:
+        mrhs_future = None if args.no_mrhs else ex.submit(mrhs_field)
         fields = list(ex.map(make_field, SEEDS))
+        mrhs_U = None if mrhs_future is None else mrhs_future.result()
 
     import torch
 
@@ -468,6 +572,7 @@ def main():
     keep.clear()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    mrhs = None if args.no_mrhs else mrhs_leg(args, torch, smg, dev, mrhs_U)
     serving = None if args.no_serve else serving_leg(args, torch, smg, dev)
 
     cpu = None
@@ -517,6 +622,7 @@ def main():
         "dslash": dslash_2048,
         "dslash_4096": dslash_4096,
         "cpu_baseline": cpu,
+        "multi_rhs": mrhs,
         "serving": serving,
     }
     print(json.dumps(line))

@@ -66,6 +66,9 @@ enum {
 enum { SMG_COARSEST_DIRECT = 0, SMG_COARSEST_CG = 1 };
 enum { SMG_FP64 = 0, SMG_MIXED = 1 };
 
+/* storage of the FP32 V-cycle's fine-level smoother iterates */
+enum { SMG_STORE_F32 = 0, SMG_STORE_BF16 = 1, SMG_STORE_F16 = 2 };
+
 typedef struct smg_ctx* smg_handle;
 typedef struct smg_batch_s* smg_batch;
 
@@ -89,6 +92,10 @@ typedef struct {
                                      the calibration start); 0 = plain aggregation.  Applied
                                      where both block extents are >= 4 and both coarse
                                      extents >= 2 (the coarse operator stays 9-point). */
+  int32_t smoother_storage;       /* mixed precision: storage of the fine-level smoother
+                                     iterates in the FP32 V-cycle, SMG_STORE_F32 / _BF16 /
+                                     _F16 (arithmetic stays FP32; BF16/FP16 need
+                                     lx % 32 == 0 and lt % 16 == 0) */
   int32_t mfma_min_rhs;           /* FP32 coarse applies of at least this many right-hand
                                      sides run on the matrix cores (MFMA FP32, levels with
                                      nc <= 16); 1 = always, 0 = never.  Results differ from
@@ -108,7 +115,7 @@ typedef struct {
 /* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
- * mfma_min_rhs = 16. */
+ * smoother_storage = SMG_STORE_F32, mfma_min_rhs = 16. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
@@ -189,6 +196,11 @@ int smg_smooth(smg_handle h, int32_t level, const double* b, double* x, int32_t 
 /* x = V b, one V-cycle from the finest level (Multigrid section, steps 1-5; Eq. 3
  * with the sign of its R A R^H term taken from those steps).  FP64.  ASYNC. */
 int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream);
+
+/* The FP32 V-cycle of the mixed-precision solve (same steps; FP32 operators, the
+ * fine smoother iterates stored as smoother_storage says): x = V b for complex64
+ * device vectors [nrhs][n].  Errors: SMG_EINVAL. */
+int smg_vcycle_f32(smg_handle h, const float* b, float* x, int32_t nrhs, void* stream);
 
 /* Solve A x = rhs for nrhs independent right-hand sides with MG-CG (Results
  * section).  precision SMG_FP64: FP64 throughout.  SMG_MIXED: FP32 operators,

@@ -28,6 +28,9 @@ __all__ = [
     "MIXED",
     "COARSEST_DIRECT",
     "COARSEST_CG",
+    "STORE_F32",
+    "STORE_BF16",
+    "STORE_F16",
     "library_path",
 ]
 
@@ -36,6 +39,9 @@ FP64 = 0
 MIXED = 1
 COARSEST_DIRECT = 0
 COARSEST_CG = 1
+STORE_F32 = 0
+STORE_BF16 = 1
+STORE_F16 = 2
 
 OK = 0
 NOTCONV = 1
@@ -69,6 +75,7 @@ class Params(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("sa_scale", ctypes.c_double),
+        ("smoother_storage", ctypes.c_int32),
         ("mfma_min_rhs", ctypes.c_int32),
     ]
 
@@ -129,6 +136,7 @@ def load_library():
         "smg_prolong": (i32, [h, i32, P, P, i32, P]),
         "smg_smooth": (i32, [h, i32, P, P, i32, P]),
         "smg_vcycle": (i32, [h, P, P, i32, P]),
+        "smg_vcycle_f32": (i32, [h, P, P, i32, P]),
         "smg_solve": (i32, [h, P, P, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(Stats)]),
         "smg_cg": (i32, [h, P, P, i32, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
         "smg_level_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -169,7 +177,8 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 nv: Sequence[int] = (8,), setup_iters: int = 5, smoother_steps: int = 4,
                 smoother_omega: float = 0.8, t_antiperiodic: bool = True, coarsest: int = COARSEST_DIRECT,
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
-                seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16) -> Params:
+                seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16,
+                smoother_storage: int = STORE_F32) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -188,6 +197,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.seed = seed
     p.sa_scale = sa_scale
     p.mfma_min_rhs = mfma_min_rhs
+    p.smoother_storage = smoother_storage
     return p
 
 
@@ -361,6 +371,17 @@ class Solver:
         nr = self._nrhs(b, self.level_size(0))
         x = self._new(b.shape, b)
         _check(self.lib.smg_vcycle(self.handle, _ptr(b), _ptr(x), nr, _stream(stream)))
+        return x
+
+    def vcycle_f32(self, b, stream=None):
+        """The mixed solve's FP32 V-cycle (complex64 in/out)."""
+        if not (b.is_cuda and b.dtype == self._torch.complex64):
+            raise TypeError("expected a complex64 CUDA tensor")
+        b = b.contiguous()
+        nr = self._nrhs(b, self.level_size(0))
+        x = self._torch.empty_like(b)
+        _check(self.lib.smg_vcycle_f32(self.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                       nr, _stream(stream)))
         return x
 
     # -- solvers ------------------------------------------------------------------

@@ -102,6 +102,13 @@ __global__ void k_axpy_const(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ 
     y[off + i] = y[off + i] + a * x[off + i];
 }
 
+template <typename TI>
+__global__ void k_axpy_const_lp(z32* __restrict__ y, const TI* __restrict__ x, float a, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[off + i] = y[off + i] + a * ldv(x, off + i);
+}
+
 template <typename R>
 __global__ void k_sub(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, cpx<R>* __restrict__ y, size_t n) {
   const size_t off = (size_t)blockIdx.y * n;
@@ -233,6 +240,14 @@ void launch_axpy_const(cpx<R>* y, const cpx<R>* x, double a, size_t n, int nrhs,
   hipLaunchKernelGGL((k_axpy_const<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, y, x, (R)a, n);
   HIPCHECK(hipGetLastError());
 }
+
+template <typename TI>
+void launch_axpy_const_lp(z32* y, const TI* x, double a, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_const_lp<TI>), ew_grid(n, nrhs), dim3(kThreads), 0, st, y, x, (float)a, n);
+  HIPCHECK(hipGetLastError());
+}
+template void launch_axpy_const_lp<bfc>(z32*, const bfc*, double, size_t, int, hipStream_t);
+template void launch_axpy_const_lp<hfc>(z32*, const hfc*, double, size_t, int, hipStream_t);
 
 template <typename R>
 void launch_sub(const cpx<R>* a, const cpx<R>* b, cpx<R>* y, size_t n, int nrhs, hipStream_t st) {

@@ -61,6 +61,36 @@ __host__ __device__ inline cpx<Ro> cvt(cpx<Ri> a) { return mk((Ro)a.re, (Ro)a.im
 using z64 = cpx<double>;
 using z32 = cpx<float>;
 
+// 4-byte complex storage for the fine-level smoother iterates of the FP32 V-cycle
+// (BF16 or FP16 halves; all arithmetic stays FP32).
+struct alignas(4) bfc { __bf16 re, im; };
+struct alignas(4) hfc { _Float16 re, im; };
+
+template <typename R>
+__device__ inline cpx<R> ldv(const cpx<R>* p, size_t i) { return p[i]; }
+__device__ inline z32 ldv(const bfc* p, size_t i) {
+  const bfc t = p[i];
+  return mk((float)t.re, (float)t.im);
+}
+__device__ inline z32 ldv(const hfc* p, size_t i) {
+  const hfc t = p[i];
+  return mk((float)t.re, (float)t.im);
+}
+template <typename R>
+__device__ inline void stv(cpx<R>* p, size_t i, cpx<R> v) { p[i] = v; }
+__device__ inline void stv(bfc* p, size_t i, z32 v) {
+  bfc t;
+  t.re = (__bf16)v.re;
+  t.im = (__bf16)v.im;
+  p[i] = t;
+}
+__device__ inline void stv(hfc* p, size_t i, z32 v) {
+  hfc t;
+  t.re = (_Float16)v.re;
+  t.im = (_Float16)v.im;
+  p[i] = t;
+}
+
 // Error raised inside the library and turned into a return code at the C boundary.
 struct Error : std::runtime_error {
   int code;
@@ -105,6 +135,19 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
                    int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+
+// FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
+// (lx and lt multiples of 16).
+template <typename TI, typename TO>
+void launch_normal_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
+                      z32* xacc, const z32* aux, hipStream_t st);
+bool normal_lp_fits(int lx, int lt);
+// P^H x for a fine vector stored as TI; x += a y for y stored as TI.
+template <typename TI>
+void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h, int nc,
+                        int ldk, int nrhs, hipStream_t st);
+template <typename TI>
+void launch_axpy_const_lp(z32* y, const TI* x, double a, size_t n, int nrhs, hipStream_t st);
 
 // Coarse 9-point operator on level with extents (cx, ct), nc dof; links [9][nc][K][nc].
 template <typename R>

@@ -60,8 +60,8 @@ __device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
 // The result goes to out[k * ostride_k] (plain restriction or a column of the
 // Galerkin links).
 // ---------------------------------------------------------------------------
-template <typename R, int NCH>
-__device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x, int K, int lx,
+template <typename R, int NCH, typename TX = cpx<R>>
+__device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __restrict__ x, int K, int lx,
                                     int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
                                     cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1) {
   const int lane = threadIdx.x & 63;
@@ -70,7 +70,7 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* 
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = lane + 64 * c;
-    xv[c] = (i < nagg) ? x[win_index(K, i, lx, lt, dof, bx, bt, cx, h)] : mk<R>(0, 0);
+    xv[c] = (i < nagg) ? ldv(x, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<R>(0, 0);
   }
   const cpx<R>* PK = P + (size_t)K * ldk * nagg;
   for (int k = kbeg; k < nc; k += kstep) {
@@ -91,8 +91,8 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const cpx<R>* 
 }
 
 // One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...
-template <typename R, int NCH>
-__global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ x,
+template <typename R, int NCH, typename TX = cpx<R>>
+__global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const TX* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
                                                        int bt, int h, int nc, int ldk) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
@@ -100,8 +100,8 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict_
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
   const int rhs = blockIdx.y;
-  restrict_one<R, NCH>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
-                       y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
+  restrict_one<R, NCH, TX>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                           y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
 }
 
 // Prolongation y (+)= P e in two deterministic phases.
@@ -607,6 +607,23 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
   });
   HIPCHECK(hipGetLastError());
 }
+
+template <typename TI>
+void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h, int nc,
+                        int ldk, int nrhs, hipStream_t st) {
+  const int nK = (lx / bx) * (lt / bt);
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  dim3 grid(nK, nrhs);
+  dispatch_chunks((nw + 63) / 64, [&](auto c) {
+    hipLaunchKernelGGL((k_restrict<float, decltype(c)::v, TI>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof,
+                       bx, bt, h, nc, ldk);
+  });
+  HIPCHECK(hipGetLastError());
+}
+template void launch_restrict_lp<bfc>(const z32*, const bfc*, z32*, int, int, int, int, int, int, int, int, int,
+                                      hipStream_t);
+template void launch_restrict_lp<hfc>(const z32*, const hfc*, z32*, int, int, int, int, int, int, int, int, int,
+                                      hipStream_t);
 
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,

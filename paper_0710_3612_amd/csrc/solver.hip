@@ -84,6 +84,7 @@ struct Level {
   int cap = 0;
   cpx<R>*b = nullptr, *x = nullptr, *r = nullptr, *t = nullptr, *tmp = nullptr;
   cpx<R>* wbuf = nullptr;           // prolongation scratch, cap * nK * nw values
+  void *r_lp = nullptr, *t_lp = nullptr;  // BF16/FP16 smoother iterates (FP32 fine level), cap columns
   size_t nkw() const { return bx ? (size_t)(lx / bx) * (lt / bt) * (bx + 2 * halo) * (bt + 2 * halo) * dof : 0; }
 };
 
@@ -191,6 +192,10 @@ void ensure_level_work(Ctx& c, int nrhs) {
     lv.t = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
     if (lv.fine) lv.tmp = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
     if (lv.bx) lv.wbuf = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.nkw());
+    if (std::is_same<R, float>::value && lv.fine && c.prm.smoother_storage != SMG_STORE_F32) {
+      lv.r_lp = c.pool.alloc<uint32_t>((size_t)nrhs * lv.n);  // 4-byte complex entries
+      lv.t_lp = c.pool.alloc<uint32_t>((size_t)nrhs * lv.n);
+    }
   }
 }
 
@@ -278,6 +283,9 @@ void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool us
     coarse_cg<R>(c, l, b, x, nrhs, c.prm.coarsest_tol, c.prm.coarsest_maxiter);
 }
 
+template <typename S>
+void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_cg);
+
 // One V-cycle on level l (steps 1-5 of the Multigrid section); `last` is the level
 // solved exactly.  b is read only; x receives V b.
 template <typename R>
@@ -286,6 +294,16 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   if (l == last) {
     coarsest_solve<R>(c, l, b, x, nrhs, use_cg);
     return;
+  }
+  if constexpr (std::is_same<R, float>::value) {
+    if (l == 0 && c.prm.smoother_storage == SMG_STORE_BF16) {
+      vcycle_fine_lp<bfc>(c, last, b, x, nrhs, use_cg);
+      return;
+    }
+    if (l == 0 && c.prm.smoother_storage == SMG_STORE_F16) {
+      vcycle_fine_lp<hfc>(c, last, b, x, nrhs, use_cg);
+      return;
+    }
   }
   Level<R>& lv = Ls[l];
   Level<R>& nx = Ls[l + 1];
@@ -319,6 +337,49 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
     }
   }
   if (l == 0) c.vcycles += nrhs;
+}
+
+// The FP32 V-cycle's fine level with the smoother iterates stored as S (BF16 or
+// FP16): the same steps as vcycle, with every residual iterate r_k written and
+// read in S while x, b and all arithmetic stay FP32.
+template <typename S>
+void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_cg) {
+  Level<float>& lv = c.L32[0];
+  Level<float>& nx = c.L32[1];
+  const int nu = (int)lv.coefs.size();
+  S* bufs[2] = {static_cast<S*>(lv.r_lp), static_cast<S*>(lv.t_lp)};
+  // 1. pre-smoothing from x = 0
+  zero(x, (size_t)nrhs * lv.n * sizeof(z32), c.st);
+  launch_normal_lp<z32, S>(lv.U, b, bufs[0], lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[0], x, nullptr, c.st);
+  const S* cur = bufs[0];
+  for (int k = 1; k < nu; ++k) {
+    S* nxt = bufs[k & 1];
+    launch_normal_lp<S, S>(lv.U, cur, nxt, lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[k], x, nullptr, c.st);
+    cur = nxt;
+  }
+  c.fine_applies += (int64_t)nrhs * nu;
+  // 2. r_c = P^H (b - A x)
+  launch_restrict_lp<S>(lv.P, cur, nx.b, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
+  // 3. e = V^(1) r_c
+  vcycle<float>(c, 1, last, nx.b, nx.x, nrhs, use_cg);
+  // 4. x = x + P e
+  prolong_from<float>(c, lv, nx.x, x, nrhs, 1);
+  // 5. x = x + R (b - A x)
+  launch_normal_lp<z32, S>(lv.U, x, bufs[0], lv.lx, lv.lt, lv.diag, nrhs, 2, 0.0, nullptr, b, c.st);
+  c.fine_applies += nrhs;
+  cur = bufs[0];
+  S* pb[2] = {bufs[1], bufs[0]};
+  for (int k = 0; k < nu; ++k) {
+    if (k + 1 < nu) {
+      S* nxt = pb[k & 1];
+      launch_normal_lp<S, S>(lv.U, cur, nxt, lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[k], x, nullptr, c.st);
+      c.fine_applies += nrhs;
+      cur = nxt;
+    } else {
+      launch_axpy_const_lp<S>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
+    }
+  }
+  c.vcycles += nrhs;
 }
 
 // ---------------------------------------------------------------------------
@@ -713,6 +774,10 @@ void validate(const smg_params& p) {
   if (!std::isfinite(p.mass)) throw Error(SMG_EINVAL, "mass must be finite");
   if (p.coarsest != SMG_COARSEST_DIRECT && p.coarsest != SMG_COARSEST_CG) throw Error(SMG_EINVAL, "bad coarsest");
   if (!(p.sa_scale >= 0) || !std::isfinite(p.sa_scale)) throw Error(SMG_EINVAL, "sa_scale must be >= 0");
+  if (p.smoother_storage < SMG_STORE_F32 || p.smoother_storage > SMG_STORE_F16)
+    throw Error(SMG_EINVAL, "bad smoother_storage");
+  if (p.smoother_storage != SMG_STORE_F32 && (p.levels < 2 || !normal_lp_fits(p.lx, p.lt)))
+    throw Error(SMG_EINVAL, "BF16/FP16 smoother storage needs levels >= 2, lx % 32 == 0 and lt % 16 == 0");
   int lx = p.lx, lt = p.lt, dof = 2;
   for (int l = 0; l + 1 < p.levels; ++l) {
     const int bx = p.block[l][0], bt = p.block[l][1];
@@ -1310,6 +1375,19 @@ int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* str
   c->st = (hipStream_t)stream;
   ensure_level_work<double>(*c, nrhs);
   vcycle<double>(*c, 0, c->nlev - 1, (const z64*)b, (z64*)x, nrhs, c->prm.coarsest == SMG_COARSEST_CG);
+  return SMG_OK;
+  API_END
+}
+
+int smg_vcycle_f32(smg_handle h, const float* b, float* x, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!x || !b) throw Error(SMG_EINVAL, "null vector");
+  c->st = (hipStream_t)stream;
+  ensure_f32(*c);
+  ensure_level_work<float>(*c, nrhs);
+  vcycle<float>(*c, 0, c->nlev - 1, (const z32*)b, (z32*)x, nrhs, c->prm.coarsest == SMG_COARSEST_CG);
   return SMG_OK;
   API_END
 }

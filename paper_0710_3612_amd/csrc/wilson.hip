@@ -12,6 +12,8 @@
 // antiperiodic-t sign folded into mu = 1, t = lt - 1.  One thread per site; the
 // four neighbours of consecutive threads are consecutive, so every load is
 // coalesced.
+#include <type_traits>
+
 #include "common.h"
 
 namespace smg {
@@ -162,9 +164,9 @@ __device__ inline int fused_tile(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <typename R, int TX, int TT, int MODE, bool NT>
-__global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const cpx<R>* __restrict__ x,
-                                                           cpx<R>* __restrict__ y, int lx, int lt, R diag, R c,
+template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>>
+__global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
+                                                           TO* __restrict__ y, int lx, int lt, R diag, R c,
                                                            cpx<R>* __restrict__ xacc,
                                                            const cpx<R>* __restrict__ aux) {
   constexpr int HX = TX + 2, HT = TT + 2;
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const int tile = fused_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
   const size_t off = (size_t)blockIdx.y * 2 * V;
-  const cpx<R>* __restrict__ xb = x + off;
+  const TI* __restrict__ xb = x + off;
 
   // ---- stage psi (tile + halo) ----------------------------------------------
   for (int i = threadIdx.x; i < HT * HX * 2; i += kThreads) {
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
     int gx = x0 + hx - 1, gt = t0 + ht - 1;
     gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
     gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
-    sp[i] = xb[2 * (gt * lx + gx) + comp];
+    sp[i] = ldv(xb, 2 * (gt * lx + gx) + comp);
   }
   __syncthreads();
 
@@ -301,23 +303,24 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
     const cpx<R> o1 = diag * f1[k] - half * s1;
     const size_t i0 = off + 2 * (size_t)s, i1 = i0 + 1;
     if (MODE == 0) {
-      if (NT) {  // streaming output: keep it out of the caches
+      if constexpr (NT && std::is_same<TO, cpx<R>>::value) {  // streaming output: keep it out of the caches
         __builtin_nontemporal_store(o0.re, &y[i0].re);
         __builtin_nontemporal_store(o0.im, &y[i0].im);
         __builtin_nontemporal_store(o1.re, &y[i1].re);
         __builtin_nontemporal_store(o1.im, &y[i1].im);
       } else {
-        y[i0] = o0; y[i1] = o1;
+        stv(y, i0, o0);
+        stv(y, i1, o1);
       }
     } else if (MODE == 1) {
       const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
       xacc[i0] = xacc[i0] + c * v0;
       xacc[i1] = xacc[i1] + c * v1;
-      y[i0] = v0 - c * o0;
-      y[i1] = v1 - c * o1;
+      stv(y, i0, v0 - c * o0);
+      stv(y, i1, v1 - c * o1);
     } else {
-      y[i0] = aux[i0] - o0;
-      y[i1] = aux[i1] - o1;
+      stv(y, i0, aux[i0] - o0);
+      stv(y, i1, aux[i1] - o1);
     }
   }
 }
@@ -435,6 +438,40 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
   }
   HIPCHECK(hipGetLastError());
 }
+
+template <int TX, int TT, typename TI, typename TO>
+void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
+                     z32* xacc, const z32* aux, hipStream_t st) {
+  dim3 grid((lx / TX) * (lt / TT), nrhs);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 0, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
+                       lt, (float)diag, (float)c, xacc, aux);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 1, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
+                       lt, (float)diag, (float)c, xacc, aux);
+  else
+    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 2, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
+                       lt, (float)diag, (float)c, xacc, aux);
+  HIPCHECK(hipGetLastError());
+}
+
+bool normal_lp_fits(int lx, int lt) { return lx % 32 == 0 && lt % 16 == 0; }
+
+template <typename TI, typename TO>
+void launch_normal_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
+                      z32* xacc, const z32* aux, hipStream_t st) {
+  if (!normal_lp_fits(lx, lt)) throw Error(-1, "reduced-precision smoother storage needs lx % 32 == 0, lt % 16 == 0");
+  launch_fused_lp<32, 16>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st);
+}
+
+#define INST_LP(TI, TO)                                                                                          \
+  template void launch_normal_lp<TI, TO>(const z32*, const TI*, TO*, int, int, double, int, int, double, z32*,   \
+                                         const z32*, hipStream_t);
+INST_LP(z32, bfc)
+INST_LP(bfc, bfc)
+INST_LP(z32, hfc)
+INST_LP(hfc, hfc)
+#undef INST_LP
 
 template <typename R>
 void launch_prepare_links(const z64* gauge, cpx<R>* U, int lx, int lt, int antiperiodic, hipStream_t st) {

@@ -41,7 +41,7 @@ def c_layout():
     fields = {
         "smg_params": ["lx", "lt", "mass", "levels", "block", "nv", "setup_iters", "smoother_steps",
                        "smoother_omega", "t_antiperiodic", "coarsest", "coarsest_tol", "coarsest_maxiter",
-                       "inner_tol", "seed", "sa_scale", "mfma_min_rhs"],
+                       "inner_tol", "seed", "sa_scale", "smoother_storage", "mfma_min_rhs"],
         "smg_stats": ["status", "iterations", "refinements", "vcycles", "fine_applies", "true_relres", "seconds"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {", 'printf("{");']
@@ -102,3 +102,16 @@ def test_setup_rejects_bad_shapes_without_touching_the_device():
     p = smg.make_params(32, 32, float("nan"))
     assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
     assert lib.smg_setup(None, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+
+
+def test_reduced_smoother_storage_rejected_where_no_tile_fits():
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    p = smg.make_params(48, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4], smoother_storage=smg.STORE_BF16)
+    assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+    assert "lx % 32" in lib.smg_last_error().decode()
+    p = smg.make_params(64, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4], smoother_storage=7)
+    assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1

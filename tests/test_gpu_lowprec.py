@@ -1,0 +1,93 @@
+"""GPU: the FP32 V-cycle of the mixed solve, with the fine smoother iterates
+stored in FP32, BF16 or FP16, against the oracle's FP64 V-cycle; and mixed
+solves with each storage reaching the 1e-10 true residual of the FP64 oracle.
+
+Bounds for the V-cycle output (max-norm relative to the largest entry): FP32
+rounding of a few hundred accumulated products stays far below 1e-4.  BF16 keeps
+8 significant bits (unit roundoff 2^-9 = 2.0e-3) and FP16 11 (2^-12 = 2.4e-4);
+2 nu = 8 smoother iterates are rounded per V-cycle and the coarse correction
+carries the rounding of the restricted residual, so 8 u times a margin of 3 gives
+5e-2 (BF16) and 6e-3 (FP16).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import multigrid as mg
+from oracle.wilson import dirac_matrix, normal_matrix
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {0: 1e-4, 1: 5e-2, 2: 6e-3}
+
+
+def dev(x, dtype=np.complex128):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0710_3612_amd as smg
+
+    lx, lt, m = 64, 32, 0.05
+    blocks, nvs = [(4, 4), (2, 2)], [6, 6]
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 20, 314))
+    shapes = synth.level_shapes(lx, lt, blocks, nvs)
+    vecs, calib = [], []
+    for l, nv in enumerate(nvs):
+        cx, ct, dof = shapes[l]
+        vecs.append(synth.gaussian((nv, cx * ct * dof), 600 + l))
+        calib.append(synth.gaussian(cx * ct * dof, 650 + l))
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=4 / 3)
+    vv = dev(np.concatenate([v.ravel() for v in vecs]))
+    cc = dev(np.concatenate(calib))
+    solvers = {}
+    for st in (smg.STORE_F32, smg.STORE_BF16, smg.STORE_F16):
+        p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, smoother_storage=st)
+        solvers[st] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    yield dict(U=U, A=A, h=h, m=m, n=2 * lx * lt, s=solvers)
+    for s in solvers.values():
+        s.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_fp32_vcycle_with_storage(lp, storage):
+    nrhs = 3
+    b = synth.gaussian((nrhs, lp["n"]), 77).astype(np.complex64)
+    x = host(lp["s"][storage].vcycle_f32(dev(b, np.complex64))).reshape(nrhs, -1)
+    for j in range(nrhs):
+        ref = mg.vcycle(lp["h"], 0, b[j].astype(np.complex128))
+        err = np.max(np.abs(x[j] - ref)) / np.max(np.abs(ref))
+        assert err <= BOUND[storage], (storage, j, err)
+        if storage == 0:
+            assert err <= 1e-4
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_mixed_solve_with_reduced_storage(lp, storage):
+    import paper_0710_3612_amd as smg
+
+    A = lp["A"]
+    n = lp["n"]
+    D = dirac_matrix(lp["U"], lp["m"])
+    B = np.stack([D.conj().T @ v for v in synth.gaussian((4, n), 88)])
+    x, st, code = lp["s"][storage].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.MIXED)
+    assert code == 0
+    xh = host(x).reshape(4, n)
+    _, st32, _ = lp["s"][0].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.MIXED)
+    for j in range(4):
+        assert np.linalg.norm(B[j] - A @ xh[j]) / np.linalg.norm(B[j]) <= 1e-10
+        # the cheaper smoother may cost iterations, not convergence
+        assert st[j]["iterations"] <= 2 * st32[j]["iterations"] + 5

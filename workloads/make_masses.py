@@ -13,7 +13,11 @@ with the FP64 oracle's sparse D and A:
      the field is gapped and r is out of reach, m* is used and the reached ratio
      is recorded.
 
-Usage: python -m workloads.make_masses  (writes workloads/c2_masses.json)
+For the 512^2 lattice (one field, one target) the scan and the bisection run as
+8-point parallel searches instead: each LU of D takes most of a minute there.
+
+Usage: python -m workloads.make_masses [256_beta6 | 512_beta6]
+       (writes workloads/masses_<name>.json)
 """
 
 from __future__ import annotations
@@ -34,8 +38,11 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 from oracle.wilson import dirac_matrix  # noqa: E402
 
-C2 = dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
-          ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4])
+CONFIGS = {
+    "256_beta6": dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
+                      ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4]),
+    "512_beta6": dict(L=512, beta=6.0, sweeps=500, seeds=[5000], ratios=[1e-3]),
+}
 
 _FIELDS = {}
 
@@ -116,21 +123,66 @@ def bisect_target(args):
     return dict(target=target, mass=hi, ratio=mn / mx, reached=True)
 
 
+def _lmin_job(args):
+    L, beta, sweeps, seed, m = args
+    U = synth.links_from_angles(field(L, beta, sweeps, seed))
+    return extremes(U, m)
+
+
+def parallel_field(cfg, seed, ex, width=8):
+    """m* by nested 8-point grids, then each target ratio by 8-ary search."""
+    L, beta, sweeps = cfg["L"], cfg["beta"], cfg["sweeps"]
+    lo, hi = -0.3, 0.1
+    best = None
+    for _ in range(3):
+        grid = list(np.linspace(lo, hi, width))
+        vals = list(ex.map(_lmin_job, [(L, beta, sweeps, seed, float(m)) for m in grid]))
+        i = int(np.argmin([v[0] for v in vals]))
+        best = (grid[i], vals[i])
+        step = grid[1] - grid[0]
+        lo, hi = grid[i] - step, grid[i] + step
+    mstar, (mn0, mx0) = best
+    th = field(L, beta, sweeps, seed)
+    out = dict(seed=seed, m_star=mstar, lambda_min=mn0, lambda_max=mx0, plaquette=synth.mean_plaquette(th),
+               topological_charge=round(synth.topological_charge(th)), masses=[])
+    for target in cfg["ratios"]:
+        if mn0 / mx0 >= target:
+            out["masses"].append(dict(target=target, mass=mstar, ratio=mn0 / mx0, reached=False))
+            continue
+        lo, hi = mstar, mstar + 0.2
+        res = None
+        for _ in range(3):
+            grid = list(np.linspace(lo, hi, width + 2))[1:-1]
+            vals = list(ex.map(_lmin_job, [(L, beta, sweeps, seed, float(m)) for m in grid]))
+            above = [k for k, v in enumerate(vals) if v[0] / v[1] > target]
+            k = above[0] if above else len(grid) - 1
+            res = (grid[k], vals[k])
+            lo, hi = (grid[k - 1] if k > 0 else lo), grid[k]
+        m, (mn, mx) = res
+        out["masses"].append(dict(target=target, mass=m, ratio=mn / mx, reached=mn / mx > target))
+    return out
+
+
 def main():
-    cfg = C2
+    name = sys.argv[1] if len(sys.argv) > 1 else "256_beta6"
+    cfg = CONFIGS[name]
     t0 = time.time()
     base = [(cfg["L"], cfg["beta"], cfg["sweeps"], s) for s in cfg["seeds"]]
     with ProcessPoolExecutor(max_workers=8) as ex:
-        stars = list(ex.map(find_mstar, base))
-        jobs = [(cfg["L"], cfg["beta"], cfg["sweeps"], st["seed"], st["m_star"], st["lambda_min"] / st["lambda_max"], r)
-                for st in stars for r in cfg["ratios"]]
-        res = list(ex.map(bisect_target, jobs))
-    fields = []
-    for k, st in enumerate(stars):
-        fld = dict(st, L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
-        fld["masses"] = res[k * len(cfg["ratios"]):(k + 1) * len(cfg["ratios"])]
-        fields.append(fld)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_masses.json")
+        if cfg["L"] <= 256:
+            stars = list(ex.map(find_mstar, base))
+            jobs = [(cfg["L"], cfg["beta"], cfg["sweeps"], st["seed"], st["m_star"],
+                     st["lambda_min"] / st["lambda_max"], r) for st in stars for r in cfg["ratios"]]
+            res = list(ex.map(bisect_target, jobs))
+            fields = []
+            for k, st in enumerate(stars):
+                fld = dict(st, L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
+                fld["masses"] = res[k * len(cfg["ratios"]):(k + 1) * len(cfg["ratios"])]
+                fields.append(fld)
+        else:
+            fields = [dict(parallel_field(cfg, s, ex), L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
+                      for s in cfg["seeds"]]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"masses_{name}.json")
     with open(path, "w") as f:
         json.dump(dict(config=cfg, fields=fields, seconds=time.time() - t0), f, indent=1)
     print(path)
