@@ -58,7 +58,8 @@ SERVE_CAPACITY = 16
 # Multi-RHS workload: 32 Z2-noise sources on one 512x512 field at beta = 6 (500
 # sweeps, seed 5000) at the mass where lambda_min(A)/lambda_max(A) = 1e-3, 3 levels of
 # 4x4 aggregates with Nv = 16 (coarse links 16x16 on the matrix cores, dense inverse
-# of the 16384-variable coarsest operator).
+# of the 16384-variable coarsest operator, BF16 storage of the fine smoother iterates
+# in the mixed solve).
 MRHS_L = 512
 MRHS_SEED = 5000
 MRHS_NRHS = 32
@@ -174,7 +175,7 @@ def mrhs_leg(args, torch, smg, dev, U):
     n = 2 * MRHS_L * MRHS_L
     p = smg.make_params(MRHS_L, MRHS_L, mass, levels=3, blocks=[(4, 4), (4, 4)], nv=MRHS_NV,
                         setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=MRHS_SEED,
-                        sa_scale=SA_SCALE, mfma_min_rhs=16)
+                        sa_scale=SA_SCALE, mfma_min_rhs=16, smoother_storage=smg.STORE_BF16)
     g = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -223,7 +224,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     torch.cuda.empty_cache()
     return dict(workload=(f"{MRHS_L}x{MRHS_L} U(1) beta={BETA:g} ({SWEEPS} sweeps, seed {MRHS_SEED}), mass {mass:.5f} "
                           f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
-                          f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}"),
+                          f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}; mixed: FP32 inner "
+                          f"MG-CG, BF16 storage of the fine smoother iterates, coarse links on the matrix cores"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
 

@@ -284,6 +284,13 @@ int smg_batch_harvest(smg_batch b, int32_t slot, double* x, void* stream);
 /* Free a slot whether or not it has finished (the other slots are unaffected). */
 int smg_batch_cancel(smg_batch b, int32_t slot, void* stream);
 
+/* Replay each iteration's device work as a captured HIP graph (enable = 1) or
+ * launch it kernel by kernel (0, the default).  One graph is captured per number
+ * of leading occupied slots and kept until the handle's operators change; results
+ * are bitwise identical either way.  Errors: SMG_EINVAL (graphs with a CG coarsest
+ * solve, which synchronises with the host). */
+int smg_batch_use_graphs(smg_batch b, int32_t enable);
+
 /* Device bytes held by the batch (in addition to its handle). */
 int smg_batch_memory_bytes(smg_batch b, size_t* bytes);
 

@@ -153,6 +153,7 @@ def load_library():
         "smg_batch_harvest": (i32, [h, i32, P, P]),
         "smg_batch_cancel": (i32, [h, i32, P]),
         "smg_batch_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_batch_use_graphs": (i32, [h, i32]),
         "smg_batch_destroy": (None, [h]),
         "smg_destroy": (None, [h]),
         "smg_strerror": (ctypes.c_char_p, [i32]),
@@ -527,3 +528,7 @@ class Batch:
         b = ctypes.c_size_t()
         _check(self.lib.smg_batch_memory_bytes(self.handle, ctypes.byref(b)))
         return b.value
+
+    def use_graphs(self, enable: bool):
+        """Replay iterations as captured HIP graphs (default with a direct coarsest solve) or not."""
+        _check(self.lib.smg_batch_use_graphs(self.handle, int(bool(enable))))

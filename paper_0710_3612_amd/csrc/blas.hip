@@ -7,6 +7,8 @@
 // pass adds the block partials in a fixed order.  Sums are accumulated in FP64
 // for FP32 vectors too.  Krylov scalars live on the device, so the CG loop needs
 // no host round trip except the convergence check.
+#include <algorithm>
+
 #include "common.h"
 
 namespace smg {
@@ -100,6 +102,12 @@ __global__ void k_axpy_const(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ 
   const size_t off = (size_t)blockIdx.y * n;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[off + i] = y[off + i] + a * x[off + i];
+}
+
+// Zero fill with a kernel (memset nodes are avoided where a caller may capture a graph).
+__global__ void k_zero(unsigned long long* __restrict__ p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 template <typename TI>
@@ -238,6 +246,15 @@ void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int n
 template <typename R>
 void launch_axpy_const(cpx<R>* y, const cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL((k_axpy_const<R>), ew_grid(n, nrhs), dim3(kThreads), 0, st, y, x, (R)a, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes % 8 != 0) throw Error(-1, "launch_zero needs a multiple of 8 bytes");
+  const size_t words = bytes / 8;
+  if (words == 0) return;
+  const unsigned blocks = (unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(kThreads), 0, st, static_cast<unsigned long long*>(p), words);
   HIPCHECK(hipGetLastError());
 }
 

@@ -148,6 +148,8 @@ void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int d
                         int ldk, int nrhs, hipStream_t st);
 template <typename TI>
 void launch_axpy_const_lp(z32* y, const TI* x, double a, size_t n, int nrhs, hipStream_t st);
+// Zero fill by a kernel (bytes a multiple of 8).
+void launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // Coarse 9-point operator on level with extents (cx, ct), nc dof; links [9][nc][K][nc].
 template <typename R>

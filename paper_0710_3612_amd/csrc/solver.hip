@@ -103,6 +103,7 @@ struct Ctx {
   smg_params prm{};
   int nlev = 0;
   int mfma_pin = -1;                // -1: by mfma_min_rhs; 0 / 1: vector ALU / matrix cores
+  uint64_t gen = 0;                 // bumped whenever operators or coefficients change (captured graphs)
   rocblas_handle blas = nullptr;    // GEMMs of the blocked coarsest inversion (setup only)
   hipStream_t st = nullptr;
   Pool pool;
@@ -252,7 +253,7 @@ void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, in
 // x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).
 template <typename R>
 void smooth(Ctx& c, Level<R>& lv, const cpx<R>* b, cpx<R>* x, int nrhs) {
-  zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
   const int nu = (int)lv.coefs.size();
   const cpx<R>* cur = b;
   cpx<R>* bufs[2] = {lv.r, lv.t};
@@ -309,7 +310,7 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   Level<R>& nx = Ls[l + 1];
   const int nu = (int)lv.coefs.size();
   // 1. x = R^H b (= R b: the polynomial is real), tracking r = b - A x
-  zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
   const cpx<R>* cur = b;
   cpx<R>* bufs[2] = {lv.r, lv.t};
   for (int k = 0; k < nu; ++k) {
@@ -349,7 +350,7 @@ void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_c
   const int nu = (int)lv.coefs.size();
   S* bufs[2] = {static_cast<S*>(lv.r_lp), static_cast<S*>(lv.t_lp)};
   // 1. pre-smoothing from x = 0
-  zero(x, (size_t)nrhs * lv.n * sizeof(z32), c.st);
+  launch_zero(x, (size_t)nrhs * lv.n * sizeof(z32), c.st);
   launch_normal_lp<z32, S>(lv.U, b, bufs[0], lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[0], x, nullptr, c.st);
   const S* cur = bufs[0];
   for (int k = 1; k < nu; ++k) {
@@ -889,11 +890,13 @@ void ensure_f32(Ctx& c) {
     launch_links_convert<float>(c.Minv, c.Minv32, nn, c.st);
   }
   c.f32_ready = true;
+  ++c.gen;
 }
 
 void finish_setup(Ctx& c) {
   build_coarsest_inverse(c);
   c.f32_ready = false;
+  ++c.gen;
   sync(c);
 }
 
@@ -970,7 +973,25 @@ struct Batch {
   std::vector<int> used, act, its, stat, bad;
   std::vector<double> bb, rel;
   int64_t applies0 = 0;
+  // One captured graph of an iteration's device work per number of leading slots
+  // (pointers and coefficients are fixed for a given count); dropped when the
+  // handle's operators change.
+  bool use_graphs = false;
+  std::vector<hipGraphExec_t> graphs;
+  uint64_t graph_gen = 0;
+  hipStream_t gs = nullptr;  // the batch's own stream: graphs cannot be captured on the null stream
+  hipEvent_t ev = nullptr;
+  void drop_graphs() {
+    for (auto& g : graphs)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
   ~Batch() {
+    drop_graphs();
+    if (ev) (void)hipEventDestroy(ev);
+    if (gs) (void)hipStreamDestroy(gs);
     if (h) (void)hipHostFree(h);
     if (hi_) (void)hipHostFree(hi_);
   }
@@ -1025,34 +1046,76 @@ void batch_clear(Batch& B, int j, hipStream_t st) {
 // One MG-CG iteration per step of the loop, ordered so that a fresh slot joins
 // without work of its own: z = M r, beta (0 for a fresh slot, whose <r,z>_old is
 // 0), p = z + beta p, q = A p, alpha, x/r update, convergence check.
+// The device work of one iteration over slots [0, hi): no host synchronisation,
+// memset or allocation, so it can be captured as a graph.
+void batch_iter_device(Batch& B, int hi, hipStream_t st) {
+  Ctx& c = *B.c;
+  c.st = st;
+  auto& lv = c.L64[0];
+  const size_t n = B.n;
+  if (B.prec == SMG_MIXED) launch_links_convert<double>(B.z, B.zo, (size_t)hi * n, st);  // z_old = z
+  batch_precondition(B, 0, hi, st);
+  launch_dot<double>(B.r, B.z, n, hi, B.partial, B.S.pq, st);
+  if (B.prec == SMG_MIXED) {
+    launch_dot<double>(B.r, B.zo, n, hi, B.partial, B.rzo, st);
+    launch_cg_beta_flex(B.S.pq, B.rzo, B.S.rz, B.S.ab, B.S.active, hi, st);
+  } else {
+    launch_cg_beta(B.S.pq, B.S.rz, B.S.ab, B.S.active, hi, st);
+  }
+  launch_xpay<double>(B.z, B.p, B.S.ab, n, hi, st);
+  apply_op<double>(c, lv, B.p, B.q, hi, 0, 0.0, nullptr, nullptr);
+  launch_dot<double>(B.p, B.q, n, hi, B.partial, B.S.pq, st);
+  launch_cg_alpha(B.S.rz, B.S.pq, B.S.ab, B.S.active, B.S.bad, hi, st);
+  launch_axpy_update<double>(B.x, B.r, B.p, B.q, B.S.ab, n, hi, B.partial, B.S.rr, st);
+}
+
 void batch_step(Batch& B, int iters, hipStream_t st) {
   Ctx& c = *B.c;
   c.st = st;
   auto& lv = c.L64[0];
   const size_t n = B.n;
+  if (B.prec == SMG_MIXED) ensure_f32(c);
+  if (B.graph_gen != c.gen) {
+    B.drop_graphs();
+    B.graph_gen = c.gen;
+  }
   for (int it = 0; it < iters; ++it) {
     const int hi = B.hi();
     int nact = 0;
     for (int j = 0; j < hi; ++j) nact += B.act[j];
     if (nact == 0) return;
-    if (B.prec == SMG_MIXED)
-      HIPCHECK(hipMemcpyAsync(B.zo, B.z, (size_t)hi * n * sizeof(z64), hipMemcpyDeviceToDevice, st));
-    batch_precondition(B, 0, hi, st);
-    launch_dot<double>(B.r, B.z, n, hi, B.partial, B.S.pq, st);
-    if (B.prec == SMG_MIXED) {
-      launch_dot<double>(B.r, B.zo, n, hi, B.partial, B.rzo, st);
-      launch_cg_beta_flex(B.S.pq, B.rzo, B.S.rz, B.S.ab, B.S.active, hi, st);
+    if (B.use_graphs) {
+      // replay on the batch's own stream, after the caller's work on st
+      HIPCHECK(hipEventRecord(B.ev, st));
+      HIPCHECK(hipStreamWaitEvent(B.gs, B.ev, 0));
+      hipGraphExec_t& g = B.graphs[hi];
+      if (!g) {
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(B.gs, hipStreamCaptureModeThreadLocal));
+        try {
+          batch_iter_device(B, hi, B.gs);
+        } catch (...) {
+          (void)hipStreamEndCapture(B.gs, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          c.st = st;
+          throw;
+        }
+        HIPCHECK(hipStreamEndCapture(B.gs, &graph));
+        const hipError_t e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+      }
+      HIPCHECK(hipGraphLaunch(g, B.gs));
+      HIPCHECK(hipMemcpyAsync(B.h, B.S.rr, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, B.gs));
+      HIPCHECK(hipMemcpyAsync(B.hi_, B.S.bad, sizeof(int) * hi, hipMemcpyDeviceToHost, B.gs));
+      HIPCHECK(hipStreamSynchronize(B.gs));
+      c.st = st;
     } else {
-      launch_cg_beta(B.S.pq, B.S.rz, B.S.ab, B.S.active, hi, st);
+      batch_iter_device(B, hi, st);
+      HIPCHECK(hipMemcpyAsync(B.h, B.S.rr, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(B.hi_, B.S.bad, sizeof(int) * hi, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
     }
-    launch_xpay<double>(B.z, B.p, B.S.ab, n, hi, st);
-    apply_op<double>(c, lv, B.p, B.q, hi, 0, 0.0, nullptr, nullptr);
-    launch_dot<double>(B.p, B.q, n, hi, B.partial, B.S.pq, st);
-    launch_cg_alpha(B.S.rz, B.S.pq, B.S.ab, B.S.active, B.S.bad, hi, st);
-    launch_axpy_update<double>(B.x, B.r, B.p, B.q, B.S.ab, n, hi, B.partial, B.S.rr, st);
-    HIPCHECK(hipMemcpyAsync(B.h, B.S.rr, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(B.hi_, B.S.bad, sizeof(int) * hi, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
     bool changed = false, any_cand = false;
     std::vector<int> cand(hi, 0);
     auto stop = [&](int j, int status, double rel) {
@@ -1633,6 +1696,13 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     B->S.bad = B->pool.alloc<int>(max_rhs);
     HIPCHECK(hipHostMalloc((void**)&B->h, sizeof(double) * 2 * max_rhs, hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&B->hi_, sizeof(int) * max_rhs, hipHostMallocDefault));
+    // off by default: each (batch, slot count) pays a capture, and replays do not
+    // shorten the iteration where the device front end bounds it (smg_batch_use_graphs)
+    B->use_graphs = false;
+    HIPCHECK(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&B->ev, hipEventDisableTiming));
+    B->graphs.assign(max_rhs + 1, nullptr);
+    B->graph_gen = c->gen;
     B->used.assign(max_rhs, 0);
     B->act.assign(max_rhs, 0);
     B->its.assign(max_rhs, 0);
@@ -1767,6 +1837,18 @@ int smg_batch_cancel(smg_batch b, int32_t slot, void* stream) {
   B->act[slot] = 0;
   batch_clear(*B, slot, (hipStream_t)stream);
   batch_upload_active(*B, (hipStream_t)stream);
+  return SMG_OK;
+  API_END
+}
+
+int smg_batch_use_graphs(smg_batch b, int32_t enable) {
+  API_BEGIN
+  Batch* B = BH(b);
+  Ctx& c = *B->c;
+  const bool can = c.nlev < 2 || c.prm.coarsest == SMG_COARSEST_DIRECT;
+  if (enable && !can) throw Error(SMG_EINVAL, "graphs need a direct coarsest solve");
+  B->drop_graphs();
+  B->use_graphs = enable != 0;
   return SMG_OK;
   API_END
 }

@@ -270,3 +270,34 @@ def test_server_results_equal_alone(cuda):
         finally:
             for v in ref_solvers.values():
                 v.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_equal_eager_launches(setup32, precision):
+    """Each iteration's device work replayed from a captured graph gives bitwise
+    the results of launching it kernel by kernel, over many replays and with slots
+    entering and leaving (different leading-slot counts, eager work in between)."""
+    smg = smg_mod()
+    s, B = setup32["s"], setup32["B"]
+
+    def run(graphs):
+        out = {}
+        with smg.Batch(s, 4, tol=1e-10, maxiter=500, precision=precision) as bt:
+            bt.use_graphs(graphs)
+            a = bt.admit(dev(B[0]))
+            bt.step(3)
+            b = bt.admit(dev(B[1]))
+            c = bt.admit(dev(B[2]))
+            bt.step(2)
+            bt.cancel(b)
+            d = bt.admit(dev(B[3]))
+            done = run_to_end(bt, [a, c, d])
+            for name, slot in (("a", a), ("c", c), ("d", d)):
+                out[name] = (host(bt.harvest(slot)), done[slot]["iterations"], done[slot]["status"])
+        return out
+
+    g, e = run(True), run(False)
+    for k in g:
+        assert g[k][2] == 0 and e[k][2] == 0
+        assert g[k][1] == e[k][1], k
+        assert np.array_equal(g[k][0], e[k][0]), k

@@ -16,7 +16,7 @@ with the FP64 oracle's sparse D and A:
 For the 512^2 lattice (one field, one target) the scan and the bisection run as
 8-point parallel searches instead: each LU of D takes most of a minute there.
 
-Usage: python -m workloads.make_masses [256_beta6 | 512_beta6]
+Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 128_beta6 | 128_beta10]
        (writes workloads/masses_<name>.json)
 """
 
@@ -42,6 +42,9 @@ CONFIGS = {
     "256_beta6": dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
                       ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4]),
     "512_beta6": dict(L=512, beta=6.0, sweeps=500, seeds=[5000], ratios=[1e-3]),
+    # the paper's 128^2 experiment: m_crit (= m*) of candidate fields, picked by topological charge
+    "128_beta6": dict(L=128, beta=6.0, sweeps=1000, seeds=list(range(7000, 7008)), ratios=[]),
+    "128_beta10": dict(L=128, beta=10.0, sweeps=1000, seeds=list(range(7100, 7108)), ratios=[]),
 }
 
 _FIELDS = {}

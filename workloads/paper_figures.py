@@ -1,0 +1,113 @@
+"""The paper's experiment (Results section, Figs. 1 and 2) on synthetic fields.
+
+Fine-lattice applications of D and D^H for CG and for MG-CG as a function of the
+mass gap m - m_crit on 128^2 quenched U(1) fields at beta = 6 and 10, one field of
+trivial and one of nontrivial topological charge per beta.  As in the paper:
+4x4 blocks coarsened twice with M = 8 vectors down to an 8x8 lattice solved
+exactly (dense inverse), a degree-2 MR polynomial smoother with omega = 0.8, the
+setup run at the lightest mass only and its vectors reused for heavier masses
+(smg_derive), a point source and relative residual 1e-14.  The fields are not
+the paper's (they are not available): 1000 Metropolis sweeps from a hot start,
+the first seeds with Q = 0 and Q != 0.  m_crit of each field is the mass that
+minimises lambda_min(A), found offline (workloads/make_masses.py 128_beta6 /
+128_beta10).  The system solved is A x = D^H b with b the point source, so the
+residual is that of the normal equations.
+
+Counts reported per solve:
+  * CG: 2 D applications per iteration (one A), plus those of the true-residual checks;
+  * MG-CG, measured: 2 per fine A application (outer A, 2 nu + 1 per V-cycle, checks);
+  * MG-CG, the paper's accounting: 6 applications of A per iteration (1 outer, 2 pre,
+    2 post, 1 residual), i.e. 12 D applications per iteration.
+
+Usage: python -m workloads.paper_figures [out.json]   (needs the GPU; default workloads/paper_figures.json)
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+L = 128
+GAPS = [0.2, 0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001]
+TOL = 1e-14
+
+
+def pick_fields(beta):
+    with open(os.path.join(ROOT, "workloads", f"masses_128_beta{int(beta)}.json")) as f:
+        data = json.load(f)
+    fields = data["fields"]
+    out = []
+    for want_zero in (True, False):
+        for fld in fields:
+            if (fld["topological_charge"] == 0) == want_zero:
+                out.append(fld)
+                break
+    return out
+
+
+def run_field(smg, torch, fld):
+    seed, beta, sweeps = fld["seed"], fld["beta"], fld["sweeps"]
+    U = synth.links_from_angles(synth.metropolis_u1(L, L, beta, sweeps, seed))
+    mcrit = fld["m_star"]
+    masses = [mcrit + g for g in GAPS]
+    light = min(masses)
+    p = smg.make_params(L, L, light, levels=3, blocks=[(4, 4), (4, 4)], nv=[8, 8], setup_iters=5,
+                        smoother_steps=2, smoother_omega=0.8, seed=seed)
+    R = synth.setup_randoms(L, L, [(4, 4), (4, 4)], [8, 8], seed)
+    dev = torch.device("cuda:0")
+    g = torch.from_numpy(U).to(dev)
+    rnd = torch.from_numpy(np.concatenate([r.ravel() for r in R])).to(dev)
+    t0 = time.perf_counter()
+    s0 = smg.Solver(g, p, randoms=rnd)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    b = torch.from_numpy(synth.point_source(L, L)).to(dev)
+    rows = []
+    for gap, m in zip(GAPS, masses):
+        s = s0 if m == light else s0.derive(m)
+        rhs = s.apply_D(b, dagger=True)
+        _, stm, cm = s.solve(rhs, tol=TOL, maxiter=5000, precision=smg.FP64)
+        _, stc, cc = s.cg(rhs, tol=TOL, maxiter=400000)
+        mg_it = stm[0]["iterations"]
+        rows.append(dict(gap=gap, mass=m,
+                         cg_iterations=stc[0]["iterations"], cg_D_applications=2 * stc[0]["fine_applies"],
+                         cg_relres=stc[0]["true_relres"], cg_status=cc,
+                         mgcg_iterations=mg_it, mgcg_D_applications=2 * stm[0]["fine_applies"],
+                         mgcg_D_applications_paper_accounting=12 * mg_it,
+                         mgcg_relres=stm[0]["true_relres"], mgcg_status=cm))
+        print(f"beta {beta:g} Q {fld['topological_charge']:+d} gap {gap:<6g} CG {stc[0]['iterations']:6d} it "
+              f"MG-CG {mg_it:4d} it  D-applications CG {rows[-1]['cg_D_applications']:7d} "
+              f"MG-CG {rows[-1]['mgcg_D_applications']:6d}", flush=True)
+        if s is not s0:
+            s.close()
+    s0.close()
+    return dict(seed=seed, beta=beta, sweeps=sweeps, topological_charge=fld["topological_charge"],
+                plaquette=fld["plaquette"], m_crit=mcrit, setup_s=setup_s, rows=rows)
+
+
+def main():
+    import torch
+
+    import paper_0710_3612_amd as smg
+
+    out = []
+    for beta in (6.0, 10.0):
+        for fld in pick_fields(beta):
+            out.append(run_field(smg, torch, fld))
+    path = sys.argv[1] if len(sys.argv) > 1 else os.path.join(ROOT, "workloads", "paper_figures.json")
+    with open(path, "w") as f:
+        json.dump(dict(lattice=L, tol=TOL, gaps=GAPS, fields=out), f, indent=1)
+    print(path)
+
+
+if __name__ == "__main__":
+    main()
