@@ -391,6 +391,38 @@ def kernel_probe(reps):
     print(json.dumps(dict(roofline=roof, copy_read_bytes=a.numel() * 4, copy_write_bytes=b.numel() * 4)))
 
 
+def mfma_probe(reps):
+    """Launch only the matrix-core coarse operator (512^2 hierarchy, level 1: 128^2 sites,
+    nc = 16, 32 RHS) for profiler runs; prints its event-timed rate."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_0710_3612_amd as smg
+    import synth
+
+    dev = torch.device("cuda:0")
+    U = synth.links_from_angles(synth.metropolis_u1(MRHS_L, MRHS_L, BETA, 20, MRHS_SEED))
+    p = smg.make_params(MRHS_L, MRHS_L, 0.0, levels=3, blocks=[(4, 4), (4, 4)], nv=MRHS_NV, setup_iters=0,
+                        smoother_steps=NU, smoother_omega=OMEGA, seed=MRHS_SEED, sa_scale=SA_SCALE,
+                        coarsest=smg.COARSEST_CG, mfma_min_rhs=16)
+    s = smg.Solver(torch.from_numpy(np.ascontiguousarray(U)).to(dev), p)
+    cx, ct, nc = s.level_info(1)
+    v = torch.randn(MRHS_NRHS * cx * ct * nc, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(v)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    lib = smg.load_library()
+    h = s.handle
+    px, py, nul = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p()
+    dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), reps, stream)
+    flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
+    print(json.dumps(dict(kernel="k_coarse_mfma", sites=cx * ct, nc=nc, nrhs=MRHS_NRHS, avg_launch_us=dur * 1e6,
+                          tflops=flops / dur / 1e12, frac=flops / dur / 1e12 / 157.3,
+                          link_bytes=9 * nc * nc * 8 * cx * ct)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,11 +440,15 @@ def main():
     ap.add_argument("--no-mrhs", action="store_true")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
+    ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the roofline kernel and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
     if args.kernel_probe:
         kernel_probe(args.dslash_reps)
+        return 0
+    if args.mfma_probe:
+        mfma_probe(args.dslash_reps)
         return 0
 
     if args.cpu_baseline_leg:

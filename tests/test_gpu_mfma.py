@@ -7,8 +7,9 @@ matrix in FP64 on the same FP32-rounded inputs, and with the vector-ALU path.
 Inputs and links are rounded to FP32 (unit roundoff 6e-8) and an output sums at
 most 9 * 16 complex products, so 2e-5 of the column's largest entry bounds the
 difference with a wide margin.  Cases cover nc = 16, 12 and an odd nc = 5, tiles
-cut by the lattice edge (coarse extents not multiples of the 4 x 4 tile), and
-right-hand-side counts that are not multiples of 32.
+cut by the lattice edge (coarse extents not multiples of the tile), both tile
+shapes (2x2 on small coarse lattices, 4x4 from 64x64 sites), and right-hand-side
+counts that are not multiples of 32.
 """
 
 import numpy as np
@@ -29,6 +30,7 @@ CASES = [
     (20, 20, [(4, 4)], [5], 0.2),                 # 5x5x5: odd nc
     (24, 24, [(4, 4)], [16], 0.03),               # 6x6x16: tiles cut at both edges
     (16, 16, [(4, 4), (2, 2)], [8, 16], 0.1),     # 2x2x16: the ring wraps more than once
+    (256, 256, [(4, 4), (4, 4)], [16, 4], 0.05),  # 64x64x16: the 4x4-tile path (>= 256 tiles)
 ]
 
 

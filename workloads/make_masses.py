@@ -26,6 +26,10 @@ import json
 import math
 import os
 import sys
+
+# one BLAS thread per worker process: the pool already fills the cores
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
 import time
 from concurrent.futures import ProcessPoolExecutor
 
