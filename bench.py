@@ -325,6 +325,20 @@ COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f32_level1_256_counters.md"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip")
 
 
+def kernel_source_digest():
+    """sha256 of the roofline kernel's own source: the k_coarse kernel and its two
+    launch functions (edits elsewhere in the file leave its counters valid)."""
+    import hashlib
+
+    text = open(KERNEL_SOURCE).read()
+    parts = []
+    for start in ("template <typename R, int MODE, int NR>\n__global__ void __launch_bounds__(kThreads) k_coarse(",
+                  "void launch_coarse_nr(", "void launch_coarse(const cpx<R>* L"):
+        i = text.index(start)
+        parts.append(text[i:text.index("\n}\n", i) + 3])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the roofline kernel from the committed counter runs
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size), or None when
@@ -336,8 +350,7 @@ def measured_traffic():
     except OSError:
         return None
     vals = dict(line.split(" = ", 1) for line in text.splitlines() if " = " in line and line[:1].isalpha())
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256", "").strip() != src:
+    if vals.get("kernel_source_sha256", "").strip() != kernel_source_digest():
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])

@@ -13,8 +13,10 @@ with the FP64 oracle's sparse D and A:
      the field is gapped and r is out of reach, m* is used and the reached ratio
      is recorded.
 
-For the 512^2 lattice (one field, one target) the scan and the bisection run as
-8-point parallel searches instead: each LU of D takes most of a minute there.
+For the 512^2 lattice (one field, one target) a full scan is too slow (each LU of
+D takes most of a minute and some near-critical ones far longer), so the target is
+reached from a starting mass by secant steps on sigma_min(D) = sqrt(lambda_min(A)),
+which moves almost linearly with m away from m_crit; m* is not searched there.
 
 Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 128_beta6 | 128_beta10]
        (writes workloads/masses_<name>.json)
@@ -45,7 +47,7 @@ from oracle.wilson import dirac_matrix  # noqa: E402
 CONFIGS = {
     "256_beta6": dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
                       ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4]),
-    "512_beta6": dict(L=512, beta=6.0, sweeps=500, seeds=[5000], ratios=[1e-3]),
+    "512_beta6": dict(L=512, beta=6.0, sweeps=500, seeds=[5000], ratios=[1e-3], start=0.065),
     # the paper's 128^2 experiment: m_crit (= m*) of candidate fields, picked by topological charge
     "128_beta6": dict(L=128, beta=6.0, sweeps=1000, seeds=list(range(7000, 7008)), ratios=[]),
     "128_beta10": dict(L=128, beta=10.0, sweeps=1000, seeds=list(range(7100, 7108)), ratios=[]),
@@ -170,6 +172,29 @@ def parallel_field(cfg, seed, ex, width=8):
     return out
 
 
+def secant_field(cfg, seed, ex):
+    """Each target ratio by secant steps on sigma_min from cfg['start'] (3 evaluations)."""
+    L, beta, sweeps = cfg["L"], cfg["beta"], cfg["sweeps"]
+    th = field(L, beta, sweeps, seed)
+    out = dict(seed=seed, m_star=None, plaquette=synth.mean_plaquette(th),
+               topological_charge=round(synth.topological_charge(th)), masses=[])
+    for target in cfg["ratios"]:
+        m0 = cfg["start"]
+        mn, mx = _lmin_job((L, beta, sweeps, seed, m0))
+        pts = [(m0, mn, mx)]
+        m1 = m0 + (math.sqrt(target * mx) - math.sqrt(mn))
+        for _ in range(2):
+            mn, mx = _lmin_job((L, beta, sweeps, seed, m1))
+            pts.append((m1, mn, mx))
+            (ma, na, xa), (mb, nb, xb) = pts[-2], pts[-1]
+            sa, sb = math.sqrt(na) - math.sqrt(target * xa), math.sqrt(nb) - math.sqrt(target * xb)
+            m1 = mb - sb * (mb - ma) / (sb - sa) if sb != sa else mb
+        m, mn, mx = min(pts, key=lambda t: abs(math.log(t[1] / t[2] / target)))
+        out["masses"].append(dict(target=target, mass=m, ratio=mn / mx, reached=abs(mn / mx / target - 1) < 0.1,
+                                  evaluations=[dict(mass=a, lambda_min=b, lambda_max=c) for a, b, c in pts]))
+    return out
+
+
 def main():
     name = sys.argv[1] if len(sys.argv) > 1 else "256_beta6"
     cfg = CONFIGS[name]
@@ -186,6 +211,9 @@ def main():
                 fld = dict(st, L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
                 fld["masses"] = res[k * len(cfg["ratios"]):(k + 1) * len(cfg["ratios"])]
                 fields.append(fld)
+        elif "start" in cfg:
+            fields = [dict(secant_field(cfg, s, ex), L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
+                      for s in cfg["seeds"]]
         else:
             fields = [dict(parallel_field(cfg, s, ex), L=cfg["L"], beta=cfg["beta"], sweeps=cfg["sweeps"])
                       for s in cfg["seeds"]]
