@@ -64,12 +64,16 @@ def _wrap(a: np.ndarray) -> np.ndarray:
     return (a + math.pi) % TWO_PI - math.pi
 
 
-def metropolis_u1(lx: int, lt: int, beta: float, sweeps: int, seed: int) -> np.ndarray:
-    """Return link angles theta[2, lt, lx] after ``sweeps`` Metropolis sweeps from a hot start."""
+def metropolis_u1(lx: int, lt: int, beta: float, sweeps: int, seed: int, cold: bool = False) -> np.ndarray:
+    """Return link angles theta[2, lt, lx] after ``sweeps`` Metropolis sweeps from a hot
+    start (uniform angles), or from a cold start (all angles 0, topological charge 0,
+    which local updates at these couplings practically never change)."""
     if lx % 2 or lt % 2:
         raise ValueError("checkerboard update needs even extents")
     rng = np.random.default_rng(seed)
     theta = rng.uniform(-math.pi, math.pi, size=(2, lt, lx))
+    if cold:
+        theta[:] = 0.0
     delta = math.sqrt(2.0 / beta) if beta > 0 else math.pi
     for _ in range(sweeps):
         for mu in (0, 1):

@@ -18,7 +18,8 @@ D takes most of a minute and some near-critical ones far longer), so the target 
 reached from a starting mass by secant steps on sigma_min(D) = sqrt(lambda_min(A)),
 which moves almost linearly with m away from m_crit; m* is not searched there.
 
-Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 128_beta6 | 128_beta10]
+Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 128_beta6 | 128_beta10 | 128_beta6_cold |
+       128_beta10_cold]
        (writes workloads/masses_<name>.json)
 """
 
@@ -51,15 +52,18 @@ CONFIGS = {
     # the paper's 128^2 experiment: m_crit (= m*) of candidate fields, picked by topological charge
     "128_beta6": dict(L=128, beta=6.0, sweeps=1000, seeds=list(range(7000, 7008)), ratios=[]),
     "128_beta10": dict(L=128, beta=10.0, sweeps=1000, seeds=list(range(7100, 7108)), ratios=[]),
+    # cold starts; the first seeds whose field keeps topological charge 0 after 1000 sweeps
+    "128_beta6_cold": dict(L=128, beta=6.0, sweeps=1000, seeds=[7014], ratios=[], cold=True),
+    "128_beta10_cold": dict(L=128, beta=10.0, sweeps=1000, seeds=[7110], ratios=[], cold=True),
 }
 
 _FIELDS = {}
 
 
-def field(L, beta, sweeps, seed):
-    key = (L, beta, sweeps, seed)
+def field(L, beta, sweeps, seed, cold=False):
+    key = (L, beta, sweeps, seed, cold)
     if key not in _FIELDS:
-        _FIELDS[key] = synth.metropolis_u1(L, L, beta, sweeps, seed)
+        _FIELDS[key] = synth.metropolis_u1(L, L, beta, sweeps, seed, cold=cold)
     return _FIELDS[key]
 
 
@@ -82,8 +86,9 @@ def extremes(U, m):
 
 
 def find_mstar(args):
-    L, beta, sweeps, seed = args
-    th = field(L, beta, sweeps, seed)
+    L, beta, sweeps, seed = args[:4]
+    cold = len(args) > 4 and args[4]
+    th = field(L, beta, sweeps, seed, cold)
     U = synth.links_from_angles(th)
     cache = {}
 
@@ -106,7 +111,7 @@ def find_mstar(args):
         c, d = b - g * (b - a), a + g * (b - a)
     mstar = 0.5 * (a + b)
     lo_min, lo_max = extremes(U, mstar)
-    return dict(seed=seed, m_star=mstar, lambda_min=lo_min, lambda_max=lo_max,
+    return dict(seed=seed, cold=bool(cold), m_star=mstar, lambda_min=lo_min, lambda_max=lo_max,
                 plaquette=synth.mean_plaquette(th), topological_charge=round(synth.topological_charge(th)))
 
 
@@ -199,7 +204,7 @@ def main():
     name = sys.argv[1] if len(sys.argv) > 1 else "256_beta6"
     cfg = CONFIGS[name]
     t0 = time.time()
-    base = [(cfg["L"], cfg["beta"], cfg["sweeps"], s) for s in cfg["seeds"]]
+    base = [(cfg["L"], cfg["beta"], cfg["sweeps"], s, cfg.get("cold", False)) for s in cfg["seeds"]]
     with ProcessPoolExecutor(max_workers=8) as ex:
         if cfg["L"] <= 256:
             stars = list(ex.map(find_mstar, base))

@@ -7,8 +7,8 @@ trivial and one of nontrivial topological charge per beta.  As in the paper:
 exactly (dense inverse), a degree-2 MR polynomial smoother with omega = 0.8, the
 setup run at the lightest mass only and its vectors reused for heavier masses
 (smg_derive), a point source and relative residual 1e-14.  The fields are not
-the paper's (they are not available): 1000 Metropolis sweeps from a hot start,
-the first seeds with Q = 0 and Q != 0.  m_crit of each field is the mass that
+the paper's (they are not available): 1000 Metropolis sweeps, the Q = 0 field
+from a cold start and the Q != 0 field from a hot start.  m_crit of each field is the mass that
 minimises lambda_min(A), found offline (workloads/make_masses.py 128_beta6 /
 128_beta10).  The system solved is A x = D^H b with b the point source, so the
 residual is that of the normal equations.
@@ -42,12 +42,12 @@ TOL = 1e-14
 
 
 def pick_fields(beta):
-    with open(os.path.join(ROOT, "workloads", f"masses_128_beta{int(beta)}.json")) as f:
-        data = json.load(f)
-    fields = data["fields"]
+    """(field with Q = 0 from a cold start, first hot-start field with Q != 0)."""
     out = []
-    for want_zero in (True, False):
-        for fld in fields:
+    for name, want_zero in ((f"masses_128_beta{int(beta)}_cold.json", True), (f"masses_128_beta{int(beta)}.json", False)):
+        with open(os.path.join(ROOT, "workloads", name)) as f:
+            data = json.load(f)
+        for fld in data["fields"]:
             if (fld["topological_charge"] == 0) == want_zero:
                 out.append(fld)
                 break
@@ -55,8 +55,8 @@ def pick_fields(beta):
 
 
 def run_field(smg, torch, fld):
-    seed, beta, sweeps = fld["seed"], fld["beta"], fld["sweeps"]
-    U = synth.links_from_angles(synth.metropolis_u1(L, L, beta, sweeps, seed))
+    seed, beta, sweeps, cold = fld["seed"], fld["beta"], fld["sweeps"], fld.get("cold", False)
+    U = synth.links_from_angles(synth.metropolis_u1(L, L, beta, sweeps, seed, cold=cold))
     mcrit = fld["m_star"]
     masses = [mcrit + g for g in GAPS]
     light = min(masses)
@@ -90,7 +90,7 @@ def run_field(smg, torch, fld):
         if s is not s0:
             s.close()
     s0.close()
-    return dict(seed=seed, beta=beta, sweeps=sweeps, topological_charge=fld["topological_charge"],
+    return dict(seed=seed, cold=cold, beta=beta, sweeps=sweeps, topological_charge=fld["topological_charge"],
                 plaquette=fld["plaquette"], m_crit=mcrit, setup_s=setup_s, rows=rows)
 
 
