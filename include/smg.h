@@ -96,6 +96,9 @@ typedef struct {
                                      iterates in the FP32 V-cycle, SMG_STORE_F32 / _BF16 /
                                      _F16 (arithmetic stays FP32; BF16/FP16 need
                                      lx % 32 == 0 and lt % 16 == 0) */
+  int32_t stop_recursive;         /* FP64 MG-CG and CG: 0 (default) = converged when the recomputed
+                                     residual ||rhs - A x|| / ||rhs|| reaches tol; 1 = when CG's
+                                     recursive residual does (the true one is still reported) */
   int32_t mfma_min_rhs;           /* FP32 coarse applies of at least this many right-hand
                                      sides run on the matrix cores (MFMA FP32, levels with
                                      nc <= 16); 1 = always, 0 = never.  Results differ from
@@ -115,7 +118,7 @@ typedef struct {
 /* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
- * smoother_storage = SMG_STORE_F32, mfma_min_rhs = 16. */
+ * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).

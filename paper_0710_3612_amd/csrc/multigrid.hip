@@ -961,10 +961,43 @@ void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hip
   HIPCHECK(hipGetLastError());
 }
 
+// Y = M X with one wavefront per (row, column): lanes take j = lane, lane + 64, ...
+// and the partial sums meet in a fixed butterfly.  For coarsest operators small
+// enough to stay in the caches (n <= kDenseRowsMax) this fills the chip where the
+// tiled kernel would launch a few dozen workgroups.
+constexpr int kDenseRowsMax = 4096;
+
+template <typename RM, typename R>
+__global__ void __launch_bounds__(kThreads) k_dense_rows(const cpx<RM>* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                         cpx<R>* __restrict__ y, int n) {
+  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const cpx<R>* xb = x + (size_t)blockIdx.y * n;
+  const cpx<RM>* Mr = M + (size_t)row * n;
+  double re = 0, im = 0;
+  for (int j = lane; j < n; j += 64) {
+    const cpx<RM> m = Mr[j];
+    const cpx<R> v = xb[j];
+    re = fma((double)m.re, (double)v.re, re);
+    re = fma(-(double)m.im, (double)v.im, re);
+    im = fma((double)m.re, (double)v.im, im);
+    im = fma((double)m.im, (double)v.re, im);
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)re, (R)im);
+}
+
+// The kernel is chosen by n alone, so a column's result never depends on nrhs.
 template <typename RM, typename R>
 void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
-  dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
-  hipLaunchKernelGGL((k_dense_gemm<RM, R>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs);
+  if (n <= kDenseRowsMax) {
+    hipLaunchKernelGGL((k_dense_rows<RM, R>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n);
+  } else {
+    dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
+    hipLaunchKernelGGL((k_dense_gemm<RM, R>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs);
+  }
   HIPCHECK(hipGetLastError());
 }
 

@@ -1474,7 +1474,8 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
   if (precision == SMG_FP64) {
     ensure_level_work<double>(*c, nrhs);
     ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * n);
-    pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, mg, c->f64, &cs, 1, 0);
+    pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, mg, c->f64, &cs, 1, 0,
+                c->prm.stop_recursive == 0);
   } else {
     // FP64 defect correction around FP32 MG-CG.
     ensure_f32(*c);
@@ -1570,7 +1571,8 @@ int smg_cg(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol,
   ensure_level_work<double>(*c, nrhs);
   ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * c->L64[0].n);
   ColStats cs;
-  pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, false, c->f64, &cs, 1, 0);
+  pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, false, c->f64, &cs, 1, 0,
+              c->prm.stop_recursive == 0);
   sync(*c);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fill_stats(stats, nrhs, cs, 1, c->fine_applies - fa0, 0, secs);

@@ -122,6 +122,7 @@ CASES = [
     (20, 20, [(4, 4)], [5], 0.1, SA),               # odd coarse vector length (5 x 5 x 5)
     (64, 64, [(4, 4)], [8], 0.1, SA),               # coarsest 2048: blocked Gauss-Jordan, 4 blocks
     (48, 48, [(4, 4)], [7], 0.1, SA),               # coarsest 1008: blocked, ragged last block
+    (64, 64, [(2, 2)], [5], 0.1, SA),               # coarsest 5120: blocked inverse, tiled multi-RHS apply
 ]
 
 
@@ -372,3 +373,27 @@ def test_fp32_operators(pair):
         Al = h.levels[l].A
         for j in range(2):
             assert rel_err(y[j], Al @ x[j]) <= 2e-5
+
+
+def test_stop_on_recursive_residual(cuda):
+    """stop_recursive: MG-CG and CG stop when the recursive residual reaches tol
+    (the paper's stopping rule); the recomputed residual is still reported and,
+    for a well-conditioned system, agrees with the oracle's to rounding."""
+    smg = smg_mod()
+    lx = lt = 24
+    U = field(lx, lt, seed=12, sweeps=30)
+    A = normal_matrix(U, 0.1)
+    b = synth.gaussian(2 * lx * lt, 31)
+    out = {}
+    for flag in (False, True):
+        p = smg.make_params(lx, lt, 0.1, levels=2, blocks=[(4, 4)], nv=[6], seed=4, stop_recursive=flag)
+        with smg.Solver(dev(U), p) as s:
+            x, st, code = s.solve(dev(b), tol=1e-10, maxiter=500, precision=smg.FP64)
+            xc, stc, codec = s.cg(dev(b), tol=1e-10, maxiter=5000)
+            assert code == 0 and codec == 0
+            for xx, ss in ((x, st), (xc, stc)):
+                res = np.linalg.norm(b - A @ host(xx)) / np.linalg.norm(b)
+                assert abs(res - ss[0]["true_relres"]) <= 1e-3 * res + 1e-15
+                assert res <= 1e-9
+            out[flag] = (st[0]["iterations"], stc[0]["iterations"])
+    assert out[True][0] <= out[False][0] and out[True][1] <= out[False][1]
