@@ -4,7 +4,10 @@
 // Reductions are deterministic and batch invariant: every column of a batch is
 // reduced by the same fixed number of blocks (a function of the column length
 // only), each block sums in a fixed order with wavefront shuffles, and a second
-// pass adds the block partials in a fixed order.  Sums are accumulated in FP64
+// pass adds the block partials in a fixed order.  (A single pass with a
+// last-block finisher needs a device-scope release per block, which on gfx950
+// writes back the XCD's L2 and was measured slower.)  The second pass also takes
+// the CG scalar updates that follow a dot product (alpha; beta and <r,z>).  Sums are accumulated in FP64
 // for FP32 vectors too.  Krylov scalars live on the device, so the CG loop needs
 // no host round trip except the convergence check.
 #include <algorithm>
@@ -51,17 +54,47 @@ __global__ void __launch_bounds__(kThreads) k_dot_partial(const cpx<R>* __restri
   }
 }
 
+// Second pass, one block per column: the partials in index order.  EPI 0: out =
+// sum.  EPI 1 (alpha; sum = <p,q>, s = <r,z>): out = alpha, breakdown flagged in
+// bad.  EPI 2 (beta; sum = <r,z>_new, s = <r,z>_old): out = beta, s <- sum.
+template <int EPI>
 __global__ void __launch_bounds__(kThreads) k_reduce_final(const double* __restrict__ partial, int nb,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out, double* __restrict__ s,
+                                                           const int* __restrict__ active, int* __restrict__ bad) {
   double re = 0, im = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     re += partial[2 * ((size_t)blockIdx.x * nb + i)];
     im += partial[2 * ((size_t)blockIdx.x * nb + i) + 1];
   }
   block_sum2(re, im);
-  if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = re;
-    out[2 * blockIdx.x + 1] = im;
+  if (threadIdx.x != 0) return;
+  const int j = blockIdx.x;
+  if (EPI == 0) {
+    out[2 * j] = re;
+    out[2 * j + 1] = im;
+  } else if (EPI == 1) {
+    double al = 0;
+    if (active[j]) {
+      const double num = s[2 * j], den = re;
+      if (!isfinite(num) || !isfinite(den)) {
+        bad[j] = 1;
+      } else if (num == 0) {
+        al = 0;  // residual is exactly zero: nothing left to do in this column
+      } else if (!(den > 0)) {
+        bad[j] = 1;
+      } else {
+        al = num / den;
+      }
+    }
+    out[j] = al;
+  } else {
+    double be = 0;
+    if (active[j] && s[2 * j] != 0) be = re / s[2 * j];
+    out[j] = be;
+    if (active[j]) {
+      s[2 * j] = re;
+      s[2 * j + 1] = im;
+    }
   }
 }
 
@@ -220,20 +253,42 @@ inline dim3 ew_grid(size_t n, int nrhs) {
 }  // namespace
 
 template <typename R>
-void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, double* partial, double* out,
-                hipStream_t st) {
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, a, b, n, nb, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs), dim3(kThreads), 0, st, partial, nb, out);
+  hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, a, b, n, nb, red.partial);
+  hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, out, nullptr, nullptr,
+                     nullptr);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
+                      double* alpha, const int* active, int* bad, hipStream_t st) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, p, q, n, nb, red.partial);
+  hipLaunchKernelGGL((k_reduce_final<1>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, alpha,
+                     const_cast<double*>(rz), active, bad);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
+                     const int* active, hipStream_t st) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, r, z, n, nb, red.partial);
+  hipLaunchKernelGGL((k_reduce_final<2>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, beta, rz, active,
+                     nullptr);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
-                        int nrhs, double* partial, double* rr, hipStream_t st) {
+                        int nrhs, Red red, double* rr, hipStream_t st) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL((k_axpy_update<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, alpha, n, nb, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(nrhs), dim3(kThreads), 0, st, partial, nb, rr);
+  hipLaunchKernelGGL((k_axpy_update<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, alpha, n, nb,
+                     red.partial);
+  hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, rr, nullptr, nullptr,
+                     nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -318,9 +373,13 @@ void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* a
 }
 
 #define INST(R)                                                                                              \
-  template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, double*, double*, hipStream_t);       \
+  template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, hipStream_t);          \
+  template void launch_dot_alpha<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, const double*, double*,    \
+                                    const int*, int*, hipStream_t);                                           \
+  template void launch_dot_beta<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, double*,            \
+                                   const int*, hipStream_t);                                                  \
   template void launch_axpy_update<R>(cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double*, size_t,  \
-                                      int, double*, double*, hipStream_t);                                    \
+                                      int, Red, double*, hipStream_t);                                        \
   template void launch_xpay<R>(const cpx<R>*, cpx<R>*, const double*, size_t, int, hipStream_t);              \
   template void launch_axpy_const<R>(cpx<R>*, const cpx<R>*, double, size_t, int, hipStream_t);              \
   template void launch_sub<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, size_t, int, hipStream_t);              \

@@ -193,12 +193,23 @@ template <typename RM, typename R>
 void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
 
 // Level-1 BLAS (batched over nrhs columns of length n).
+// Scratch of the reductions: per column `nb` block partials.
+struct Red {
+  double* partial = nullptr;
+};
 template <typename R>
-void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, double* partial, double* out,
-                hipStream_t st);  // out[2*rhs] = <a,b> (complex)
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st);
+// <p, q> per column, then alpha = <r,z> / <p,q> (0 for inactive columns, breakdown flagged in bad).
+template <typename R>
+void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
+                      double* alpha, const int* active, int* bad, hipStream_t st);
+// <r, z>_new per column, then beta = <r,z>_new / <r,z>_old and <r,z>_old <- <r,z>_new (active columns).
+template <typename R>
+void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
+                     const int* active, hipStream_t st);  // out[2*rhs] = <a,b> (complex)
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
-                        int nrhs, double* partial, double* rr, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2
+                        int nrhs, Red red, double* rr, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2
 template <typename R>
 void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
 template <typename R>

@@ -121,7 +121,7 @@ struct Ctx {
   // per-column scalars on the device: one set per CG nesting depth (the outer
   // solve and a coarsest-level CG running inside its V-cycle)
   int scal_cap = 0;
-  double* partial = nullptr;
+  Red red;                          // reduction scratch
   Scal sc[2];
   double *dc_down = nullptr, *dc_up = nullptr;
   int* fail = nullptr;
@@ -160,7 +160,7 @@ void ensure_scalars(Ctx& c, int nrhs) {
   if (nrhs <= c.scal_cap) return;
   const int cap = std::max(nrhs, 8);
   const int nb = red_blocks(c.L64[0].n);
-  c.partial = c.pool.alloc<double>((size_t)2 * nb * cap);
+  c.red.partial = c.pool.alloc<double>((size_t)2 * nb * cap);
   for (auto& s : c.sc) {
     s.bb = c.pool.alloc<double>(2 * cap);
     s.rz = c.pool.alloc<double>(2 * cap);
@@ -405,7 +405,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   const size_t n = lv.n;
   ensure_scalars(c, nrhs);
   const size_t bytes = (size_t)nrhs * n * sizeof(cpx<R>);
-  launch_dot<R>(b, b, n, nrhs, c.partial, S.bb, c.st);
+  launch_dot<R>(b, b, n, nrhs, c.red, S.bb, c.st);
   HIPCHECK(hipMemcpyAsync(c.h_scal, S.bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
   sync(c);
   std::vector<double> hbb(nrhs), rel(nrhs, 0.0);
@@ -438,13 +438,12 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   if (nact > 0) {
     precondition(v.r, v.z);
     HIPCHECK(hipMemcpyAsync(v.p, v.z, bytes, hipMemcpyDeviceToDevice, c.st));
-    launch_dot<R>(v.r, v.z, n, nrhs, c.partial, S.rz, c.st);
+    launch_dot<R>(v.r, v.z, n, nrhs, c.red, S.rz, c.st);
   }
   for (int it = 1; it <= maxiter && nact > 0; ++it) {
     apply_op<R>(c, lv, v.p, v.q, nrhs, 0, 0.0, nullptr, nullptr);
-    launch_dot<R>(v.p, v.q, n, nrhs, c.partial, S.pq, c.st);
-    launch_cg_alpha(S.rz, S.pq, S.ab, S.active, S.bad, nrhs, c.st);
-    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.partial, S.rr, c.st);
+    launch_dot_alpha<R>(v.p, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st);
+    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.red, S.rr, c.st);
     for (int j = 0; j < nrhs; ++j) its[j] += act[j];
     if (it % check_interval == 0 || it == maxiter) {
       HIPCHECK(hipMemcpyAsync(c.h_scal, S.rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
@@ -477,7 +476,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
       } else if (any_cand) {
         // confirm on the true residual t = b - A x
         apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
-        launch_dot<R>(v.t, v.t, n, nrhs, c.partial, S.tt, c.st);
+        launch_dot<R>(v.t, v.t, n, nrhs, c.red, S.tt, c.st);
         HIPCHECK(hipMemcpyAsync(c.h_scal, S.tt, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
         sync(c);
         bool changed = false;
@@ -503,13 +502,12 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
       }
     }
     precondition(v.r, v.z);
-    launch_dot<R>(v.r, v.z, n, nrhs, c.partial, S.pq, c.st);
-    launch_cg_beta(S.pq, S.rz, S.ab, S.active, nrhs, c.st);
+    launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
     launch_xpay<R>(v.z, v.p, S.ab, n, nrhs, c.st);
   }
   if (nact > 0) {  // true residual of the columns that did not converge
     apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
-    launch_dot<R>(v.t, v.t, n, nrhs, c.partial, S.tt, c.st);
+    launch_dot<R>(v.t, v.t, n, nrhs, c.red, S.tt, c.st);
     HIPCHECK(hipMemcpyAsync(c.h_scal, S.tt, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
     sync(c);
     for (int j = 0; j < nrhs; ++j)
@@ -553,7 +551,7 @@ void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, 
 // ---------------------------------------------------------------------------
 double dev_dot_re(Ctx& c, const z64* a, const z64* b, size_t n) {
   ensure_scalars(c, 1);
-  launch_dot<double>(a, b, n, 1, c.partial, c.sc[1].tt, c.st);
+  launch_dot<double>(a, b, n, 1, c.red, c.sc[1].tt, c.st);
   HIPCHECK(hipMemcpyAsync(c.h_scal, c.sc[1].tt, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st));
   sync(c);
   return c.h_scal[0];
@@ -965,7 +963,7 @@ struct Batch {
   z64 *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zo = nullptr,
       *t = nullptr;
   z32 *r32 = nullptr, *z32v = nullptr;
-  double* partial = nullptr;
+  Red red;
   Scal S;
   double* rzo = nullptr;
   double* h = nullptr;  // pinned host scratch
@@ -1055,18 +1053,17 @@ void batch_iter_device(Batch& B, int hi, hipStream_t st) {
   const size_t n = B.n;
   if (B.prec == SMG_MIXED) launch_links_convert<double>(B.z, B.zo, (size_t)hi * n, st);  // z_old = z
   batch_precondition(B, 0, hi, st);
-  launch_dot<double>(B.r, B.z, n, hi, B.partial, B.S.pq, st);
   if (B.prec == SMG_MIXED) {
-    launch_dot<double>(B.r, B.zo, n, hi, B.partial, B.rzo, st);
+    launch_dot<double>(B.r, B.z, n, hi, B.red, B.S.pq, st);
+    launch_dot<double>(B.r, B.zo, n, hi, B.red, B.rzo, st);
     launch_cg_beta_flex(B.S.pq, B.rzo, B.S.rz, B.S.ab, B.S.active, hi, st);
   } else {
-    launch_cg_beta(B.S.pq, B.S.rz, B.S.ab, B.S.active, hi, st);
+    launch_dot_beta<double>(B.r, B.z, n, hi, B.red, B.S.rz, B.S.ab, B.S.active, st);
   }
   launch_xpay<double>(B.z, B.p, B.S.ab, n, hi, st);
   apply_op<double>(c, lv, B.p, B.q, hi, 0, 0.0, nullptr, nullptr);
-  launch_dot<double>(B.p, B.q, n, hi, B.partial, B.S.pq, st);
-  launch_cg_alpha(B.S.rz, B.S.pq, B.S.ab, B.S.active, B.S.bad, hi, st);
-  launch_axpy_update<double>(B.x, B.r, B.p, B.q, B.S.ab, n, hi, B.partial, B.S.rr, st);
+  launch_dot_alpha<double>(B.p, B.q, n, hi, B.red, B.S.rz, B.S.ab, B.S.active, B.S.bad, st);
+  launch_axpy_update<double>(B.x, B.r, B.p, B.q, B.S.ab, n, hi, B.red, B.S.rr, st);
 }
 
 void batch_step(Batch& B, int iters, hipStream_t st) {
@@ -1140,7 +1137,7 @@ void batch_step(Batch& B, int iters, hipStream_t st) {
     }
     if (any_cand) {  // confirm on the true residual t = b - A x
       apply_op<double>(c, lv, B.x, B.t, hi, 2, 0.0, nullptr, B.b);
-      launch_dot<double>(B.t, B.t, n, hi, B.partial, B.S.tt, st);
+      launch_dot<double>(B.t, B.t, n, hi, B.red, B.S.tt, st);
       HIPCHECK(hipMemcpyAsync(B.h, B.S.tt, sizeof(double) * 2 * hi, hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       for (int j = 0; j < hi; ++j) {
@@ -1494,7 +1491,7 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
     z64* xx = (z64*)x;
     zero(xx, bytes, c->st);
     HIPCHECK(hipMemcpyAsync(c->r64, b, bytes, hipMemcpyDeviceToDevice, c->st));
-    launch_dot<double>(b, b, n, nrhs, c->partial, c->sc[1].bb, c->st);
+    launch_dot<double>(b, b, n, nrhs, c->red, c->sc[1].bb, c->st);
     HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
     sync(*c);
     std::vector<double> hbb(nrhs), rel(nrhs, 0.0), down(nrhs), up(nrhs);
@@ -1507,7 +1504,7 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
     refinements = 0;
     int used = 0;
     while (true) {
-      launch_dot<double>(c->r64, c->r64, n, nrhs, c->partial, c->sc[1].rr, c->st);
+      launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st);
       HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
       sync(*c);
       int nact = 0;
@@ -1687,7 +1684,7 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
       ensure_f32(*c);
       ensure_level_work<float>(*c, max_rhs);
     }
-    B->partial = B->pool.alloc<double>((size_t)2 * red_blocks(B->n) * max_rhs);
+    B->red.partial = B->pool.alloc<double>((size_t)2 * red_blocks(B->n) * max_rhs);
     B->S.bb = B->pool.alloc<double>(2 * max_rhs);
     B->S.rz = B->pool.alloc<double>(2 * max_rhs);
     B->S.pq = B->pool.alloc<double>(2 * max_rhs);
@@ -1747,7 +1744,7 @@ int smg_batch_admit(smg_batch b, const double* rhs, int32_t* slot, void* stream)
   zero(B->p + off, n * sizeof(z64), st);
   zero(B->S.rz + 2 * s, sizeof(double) * 2, st);
   zero(B->S.bad + s, sizeof(int), st);
-  launch_dot<double>(B->b + off, B->b + off, n, 1, B->partial, B->S.bb + 2 * s, st);
+  launch_dot<double>(B->b + off, B->b + off, n, 1, B->red, B->S.bb + 2 * s, st);
   HIPCHECK(hipMemcpyAsync(B->h, B->S.bb + 2 * s, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   const double bb = B->h[0];
