@@ -177,8 +177,9 @@ int smg_apply_level_f32(smg_handle h, int32_t level, const float* x, float* y, i
 /* FP32 operator of level `level` with the epilogues the V-cycle uses (Multigrid
  * section, steps 1-5; Results for the smoother): mode 0: y = A_l x; mode 1 (one
  * frozen MR step): xacc += coef x and y = x - coef A_l x; mode 2 (residual):
- * y = aux - A_l x.  Vectors are complex64 device arrays [nrhs][n_l] (xacc, aux
- * may be NULL where unused).  Coarse levels with nc <= 16 and
+ * y = aux - A_l x; mode 3 (the first MR step, from a zero iterate): xacc = coef x
+ * and y = x - coef A_l x.  Vectors are complex64 device arrays [nrhs][n_l] (xacc,
+ * aux may be NULL where unused).  Coarse levels with nc <= 16 and
  * nrhs >= mfma_min_rhs run on the matrix cores.  Errors: SMG_EINVAL. */
 int smg_level_op_f32(smg_handle h, int32_t level, int32_t mode, double coef, const float* x, float* y, float* xacc,
                      const float* aux, int32_t nrhs, void* stream);

@@ -334,7 +334,7 @@ class Solver:
 
     def level_op_f32(self, level: int, x, mode: int = 0, coef: float = 0.0, xacc=None, aux=None, stream=None):
         """FP32 level operator with the V-cycle's epilogues (smg_level_op_f32);
-        complex64 tensors; returns y (xacc is updated in place for mode 1)."""
+        complex64 tensors; returns y (xacc is updated in place for modes 1 and 3)."""
         def p32(t):
             if t is None:
                 return ctypes.c_void_p()

@@ -217,9 +217,9 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ 
     const size_t o = (size_t)(rhs0 + r) * n + tid;
     if (MODE == 0) {
       y[o] = sum;
-    } else if (MODE == 1) {
+    } else if (MODE == 1 || MODE == 3) {
       const cpx<R> vi = v[o];
-      xacc[o] = xacc[o] + c * vi;
+      xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
       y[o] = vi - c * sum;
     } else {
       y[o] = aux[o] - sum;
@@ -653,6 +653,9 @@ void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int c
   else if (mode == 1)
     hipLaunchKernelGGL((k_coarse<R, 1, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
+  else if (mode == 3)
+    hipLaunchKernelGGL((k_coarse<R, 3, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+                       aux);
   else
     hipLaunchKernelGGL((k_coarse<R, 2, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
@@ -835,10 +838,10 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
       const size_t o = ob + dof;
       if (MODE == 0) {
         y[o] = sum;
-      } else if (MODE == 1) {
+      } else if (MODE == 1 || MODE == 3) {
         const float2 t = vs[(lsc * 16 + dof) * kMfmaRS + j];
         const z32 vi = mk<float>(t.x, t.y);
-        xacc[o] = xacc[o] + c * vi;
+        xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
         y[o] = vi - c * sum;
       } else {
         y[o] = aux[o] - sum;
@@ -859,6 +862,9 @@ void launch_coarse_mfma_t(const z32* L, const z32* x, z32* y, int cx, int ct, in
                        (float)c, xacc, aux, pairs);
   else if (mode == 1)
     hipLaunchKernelGGL((k_coarse_mfma<1, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, xacc, aux, pairs);
+  else if (mode == 3)
+    hipLaunchKernelGGL((k_coarse_mfma<3, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
                        (float)c, xacc, aux, pairs);
   else
     hipLaunchKernelGGL((k_coarse_mfma<2, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,

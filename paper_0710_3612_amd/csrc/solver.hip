@@ -253,14 +253,15 @@ void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, in
 // x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).
 template <typename R>
 void smooth(Ctx& c, Level<R>& lv, const cpx<R>* b, cpx<R>* x, int nrhs) {
-  launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
   const int nu = (int)lv.coefs.size();
+  if (nu == 1) launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
   const cpx<R>* cur = b;
   cpx<R>* bufs[2] = {lv.r, lv.t};
   for (int k = 0; k < nu; ++k) {
     if (k + 1 < nu) {
       cpx<R>* nxt = bufs[k & 1];
-      apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
+      // the first step sets x = c_0 b rather than accumulating into a cleared x
+      apply_op<R>(c, lv, cur, nxt, nrhs, k == 0 ? 3 : 1, lv.coefs[k], x, nullptr);
       cur = nxt;
     } else {
       launch_axpy_const<R>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
@@ -309,13 +310,13 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   Level<R>& lv = Ls[l];
   Level<R>& nx = Ls[l + 1];
   const int nu = (int)lv.coefs.size();
-  // 1. x = R^H b (= R b: the polynomial is real), tracking r = b - A x
-  launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  // 1. x = R^H b (= R b: the polynomial is real), tracking r = b - A x; the
+  // first step starts from x = 0 (mode 3 writes x = c_0 b)
   const cpx<R>* cur = b;
   cpx<R>* bufs[2] = {lv.r, lv.t};
   for (int k = 0; k < nu; ++k) {
     cpx<R>* nxt = bufs[k & 1];
-    apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
+    apply_op<R>(c, lv, cur, nxt, nrhs, k == 0 ? 3 : 1, lv.coefs[k], x, nullptr);
     cur = nxt;
   }
   // 2. r_c = P^H (b - A x)
@@ -349,9 +350,8 @@ void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_c
   Level<float>& nx = c.L32[1];
   const int nu = (int)lv.coefs.size();
   S* bufs[2] = {static_cast<S*>(lv.r_lp), static_cast<S*>(lv.t_lp)};
-  // 1. pre-smoothing from x = 0
-  launch_zero(x, (size_t)nrhs * lv.n * sizeof(z32), c.st);
-  launch_normal_lp<z32, S>(lv.U, b, bufs[0], lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[0], x, nullptr, c.st);
+  // 1. pre-smoothing from x = 0 (mode 3 writes x = c_0 b)
+  launch_normal_lp<z32, S>(lv.U, b, bufs[0], lv.lx, lv.lt, lv.diag, nrhs, 3, lv.coefs[0], x, nullptr, c.st);
   const S* cur = bufs[0];
   for (int k = 1; k < nu; ++k) {
     S* nxt = bufs[k & 1];
@@ -1371,8 +1371,8 @@ int smg_level_op_f32(smg_handle h, int32_t level, int32_t mode, double coef, con
   Ctx* c = H(h);
   check_level(c, level);
   check_nrhs(nrhs);
-  if (mode < 0 || mode > 2) throw Error(SMG_EINVAL, "mode must be 0, 1 or 2");
-  if (!x || !y || (mode == 1 && !xacc) || (mode == 2 && !aux)) throw Error(SMG_EINVAL, "null vector");
+  if (mode < 0 || mode > 3) throw Error(SMG_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (!x || !y || ((mode == 1 || mode == 3) && !xacc) || (mode == 2 && !aux)) throw Error(SMG_EINVAL, "null vector");
   if (!std::isfinite(coef)) throw Error(SMG_EINVAL, "coef must be finite");
   c->st = (hipStream_t)stream;
   ensure_f32(*c);

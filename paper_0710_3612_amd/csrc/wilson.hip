@@ -114,10 +114,10 @@ __global__ void __launch_bounds__(kThreads) k_normal2(const cpx<R>* __restrict__
   const size_t i0 = off + 2 * s, i1 = i0 + 1;
   if (MODE == 0) {
     y[i0] = o0; y[i1] = o1;
-  } else if (MODE == 1) {
+  } else if (MODE == 1 || MODE == 3) {
     const cpx<R> v0 = x[i0], v1 = x[i1];
-    xacc[i0] = xacc[i0] + c * v0;
-    xacc[i1] = xacc[i1] + c * v1;
+    xacc[i0] = MODE == 3 ? c * v0 : xacc[i0] + c * v0;
+    xacc[i1] = MODE == 3 ? c * v1 : xacc[i1] + c * v1;
     y[i0] = v0 - c * o0;
     y[i1] = v1 - c * o1;
   } else {
@@ -312,10 +312,10 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
         stv(y, i0, o0);
         stv(y, i1, o1);
       }
-    } else if (MODE == 1) {
+    } else if (MODE == 1 || MODE == 3) {
       const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      xacc[i0] = xacc[i0] + c * v0;
-      xacc[i1] = xacc[i1] + c * v1;
+      xacc[i0] = MODE == 3 ? c * v0 : xacc[i0] + c * v0;
+      xacc[i1] = MODE == 3 ? c * v1 : xacc[i1] + c * v1;
       stv(y, i0, v0 - c * o0);
       stv(y, i1, v1 - c * o1);
     } else {
@@ -361,6 +361,10 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
       break;
     case 1:
       hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 1, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
+                         (R)c, xacc, aux);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 3, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
                          (R)c, xacc, aux);
       break;
     default:
@@ -432,6 +436,10 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
       hipLaunchKernelGGL((k_normal2<R, 1>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
                          xacc, aux);
       break;
+    case 3:
+      hipLaunchKernelGGL((k_normal2<R, 3>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
+                         xacc, aux);
+      break;
     default:
       hipLaunchKernelGGL((k_normal2<R, 2>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
                          xacc, aux);
@@ -448,6 +456,9 @@ void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double di
                        lt, (float)diag, (float)c, xacc, aux);
   else if (mode == 1)
     hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 1, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
+                       lt, (float)diag, (float)c, xacc, aux);
+  else if (mode == 3)
+    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 3, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
                        lt, (float)diag, (float)c, xacc, aux);
   else
     hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 2, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,

@@ -2,7 +2,7 @@
 
 The coarse operator of Eq. 2 applied to many right-hand sides runs on
 v_mfma_f32_32x32x2f32 for levels with nc <= 16.  Each mode (plain apply, one
-frozen MR smoother step, residual) is compared with the oracle's sparse coarse
+frozen MR smoother step, residual, first smoother step from a zero iterate) is compared with the oracle's sparse coarse
 matrix in FP64 on the same FP32-rounded inputs, and with the vector-ALU path.
 Inputs and links are rounded to FP32 (unit roundoff 6e-8) and an output sums at
 most 9 * 16 complex products, so 2e-5 of the column's largest entry bounds the
@@ -103,11 +103,16 @@ def test_mfma_coarse_modes(hier, nrhs):
             y1 = host(s.level_op_f32(level, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
             a1 = host(xacc).reshape(nrhs, n)
             y2 = host(s.level_op_f32(level, xt, mode=2, aux=dev(aux, np.complex64))).reshape(nrhs, n)
+            xacc3 = dev(acc0, np.complex64)
+            y3 = host(s.level_op_f32(level, xt, mode=3, coef=coef, xacc=xacc3)).reshape(nrhs, n)
+            a3 = host(xacc3).reshape(nrhs, n)
             torch.cuda.synchronize()
             assert colerr(y0, Ax) <= TOL32, (name, level, "mode 0")
             assert colerr(y1, x64 - coef * Ax) <= TOL32, (name, level, "mode 1")
             assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (name, level, "mode 1 acc")
             assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL32, (name, level, "mode 2")
+            assert colerr(y3, x64 - coef * Ax) <= TOL32, (name, level, "mode 3")
+            assert colerr(a3, coef * x64) <= TOL32, (name, level, "mode 3 acc")
             got[name] = y0
         assert colerr(got["mfma"], got["valu"].astype(np.complex128)) <= TOL32
 
