@@ -332,8 +332,8 @@ def kernel_source_digest():
 
     text = open(KERNEL_SOURCE).read()
     parts = []
-    for start in ("template <typename R, int MODE, int NR>\n__global__ void __launch_bounds__(kThreads) k_coarse(",
-                  "void launch_coarse_nr(", "void launch_coarse(const cpx<R>* L"):
+    for start in ("template <typename R, int MODE, int NR, int Q>\n__global__ void __launch_bounds__(kThreads) k_coarse(",
+                  "void launch_coarse_q(", "void launch_coarse_nr(", "void launch_coarse(const cpx<R>* L"):
         i = text.index(start)
         parts.append(text[i:text.index("\n}\n", i) + 3])
     return hashlib.sha256("".join(parts).encode()).hexdigest()
@@ -371,7 +371,9 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     dur = timed_events(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
     nbytes = 9 * nc * nc * 8 * cx * ct + 2 * cx * ct * nc * 8
     gbs = nbytes / dur / 1e9
-    return dict(kernel=f"k_coarse<float,0,1>: FP32 coarse 9-point operator, level 1 ({cx}x{ct} sites, nc={nc}), "
+    q = (nc + 3) // 4
+    cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
+    return dict(kernel=f"k_coarse<float,0,1,{cols}>: FP32 coarse 9-point operator, level 1 ({cx}x{ct} sites, nc={nc}), "
                        "single RHS", bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
                 traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes)
 

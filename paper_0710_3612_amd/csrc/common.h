@@ -66,16 +66,13 @@ using z32 = cpx<float>;
 struct alignas(4) bfc { __bf16 re, im; };
 struct alignas(4) hfc { _Float16 re, im; };
 
+// Arithmetic value of a stored element (exact: BF16 and FP16 widen to FP32 exactly).
 template <typename R>
-__device__ inline cpx<R> ldv(const cpx<R>* p, size_t i) { return p[i]; }
-__device__ inline z32 ldv(const bfc* p, size_t i) {
-  const bfc t = p[i];
-  return mk((float)t.re, (float)t.im);
-}
-__device__ inline z32 ldv(const hfc* p, size_t i) {
-  const hfc t = p[i];
-  return mk((float)t.re, (float)t.im);
-}
+__device__ inline cpx<R> widen(cpx<R> t) { return t; }
+__device__ inline z32 widen(bfc t) { return mk((float)t.re, (float)t.im); }
+__device__ inline z32 widen(hfc t) { return mk((float)t.re, (float)t.im); }
+template <typename T>
+__device__ inline auto ldv(const T* p, size_t i) { return widen(p[i]); }
 template <typename R>
 __device__ inline void stv(cpx<R>* p, size_t i, cpx<R> v) { p[i] = v; }
 __device__ inline void stv(bfc* p, size_t i, z32 v) {

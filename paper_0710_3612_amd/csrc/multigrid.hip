@@ -169,8 +169,12 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
 // consecutive words.  A workgroup owns 64 consecutive outputs; its four
 // wavefronts each sum a quarter of the columns for all nine link blocks and the
 // partial sums meet in LDS.  Up to NR right-hand sides share every link load.
+// A wave takes its columns Q at a time and the directions DU at a time (all nine
+// for one FP32 right-hand side, fewer where more registers per load are needed):
+// the column index is clamped rather than branched on and the excess products are
+// masked at use, so every load of a group is issued before the first wait.
 // ---------------------------------------------------------------------------
-template <typename R, int MODE, int NR>
+template <typename R, int MODE, int NR, int Q>
 __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ L, const cpx<R>* __restrict__ v,
                                                      cpx<R>* __restrict__ y, int cx, int ct, int nc, int nrhs, R c,
                                                      cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux) {
@@ -189,18 +193,35 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ 
   if (live) {
     const int K = tid / nc;
     const int Kt = K / cx, Kx = K - Kt * cx;
-    for (int D = 0; D < 9; ++D) {
-      const int dt = D / 3 - 1, dx = D % 3 - 1;
-      int nx = Kx + dx, nt = Kt + dt;
-      nx = nx < 0 ? nx + cx : (nx >= cx ? nx - cx : nx);
-      nt = nt < 0 ? nt + ct : (nt >= ct ? nt - ct : nt);
-      const size_t vn = (size_t)(nt * cx + nx) * nc;
-      const cpx<R>* LD = L + (size_t)D * nc * n + tid;
-      for (int col = c0; col < c1; ++col) {
-        const cpx<R> l = LD[(size_t)col * n];
+    const int xm = Kx == 0 ? cx - 1 : Kx - 1, xp = Kx == cx - 1 ? 0 : Kx + 1;
+    const int tm = Kt == 0 ? ct - 1 : Kt - 1, tp = Kt == ct - 1 ? 0 : Kt + 1;
+    const cpx<R>* vr[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-          if (rhs0 + r < nrhs) fma_acc(acc[r], l, v[(size_t)(rhs0 + r) * n + vn + col]);
+    for (int r = 0; r < NR; ++r) vr[r] = v + (size_t)min(rhs0 + r, nrhs - 1) * n;
+    constexpr int DU = NR >= 4 ? 1 : (NR == 1 && sizeof(R) == 4 ? 9 : 3);
+    for (int cb = c0; cb < c1; cb += Q) {
+#pragma unroll 1
+      for (int D0 = 0; D0 < 9; D0 += DU) {
+#pragma unroll
+      for (int dd = 0; dd < DU; ++dd) {
+        const int D = D0 + dd;
+        const int nt = D / 3 == 0 ? tm : (D / 3 == 1 ? Kt : tp);
+        const int nx = D % 3 == 0 ? xm : (D % 3 == 1 ? Kx : xp);
+        const size_t vn = (size_t)(nt * cx + nx) * nc;
+        const cpx<R>* LD = L + (size_t)D * nc * n + tid;
+        cpx<R> l[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) l[j] = LD[(size_t)min(cb + j, c1 - 1) * n];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            cpx<R> x = vr[r][vn + min(cb + j, c1 - 1)];
+            if (cb + j >= c1 || rhs0 + r >= nrhs) x = mk<R>(0, 0);
+            fma_acc(acc[r], l[j], x);
+          }
+        }
+      }
       }
     }
   }
@@ -642,24 +663,38 @@ void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, i
   HIPCHECK(hipGetLastError());
 }
 
-template <typename R, int NR>
-void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                      double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+template <typename R, int NR, int Q>
+void launch_coarse_q(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+                     double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   const size_t total = (size_t)cx * ct * nc;
   dim3 grid((unsigned)((total + 63) / 64), (nrhs + NR - 1) / NR);
   if (mode == 0)
-    hipLaunchKernelGGL((k_coarse<R, 0, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+    hipLaunchKernelGGL((k_coarse<R, 0, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse<R, 1, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+    hipLaunchKernelGGL((k_coarse<R, 1, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
   else if (mode == 3)
-    hipLaunchKernelGGL((k_coarse<R, 3, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+    hipLaunchKernelGGL((k_coarse<R, 3, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
   else
-    hipLaunchKernelGGL((k_coarse<R, 2, NR>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
+    hipLaunchKernelGGL((k_coarse<R, 2, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
                        aux);
   HIPCHECK(hipGetLastError());
+}
+
+// Columns per pass: a wave's share of the columns (ceil(nc / 4)) in one pass up to
+// 4, in passes of 4 above.
+template <typename R, int NR>
+void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+                      double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  const int q = (nc + 3) / 4;
+  if (q <= 2)
+    launch_coarse_q<R, NR, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else if (q == 3)
+    launch_coarse_q<R, NR, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else
+    launch_coarse_q<R, NR, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
 }
 
 // ---------------------------------------------------------------------------

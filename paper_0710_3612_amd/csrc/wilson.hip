@@ -183,15 +183,68 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
   const size_t off = (size_t)blockIdx.y * 2 * V;
   const TI* __restrict__ xb = x + off;
+  constexpr int NRING = 2 * TX + 2 * TT;
+  static_assert(NRING <= kThreads, "one ring site per thread");
 
-  // ---- stage psi (tile + halo) ----------------------------------------------
-  for (int i = threadIdx.x; i < HT * HX * 2; i += kThreads) {
-    const int comp = i & 1, site = i >> 1;
-    const int ht = site / HX, hx = site - ht * HX;
-    int gx = x0 + hx - 1, gt = t0 + ht - 1;
+  // ---- links, loaded before psi is staged so that both are in flight together
+  const int lxi = threadIdx.x % TX, lti = threadIdx.x / TX;
+  cpx<R> ku0[PER], ku1[PER], ku0m[PER], ku1m[PER], f0[PER], f1[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int gx = x0 + lxi, gt = t0 + lti + k * RG;
+    const int s = gt * lx + gx;
+    ku0[k] = U[s];
+    ku1[k] = U[V + s];
+    ku0m[k] = U[gt * lx + (gx == 0 ? lx - 1 : gx - 1)];
+    ku1m[k] = U[V + (gt == 0 ? lt - 1 : gt - 1) * lx + gx];
+  }
+  // the epilogue's other operand (xacc for a smoother step, aux for a residual), also early
+  cpx<R> ep0[PER], ep1[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const size_t i0 = off + 2 * (size_t)((t0 + lti + k * RG) * lx + x0 + lxi);
+    if (MODE == 1) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
+    if (MODE == 2) { ep0[k] = aux[i0]; ep1[k] = aux[i0 + 1]; }
+  }
+  // ring site of this thread (threads 0 .. NRING-1): halo coordinates, the hop it skips, its links
+  int rhx = 0, rht = 0, rskip = kSkipNone;
+  cpx<R> ru0 = mk<R>(0, 0), ru1 = ru0, ru0m = ru0, ru1m = ru0;
+  if (threadIdx.x < NRING) {
+    const int i = threadIdx.x;
+    if (i < TT) { rhx = 0; rht = i + 1; rskip = kSkipXm; }                        // x = x0 - 1
+    else if (i < 2 * TT) { rhx = TX + 1; rht = i - TT + 1; rskip = kSkipXp; }     // x = x0 + TX
+    else if (i < 2 * TT + TX) { rhx = i - 2 * TT + 1; rht = 0; rskip = kSkipTm; }  // t = t0 - 1
+    else { rhx = i - 2 * TT - TX + 1; rht = TT + 1; rskip = kSkipTp; }             // t = t0 + TT
+    int gx = x0 + rhx - 1, gt = t0 + rht - 1;
     gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
     gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
-    sp[i] = ldv(xb, 2 * (gt * lx + gx) + comp);
+    const int s = gt * lx + gx;
+    if (rskip != kSkipXp) ru0 = U[s];
+    if (rskip != kSkipXm) ru0m = U[gt * lx + (gx == 0 ? lx - 1 : gx - 1)];
+    if (rskip != kSkipTp) ru1 = U[V + s];
+    if (rskip != kSkipTm) ru1m = U[V + (gt == 0 ? lt - 1 : gt - 1) * lx + gx];
+  }
+
+  // ---- stage psi (tile + halo): every load is issued before the first LDS write,
+  // so a workgroup waits for one memory latency, not one per pass
+  constexpr int NSP = HT * HX * 2, NPASS = (NSP + kThreads - 1) / kThreads;
+  TI stage[NPASS];  // raw stored values: widened only after every load has been issued
+#pragma unroll
+  for (int j = 0; j < NPASS; ++j) {
+    const int i = threadIdx.x + j * kThreads;
+    if (i < NSP) {
+      const int comp = i & 1, site = i >> 1;
+      const int ht = site / HX, hx = site - ht * HX;
+      int gx = x0 + hx - 1, gt = t0 + ht - 1;
+      gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
+      gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
+      stage[j] = xb[2 * (gt * lx + gx) + comp];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NPASS; ++j) {
+    const int i = threadIdx.x + j * kThreads;
+    if (i < NSP) sp[i] = widen(stage[j]);
   }
   __syncthreads();
 
@@ -199,8 +252,8 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const R half = (R)0.5;
 
   // D (or a projection of it) at halo coordinates (hx, ht), global (gx, gt).
-  auto d_at = [&](int hx, int ht, int gx, int gt, int skip, cpx<R> u0, cpx<R> u1, cpx<R> u0m, cpx<R> u1m,
-                  cpx<R>& o0, cpx<R>& o1) {
+  auto d_at = [&](int hx, int ht, cpx<R> u0, cpx<R> u1, cpx<R> u0m, cpx<R> u1m, int skip, cpx<R>& o0,
+                  cpx<R>& o1) {
     cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
     if (skip != kSkipXp) hop_acc<R, false>(s0, s1, 0, u0, P(ht, hx + 1, 0), P(ht, hx + 1, 1));
     if (skip != kSkipXm) hop_acc<R, false>(s0, s1, 1, cj(u0m), P(ht, hx - 1, 0), P(ht, hx - 1, 1));
@@ -211,52 +264,26 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   };
 
   // ---- phase 1: phi on the tile ------------------------------------------------
-  const int lxi = threadIdx.x % TX, lti = threadIdx.x / TX;
-  cpx<R> ku0[PER], ku1[PER], ku0m[PER], ku1m[PER], f0[PER], f1[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int r = lti + k * RG;
-    const int gx = x0 + lxi, gt = t0 + r;
-    const int s = gt * lx + gx;
-    const int sxm = gt * lx + (gx == 0 ? lx - 1 : gx - 1);
-    const int stm = (gt == 0 ? lt - 1 : gt - 1) * lx + gx;
-    ku0[k] = U[s];
-    ku1[k] = U[V + s];
-    ku0m[k] = U[sxm];
-    ku1m[k] = U[V + stm];
-    d_at(lxi + 1, r + 1, gx, gt, kSkipNone, ku0[k], ku1[k], ku0m[k], ku1m[k], f0[k], f1[k]);
+    d_at(lxi + 1, r + 1, ku0[k], ku1[k], ku0m[k], ku1m[k], kSkipNone, f0[k], f1[k]);
     sf[(r * TX + lxi) * 2] = f0[k];
     sf[(r * TX + lxi) * 2 + 1] = f1[k];
   }
   // ---- phase 1b: projected phi on the ring -------------------------------------
-  for (int i = threadIdx.x; i < 2 * TX + 2 * TT; i += kThreads) {
-    int hx, ht, skip;
-    if (i < TT) { hx = 0; ht = i + 1; skip = kSkipXm; }                       // x = x0 - 1
-    else if (i < 2 * TT) { hx = TX + 1; ht = i - TT + 1; skip = kSkipXp; }    // x = x0 + TX
-    else if (i < 2 * TT + TX) { hx = i - 2 * TT + 1; ht = 0; skip = kSkipTm; }  // t = t0 - 1
-    else { hx = i - 2 * TT - TX + 1; ht = TT + 1; skip = kSkipTp; }            // t = t0 + TT
-    int gx = x0 + hx - 1, gt = t0 + ht - 1;
-    gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
-    gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
-    const int s = gt * lx + gx;
-    const int sxm = gt * lx + (gx == 0 ? lx - 1 : gx - 1);
-    const int stm = (gt == 0 ? lt - 1 : gt - 1) * lx + gx;
-    const cpx<R> z = mk<R>(0, 0);
-    const cpx<R> u0 = skip == kSkipXp ? z : U[s];
-    const cpx<R> u0m = skip == kSkipXm ? z : U[sxm];
-    const cpx<R> u1 = skip == kSkipTp ? z : U[V + s];
-    const cpx<R> u1m = skip == kSkipTm ? z : U[V + stm];
+  if (threadIdx.x < NRING) {
     cpx<R> o0, o1;
-    d_at(hx, ht, gx, gt, skip, u0, u1, u0m, u1m, o0, o1);
+    d_at(rhx, rht, ru0, ru1, ru0m, ru1m, rskip, o0, o1);
     // D^H at the neighbouring tile site uses: from x0-1 (its -x hop) (1 - s1) -> o0 - o1;
     // from x0+TX (+x hop) (1 + s1) -> o0 + o1; from t0-1 (1 - s2) -> o0 + i o1;
     // from t0+TT (1 + s2) -> o0 - i o1.
     cpx<R> h;
-    if (skip == kSkipXm) h = o0 - o1;
-    else if (skip == kSkipXp) h = o0 + o1;
-    else if (skip == kSkipTm) h = o0 + imul(o1);
+    if (rskip == kSkipXm) h = o0 - o1;
+    else if (rskip == kSkipXp) h = o0 + o1;
+    else if (rskip == kSkipTm) h = o0 + imul(o1);
     else h = o0 - imul(o1);
-    sr[i] = h;
+    sr[threadIdx.x] = h;
   }
   __syncthreads();
 
@@ -314,13 +341,13 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       }
     } else if (MODE == 1 || MODE == 3) {
       const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      xacc[i0] = MODE == 3 ? c * v0 : xacc[i0] + c * v0;
-      xacc[i1] = MODE == 3 ? c * v1 : xacc[i1] + c * v1;
+      xacc[i0] = MODE == 3 ? c * v0 : ep0[k] + c * v0;
+      xacc[i1] = MODE == 3 ? c * v1 : ep1[k] + c * v1;
       stv(y, i0, v0 - c * o0);
       stv(y, i1, v1 - c * o1);
     } else {
-      stv(y, i0, aux[i0] - o0);
-      stv(y, i1, aux[i1] - o1);
+      stv(y, i0, ep0[k] - o0);
+      stv(y, i1, ep1[k] - o1);
     }
   }
 }
@@ -374,30 +401,16 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
   HIPCHECK(hipGetLastError());
 }
 
-// Tile shape of the fused kernel, from measurements on MI355X at 2048^2 and 4096^2:
-//   FP64 with a working set (psi + links + y = 96 B/site) above 1 GB: 64x4;
-//   smaller FP64 lattices: 64x8 with non-temporal output stores; FP32: 32x16
-//   with non-temporal output stores.
+// Tile shape of the fused kernel, from measurements on MI355X at 1024^2 to 4096^2
+// (all loads of a workgroup issued before its first wait): 64x8 with non-temporal
+// output stores is the fastest in both precisions at every size; 32x16 comes next.
 // Shapes that do not divide the lattice fall back to the next one that does;
 // kTileNone means no tile fits and A is applied as D followed by D^H.
 enum { kTileNone = 0, kT64x4, kT64x8nt, kT32x16nt, kT32x8, kT16x16 };
 
 template <typename R>
 int fused_shape(int lx, int lt) {
-  const double ws = 96.0 * (sizeof(R) / 8.0) * lx * lt;
-  const bool big = ws > 1024.0 * (1 << 20);
-  int pref[4];
-  if (sizeof(R) == 8) {
-    pref[0] = big ? kT64x4 : kT64x8nt;
-    pref[1] = big ? kT64x8nt : kT64x4;
-    pref[2] = kT32x16nt;
-    pref[3] = kT32x8;
-  } else {
-    pref[0] = kT32x16nt;
-    pref[1] = kT64x8nt;
-    pref[2] = kT64x4;
-    pref[3] = kT32x8;
-  }
+  const int pref[4] = {kT64x8nt, kT32x16nt, kT64x4, kT32x8};
   auto fits = [&](int sh) {
     switch (sh) {
       case kT64x4: return lx % 64 == 0 && lt % 4 == 0;
