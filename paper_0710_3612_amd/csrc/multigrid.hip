@@ -18,7 +18,8 @@ namespace smg {
 
 namespace {
 
-__device__ inline double wave_sum(double v) {
+template <typename T>
+__device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
@@ -60,10 +61,13 @@ __device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
 // The result goes to out[k * ostride_k] (plain restriction or a column of the
 // Galerkin links).
 // ---------------------------------------------------------------------------
-template <typename R, int NCH, typename TX = cpx<R>>
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1>
 __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __restrict__ x, int K, int lx,
                                     int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
                                     cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1) {
+  // KW inner products per pass: their P rows are all requested before the first
+  // is used (k clamped to nc - 1, window index clamped to nagg - 1; the excess
+  // products are zeroed through xv and the excess results are not stored).
   const int lane = threadIdx.x & 63;
   const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
   cpx<R> xv[NCH];
@@ -73,25 +77,41 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __re
     xv[c] = (i < nagg) ? ldv(x, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<R>(0, 0);
   }
   const cpx<R>* PK = P + (size_t)K * ldk * nagg;
-  for (int k = kbeg; k < nc; k += kstep) {
-    double re = 0, im = 0;
+  for (int k0 = kbeg; k0 < nc; k0 += KW * kstep) {
+    cpx<R> p[KW][NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int i = lane + 64 * c;
-      if (i < nagg) {
-        const cpx<R> p = PK[(size_t)k * nagg + i];
-        re += (double)p.re * xv[c].re + (double)p.im * xv[c].im;
-        im += (double)p.re * xv[c].im - (double)p.im * xv[c].re;
+    for (int j = 0; j < KW; ++j) {
+      const int k = min(k0 + j * kstep, nc - 1);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) p[j][c] = PK[(size_t)k * nagg + min(lane + 64 * c, nagg - 1)];
+    }
+    R re[KW], im[KW];
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      re[j] = 0;
+      im[j] = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        re[j] += p[j][c].re * xv[c].re + p[j][c].im * xv[c].im;
+        im[j] += p[j][c].re * xv[c].im - p[j][c].im * xv[c].re;
       }
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) out[(size_t)k * ostride_k] = mk<R>((R)re, (R)im);
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      re[j] = wave_sum(re[j]);
+      im[j] = wave_sum(im[j]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < KW; ++j)
+        if (k0 + j * kstep < nc) out[(size_t)(k0 + j * kstep) * ostride_k] = mk<R>(re[j], im[j]);
+    }
   }
 }
 
-// One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...
-template <typename R, int NCH, typename TX = cpx<R>>
+// One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...,
+// KW of them per pass.
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1>
 __global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const TX* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
                                                        int bt, int h, int nc, int ldk) {
@@ -100,8 +120,29 @@ __global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict_
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
   const int rhs = blockIdx.y;
-  restrict_one<R, NCH, TX>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
-                           y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
+  restrict_one<R, NCH, TX, KW>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                               y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
+}
+
+// k_restrict with KW = the inner products of one wave (ceil(nc / 4)), at most 4 per
+// pass and at most 64 words of P rows in flight per lane.
+template <typename R, int NCH, typename TX>
+void launch_restrict_kw(dim3 grid, hipStream_t st, const cpx<R>* P, const TX* x, cpx<R>* y, int lx, int lt, int dof,
+                        int bx, int bt, int h, int nc, int ldk) {
+  const int cap = (int)(64 / (NCH * sizeof(cpx<R>) / sizeof(float)));
+  const int q = std::min((nc + 3) / 4, std::max(cap, 1));
+  if (q <= 1)
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 1>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
+                       ldk);
+  else if (q == 2)
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 2>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
+                       ldk);
+  else if (q == 3)
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 3>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
+                       ldk);
+  else
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 4>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
+                       ldk);
 }
 
 // Prolongation y (+)= P e in two deterministic phases.
@@ -117,7 +158,18 @@ __global__ void __launch_bounds__(kThreads) k_prolong_win(const cpx<R>* __restri
   const cpx<R>* PK = P + (size_t)K * ldk * nw + i;
   const cpx<R>* eK = e + ((size_t)rhs * nK + K) * nc;
   cpx<R> acc = mk<R>(0, 0);
-  for (int k = 0; k < nc; ++k) fma_acc(acc, PK[(size_t)k * nw], eK[k]);
+  for (int k0 = 0; k0 < nc; k0 += 4) {  // four columns per group, index clamped: loads in flight together
+    cpx<R> pv[4], ev[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = min(k0 + j, nc - 1);
+      pv[j] = PK[(size_t)k * nw];
+      ev[j] = eK[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (k0 + j < nc) fma_acc(acc, pv[j], ev[j]);
+  }
   wbuf[(size_t)rhs * nK * nw + idx] = acc;
 }
 
@@ -136,6 +188,8 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
   const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
   const int t = site / lx, x = site - t * lx;
   const cpx<R>* wb = wbuf + (size_t)rhs * nK * nw;
+  const size_t o = (size_t)rhs * n + idx;
+  const cpx<R> y0 = MODE == 1 ? y[o] : mk<R>(0, 0);  // requested early, added last
   cpx<R> acc = mk<R>(0, 0);
   int jts[3], njt = 0, jxs[3], njx = 0;
   for (int q = -h; q <= h; ++q) {  // distinct candidate blocks
@@ -156,11 +210,7 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
       acc = acc + wb[(size_t)(jts[a] * cx + jxs[b]) * nw + ((ot + h) * wxw + (ox + h)) * dof + d];
     }
   }
-  const size_t o = (size_t)rhs * n + idx;
-  if (MODE == 0)
-    y[o] = acc;
-  else
-    y[o] = y[o] + acc;
+  y[o] = MODE == 0 ? acc : y0 + acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -623,8 +673,7 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
-    hipLaunchKernelGGL((k_restrict<R, decltype(c)::v>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h,
-                       nc, ldk);
+    launch_restrict_kw<R, decltype(c)::v, cpx<R>>(grid, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
   });
   HIPCHECK(hipGetLastError());
 }
@@ -636,8 +685,7 @@ void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int d
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
-    hipLaunchKernelGGL((k_restrict<float, decltype(c)::v, TI>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof,
-                       bx, bt, h, nc, ldk);
+    launch_restrict_kw<float, decltype(c)::v, TI>(grid, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
   });
   HIPCHECK(hipGetLastError());
 }
