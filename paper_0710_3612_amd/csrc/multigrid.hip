@@ -1065,13 +1065,24 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const cpx<RM>* __restri
   const cpx<R>* xb = x + (size_t)blockIdx.y * n;
   const cpx<RM>* Mr = M + (size_t)row * n;
   double re = 0, im = 0;
-  for (int j = lane; j < n; j += 64) {
-    const cpx<RM> m = Mr[j];
-    const cpx<R> v = xb[j];
-    re = fma((double)m.re, (double)v.re, re);
-    re = fma(-(double)m.im, (double)v.im, re);
-    im = fma((double)m.re, (double)v.im, im);
-    im = fma((double)m.im, (double)v.re, im);
+  constexpr int U = 8;  // row segments per group: their loads are in flight together (index clamped)
+  for (int j0 = lane; j0 < n; j0 += 64 * U) {
+    cpx<RM> m[U];
+    cpx<R> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = min(j0 + 64 * u, n - 1);
+      m[u] = Mr[j];
+      v[u] = xb[j];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j0 + 64 * u >= n) v[u] = mk<R>(0, 0);  // a clamped duplicate contributes nothing
+      re = fma((double)m[u].re, (double)v[u].re, re);
+      re = fma(-(double)m[u].im, (double)v[u].im, re);
+      im = fma((double)m[u].re, (double)v[u].im, im);
+      im = fma((double)m[u].im, (double)v[u].re, im);
+    }
   }
   re = wave_sum(re);
   im = wave_sum(im);

@@ -401,16 +401,25 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
   HIPCHECK(hipGetLastError());
 }
 
-// Tile shape of the fused kernel, from measurements on MI355X at 1024^2 to 4096^2
+// Tile shape of the fused kernel, from measurements on MI355X at 256^2 to 4096^2
 // (all loads of a workgroup issued before its first wait): 64x8 with non-temporal
-// output stores is the fastest in both precisions at every size; 32x16 comes next.
-// Shapes that do not divide the lattice fall back to the next one that does;
-// kTileNone means no tile fits and A is applied as D followed by D^H.
+// output stores is the fastest in both precisions once the lattice has at least
+// 256 (FP64) or 1024 (FP32) such tiles; smaller lattices run faster on 16x16 tiles
+// (one site per thread, twice the workgroups).  Shapes that do not divide the
+// lattice fall back to the next one that does; kTileNone means no tile fits and A
+// is applied as D followed by D^H.
 enum { kTileNone = 0, kT64x4, kT64x8nt, kT32x16nt, kT32x8, kT16x16 };
 
 template <typename R>
 int fused_shape(int lx, int lt) {
-  const int pref[4] = {kT64x8nt, kT32x16nt, kT64x4, kT32x8};
+  const bool small = (long)lx * lt / 512 < (sizeof(R) == 8 ? 256 : 1024);
+  int pref[4] = {kT64x8nt, kT32x16nt, kT64x4, kT32x8};
+  if (small) {
+    pref[0] = kT16x16;
+    pref[1] = kT32x8;
+    pref[2] = kT64x8nt;
+    pref[3] = kT32x16nt;
+  }
   auto fits = [&](int sh) {
     switch (sh) {
       case kT64x4: return lx % 64 == 0 && lt % 4 == 0;
