@@ -66,7 +66,7 @@ enum {
 enum { SMG_COARSEST_DIRECT = 0, SMG_COARSEST_CG = 1 };
 enum { SMG_FP64 = 0, SMG_MIXED = 1 };
 
-/* storage of the FP32 V-cycle's fine-level smoother iterates */
+/* reduced-precision storage in the FP32 V-cycle (smoother iterates, operators) */
 enum { SMG_STORE_F32 = 0, SMG_STORE_BF16 = 1, SMG_STORE_F16 = 2 };
 
 typedef struct smg_ctx* smg_handle;
@@ -103,6 +103,12 @@ typedef struct {
                                      sides run on the matrix cores (MFMA FP32, levels with
                                      nc <= 16); 1 = always, 0 = never.  Results differ from
                                      the vector-ALU path by FP32 rounding only. */
+  int32_t operator_storage;       /* mixed precision: storage of the FP32 V-cycle's coarse
+                                     links (vector-ALU path; the matrix-core path keeps FP32),
+                                     prolongators and coarsest dense inverse, SMG_STORE_F32 or
+                                     SMG_STORE_F16 (each array scaled by a power of two so
+                                     that its entries are at most 1; arithmetic stays FP32,
+                                     the outer FP64 correction sets the final accuracy) */
 } smg_params;
 
 typedef struct {
@@ -118,7 +124,8 @@ typedef struct {
 /* Fill *p with the defaults: 2 levels of 4x4 blocks, Nv = 8, setup_iters = 5,
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
- * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16. */
+ * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16,
+ * operator_storage = SMG_STORE_F32. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).

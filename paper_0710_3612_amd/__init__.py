@@ -78,6 +78,7 @@ class Params(ctypes.Structure):
         ("smoother_storage", ctypes.c_int32),
         ("stop_recursive", ctypes.c_int32),
         ("mfma_min_rhs", ctypes.c_int32),
+        ("operator_storage", ctypes.c_int32),
     ]
 
 
@@ -180,7 +181,8 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 smoother_omega: float = 0.8, t_antiperiodic: bool = True, coarsest: int = COARSEST_DIRECT,
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
                 seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16,
-                smoother_storage: int = STORE_F32, stop_recursive: bool = False) -> Params:
+                smoother_storage: int = STORE_F32, stop_recursive: bool = False,
+                operator_storage: int = STORE_F32) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -201,6 +203,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.mfma_min_rhs = mfma_min_rhs
     p.smoother_storage = smoother_storage
     p.stop_recursive = int(bool(stop_recursive))
+    p.operator_storage = operator_storage
     return p
 
 

@@ -139,10 +139,12 @@ template <typename TI, typename TO>
 void launch_normal_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
                       z32* xacc, const z32* aux, hipStream_t st);
 bool normal_lp_fits(int lx, int lt);
-// P^H x for a fine vector stored as TI; x += a y for y stored as TI.
-template <typename TI>
-void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h, int nc,
-                        int ldk, int nrhs, hipStream_t st);
+// FP32 P^H x with P stored as TP (z32, or hfc scaled by 1 / ps) and x stored as TI
+// (z32, bfc or hfc).
+template <typename TP, typename TI>
+void launch_restrict_s(const TP* P, float ps, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h,
+                       int nc, int ldk, int nrhs, hipStream_t st);
+// x += a y for y stored as TI.
 template <typename TI>
 void launch_axpy_const_lp(z32* y, const TI* x, double a, size_t n, int nrhs, hipStream_t st);
 // Zero fill by a kernel (bytes a multiple of 8).
@@ -152,6 +154,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t st);
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                    double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+// The same with the links stored in FP16 scaled by 1 / lscale (a power of two).
+void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
+                       double c, z32* xacc, const z32* aux, hipStream_t st);
 // Matrix-core (MFMA FP32) coarse apply for 1 <= nc <= 16, any number of right-hand sides.
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                         z32* xacc, const z32* aux, hipStream_t st);
@@ -166,6 +171,10 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
                     int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
+
+// FP32 prolongation with P stored in FP16 scaled by 1 / ps.
+void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,
+                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
 
 // Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
@@ -188,6 +197,12 @@ void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hip
 // Y = M X, M dense row-major n x n in precision RM, X and Y [nrhs][n].
 template <typename RM, typename R>
 void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
+// FP32 y = M x with M stored in FP16 scaled by 1 / mscale (a power of two).
+void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st);
+// Per-block maxima of max(|re|, |im|) over n values into part[0 .. blocks).
+void launch_absmax_partial(const z64* a, size_t n, double* part, int blocks, hipStream_t st);
+// out = FP16(in * inv_scale).
+void launch_convert_h16(const z64* in, hfc* out, size_t n, double inv_scale, hipStream_t st);
 
 // Level-1 BLAS (batched over nrhs columns of length n).
 // Scratch of the reductions: per column `nb` block partials.

@@ -18,6 +18,11 @@ namespace smg {
 
 namespace {
 
+template <int N>
+struct IntC {
+  static constexpr int v = N;
+};
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -61,10 +66,11 @@ __device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
 // The result goes to out[k * ostride_k] (plain restriction or a column of the
 // Galerkin links).
 // ---------------------------------------------------------------------------
-template <typename R, int NCH, typename TX = cpx<R>, int KW = 1>
-__device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __restrict__ x, int K, int lx,
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>>
+__device__ inline void restrict_one(const TP* __restrict__ P, const TX* __restrict__ x, int K, int lx,
                                     int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
-                                    cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1) {
+                                    cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1,
+                                    R ps = 1) {
   // KW inner products per pass: their P rows are all requested before the first
   // is used (k clamped to nc - 1, window index clamped to nagg - 1; the excess
   // products are zeroed through xv and the excess results are not stored).
@@ -76,14 +82,14 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __re
     const int i = lane + 64 * c;
     xv[c] = (i < nagg) ? ldv(x, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<R>(0, 0);
   }
-  const cpx<R>* PK = P + (size_t)K * ldk * nagg;
+  const TP* PK = P + (size_t)K * ldk * nagg;
   for (int k0 = kbeg; k0 < nc; k0 += KW * kstep) {
     cpx<R> p[KW][NCH];
 #pragma unroll
     for (int j = 0; j < KW; ++j) {
       const int k = min(k0 + j * kstep, nc - 1);
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) p[j][c] = PK[(size_t)k * nagg + min(lane + 64 * c, nagg - 1)];
+      for (int c = 0; c < NCH; ++c) p[j][c] = widen(PK[(size_t)k * nagg + min(lane + 64 * c, nagg - 1)]);
     }
     R re[KW], im[KW];
 #pragma unroll
@@ -104,58 +110,61 @@ __device__ inline void restrict_one(const cpx<R>* __restrict__ P, const TX* __re
     if (lane == 0) {
 #pragma unroll
       for (int j = 0; j < KW; ++j)
-        if (k0 + j * kstep < nc) out[(size_t)(k0 + j * kstep) * ostride_k] = mk<R>(re[j], im[j]);
+        if (k0 + j * kstep < nc) out[(size_t)(k0 + j * kstep) * ostride_k] = mk<R>(ps * re[j], ps * im[j]);
     }
   }
 }
 
 // One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...,
 // KW of them per pass.
-template <typename R, int NCH, typename TX = cpx<R>, int KW = 1>
-__global__ void __launch_bounds__(kThreads) k_restrict(const cpx<R>* __restrict__ P, const TX* __restrict__ x,
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>>
+__global__ void __launch_bounds__(kThreads) k_restrict(const TP* __restrict__ P, const TX* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                       int bt, int h, int nc, int ldk) {
+                                                       int bt, int h, int nc, int ldk, R ps) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x;
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
   const int rhs = blockIdx.y;
-  restrict_one<R, NCH, TX, KW>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
-                               y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64);
+  restrict_one<R, NCH, TX, KW, TP>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                                   y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64,
+                                   ps);
 }
 
 // k_restrict with KW = the inner products of one wave (ceil(nc / 4)), at most 4 per
 // pass and at most 64 words of P rows in flight per lane.
-template <typename R, int NCH, typename TX>
-void launch_restrict_kw(dim3 grid, hipStream_t st, const cpx<R>* P, const TX* x, cpx<R>* y, int lx, int lt, int dof,
-                        int bx, int bt, int h, int nc, int ldk) {
+template <typename R, int NCH, typename TX, typename TP>
+void launch_restrict_kw(dim3 grid, hipStream_t st, const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt,
+                        int dof, int bx, int bt, int h, int nc, int ldk) {
   const int cap = (int)(64 / (NCH * sizeof(cpx<R>) / sizeof(float)));
   const int q = std::min((nc + 3) / 4, std::max(cap, 1));
+  auto go = [&](auto kw) {
+    constexpr int KW = decltype(kw)::v;
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, KW, TP>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt,
+                       h, nc, ldk, ps);
+  };
   if (q <= 1)
-    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 1>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
-                       ldk);
+    go(IntC<1>{});
   else if (q == 2)
-    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 2>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
-                       ldk);
+    go(IntC<2>{});
   else if (q == 3)
-    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 3>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
-                       ldk);
+    go(IntC<3>{});
   else
-    hipLaunchKernelGGL((k_restrict<R, NCH, TX, 4>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc,
-                       ldk);
+    go(IntC<4>{});
 }
 
 // Prolongation y (+)= P e in two deterministic phases.
 // Phase 1: per aggregate window, w[K][i] = sum_k P[K][k][i] e[K][k] (lanes walk the
 // window variables, so P rows are read coalesced and e is a broadcast).
-template <typename R>
-__global__ void __launch_bounds__(kThreads) k_prolong_win(const cpx<R>* __restrict__ P, const cpx<R>* __restrict__ e,
-                                                          cpx<R>* __restrict__ wbuf, int nK, int nw, int nc, int ldk) {
+template <typename R, typename TP = cpx<R>>
+__global__ void __launch_bounds__(kThreads) k_prolong_win(const TP* __restrict__ P, const cpx<R>* __restrict__ e,
+                                                          cpx<R>* __restrict__ wbuf, int nK, int nw, int nc, int ldk,
+                                                          R ps) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nK * nw) return;
   const int K = (int)(idx / nw), i = (int)(idx - (size_t)K * nw);
   const int rhs = blockIdx.y;
-  const cpx<R>* PK = P + (size_t)K * ldk * nw + i;
+  const TP* PK = P + (size_t)K * ldk * nw + i;
   const cpx<R>* eK = e + ((size_t)rhs * nK + K) * nc;
   cpx<R> acc = mk<R>(0, 0);
   for (int k0 = 0; k0 < nc; k0 += 4) {  // four columns per group, index clamped: loads in flight together
@@ -163,14 +172,14 @@ __global__ void __launch_bounds__(kThreads) k_prolong_win(const cpx<R>* __restri
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int k = min(k0 + j, nc - 1);
-      pv[j] = PK[(size_t)k * nw];
+      pv[j] = widen(PK[(size_t)k * nw]);
       ev[j] = eK[k];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (k0 + j < nc) fma_acc(acc, pv[j], ev[j]);
   }
-  wbuf[(size_t)rhs * nK * nw + idx] = acc;
+  wbuf[(size_t)rhs * nK * nw + idx] = ps * acc;
 }
 
 // Phase 2: every fine variable sums the window values that cover it (one window
@@ -224,10 +233,11 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
 // the column index is clamped rather than branched on and the excess products are
 // masked at use, so every load of a group is issued before the first wait.
 // ---------------------------------------------------------------------------
-template <typename R, int MODE, int NR, int Q>
-__global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ L, const cpx<R>* __restrict__ v,
+template <typename R, int MODE, int NR, int Q, typename TL = cpx<R>>
+__global__ void __launch_bounds__(kThreads) k_coarse(const TL* __restrict__ L, const cpx<R>* __restrict__ v,
                                                      cpx<R>* __restrict__ y, int cx, int ct, int nc, int nrhs, R c,
-                                                     cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux) {
+                                                     cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux,
+                                                     R lscale) {
   __shared__ cpx<R> part[3][NR][64];
   const int nK = cx * ct;
   const size_t n = (size_t)nK * nc;
@@ -258,10 +268,10 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ 
         const int nt = D / 3 == 0 ? tm : (D / 3 == 1 ? Kt : tp);
         const int nx = D % 3 == 0 ? xm : (D % 3 == 1 ? Kx : xp);
         const size_t vn = (size_t)(nt * cx + nx) * nc;
-        const cpx<R>* LD = L + (size_t)D * nc * n + tid;
+        const TL* LD = L + (size_t)D * nc * n + tid;
         cpx<R> l[Q];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) l[j] = LD[(size_t)min(cb + j, c1 - 1) * n];
+        for (int j = 0; j < Q; ++j) l[j] = widen(LD[(size_t)min(cb + j, c1 - 1) * n]);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
 #pragma unroll
@@ -284,7 +294,8 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const cpx<R>* __restrict__ 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (rhs0 + r >= nrhs) break;
-    const cpx<R> sum = acc[r] + part[0][r][lane] + part[1][r][lane] + part[2][r][lane];
+    // lscale: power-of-two scale of reduced-precision links (1 otherwise): exact
+    const cpx<R> sum = lscale * (acc[r] + part[0][r][lane] + part[1][r][lane] + part[2][r][lane]);
     const size_t o = (size_t)(rhs0 + r) * n + tid;
     if (MODE == 0) {
       y[o] = sum;
@@ -523,9 +534,9 @@ __global__ void k_gj_update(z64* __restrict__ M, int n, int k, const z64* __rest
 // result does not depend on nrhs or on the other columns.
 constexpr int kGemmTR = 64, kGemmTC = 32, kGemmTJ = 16;
 
-template <typename RM, typename R>
-__global__ void __launch_bounds__(kThreads) k_dense_gemm(const cpx<RM>* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                         cpx<R>* __restrict__ y, int n, int nrhs) {
+template <typename RM, typename R, typename TM = cpx<RM>>
+__global__ void __launch_bounds__(kThreads) k_dense_gemm(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                         cpx<R>* __restrict__ y, int n, int nrhs, double mscale) {
   __shared__ cpx<RM> Ms[kGemmTJ][kGemmTR + 1];
   __shared__ cpx<RM> Xs[kGemmTJ][kGemmTC + 1];
   const int r0 = blockIdx.x * kGemmTR, c0 = blockIdx.y * kGemmTC;
@@ -542,7 +553,7 @@ __global__ void __launch_bounds__(kThreads) k_dense_gemm(const cpx<RM>* __restri
       const int e = t + q * kThreads;
       const int row = e / kGemmTJ, jj = e % kGemmTJ;
       const int gr = r0 + row, gj = j0 + jj;
-      Ms[jj][row] = (gr < n && gj < n) ? M[(size_t)gr * n + gj] : mk<RM>(0, 0);
+      Ms[jj][row] = (gr < n && gj < n) ? widen(M[(size_t)gr * n + gj]) : mk<RM>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < kGemmTC * kGemmTJ / kThreads; ++q) {
@@ -581,7 +592,8 @@ __global__ void __launch_bounds__(kThreads) k_dense_gemm(const cpx<RM>* __restri
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int gr = r0 + tr + 32 * a, gc = c0 + tc + 8 * k;
-      if (gr < n && gc < nrhs) y[(size_t)gc * n + gr] = mk<R>((R)are[a][k], (R)aim[a][k]);
+      if (gr < n && gc < nrhs)
+        y[(size_t)gc * n + gr] = mk<R>((R)(mscale * are[a][k]), (R)(mscale * aim[a][k]));
     }
 }
 
@@ -645,11 +657,6 @@ __global__ void k_copy_convert(const z64* __restrict__ in, cpx<Ro>* __restrict__
     out[i] = cvt<Ro>(in[i]);
 }
 
-template <int N>
-struct IntC {
-  static constexpr int v = N;
-};
-
 // Dispatch on the number of 64-lane (or 256-thread) chunks covering an aggregate.
 template <typename F>
 void dispatch_chunks(int chunks, F&& f) {
@@ -666,42 +673,48 @@ void dispatch_chunks(int chunks, F&& f) {
 
 int colors_along(int extent) { return extent < 3 ? extent : 3 + (extent - 3 * (extent / 3)); }
 
+template <typename R, typename TP, typename TX>
+void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
+                       int nc, int ldk, int nrhs, hipStream_t st) {
+  const int nK = (lx / bx) * (lt / bt);
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  dim3 grid(nK, nrhs);
+  dispatch_chunks((nw + 63) / 64, [&](auto c) {
+    launch_restrict_kw<R, decltype(c)::v, TX, TP>(grid, st, P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename R>
 void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                      int nc, int ldk, int nrhs, hipStream_t st) {
-  const int nK = (lx / bx) * (lt / bt);
-  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
-  dim3 grid(nK, nrhs);
-  dispatch_chunks((nw + 63) / 64, [&](auto c) {
-    launch_restrict_kw<R, decltype(c)::v, cpx<R>>(grid, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
-  });
-  HIPCHECK(hipGetLastError());
+  launch_restrict_t<R, cpx<R>, cpx<R>>(P, (R)1, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, st);
 }
 
-template <typename TI>
-void launch_restrict_lp(const z32* P, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h, int nc,
-                        int ldk, int nrhs, hipStream_t st) {
-  const int nK = (lx / bx) * (lt / bt);
-  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
-  dim3 grid(nK, nrhs);
-  dispatch_chunks((nw + 63) / 64, [&](auto c) {
-    launch_restrict_kw<float, decltype(c)::v, TI>(grid, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
-  });
-  HIPCHECK(hipGetLastError());
+template <typename TP, typename TI>
+void launch_restrict_s(const TP* P, float ps, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h,
+                       int nc, int ldk, int nrhs, hipStream_t st) {
+  launch_restrict_t<float, TP, TI>(P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, st);
 }
-template void launch_restrict_lp<bfc>(const z32*, const bfc*, z32*, int, int, int, int, int, int, int, int, int,
-                                      hipStream_t);
-template void launch_restrict_lp<hfc>(const z32*, const hfc*, z32*, int, int, int, int, int, int, int, int, int,
-                                      hipStream_t);
+#define INST_RS(TP, TI)                                                                                         \
+  template void launch_restrict_s<TP, TI>(const TP*, float, const TI*, z32*, int, int, int, int, int, int, int, \
+                                          int, int, hipStream_t);
+INST_RS(z32, z32)
+INST_RS(z32, bfc)
+INST_RS(z32, hfc)
+INST_RS(hfc, z32)
+INST_RS(hfc, bfc)
+INST_RS(hfc, hfc)
+#undef INST_RS
 
-template <typename R>
-void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+template <typename R, typename TP>
+void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
+                      int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   const size_t nkw = (size_t)nK * nw;
-  hipLaunchKernelGGL((k_prolong_win<R>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs), dim3(kThreads), 0,
-                     st, P, e, wbuf, nK, nw, nc, ldk);
+  hipLaunchKernelGGL((k_prolong_win<R, TP>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs), dim3(kThreads),
+                     0, st, P, e, wbuf, nK, nw, nc, ldk, ps);
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
   if (mode == 0)
@@ -711,38 +724,49 @@ void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, i
   HIPCHECK(hipGetLastError());
 }
 
-template <typename R, int NR, int Q>
-void launch_coarse_q(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+template <typename R>
+void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+  launch_prolong_t<R, cpx<R>>(P, (R)1, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st);
+}
+
+void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,
+                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+  launch_prolong_t<float, hfc>(P, ps, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st);
+}
+
+template <typename R, int NR, int Q, typename TL>
+void launch_coarse_q(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                      double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   const size_t total = (size_t)cx * ct * nc;
   dim3 grid((unsigned)((total + 63) / 64), (nrhs + NR - 1) / NR);
   if (mode == 0)
-    hipLaunchKernelGGL((k_coarse<R, 0, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
-                       aux);
+    hipLaunchKernelGGL((k_coarse<R, 0, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
+                       xacc, aux, lscale);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse<R, 1, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
-                       aux);
+    hipLaunchKernelGGL((k_coarse<R, 1, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
+                       xacc, aux, lscale);
   else if (mode == 3)
-    hipLaunchKernelGGL((k_coarse<R, 3, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
-                       aux);
+    hipLaunchKernelGGL((k_coarse<R, 3, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
+                       xacc, aux, lscale);
   else
-    hipLaunchKernelGGL((k_coarse<R, 2, NR, Q>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c, xacc,
-                       aux);
+    hipLaunchKernelGGL((k_coarse<R, 2, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
+                       xacc, aux, lscale);
   HIPCHECK(hipGetLastError());
 }
 
 // Columns per pass: a wave's share of the columns (ceil(nc / 4)) in one pass up to
 // 4, in passes of 4 above.
-template <typename R, int NR>
-void launch_coarse_nr(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+template <typename R, int NR, typename TL>
+void launch_coarse_nr(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                       double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   const int q = (nc + 3) / 4;
   if (q <= 2)
-    launch_coarse_q<R, NR, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
   else if (q == 3)
-    launch_coarse_q<R, NR, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 3, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
   else
-    launch_coarse_q<R, NR, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -983,17 +1007,28 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
     launch_coarse_mfma_s<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
 }
 
+template <typename R, typename TL>
+void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
+                     double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  if (nrhs == 1)
+    launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else if (nrhs <= 2)
+    launch_coarse_nr<R, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else if (nrhs <= 4)
+    launch_coarse_nr<R, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  else
+    launch_coarse_nr<R, 8, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+}
+
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                    cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
-  if (nrhs == 1)
-    launch_coarse_nr<R, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
-  else if (nrhs <= 2)
-    launch_coarse_nr<R, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
-  else if (nrhs <= 4)
-    launch_coarse_nr<R, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
-  else
-    launch_coarse_nr<R, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+  launch_coarse_t<R, cpx<R>>(L, (R)1, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+}
+
+void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
+                       double c, z32* xacc, const z32* aux, hipStream_t st) {
+  launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
 }
 
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int* fail,
@@ -1056,14 +1091,14 @@ void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hip
 // tiled kernel would launch a few dozen workgroups.
 constexpr int kDenseRowsMax = 4096;
 
-template <typename RM, typename R>
-__global__ void __launch_bounds__(kThreads) k_dense_rows(const cpx<RM>* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                         cpx<R>* __restrict__ y, int n) {
+template <typename RM, typename R, typename TM = cpx<RM>>
+__global__ void __launch_bounds__(kThreads) k_dense_rows(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                         cpx<R>* __restrict__ y, int n, double mscale) {
   const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const cpx<R>* xb = x + (size_t)blockIdx.y * n;
-  const cpx<RM>* Mr = M + (size_t)row * n;
+  const TM* Mr = M + (size_t)row * n;
   double re = 0, im = 0;
   constexpr int U = 8;  // row segments per group: their loads are in flight together (index clamped)
   for (int j0 = lane; j0 < n; j0 += 64 * U) {
@@ -1072,7 +1107,7 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const cpx<RM>* __restri
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = min(j0 + 64 * u, n - 1);
-      m[u] = Mr[j];
+      m[u] = widen(Mr[j]);
       v[u] = xb[j];
     }
 #pragma unroll
@@ -1086,19 +1121,29 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const cpx<RM>* __restri
   }
   re = wave_sum(re);
   im = wave_sum(im);
-  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)re, (R)im);
+  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)(mscale * re), (R)(mscale * im));
 }
 
 // The kernel is chosen by n alone, so a column's result never depends on nrhs.
-template <typename RM, typename R>
-void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
+// mscale: power-of-two scale of a reduced-precision M (1 otherwise), applied exactly.
+template <typename RM, typename R, typename TM>
+void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
   if (n <= kDenseRowsMax) {
-    hipLaunchKernelGGL((k_dense_rows<RM, R>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n);
+    hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale);
   } else {
     dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
-    hipLaunchKernelGGL((k_dense_gemm<RM, R>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs);
+    hipLaunchKernelGGL((k_dense_gemm<RM, R, TM>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs, mscale);
   }
   HIPCHECK(hipGetLastError());
+}
+
+template <typename RM, typename R>
+void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
+  launch_dense_apply_t<RM, R, cpx<RM>>(M, 1.0, x, y, n, nrhs, st);
+}
+
+void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st) {
+  launch_dense_apply_t<float, float, hfc>(M, mscale, x, y, n, nrhs, st);
 }
 
 void launch_random_gaussian(z64* v, size_t n, uint64_t seed, uint64_t stream_id, hipStream_t st) {
@@ -1119,6 +1164,45 @@ void launch_links_convert(const z64* L, cpx<Ro>* out, size_t n, hipStream_t st) 
   size_t g = (n + kThreads - 1) / kThreads;
   if (g > 65536) g = 65536;
   hipLaunchKernelGGL((k_copy_convert<Ro>), dim3((unsigned)g), dim3(kThreads), 0, st, L, out, n);
+  HIPCHECK(hipGetLastError());
+}
+
+// Largest |re| or |im| of n complex values: per-block maxima into part[0 .. blocks).
+__global__ void __launch_bounds__(kThreads) k_absmax_partial(const z64* __restrict__ a, size_t n,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64];
+  double m = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    m = fmax(m, fmax(fabs(a[i].re), fabs(a[i].im)));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, sh[w]);
+    part[blockIdx.x] = m;
+  }
+}
+
+// out = FP16(in * inv_scale) (inv_scale a power of two, so only the FP16 rounding is inexact).
+__global__ void k_convert_h16(const z64* __restrict__ in, hfc* __restrict__ out, size_t n, double inv_scale) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    hfc t;
+    t.re = (_Float16)(in[i].re * inv_scale);
+    t.im = (_Float16)(in[i].im * inv_scale);
+    out[i] = t;
+  }
+}
+
+void launch_absmax_partial(const z64* a, size_t n, double* part, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_absmax_partial, dim3(blocks), dim3(kThreads), 0, st, a, n, part);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_convert_h16(const z64* in, hfc* out, size_t n, double inv_scale, hipStream_t st) {
+  size_t g = (n + kThreads - 1) / kThreads;
+  if (g > 65536) g = 65536;
+  if (g == 0) return;
+  hipLaunchKernelGGL(k_convert_h16, dim3((unsigned)g), dim3(kThreads), 0, st, in, out, n, inv_scale);
   HIPCHECK(hipGetLastError());
 }
 

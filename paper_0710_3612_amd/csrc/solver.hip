@@ -85,6 +85,10 @@ struct Level {
   cpx<R>*b = nullptr, *x = nullptr, *r = nullptr, *t = nullptr, *tmp = nullptr;
   cpx<R>* wbuf = nullptr;           // prolongation scratch, cap * nK * nw values
   void *r_lp = nullptr, *t_lp = nullptr;  // BF16/FP16 smoother iterates (FP32 fine level), cap columns
+  hfc* L16 = nullptr;               // FP16 coarse links (operator_storage F16), scaled by 1 / lscale
+  float lscale = 1;
+  hfc* P16 = nullptr;               // FP16 prolongator (operator_storage F16), scaled by 1 / pscale
+  float pscale = 1;
   size_t nkw() const { return bx ? (size_t)(lx / bx) * (lt / bt) * (bx + 2 * halo) * (bt + 2 * halo) * dof : 0; }
 };
 
@@ -116,6 +120,9 @@ struct Ctx {
   // dense inverse of the coarsest operator
   z64* Minv = nullptr;
   z32* Minv32 = nullptr;            // FP32 copy for the mixed solve's V-cycles
+  hfc* Minv16 = nullptr;            // FP16 copy (operator_storage F16), scaled by 1 / mscale
+  double mscale = 1;
+  double* absmax_part = nullptr;    // per-block maxima for the FP16 scales
   z64* colk = nullptr;
   double* piv = nullptr;
   // per-column scalars on the device: one set per CG nesting depth (the outer
@@ -236,17 +243,35 @@ void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mo
       launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
       return;
     }
+    if (lv.L16) {
+      launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+      return;
+    }
   }
   launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
 }
 
 template <typename R>
 void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (lv.P16) {
+      launch_restrict_s<hfc, z32>(lv.P16, lv.pscale, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk,
+                                  nrhs, c.st);
+      return;
+    }
+  }
   launch_restrict<R>(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
 }
 
 template <typename R>
 void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, int mode) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (lv.P16) {
+      launch_prolong_h16(lv.P16, lv.pscale, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk,
+                         nrhs, mode, c.st);
+      return;
+    }
+  }
   launch_prolong<R>(lv.P, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st);
 }
 
@@ -277,8 +302,12 @@ template <typename R>
 void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool use_cg) {
   auto& lv = levels_of<R>(c)[l];
   if (!use_cg && c.Minv && l == c.nlev - 1) {
-    if constexpr (std::is_same<R, float>::value)
-      launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st);
+    if constexpr (std::is_same<R, float>::value) {
+      if (c.Minv16)
+        launch_dense_apply_h16(c.Minv16, c.mscale, b, x, (int)lv.n, nrhs, c.st);
+      else
+        launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st);
+    }
     else
       launch_dense_apply<double, double>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
   } else
@@ -360,7 +389,12 @@ void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_c
   }
   c.fine_applies += (int64_t)nrhs * nu;
   // 2. r_c = P^H (b - A x)
-  launch_restrict_lp<S>(lv.P, cur, nx.b, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
+  if (lv.P16)
+    launch_restrict_s<hfc, S>(lv.P16, lv.pscale, cur, nx.b, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc,
+                              lv.ldk, nrhs, c.st);
+  else
+    launch_restrict_s<z32, S>(lv.P, 1.0f, cur, nx.b, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs,
+                              c.st);
   // 3. e = V^(1) r_c
   vcycle<float>(c, 1, last, nx.b, nx.x, nrhs, use_cg);
   // 4. x = x + P e
@@ -775,6 +809,8 @@ void validate(const smg_params& p) {
   if (!(p.sa_scale >= 0) || !std::isfinite(p.sa_scale)) throw Error(SMG_EINVAL, "sa_scale must be >= 0");
   if (p.smoother_storage < SMG_STORE_F32 || p.smoother_storage > SMG_STORE_F16)
     throw Error(SMG_EINVAL, "bad smoother_storage");
+  if (p.operator_storage != SMG_STORE_F32 && p.operator_storage != SMG_STORE_F16)
+    throw Error(SMG_EINVAL, "operator_storage must be SMG_STORE_F32 or SMG_STORE_F16");
   if (p.smoother_storage != SMG_STORE_F32 && (p.levels < 2 || !normal_lp_fits(p.lx, p.lt)))
     throw Error(SMG_EINVAL, "BF16/FP16 smoother storage needs levels >= 2, lx % 32 == 0 and lt % 16 == 0");
   int lx = p.lx, lt = p.lt, dof = 2;
@@ -857,8 +893,27 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z6
 }
 
 // FP32 copy of the hierarchy for the mixed-precision inner solves.
+// Power-of-two scale s with max|a| / s in [0.5, 1) (1 for an all-zero array): FP16
+// copies store a / s, so every stored entry is at most 1 in magnitude.
+double fp16_scale(Ctx& c, const z64* a, size_t n) {
+  constexpr int kBlocks = 256;
+  if (!c.absmax_part) c.absmax_part = c.pool.alloc<double>(kBlocks);
+  launch_absmax_partial(a, n, c.absmax_part, kBlocks, c.st);
+  double h[kBlocks];
+  HIPCHECK(hipMemcpyAsync(h, c.absmax_part, sizeof h, hipMemcpyDeviceToHost, c.st));
+  sync(c);
+  double m = 0;
+  for (double v : h) m = std::max(m, v);
+  if (!std::isfinite(m)) throw Error(SMG_EBREAKDOWN, "operator contains NaN/Inf");
+  if (!(m > 0)) return 1.0;
+  int e = 0;
+  std::frexp(m, &e);
+  return std::ldexp(1.0, e);
+}
+
 void ensure_f32(Ctx& c) {
   if (c.f32_ready) return;
+  const bool h16 = c.prm.operator_storage == SMG_STORE_F16;
   const bool fresh = c.L32.empty();
   if (fresh) {
     c.L32.resize(c.nlev);
@@ -875,17 +930,34 @@ void ensure_f32(Ctx& c) {
       const size_t nl = 9 * (size_t)a.lx * a.lt * a.dof * a.dof;
       if (fresh) b.L = c.pool.alloc<z32>(nl);
       launch_links_convert<float>(a.L, b.L, nl, c.st);
+      if (h16) {
+        if (!b.L16) b.L16 = c.pool.alloc<hfc>(nl);
+        const double sc = fp16_scale(c, a.L, nl);
+        b.lscale = (float)sc;
+        launch_convert_h16(a.L, b.L16, nl, 1.0 / sc, c.st);
+      }
     }
     if (a.P) {
       const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * a.halo) * (a.bt + 2 * a.halo) * a.dof;
       if (fresh) b.P = c.pool.alloc<z32>(np);
       launch_links_convert<float>(a.P, b.P, np, c.st);
+      if (h16) {
+        if (!b.P16) b.P16 = c.pool.alloc<hfc>(np);
+        const double sc = fp16_scale(c, a.P, np);
+        b.pscale = (float)sc;
+        launch_convert_h16(a.P, b.P16, np, 1.0 / sc, c.st);
+      }
     }
   }
   if (c.Minv) {
     const size_t nn = c.L64[c.nlev - 1].n * c.L64[c.nlev - 1].n;
     if (!c.Minv32) c.Minv32 = c.pool.alloc<z32>(nn);
     launch_links_convert<float>(c.Minv, c.Minv32, nn, c.st);
+    if (h16) {
+      if (!c.Minv16) c.Minv16 = c.pool.alloc<hfc>(nn);
+      c.mscale = fp16_scale(c, c.Minv, nn);
+      launch_convert_h16(c.Minv, c.Minv16, nn, 1.0 / c.mscale, c.st);
+    }
   }
   c.f32_ready = true;
   ++c.gen;
@@ -1202,6 +1274,7 @@ void smg_default_params(smg_params* p) {
   p->seed = 1;
   p->sa_scale = 4.0 / 3.0;
   p->mfma_min_rhs = 16;
+  p->operator_storage = SMG_STORE_F32;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,

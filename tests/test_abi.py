@@ -41,7 +41,8 @@ def c_layout():
     fields = {
         "smg_params": ["lx", "lt", "mass", "levels", "block", "nv", "setup_iters", "smoother_steps",
                        "smoother_omega", "t_antiperiodic", "coarsest", "coarsest_tol", "coarsest_maxiter",
-                       "inner_tol", "seed", "sa_scale", "smoother_storage", "stop_recursive", "mfma_min_rhs"],
+                       "inner_tol", "seed", "sa_scale", "smoother_storage", "stop_recursive", "mfma_min_rhs",
+                       "operator_storage"],
         "smg_stats": ["status", "iterations", "refinements", "vcycles", "fine_applies", "true_relres", "seconds"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {", 'printf("{");']
@@ -115,3 +116,20 @@ def test_reduced_smoother_storage_rejected_where_no_tile_fits():
     assert "lx % 32" in lib.smg_last_error().decode()
     p = smg.make_params(64, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4], smoother_storage=7)
     assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+
+
+def test_operator_storage_validation():
+    """operator_storage takes FP32 (default) or FP16 only; anything else is rejected
+    before any device call."""
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    p = smg.Params()
+    lib.smg_default_params(ctypes.byref(p))
+    assert p.operator_storage == smg.STORE_F32
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    for bad in (smg.STORE_BF16, 7, -1):
+        p = smg.make_params(64, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4], operator_storage=bad)
+        assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
+        assert "operator_storage" in lib.smg_last_error().decode()

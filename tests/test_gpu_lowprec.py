@@ -20,6 +20,7 @@ from oracle.wilson import dirac_matrix, normal_matrix
 pytestmark = pytest.mark.gpu
 
 BOUND = {0: 1e-4, 1: 5e-2, 2: 6e-3}
+OP16_BOUND = 1e-3  # FP16 unit roundoff 2^-11 = 4.9e-4, times 2: the rounded coarse operators enter the coarse correction only
 
 
 def dev(x, dtype=np.complex128):
@@ -57,6 +58,8 @@ def lp():
     for st in (smg.STORE_F32, smg.STORE_BF16, smg.STORE_F16):
         p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, smoother_storage=st)
         solvers[st] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, operator_storage=smg.STORE_F16, mfma_min_rhs=0)
+    solvers["op16"] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
     yield dict(U=U, A=A, h=h, m=m, n=2 * lx * lt, s=solvers)
     for s in solvers.values():
         s.close()
@@ -90,4 +93,35 @@ def test_mixed_solve_with_reduced_storage(lp, storage):
     for j in range(4):
         assert np.linalg.norm(B[j] - A @ xh[j]) / np.linalg.norm(B[j]) <= 1e-10
         # the cheaper smoother may cost iterations, not convergence
+        assert st[j]["iterations"] <= 2 * st32[j]["iterations"] + 5
+
+
+def test_fp32_vcycle_with_fp16_operators(lp):
+    """Coarse links, prolongators and the coarsest inverse stored in FP16 (each array scaled by a
+    power of two): the V-cycle stays within OP16_BOUND of the oracle's FP64 one."""
+    nrhs = 3
+    b = synth.gaussian((nrhs, lp["n"]), 78).astype(np.complex64)
+    x = host(lp["s"]["op16"].vcycle_f32(dev(b, np.complex64))).reshape(nrhs, -1)
+    errs = []
+    for j in range(nrhs):
+        ref = mg.vcycle(lp["h"], 0, b[j].astype(np.complex128))
+        errs.append(np.max(np.abs(x[j] - ref)) / np.max(np.abs(ref)))
+    print("fp16 operators: V-cycle error", errs)
+    assert max(errs) <= OP16_BOUND, errs
+
+
+def test_mixed_solve_with_fp16_operators(lp):
+    import paper_0710_3612_amd as smg
+
+    A = lp["A"]
+    n = lp["n"]
+    D = dirac_matrix(lp["U"], lp["m"])
+    B = np.stack([D.conj().T @ v for v in synth.gaussian((4, n), 89)])
+    x, st, code = lp["s"]["op16"].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.MIXED)
+    assert code == 0
+    xh = host(x).reshape(4, n)
+    _, st32, _ = lp["s"][0].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.MIXED)
+    print("fp16 operators: iterations", [c["iterations"] for c in st], "fp32:", [c["iterations"] for c in st32])
+    for j in range(4):
+        assert np.linalg.norm(B[j] - A @ xh[j]) / np.linalg.norm(B[j]) <= 1e-10
         assert st[j]["iterations"] <= 2 * st32[j]["iterations"] + 5

@@ -22,6 +22,7 @@ from oracle.wilson import normal_matrix
 pytestmark = pytest.mark.gpu
 
 TOL32 = 2e-5
+TOL16 = 2e-3  # FP16 unit roundoff 2^-11 per link entry, times 4 for cancellation in sums of random terms
 
 CASES = [
     # lx, lt, blocks, nvs, mass
@@ -75,8 +76,11 @@ def hier(request):
     for name, mmin in (("mfma", 1), ("valu", 0)):
         p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, mfma_min_rhs=mmin)
         out[name] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, mfma_min_rhs=0,
+                        operator_storage=smg.STORE_F16)
+    out["h16"] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
     yield dict(h=h, A=A, U=U, m=m, nlev=len(blocks) + 1, **out)
-    for s in (out["mfma"], out["valu"]):
+    for s in out.values():
         s.close()
 
 
@@ -136,3 +140,34 @@ def test_mfma_mixed_solve_many_rhs(hier):
         xs[name] = xh
     d = np.linalg.norm(xs["mfma"] - xs["valu"], axis=1) / np.linalg.norm(xs["valu"], axis=1)
     assert d.max() < 1e-6
+
+
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_fp16_link_coarse_modes(hier, nrhs):
+    """Vector-ALU coarse operator with FP16 links (scaled by a power of two): every
+    mode within TOL16 of the oracle's FP64 operator."""
+    import torch
+
+    for level in range(1, hier["nlev"]):
+        Ac = hier["h"].levels[level].A
+        n = Ac.shape[0]
+        rng = np.random.default_rng(level * 1000 + nrhs)
+        x = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        aux = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        acc0 = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        coef = 0.37
+        x64 = x.astype(np.complex128)
+        Ax = np.stack([Ac @ x64[j] for j in range(nrhs)])
+        s = hier["h16"]
+        xt = dev(x, np.complex64)
+        y0 = host(s.level_op_f32(level, xt, mode=0)).reshape(nrhs, n)
+        xacc = dev(acc0, np.complex64)
+        y1 = host(s.level_op_f32(level, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
+        a1 = host(xacc).reshape(nrhs, n)
+        y2 = host(s.level_op_f32(level, xt, mode=2, aux=dev(aux, np.complex64))).reshape(nrhs, n)
+        torch.cuda.synchronize()
+        print("fp16 links level", level, "mode 0 error", colerr(y0, Ax))
+        assert colerr(y0, Ax) <= TOL16, (level, "mode 0")
+        assert colerr(y1, x64 - coef * Ax) <= TOL16, (level, "mode 1")
+        assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (level, "mode 1 acc")
+        assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL16, (level, "mode 2")
