@@ -11,7 +11,8 @@ right-hand side per field (rhs = D^H b), true residual 1e-10.
 The adaptive setup runs once per field at its lightest mass; the heavier masses
 reuse its near-null vectors (their coarse operators are rebuilt) -- both are timed
 separately as setup.  One step solves all 20 (field, mass) systems.  `value` is
-mixed-precision (FP32 inner, FP64 defect correction) solves/s; the plain FP64
+mixed-precision (FP32 inner MG-CG with FP16-stored operators, FP64 defect
+correction) solves/s; the plain FP64
 GPU MG is timed on the same hierarchies and reported beside it.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build uses one GPU.
@@ -52,6 +53,9 @@ SERVE_FIELDS_PER_SIZE = 8
 SERVE_SWEEPS = 200
 SERVE_MASSES = {3.0: [0.02, 0.05, 0.1, 0.2], 6.0: [0.01, 0.03, 0.06, 0.1], 10.0: [0.005, 0.02, 0.05, 0.1]}
 SERVE_NV = 8
+# Mixed solves of every leg store the FP32 V-cycle's operators (coarse links on the
+# vector-ALU path, prolongators, coarsest dense inverse) in FP16 (smg.STORE_F16).
+OPERATOR_STORAGE = 2
 SERVE_BUDGET = 200 * 10**9
 SERVE_CAPACITY = 16
 
@@ -59,7 +63,7 @@ SERVE_CAPACITY = 16
 # sweeps, seed 5000) at the mass where lambda_min(A)/lambda_max(A) = 1e-3, 3 levels of
 # 4x4 aggregates with Nv = 16 (coarse links 16x16 on the matrix cores, dense inverse
 # of the 16384-variable coarsest operator, BF16 storage of the fine smoother iterates
-# in the mixed solve).
+# and FP16 storage of the prolongators and coarsest inverse in the mixed solve).
 MRHS_L = 512
 MRHS_SEED = 5000
 MRHS_NRHS = 32
@@ -175,7 +179,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     n = 2 * MRHS_L * MRHS_L
     p = smg.make_params(MRHS_L, MRHS_L, mass, levels=3, blocks=[(4, 4), (4, 4)], nv=MRHS_NV,
                         setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=MRHS_SEED,
-                        sa_scale=SA_SCALE, mfma_min_rhs=16, smoother_storage=smg.STORE_BF16)
+                        sa_scale=SA_SCALE, mfma_min_rhs=16, smoother_storage=smg.STORE_BF16,
+                        operator_storage=OPERATOR_STORAGE)
     g = torch.from_numpy(np.ascontiguousarray(U)).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -225,7 +230,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     return dict(workload=(f"{MRHS_L}x{MRHS_L} U(1) beta={BETA:g} ({SWEEPS} sweeps, seed {MRHS_SEED}), mass {mass:.5f} "
                           f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
                           f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}; mixed: FP32 inner "
-                          f"MG-CG, BF16 storage of the fine smoother iterates, coarse links on the matrix cores"),
+                          f"MG-CG, BF16 storage of the fine smoother iterates, FP16 storage of the prolongators "
+                          f"and coarsest inverse, coarse links on the matrix cores"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
 
@@ -250,7 +256,7 @@ def serving_leg(args, torch, smg, dev):
         lv = serve.levels_for(L)
         p = smg.make_params(L, L, 0.0, levels=lv, blocks=[(4, 4)] * (lv - 1), nv=[SERVE_NV] * (lv - 1),
                             setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=seed,
-                            sa_scale=SA_SCALE)
+                            sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE)
         fields[seed] = (torch.from_numpy(np.ascontiguousarray(U)).to(dev), p)
         masses[seed] = SERVE_MASSES[beta]
     torch.cuda.synchronize()
@@ -332,8 +338,9 @@ def kernel_source_digest():
 
     text = open(KERNEL_SOURCE).read()
     parts = []
-    for start in ("template <typename R, int MODE, int NR, int Q>\n__global__ void __launch_bounds__(kThreads) k_coarse(",
-                  "void launch_coarse_q(", "void launch_coarse_nr(", "void launch_coarse(const cpx<R>* L"):
+    for start in ("template <typename R, int MODE, int NR, int Q, typename TL = cpx<R>>\n"
+                  "__global__ void __launch_bounds__(kThreads) k_coarse(",
+                  "void launch_coarse_q(", "void launch_coarse_nr(", "void launch_coarse_t(", "void launch_coarse_h16("):
         i = text.index(start)
         parts.append(text[i:text.index("\n}\n", i) + 3])
     return hashlib.sha256("".join(parts).encode()).hexdigest()
@@ -361,7 +368,8 @@ def measured_traffic():
 def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     """Average launch time of the FP32 coarse operator on level 1 (the kernel that
     dominates the mixed-precision V-cycle), and its algorithmic bytes: 9 link
-    blocks of nc x nc complex64 per coarse site plus the input and output vector."""
+    blocks of nc x nc complex values per coarse site (4 bytes each in FP16 operator
+    storage, 8 in FP32) plus the input and output vector (complex64)."""
     import ctypes
 
     cx, ct, nc = s.level_info(1)
@@ -369,12 +377,15 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     y = torch.empty_like(v)
     px, py = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr())
     dur = timed_events(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
-    nbytes = 9 * nc * nc * 8 * cx * ct + 2 * cx * ct * nc * 8
+    h16 = OPERATOR_STORAGE == smg.STORE_F16
+    nbytes = 9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8
     gbs = nbytes / dur / 1e9
     q = (nc + 3) // 4
     cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
-    return dict(kernel=f"k_coarse<float,0,1,{cols}>: FP32 coarse 9-point operator, level 1 ({cx}x{ct} sites, nc={nc}), "
-                       "single RHS", bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
+    name = f"k_coarse<float,0,1,{cols}{',hfc' if h16 else ''}>"
+    what = "FP16 links (scaled), FP32 arithmetic" if h16 else "FP32"
+    return dict(kernel=f"{name}: coarse 9-point operator, {what}, level 1 ({cx}x{ct} sites, nc={nc}), single RHS",
+                bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
                 traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes)
 
 
@@ -391,7 +402,7 @@ def kernel_probe(reps):
     dev = torch.device("cuda:0")
     U = synth.links_from_angles(synth.metropolis_u1(L, L, BETA, 20, SEEDS[0]))
     p = smg.make_params(L, L, 0.0, levels=3, blocks=BLOCKS, nv=NV, setup_iters=0, smoother_steps=NU,
-                        smoother_omega=OMEGA, seed=SEEDS[0], sa_scale=SA_SCALE)
+                        smoother_omega=OMEGA, seed=SEEDS[0], sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE)
     s = smg.Solver(torch.from_numpy(U).to(dev), p)
     lib = smg.load_library()
     stream = torch.cuda.current_stream()
@@ -524,7 +535,8 @@ def main():
         ms = masses[seed]
         m_light = min(ms)
         p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=NV, setup_iters=SETUP_ITERS,
-                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE)
+                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE,
+                            operator_storage=OPERATOR_STORAGE)
         R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
         g = T(U)
         rnd = T(np.concatenate([r.ravel() for r in R]))
@@ -656,11 +668,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 inner / f64 outer",
+        "dtype": "f32 inner (f16 operator storage) / f64 outer",
         "data": "synthetic",
         "config": {
             "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
-                        "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10",
+                        "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG with "
+                        "FP16-stored coarse links, prolongators and coarsest inverse inside FP64 defect correction",
             "systems_per_step": n_systems,
             "concurrent_streams": nwork,
             "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
