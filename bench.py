@@ -327,7 +327,7 @@ def timed_events(fn, reps, stream):
     return start.elapsed_time(stop) * 1e-3 / reps
 
 
-COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f32_level1_256_counters.md")
+COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip")
 
 

@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(kThreads) k_dot_partial(const cpx<R>* __restri
 template <int EPI>
 __global__ void __launch_bounds__(kThreads) k_reduce_final(const double* __restrict__ partial, int nb,
                                                            double* __restrict__ out, double* __restrict__ s,
-                                                           const int* __restrict__ active, int* __restrict__ bad) {
+                                                           const int* __restrict__ active, int* __restrict__ bad,
+                                                           double* __restrict__ out_host, int* __restrict__ bad_host) {
   double re = 0, im = 0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     re += partial[2 * ((size_t)blockIdx.x * nb + i)];
@@ -69,22 +70,33 @@ __global__ void __launch_bounds__(kThreads) k_reduce_final(const double* __restr
   block_sum2(re, im);
   if (threadIdx.x != 0) return;
   const int j = blockIdx.x;
+  // out_host / bad_host (may be null): host-visible mirrors (coherent pinned memory) that
+  // the host reads after a stream synchronisation, without a copy of its own
   if (EPI == 0) {
     out[2 * j] = re;
     out[2 * j + 1] = im;
+    if (out_host) {
+      out_host[2 * j] = re;
+      out_host[2 * j + 1] = im;
+    }
   } else if (EPI == 1) {
     double al = 0;
+    bool broke = false;
     if (active[j]) {
       const double num = s[2 * j], den = re;
       if (!isfinite(num) || !isfinite(den)) {
-        bad[j] = 1;
+        broke = true;
       } else if (num == 0) {
         al = 0;  // residual is exactly zero: nothing left to do in this column
       } else if (!(den > 0)) {
-        bad[j] = 1;
+        broke = true;
       } else {
         al = num / den;
       }
+    }
+    if (broke) {
+      bad[j] = 1;
+      if (bad_host) bad_host[j] = 1;
     }
     out[j] = al;
   } else {
@@ -257,17 +269,17 @@ void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, d
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, a, b, n, nb, red.partial);
   hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, out, nullptr, nullptr,
-                     nullptr);
+                     nullptr, nullptr, nullptr);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
 void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
-                      double* alpha, const int* active, int* bad, hipStream_t st) {
+                      double* alpha, const int* active, int* bad, hipStream_t st, int* bad_host) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, p, q, n, nb, red.partial);
   hipLaunchKernelGGL((k_reduce_final<1>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, alpha,
-                     const_cast<double*>(rz), active, bad);
+                     const_cast<double*>(rz), active, bad, nullptr, bad_host);
   HIPCHECK(hipGetLastError());
 }
 
@@ -277,18 +289,18 @@ void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red r
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, r, z, n, nb, red.partial);
   hipLaunchKernelGGL((k_reduce_final<2>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, beta, rz, active,
-                     nullptr);
+                     nullptr, nullptr, nullptr);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
-                        int nrhs, Red red, double* rr, hipStream_t st) {
+                        int nrhs, Red red, double* rr, hipStream_t st, double* rr_host) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_axpy_update<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, alpha, n, nb,
                      red.partial);
   hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, rr, nullptr, nullptr,
-                     nullptr);
+                     nullptr, rr_host, nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -375,11 +387,11 @@ void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* a
 #define INST(R)                                                                                              \
   template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, hipStream_t);          \
   template void launch_dot_alpha<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, const double*, double*,    \
-                                    const int*, int*, hipStream_t);                                           \
+                                    const int*, int*, hipStream_t, int*);                                     \
   template void launch_dot_beta<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, double*,            \
                                    const int*, hipStream_t);                                                  \
   template void launch_axpy_update<R>(cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, const double*, size_t,  \
-                                      int, Red, double*, hipStream_t);                                        \
+                                      int, Red, double*, hipStream_t, double*);                               \
   template void launch_xpay<R>(const cpx<R>*, cpx<R>*, const double*, size_t, int, hipStream_t);              \
   template void launch_axpy_const<R>(cpx<R>*, const cpx<R>*, double, size_t, int, hipStream_t);              \
   template void launch_sub<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, size_t, int, hipStream_t);              \

@@ -99,6 +99,30 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 
 constexpr int kThreads = 256;
 
+// Epilogues of the operator applies (y = A x computed in registers, c and c2 real):
+//   0: y = A x
+//   1: xacc += c x ; y = x - c A x              (one frozen MR step)
+//   2: y = aux - A x                            (residual)
+//   3: xacc  = c x ; y = x - c A x              (first MR step, from a zero iterate)
+//   4: xacc += c x + c2 (x - c A x)             (the last two MR steps; y is not written)
+//   5: xacc  = c x + c2 (x - c A x)             (both steps of a two-step smoother from zero)
+template <int N>
+struct ModeC {
+  static constexpr int v = N;
+};
+template <typename F>
+void with_mode(int mode, F&& f) {
+  switch (mode) {
+    case 0: f(ModeC<0>{}); break;
+    case 1: f(ModeC<1>{}); break;
+    case 2: f(ModeC<2>{}); break;
+    case 3: f(ModeC<3>{}); break;
+    case 4: f(ModeC<4>{}); break;
+    case 5: f(ModeC<5>{}); break;
+    default: throw Error(-1, "unknown operator epilogue");
+  }
+}
+
 inline unsigned grid_for(size_t n, int threads = kThreads, size_t cap = 1u << 20) {
   size_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -131,13 +155,13 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
 // A x = D^H (D x); `tmp` holds D x ([nrhs][V][2]).
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
-                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
 
 // FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
 // (lx and lt multiples of 16).
 template <typename TI, typename TO>
 void launch_normal_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
-                      z32* xacc, const z32* aux, hipStream_t st);
+                      z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
 bool normal_lp_fits(int lx, int lt);
 // FP32 P^H x with P stored as TP (z32, or hfc scaled by 1 / ps) and x stored as TI
 // (z32, bfc or hfc).
@@ -153,13 +177,13 @@ void launch_zero(void* p, size_t bytes, hipStream_t st);
 // Coarse 9-point operator on level with extents (cx, ct), nc dof; links [9][nc][K][nc].
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                   double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st);
+                   double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
 // The same with the links stored in FP16 scaled by 1 / lscale (a power of two).
 void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
-                       double c, z32* xacc, const z32* aux, hipStream_t st);
+                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
 // Matrix-core (MFMA FP32) coarse apply for 1 <= nc <= 16, any number of right-hand sides.
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                        z32* xacc, const z32* aux, hipStream_t st);
+                        z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
 
 // Transfer between level (lx, lt, dof) and its aggregates of (bx, bt) sites.
 // P is [J][ldk][nw] (ldk >= nc vectors stored per aggregate) over windows of
@@ -211,17 +235,19 @@ struct Red {
 };
 template <typename R>
 void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st);
-// <p, q> per column, then alpha = <r,z> / <p,q> (0 for inactive columns, breakdown flagged in bad).
+// <p, q> per column, then alpha = <r,z> / <p,q> (0 for inactive columns, breakdown flagged in bad and,
+// when bad_host is given, in that host-visible mirror too).
 template <typename R>
 void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
-                      double* alpha, const int* active, int* bad, hipStream_t st);
+                      double* alpha, const int* active, int* bad, hipStream_t st, int* bad_host = nullptr);
 // <r, z>_new per column, then beta = <r,z>_new / <r,z>_old and <r,z>_old <- <r,z>_new (active columns).
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st);  // out[2*rhs] = <a,b> (complex)
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
-                        int nrhs, Red red, double* rr, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2
+                        int nrhs, Red red, double* rr, hipStream_t st,
+                        double* rr_host = nullptr);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
 template <typename R>
 void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
 template <typename R>

@@ -236,8 +236,8 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
 template <typename R, int MODE, int NR, int Q, typename TL = cpx<R>>
 __global__ void __launch_bounds__(kThreads) k_coarse(const TL* __restrict__ L, const cpx<R>* __restrict__ v,
                                                      cpx<R>* __restrict__ y, int cx, int ct, int nc, int nrhs, R c,
-                                                     cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux,
-                                                     R lscale) {
+                                                     R c2, cpx<R>* __restrict__ xacc,
+                                                     const cpx<R>* __restrict__ aux, R lscale) {
   __shared__ cpx<R> part[3][NR][64];
   const int nK = cx * ct;
   const size_t n = (size_t)nK * nc;
@@ -303,6 +303,10 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const TL* __restrict__ L, c
       const cpx<R> vi = v[o];
       xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
       y[o] = vi - c * sum;
+    } else if (MODE == 4 || MODE == 5) {
+      const cpx<R> vi = v[o];
+      const cpx<R> a = MODE == 5 ? c * vi : xacc[o] + c * vi;
+      xacc[o] = a + c2 * (vi - c * sum);
     } else {
       y[o] = aux[o] - sum;
     }
@@ -737,21 +741,13 @@ void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf,
 
 template <typename R, int NR, int Q, typename TL>
 void launch_coarse_q(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                     double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                     double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   const size_t total = (size_t)cx * ct * nc;
   dim3 grid((unsigned)((total + 63) / 64), (nrhs + NR - 1) / NR);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_coarse<R, 0, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
-                       xacc, aux, lscale);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse<R, 1, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
-                       xacc, aux, lscale);
-  else if (mode == 3)
-    hipLaunchKernelGGL((k_coarse<R, 3, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
-                       xacc, aux, lscale);
-  else
-    hipLaunchKernelGGL((k_coarse<R, 2, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, nrhs, (R)c,
-                       xacc, aux, lscale);
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_coarse<R, decltype(m)::v, NR, Q, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc,
+                       nrhs, (R)c, (R)c2, xacc, aux, lscale);
+  });
   HIPCHECK(hipGetLastError());
 }
 
@@ -759,14 +755,14 @@ void launch_coarse_q(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, 
 // 4, in passes of 4 above.
 template <typename R, int NR, typename TL>
 void launch_coarse_nr(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                      double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                      double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   const int q = (nc + 3) / 4;
   if (q <= 2)
-    launch_coarse_q<R, NR, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else if (q == 3)
-    launch_coarse_q<R, NR, 3, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 3, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else
-    launch_coarse_q<R, NR, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_q<R, NR, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -799,7 +795,7 @@ __device__ inline int xcd_tile(int b, int nb) {
 template <int MODE, int TX, int TT, int NW, int S>
 __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__ L, const z32* __restrict__ v,
                                                         z32* __restrict__ y, int cx, int ct, int nc, int nrhs,
-                                                        float c, z32* __restrict__ xacc,
+                                                        float c, float c2, z32* __restrict__ xacc,
                                                         const z32* __restrict__ aux, int pairs) {
   // S = ceil(nc / 2): MFMA pairs per link direction and staged column pairs.  It is
   // a compile-time constant so that the loads below are straight-line code (loads
@@ -950,6 +946,11 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
         const z32 vi = mk<float>(t.x, t.y);
         xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
         y[o] = vi - c * sum;
+      } else if (MODE == 4 || MODE == 5) {
+        const float2 t = vs[(lsc * 16 + dof) * kMfmaRS + j];
+        const z32 vi = mk<float>(t.x, t.y);
+        const z32 a = MODE == 5 ? c * vi : xacc[o] + c * vi;
+        xacc[o] = a + c2 * (vi - c * sum);
       } else {
         y[o] = aux[o] - sum;
       }
@@ -959,38 +960,30 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
 
 template <int TX, int TT, int NW, int S>
 void launch_coarse_mfma_t(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                          z32* xacc, const z32* aux, hipStream_t st) {
+                          double c2, z32* xacc, const z32* aux, hipStream_t st) {
   const int tiles = ((cx + TX - 1) / TX) * ((ct + TT - 1) / TT);
   dim3 grid((unsigned)tiles, (unsigned)((nrhs + 31) / 32));
   // 16-byte loads of column pairs need an even nc and a 16-byte aligned input
   const int pairs = (nc % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_coarse_mfma<0, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux, pairs);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_coarse_mfma<1, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux, pairs);
-  else if (mode == 3)
-    hipLaunchKernelGGL((k_coarse_mfma<3, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux, pairs);
-  else
-    hipLaunchKernelGGL((k_coarse_mfma<2, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct, nc, nrhs,
-                       (float)c, xacc, aux, pairs);
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_coarse_mfma<decltype(m)::v, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct,
+                       nc, nrhs, (float)c, (float)c2, xacc, aux, pairs);
+  });
   HIPCHECK(hipGetLastError());
 }
 
 template <int TX, int TT, int NW>
 void launch_coarse_mfma_s(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                          z32* xacc, const z32* aux, hipStream_t st) {
+                          double c2, z32* xacc, const z32* aux, hipStream_t st) {
   switch ((nc + 1) / 2) {
-    case 1: launch_coarse_mfma_t<TX, TT, NW, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 2: launch_coarse_mfma_t<TX, TT, NW, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 3: launch_coarse_mfma_t<TX, TT, NW, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 4: launch_coarse_mfma_t<TX, TT, NW, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 5: launch_coarse_mfma_t<TX, TT, NW, 5>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 6: launch_coarse_mfma_t<TX, TT, NW, 6>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    case 7: launch_coarse_mfma_t<TX, TT, NW, 7>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
-    default: launch_coarse_mfma_t<TX, TT, NW, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st); break;
+    case 1: launch_coarse_mfma_t<TX, TT, NW, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 2: launch_coarse_mfma_t<TX, TT, NW, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 3: launch_coarse_mfma_t<TX, TT, NW, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 4: launch_coarse_mfma_t<TX, TT, NW, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 5: launch_coarse_mfma_t<TX, TT, NW, 5>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 6: launch_coarse_mfma_t<TX, TT, NW, 6>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 7: launch_coarse_mfma_t<TX, TT, NW, 7>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    default: launch_coarse_mfma_t<TX, TT, NW, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
   }
 }
 
@@ -998,37 +991,37 @@ void launch_coarse_mfma_s(const z32* L, const z32* x, z32* y, int cx, int ct, in
 // lattices 2x2 tiles (4 waves, 68 KB) give four times the workgroups (measured on
 // MI355X: 32^2 sites, 32 RHS: 14 us vs 35 us; 128^2 sites: 4x4 ahead by 9%).
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                        z32* xacc, const z32* aux, hipStream_t st) {
+                        z32* xacc, const z32* aux, hipStream_t st, double c2) {
   if (nc < 1 || nc > 16) throw Error(-1, "matrix-core coarse apply needs 1 <= nc <= 16");
   const long tiles44 = (long)((cx + 3) / 4) * ((ct + 3) / 4);
   if (tiles44 < 256)
-    launch_coarse_mfma_s<2, 2, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_mfma_s<2, 2, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else
-    launch_coarse_mfma_s<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_mfma_s<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 template <typename R, typename TL>
 void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                     double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                     double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   if (nrhs == 1)
-    launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else if (nrhs <= 2)
-    launch_coarse_nr<R, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_nr<R, 2, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else if (nrhs <= 4)
-    launch_coarse_nr<R, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_nr<R, 4, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else
-    launch_coarse_nr<R, 8, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+    launch_coarse_nr<R, 8, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                   cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
-  launch_coarse_t<R, cpx<R>>(L, (R)1, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+                   cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2) {
+  launch_coarse_t<R, cpx<R>>(L, (R)1, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
-                       double c, z32* xacc, const z32* aux, hipStream_t st) {
-  launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st);
+                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
+  launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int* fail,
@@ -1219,7 +1212,7 @@ void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int n
   template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int, int, int, int, int,  \
                                   int, int, int, int, hipStream_t);                                              \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
-                                 const cpx<R>*, hipStream_t);                                                    \
+                                 const cpx<R>*, hipStream_t, double);                                            \
   template void launch_links_convert<R>(const z64*, cpx<R>*, size_t, hipStream_t);
 INST(double)
 INST(float)

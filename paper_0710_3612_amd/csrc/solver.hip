@@ -95,6 +95,10 @@ struct Level {
 struct Scal {
   double *bb = nullptr, *rz = nullptr, *pq = nullptr, *ab = nullptr, *rr = nullptr, *tt = nullptr;
   int *active = nullptr, *bad = nullptr;
+  // host-visible mirrors of rr and bad in coherent pinned memory, written by the reductions
+  // themselves: the per-iteration convergence check needs a synchronisation but no copy
+  double* rr_host = nullptr;
+  int* bad_host = nullptr;
 };
 
 template <typename R>
@@ -150,6 +154,10 @@ struct Ctx {
     if (blas) (void)rocblas_destroy_handle(blas);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_int) (void)hipHostFree(h_int);
+    for (auto& s : sc) {
+      if (s.rr_host) (void)hipHostFree(s.rr_host);
+      if (s.bad_host) (void)hipHostFree(s.bad_host);
+    }
   }
 };
 
@@ -177,6 +185,12 @@ void ensure_scalars(Ctx& c, int nrhs) {
     s.tt = c.pool.alloc<double>(2 * cap);
     s.active = c.pool.alloc<int>(cap);
     s.bad = c.pool.alloc<int>(cap);
+    if (s.rr_host) (void)hipHostFree(s.rr_host);
+    if (s.bad_host) (void)hipHostFree(s.bad_host);
+    s.rr_host = nullptr;
+    s.bad_host = nullptr;
+    HIPCHECK(hipHostMalloc((void**)&s.rr_host, sizeof(double) * 2 * cap, hipHostMallocCoherent));
+    HIPCHECK(hipHostMalloc((void**)&s.bad_host, sizeof(int) * cap, hipHostMallocCoherent));
   }
   c.dc_down = c.pool.alloc<double>(cap);
   c.dc_up = c.pool.alloc<double>(cap);
@@ -232,23 +246,23 @@ bool use_mfma(const Ctx& c, int nc, int nrhs) {
 
 template <typename R>
 void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mode, double coef, cpx<R>* xacc,
-              const cpx<R>* aux) {
+              const cpx<R>* aux, double coef2 = 0) {
   if (lv.fine) {
-    launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st);
+    launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st, coef2);
     c.fine_applies += nrhs;
     return;
   }
   if constexpr (std::is_same<R, float>::value) {
     if (use_mfma(c, lv.dof, nrhs)) {
-      launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+      launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
       return;
     }
     if (lv.L16) {
-      launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+      launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
       return;
     }
   }
-  launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st);
+  launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
 }
 
 template <typename R>
@@ -279,18 +293,21 @@ void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, in
 template <typename R>
 void smooth(Ctx& c, Level<R>& lv, const cpx<R>* b, cpx<R>* x, int nrhs) {
   const int nu = (int)lv.coefs.size();
-  if (nu == 1) launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+  if (nu == 1) {
+    launch_zero(x, (size_t)nrhs * lv.n * sizeof(cpx<R>), c.st);
+    launch_axpy_const<R>(x, b, lv.coefs[0], lv.n, nrhs, c.st);
+    return;
+  }
   const cpx<R>* cur = b;
   cpx<R>* bufs[2] = {lv.r, lv.t};
-  for (int k = 0; k < nu; ++k) {
-    if (k + 1 < nu) {
-      cpx<R>* nxt = bufs[k & 1];
-      // the first step sets x = c_0 b rather than accumulating into a cleared x
-      apply_op<R>(c, lv, cur, nxt, nrhs, k == 0 ? 3 : 1, lv.coefs[k], x, nullptr);
-      cur = nxt;
-    } else {
-      launch_axpy_const<R>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
-    }
+  for (int k = 0; k + 1 < nu; ++k) {
+    // the first step sets x = c_0 b rather than accumulating into a cleared x; the
+    // last apply also adds the final step's c_{nu-1} r_{nu-1} (no residual is written)
+    const bool last = k + 2 == nu;
+    const int mode = last ? (k == 0 ? 5 : 4) : (k == 0 ? 3 : 1);
+    cpx<R>* nxt = bufs[k & 1];
+    apply_op<R>(c, lv, cur, nxt, nrhs, mode, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0);
+    cur = nxt;
   }
 }
 
@@ -354,18 +371,16 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   vcycle<R>(c, l + 1, last, nx.b, nx.x, nrhs, use_cg);
   // 4. x = x + P e
   prolong_from<R>(c, lv, nx.x, x, nrhs, 1);
-  // 5. x = x + R (b - A x)
+  // 5. x = x + R (b - A x); the last apply also adds the final step (mode 4)
   apply_op<R>(c, lv, x, lv.r, nrhs, 2, 0.0, nullptr, b);
   cur = lv.r;
   cpx<R>* pb[2] = {lv.t, lv.r};
-  for (int k = 0; k < nu; ++k) {
-    if (k + 1 < nu) {
-      cpx<R>* nxt = pb[k & 1];
-      apply_op<R>(c, lv, cur, nxt, nrhs, 1, lv.coefs[k], x, nullptr);
-      cur = nxt;
-    } else {
-      launch_axpy_const<R>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
-    }
+  if (nu == 1) launch_axpy_const<R>(x, cur, lv.coefs[0], lv.n, nrhs, c.st);
+  for (int k = 0; k + 1 < nu; ++k) {
+    const bool last = k + 2 == nu;
+    cpx<R>* nxt = pb[k & 1];
+    apply_op<R>(c, lv, cur, nxt, nrhs, last ? 4 : 1, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0);
+    cur = nxt;
   }
   if (l == 0) c.vcycles += nrhs;
 }
@@ -404,15 +419,14 @@ void vcycle_fine_lp(Ctx& c, int last, const z32* b, z32* x, int nrhs, bool use_c
   c.fine_applies += nrhs;
   cur = bufs[0];
   S* pb[2] = {bufs[1], bufs[0]};
-  for (int k = 0; k < nu; ++k) {
-    if (k + 1 < nu) {
-      S* nxt = pb[k & 1];
-      launch_normal_lp<S, S>(lv.U, cur, nxt, lv.lx, lv.lt, lv.diag, nrhs, 1, lv.coefs[k], x, nullptr, c.st);
-      c.fine_applies += nrhs;
-      cur = nxt;
-    } else {
-      launch_axpy_const_lp<S>(x, cur, lv.coefs[k], lv.n, nrhs, c.st);
-    }
+  if (nu == 1) launch_axpy_const_lp<S>(x, cur, lv.coefs[0], lv.n, nrhs, c.st);
+  for (int k = 0; k + 1 < nu; ++k) {
+    const bool last = k + 2 == nu;  // mode 4: this apply also adds the final step
+    S* nxt = pb[k & 1];
+    launch_normal_lp<S, S>(lv.U, cur, nxt, lv.lx, lv.lt, lv.diag, nrhs, last ? 4 : 1, lv.coefs[k], x, nullptr, c.st,
+                           last ? lv.coefs[k + 1] : 0.0);
+    c.fine_applies += nrhs;
+    cur = nxt;
   }
   c.vcycles += nrhs;
 }
@@ -462,6 +476,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   zero(x, bytes, c.st);
   HIPCHECK(hipMemcpyAsync(v.r, b, bytes, hipMemcpyDeviceToDevice, c.st));
   zero(S.bad, sizeof(int) * nrhs, c.st);
+  for (int j = 0; j < nrhs; ++j) S.bad_host[j] = 0;  // no kernel of this stream is running (synchronised above)
   upload_active();
   auto precondition = [&](const cpx<R>* r, cpx<R>* z) {
     if (precond)
@@ -476,20 +491,18 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   }
   for (int it = 1; it <= maxiter && nact > 0; ++it) {
     apply_op<R>(c, lv, v.p, v.q, nrhs, 0, 0.0, nullptr, nullptr);
-    launch_dot_alpha<R>(v.p, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st);
-    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.red, S.rr, c.st);
+    launch_dot_alpha<R>(v.p, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st, S.bad_host);
+    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.red, S.rr, c.st, S.rr_host);
     for (int j = 0; j < nrhs; ++j) its[j] += act[j];
     if (it % check_interval == 0 || it == maxiter) {
-      HIPCHECK(hipMemcpyAsync(c.h_scal, S.rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
-      HIPCHECK(hipMemcpyAsync(c.h_int + nrhs, S.bad, sizeof(int) * nrhs, hipMemcpyDeviceToHost, c.st));
-      sync(c);
+      sync(c);  // the reductions wrote |r|^2 and the breakdown flags to S.rr_host / S.bad_host
       std::vector<int> cand(nrhs, 0);
       bool any_cand = false;
       for (int j = 0; j < nrhs; ++j) {
         if (!act[j]) continue;
-        if (c.h_int[nrhs + j])
+        if (S.bad_host[j])
           throw Error(SMG_EBREAKDOWN, "CG breakdown (<p,Ap> <= 0 or NaN) in column " + std::to_string(j));
-        const double r2 = c.h_scal[2 * j];
+        const double r2 = S.rr_host[2 * j];
         if (!std::isfinite(r2)) throw Error(SMG_EBREAKDOWN, "CG residual is NaN/Inf");
         if (r2 <= tol * tol * hbb[j]) {
           cand[j] = 1;
@@ -501,7 +514,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
           if (cand[j]) {
             act[j] = 0;
             stat[j] = SMG_OK;
-            rel[j] = std::sqrt(c.h_scal[2 * j] / hbb[j]);
+            rel[j] = std::sqrt(S.rr_host[2 * j] / hbb[j]);
           }
         nact = 0;
         for (int j = 0; j < nrhs; ++j) nact += act[j];

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kThreads) k_wilson(const cpx<R>* __restrict__ 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kThreads) k_normal2(const cpx<R>* __restrict__ U, const cpx<R>* __restrict__ t,
                                                       const cpx<R>* __restrict__ x, cpx<R>* __restrict__ y, int lx,
-                                                      int lt, R diag, R c, cpx<R>* __restrict__ xacc,
+                                                      int lt, R diag, R c, R c2, cpx<R>* __restrict__ xacc,
                                                       const cpx<R>* __restrict__ aux) {
   const int V = lx * lt;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -120,6 +120,12 @@ __global__ void __launch_bounds__(kThreads) k_normal2(const cpx<R>* __restrict__
     xacc[i1] = MODE == 3 ? c * v1 : xacc[i1] + c * v1;
     y[i0] = v0 - c * o0;
     y[i1] = v1 - c * o1;
+  } else if (MODE == 4 || MODE == 5) {
+    const cpx<R> v0 = x[i0], v1 = x[i1];
+    const cpx<R> a0 = MODE == 5 ? c * v0 : xacc[i0] + c * v0;
+    const cpx<R> a1 = MODE == 5 ? c * v1 : xacc[i1] + c * v1;
+    xacc[i0] = a0 + c2 * (v0 - c * o0);
+    xacc[i1] = a1 + c2 * (v1 - c * o1);
   } else {
     y[i0] = aux[i0] - o0;
     y[i1] = aux[i1] - o1;
@@ -166,7 +172,7 @@ __device__ inline int fused_tile(int b, int nb) {
 
 template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>>
 __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
-                                                           TO* __restrict__ y, int lx, int lt, R diag, R c,
+                                                           TO* __restrict__ y, int lx, int lt, R diag, R c, R c2,
                                                            cpx<R>* __restrict__ xacc,
                                                            const cpx<R>* __restrict__ aux) {
   constexpr int HX = TX + 2, HT = TT + 2;
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const size_t i0 = off + 2 * (size_t)((t0 + lti + k * RG) * lx + x0 + lxi);
-    if (MODE == 1) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
+    if (MODE == 1 || MODE == 4) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
     if (MODE == 2) { ep0[k] = aux[i0]; ep1[k] = aux[i0 + 1]; }
   }
   // ring site of this thread (threads 0 .. NRING-1): halo coordinates, the hop it skips, its links
@@ -345,6 +351,12 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       xacc[i1] = MODE == 3 ? c * v1 : ep1[k] + c * v1;
       stv(y, i0, v0 - c * o0);
       stv(y, i1, v1 - c * o1);
+    } else if (MODE == 4 || MODE == 5) {
+      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+      const cpx<R> a0 = MODE == 5 ? c * v0 : ep0[k] + c * v0;
+      const cpx<R> a1 = MODE == 5 ? c * v1 : ep1[k] + c * v1;
+      xacc[i0] = a0 + c2 * (v0 - c * o0);
+      xacc[i1] = a1 + c2 * (v1 - c * o1);
     } else {
       stv(y, i0, ep0[k] - o0);
       stv(y, i1, ep1[k] - o1);
@@ -379,25 +391,12 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
 
 template <typename R, int TX, int TT, bool NT>
 void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs, int mode,
-                  double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                  double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 0, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
-                         (R)c, xacc, aux);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 1, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
-                         (R)c, xacc, aux);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 3, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
-                         (R)c, xacc, aux);
-      break;
-    default:
-      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 2, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag,
-                         (R)c, xacc, aux);
-  }
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, decltype(m)::v, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt,
+                       (R)diag, (R)c, (R)c2, xacc, aux);
+  });
   HIPCHECK(hipGetLastError());
 }
 
@@ -437,54 +436,33 @@ int fused_shape(int lx, int lt) {
 
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
-                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2) {
   switch (fused_shape<R>(lx, lt)) {
-    case kT64x4: launch_fused<R, 64, 4, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
-    case kT64x8nt: launch_fused<R, 64, 8, true>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
-    case kT32x16nt: launch_fused<R, 32, 16, true>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
-    case kT32x8: launch_fused<R, 32, 8, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
-    case kT16x16: launch_fused<R, 16, 16, false>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st); return;
+    case kT64x4: launch_fused<R, 64, 4, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
+    case kT64x8nt: launch_fused<R, 64, 8, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
+    case kT32x16nt: launch_fused<R, 32, 16, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
+    case kT32x8: launch_fused<R, 32, 8, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
+    case kT16x16: launch_fused<R, 16, 16, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
     default: break;
   }
   launch_wilson<R>(U, x, tmp, lx, lt, diag, nrhs, false, st);
   const int V = lx * lt;
   dim3 grid((V + kThreads - 1) / kThreads, nrhs);
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((k_normal2<R, 0>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
-                         xacc, aux);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_normal2<R, 1>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
-                         xacc, aux);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_normal2<R, 3>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
-                         xacc, aux);
-      break;
-    default:
-      hipLaunchKernelGGL((k_normal2<R, 2>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag, (R)c,
-                         xacc, aux);
-  }
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_normal2<R, decltype(m)::v>), grid, dim3(kThreads), 0, st, U, tmp, x, y, lx, lt, (R)diag,
+                       (R)c, (R)c2, xacc, aux);
+  });
   HIPCHECK(hipGetLastError());
 }
 
 template <int TX, int TT, typename TI, typename TO>
 void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
-                     z32* xacc, const z32* aux, hipStream_t st) {
+                     double c2, z32* xacc, const z32* aux, hipStream_t st) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 0, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
-                       lt, (float)diag, (float)c, xacc, aux);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 1, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
-                       lt, (float)diag, (float)c, xacc, aux);
-  else if (mode == 3)
-    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 3, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
-                       lt, (float)diag, (float)c, xacc, aux);
-  else
-    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, 2, false, TI, TO>), grid, dim3(kThreads), 0, st, U, x, y, lx,
-                       lt, (float)diag, (float)c, xacc, aux);
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_normal_fused<float, TX, TT, decltype(m)::v, false, TI, TO>), grid, dim3(kThreads), 0, st, U,
+                       x, y, lx, lt, (float)diag, (float)c, (float)c2, xacc, aux);
+  });
   HIPCHECK(hipGetLastError());
 }
 
@@ -492,14 +470,14 @@ bool normal_lp_fits(int lx, int lt) { return lx % 32 == 0 && lt % 16 == 0; }
 
 template <typename TI, typename TO>
 void launch_normal_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
-                      z32* xacc, const z32* aux, hipStream_t st) {
+                      z32* xacc, const z32* aux, hipStream_t st, double c2) {
   if (!normal_lp_fits(lx, lt)) throw Error(-1, "reduced-precision smoother storage needs lx % 32 == 0, lt % 16 == 0");
-  launch_fused_lp<32, 16>(U, x, y, lx, lt, diag, nrhs, mode, c, xacc, aux, st);
+  launch_fused_lp<32, 16>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st);
 }
 
 #define INST_LP(TI, TO)                                                                                          \
   template void launch_normal_lp<TI, TO>(const z32*, const TI*, TO*, int, int, double, int, int, double, z32*,   \
-                                         const z32*, hipStream_t);
+                                         const z32*, hipStream_t, double);
 INST_LP(z32, bfc)
 INST_LP(bfc, bfc)
 INST_LP(z32, hfc)
@@ -517,9 +495,9 @@ void launch_prepare_links(const z64* gauge, cpx<R>* U, int lx, int lt, int antip
 template void launch_wilson<double>(const z64*, const z64*, z64*, int, int, double, int, bool, hipStream_t);
 template void launch_wilson<float>(const z32*, const z32*, z32*, int, int, double, int, bool, hipStream_t);
 template void launch_normal<double>(const z64*, const z64*, z64*, z64*, int, int, double, int, int, double, z64*,
-                                    const z64*, hipStream_t);
+                                    const z64*, hipStream_t, double);
 template void launch_normal<float>(const z32*, const z32*, z32*, z32*, int, int, double, int, int, double, z32*,
-                                   const z32*, hipStream_t);
+                                   const z32*, hipStream_t, double);
 template void launch_prepare_links<double>(const z64*, z64*, int, int, int, hipStream_t);
 template void launch_prepare_links<float>(const z64*, z32*, int, int, int, hipStream_t);
 

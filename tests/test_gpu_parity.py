@@ -397,3 +397,37 @@ def test_stop_on_recursive_residual(cuda):
                 assert res <= 1e-9
             out[flag] = (st[0]["iterations"], stc[0]["iterations"])
     assert out[True][0] <= out[False][0] and out[True][1] <= out[False][1]
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3])
+def test_smoother_degrees(nu):
+    """Smoother and V-cycle with nu = 1, 2 (the degree of the paper's experiment) and
+    3 MR steps, which take the one-step, two-step-from-zero and first/last-step
+    epilogues of the operator kernels: FP64 against the oracle to 1e-11, the FP32
+    V-cycle to 1e-4 (FP32 rounding, as in the mixed-precision tests)."""
+    smg = smg_mod()
+    lx, lt, blocks, nvs, m = 32, 32, [(4, 4), (2, 2)], [6, 6], 0.07
+    U = field(lx, lt, seed=41 + nu)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, 43 + nu)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=nu, omega=0.8, sa_scale=4 / 3)
+    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, smoother_steps=nu)
+    s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])), calib=dev(np.concatenate(calib)))
+    try:
+        n = s.level_size(0)
+        b = synth.gaussian((2, n), 47 + nu)
+        x = host(s.vcycle(dev(b))).reshape(2, -1)
+        for l in range(2):
+            bl = synth.gaussian((2, s.level_size(l)), 53 + l)
+            rb = host(s.smooth(l, dev(bl))).reshape(2, -1)
+            for j in range(2):
+                assert rel_err(rb[j], mg.smoother_apply(h.levels[l].A, h.levels[l].coefs, bl[j])) <= 1e-11, (l, j)
+        import torch
+
+        x32 = host(s.vcycle_f32(torch.from_numpy(b.astype(np.complex64)).to("cuda"))).reshape(2, -1)
+        for j in range(2):
+            ref = mg.vcycle(h, 0, b[j])
+            assert rel_err(x[j], ref) <= 1e-11, j
+            assert rel_err(x32[j], ref) <= 1e-4, j
+    finally:
+        s.close()
