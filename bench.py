@@ -311,6 +311,34 @@ def serving_leg(args, torch, smg, dev):
     torch.cuda.empty_cache()
     return summ
 
+def timed_graph(fn, reps, stream, per_graph=20):
+    """Average duration of fn() with the launches replayed from a HIP graph of
+    per_graph calls, HIP events on `stream`: for kernels of a few microseconds the
+    host cannot enqueue single launches as fast as the GPU retires them, and the
+    graph removes that host time from the measurement.  fn must only launch kernels
+    on `stream` (no allocation, copy or synchronisation)."""
+    import torch
+
+    with torch.cuda.stream(stream):
+        fn()
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(per_graph):
+            fn()
+    n = max(1, reps // per_graph)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        g.replay()
+        start.record(stream)
+        for _ in range(n):
+            g.replay()
+        stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) * 1e-3 / (n * per_graph)
+
+
 def timed_events(fn, reps, stream):
     """Average duration of fn() over reps launches, HIP events on `stream`."""
     import torch
@@ -376,7 +404,7 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     v = torch.randn(cx * ct * nc, dtype=torch.complex64, device=dev)
     y = torch.empty_like(v)
     px, py = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr())
-    dur = timed_events(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
+    dur = timed_graph(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
     h16 = OPERATOR_STORAGE == smg.STORE_F16
     nbytes = 9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8
     gbs = nbytes / dur / 1e9
@@ -405,7 +433,7 @@ def kernel_probe(reps):
                         smoother_omega=OMEGA, seed=SEEDS[0], sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE)
     s = smg.Solver(torch.from_numpy(U).to(dev), p)
     lib = smg.load_library()
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream(dev)  # graphs are not captured on the null stream
     sp = ctypes.c_void_p(stream.cuda_stream)
     roof = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev)
     # calibration: an elementwise FP32 kernel that reads and writes 64 MiB each
@@ -467,6 +495,8 @@ def main():
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
     ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
+    ap.add_argument("--solves-only", action="store_true",
+                    help="set up the precision workload, pause 1 s, run --steps mixed steps (for kernel traces)")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only launch the roofline kernel and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
@@ -585,6 +615,19 @@ def main():
         futs = [pool.submit(run_share, w, prec, rec) for w in range(nwork)]
         for f in futs:
             f.result()
+
+    if args.solves_only:
+        step(smg.MIXED)
+        torch.cuda.synchronize()
+        time.sleep(1.0)  # an idle gap that separates setup from the steps in a kernel trace
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(smg.MIXED)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pool.shutdown()
+        print(json.dumps(dict(solves_per_s=len(systems) * args.steps / dt, steps=args.steps, streams=nwork)))
+        return 0
 
     results = {}
     for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
