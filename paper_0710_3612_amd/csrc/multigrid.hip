@@ -1118,11 +1118,90 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const TM* __restrict__ 
 }
 
 // The kernel is chosen by n alone, so a column's result never depends on nrhs.
+// Y = M X on the matrix cores, FP32 (M stored as TM: z32 or scaled hfc), for the
+// large coarsest inverses (n > kDenseRowsMax).  A workgroup owns 32 rows x 32
+// right-hand sides; its four waves each take a quarter of the k range (a multiple
+// of 4).  The complex product uses the real embedding of the coarse matrix-core
+// kernel: per complex k two v_mfma_f32_32x32x2f32, A = [Mr, -Mi] into Re Y and
+// A = [Mi, Mr] into Im Y, both against B = [Xr; Xi] (lane l supplies A[l%32][l/32]
+// and B[l/32][l%32]; accumulator r of lane l is row 8(r/4) + 4(l/32) + r%4, column
+// l%32).  Indices past n or nrhs are clamped for the loads, the tail of the k range
+// is masked by a zero factor, and the partial sums of the four waves meet in LDS in
+// a fixed order.  The k split depends on n only, so a column's result does not
+// depend on nrhs.
+template <typename TM>
+__global__ void __launch_bounds__(256) k_dense_mfma(const TM* __restrict__ M, const z32* __restrict__ x,
+                                                    z32* __restrict__ y, int n, int nrhs, float mscale) {
+  __shared__ float red[3][2][16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 31, half = lane >> 5;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const TM* Mr = M + (size_t)min(r0 + i, n - 1) * n;
+  const z32* Xc = x + (size_t)min(c0 + i, nrhs - 1) * n;
+  const int kw = ((n + 15) / 16) * 4;  // k per wave, a multiple of 4
+  const int kb = w * kw, ke = min(n, kb + kw);
+  floatx16 accR, accI;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) accR[r] = accI[r] = 0.f;
+  // blocks of U complex k pass through a ring of D register blocks: the loads of a
+  // block are issued D - 1 blocks before its products
+  constexpr int U = 4, D = 4;
+  TM mb[D][U];
+  z32 vb[D][U];
+  auto load = [&](int d, int k0) {
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int k = min(k0 + t, n - 1);
+      mb[d][t] = Mr[k];
+      vb[d][t] = Xc[k];
+    }
+  };
+#pragma unroll
+  for (int d = 0; d + 1 < D; ++d) load(d, kb + d * U);
+  for (int k4 = kb; k4 < ke; k4 += D * U) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      load((d + D - 1) % D, k4 + (d + D - 1) * U);
+      __builtin_amdgcn_sched_barrier(0);  // keep the refill where it is issued
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const z32 m = widen(mb[d][t]), v = vb[d][t];
+        const float am = (k4 + d * U + t < ke) ? 1.f : 0.f;
+        const float a_re = am * (half ? -m.im : m.re);
+        const float a_im = am * (half ? m.re : m.im);
+        const float b = half ? v.im : v.re;
+        accR = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b, accI, 0, 0, 0);
+      }
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      red[w - 1][0][r][lane] = accR[r];
+      red[w - 1][1][r][lane] = accI[r];
+    }
+  }
+  __syncthreads();
+  if (w != 0) return;
+  const int col = c0 + i;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = r0 + 8 * (r / 4) + 4 * half + (r % 4);
+    const float re = ((accR[r] + red[0][0][r][lane]) + red[1][0][r][lane]) + red[2][0][r][lane];
+    const float im = ((accI[r] + red[0][1][r][lane]) + red[1][1][r][lane]) + red[2][1][r][lane];
+    if (row < n && col < nrhs) y[(size_t)col * n + row] = mk<float>(mscale * re, mscale * im);
+  }
+}
+
 // mscale: power-of-two scale of a reduced-precision M (1 otherwise), applied exactly.
 template <typename RM, typename R, typename TM>
 void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
   if (n <= kDenseRowsMax) {
     hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale);
+  } else if constexpr (std::is_same<R, float>::value) {
+    dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
+    hipLaunchKernelGGL((k_dense_mfma<TM>), grid, dim3(256), 0, st, M, x, y, n, nrhs, (float)mscale);
   } else {
     dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
     hipLaunchKernelGGL((k_dense_gemm<RM, R, TM>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs, mscale);

@@ -431,3 +431,35 @@ def test_smoother_degrees(nu):
             assert rel_err(x32[j], ref) <= 1e-4, j
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("opst", [0, 2])
+def test_fp32_vcycle_large_coarsest_matrix_cores(opst):
+    """FP32 V-cycle whose 5120-variable coarsest inverse is applied on the matrix
+    cores (n above the row-kernel limit), with FP32 or FP16 operator storage: within
+    1e-4 (FP32) or 1e-3 (FP16, unit roundoff 2^-11 times 2) of the oracle's FP64
+    V-cycle, for 1 and 33 right-hand sides (two column tiles, the second ragged);
+    a column's result is bitwise the same alone and inside the batch."""
+    import torch
+
+    smg = smg_mod()
+    lx, lt, blocks, nvs, m = 64, 64, [(2, 2)], [5], 0.1
+    U = field(lx, lt, seed=61)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, 63)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=4 / 3)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=blocks, nv=nvs, operator_storage=opst)
+    s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])), calib=dev(np.concatenate(calib)))
+    try:
+        assert s.level_size(1) == 5120
+        n = s.level_size(0)
+        b = synth.gaussian((33, n), 67).astype(np.complex64)
+        xa = host(s.vcycle_f32(torch.from_numpy(b[:1].copy()).to("cuda"))).reshape(1, -1)
+        xb = host(s.vcycle_f32(torch.from_numpy(b).to("cuda"))).reshape(33, -1)
+        assert np.array_equal(xa[0], xb[0])
+        bound = 1e-4 if opst == 0 else 1e-3
+        for j in (0, 17, 32):
+            ref = mg.vcycle(h, 0, b[j].astype(np.complex128))
+            assert rel_err(xb[j], ref) <= bound, (j, rel_err(xb[j], ref))
+    finally:
+        s.close()
