@@ -190,6 +190,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     eta = torch.from_numpy(synth.z2_noise((MRHS_NRHS, n), MRHS_SEED + 1)).to(dev)
     rhs = s.apply_D(eta, dagger=True)
     x = torch.empty_like(rhs)
+    torch.cuda.synchronize()
+    time.sleep(1.0)  # an idle gap that separates the setup from the solves in a kernel trace
     out = {}
     for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
         _, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=x)
