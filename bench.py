@@ -414,9 +414,14 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
     name = f"k_coarse<float,0,1,{cols}{',hfc' if h16 else ''}>"
     what = "FP16 links (scaled), FP32 arithmetic" if h16 else "FP32"
+    # context: a plain device copy moving the same bytes (half read, half written), timed the same way
+    src = torch.ones(nbytes // 8, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dcopy = timed_graph(lambda: dst.copy_(src), reps, stream)
     return dict(kernel=f"{name}: coarse 9-point operator, {what}, level 1 ({cx}x{ct} sites, nc={nc}), single RHS",
                 bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
-                traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes)
+                traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes,
+                same_bytes_copy_us=dcopy * 1e6, same_bytes_copy_GBps=nbytes / dcopy / 1e9)
 
 
 def kernel_probe(reps):
@@ -487,7 +492,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dslash-reps", type=int, default=200)
-    ap.add_argument("--streams", type=int, default=8, help="concurrent solve streams")
+    ap.add_argument("--streams", type=int, default=16, help="concurrent solve streams")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=100.0, help="offered requests/s of the serving trace")
     ap.add_argument("--serve-lanes", type=int, default=8, help="concurrent (field, mass) lanes")
