@@ -283,6 +283,13 @@ void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red 
   HIPCHECK(hipGetLastError());
 }
 
+void launch_alpha_from_partials(const double* partial, int nb, int nrhs, const double* rz, double* alpha,
+                                const int* active, int* bad, int* bad_host, hipStream_t st) {
+  hipLaunchKernelGGL((k_reduce_final<1>), dim3(nrhs), dim3(kThreads), 0, st, partial, nb, alpha,
+                     const_cast<double*>(rz), active, bad, nullptr, bad_host);
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st) {

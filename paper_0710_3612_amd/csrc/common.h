@@ -157,6 +157,14 @@ template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
                    int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
 
+// The outer CG step on the fine level in one fused kernel: p = z + beta p_old (p = z
+// where beta = 0), q = A p, and per workgroup <p, q> into partial[rhs][block] for
+// cg_step_blocks(lx, lt) blocks (0: no fused tile fits, use the separate kernels).
+template <typename R>
+int cg_step_blocks(int lx, int lt);
+template <typename R>
+void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
+                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st);
 // FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
 // (lx and lt multiples of 16).
 template <typename TI, typename TO>
@@ -241,6 +249,9 @@ template <typename R>
 void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
                       double* alpha, const int* active, int* bad, hipStream_t st, int* bad_host = nullptr);
 // <r, z>_new per column, then beta = <r,z>_new / <r,z>_old and <r,z>_old <- <r,z>_new (active columns).
+// alpha = <r,z> / <p,q> from nb given partials of <p, q> per column (as launch_dot_alpha's second pass).
+void launch_alpha_from_partials(const double* partial, int nb, int nrhs, const double* rz, double* alpha,
+                                const int* active, int* bad, int* bad_host, hipStream_t st);
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st);  // out[2*rhs] = <a,b> (complex)

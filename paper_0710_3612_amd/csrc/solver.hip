@@ -104,6 +104,7 @@ struct Scal {
 template <typename R>
 struct KVecs {
   cpx<R>*r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *t = nullptr;
+  cpx<R>* p2 = nullptr;             // second search-direction buffer of the fused CG step
   size_t cap = 0;                   // elements per vector
 };
 
@@ -127,6 +128,8 @@ struct Ctx {
   hfc* Minv16 = nullptr;            // FP16 copy (operator_storage F16), scaled by 1 / mscale
   double mscale = 1;
   double* absmax_part = nullptr;    // per-block maxima for the FP16 scales
+  double* cg_partial = nullptr;     // per-workgroup <p, A p> of the fused CG step
+  size_t cg_partial_cap = 0;
   z64* colk = nullptr;
   double* piv = nullptr;
   // per-column scalars on the device: one set per CG nesting depth (the outer
@@ -229,6 +232,7 @@ void ensure_kvecs(Ctx& c, KVecs<R>& v, size_t elems) {
   v.q = c.pool.alloc<cpx<R>>(elems);
   v.z = c.pool.alloc<cpx<R>>(elems);
   v.t = c.pool.alloc<cpx<R>>(elems);
+  v.p2 = c.pool.alloc<cpx<R>>(elems);
   v.cap = elems;
 }
 
@@ -484,15 +488,42 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     else
       HIPCHECK(hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, c.st));
   };
+  // The FP32 outer solve on the fine level takes each CG step in one fused kernel:
+  // p = z + beta p_old, q = A p and the partial sums of <p, q> (the search direction
+  // alternates between two buffers because neighbouring workgroups read p_old).
+  int fuse_nb = 0;
+  if constexpr (std::is_same<R, float>::value)
+    if (lv.fine) fuse_nb = cg_step_blocks<float>(lv.lx, lv.lt);
+  if (fuse_nb > 0) {
+    const size_t need = (size_t)2 * fuse_nb * nrhs;
+    if (c.cg_partial_cap < need) {
+      c.cg_partial = c.pool.alloc<double>(need);
+      c.cg_partial_cap = need;
+    }
+  }
+  cpx<R>* p_cur = v.p;
+  cpx<R>* p_alt = v.p2;
   if (nact > 0) {
     precondition(v.r, v.z);
-    HIPCHECK(hipMemcpyAsync(v.p, v.z, bytes, hipMemcpyDeviceToDevice, c.st));
+    if (fuse_nb > 0)
+      launch_zero(S.ab, sizeof(double) * 2 * nrhs, c.st);  // beta = 0: the first step takes p = z
+    else
+      HIPCHECK(hipMemcpyAsync(v.p, v.z, bytes, hipMemcpyDeviceToDevice, c.st));
     launch_dot<R>(v.r, v.z, n, nrhs, c.red, S.rz, c.st);
   }
   for (int it = 1; it <= maxiter && nact > 0; ++it) {
-    apply_op<R>(c, lv, v.p, v.q, nrhs, 0, 0.0, nullptr, nullptr);
-    launch_dot_alpha<R>(v.p, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st, S.bad_host);
-    launch_axpy_update<R>(x, v.r, v.p, v.q, S.ab, n, nrhs, c.red, S.rr, c.st, S.rr_host);
+    if (fuse_nb > 0) {
+      if constexpr (std::is_same<R, float>::value) {
+        launch_cg_step<float>(lv.U, v.z, p_cur, p_alt, v.q, lv.lx, lv.lt, lv.diag, nrhs, S.ab, c.cg_partial, c.st);
+        c.fine_applies += nrhs;
+        std::swap(p_cur, p_alt);
+        launch_alpha_from_partials(c.cg_partial, fuse_nb, nrhs, S.rz, S.ab, S.active, S.bad, S.bad_host, c.st);
+      }
+    } else {
+      apply_op<R>(c, lv, p_cur, v.q, nrhs, 0, 0.0, nullptr, nullptr);
+      launch_dot_alpha<R>(p_cur, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st, S.bad_host);
+    }
+    launch_axpy_update<R>(x, v.r, p_cur, v.q, S.ab, n, nrhs, c.red, S.rr, c.st, S.rr_host);
     for (int j = 0; j < nrhs; ++j) its[j] += act[j];
     if (it % check_interval == 0 || it == maxiter) {
       sync(c);  // the reductions wrote |r|^2 and the breakdown flags to S.rr_host / S.bad_host
@@ -550,7 +581,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     }
     precondition(v.r, v.z);
     launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
-    launch_xpay<R>(v.z, v.p, S.ab, n, nrhs, c.st);
+    if (fuse_nb == 0) launch_xpay<R>(v.z, p_cur, S.ab, n, nrhs, c.st);  // fused: in the next CG step
   }
   if (nact > 0) {  // true residual of the columns that did not converge
     apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);

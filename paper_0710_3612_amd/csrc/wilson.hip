@@ -170,11 +170,16 @@ __device__ inline int fused_tile(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// MODE 6 is the CG step of the outer solve: the staged vector is p = z + beta p_old
+// (z = x, p_old = aux, beta per right-hand side; p = z where beta = 0), p is written to
+// xacc, y = A p, and the workgroup's share of <p, A p> goes to partial[rhs][block].
 template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>>
 __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
                                                            TO* __restrict__ y, int lx, int lt, R diag, R c, R c2,
                                                            cpx<R>* __restrict__ xacc,
-                                                           const cpx<R>* __restrict__ aux) {
+                                                           const cpx<R>* __restrict__ aux,
+                                                           const double* __restrict__ beta = nullptr,
+                                                           double* __restrict__ partial = nullptr) {
   constexpr int HX = TX + 2, HT = TT + 2;
   constexpr int RG = kThreads / TX;          // row groups
   constexpr int PER = TX * TT / kThreads;    // sites per thread
@@ -235,6 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   // so a workgroup waits for one memory latency, not one per pass
   constexpr int NSP = HT * HX * 2, NPASS = (NSP + kThreads - 1) / kThreads;
   TI stage[NPASS];  // raw stored values: widened only after every load has been issued
+  cpx<R> stage2[MODE == 6 ? NPASS : 1];
 #pragma unroll
   for (int j = 0; j < NPASS; ++j) {
     const int i = threadIdx.x + j * kThreads;
@@ -245,12 +251,20 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
       gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
       stage[j] = xb[2 * (gt * lx + gx) + comp];
+      if constexpr (MODE == 6) stage2[j] = aux[off + 2 * (gt * lx + gx) + comp];
     }
   }
+  R bt = 0;
+  if constexpr (MODE == 6) bt = (R)beta[blockIdx.y];
 #pragma unroll
   for (int j = 0; j < NPASS; ++j) {
     const int i = threadIdx.x + j * kThreads;
-    if (i < NSP) sp[i] = widen(stage[j]);
+    if constexpr (MODE == 6) {
+      // p = z + beta p_old; p = z where beta = 0 (p_old is not read into the sum then)
+      if (i < NSP) sp[i] = bt != (R)0 ? widen(stage[j]) + bt * stage2[j] : widen(stage[j]);
+    } else {
+      if (i < NSP) sp[i] = widen(stage[j]);
+    }
   }
   __syncthreads();
 
@@ -294,6 +308,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   __syncthreads();
 
   // ---- phase 2: D^H phi on the tile ---------------------------------------------
+  double dre = 0, dim = 0;  // MODE 6: this thread's share of <p, A p>
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int r = lti + k * RG;
@@ -357,9 +372,39 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       const cpx<R> a1 = MODE == 5 ? c * v1 : ep1[k] + c * v1;
       xacc[i0] = a0 + c2 * (v0 - c * o0);
       xacc[i1] = a1 + c2 * (v1 - c * o1);
+    } else if (MODE == 6) {
+      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+      xacc[i0] = v0;
+      xacc[i1] = v1;
+      stv(y, i0, o0);
+      stv(y, i1, o1);
+      dre += (double)v0.re * o0.re + (double)v0.im * o0.im + (double)v1.re * o1.re + (double)v1.im * o1.im;
+      dim += (double)v0.re * o0.im - (double)v0.im * o0.re + (double)v1.re * o1.im - (double)v1.im * o1.re;
     } else {
       stv(y, i0, ep0[k] - o0);
       stv(y, i1, ep1[k] - o1);
+    }
+  }
+  if constexpr (MODE == 6) {
+    __shared__ double sred[2 * (kThreads / 64)];
+    for (int o = 32; o > 0; o >>= 1) {
+      dre += __shfl_xor(dre, o, 64);
+      dim += __shfl_xor(dim, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sred[2 * (threadIdx.x >> 6)] = dre;
+      sred[2 * (threadIdx.x >> 6) + 1] = dim;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0, b = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        a += sred[2 * w];
+        b += sred[2 * w + 1];
+      }
+      const size_t pi = 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x);
+      partial[pi] = a;
+      partial[pi + 1] = b;
     }
   }
 }
@@ -397,6 +442,15 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
     hipLaunchKernelGGL((k_normal_fused<R, TX, TT, decltype(m)::v, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt,
                        (R)diag, (R)c, (R)c2, xacc, aux);
   });
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R, int TX, int TT, bool NT>
+void launch_cg_step_t(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
+                      double diag, int nrhs, const double* beta, double* partial, hipStream_t st) {
+  dim3 grid((lx / TX) * (lt / TT), nrhs);
+  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT>), grid, dim3(kThreads), 0, st, U, z, q, lx, lt, (R)diag,
+                     (R)0, (R)0, p, p_old, beta, partial);
   HIPCHECK(hipGetLastError());
 }
 
@@ -454,6 +508,38 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
   });
   HIPCHECK(hipGetLastError());
 }
+
+template <typename R>
+int cg_step_blocks(int lx, int lt) {
+  switch (fused_shape<R>(lx, lt)) {
+    case kT64x4: return (lx / 64) * (lt / 4);
+    case kT64x8nt: return (lx / 64) * (lt / 8);
+    case kT32x16nt: return (lx / 32) * (lt / 16);
+    case kT32x8: return (lx / 32) * (lt / 8);
+    case kT16x16: return (lx / 16) * (lt / 16);
+    default: return 0;
+  }
+}
+
+template <typename R>
+void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
+                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st) {
+  switch (fused_shape<R>(lx, lt)) {
+    case kT64x4: launch_cg_step_t<R, 64, 4, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
+    case kT64x8nt: launch_cg_step_t<R, 64, 8, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
+    case kT32x16nt:
+      launch_cg_step_t<R, 32, 16, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st);
+      return;
+    case kT32x8: launch_cg_step_t<R, 32, 8, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
+    case kT16x16:
+      launch_cg_step_t<R, 16, 16, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st);
+      return;
+    default: throw Error(-1, "CG step kernel needs a fused tile shape");
+  }
+}
+template int cg_step_blocks<float>(int, int);
+template void launch_cg_step<float>(const z32*, const z32*, const z32*, z32*, z32*, int, int, double, int,
+                                    const double*, double*, hipStream_t);
 
 template <int TX, int TT, typename TI, typename TO>
 void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
