@@ -190,6 +190,18 @@ __global__ void k_convert(const cpx<Ri>* __restrict__ in, cpx<Ro>* __restrict__ 
     out[i] = cvt<Ro>(in[i]);
 }
 
+// Defect-correction scales per column from |r|^2 (complex pairs) and the host's
+// decision `on` (read from host-visible memory): a running column gets down = 1/|r|
+// and up = |r|, a converged one 0 and 0.
+__global__ void k_dc_scales(const double* __restrict__ rr, const int* __restrict__ on, double* __restrict__ down,
+                            double* __restrict__ up, int nrhs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  const double r2 = rr[2 * j];
+  down[j] = on[j] ? 1.0 / sqrt(r2) : 0.0;
+  up[j] = on[j] ? sqrt(r2) : 0.0;
+}
+
 __global__ void k_scale_down(const z64* __restrict__ in, z32* __restrict__ out, const double* __restrict__ s,
                              size_t n) {
   const size_t off = (size_t)blockIdx.y * n;
@@ -265,11 +277,12 @@ inline dim3 ew_grid(size_t n, int nrhs) {
 }  // namespace
 
 template <typename R>
-void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st) {
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st,
+                double* out_host) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_dot_partial<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, a, b, n, nb, red.partial);
   hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, out, nullptr, nullptr,
-                     nullptr, nullptr, nullptr);
+                     nullptr, out_host, nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -364,6 +377,11 @@ void launch_convert(const cpx<Ri>* in, cpx<Ro>* out, size_t n, hipStream_t st) {
   HIPCHECK(hipGetLastError());
 }
 
+void launch_dc_scales(const double* rr, const int* on, double* down, double* up, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_scales, dim3((nrhs + 63) / 64), dim3(64), 0, st, rr, on, down, up, nrhs);
+  HIPCHECK(hipGetLastError());
+}
+
 void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_down, ew_grid(n, nrhs), dim3(kThreads), 0, st, in, out, s, n);
   HIPCHECK(hipGetLastError());
@@ -392,7 +410,7 @@ void launch_cg_beta(const double* rz_new, double* rz, double* beta, const int* a
 }
 
 #define INST(R)                                                                                              \
-  template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, hipStream_t);          \
+  template void launch_dot<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, hipStream_t, double*);          \
   template void launch_dot_alpha<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, const double*, double*,    \
                                     const int*, int*, hipStream_t, int*);                                     \
   template void launch_dot_beta<R>(const cpx<R>*, const cpx<R>*, size_t, int, Red, double*, double*,            \

@@ -242,7 +242,8 @@ struct Red {
   double* partial = nullptr;
 };
 template <typename R>
-void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st);
+void launch_dot(const cpx<R>* a, const cpx<R>* b, size_t n, int nrhs, Red red, double* out, hipStream_t st,
+                double* out_host = nullptr);  // out (and out_host when given)[2*rhs] = <a,b>
 // <p, q> per column, then alpha = <r,z> / <p,q> (0 for inactive columns, breakdown flagged in bad and,
 // when bad_host is given, in that host-visible mirror too).
 template <typename R>
@@ -271,6 +272,9 @@ template <typename R>
 void launch_scale_const(cpx<R>* x, double a, size_t n, int nrhs, hipStream_t st);  // x *= a
 template <typename Ro, typename Ri>
 void launch_convert(const cpx<Ri>* in, cpx<Ro>* out, size_t n, hipStream_t st);
+// Defect-correction scales from |r|^2 per column: down = 1/|r| and up = |r| where on[rhs]
+// (host-visible memory, set by the host) is nonzero, else 0 and 0.
+void launch_dc_scales(const double* rr, const int* on, double* down, double* up, int nrhs, hipStream_t st);
 // out32 = in64 * s[rhs]   (defect-correction right-hand side)
 void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st);
 // x64 += s[rhs] * e32     (defect-correction update)

@@ -99,6 +99,7 @@ struct Scal {
   // themselves: the per-iteration convergence check needs a synchronisation but no copy
   double* rr_host = nullptr;
   int* bad_host = nullptr;
+  int* on_host = nullptr;           // running columns of a defect correction, read by its scale kernel
 };
 
 template <typename R>
@@ -160,6 +161,7 @@ struct Ctx {
     for (auto& s : sc) {
       if (s.rr_host) (void)hipHostFree(s.rr_host);
       if (s.bad_host) (void)hipHostFree(s.bad_host);
+      if (s.on_host) (void)hipHostFree(s.on_host);
     }
   }
 };
@@ -190,10 +192,13 @@ void ensure_scalars(Ctx& c, int nrhs) {
     s.bad = c.pool.alloc<int>(cap);
     if (s.rr_host) (void)hipHostFree(s.rr_host);
     if (s.bad_host) (void)hipHostFree(s.bad_host);
+    if (s.on_host) (void)hipHostFree(s.on_host);
     s.rr_host = nullptr;
     s.bad_host = nullptr;
+    s.on_host = nullptr;
     HIPCHECK(hipHostMalloc((void**)&s.rr_host, sizeof(double) * 2 * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.bad_host, sizeof(int) * cap, hipHostMallocCoherent));
+    HIPCHECK(hipHostMalloc((void**)&s.on_host, sizeof(int) * cap, hipHostMallocCoherent));
   }
   c.dc_down = c.pool.alloc<double>(cap);
   c.dc_up = c.pool.alloc<double>(cap);
@@ -450,20 +455,23 @@ template <typename R>
 // FP32 solves of defect correction stop on the recursive residual instead: in FP32
 // the recomputed residual of an ill-conditioned system has a rounding floor above
 // the inner tolerance, and the outer FP64 loop checks the true residual anyway.
+// bb_known: |b|^2 per column when the caller knows it (host array), else NULL and
+// it is computed here.
 void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter, bool precond, KVecs<R>& v,
-         ColStats* cs, int check_interval, int depth, bool true_check = true) {
+         ColStats* cs, int check_interval, int depth, bool true_check = true, const double* bb_known = nullptr) {
   auto& lv = levels_of<R>(c)[l];
   Scal& S = c.sc[depth];
   const size_t n = lv.n;
   ensure_scalars(c, nrhs);
   const size_t bytes = (size_t)nrhs * n * sizeof(cpx<R>);
-  launch_dot<R>(b, b, n, nrhs, c.red, S.bb, c.st);
-  HIPCHECK(hipMemcpyAsync(c.h_scal, S.bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
-  sync(c);
+  if (!bb_known) {
+    launch_dot<R>(b, b, n, nrhs, c.red, S.bb, c.st, S.rr_host);
+    sync(c);
+  }
   std::vector<double> hbb(nrhs), rel(nrhs, 0.0);
   std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
   for (int j = 0; j < nrhs; ++j) {
-    hbb[j] = c.h_scal[2 * j];
+    hbb[j] = bb_known ? bb_known[j] : S.rr_host[2 * j];
     if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
     if (!(hbb[j] > 0)) {
       act[j] = 0;
@@ -1620,14 +1628,14 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
     }
     refinements = 0;
     int used = 0;
+    std::vector<double> bb_inner(nrhs);
     while (true) {
-      launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st);
-      HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].rr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
+      launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st, c->sc[1].rr_host);
       sync(*c);
       int nact = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (!act[j]) { down[j] = 0; up[j] = 0; continue; }
-        const double rr = c->h_scal[2 * j];
+        const double rr = c->sc[1].rr_host[2 * j];
         if (!std::isfinite(rr)) throw Error(SMG_EBREAKDOWN, "defect correction residual is NaN/Inf");
         rel[j] = std::sqrt(rr / hbb[j]);
         if (rel[j] <= tol) { act[j] = 0; stat[j] = SMG_OK; down[j] = 0; up[j] = 0; continue; }
@@ -1636,19 +1644,16 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
         ++nact;
       }
       if (nact == 0 || used >= maxiter) break;
-      for (int j = 0; j < nrhs; ++j) {
-        c->h_scal[j] = down[j];
-        c->h_scal[nrhs + j] = up[j];
-      }
-      HIPCHECK(hipMemcpyAsync(c->dc_down, c->h_scal, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->st));
-      HIPCHECK(hipMemcpyAsync(c->dc_up, c->h_scal + nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->st));
+      // the same scales on the device, from the same |r|^2 and this decision (no copy)
+      for (int j = 0; j < nrhs; ++j) c->sc[1].on_host[j] = down[j] != 0 ? 1 : 0;
+      launch_dc_scales(c->sc[1].rr, c->sc[1].on_host, c->dc_down, c->dc_up, nrhs, c->st);
       launch_scale_down(c->r64, c->b32, c->dc_down, n, nrhs, c->st);
-      sync(*c);
       ColStats inner;
       // The inner solve's own convergence test uses inner_tol; its limit is what is
-      // left of maxiter.
+      // left of maxiter.  Its right-hand side has unit norm in every running column.
+      for (int j = 0; j < nrhs; ++j) bb_inner[j] = down[j] != 0 ? 1.0 : 0.0;
       pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0,
-                 false);
+                 false, bb_inner.data());
       int maxit = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (down[j] != 0) its[j] += inner.iters[j];
