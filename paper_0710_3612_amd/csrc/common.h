@@ -165,6 +165,15 @@ int cg_step_blocks(int lx, int lt);
 template <typename R>
 void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
                     double diag, int nrhs, const double* beta, double* partial, hipStream_t st);
+// The last fine apply of a V-cycle with the CG dot folded in: z += c v + c2 (v - c A v)
+// (the last two smoother steps) and per workgroup <r, z> into partial[rhs][block]
+// (cg_step_blocks(lx, lt) blocks).
+template <typename R>
+void launch_vcycle_end(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
+                       int nrhs, double c, double c2, double* partial, hipStream_t st);
+// beta = <r,z>_new / <r,z>_old (and <r,z>_old <- <r,z>_new) from nb given partials of <r, z>.
+void launch_beta_from_partials(const double* partial, int nb, int nrhs, double* rz, double* beta, const int* active,
+                               hipStream_t st);
 // FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
 // (lx and lt multiples of 16).
 template <typename TI, typename TO>

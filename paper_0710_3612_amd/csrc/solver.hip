@@ -131,6 +131,10 @@ struct Ctx {
   double* absmax_part = nullptr;    // per-block maxima for the FP16 scales
   double* cg_partial = nullptr;     // per-workgroup <p, A p> of the fused CG step
   size_t cg_partial_cap = 0;
+  // set by the FP32 CG around a V-cycle: its last fine apply also leaves the partial
+  // sums of <r, z> here (vend_done tells the CG that it did)
+  double* vend_partial = nullptr;
+  bool vend_done = false;
   z64* colk = nullptr;
   double* piv = nullptr;
   // per-column scalars on the device: one set per CG nesting depth (the outer
@@ -380,7 +384,8 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   vcycle<R>(c, l + 1, last, nx.b, nx.x, nrhs, use_cg);
   // 4. x = x + P e
   prolong_from<R>(c, lv, nx.x, x, nrhs, 1);
-  // 5. x = x + R (b - A x); the last apply also adds the final step (mode 4)
+  // 5. x = x + R (b - A x); the last apply also adds the final step (mode 4) and, when
+  // a surrounding FP32 CG asks for it, the partial sums of <b, x>
   apply_op<R>(c, lv, x, lv.r, nrhs, 2, 0.0, nullptr, b);
   cur = lv.r;
   cpx<R>* pb[2] = {lv.t, lv.r};
@@ -388,6 +393,15 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   for (int k = 0; k + 1 < nu; ++k) {
     const bool last = k + 2 == nu;
     cpx<R>* nxt = pb[k & 1];
+    if constexpr (std::is_same<R, float>::value) {
+      if (last && l == 0 && lv.fine && c.vend_partial) {
+        launch_vcycle_end<float>(lv.U, cur, x, b, lv.lx, lv.lt, lv.diag, nrhs, lv.coefs[k], lv.coefs[k + 1],
+                                 c.vend_partial, c.st);
+        c.fine_applies += nrhs;
+        c.vend_done = true;
+        break;
+      }
+    }
     apply_op<R>(c, lv, cur, nxt, nrhs, last ? 4 : 1, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0);
     cur = nxt;
   }
@@ -587,8 +601,21 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         if (nact == 0) break;
       }
     }
-    precondition(v.r, v.z);
-    launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
+    bool folded = false;
+    if (fuse_nb > 0) {  // the V-cycle's last fine apply also forms the partial sums of <r, z>
+      c.vend_partial = c.cg_partial;
+      c.vend_done = false;
+      precondition(v.r, v.z);
+      folded = c.vend_done;
+      c.vend_partial = nullptr;
+      c.vend_done = false;
+    } else {
+      precondition(v.r, v.z);
+    }
+    if (folded)
+      launch_beta_from_partials(c.cg_partial, fuse_nb, nrhs, S.rz, S.ab, S.active, c.st);
+    else
+      launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
     if (fuse_nb == 0) launch_xpay<R>(v.z, p_cur, S.ab, n, nrhs, c.st);  // fused: in the next CG step
   }
   if (nact > 0) {  // true residual of the columns that did not converge

@@ -173,6 +173,9 @@ __device__ inline int fused_tile(int b, int nb) {
 // MODE 6 is the CG step of the outer solve: the staged vector is p = z + beta p_old
 // (z = x, p_old = aux, beta per right-hand side; p = z where beta = 0), p is written to
 // xacc, y = A p, and the workgroup's share of <p, A p> goes to partial[rhs][block].
+// MODE 7 ends a V-cycle: the last two smoother steps of MODE 4 (xacc becomes the
+// V-cycle's output z) and the workgroup's share of <r, z> with r = aux, the V-cycle's
+// input, into partial[rhs][block].
 template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>>
 __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
                                                            TO* __restrict__ y, int lx, int lt, R diag, R c, R c2,
@@ -211,11 +214,13 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   }
   // the epilogue's other operand (xacc for a smoother step, aux for a residual), also early
   cpx<R> ep0[PER], ep1[PER];
+  cpx<R> ea0[MODE == 7 ? PER : 1], ea1[MODE == 7 ? PER : 1];  // MODE 7: the V-cycle's input r
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const size_t i0 = off + 2 * (size_t)((t0 + lti + k * RG) * lx + x0 + lxi);
-    if (MODE == 1 || MODE == 4) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
+    if (MODE == 1 || MODE == 4 || MODE == 7) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
     if (MODE == 2) { ep0[k] = aux[i0]; ep1[k] = aux[i0 + 1]; }
+    if (MODE == 7) { ea0[k] = aux[i0]; ea1[k] = aux[i0 + 1]; }
   }
   // ring site of this thread (threads 0 .. NRING-1): halo coordinates, the hop it skips, its links
   int rhx = 0, rht = 0, rskip = kSkipNone;
@@ -372,6 +377,15 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       const cpx<R> a1 = MODE == 5 ? c * v1 : ep1[k] + c * v1;
       xacc[i0] = a0 + c2 * (v0 - c * o0);
       xacc[i1] = a1 + c2 * (v1 - c * o1);
+    } else if (MODE == 7) {
+      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+      const cpx<R> z0 = ep0[k] + c * v0 + c2 * (v0 - c * o0);
+      const cpx<R> z1 = ep1[k] + c * v1 + c2 * (v1 - c * o1);
+      xacc[i0] = z0;
+      xacc[i1] = z1;
+      const cpx<R> a0 = ea0[k], a1 = ea1[k];
+      dre += (double)a0.re * z0.re + (double)a0.im * z0.im + (double)a1.re * z1.re + (double)a1.im * z1.im;
+      dim += (double)a0.re * z0.im - (double)a0.im * z0.re + (double)a1.re * z1.im - (double)a1.im * z1.re;
     } else if (MODE == 6) {
       const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
       xacc[i0] = v0;
@@ -385,7 +399,7 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
       stv(y, i1, ep1[k] - o1);
     }
   }
-  if constexpr (MODE == 6) {
+  if constexpr (MODE == 6 || MODE == 7) {
     __shared__ double sred[2 * (kThreads / 64)];
     for (int o = 32; o > 0; o >>= 1) {
       dre += __shfl_xor(dre, o, 64);
@@ -508,6 +522,30 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
   });
   HIPCHECK(hipGetLastError());
 }
+
+template <typename R, int TX, int TT, bool NT>
+void launch_vcycle_end_t(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
+                         int nrhs, double c, double c2, double* partial, hipStream_t st) {
+  dim3 grid((lx / TX) * (lt / TT), nrhs);
+  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT>), grid, dim3(kThreads), 0, st, U, v, static_cast<cpx<R>*>(nullptr),
+                     lx, lt, (R)diag, (R)c, (R)c2, z, r, static_cast<const double*>(nullptr), partial);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename R>
+void launch_vcycle_end(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
+                       int nrhs, double c, double c2, double* partial, hipStream_t st) {
+  switch (fused_shape<R>(lx, lt)) {
+    case kT64x4: launch_vcycle_end_t<R, 64, 4, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    case kT64x8nt: launch_vcycle_end_t<R, 64, 8, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    case kT32x16nt: launch_vcycle_end_t<R, 32, 16, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    case kT32x8: launch_vcycle_end_t<R, 32, 8, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    case kT16x16: launch_vcycle_end_t<R, 16, 16, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    default: throw Error(-1, "V-cycle end kernel needs a fused tile shape");
+  }
+}
+template void launch_vcycle_end<float>(const z32*, const z32*, z32*, const z32*, int, int, double, int, double, double,
+                                       double*, hipStream_t);
 
 template <typename R>
 int cg_step_blocks(int lx, int lt) {
