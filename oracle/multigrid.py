@@ -13,7 +13,14 @@ Readings of the paper taken here (the paper is silent or garbled at these points
 * The relaxation used inside the setup (Eq. 4) is the solve smoother itself:
   the frozen minimal-residual polynomial, so I - R A = prod_k (I - c_k A).
 * An aggregate is all degrees of freedom of a bx x bt block of sites (4x4 in the
-  paper), so a coarse site carries M = Nv degrees of freedom.
+  paper), so a coarse site carries M = Nv degrees of freedom.  The alternative
+  reading, aggregates split by chirality (the paper's aggregates are subsets of
+  variables), is the `split` option: each block holds two aggregates, the
+  variables d with d % 2 = 0 and those with d % 2 = 1.  On the fine lattice d is
+  the spin index and gamma5 = sigma3, so the two halves are the chiralities +1
+  and -1; a coarse site then carries 2 Nv degrees of freedom, ordered 2k + chi
+  (candidate k, chirality chi), so the same parity rule holds on every level and
+  the tentative P maps chirality to chirality.
 * The setup's V-cycle on level l is the two-level cycle on the current P with the
   coarse system solved exactly (sparse direct solve here).
 * Smoothed aggregation (Adaptive Multigrid section): the block-orthonormal
@@ -104,12 +111,14 @@ def smoother_matrix(A_dense: np.ndarray, coefs: Sequence[float]) -> np.ndarray:
 # M-vector form that follows it).
 # ---------------------------------------------------------------------------
 
-def aggregate_gather(shape, block) -> np.ndarray:
+def aggregate_gather(shape, block, split: bool = False) -> np.ndarray:
     """G[J, i]: fine-vector index of the i-th variable of aggregate J.
 
     shape = (lx, lt, dof) of the fine side, block = (bx, bt).  Aggregate J =
     Jt*(lx/bx) + Jx holds the sites x in [Jx*bx, Jx*bx+bx), t in [Jt*bt, Jt*bt+bt)
     with all dof components; within it i = ((t % bt)*bx + (x % bx))*dof + d.
+    With split, row 2J + chi keeps only the variables with d % 2 = chi (chirality
+    split; the order within the row is unchanged).
     """
     lx, lt, dof = shape
     bx, bt = block
@@ -120,7 +129,13 @@ def aggregate_gather(shape, block) -> np.ndarray:
         np.arange(ct), np.arange(cx), np.arange(bt), np.arange(bx), np.arange(dof), indexing="ij"
     )
     fine = ((Jt * bt + ty) * lx + (Jx * bx + tx)) * dof + d
-    return fine.reshape(ct * cx, bt * bx * dof)
+    G = fine.reshape(ct * cx, bt * bx * dof)
+    if not split:
+        return G
+    if dof % 2:
+        raise ValueError("a chirality split needs an even number of components per site")
+    chi = np.arange(bt * bx * dof) % dof % 2
+    return np.stack([G[:, chi == 0], G[:, chi == 1]], axis=1).reshape(2 * ct * cx, -1)
 
 
 def block_gram_schmidt(vectors: np.ndarray, gather: np.ndarray, tol: float = 1e-12) -> np.ndarray:
@@ -151,12 +166,16 @@ def block_gram_schmidt(vectors: np.ndarray, gather: np.ndarray, tol: float = 1e-
     return U
 
 
-def prolongator(U: np.ndarray, gather: np.ndarray, n_fine: int) -> sp.csr_matrix:
-    """P with P[gather[J, i], J*Nv + k] = U[J, k, i] (coarse index (K*Nv + k))."""
+def prolongator(U: np.ndarray, gather: np.ndarray, n_fine: int, split: bool = False) -> sp.csr_matrix:
+    """P with P[gather[J, i], J*Nv + k] = U[J, k, i] (coarse index (K*Nv + k)).
+
+    With split (gather rows 2K + chi), P[gather[2K + chi, i], K*2Nv + 2k + chi] =
+    U[2K + chi, k, i]: coarse site K carries 2 Nv variables, candidate-major."""
     nJ, nv, nagg = U.shape
     rows = np.broadcast_to(gather[:, None, :], (nJ, nv, nagg)).ravel()
-    cols = np.broadcast_to((np.arange(nJ)[:, None] * nv + np.arange(nv)[None, :])[:, :, None],
-                           (nJ, nv, nagg)).ravel()
+    R, k = np.arange(nJ)[:, None], np.arange(nv)[None, :]
+    col = (R // 2) * 2 * nv + 2 * k + R % 2 if split else R * nv + k
+    cols = np.broadcast_to(col[:, :, None], (nJ, nv, nagg)).ravel()
     return sp.coo_matrix((U.ravel(), (rows, cols)), shape=(n_fine, nJ * nv)).tocsr()
 
 
@@ -240,6 +259,7 @@ class Level:
     P_t: Optional[sp.csr_matrix] = None
     gather: Optional[np.ndarray] = None
     sa_weight: float = 0.0
+    split: bool = False             # chirality-split aggregates towards the next level
 
 
 @dataclass
@@ -315,20 +335,22 @@ def sa_applies(shape, block) -> bool:
     return bx >= 4 and bt >= 4 and lx // bx >= 2 and lt // bt >= 2
 
 
-def coarsen(level: Level, vectors: np.ndarray, block, sa_weight: float = 0.0) -> (Level, Level):
+def coarsen(level: Level, vectors: np.ndarray, block, sa_weight: float = 0.0,
+            split: bool = False) -> (Level, Level):
     """Given candidate vectors on `level`, form P (block Gram-Schmidt, then the
-    smoothed-aggregation step when sa_weight > 0) and A_c = P^H A P (Eq. 2)."""
-    gather = aggregate_gather(level.shape, block)
+    smoothed-aggregation step when sa_weight > 0) and A_c = P^H A P (Eq. 2).
+    With split the aggregates are the two chirality halves of each block."""
+    gather = aggregate_gather(level.shape, block, split)
     U = block_gram_schmidt(vectors, gather)
-    P_t = prolongator(U, gather, level.A.shape[0])
+    P_t = prolongator(U, gather, level.A.shape[0], split)
     P = P_t
     if sa_weight > 0:
         P = (P_t - sa_weight * (level.A @ P_t)).tocsr()
     level.block, level.U, level.P, level.P_t, level.gather = tuple(block), U, P, P_t, gather
-    level.sa_weight = sa_weight
+    level.sa_weight, level.split = sa_weight, split
     lx, lt, _ = level.shape
-    nv = vectors.shape[0]
-    nxt = Level(A=galerkin(level.A, P), shape=(lx // block[0], lt // block[1], nv))
+    nc = vectors.shape[0] * (2 if split else 1)
+    nxt = Level(A=galerkin(level.A, P), shape=(lx // block[0], lt // block[1], nc))
     return level, nxt
 
 
@@ -339,18 +361,20 @@ def level_sa_weight(level: Level, block, calib: np.ndarray, sa_scale: float) -> 
 
 
 def hierarchy_from_vectors(A, shape, blocks, vectors_per_level, calib_per_level, nu, omega,
-                           coarsest="cholesky", coarsest_tol=1e-12, sa_scale: float = 0.0) -> Hierarchy:
+                           coarsest="cholesky", coarsest_tol=1e-12, sa_scale: float = 0.0,
+                           split: bool = False) -> Hierarchy:
     """Hierarchy from given near-null vectors (no adaptive iteration).
 
     vectors_per_level[l] is [Nv_l, n_l]; calib_per_level[l] starts the MR
-    calibration (and the lambda_max estimate) of level l.
+    calibration (and the lambda_max estimate) of level l.  split: chirality-split
+    aggregates on every coarsening.
     """
     levels = [Level(A=A, shape=tuple(shape))]
     for l, block in enumerate(blocks):
         cur = levels[-1]
         cur.coefs = mr_coefficients(cur.A, calib_per_level[l], nu, omega)
         wsa = level_sa_weight(cur, block, calib_per_level[l], sa_scale)
-        cur, nxt = coarsen(cur, np.asarray(vectors_per_level[l]), block, wsa)
+        cur, nxt = coarsen(cur, np.asarray(vectors_per_level[l]), block, wsa, split)
         levels.append(nxt)
     return Hierarchy(levels, coarsest, coarsest_tol).factor_coarsest()
 
@@ -372,7 +396,7 @@ def _two_level_exact(level: Level, Ac) -> Callable:
 
 def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_iters: int,
                    coarsest="cholesky", coarsest_tol=1e-12, log: Optional[list] = None,
-                   sa_scale: float = 0.0) -> Hierarchy:
+                   sa_scale: float = 0.0, split: bool = False) -> Hierarchy:
     """Adaptive setup (Adaptive Multigrid section), level by level.
 
     For each coarsening l with random starts randoms[l] ([1 + Nv, n_l]):
@@ -384,7 +408,8 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
         error is restricted to the aggregates, orthonormalised against the earlier
         vectors and appended, and A_c is rebuilt;
       * the finished A_c is the next level's operator (the procedure recurses).
-    With sa_scale > 0 every prolongator is the smoothed one (see the module notes).
+    With sa_scale > 0 every prolongator is the smoothed one (see the module notes);
+    with split every coarsening uses chirality-split aggregates.
     """
     levels = [Level(A=A, shape=tuple(shape))]
     for l, block in enumerate(blocks):
@@ -397,7 +422,7 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
             e = e - smoother_apply(cur.A, cur.coefs, cur.A @ e)
             e = e / norm(e)
         vecs = [e]
-        cur, nxt = coarsen(cur, np.array(vecs), block, wsa)
+        cur, nxt = coarsen(cur, np.array(vecs), block, wsa, split)
         for k in range(1, nvs[l]):
             V = _two_level_exact(cur, nxt.A)
             e = np.array(R[1 + k], copy=True)
@@ -405,7 +430,7 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
                 e = e - V(cur.A @ e)
                 e = e / norm(e)
             vecs.append(e)
-            cur, nxt = coarsen(cur, np.array(vecs), block, wsa)
+            cur, nxt = coarsen(cur, np.array(vecs), block, wsa, split)
         if log is not None:
             log.append({"level": l, "coefs": list(cur.coefs)})
         levels.append(nxt)
@@ -420,7 +445,7 @@ def set_mass(h: Hierarchy, A_fine, calib_per_level, nu: int, omega: float) -> Hi
     A = A_fine
     for l, lev in enumerate(h.levels):
         new = Level(A=A, shape=lev.shape, block=lev.block, U=lev.U, P=lev.P, P_t=lev.P_t, gather=lev.gather,
-                    sa_weight=lev.sa_weight)
+                    sa_weight=lev.sa_weight, split=lev.split)
         if lev.P is not None:
             new.coefs = mr_coefficients(A, calib_per_level[l], nu, omega)
             A = galerkin(A, lev.P)

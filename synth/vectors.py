@@ -41,25 +41,26 @@ def point_source(lx: int, lt: int, x: int = 0, t: int = 0, spin: int = 0) -> np.
     return v
 
 
-def level_shapes(lx: int, lt: int, blocks: Sequence[Sequence[int]], nvs: Sequence[int]):
-    """(lx_l, lt_l, dof_l) for every level of a hierarchy; level 0 is the fine lattice."""
+def level_shapes(lx: int, lt: int, blocks: Sequence[Sequence[int]], nvs: Sequence[int], split: bool = False):
+    """(lx_l, lt_l, dof_l) for every level of a hierarchy; level 0 is the fine lattice.
+    A coarse site carries Nv variables, or 2 Nv with chirality-split aggregates."""
     shapes = [(lx, lt, 2)]
     for (bx, bt), nv in zip(blocks, nvs):
         cx, ct, _ = shapes[-1]
         if cx % bx or ct % bt:
             raise ValueError(f"extent {cx}x{ct} not divisible by block {bx}x{bt}")
-        shapes.append((cx // bx, ct // bt, nv))
+        shapes.append((cx // bx, ct // bt, nv * (2 if split else 1)))
     return shapes
 
 
-def setup_randoms(lx: int, lt: int, blocks, nvs, seed: int):
+def setup_randoms(lx: int, lt: int, blocks, nvs, seed: int, split: bool = False):
     """Random starts for the adaptive setup, one array per coarsening.
 
     For coarsening l (fine side of size n_l = lx_l*lt_l*dof_l) the array has shape
     ``[1 + Nv_l, n_l]``: row 0 starts the smoother calibration, rows 1..Nv_l start
     the Nv_l candidate near-null vectors in order.
     """
-    shapes = level_shapes(lx, lt, blocks, nvs)
+    shapes = level_shapes(lx, lt, blocks, nvs, split)
     out = []
     for lvl, nv in enumerate(nvs):
         cx, ct, dof = shapes[lvl]

@@ -535,3 +535,103 @@ def test_sa_vcycle_error_propagator_and_projector(levels):
     v2 = v1 - P @ mg.vcycle(h, 1, P.conj().T @ (A @ v1))
     rhs = v2 - R_(A @ v2)
     np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------------------
+# Chirality-split aggregates (the alternative reading of the aggregates S_j as
+# subsets of variables: each block split by chirality, gamma5 = sigma3)
+# ---------------------------------------------------------------------------
+
+def _split_hierarchy(levels=3, lx=16, lt=16, nv=3, sa_scale=0.0, seed=61):
+    U = hot_field(lx, lt, seed, sweeps=10)
+    A = normal_matrix(U, 0.15)
+    blocks = [(2, 2)] * (levels - 1)
+    nvs = [nv] * (levels - 1)
+    R = synth.setup_randoms(lx, lt, blocks, nvs, seed, split=True)
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, nu=2, omega=0.8, setup_iters=2, sa_scale=sa_scale,
+                          split=True)
+    return A, h
+
+
+def test_split_gather_partitions_by_component_parity():
+    G = mg.aggregate_gather((8, 4, 2), (2, 2), split=True)
+    assert G.shape == (2 * 4 * 2, 2 * 2)
+    assert np.array_equal(np.sort(G.ravel()), np.arange(8 * 4 * 2))
+    # row 2J + chi: block J, spin chi, sites in the unsplit order
+    assert G[0].tolist() == [0, 2, 16, 18] and G[1].tolist() == [1, 3, 17, 19]
+    Gc = mg.aggregate_gather((4, 4, 6), (2, 2), split=True)
+    assert all(int(i) % 6 % 2 == 0 for i in Gc[0]) and all(int(i) % 6 % 2 == 1 for i in Gc[1])
+
+
+def test_split_tentative_prolongator_commutes_with_gamma5():
+    """gamma5 P_t = P_t gamma5_c with gamma5_c = diag((-1)^c) on every coarse site: on the
+    fine level gamma5 = sigma3, on a coarse level the parity of the variable."""
+    _, h = _split_hierarchy()
+    for l in range(2):
+        lev = h.levels[l]
+        P = lev.P_t.toarray()
+        n, nc_tot = P.shape
+        g_f = np.where(np.arange(n) % lev.shape[2] % 2 == 0, 1.0, -1.0)
+        g_c = np.where(np.arange(nc_tot) % 2 == 0, 1.0, -1.0)
+        if l == 0:
+            np.testing.assert_array_equal(g_f, np.diag(gamma5_matrix(16 * 16).toarray()))
+        assert np.max(np.abs(g_f[:, None] * P - P * g_c[None, :])) == 0.0
+        np.testing.assert_allclose(P.conj().T @ P, np.eye(nc_tot), atol=1e-14)
+        assert h.levels[l + 1].shape[2] == 2 * 3
+
+
+def test_split_columns_equal_qr_of_restricted_candidates():
+    """Column 2k + chi on block K is the k-th column of the QR factor (positive real
+    diagonal of R) of the candidates restricted to the chi-variables of K."""
+    rng = np.random.default_rng(12)
+    lx, lt, nv = 4, 4, 3
+    V = rng.standard_normal((nv, 2 * lx * lt)) + 1j * rng.standard_normal((nv, 2 * lx * lt))
+    lev = mg.Level(A=normal_matrix(hot_field(lx, lt, 3, sweeps=2), 0.3), shape=(lx, lt, 2))
+    lev, nxt = mg.coarsen(lev, V, (2, 2), split=True)
+    P = lev.P_t.toarray()
+    Gb = mg.aggregate_gather((lx, lt, 2), (2, 2))
+    for K in range(Gb.shape[0]):
+        for chi in (0, 1):
+            rows = [int(i) for i in Gb[K] if i % 2 == chi]
+            Q, Rr = np.linalg.qr(V[:, rows].T)
+            ph = np.diag(Rr) / np.abs(np.diag(Rr))   # Q R = (Q ph)(ph^* R), diag(ph^* R) > 0
+            cols = [K * 2 * nv + 2 * k + chi for k in range(nv)]
+            np.testing.assert_allclose(P[np.ix_(rows, cols)], Q * ph[None, :], atol=1e-13)
+    assert nxt.shape == (2, 2, 2 * nv)
+
+
+def test_split_range_contains_unsplit_range():
+    """Every unsplit column lies in the span of the split columns of its block."""
+    rng = np.random.default_rng(13)
+    V = rng.standard_normal((3, 2 * 8 * 8)) + 1j * rng.standard_normal((3, 2 * 8 * 8))
+    A = normal_matrix(hot_field(8, 8, 4, sweeps=2), 0.3)
+    Pu = mg.coarsen(mg.Level(A=A, shape=(8, 8, 2)), V, (2, 2))[0].P_t.toarray()
+    Ps = mg.coarsen(mg.Level(A=A, shape=(8, 8, 2)), V, (2, 2), split=True)[0].P_t.toarray()
+    np.testing.assert_allclose(Ps @ (Ps.conj().T @ Pu), Pu, atol=1e-13)
+    assert np.linalg.matrix_rank(Ps) == 2 * np.linalg.matrix_rank(Pu)
+
+
+@pytest.mark.parametrize("sa_scale", [0.0, 4 / 3])
+def test_split_hierarchy_vcycle_identity_and_mgcg(sa_scale):
+    """With split aggregates the V-cycle keeps I - V A = (I - R A)(I - P V_c P^H A)(I - R A)
+    and MG-CG converges to the direct solution."""
+    lx = lt = 16
+    U = hot_field(lx, lt, 62, sweeps=10)
+    A = normal_matrix(U, 0.15)
+    blocks = [(4, 4)]
+    R = synth.setup_randoms(lx, lt, blocks, [3], 62, split=True)
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, [3], R, nu=2, omega=0.8, setup_iters=2, sa_scale=sa_scale,
+                          split=True)
+    assert h.levels[1].shape == (4, 4, 6) and (h.levels[0].sa_weight > 0) == (sa_scale > 0)
+    lev = h.levels[0]
+    P = lev.P.toarray()
+    Ad = A.toarray()
+    b = synth.gaussian(A.shape[0], 9)
+    lhs = b - mg.vcycle(h, 0, A @ b)
+    v1 = b - mg.smoother_apply(A, lev.coefs, A @ b)
+    v2 = v1 - P @ np.linalg.solve(h.levels[1].A.toarray(), P.conj().T @ (A @ v1))
+    rhs = v2 - mg.smoother_apply(A, lev.coefs, A @ v2)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.linalg.norm(b))
+    x, info = mg.mg_cg(h, b, 1e-12)
+    assert info.converged
+    np.testing.assert_allclose(x, np.linalg.solve(Ad, b), atol=1e-9 * np.linalg.norm(np.linalg.solve(Ad, b)))
