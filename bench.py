@@ -37,6 +37,7 @@ SWEEPS = 500
 SEEDS = [2000, 2001, 2002, 2003]
 BLOCKS = [(4, 4), (4, 4)]
 NV = [12, 12]
+SPLIT_NV = [6, 6]   # chirality-split comparison: 2 x 6 = 12 coarse variables per site, as above
 NU = 4
 OMEGA = 0.8
 SETUP_ITERS = 5
@@ -499,6 +500,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
     ap.add_argument("--no-mrhs", action="store_true")
+    ap.add_argument("--no-split", action="store_true", help="skip the chirality-split comparison")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
     ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
@@ -650,6 +652,61 @@ def main():
         dt = time.perf_counter() - t0
         results[name] = dict(seconds=dt, solves=len(systems) * args.steps, records=rec)
         log(f"{name}: {len(systems) * args.steps / dt:.1f} solves/s")
+
+    # ---- chirality-split aggregates on the same systems: Nv = 6 candidates per level, each
+    # block split by chirality, so the coarse levels carry 12 variables per site as above
+    split = None
+    if not args.no_split:
+        ssys, ssetup = [], []
+        rhs_of = {(seed, m): rhs for _, rhs, seed, m in systems}
+        for seed, U in zip(SEEDS, fields):
+            ms = masses[seed]
+            m_light = min(ms)
+            p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=SPLIT_NV, setup_iters=SETUP_ITERS,
+                                smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE,
+                                operator_storage=OPERATOR_STORAGE, split_chirality=True)
+            R = synth.setup_randoms(L, L, BLOCKS, SPLIT_NV, seed, split=True)
+            g, rnd = T(U), T(np.concatenate([r.ravel() for r in R]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s0 = smg.Solver(g, p, randoms=rnd)
+            torch.cuda.synchronize()
+            ssetup.append(time.perf_counter() - t0)
+            for m in ms:
+                ssys.append((s0 if m == m_light else s0.derive(m), rhs_of[(seed, m)]))
+
+        def run_split(w, rec):
+            with torch.cuda.stream(streams[w]):
+                for k in range(w, len(ssys), nwork):
+                    s, rhs = ssys[k]
+                    x, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=smg.MIXED, out=xs[k],
+                                          stream=streams[w])
+                    if code != 0 or st[0]["true_relres"] > TOL:
+                        raise RuntimeError(f"split solve did not converge: system {k} {st[0]}")
+                    if rec is not None:
+                        rec.append(st[0]["iterations"])
+
+        srec = []
+        for f in [pool.submit(run_split, w, srec) for w in range(nwork)]:
+            f.result()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for f in [pool.submit(run_split, w, None) for w in range(nwork)]:
+                f.result()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        split = dict(nv=SPLIT_NV, coarse_dof=[2 * k for k in SPLIT_NV],
+                     mixed_solves_per_s=len(ssys) * args.steps / dt,
+                     mean_iterations_mixed=sum(srec) / len(srec),
+                     unsplit_mean_iterations_mixed=sum(r["iterations"] for r in results["mixed"]["records"])
+                     / len(results["mixed"]["records"]),
+                     setup_s_per_field=ssetup)
+        log(f"chirality split: {split['mixed_solves_per_s']:.1f} solves/s, "
+            f"{split['mean_iterations_mixed']:.2f} iterations")
+        for s, _ in ssys:
+            s.close()
+        del ssys
     pool.shutdown()
 
     # ---- dominant-kernel roofline: the FP32 level-2 coarse operator of the mixed solve
@@ -740,6 +797,7 @@ def main():
         "cpu_baseline": cpu,
         "multi_rhs": mrhs,
         "serving": serving,
+        "chirality_split": split,
     }
     print(json.dumps(line))
     return 0

@@ -109,6 +109,15 @@ typedef struct {
                                      SMG_STORE_F16 (each array scaled by a power of two so
                                      that its entries are at most 1; arithmetic stays FP32,
                                      the outer FP64 correction sets the final accuracy) */
+  int32_t split_chirality;        /* 1: every aggregate is split by chirality (Adaptive Multigrid
+                                     section: aggregates are subsets of variables).  The
+                                     variables d of a block with d % 2 = 0 and with d % 2 = 1
+                                     (on the fine lattice the spin components, gamma5 = sigma3)
+                                     form two aggregates, so a coarse site carries 2 nv[l]
+                                     variables, ordered 2k + chi for candidate k and chirality
+                                     chi, and P maps chirality to chirality on every level.
+                                     Needs nv[l] <= bx * bt * dof / 2 and 2 nv[l] <= 64.
+                                     0 (default): one aggregate per block, nv[l] variables. */
 } smg_params;
 
 typedef struct {
@@ -125,7 +134,7 @@ typedef struct {
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
  * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16,
- * operator_storage = SMG_STORE_F32. */
+ * operator_storage = SMG_STORE_F32, split_chirality = 0. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).

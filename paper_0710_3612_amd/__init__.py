@@ -79,6 +79,7 @@ class Params(ctypes.Structure):
         ("stop_recursive", ctypes.c_int32),
         ("mfma_min_rhs", ctypes.c_int32),
         ("operator_storage", ctypes.c_int32),
+        ("split_chirality", ctypes.c_int32),
     ]
 
 
@@ -182,7 +183,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
                 seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16,
                 smoother_storage: int = STORE_F32, stop_recursive: bool = False,
-                operator_storage: int = STORE_F32) -> Params:
+                operator_storage: int = STORE_F32, split_chirality: bool = False) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -204,6 +205,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.smoother_storage = smoother_storage
     p.stop_recursive = int(bool(stop_recursive))
     p.operator_storage = operator_storage
+    p.split_chirality = int(bool(split_chirality))
     return p
 
 
@@ -419,7 +421,7 @@ class Solver:
         return h.value, w.value
 
     def prolongator(self, level: int, smoothed: bool = False, stream=None):
-        """P of coarsening `level` as [J, nv, nw] complex128: the tentative one
+        """P of coarsening `level` as [J, nc, nw] complex128: the tentative one
         (smoothed=False, nw = bx*bt*dof) or the one the V-cycle uses (windows of
         (bx+2h)(bt+2h) sites)."""
         lx, lt, dof = self.level_info(level)

@@ -218,7 +218,7 @@ void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf,
                         int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
 
 // Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
-void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk,
+void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int m,
                       int* fail, hipStream_t st);
 
 // Galerkin helpers: X = sum over aggregates J of colour (cxc, ctc) of P[J][k] (zero elsewhere).

@@ -329,12 +329,18 @@ __device__ inline void block_allreduce2(double& a, double& b, double* sh) {
   for (int i = 0; i < kThreads / 64; ++i) { a += sh[2 * i]; b += sh[2 * i + 1]; }
 }
 
+// Candidate k of block J (blockIdx.x) appended to the tentative P, two passes of
+// modified Gram-Schmidt.  m = 1: one aggregate per block, column k.  m = 2
+// (chirality split): blockIdx.y = chi takes the variables with d % 2 = chi, is made
+// orthogonal to the earlier columns of the same chirality (those of the other one
+// have disjoint support) and becomes column 2k + chi, zero on the other variables.
 template <int NCH>
 __global__ void __launch_bounds__(kThreads) k_gs_append(z64* __restrict__ P, const z64* __restrict__ v, int lx,
-                                                        int dof, int bx, int bt, int cx, int k, int ldk,
+                                                        int dof, int bx, int bt, int cx, int k, int ldk, int m,
                                                         int* __restrict__ fail) {
   __shared__ double sh[2 * (kThreads / 64)];
   const int J = blockIdx.x;
+  const int chi = blockIdx.y;
   const int nagg = bx * bt * dof;
   z64* PJ = P + (size_t)J * ldk * nagg;
   z64 w[NCH];
@@ -342,12 +348,13 @@ __global__ void __launch_bounds__(kThreads) k_gs_append(z64* __restrict__ P, con
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = threadIdx.x + kThreads * c;
-    w[c] = (i < nagg) ? v[agg_index(J, i, lx, dof, bx, bt, cx)] : mk(0.0, 0.0);
+    const bool mine = i < nagg && (m == 1 || (i % dof) % 2 == chi);
+    w[c] = mine ? v[agg_index(J, i, lx, dof, bx, bt, cx)] : mk(0.0, 0.0);
     ref += w[c].re * w[c].re + w[c].im * w[c].im;
   }
   block_allreduce2(ref, dummy, sh);
   for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < k; ++j) {
+    for (int j = chi; j < m * k; j += m) {
       const z64* u = PJ + (size_t)j * nagg;
       double re = 0, im = 0;
 #pragma unroll
@@ -379,7 +386,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_append(z64* __restrict__ P, con
     nrm = 1.0;
   }
   const double inv = 1.0 / nrm;
-  z64* out = PJ + (size_t)k * nagg;
+  z64* out = PJ + (size_t)(m * k + chi) * nagg;
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = threadIdx.x + kThreads * c;
@@ -1024,13 +1031,15 @@ void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx,
   launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
-void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int* fail,
-                      hipStream_t st) {
+void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int m,
+                      int* fail, hipStream_t st) {
   const int cx = lx / bx, nK = cx * (lt / bt);
   const int nagg = bx * bt * dof;
+  if ((m != 1 && m != 2) || (m == 2 && dof % 2) || m * (k + 1) > ldk)
+    throw Error(-1, "Gram-Schmidt append: bad split or column index");
   dispatch_chunks((nagg + kThreads - 1) / kThreads, [&](auto c) {
-    hipLaunchKernelGGL((k_gs_append<decltype(c)::v>), dim3(nK), dim3(kThreads), 0, st, (z64*)P, v, lx, dof, bx, bt,
-                       cx, k, ldk, fail);
+    hipLaunchKernelGGL((k_gs_append<decltype(c)::v>), dim3(nK, m), dim3(kThreads), 0, st, (z64*)P, v, lx, dof, bx,
+                       bt, cx, k, ldk, m, fail);
   });
   HIPCHECK(hipGetLastError());
 }

@@ -736,12 +736,17 @@ void smooth_column(Ctx& c, int l, int k) {
     }
 }
 
+// Prolongator columns per candidate vector: 2 with chirality-split aggregates.
+inline int cols_per_vector(const smg_params& p) { return p.split_chirality ? 2 : 1; }
+
+// Appends candidate k: column k, or columns 2k and 2k + 1 with chirality-split aggregates.
 void gs_append(Ctx& c, int l, const z64* v, int k) {
   auto& lv = c.L64[l];
+  const int m = cols_per_vector(c.prm);
   zero(c.fail, sizeof(int), c.st);
-  launch_gs_append((double*)lv.Pt, v, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, c.fail, c.st);
+  launch_gs_append((double*)lv.Pt, v, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, k, lv.ldk, m, c.fail, c.st);
   check_fail(c, "block Gram-Schmidt: candidate vector is degenerate on an aggregate");
-  smooth_column(c, l, k);
+  for (int chi = 0; chi < m; ++chi) smooth_column(c, l, m * k + chi);
 }
 
 // Smoothed-aggregation weight of level l: w = sa_scale / lambda, lambda the Rayleigh
@@ -858,7 +863,8 @@ void adaptive_level(Ctx& c, int l, const z64* rnd) {
     launch_axpy_const<double>(c.se, c.sz, -1.0, n, 1, c.st);
     scale_to_unit(c, c.se, n);
   }
-  set_nc(c, l, 1);
+  const int m = cols_per_vector(c.prm);
+  set_nc(c, l, m);
   gs_append(c, l, c.se, 0);
   galerkin(c, l);
   // further candidates: the current two-level V-cycle as error propagator
@@ -871,7 +877,7 @@ void adaptive_level(Ctx& c, int l, const z64* rnd) {
       scale_to_unit(c, c.se, n);
     }
     gs_append(c, l, c.se, k);
-    set_nc(c, l, k + 1);
+    set_nc(c, l, m * (k + 1));
     galerkin(c, l);
   }
 }
@@ -890,6 +896,8 @@ void validate(const smg_params& p) {
     throw Error(SMG_EINVAL, "bad smoother_storage");
   if (p.operator_storage != SMG_STORE_F32 && p.operator_storage != SMG_STORE_F16)
     throw Error(SMG_EINVAL, "operator_storage must be SMG_STORE_F32 or SMG_STORE_F16");
+  if (p.split_chirality != 0 && p.split_chirality != 1) throw Error(SMG_EINVAL, "split_chirality must be 0 or 1");
+  const int m = p.split_chirality ? 2 : 1;
   if (p.smoother_storage != SMG_STORE_F32 && (p.levels < 2 || !normal_lp_fits(p.lx, p.lt)))
     throw Error(SMG_EINVAL, "BF16/FP16 smoother storage needs levels >= 2, lx % 32 == 0 and lt % 16 == 0");
   int lx = p.lx, lt = p.lt, dof = 2;
@@ -898,12 +906,12 @@ void validate(const smg_params& p) {
     if (bx < 1 || bt < 1) throw Error(SMG_EINVAL, "block extents must be positive");
     if (lx % bx || lt % bt) throw Error(SMG_ESHAPE, "lattice extent not divisible by the block extent");
     const int nv = p.nv[l];
-    if (nv < 1 || nv > 64) throw Error(SMG_EINVAL, "nv must be in [1, 64]");
-    if (nv > bx * bt * dof) throw Error(SMG_EINVAL, "nv exceeds the variables of an aggregate");
+    if (nv < 1 || m * nv > 64) throw Error(SMG_EINVAL, "nv must be in [1, 64] (in [1, 32] with split_chirality)");
+    if (m * nv > bx * bt * dof) throw Error(SMG_EINVAL, "nv exceeds the variables of an aggregate");
     if (bx * bt * dof > 1024) throw Error(SMG_EINVAL, "aggregates larger than 1024 variables are not supported");
     lx /= bx;
     lt /= bt;
-    dof = nv;
+    dof = m * nv;
   }
   if ((size_t)p.lx * p.lt * 2 > (size_t)1 << 30) throw Error(SMG_EINVAL, "lattice too large");
 }
@@ -939,7 +947,7 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z6
       auto& lv = c->L64[l];
       lv.lx = pv.lx / prm->block[l - 1][0];
       lv.lt = pv.lt / prm->block[l - 1][1];
-      lv.dof = prm->nv[l - 1];
+      lv.dof = prm->nv[l - 1] * (prm->split_chirality ? 2 : 1);
       lv.n = (size_t)lv.lx * lv.lt * lv.dof;
       lv.L = c->pool.alloc<z64>(9 * (size_t)lv.lx * lv.lt * lv.dof * lv.dof);
       pv.bx = prm->block[l - 1][0];
@@ -1354,6 +1362,7 @@ void smg_default_params(smg_params* p) {
   p->sa_scale = 4.0 / 3.0;
   p->mfma_min_rhs = 16;
   p->operator_storage = SMG_STORE_F32;
+  p->split_chirality = 0;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
@@ -1409,7 +1418,7 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
       sa_weight(*c, l);
       const z64* vl = (const z64*)vectors + level_offset_randoms(*c, l, false);
       for (int k = 0; k < nv; ++k) gs_append(*c, l, vl + (size_t)k * n, k);
-      set_nc(*c, l, nv);
+      set_nc(*c, l, nv * cols_per_vector(c->prm));
       galerkin(*c, l);
     }
     finish_setup(*c);
@@ -1465,7 +1474,7 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
       c->calib[l] = cb;
     }
     for (int l = 0; l + 1 < c->nlev; ++l) {
-      set_nc(*c, l, c->prm.nv[l]);
+      set_nc(*c, l, c->prm.nv[l] * cols_per_vector(c->prm));
       calibrate(*c, l);
       galerkin(*c, l);
     }

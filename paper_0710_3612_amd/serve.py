@@ -677,7 +677,8 @@ class DeviceBackend:
     def estimate(self, field, capacity: int) -> int:
         g, p = self.fields[field]
         blocks = [(p.block[l][0], p.block[l][1]) for l in range(p.levels - 1)]
-        nv = [p.nv[l] for l in range(p.levels - 1)]
+        # coarse variables per site: nv, or 2 nv with chirality-split aggregates
+        nv = [p.nv[l] * (2 if p.split_chirality else 1) for l in range(p.levels - 1)]
         return estimate_bytes(p.lx, p.lt, blocks, nv, capacity, mixed=self.mixed,
                               smoothed=p.sa_scale > 0, coarsest_direct=p.coarsest == 0)
 

@@ -46,9 +46,9 @@ def smg_mod():
     return smg
 
 
-def hierarchy_inputs(lx, lt, blocks, nvs, seed):
+def hierarchy_inputs(lx, lt, blocks, nvs, seed, split=False):
     """Near-null vectors and calibration starts per level, shared by both sides."""
-    shapes = synth.level_shapes(lx, lt, blocks, nvs)
+    shapes = synth.level_shapes(lx, lt, blocks, nvs, split)
     vecs, calib = [], []
     for l, nv in enumerate(nvs):
         cx, ct, dof = shapes[l]
@@ -123,6 +123,10 @@ CASES = [
     (64, 64, [(4, 4)], [8], 0.1, SA),               # coarsest 2048: blocked Gauss-Jordan, 4 blocks
     (48, 48, [(4, 4)], [7], 0.1, SA),               # coarsest 1008: blocked, ragged last block
     (64, 64, [(2, 2)], [5], 0.1, SA),               # coarsest 5120: blocked inverse, tiled multi-RHS apply
+    # chirality-split aggregates: 2 Nv coarse variables per site
+    (32, 32, [(4, 4), (2, 2)], [4, 3], 0.05, SA, True),  # split on both levels (dof 8, then 6)
+    (64, 64, [(4, 4)], [6], 0.1, SA, True),              # nc = 12 on 16^2 coarse sites, fused fine kernel
+    (24, 24, [(4, 4)], [8], 0.1, 0.0, True),             # plain aggregation, nc = 16
 ]
 
 
@@ -155,12 +159,14 @@ def pair(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     smg = smg_mod()
-    lx, lt, blocks, nvs, m, sa = CASES[request.param]
+    lx, lt, blocks, nvs, m, sa = CASES[request.param][:6]
+    split = CASES[request.param][6] if len(CASES[request.param]) > 6 else False
     U = field(lx, lt, seed=request.param + 1)
-    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, request.param + 7)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, request.param + 7, split)
     A = normal_matrix(U, m)
-    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=sa)
-    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, sa_scale=sa)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=sa, split=split)
+    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, sa_scale=sa,
+                        split_chirality=split)
     s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])),
                    calib=dev(np.concatenate(calib)))
     yield dict(U=U, A=A, h=h, s=s, lx=lx, lt=lt, blocks=blocks, nvs=nvs, m=m, calib=calib)
@@ -178,12 +184,16 @@ def test_prolongator(pair):
     h, s = pair["h"], pair["s"]
     for l in range(len(pair["blocks"])):
         lev = h.levels[l]
-        assert rel_err(host(s.prolongator(l)), lev.U) <= 1e-12
+        nc = s.level_info(l + 1)[2]
+        if lev.split:
+            assert rel_err(host(s.prolongator(l)), windowed(lev.P_t, lev.shape, lev.block, nc, 0)) <= 1e-12
+        else:
+            assert rel_err(host(s.prolongator(l)), lev.U) <= 1e-12
         halo, w = s.transfer_info(l)
         assert halo == (1 if lev.sa_weight > 0 else 0)
         if halo:
             assert abs(w - lev.sa_weight) <= 1e-12 * lev.sa_weight
-        ref = windowed(lev.P, lev.shape, lev.block, lev.U.shape[1], halo)
+        ref = windowed(lev.P, lev.shape, lev.block, nc, halo)
         assert rel_err(host(s.prolongator(l, smoothed=True)), ref) <= 1e-12
 
 
@@ -325,6 +335,47 @@ def test_adaptive_setup_and_solve_c1(cuda):
     xc, stc, code = s.cg(dev(rhs), tol=1e-10)
     _, ic = mg.cg(A, rhs, 1e-10)
     assert code == 0 and abs(stc[0]["iterations"] - ic.iterations) <= 2
+    s.close()
+
+
+def test_adaptive_setup_split_chirality(cuda):
+    """Adaptive setup with chirality-split aggregates (3 levels, 2 Nv coarse variables
+    per site): smoothers, the per-block projectors of P and the solves against the oracle."""
+    smg = smg_mod()
+    lx = lt = 32
+    m = 0.08
+    blocks, nvs = [(4, 4), (2, 2)], [4, 3]
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 50, 1001))
+    R = synth.setup_randoms(lx, lt, blocks, nvs, 2, split=True)
+    A = normal_matrix(U, m)
+    rhs = dirac_matrix(U, m).conj().T @ synth.gaussian(2 * lx * lt, 1)
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, nu=4, omega=0.8, setup_iters=4, sa_scale=4 / 3,
+                          split=True)
+    xo, io = mg.mg_cg(h, rhs, 1e-10)
+    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, setup_iters=4, sa_scale=4 / 3,
+                        split_chirality=True)
+    s = smg.Solver(dev(U), p, randoms=dev(np.concatenate([r.ravel() for r in R])))
+    assert s.level_info(1) == (8, 8, 8) and s.level_info(2) == (4, 4, 6)
+    np.testing.assert_allclose(s.smoother_coefs(0), h.levels[0].coefs, rtol=1e-12)
+    for l in range(2):
+        Pg = host(s.prolongator(l))
+        Po = windowed(h.levels[l].P_t, h.levels[l].shape, h.levels[l].block, Pg.shape[1], 0)
+        proj_g = np.einsum("jki,jkl->jil", Pg, Pg.conj())
+        proj_o = np.einsum("jki,jkl->jil", Po, Po.conj())
+        assert np.max(np.abs(proj_g - proj_o)) <= 1e-7, l
+        # chirality: column 2k + chi vanishes on the variables of the other chirality
+        dof = h.levels[l].shape[2]
+        chi_var = np.arange(Pg.shape[2]) % dof % 2
+        for c in range(Pg.shape[1]):
+            assert np.max(np.abs(Pg[:, c, chi_var != c % 2])) == 0.0
+    for prec in (smg.FP64, smg.MIXED):
+        x, st, code = s.solve(dev(rhs), tol=1e-10, maxiter=500, precision=prec)
+        assert code == 0
+        xh = host(x)
+        assert np.linalg.norm(rhs - A @ xh) / np.linalg.norm(rhs) <= 1e-10
+        assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) < 1e-7
+        if prec == smg.FP64:
+            assert abs(st[0]["iterations"] - io.iterations) <= 1
     s.close()
 
 
