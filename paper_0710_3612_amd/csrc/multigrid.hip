@@ -153,6 +153,80 @@ void launch_restrict_kw(dim3 grid, hipStream_t st, const TP* P, R ps, const TX* 
     go(IntC<4>{});
 }
 
+// FP32 restriction with one wavefront per aggregate forming all NCOL >= nc inner
+// products: each lane accumulates 2 * NCOL partial sums (re and im per column) over
+// its window variables, with every P row requested before the first product.  A
+// halving butterfly then sums them across the wavefront: at offset o each lane
+// keeps half of its values and adds the other half of its partner's, so after
+// log2(2 NCOL) steps (offsets 32, 16, ...) one sum is left per lane group and plain
+// steps finish it.  That is 2 NCOL - 1 shuffles, where reducing each sum on its own
+// takes 6 per sum.  Four aggregates per workgroup, no barrier.
+template <int NCOL>
+__device__ inline float butterfly_sum(float (&v)[2 * NCOL], int lane) {
+  constexpr int V = 2 * NCOL;
+  int o = 32;
+#pragma unroll
+  for (int cnt = V; cnt > 1; cnt >>= 1, o >>= 1) {
+    const bool up = lane & o;
+#pragma unroll
+    for (int j = 0; j < cnt / 2; ++j) {
+      const float send = up ? v[2 * j] : v[2 * j + 1];
+      const float keep = up ? v[2 * j + 1] : v[2 * j];
+      v[j] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  float r = v[0];
+  for (; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+template <int NCOL, int NCH, typename TX, typename TP>
+__global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__ P, const TX* __restrict__ x,
+                                                          z32* __restrict__ y, int lx, int lt, int dof, int bx,
+                                                          int bt, int h, int nc, int ldk, float ps) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (K >= nK) return;  // whole wavefronts; the kernel has no barrier
+  const int lane = threadIdx.x & 63;
+  const size_t n = (size_t)lx * lt * dof;
+  const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
+  const TX* xr = x + blockIdx.y * n;
+  const TP* PK = P + (size_t)K * ldk * nagg;
+  TP pv[NCOL][NCH];
+#pragma unroll
+  for (int k = 0; k < NCOL; ++k)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) pv[k][c] = PK[(size_t)min(k, nc - 1) * nagg + min(lane + 64 * c, nagg - 1)];
+  z32 xv[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = lane + 64 * c;
+    xv[c] = (i < nagg) ? ldv(xr, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<float>(0, 0);
+  }
+  float v[2 * NCOL];
+#pragma unroll
+  for (int k = 0; k < NCOL; ++k) {
+    float re = 0, im = 0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const z32 a = widen(pv[k][c]);
+      re += a.re * xv[c].re + a.im * xv[c].im;
+      im += a.re * xv[c].im - a.im * xv[c].re;
+    }
+    v[2 * k] = re;
+    v[2 * k + 1] = im;
+  }
+  const float r = butterfly_sum<NCOL>(v, lane);
+  // the sum left in this lane: bit s of its index is lane bit 5 - s
+  constexpr int V = 2 * NCOL, LOGV = V == 8 ? 3 : V == 16 ? 4 : 5;
+  int idx = 0;
+#pragma unroll
+  for (int b = 0; b < LOGV; ++b) idx |= ((lane >> (5 - b)) & 1) << b;
+  const int k = idx >> 1;
+  if ((lane & (64 / V - 1)) == 0 && k < nc)
+    reinterpret_cast<float*>(y + ((size_t)blockIdx.y * nK + K) * nc)[idx] = ps * r;
+}
+
 // Prolongation y (+)= P e in two deterministic phases.
 // Phase 1: per aggregate window, w[K][i] = sum_k P[K][k][i] e[K][k] (lanes walk the
 // window variables, so P rows are read coalesced and e is a broadcast).
@@ -689,6 +763,26 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
                        int nc, int ldk, int nrhs, hipStream_t st) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  if constexpr (std::is_same<R, float>::value) {
+    // one wavefront per aggregate while its P rows fit in registers (at most 64 words)
+    const int nch = (nw + 63) / 64, ncol = nc <= 4 ? 4 : nc <= 8 ? 8 : 16;
+    if (nc <= 16 && nch <= 2 && ncol * nch * (int)(sizeof(TP) / 4) <= 64) {
+      dim3 g((nK + kThreads / 64 - 1) / (kThreads / 64), nrhs);
+      auto go = [&](auto ncl, auto ch) {
+        hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP>), g, dim3(kThreads), 0, st, P,
+                           x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps);
+      };
+      auto by_ch = [&](auto ncl) {
+        if (nch == 1) go(ncl, IntC<1>{});
+        else go(ncl, IntC<2>{});
+      };
+      if (ncol == 4) by_ch(IntC<4>{});
+      else if (ncol == 8) by_ch(IntC<8>{});
+      else by_ch(IntC<16>{});
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+  }
   dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
     launch_restrict_kw<R, decltype(c)::v, TX, TP>(grid, st, P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
