@@ -227,6 +227,58 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__
     reinterpret_cast<float*>(y + ((size_t)blockIdx.y * nK + K) * nc)[idx] = ps * r;
 }
 
+// The same for windows of more than 128 variables: one workgroup per aggregate,
+// wavefront w takes the 64-variable chunks w, w + 4, ... (at most CPW of them), and
+// the four butterfly results are added in wavefront order through LDS.
+template <int NCOL, int CPW, typename TX, typename TP>
+__global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict__ P, const TX* __restrict__ x,
+                                                           z32* __restrict__ y, int lx, int lt, int dof, int bx,
+                                                           int bt, int h, int nc, int ldk, float ps) {
+  constexpr int NW = kThreads / 64, V = 2 * NCOL, LOGV = V == 8 ? 3 : V == 16 ? 4 : 5;
+  __shared__ float part[NW][V];
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int K = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t n = (size_t)lx * lt * dof;
+  const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
+  const TX* xr = x + blockIdx.y * n;
+  const TP* PK = P + (size_t)K * ldk * nagg;
+  TP pv[CPW][NCOL];
+  z32 xv[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int i = lane + 64 * (w + NW * j);
+#pragma unroll
+    for (int k = 0; k < NCOL; ++k) pv[j][k] = PK[(size_t)min(k, nc - 1) * nagg + min(i, nagg - 1)];
+    xv[j] = (i < nagg) ? ldv(xr, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<float>(0, 0);
+  }
+  float v[V];
+#pragma unroll
+  for (int k = 0; k < NCOL; ++k) {
+    float re = 0, im = 0;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const z32 a = widen(pv[j][k]);
+      re += a.re * xv[j].re + a.im * xv[j].im;
+      im += a.re * xv[j].im - a.im * xv[j].re;
+    }
+    v[2 * k] = re;
+    v[2 * k + 1] = im;
+  }
+  const float r = butterfly_sum<NCOL>(v, lane);
+  int idx = 0;
+#pragma unroll
+  for (int b = 0; b < LOGV; ++b) idx |= ((lane >> (5 - b)) & 1) << b;
+  if ((lane & (64 / V - 1)) == 0) part[w][idx] = r;
+  __syncthreads();
+  if (threadIdx.x < 2 * nc) {
+    float t = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += part[q][threadIdx.x];
+    reinterpret_cast<float*>(y + ((size_t)blockIdx.y * nK + K) * nc)[threadIdx.x] = ps * t;
+  }
+}
+
 // Prolongation y (+)= P e in two deterministic phases.
 // Phase 1: per aggregate window, w[K][i] = sum_k P[K][k][i] e[K][k] (lanes walk the
 // window variables, so P rows are read coalesced and e is a broadcast).
@@ -779,6 +831,24 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
       if (ncol == 4) by_ch(IntC<4>{});
       else if (ncol == 8) by_ch(IntC<8>{});
       else by_ch(IntC<16>{});
+      HIPCHECK(hipGetLastError());
+      return;
+    }
+    // one workgroup per aggregate, the chunks spread over its four wavefronts
+    const int cpw = (nch + kThreads / 64 - 1) / (kThreads / 64);
+    if (nc <= 16 && cpw <= 2 && ncol * cpw * (int)(sizeof(TP) / 4) <= 64) {
+      dim3 g(nK, nrhs);
+      auto go = [&](auto ncl, auto cw) {
+        hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP>), g, dim3(kThreads), 0, st, P,
+                           x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps);
+      };
+      auto by_cw = [&](auto ncl) {
+        if (cpw == 1) go(ncl, IntC<1>{});
+        else go(ncl, IntC<2>{});
+      };
+      if (ncol == 4) by_cw(IntC<4>{});
+      else if (ncol == 8) by_cw(IntC<8>{});
+      else by_cw(IntC<16>{});
       HIPCHECK(hipGetLastError());
       return;
     }
