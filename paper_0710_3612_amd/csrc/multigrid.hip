@@ -348,6 +348,44 @@ __global__ void __launch_bounds__(kThreads) k_prolong_gather(const cpx<R>* __res
   y[o] = MODE == 0 ? acc : y0 + acc;
 }
 
+// Phase 2 without the general search: with h = 0 a variable lies in the window of
+// its own block only; with h = 1 (both coarse extents >= 2) also in the window of
+// the block before it along an axis when it is the first site of its block there
+// (window coordinate b + 1) and of the block after it when it is the last (window
+// coordinate 0).  Windows are visited in the order of the general kernel (blocks
+// j - 1, j, j + 1 along t, then along x); four integer divisions per variable.
+template <typename R, int MODE, int H>
+__global__ void __launch_bounds__(kThreads) k_prolong_gather_f(const cpx<R>* __restrict__ wbuf,
+                                                               cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
+                                                               int bt) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int wxw = bx + 2 * H;
+  const int nw = wxw * (bt + 2 * H) * dof;
+  const size_t n = (size_t)lx * lt * dof;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int rhs = blockIdx.y;
+  const int site = (int)(idx / dof), d = (int)(idx - (size_t)site * dof);
+  const int t = site / lx, x = site - t * lx;
+  const int jt = t / bt, ut = t - jt * bt, jx = x / bx, ux = x - jx * bx;
+  const cpx<R>* wb = wbuf + (size_t)rhs * nK * nw;
+  const size_t o = (size_t)rhs * n + idx;
+  const cpx<R> y0 = MODE == 1 ? y[o] : mk<R>(0, 0);  // requested early, added last
+  // candidate blocks and window coordinates along each axis, in the order j - 1, j, j + 1
+  int bt_[3], wt_[3], nt = 0, bx_[3], wx_[3], nx = 0;
+  if (H == 1 && ut == 0) { bt_[nt] = jt == 0 ? ct - 1 : jt - 1; wt_[nt++] = bt + 1; }
+  bt_[nt] = jt; wt_[nt++] = ut + H;
+  if (H == 1 && ut == bt - 1) { bt_[nt] = jt == ct - 1 ? 0 : jt + 1; wt_[nt++] = 0; }
+  if (H == 1 && ux == 0) { bx_[nx] = jx == 0 ? cx - 1 : jx - 1; wx_[nx] = bx + 1; ++nx; }
+  bx_[nx] = jx; wx_[nx++] = ux + H;
+  if (H == 1 && ux == bx - 1) { bx_[nx] = jx == cx - 1 ? 0 : jx + 1; wx_[nx] = 0; ++nx; }
+  cpx<R> acc = mk<R>(0, 0);
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nx; ++b)
+      acc = acc + wb[(size_t)(bt_[a] * cx + bx_[b]) * nw + (wt_[a] * wxw + wx_[b]) * dof + d];
+  y[o] = MODE == 0 ? acc : y0 + acc;
+}
+
 // ---------------------------------------------------------------------------
 // Coarse 9-point operator: y_K = sum_D L_{K,D} v_{K+D}.  Links are stored
 // [D][col][K][row], so for a fixed (D, col) consecutive outputs (K, row) read
@@ -892,10 +930,22 @@ void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbu
                      0, st, P, e, wbuf, nK, nw, nc, ldk, ps);
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_prolong_gather<R, 0>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt, h);
-  else
-    hipLaunchKernelGGL((k_prolong_gather<R, 1>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt, h);
+  // h = 1 needs both coarse extents >= 2 (then no window covers a site twice) and blocks
+  // of at least 2 sites along each axis (the first and last site of a block differ)
+  const bool fast = h == 0 || (h == 1 && lx / bx >= 2 && lt / bt >= 2 && bx >= 2 && bt >= 2);
+  auto go = [&](auto md, auto hh) {
+    constexpr int M = decltype(md)::v, HH = decltype(hh)::v;
+    if (fast)
+      hipLaunchKernelGGL((k_prolong_gather_f<R, M, HH>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt);
+    else
+      hipLaunchKernelGGL((k_prolong_gather<R, M>), grid, dim3(kThreads), 0, st, wbuf, y, lx, lt, dof, bx, bt, h);
+  };
+  auto by_h = [&](auto md) {
+    if (h == 0) go(md, IntC<0>{});
+    else go(md, IntC<1>{});
+  };
+  if (mode == 0) by_h(IntC<0>{});
+  else by_h(IntC<1>{});
   HIPCHECK(hipGetLastError());
 }
 
