@@ -1340,6 +1340,53 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const TM* __restrict__ 
   if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)(mscale * re), (R)(mscale * im));
 }
 
+// k_dense_rows for n % 4 == 0: each lane reads four consecutive entries of the row
+// (and of x) per load, and up to G such quads per lane are in flight together, so a
+// row of n <= 4096 FP16 entries takes at most two round trips instead of six.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T e[4];
+};
+
+template <typename RM, typename R, typename TM, int G>
+__global__ void __launch_bounds__(kThreads) k_dense_rows4(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                          cpx<R>* __restrict__ y, int n, double mscale) {
+  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const int nq = n / 4;
+  const Quad<TM>* Mr = reinterpret_cast<const Quad<TM>*>(M + (size_t)row * n);
+  const Quad<cpx<R>>* xb = reinterpret_cast<const Quad<cpx<R>>*>(x + (size_t)blockIdx.y * n);
+  double re = 0, im = 0;
+  for (int q0 = lane; q0 < nq; q0 += 64 * G) {
+    Quad<TM> m[G];
+    Quad<cpx<R>> v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int q = min(q0 + 64 * u, nq - 1);  // clamped: all loads of the group in flight together
+      m[u] = Mr[q];
+      v[u] = xb[q];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keeps every load of the group ahead of the first product
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const bool dup = q0 + 64 * u >= nq;  // a clamped duplicate contributes nothing
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const cpx<RM> a = widen(m[u].e[e]);
+        const cpx<R> b = dup ? mk<R>(0, 0) : v[u].e[e];
+        re = fma((double)a.re, (double)b.re, re);
+        re = fma(-(double)a.im, (double)b.im, re);
+        im = fma((double)a.re, (double)b.im, im);
+        im = fma((double)a.im, (double)b.re, im);
+      }
+    }
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)(mscale * re), (R)(mscale * im));
+}
+
 // The kernel is chosen by n alone, so a column's result never depends on nrhs.
 // Y = M X on the matrix cores, FP32 (M stored as TM: z32 or scaled hfc), for the
 // large coarsest inverses (n > kDenseRowsMax).  A workgroup owns 32 rows x 32
@@ -1420,7 +1467,23 @@ __global__ void __launch_bounds__(256) k_dense_mfma(const TM* __restrict__ M, co
 // mscale: power-of-two scale of a reduced-precision M (1 otherwise), applied exactly.
 template <typename RM, typename R, typename TM>
 void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
-  if (n <= kDenseRowsMax) {
+  if (n <= kDenseRowsMax && n % 4 == 0) {
+    // quads in flight per lane: all of a row of n <= 4096 in one group where registers allow
+    constexpr int W = (int)((sizeof(TM) + sizeof(cpx<R>)) / 4);  // registers per entry pair
+    constexpr int GMAX = W <= 3 ? 16 : (W <= 4 ? 8 : 4);
+    const int want = (n / 4 + 63) / 64;
+    const dim3 g((n + 3) / 4, nrhs);
+    if (want <= 4 || GMAX == 4)
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4>), g, dim3(kThreads), 0, st, M, x, y, n, mscale);
+    else if (want <= 8 || GMAX == 8)
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 8>), g, dim3(kThreads), 0, st, M, x, y, n, mscale);
+    else if (want <= 12)
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 12 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
+                         mscale);
+    else
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 16 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
+                         mscale);
+  } else if (n <= kDenseRowsMax) {
     hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale);
   } else if constexpr (std::is_same<R, float>::value) {
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
