@@ -133,6 +133,69 @@ __global__ void __launch_bounds__(kThreads) k_axpy_update(cpx<R>* __restrict__ x
   }
 }
 
+// k_axpy_update with alpha formed in every block from the per-workgroup partials of
+// <p, A p> (the fused CG step), in the order of k_reduce_final<1>, so alpha is the
+// same in every block and equal to what that pass would give; block 0 records it
+// and a breakdown.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_axpy_update_fold(cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
+                                                               const cpx<R>* __restrict__ p,
+                                                               const cpx<R>* __restrict__ q,
+                                                               const double* __restrict__ ppart, int pnb,
+                                                               const double* __restrict__ rz,
+                                                               double* __restrict__ alpha, const int* __restrict__ active,
+                                                               int* __restrict__ bad, int* __restrict__ bad_host,
+                                                               size_t n, int nb, double* __restrict__ partial) {
+  __shared__ double s_alpha;
+  const int j = blockIdx.y;
+  double re = 0, im = 0;
+  for (int i = threadIdx.x; i < pnb; i += kThreads) {
+    re += ppart[2 * ((size_t)j * pnb + i)];
+    im += ppart[2 * ((size_t)j * pnb + i) + 1];
+  }
+  block_sum2(re, im);
+  if (threadIdx.x == 0) {
+    double al = 0;
+    bool broke = false;
+    if (active[j]) {
+      const double num = rz[2 * j], den = re;
+      if (!isfinite(num) || !isfinite(den)) {
+        broke = true;
+      } else if (num == 0) {
+        al = 0;
+      } else if (!(den > 0)) {
+        broke = true;
+      } else {
+        al = num / den;
+      }
+    }
+    if (blockIdx.x == 0) {
+      if (broke) {
+        bad[j] = 1;
+        if (bad_host) bad_host[j] = 1;
+      }
+      alpha[j] = al;
+    }
+    s_alpha = al;
+  }
+  __syncthreads();
+  const size_t off = (size_t)j * n;
+  const R a = (R)s_alpha;
+  double rr = 0, dummy = 0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)nb * kThreads) {
+    const size_t k = off + i;
+    x[k] = x[k] + a * p[k];
+    const cpx<R> rn = r[k] - a * q[k];
+    r[k] = rn;
+    rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+  }
+  block_sum2(rr, dummy);
+  if (threadIdx.x == 0) {
+    partial[2 * ((size_t)j * nb + blockIdx.x)] = rr;
+    partial[2 * ((size_t)j * nb + blockIdx.x) + 1] = 0;
+  }
+}
+
 template <typename R>
 __global__ void k_xpay(const cpx<R>* __restrict__ z, cpx<R>* __restrict__ p, const double* __restrict__ beta,
                        size_t n) {
@@ -296,13 +359,6 @@ void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red 
   HIPCHECK(hipGetLastError());
 }
 
-void launch_alpha_from_partials(const double* partial, int nb, int nrhs, const double* rz, double* alpha,
-                                const int* active, int* bad, int* bad_host, hipStream_t st) {
-  hipLaunchKernelGGL((k_reduce_final<1>), dim3(nrhs), dim3(kThreads), 0, st, partial, nb, alpha,
-                     const_cast<double*>(rz), active, bad, nullptr, bad_host);
-  HIPCHECK(hipGetLastError());
-}
-
 void launch_beta_from_partials(const double* partial, int nb, int nrhs, double* rz, double* beta, const int* active,
                                hipStream_t st) {
   hipLaunchKernelGGL((k_reduce_final<2>), dim3(nrhs), dim3(kThreads), 0, st, partial, nb, beta, rz, active, nullptr,
@@ -326,6 +382,17 @@ void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, 
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_axpy_update<R>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, alpha, n, nb,
                      red.partial);
+  hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, rr, nullptr, nullptr,
+                     nullptr, rr_host, nullptr);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_axpy_update_fold(z32* x, z32* r, const z32* p, const z32* q, const double* ppart, int pnb,
+                             const double* rz, double* alpha, const int* active, int* bad, int* bad_host, size_t n,
+                             int nrhs, Red red, double* rr, hipStream_t st, double* rr_host) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_axpy_update_fold<float>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, ppart, pnb, rz,
+                     alpha, active, bad, bad_host, n, nb, red.partial);
   hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, rr, nullptr, nullptr,
                      nullptr, rr_host, nullptr);
   HIPCHECK(hipGetLastError());

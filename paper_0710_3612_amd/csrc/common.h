@@ -259,16 +259,18 @@ template <typename R>
 void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red red, const double* rz,
                       double* alpha, const int* active, int* bad, hipStream_t st, int* bad_host = nullptr);
 // <r, z>_new per column, then beta = <r,z>_new / <r,z>_old and <r,z>_old <- <r,z>_new (active columns).
-// alpha = <r,z> / <p,q> from nb given partials of <p, q> per column (as launch_dot_alpha's second pass).
-void launch_alpha_from_partials(const double* partial, int nb, int nrhs, const double* rz, double* alpha,
-                                const int* active, int* bad, int* bad_host, hipStream_t st);
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st);  // out[2*rhs] = <a,b> (complex)
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
                         int nrhs, Red red, double* rr, hipStream_t st,
-                        double* rr_host = nullptr);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
+                        double* rr_host = nullptr);
+// x += alpha p, r -= alpha q and |r|^2 (FP32), alpha formed in every block from the
+// partial sums of <p, A p> of the fused CG step (pnb per column) and <r, z> in rz
+void launch_axpy_update_fold(z32* x, z32* r, const z32* p, const z32* q, const double* ppart, int pnb,
+                             const double* rz, double* alpha, const int* active, int* bad, int* bad_host, size_t n,
+                             int nrhs, Red red, double* rr, hipStream_t st, double* rr_host);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
 template <typename R>
 void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
 template <typename R>

@@ -539,13 +539,15 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         launch_cg_step<float>(lv.U, v.z, p_cur, p_alt, v.q, lv.lx, lv.lt, lv.diag, nrhs, S.ab, c.cg_partial, c.st);
         c.fine_applies += nrhs;
         std::swap(p_cur, p_alt);
-        launch_alpha_from_partials(c.cg_partial, fuse_nb, nrhs, S.rz, S.ab, S.active, S.bad, S.bad_host, c.st);
+        // alpha from the step's partial sums inside the update kernel
+        launch_axpy_update_fold(x, v.r, p_cur, v.q, c.cg_partial, fuse_nb, S.rz, S.ab, S.active, S.bad, S.bad_host,
+                                n, nrhs, c.red, S.rr, c.st, S.rr_host);
       }
     } else {
       apply_op<R>(c, lv, p_cur, v.q, nrhs, 0, 0.0, nullptr, nullptr);
       launch_dot_alpha<R>(p_cur, v.q, n, nrhs, c.red, S.rz, S.ab, S.active, S.bad, c.st, S.bad_host);
+      launch_axpy_update<R>(x, v.r, p_cur, v.q, S.ab, n, nrhs, c.red, S.rr, c.st, S.rr_host);
     }
-    launch_axpy_update<R>(x, v.r, p_cur, v.q, S.ab, n, nrhs, c.red, S.rr, c.st, S.rr_host);
     for (int j = 0; j < nrhs; ++j) its[j] += act[j];
     if (it % check_interval == 0 || it == maxiter) {
       sync(c);  // the reductions wrote |r|^2 and the breakdown flags to S.rr_host / S.bad_host
