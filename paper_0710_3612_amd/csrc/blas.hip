@@ -359,13 +359,6 @@ void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red 
   HIPCHECK(hipGetLastError());
 }
 
-void launch_beta_from_partials(const double* partial, int nb, int nrhs, double* rz, double* beta, const int* active,
-                               hipStream_t st) {
-  hipLaunchKernelGGL((k_reduce_final<2>), dim3(nrhs), dim3(kThreads), 0, st, partial, nb, beta, rz, active, nullptr,
-                     nullptr, nullptr);
-  HIPCHECK(hipGetLastError());
-}
-
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st) {

@@ -157,6 +157,20 @@ template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
                    int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
 
+// beta of the fused CG step formed inside the kernel (part == nullptr: read beta[rhs]).
+// Every workgroup sums the nb partials of <r, z> per column in the order of the
+// separate second pass; beta = <r,z> / rz_old[rhs] for an active column with a nonzero
+// rz_old (else 0), beta = 0 for every column when rz_old is null (the first step).
+// Workgroup 0 writes <r, z> to rz_new (rz_old where the column is not active).
+constexpr int kBetaFoldMaxBlocks = 4 * kThreads;  // largest nb of a folded beta
+struct BetaFold {
+  const double* part = nullptr;
+  int nb = 0;
+  const double* rz_old = nullptr;
+  double* rz_new = nullptr;
+  const int* active = nullptr;
+};
+
 // The outer CG step on the fine level in one fused kernel: p = z + beta p_old (p = z
 // where beta = 0), q = A p, and per workgroup <p, q> into partial[rhs][block] for
 // cg_step_blocks(lx, lt) blocks (0: no fused tile fits, use the separate kernels).
@@ -164,16 +178,14 @@ template <typename R>
 int cg_step_blocks(int lx, int lt);
 template <typename R>
 void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
-                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st);
+                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
+                    const BetaFold& bf = BetaFold{});
 // The last fine apply of a V-cycle with the CG dot folded in: z += c v + c2 (v - c A v)
 // (the last two smoother steps) and per workgroup <r, z> into partial[rhs][block]
 // (cg_step_blocks(lx, lt) blocks).
 template <typename R>
 void launch_vcycle_end(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
                        int nrhs, double c, double c2, double* partial, hipStream_t st);
-// beta = <r,z>_new / <r,z>_old (and <r,z>_old <- <r,z>_new) from nb given partials of <r, z>.
-void launch_beta_from_partials(const double* partial, int nb, int nrhs, double* rz, double* beta, const int* active,
-                               hipStream_t st);
 // FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
 // (lx and lt multiples of 16).
 template <typename TI, typename TO>

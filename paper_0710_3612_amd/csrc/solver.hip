@@ -94,6 +94,7 @@ struct Level {
 
 struct Scal {
   double *bb = nullptr, *rz = nullptr, *pq = nullptr, *ab = nullptr, *rr = nullptr, *tt = nullptr;
+  double* rz2 = nullptr;            // second <r,z> slot: the fused CG step reads one and writes the other
   int *active = nullptr, *bad = nullptr;
   // host-visible mirrors of rr and bad in coherent pinned memory, written by the reductions
   // themselves: the per-iteration convergence check needs a synchronisation but no copy
@@ -130,6 +131,7 @@ struct Ctx {
   double mscale = 1;
   double* absmax_part = nullptr;    // per-block maxima for the FP16 scales
   double* cg_partial = nullptr;     // per-workgroup <p, A p> of the fused CG step
+  double* rz_partial = nullptr;     // per-workgroup <r, z> of the V-cycle's last fine apply
   size_t cg_partial_cap = 0;
   // set by the FP32 CG around a V-cycle: its last fine apply also leaves the partial
   // sums of <r, z> here (vend_done tells the CG that it did)
@@ -188,6 +190,7 @@ void ensure_scalars(Ctx& c, int nrhs) {
   for (auto& s : c.sc) {
     s.bb = c.pool.alloc<double>(2 * cap);
     s.rz = c.pool.alloc<double>(2 * cap);
+    s.rz2 = c.pool.alloc<double>(2 * cap);
     s.pq = c.pool.alloc<double>(2 * cap);
     s.ab = c.pool.alloc<double>(2 * cap);
     s.rr = c.pool.alloc<double>(2 * cap);
@@ -520,27 +523,59 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     const size_t need = (size_t)2 * fuse_nb * nrhs;
     if (c.cg_partial_cap < need) {
       c.cg_partial = c.pool.alloc<double>(need);
+      c.rz_partial = c.pool.alloc<double>(need);
       c.cg_partial_cap = need;
     }
   }
   cpx<R>* p_cur = v.p;
   cpx<R>* p_alt = v.p2;
+  // Fused path: <r, z> lives in one of two slots.  When the V-cycle's last fine apply
+  // left its partial sums (folded), the next CG step forms beta from them, moves <r, z>
+  // to the other slot and the update kernel reads it from there; otherwise a separate
+  // pass forms beta and <r, z> in the current slot.
+  double* rz_cur = S.rz;
+  double* rz_nxt = S.rz2;
+  bool folded = false;
+  auto precondition_fold = [&](const cpx<R>* r, cpx<R>* z) {
+    if (fuse_nb > kBetaFoldMaxBlocks) {  // too many partial sums for the CG step to add itself
+      precondition(r, z);
+      return false;
+    }
+    c.vend_partial = c.rz_partial;
+    c.vend_done = false;
+    precondition(r, z);
+    const bool f = c.vend_done;
+    c.vend_partial = nullptr;
+    c.vend_done = false;
+    return f;
+  };
+  bool first = true;  // the first CG step takes p = z (beta = 0)
   if (nact > 0) {
-    precondition(v.r, v.z);
-    if (fuse_nb > 0)
-      launch_zero(S.ab, sizeof(double) * 2 * nrhs, c.st);  // beta = 0: the first step takes p = z
-    else
+    if (fuse_nb > 0) {
+      folded = precondition_fold(v.r, v.z);
+      if (!folded) {
+        launch_zero(S.ab, sizeof(double) * 2 * nrhs, c.st);
+        launch_dot<R>(v.r, v.z, n, nrhs, c.red, rz_cur, c.st);
+      }
+    } else {
+      precondition(v.r, v.z);
       HIPCHECK(hipMemcpyAsync(v.p, v.z, bytes, hipMemcpyDeviceToDevice, c.st));
-    launch_dot<R>(v.r, v.z, n, nrhs, c.red, S.rz, c.st);
+      launch_dot<R>(v.r, v.z, n, nrhs, c.red, S.rz, c.st);
+    }
   }
   for (int it = 1; it <= maxiter && nact > 0; ++it) {
     if (fuse_nb > 0) {
       if constexpr (std::is_same<R, float>::value) {
-        launch_cg_step<float>(lv.U, v.z, p_cur, p_alt, v.q, lv.lx, lv.lt, lv.diag, nrhs, S.ab, c.cg_partial, c.st);
+        BetaFold bf;
+        if (folded) bf = BetaFold{c.rz_partial, fuse_nb, first ? nullptr : rz_cur, rz_nxt, S.active};
+        launch_cg_step<float>(lv.U, v.z, p_cur, p_alt, v.q, lv.lx, lv.lt, lv.diag, nrhs, S.ab, c.cg_partial, c.st,
+                              bf);
         c.fine_applies += nrhs;
         std::swap(p_cur, p_alt);
+        if (folded) std::swap(rz_cur, rz_nxt);
+        first = false;
         // alpha from the step's partial sums inside the update kernel
-        launch_axpy_update_fold(x, v.r, p_cur, v.q, c.cg_partial, fuse_nb, S.rz, S.ab, S.active, S.bad, S.bad_host,
+        launch_axpy_update_fold(x, v.r, p_cur, v.q, c.cg_partial, fuse_nb, rz_cur, S.ab, S.active, S.bad, S.bad_host,
                                 n, nrhs, c.red, S.rr, c.st, S.rr_host);
       }
     } else {
@@ -603,22 +638,14 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         if (nact == 0) break;
       }
     }
-    bool folded = false;
     if (fuse_nb > 0) {  // the V-cycle's last fine apply also forms the partial sums of <r, z>
-      c.vend_partial = c.cg_partial;
-      c.vend_done = false;
-      precondition(v.r, v.z);
-      folded = c.vend_done;
-      c.vend_partial = nullptr;
-      c.vend_done = false;
+      folded = precondition_fold(v.r, v.z);
+      if (!folded) launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, rz_cur, S.ab, S.active, c.st);
     } else {
       precondition(v.r, v.z);
-    }
-    if (folded)
-      launch_beta_from_partials(c.cg_partial, fuse_nb, nrhs, S.rz, S.ab, S.active, c.st);
-    else
       launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
-    if (fuse_nb == 0) launch_xpay<R>(v.z, p_cur, S.ab, n, nrhs, c.st);  // fused: in the next CG step
+      launch_xpay<R>(v.z, p_cur, S.ab, n, nrhs, c.st);
+    }
   }
   if (nact > 0) {  // true residual of the columns that did not converge
     apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);

@@ -182,7 +182,8 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
                                                            cpx<R>* __restrict__ xacc,
                                                            const cpx<R>* __restrict__ aux,
                                                            const double* __restrict__ beta = nullptr,
-                                                           double* __restrict__ partial = nullptr) {
+                                                           double* __restrict__ partial = nullptr,
+                                                           BetaFold bf = BetaFold{}) {
   constexpr int HX = TX + 2, HT = TT + 2;
   constexpr int RG = kThreads / TX;          // row groups
   constexpr int PER = TX * TT / kThreads;    // sites per thread
@@ -199,6 +200,21 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const TI* __restrict__ xb = x + off;
   constexpr int NRING = 2 * TX + 2 * TT;
   static_assert(NRING <= kThreads, "one ring site per thread");
+
+  // MODE 6 with a folded beta: the partial sums of <r, z> are requested first, so that
+  // waiting for them later does not wait for the loads issued after them
+  constexpr int NBF = kBetaFoldMaxBlocks / kThreads;
+  double bre[MODE == 6 ? NBF : 1], bim[MODE == 6 ? NBF : 1];
+  if constexpr (MODE == 6) {
+    if (bf.part) {
+#pragma unroll
+      for (int u = 0; u < NBF; ++u) {
+        const int i = min((int)threadIdx.x + u * kThreads, bf.nb - 1);
+        bre[u] = bf.part[2 * ((size_t)blockIdx.y * bf.nb + i)];
+        bim[u] = bf.part[2 * ((size_t)blockIdx.y * bf.nb + i) + 1];
+      }
+    }
+  }
 
   // ---- links, loaded before psi is staged so that both are in flight together
   const int lxi = threadIdx.x % TX, lti = threadIdx.x / TX;
@@ -260,7 +276,45 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
     }
   }
   R bt = 0;
-  if constexpr (MODE == 6) bt = (R)beta[blockIdx.y];
+  if constexpr (MODE == 6) {
+    if (bf.part) {  // beta from the partial sums of <r, z>, in the order of the separate pass
+      __shared__ double sb[2 * (kThreads / 64)];
+      const int j = blockIdx.y;
+      double re = 0, im = 0;
+#pragma unroll
+      for (int u = 0; u < NBF; ++u) {
+        if ((int)threadIdx.x + u * kThreads < bf.nb) {
+          re += bre[u];
+          im += bim[u];
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+      }
+      if ((threadIdx.x & 63) == 0) {
+        sb[2 * (threadIdx.x >> 6)] = re;
+        sb[2 * (threadIdx.x >> 6) + 1] = im;
+      }
+      __syncthreads();
+      re = 0;
+      im = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        re += sb[2 * w];
+        im += sb[2 * w + 1];
+      }
+      double be = 0;
+      if (bf.rz_old && bf.active[j] && bf.rz_old[2 * j] != 0) be = re / bf.rz_old[2 * j];
+      bt = (R)be;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const bool keep = bf.rz_old && !bf.active[j];
+        bf.rz_new[2 * j] = keep ? bf.rz_old[2 * j] : re;
+        bf.rz_new[2 * j + 1] = keep ? bf.rz_old[2 * j + 1] : im;
+      }
+    } else {
+      bt = (R)beta[blockIdx.y];
+    }
+  }
 #pragma unroll
   for (int j = 0; j < NPASS; ++j) {
     const int i = threadIdx.x + j * kThreads;
@@ -461,10 +515,11 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
 
 template <typename R, int TX, int TT, bool NT>
 void launch_cg_step_t(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
-                      double diag, int nrhs, const double* beta, double* partial, hipStream_t st) {
+                      double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
+                      const BetaFold& bf) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
   hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT>), grid, dim3(kThreads), 0, st, U, z, q, lx, lt, (R)diag,
-                     (R)0, (R)0, p, p_old, beta, partial);
+                     (R)0, (R)0, p, p_old, beta, partial, bf);
   HIPCHECK(hipGetLastError());
 }
 
@@ -561,23 +616,30 @@ int cg_step_blocks(int lx, int lt) {
 
 template <typename R>
 void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
-                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st) {
+                    double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
+                    const BetaFold& bf) {
   switch (fused_shape<R>(lx, lt)) {
-    case kT64x4: launch_cg_step_t<R, 64, 4, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
-    case kT64x8nt: launch_cg_step_t<R, 64, 8, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
-    case kT32x16nt:
-      launch_cg_step_t<R, 32, 16, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st);
+    case kT64x4:
+      launch_cg_step_t<R, 64, 4, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
       return;
-    case kT32x8: launch_cg_step_t<R, 32, 8, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st); return;
+    case kT64x8nt:
+      launch_cg_step_t<R, 64, 8, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      return;
+    case kT32x16nt:
+      launch_cg_step_t<R, 32, 16, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      return;
+    case kT32x8:
+      launch_cg_step_t<R, 32, 8, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      return;
     case kT16x16:
-      launch_cg_step_t<R, 16, 16, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st);
+      launch_cg_step_t<R, 16, 16, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
       return;
     default: throw Error(-1, "CG step kernel needs a fused tile shape");
   }
 }
 template int cg_step_blocks<float>(int, int);
 template void launch_cg_step<float>(const z32*, const z32*, const z32*, z32*, z32*, int, int, double, int,
-                                    const double*, double*, hipStream_t);
+                                    const double*, double*, hipStream_t, const BetaFold&);
 
 template <int TX, int TT, typename TI, typename TO>
 void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
