@@ -382,12 +382,10 @@ void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, 
 
 void launch_axpy_update_fold(z32* x, z32* r, const z32* p, const z32* q, const double* ppart, int pnb,
                              const double* rz, double* alpha, const int* active, int* bad, int* bad_host, size_t n,
-                             int nrhs, Red red, double* rr, hipStream_t st, double* rr_host) {
+                             int nrhs, double* rr_part_host, hipStream_t st) {
   const int nb = red_blocks(n);
   hipLaunchKernelGGL((k_axpy_update_fold<float>), dim3(nb, nrhs), dim3(kThreads), 0, st, x, r, p, q, ppart, pnb, rz,
-                     alpha, active, bad, bad_host, n, nb, red.partial);
-  hipLaunchKernelGGL((k_reduce_final<0>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, rr, nullptr, nullptr,
-                     nullptr, rr_host, nullptr);
+                     alpha, active, bad, bad_host, n, nb, rr_part_host);
   HIPCHECK(hipGetLastError());
 }
 

@@ -278,11 +278,13 @@ template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
                         int nrhs, Red red, double* rr, hipStream_t st,
                         double* rr_host = nullptr);
-// x += alpha p, r -= alpha q and |r|^2 (FP32), alpha formed in every block from the
-// partial sums of <p, A p> of the fused CG step (pnb per column) and <r, z> in rz
+// x += alpha p, r -= alpha q (FP32), alpha formed in every block from the partial sums
+// of <p, A p> of the fused CG step (pnb per column) and <r, z> in rz; the per-block
+// partial sums of |r|^2 go to rr_part_host[rhs][red_blocks(n)] (host-visible memory,
+// added up by the host after a synchronisation: no second pass)
 void launch_axpy_update_fold(z32* x, z32* r, const z32* p, const z32* q, const double* ppart, int pnb,
                              const double* rz, double* alpha, const int* active, int* bad, int* bad_host, size_t n,
-                             int nrhs, Red red, double* rr, hipStream_t st, double* rr_host);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
+                             int nrhs, double* rr_part_host, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
 template <typename R>
 void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
 template <typename R>

@@ -101,6 +101,8 @@ struct Scal {
   double* rr_host = nullptr;
   int* bad_host = nullptr;
   int* on_host = nullptr;           // running columns of a defect correction, read by its scale kernel
+  double* rr_part_host = nullptr;   // per-block partial |r|^2 of the fused FP32 CG, added up by the host
+  int rr_part_nb = 0;               // blocks per column in rr_part_host
 };
 
 template <typename R>
@@ -168,6 +170,7 @@ struct Ctx {
       if (s.rr_host) (void)hipHostFree(s.rr_host);
       if (s.bad_host) (void)hipHostFree(s.bad_host);
       if (s.on_host) (void)hipHostFree(s.on_host);
+      if (s.rr_part_host) (void)hipHostFree(s.rr_part_host);
     }
   }
 };
@@ -200,12 +203,16 @@ void ensure_scalars(Ctx& c, int nrhs) {
     if (s.rr_host) (void)hipHostFree(s.rr_host);
     if (s.bad_host) (void)hipHostFree(s.bad_host);
     if (s.on_host) (void)hipHostFree(s.on_host);
+    if (s.rr_part_host) (void)hipHostFree(s.rr_part_host);
     s.rr_host = nullptr;
     s.bad_host = nullptr;
     s.on_host = nullptr;
+    s.rr_part_host = nullptr;
+    s.rr_part_nb = nb;
     HIPCHECK(hipHostMalloc((void**)&s.rr_host, sizeof(double) * 2 * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.bad_host, sizeof(int) * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.on_host, sizeof(int) * cap, hipHostMallocCoherent));
+    HIPCHECK(hipHostMalloc((void**)&s.rr_part_host, sizeof(double) * 2 * nb * cap, hipHostMallocCoherent));
   }
   c.dc_down = c.pool.alloc<double>(cap);
   c.dc_up = c.pool.alloc<double>(cap);
@@ -576,7 +583,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         first = false;
         // alpha from the step's partial sums inside the update kernel
         launch_axpy_update_fold(x, v.r, p_cur, v.q, c.cg_partial, fuse_nb, rz_cur, S.ab, S.active, S.bad, S.bad_host,
-                                n, nrhs, c.red, S.rr, c.st, S.rr_host);
+                                n, nrhs, S.rr_part_host, c.st);
       }
     } else {
       apply_op<R>(c, lv, p_cur, v.q, nrhs, 0, 0.0, nullptr, nullptr);
@@ -586,6 +593,15 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     for (int j = 0; j < nrhs; ++j) its[j] += act[j];
     if (it % check_interval == 0 || it == maxiter) {
       sync(c);  // the reductions wrote |r|^2 and the breakdown flags to S.rr_host / S.bad_host
+      if (fuse_nb > 0) {  // |r|^2 from the update kernel's per-block partial sums, in block order
+        const int nbp = red_blocks(n);
+        for (int j = 0; j < nrhs; ++j) {
+          double t = 0;
+          for (int b = 0; b < nbp; ++b) t += S.rr_part_host[2 * ((size_t)j * nbp + b)];
+          S.rr_host[2 * j] = t;
+          S.rr_host[2 * j + 1] = 0;
+        }
+      }
       std::vector<int> cand(nrhs, 0);
       bool any_cand = false;
       for (int j = 0; j < nrhs; ++j) {
