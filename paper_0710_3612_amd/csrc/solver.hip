@@ -194,7 +194,6 @@ void ensure_scalars(Ctx& c, int nrhs) {
     s.bb = c.pool.alloc<double>(2 * cap);
     s.rz = c.pool.alloc<double>(2 * cap);
     s.rz2 = c.pool.alloc<double>(2 * cap);
-    s.pq = c.pool.alloc<double>(2 * cap);
     s.ab = c.pool.alloc<double>(2 * cap);
     s.rr = c.pool.alloc<double>(2 * cap);
     s.tt = c.pool.alloc<double>(2 * cap);
