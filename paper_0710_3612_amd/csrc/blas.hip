@@ -265,6 +265,30 @@ __global__ void k_dc_scales(const double* __restrict__ rr, const int* __restrict
   up[j] = on[j] ? sqrt(r2) : 0.0;
 }
 
+// Start of an inner FP32 solve: b = s r (rounded to FP32), its copy as the first
+// residual, and the solution cleared, in one pass.
+__global__ void k_scale_down_start(const z64* __restrict__ in, z32* __restrict__ b, z32* __restrict__ r0,
+                                   z32* __restrict__ x0, const double* __restrict__ s, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  const double a = s[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const z32 v = cvt<float>(a * in[off + i]);
+    b[off + i] = v;
+    r0[off + i] = v;
+    x0[off + i] = mk(0.0f, 0.0f);
+  }
+}
+
+// Per-column flags of a Krylov solve from host-visible memory: active[j] = act_host[j],
+// and bad[j] = 0 when bad is given.
+__global__ void k_set_active(int* __restrict__ active, const int* __restrict__ act_host, int* __restrict__ bad,
+                             int nrhs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  active[j] = act_host[j];
+  if (bad) bad[j] = 0;
+}
+
 __global__ void k_scale_down(const z64* __restrict__ in, z32* __restrict__ out, const double* __restrict__ s,
                              size_t n) {
   const size_t off = (size_t)blockIdx.y * n;
@@ -449,6 +473,17 @@ void launch_dc_scales(const double* rr, const int* on, double* down, double* up,
 
 void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_down, ew_grid(n, nrhs), dim3(kThreads), 0, st, in, out, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_scale_down_start(const z64* in, z32* b, z32* r0, z32* x0, const double* s, size_t n, int nrhs,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_down_start, ew_grid(n, nrhs), dim3(kThreads), 0, st, in, b, r0, x0, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_set_active(int* active, const int* act_host, int* bad, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_active, dim3((nrhs + 63) / 64), dim3(64), 0, st, active, act_host, bad, nrhs);
   HIPCHECK(hipGetLastError());
 }
 

@@ -302,6 +302,11 @@ void launch_convert(const cpx<Ri>* in, cpx<Ro>* out, size_t n, hipStream_t st);
 void launch_dc_scales(const double* rr, const int* on, double* down, double* up, int nrhs, hipStream_t st);
 // out32 = in64 * s[rhs]   (defect-correction right-hand side)
 void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int nrhs, hipStream_t st);
+// b = s in (FP32), r0 = b and x0 = 0 in one pass (start of an inner FP32 solve)
+void launch_scale_down_start(const z64* in, z32* b, z32* r0, z32* x0, const double* s, size_t n, int nrhs,
+                             hipStream_t st);
+// active[j] = act_host[j] (host-visible memory written before the launch), bad[j] = 0 if bad
+void launch_set_active(int* active, const int* act_host, int* bad, int nrhs, hipStream_t st);
 // x64 += s[rhs] * e32     (defect-correction update)
 void launch_scale_up_add(z64* x, const z32* e, const double* s, size_t n, int nrhs, hipStream_t st);
 

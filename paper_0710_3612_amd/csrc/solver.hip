@@ -102,6 +102,7 @@ struct Scal {
   int* bad_host = nullptr;
   int* on_host = nullptr;           // running columns of a defect correction, read by its scale kernel
   double* rr_part_host = nullptr;   // per-block partial |r|^2 of the fused FP32 CG, added up by the host
+  int* act_host = nullptr;          // running columns of a Krylov solve, copied to `active` by a kernel
   int rr_part_nb = 0;               // blocks per column in rr_part_host
 };
 
@@ -171,6 +172,7 @@ struct Ctx {
       if (s.bad_host) (void)hipHostFree(s.bad_host);
       if (s.on_host) (void)hipHostFree(s.on_host);
       if (s.rr_part_host) (void)hipHostFree(s.rr_part_host);
+      if (s.act_host) (void)hipHostFree(s.act_host);
     }
   }
 };
@@ -203,6 +205,8 @@ void ensure_scalars(Ctx& c, int nrhs) {
     if (s.bad_host) (void)hipHostFree(s.bad_host);
     if (s.on_host) (void)hipHostFree(s.on_host);
     if (s.rr_part_host) (void)hipHostFree(s.rr_part_host);
+    if (s.act_host) (void)hipHostFree(s.act_host);
+    s.act_host = nullptr;
     s.rr_host = nullptr;
     s.bad_host = nullptr;
     s.on_host = nullptr;
@@ -212,6 +216,7 @@ void ensure_scalars(Ctx& c, int nrhs) {
     HIPCHECK(hipHostMalloc((void**)&s.bad_host, sizeof(int) * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.on_host, sizeof(int) * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.rr_part_host, sizeof(double) * 2 * nb * cap, hipHostMallocCoherent));
+    HIPCHECK(hipHostMalloc((void**)&s.act_host, sizeof(int) * cap, hipHostMallocCoherent));
   }
   c.dc_down = c.pool.alloc<double>(cap);
   c.dc_up = c.pool.alloc<double>(cap);
@@ -479,9 +484,11 @@ template <typename R>
 // the recomputed residual of an ill-conditioned system has a rounding floor above
 // the inner tolerance, and the outer FP64 loop checks the true residual anyway.
 // bb_known: |b|^2 per column when the caller knows it (host array), else NULL and
-// it is computed here.
+// it is computed here.  preset: the caller has already set x = 0 and the first
+// residual v.r = b.
 void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int maxiter, bool precond, KVecs<R>& v,
-         ColStats* cs, int check_interval, int depth, bool true_check = true, const double* bb_known = nullptr) {
+         ColStats* cs, int check_interval, int depth, bool true_check = true, const double* bb_known = nullptr,
+         bool preset = false) {
   auto& lv = levels_of<R>(c)[l];
   Scal& S = c.sc[depth];
   const size_t n = lv.n;
@@ -503,16 +510,19 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   }
   int nact = 0;
   for (int j = 0; j < nrhs; ++j) nact += act[j];
-  auto upload_active = [&]() {
-    for (int j = 0; j < nrhs; ++j) c.h_int[j] = act[j];
-    HIPCHECK(hipMemcpyAsync(S.active, c.h_int, sizeof(int) * nrhs, hipMemcpyHostToDevice, c.st));
-    sync(c);
+  // The running columns reach the device through host-visible memory and a small
+  // kernel, without a synchronisation: the host writes act_host again only after the
+  // next synchronisation of this stream, when that kernel has run.
+  auto upload_active = [&](bool clear_bad) {
+    for (int j = 0; j < nrhs; ++j) S.act_host[j] = act[j];
+    launch_set_active(S.active, S.act_host, clear_bad ? S.bad : nullptr, nrhs, c.st);
   };
-  zero(x, bytes, c.st);
-  HIPCHECK(hipMemcpyAsync(v.r, b, bytes, hipMemcpyDeviceToDevice, c.st));
-  zero(S.bad, sizeof(int) * nrhs, c.st);
+  if (!preset) {
+    zero(x, bytes, c.st);
+    HIPCHECK(hipMemcpyAsync(v.r, b, bytes, hipMemcpyDeviceToDevice, c.st));
+  }
   for (int j = 0; j < nrhs; ++j) S.bad_host[j] = 0;  // no kernel of this stream is running (synchronised above)
-  upload_active();
+  upload_active(true);
   auto precondition = [&](const cpx<R>* r, cpx<R>* z) {
     if (precond)
       vcycle<R>(c, l, c.nlev - 1, r, z, nrhs, c.prm.coarsest == SMG_COARSEST_CG);
@@ -623,7 +633,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
           }
         nact = 0;
         for (int j = 0; j < nrhs; ++j) nact += act[j];
-        upload_active();
+        upload_active(false);
         if (nact == 0) break;
       } else if (any_cand) {
         // confirm on the true residual t = b - A x
@@ -648,7 +658,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         if (changed) {
           nact = 0;
           for (int j = 0; j < nrhs; ++j) nact += act[j];
-          upload_active();
+          upload_active(false);
         }
         if (nact == 0) break;
       }
@@ -1727,13 +1737,13 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
       // the same scales on the device, from the same |r|^2 and this decision (no copy)
       for (int j = 0; j < nrhs; ++j) c->sc[1].on_host[j] = down[j] != 0 ? 1 : 0;
       launch_dc_scales(c->sc[1].rr, c->sc[1].on_host, c->dc_down, c->dc_up, nrhs, c->st);
-      launch_scale_down(c->r64, c->b32, c->dc_down, n, nrhs, c->st);
+      launch_scale_down_start(c->r64, c->b32, c->f32.r, c->e32, c->dc_down, n, nrhs, c->st);
       ColStats inner;
       // The inner solve's own convergence test uses inner_tol; its limit is what is
       // left of maxiter.  Its right-hand side has unit norm in every running column.
       for (int j = 0; j < nrhs; ++j) bb_inner[j] = down[j] != 0 ? 1.0 : 0.0;
       pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0,
-                 false, bb_inner.data());
+                 false, bb_inner.data(), true);
       int maxit = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (down[j] != 0) its[j] += inner.iters[j];
