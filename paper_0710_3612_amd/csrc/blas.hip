@@ -279,6 +279,14 @@ __global__ void k_scale_down_start(const z64* __restrict__ in, z32* __restrict__
   }
 }
 
+// Start of a defect correction: r = b and x = 0 in one pass.
+__global__ void k_dc_start(const z64* __restrict__ b, z64* __restrict__ r, z64* __restrict__ x, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    r[i] = b[i];
+    x[i] = mk(0.0, 0.0);
+  }
+}
+
 // Per-column flags of a Krylov solve from host-visible memory: active[j] = act_host[j],
 // and bad[j] = 0 when bad is given.
 __global__ void k_set_active(int* __restrict__ active, const int* __restrict__ act_host, int* __restrict__ bad,
@@ -479,6 +487,11 @@ void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int n
 void launch_scale_down_start(const z64* in, z32* b, z32* r0, z32* x0, const double* s, size_t n, int nrhs,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_scale_down_start, ew_grid(n, nrhs), dim3(kThreads), 0, st, in, b, r0, x0, s, n);
+  HIPCHECK(hipGetLastError());
+}
+
+void launch_dc_start(const z64* b, z64* r, z64* x, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_start, ew_grid(n, 1), dim3(kThreads), 0, st, b, r, x, n);
   HIPCHECK(hipGetLastError());
 }
 

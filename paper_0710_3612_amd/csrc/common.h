@@ -305,6 +305,8 @@ void launch_scale_down(const z64* in, z32* out, const double* s, size_t n, int n
 // b = s in (FP32), r0 = b and x0 = 0 in one pass (start of an inner FP32 solve)
 void launch_scale_down_start(const z64* in, z32* b, z32* r0, z32* x0, const double* s, size_t n, int nrhs,
                              hipStream_t st);
+// r = b and x = 0 over n complex entries (all columns of a batch: n = nrhs * length)
+void launch_dc_start(const z64* b, z64* r, z64* x, size_t n, hipStream_t st);
 // active[j] = act_host[j] (host-visible memory written before the launch), bad[j] = 0 if bad
 void launch_set_active(int* active, const int* act_host, int* bad, int nrhs, hipStream_t st);
 // x64 += s[rhs] * e32     (defect-correction update)

@@ -1701,27 +1701,26 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
       c->e32 = c->pool.alloc<z32>((size_t)nrhs * n);
       c->dc_cap = (size_t)nrhs * n;
     }
-    const size_t bytes = (size_t)nrhs * n * sizeof(z64);
     const z64* b = (const z64*)rhs;
     z64* xx = (z64*)x;
-    zero(xx, bytes, c->st);
-    HIPCHECK(hipMemcpyAsync(c->r64, b, bytes, hipMemcpyDeviceToDevice, c->st));
-    launch_dot<double>(b, b, n, nrhs, c->red, c->sc[1].bb, c->st);
-    HIPCHECK(hipMemcpyAsync(c->h_scal, c->sc[1].bb, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c->st));
-    sync(*c);
+    launch_dc_start(b, c->r64, xx, (size_t)nrhs * n, c->st);  // r = b, x = 0
     std::vector<double> hbb(nrhs), rel(nrhs, 0.0), down(nrhs), up(nrhs);
     std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
-    for (int j = 0; j < nrhs; ++j) {
-      hbb[j] = c->h_scal[2 * j];
-      if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
-      if (!(hbb[j] > 0)) { act[j] = 0; stat[j] = SMG_OK; }
-    }
     refinements = 0;
     int used = 0;
     std::vector<double> bb_inner(nrhs);
+    bool first = true;
     while (true) {
       launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st, c->sc[1].rr_host);
       sync(*c);
+      if (first) {  // r = b: the first norms are |b|^2
+        first = false;
+        for (int j = 0; j < nrhs; ++j) {
+          hbb[j] = c->sc[1].rr_host[2 * j];
+          if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
+          if (!(hbb[j] > 0)) { act[j] = 0; stat[j] = SMG_OK; }
+        }
+      }
       int nact = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (!act[j]) { down[j] = 0; up[j] = 0; continue; }
