@@ -180,51 +180,64 @@ __device__ inline float butterfly_sum(float (&v)[2 * NCOL], int lane) {
   return r;
 }
 
-template <int NCOL, int NCH, typename TX, typename TP>
+// NRB right-hand sides per wavefront (blockIdx.y takes NRB at a time): the P rows are
+// read once for all of them; each column's arithmetic is the same as with NRB = 1.
+template <int NCOL, int NCH, typename TX, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__ P, const TX* __restrict__ x,
                                                           z32* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                          int bt, int h, int nc, int ldk, float ps) {
+                                                          int bt, int h, int nc, int ldk, float ps, int nrhs) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (K >= nK) return;  // whole wavefronts; the kernel has no barrier
   const int lane = threadIdx.x & 63;
   const size_t n = (size_t)lx * lt * dof;
   const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
-  const TX* xr = x + blockIdx.y * n;
+  const int r0 = blockIdx.y * NRB;
   const TP* PK = P + (size_t)K * ldk * nagg;
   TP pv[NCOL][NCH];
 #pragma unroll
   for (int k = 0; k < NCOL; ++k)
 #pragma unroll
     for (int c = 0; c < NCH; ++c) pv[k][c] = PK[(size_t)min(k, nc - 1) * nagg + min(lane + 64 * c, nagg - 1)];
-  z32 xv[NCH];
+  int wi[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = lane + 64 * c;
-    xv[c] = (i < nagg) ? ldv(xr, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<float>(0, 0);
+    wi[c] = i < nagg ? win_index(K, i, lx, lt, dof, bx, bt, cx, h) : -1;
   }
-  float v[2 * NCOL];
+  z32 xv[NRB][NCH];  // the window of every right-hand side of the group, requested together
 #pragma unroll
-  for (int k = 0; k < NCOL; ++k) {
-    float re = 0, im = 0;
+  for (int q = 0; q < NRB; ++q) {
+    const TX* xr = x + (size_t)min(r0 + q, nrhs - 1) * n;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const z32 a = widen(pv[k][c]);
-      re += a.re * xv[c].re + a.im * xv[c].im;
-      im += a.re * xv[c].im - a.im * xv[c].re;
-    }
-    v[2 * k] = re;
-    v[2 * k + 1] = im;
+    for (int c = 0; c < NCH; ++c) xv[q][c] = wi[c] >= 0 ? ldv(xr, wi[c]) : mk<float>(0, 0);
   }
-  const float r = butterfly_sum<NCOL>(v, lane);
-  // the sum left in this lane: bit s of its index is lane bit 5 - s
+  // the sum left in a lane after the butterfly: bit s of its index is lane bit 5 - s
   constexpr int V = 2 * NCOL, LOGV = V == 8 ? 3 : V == 16 ? 4 : 5;
   int idx = 0;
 #pragma unroll
   for (int b = 0; b < LOGV; ++b) idx |= ((lane >> (5 - b)) & 1) << b;
   const int k = idx >> 1;
-  if ((lane & (64 / V - 1)) == 0 && k < nc)
-    reinterpret_cast<float*>(y + ((size_t)blockIdx.y * nK + K) * nc)[idx] = ps * r;
+#pragma unroll
+  for (int q = 0; q < NRB; ++q) {
+    if (r0 + q >= nrhs) break;
+    float v[2 * NCOL];
+#pragma unroll
+    for (int kk = 0; kk < NCOL; ++kk) {
+      float re = 0, im = 0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const z32 a = widen(pv[kk][c]);
+        re += a.re * xv[q][c].re + a.im * xv[q][c].im;
+        im += a.re * xv[q][c].im - a.im * xv[q][c].re;
+      }
+      v[2 * kk] = re;
+      v[2 * kk + 1] = im;
+    }
+    const float r = butterfly_sum<NCOL>(v, lane);
+    if ((lane & (64 / V - 1)) == 0 && k < nc)
+      reinterpret_cast<float*>(y + ((size_t)(r0 + q) * nK + K) * nc)[idx] = ps * r;
+  }
 }
 
 // The same for windows of more than 128 variables: one workgroup per aggregate,
@@ -857,10 +870,16 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
     // one wavefront per aggregate while its P rows fit in registers (at most 64 words)
     const int nch = (nw + 63) / 64, ncol = nc <= 4 ? 4 : nc <= 8 ? 8 : 16;
     if (nc <= 16 && nch <= 2 && ncol * nch * (int)(sizeof(TP) / 4) <= 64) {
-      dim3 g((nK + kThreads / 64 - 1) / (kThreads / 64), nrhs);
+      // eight right-hand sides per wavefront share its P rows once there are that many
+      const int nrb = nrhs >= 8 ? 8 : 1;
+      dim3 g((nK + kThreads / 64 - 1) / (kThreads / 64), (nrhs + nrb - 1) / nrb);
       auto go = [&](auto ncl, auto ch) {
-        hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP>), g, dim3(kThreads), 0, st, P,
-                           x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps);
+        if (nrb == 8)
+          hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP, 8>), g, dim3(kThreads), 0, st,
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+        else
+          hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP, 1>), g, dim3(kThreads), 0, st,
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
       };
       auto by_ch = [&](auto ncl) {
         if (nch == 1) go(ncl, IntC<1>{});
