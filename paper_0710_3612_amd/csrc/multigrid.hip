@@ -295,30 +295,38 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict_
 // Prolongation y (+)= P e in two deterministic phases.
 // Phase 1: per aggregate window, w[K][i] = sum_k P[K][k][i] e[K][k] (lanes walk the
 // window variables, so P rows are read coalesced and e is a broadcast).
-template <typename R, typename TP = cpx<R>>
+// NRB right-hand sides per thread (blockIdx.y takes NRB at a time): each P entry is
+// read once for all of them; every column's sums run in the same order as with NRB = 1.
+template <typename R, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_prolong_win(const TP* __restrict__ P, const cpx<R>* __restrict__ e,
                                                           cpx<R>* __restrict__ wbuf, int nK, int nw, int nc, int ldk,
-                                                          R ps) {
+                                                          R ps, int nrhs) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nK * nw) return;
   const int K = (int)(idx / nw), i = (int)(idx - (size_t)K * nw);
-  const int rhs = blockIdx.y;
+  const int r0 = blockIdx.y * NRB;
   const TP* PK = P + (size_t)K * ldk * nw + i;
-  const cpx<R>* eK = e + ((size_t)rhs * nK + K) * nc;
-  cpx<R> acc = mk<R>(0, 0);
+  cpx<R> acc[NRB];
+#pragma unroll
+  for (int q = 0; q < NRB; ++q) acc[q] = mk<R>(0, 0);
   for (int k0 = 0; k0 < nc; k0 += 4) {  // four columns per group, index clamped: loads in flight together
-    cpx<R> pv[4], ev[4];
+    cpx<R> pv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = min(k0 + j, nc - 1);
-      pv[j] = widen(PK[(size_t)k * nw]);
-      ev[j] = eK[k];
+    for (int j = 0; j < 4; ++j) pv[j] = widen(PK[(size_t)min(k0 + j, nc - 1) * nw]);
+#pragma unroll
+    for (int q = 0; q < NRB; ++q) {
+      const cpx<R>* eK = e + ((size_t)min(r0 + q, nrhs - 1) * nK + K) * nc;
+      cpx<R> ev[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ev[j] = eK[min(k0 + j, nc - 1)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + j < nc) fma_acc(acc[q], pv[j], ev[j]);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (k0 + j < nc) fma_acc(acc, pv[j], ev[j]);
   }
-  wbuf[(size_t)rhs * nK * nw + idx] = ps * acc;
+#pragma unroll
+  for (int q = 0; q < NRB; ++q)
+    if (r0 + q < nrhs) wbuf[(size_t)(r0 + q) * nK * nw + idx] = ps * acc[q];
 }
 
 // Phase 2: every fine variable sums the window values that cover it (one window
@@ -945,8 +953,12 @@ void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbu
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   const size_t nkw = (size_t)nK * nw;
-  hipLaunchKernelGGL((k_prolong_win<R, TP>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs), dim3(kThreads),
-                     0, st, P, e, wbuf, nK, nw, nc, ldk, ps);
+  if (nrhs >= 8)  // eight right-hand sides per thread share its P entries
+    hipLaunchKernelGGL((k_prolong_win<R, TP, 8>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), (nrhs + 7) / 8),
+                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
+  else
+    hipLaunchKernelGGL((k_prolong_win<R, TP, 1>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs),
+                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
   // h = 1 needs both coarse extents >= 2 (then no window covers a site twice) and blocks
