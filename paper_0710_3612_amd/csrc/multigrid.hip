@@ -243,52 +243,60 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__
 // The same for windows of more than 128 variables: one workgroup per aggregate,
 // wavefront w takes the 64-variable chunks w, w + 4, ... (at most CPW of them), and
 // the four butterfly results are added in wavefront order through LDS.
-template <int NCOL, int CPW, typename TX, typename TP>
+// NRB right-hand sides per workgroup (blockIdx.y takes NRB at a time) share the P rows.
+template <int NCOL, int CPW, typename TX, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict__ P, const TX* __restrict__ x,
                                                            z32* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                           int bt, int h, int nc, int ldk, float ps) {
+                                                           int bt, int h, int nc, int ldk, float ps, int nrhs) {
   constexpr int NW = kThreads / 64, V = 2 * NCOL, LOGV = V == 8 ? 3 : V == 16 ? 4 : 5;
-  __shared__ float part[NW][V];
+  __shared__ float part[NRB][NW][V];
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t n = (size_t)lx * lt * dof;
   const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
-  const TX* xr = x + blockIdx.y * n;
+  const int r0 = blockIdx.y * NRB;
   const TP* PK = P + (size_t)K * ldk * nagg;
   TP pv[CPW][NCOL];
-  z32 xv[CPW];
+  z32 xv[NRB][CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int i = lane + 64 * (w + NW * j);
 #pragma unroll
     for (int k = 0; k < NCOL; ++k) pv[j][k] = PK[(size_t)min(k, nc - 1) * nagg + min(i, nagg - 1)];
-    xv[j] = (i < nagg) ? ldv(xr, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<float>(0, 0);
-  }
-  float v[V];
+    const int wi = i < nagg ? win_index(K, i, lx, lt, dof, bx, bt, cx, h) : -1;
 #pragma unroll
-  for (int k = 0; k < NCOL; ++k) {
-    float re = 0, im = 0;
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const z32 a = widen(pv[j][k]);
-      re += a.re * xv[j].re + a.im * xv[j].im;
-      im += a.re * xv[j].im - a.im * xv[j].re;
-    }
-    v[2 * k] = re;
-    v[2 * k + 1] = im;
+    for (int q = 0; q < NRB; ++q)
+      xv[q][j] = wi >= 0 ? ldv(x + (size_t)min(r0 + q, nrhs - 1) * n, wi) : mk<float>(0, 0);
   }
-  const float r = butterfly_sum<NCOL>(v, lane);
   int idx = 0;
 #pragma unroll
   for (int b = 0; b < LOGV; ++b) idx |= ((lane >> (5 - b)) & 1) << b;
-  if ((lane & (64 / V - 1)) == 0) part[w][idx] = r;
+#pragma unroll
+  for (int q = 0; q < NRB; ++q) {
+    float v[V];
+#pragma unroll
+    for (int k = 0; k < NCOL; ++k) {
+      float re = 0, im = 0;
+#pragma unroll
+      for (int j = 0; j < CPW; ++j) {
+        const z32 a = widen(pv[j][k]);
+        re += a.re * xv[q][j].re + a.im * xv[q][j].im;
+        im += a.re * xv[q][j].im - a.im * xv[q][j].re;
+      }
+      v[2 * k] = re;
+      v[2 * k + 1] = im;
+    }
+    const float r = butterfly_sum<NCOL>(v, lane);
+    if ((lane & (64 / V - 1)) == 0) part[q][w][idx] = r;
+  }
   __syncthreads();
-  if (threadIdx.x < 2 * nc) {
+  const int q = threadIdx.x / (2 * nc), comp = threadIdx.x - q * 2 * nc;
+  if (q < NRB && r0 + q < nrhs) {
     float t = 0;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) t += part[q][threadIdx.x];
-    reinterpret_cast<float*>(y + ((size_t)blockIdx.y * nK + K) * nc)[threadIdx.x] = ps * t;
+    for (int u = 0; u < NW; ++u) t += part[q][u][comp];
+    reinterpret_cast<float*>(y + ((size_t)(r0 + q) * nK + K) * nc)[comp] = ps * t;
   }
 }
 
@@ -901,15 +909,22 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
     }
     // one workgroup per aggregate, the chunks spread over its four wavefronts
     const int cpw = (nch + kThreads / 64 - 1) / (kThreads / 64);
-    if (nc <= 16 && cpw <= 2 && ncol * cpw * (int)(sizeof(TP) / 4) <= 64) {
-      dim3 g(nK, nrhs);
+    if (nc <= 16 && cpw <= 3 && ncol * cpw * (int)(sizeof(TP) / 4) <= 64) {
+      // four right-hand sides per workgroup share its P rows once there are that many
+      const int nrb = nrhs >= 4 ? 4 : 1;
+      dim3 g(nK, (nrhs + nrb - 1) / nrb);
       auto go = [&](auto ncl, auto cw) {
-        hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP>), g, dim3(kThreads), 0, st, P,
-                           x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps);
+        if (nrb == 4)
+          hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP, 4>), g, dim3(kThreads), 0, st,
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+        else
+          hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP, 1>), g, dim3(kThreads), 0, st,
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
       };
       auto by_cw = [&](auto ncl) {
         if (cpw == 1) go(ncl, IntC<1>{});
-        else go(ncl, IntC<2>{});
+        else if (cpw == 2) go(ncl, IntC<2>{});
+        else go(ncl, IntC<3>{});
       };
       if (ncol == 4) by_cw(IntC<4>{});
       else if (ncol == 8) by_cw(IntC<8>{});
