@@ -50,6 +50,16 @@ __host__ __device__ inline void fma_acc(cpx<R>& acc, cpx<R> a, cpx<R> b) {
   acc.re += a.re * b.re - a.im * b.im;
   acc.im += a.re * b.im + a.im * b.re;
 }
+// acc += a b with explicit fused multiply-adds in a fixed order: the rounding does not
+// depend on how the compiler contracts the surrounding code (kernels instantiated
+// for different numbers of right-hand sides give the same bits).
+template <typename R>
+__host__ __device__ inline void fma_acc_x(cpx<R>& acc, cpx<R> a, cpx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
 template <typename R>
 __host__ __device__ inline void fma_acc_conj(cpx<R>& acc, cpx<R> a, cpx<R> b) {  // acc += conj(a) b
   acc.re += a.re * b.re + a.im * b.im;

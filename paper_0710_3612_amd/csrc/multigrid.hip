@@ -66,21 +66,26 @@ __device__ inline bool win_offset(int c, int j, int b, int L, int h, int& o) {
 // The result goes to out[k * ostride_k] (plain restriction or a column of the
 // Galerkin links).
 // ---------------------------------------------------------------------------
-template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>>
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>, int NRB = 1>
 __device__ inline void restrict_one(const TP* __restrict__ P, const TX* __restrict__ x, int K, int lx,
                                     int lt, int dof, int bx, int bt, int cx, int h, int nc, int ldk,
                                     cpx<R>* __restrict__ out, size_t ostride_k, int kbeg = 0, int kstep = 1,
-                                    R ps = 1) {
+                                    R ps = 1, int nq = 1, size_t xstride = 0, size_t ostride = 0) {
   // KW inner products per pass: their P rows are all requested before the first
   // is used (k clamped to nc - 1, window index clamped to nagg - 1; the excess
-  // products are zeroed through xv and the excess results are not stored).
+  // products are zeroed through xv and the excess results are not stored).  With
+  // NRB > 1 the nq <= NRB right-hand sides x + q xstride (results at out + q ostride)
+  // share every P row; each column's sums are those of NRB = 1.
   const int lane = threadIdx.x & 63;
   const int nagg = (bx + 2 * h) * (bt + 2 * h) * dof;
-  cpx<R> xv[NCH];
+  cpx<R> xv[NRB][NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = lane + 64 * c;
-    xv[c] = (i < nagg) ? ldv(x, win_index(K, i, lx, lt, dof, bx, bt, cx, h)) : mk<R>(0, 0);
+    const int wi = i < nagg ? win_index(K, i, lx, lt, dof, bx, bt, cx, h) : -1;
+#pragma unroll
+    for (int q = 0; q < NRB; ++q)
+      xv[q][c] = wi >= 0 ? ldv(x + (size_t)min(q, nq - 1) * xstride, wi) : mk<R>(0, 0);
   }
   const TP* PK = P + (size_t)K * ldk * nagg;
   for (int k0 = kbeg; k0 < nc; k0 += KW * kstep) {
@@ -91,57 +96,75 @@ __device__ inline void restrict_one(const TP* __restrict__ P, const TX* __restri
 #pragma unroll
       for (int c = 0; c < NCH; ++c) p[j][c] = widen(PK[(size_t)k * nagg + min(lane + 64 * c, nagg - 1)]);
     }
-    R re[KW], im[KW];
 #pragma unroll
-    for (int j = 0; j < KW; ++j) {
-      re[j] = 0;
-      im[j] = 0;
+    for (int q = 0; q < NRB; ++q) {
+      if (q >= nq) break;
+      R re[KW], im[KW];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        re[j] += p[j][c].re * xv[c].re + p[j][c].im * xv[c].im;
-        im[j] += p[j][c].re * xv[c].im - p[j][c].im * xv[c].re;
+      for (int j = 0; j < KW; ++j) {
+        re[j] = 0;
+        im[j] = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {  // explicit FMAs: the same rounding for every NRB
+          re[j] = fma(p[j][c].re, xv[q][c].re, re[j]);
+          re[j] = fma(p[j][c].im, xv[q][c].im, re[j]);
+          im[j] = fma(p[j][c].re, xv[q][c].im, im[j]);
+          im[j] = fma(-p[j][c].im, xv[q][c].re, im[j]);
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < KW; ++j) {
-      re[j] = wave_sum(re[j]);
-      im[j] = wave_sum(im[j]);
-    }
-    if (lane == 0) {
+      for (int j = 0; j < KW; ++j) {
+        re[j] = wave_sum(re[j]);
+        im[j] = wave_sum(im[j]);
+      }
+      if (lane == 0) {
 #pragma unroll
-      for (int j = 0; j < KW; ++j)
-        if (k0 + j * kstep < nc) out[(size_t)(k0 + j * kstep) * ostride_k] = mk<R>(ps * re[j], ps * im[j]);
+        for (int j = 0; j < KW; ++j)
+          if (k0 + j * kstep < nc)
+            out[(size_t)q * ostride + (size_t)(k0 + j * kstep) * ostride_k] = mk<R>(ps * re[j], ps * im[j]);
+      }
     }
   }
 }
 
 // One workgroup per aggregate: wavefront w forms the inner products k = w, w+4, ...,
 // KW of them per pass.
-template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>>
+template <typename R, int NCH, typename TX = cpx<R>, int KW = 1, typename TP = cpx<R>, int NRB = 1>
 __global__ void __launch_bounds__(kThreads) k_restrict(const TP* __restrict__ P, const TX* __restrict__ x,
                                                        cpx<R>* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                       int bt, int h, int nc, int ldk, R ps) {
+                                                       int bt, int h, int nc, int ldk, R ps, int nrhs) {
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x;
   if (K >= nK) return;
   const size_t n = (size_t)lx * lt * dof;
-  const int rhs = blockIdx.y;
-  restrict_one<R, NCH, TX, KW, TP>(P, x + rhs * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
-                                   y + (size_t)rhs * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6, kThreads / 64,
-                                   ps);
+  const int r0 = blockIdx.y * NRB;
+  restrict_one<R, NCH, TX, KW, TP, NRB>(P, x + r0 * n, K, lx, lt, dof, bx, bt, cx, h, nc, ldk,
+                                        y + (size_t)r0 * nK * nc + (size_t)K * nc, 1, threadIdx.x >> 6,
+                                        kThreads / 64, ps, min(NRB, nrhs - r0), n, (size_t)nK * nc);
 }
 
 // k_restrict with KW = the inner products of one wave (ceil(nc / 4)), at most 4 per
 // pass and at most 64 words of P rows in flight per lane.
 template <typename R, int NCH, typename TX, typename TP>
 void launch_restrict_kw(dim3 grid, hipStream_t st, const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt,
-                        int dof, int bx, int bt, int h, int nc, int ldk) {
+                        int dof, int bx, int bt, int h, int nc, int ldk, int nrhs) {
   const int cap = (int)(64 / (NCH * sizeof(cpx<R>) / sizeof(float)));
   const int q = std::min((nc + 3) / 4, std::max(cap, 1));
+  // four right-hand sides share the P rows while their windows take at most 32 registers
+  constexpr bool kShare = NCH * sizeof(cpx<R>) / sizeof(float) <= 8;
+  const bool share = kShare && nrhs >= 4;
+  if (share) grid.y = (nrhs + 3) / 4;
   auto go = [&](auto kw) {
     constexpr int KW = decltype(kw)::v;
-    hipLaunchKernelGGL((k_restrict<R, NCH, TX, KW, TP>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt,
-                       h, nc, ldk, ps);
+    if constexpr (kShare) {
+      if (share) {
+        hipLaunchKernelGGL((k_restrict<R, NCH, TX, KW, TP, 4>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx,
+                           bt, h, nc, ldk, ps, nrhs);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_restrict<R, NCH, TX, KW, TP, 1>), grid, dim3(kThreads), 0, st, P, x, y, lx, lt, dof, bx, bt,
+                       h, nc, ldk, ps, nrhs);
   };
   if (q <= 1)
     go(IntC<1>{});
@@ -226,10 +249,12 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__
     for (int kk = 0; kk < NCOL; ++kk) {
       float re = 0, im = 0;
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
+      for (int c = 0; c < NCH; ++c) {  // explicit FMAs: the same rounding for every NRB
         const z32 a = widen(pv[kk][c]);
-        re += a.re * xv[q][c].re + a.im * xv[q][c].im;
-        im += a.re * xv[q][c].im - a.im * xv[q][c].re;
+        re = fmaf(a.re, xv[q][c].re, re);
+        re = fmaf(a.im, xv[q][c].im, re);
+        im = fmaf(a.re, xv[q][c].im, im);
+        im = fmaf(-a.im, xv[q][c].re, im);
       }
       v[2 * kk] = re;
       v[2 * kk + 1] = im;
@@ -279,10 +304,12 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict_
     for (int k = 0; k < NCOL; ++k) {
       float re = 0, im = 0;
 #pragma unroll
-      for (int j = 0; j < CPW; ++j) {
+      for (int j = 0; j < CPW; ++j) {  // explicit FMAs: the same rounding for every NRB
         const z32 a = widen(pv[j][k]);
-        re += a.re * xv[q][j].re + a.im * xv[q][j].im;
-        im += a.re * xv[q][j].im - a.im * xv[q][j].re;
+        re = fmaf(a.re, xv[q][j].re, re);
+        re = fmaf(a.im, xv[q][j].im, re);
+        im = fmaf(a.re, xv[q][j].im, im);
+        im = fmaf(-a.im, xv[q][j].re, im);
       }
       v[2 * k] = re;
       v[2 * k + 1] = im;
@@ -329,7 +356,7 @@ __global__ void __launch_bounds__(kThreads) k_prolong_win(const TP* __restrict__
       for (int j = 0; j < 4; ++j) ev[j] = eK[min(k0 + j, nc - 1)];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (k0 + j < nc) fma_acc(acc[q], pv[j], ev[j]);
+        if (k0 + j < nc) fma_acc_x(acc[q], pv[j], ev[j]);
     }
   }
 #pragma unroll
@@ -935,7 +962,7 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
   }
   dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
-    launch_restrict_kw<R, decltype(c)::v, TX, TP>(grid, st, P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk);
+    launch_restrict_kw<R, decltype(c)::v, TX, TP>(grid, st, P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs);
   });
   HIPCHECK(hipGetLastError());
 }

@@ -408,6 +408,27 @@ def test_batch_invariance_and_edge_cases(cuda):
     s.close()
 
 
+def test_batch_invariance_many_columns(cuda):
+    """Nine columns take the kernels that share operator loads across right-hand sides
+    (coarse links for 8, P rows for 4 and 8 columns); each column still equals its
+    single-column solve bit for bit, in FP64 and in mixed precision."""
+    smg = smg_mod()
+    lx = lt = 32
+    U = field(lx, lt, seed=4, sweeps=50)
+    p = smg.make_params(lx, lt, 0.05, levels=3, blocks=[(4, 4), (2, 2)], nv=[6, 4], seed=11)
+    s = smg.Solver(dev(U), p)
+    n = 2 * lx * lt
+    B = synth.gaussian((9, n), 29)
+    for prec in (smg.FP64, smg.MIXED):
+        xb, _, code = s.solve(dev(B), tol=1e-10, precision=prec)
+        assert code == 0
+        xb = host(xb).reshape(9, -1)
+        for j in (0, 5, 8):
+            xa, _, _ = s.solve(dev(B[j]), tol=1e-10, precision=prec)
+            assert np.array_equal(host(xa), xb[j]), (prec, j)
+    s.close()
+
+
 def test_fp32_operators(pair):
     """The FP32 copies of every level's operator (used inside the mixed-precision
     solves) against the FP64 oracle.  Inputs and links are rounded to FP32 (unit
