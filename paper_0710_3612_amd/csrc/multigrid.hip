@@ -533,6 +533,93 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const TL* __restrict__ L, c
   }
 }
 
+// k_coarse for one right-hand side (4 <= nc <= 16, one pass of Q = ceil(nc / 4) columns
+// per wave) with the vector entries staged in LDS.  The workgroup's 64 outputs belong
+// to at most 64 / nc + 2 sites; the nc entries of their nine neighbours are loaded
+// once per workgroup, while the lanes' link loads are in flight, instead of once per
+// lane (the lanes of one site then read the same LDS word).  The products, their
+// order and the reduction over the waves are those of k_coarse.
+constexpr int kCoarseSvMax = 9 * (64 + 2 * 16);  // 9 (64 / nc + 2) nc entries at most (4 <= nc <= 16)
+
+template <typename R, int MODE, int Q, typename TL>
+__global__ void __launch_bounds__(kThreads) k_coarse_sv(const TL* __restrict__ L, const cpx<R>* __restrict__ v,
+                                                        cpx<R>* __restrict__ y, int cx, int ct, int nc, R c, R c2,
+                                                        cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux,
+                                                        R lscale) {
+  __shared__ cpx<R> part[3][64];
+  __shared__ cpx<R> sv[kCoarseSvMax];
+  const int nK = cx * ct;
+  const size_t n = (size_t)nK * nc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = blockIdx.x * 64 + lane;  // output index (K, row)
+  const bool live = tid < (int)n;
+  const int tidc = live ? tid : (int)n - 1;
+  const int c0 = w * Q, c1 = min(nc, c0 + Q);
+  // 1. the neighbours' vector entries, [site][direction][column]: thread t < 9 * sites
+  // loads the nc entries of pair t = (site, direction), requested before the link loads
+  // (a wait for them then does not wait for the links issued after them)
+  const int K_lo = (blockIdx.x * 64) / nc;
+  const int K_hi = min((blockIdx.x * 64 + 63) / nc, nK - 1);
+  const int npair = (K_hi - K_lo + 1) * 9;
+  const bool stager = (int)threadIdx.x < npair;
+  const int pr = stager ? (int)threadIdx.x : 0;
+  const int kl = pr / 9, D0 = pr - kl * 9;
+  const int Ks = K_lo + kl;
+  const int Kst = Ks / cx, Ksx = Ks - Kst * cx;
+  int st_t = Kst + D0 / 3 - 1, st_x = Ksx + D0 % 3 - 1;
+  st_t = st_t < 0 ? ct - 1 : (st_t >= ct ? 0 : st_t);
+  st_x = st_x < 0 ? cx - 1 : (st_x >= cx ? 0 : st_x);
+  const cpx<R>* src = v + (size_t)blockIdx.y * n + (size_t)(st_t * cx + st_x) * nc;
+  cpx<R> vs[16];
+#pragma unroll
+  for (int col = 0; col < 16; ++col) vs[col] = src[min(col, nc - 1)];  // pair 0 for non-stagers
+  __builtin_amdgcn_sched_barrier(0);  // keeps these loads ahead of the link loads
+  // 2. every link load of the lane (column clamped, excess products masked below)
+  TL l[9][Q];
+#pragma unroll
+  for (int D = 0; D < 9; ++D)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) l[D][j] = L[((size_t)D * nc + min(c0 + j, nc - 1)) * n + tidc];
+  __builtin_amdgcn_sched_barrier(0);  // all loads issued before the staging stores
+  if (stager) {
+#pragma unroll
+    for (int col = 0; col < 16; ++col)
+      if (col < nc) sv[pr * nc + col] = vs[col];
+  }
+  __syncthreads();
+  cpx<R> acc = mk<R>(0, 0);
+  if (live) {
+    const int ko = tid / nc - K_lo;  // this output's site within the staged ones
+#pragma unroll
+    for (int D = 0; D < 9; ++D) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        cpx<R> x = sv[(ko * 9 + D) * nc + min(c0 + j, nc - 1)];
+        if (c0 + j >= c1) x = mk<R>(0, 0);
+        fma_acc(acc, widen(l[D][j]), x);
+      }
+    }
+  }
+  if (w > 0) part[w - 1][lane] = acc;
+  __syncthreads();
+  if (w != 0 || !live) return;
+  const cpx<R> sum = lscale * (acc + part[0][lane] + part[1][lane] + part[2][lane]);
+  const size_t o = (size_t)blockIdx.y * n + tid;
+  if (MODE == 0) {
+    y[o] = sum;
+  } else if (MODE == 1 || MODE == 3) {
+    const cpx<R> vi = v[o];
+    xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
+    y[o] = vi - c * sum;
+  } else if (MODE == 4 || MODE == 5) {
+    const cpx<R> vi = v[o];
+    const cpx<R> a = MODE == 5 ? c * vi : xacc[o] + c * vi;
+    xacc[o] = a + c2 * (vi - c * sum);
+  } else {
+    y[o] = aux[o] - sum;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Block Gram-Schmidt (FP64): append candidate v as vector k of every aggregate.
 // One workgroup per aggregate; two passes of modified Gram-Schmidt against the
@@ -1297,6 +1384,28 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
 template <typename R, typename TL>
 void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                      double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+  if (nrhs == 1 && nc >= 4 && nc <= 16) {  // one right-hand side: vector entries staged in LDS
+    const size_t total = (size_t)cx * ct * nc;
+    const dim3 grid((unsigned)((total + 63) / 64), 1);
+    const int q = (nc + 3) / 4;
+    with_mode(mode, [&](auto m) {
+      constexpr int M = decltype(m)::v;
+      if (q == 1)
+        hipLaunchKernelGGL((k_coarse_sv<R, M, 1, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                           xacc, aux, lscale);
+      else if (q == 2)
+        hipLaunchKernelGGL((k_coarse_sv<R, M, 2, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                           xacc, aux, lscale);
+      else if (q == 3)
+        hipLaunchKernelGGL((k_coarse_sv<R, M, 3, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                           xacc, aux, lscale);
+      else
+        hipLaunchKernelGGL((k_coarse_sv<R, M, 4, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                           xacc, aux, lscale);
+    });
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   if (nrhs == 1)
     launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else if (nrhs <= 2)
