@@ -363,15 +363,16 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip
 
 
 def kernel_source_digest():
-    """sha256 of the roofline kernel's own source: the k_coarse kernel and its two
-    launch functions (edits elsewhere in the file leave its counters valid)."""
+    """sha256 of the roofline kernel's own source: the single-RHS coarse kernel
+    (k_coarse_sv) and the launch functions that reach it (edits elsewhere in the file
+    leave its counters valid)."""
     import hashlib
 
     text = open(KERNEL_SOURCE).read()
     parts = []
-    for start in ("template <typename R, int MODE, int NR, int Q, typename TL = cpx<R>>\n"
-                  "__global__ void __launch_bounds__(kThreads) k_coarse(",
-                  "void launch_coarse_q(", "void launch_coarse_nr(", "void launch_coarse_t(", "void launch_coarse_h16("):
+    for start in ("template <typename R, int MODE, int Q, typename TL>\n"
+                  "__global__ void __launch_bounds__(kThreads) k_coarse_sv(",
+                  "void launch_coarse_t(", "void launch_coarse_h16("):
         i = text.index(start)
         parts.append(text[i:text.index("\n}\n", i) + 3])
     return hashlib.sha256("".join(parts).encode()).hexdigest()
@@ -412,8 +413,11 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     nbytes = 9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8
     gbs = nbytes / dur / 1e9
     q = (nc + 3) // 4
-    cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
-    name = f"k_coarse<float,0,1,{cols}{',hfc' if h16 else ''}>"
+    if 4 <= nc <= 16:  # one right-hand side: the LDS-staged kernel, one pass of q columns per wave
+        name = f"k_coarse_sv<float,0,{q},{'hfc' if h16 else 'cpx<float>'}>"
+    else:
+        cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
+        name = f"k_coarse<float,0,1,{cols}{',hfc' if h16 else ''}>"
     what = "FP16 links (scaled), FP32 arithmetic" if h16 else "FP32"
     # context: a plain device copy moving the same bytes (half read, half written), timed the same way
     src = torch.ones(nbytes // 8, dtype=torch.float32, device=dev)
