@@ -1384,27 +1384,31 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
 template <typename R, typename TL>
 void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                      double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
-  if (nrhs == 1 && nc >= 4 && nc <= 16) {  // one right-hand side: vector entries staged in LDS
-    const size_t total = (size_t)cx * ct * nc;
-    const dim3 grid((unsigned)((total + 63) / 64), 1);
-    const int q = (nc + 3) / 4;
-    with_mode(mode, [&](auto m) {
-      constexpr int M = decltype(m)::v;
-      if (q == 1)
-        hipLaunchKernelGGL((k_coarse_sv<R, M, 1, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                           xacc, aux, lscale);
-      else if (q == 2)
-        hipLaunchKernelGGL((k_coarse_sv<R, M, 2, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                           xacc, aux, lscale);
-      else if (q == 3)
-        hipLaunchKernelGGL((k_coarse_sv<R, M, 3, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                           xacc, aux, lscale);
-      else
-        hipLaunchKernelGGL((k_coarse_sv<R, M, 4, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                           xacc, aux, lscale);
-    });
-    HIPCHECK(hipGetLastError());
-    return;
+  // one FP32 right-hand side: vector entries staged in LDS (in FP64 the 27 link loads and
+  // the staged entries need twice the registers, and the plain kernel is faster)
+  if constexpr (std::is_same<R, float>::value) {
+    if (nrhs == 1 && nc >= 4 && nc <= 16) {
+      const size_t total = (size_t)cx * ct * nc;
+      const dim3 grid((unsigned)((total + 63) / 64), 1);
+      const int q = (nc + 3) / 4;
+      with_mode(mode, [&](auto m) {
+        constexpr int M = decltype(m)::v;
+        if (q == 1)
+          hipLaunchKernelGGL((k_coarse_sv<R, M, 1, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                             xacc, aux, lscale);
+        else if (q == 2)
+          hipLaunchKernelGGL((k_coarse_sv<R, M, 2, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                             xacc, aux, lscale);
+        else if (q == 3)
+          hipLaunchKernelGGL((k_coarse_sv<R, M, 3, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                             xacc, aux, lscale);
+        else
+          hipLaunchKernelGGL((k_coarse_sv<R, M, 4, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
+                             xacc, aux, lscale);
+      });
+      HIPCHECK(hipGetLastError());
+      return;
+    }
   }
   if (nrhs == 1)
     launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
