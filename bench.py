@@ -97,7 +97,11 @@ def make_field(seed):
 
 def cpu_baseline_leg():
     """Oracle MG-CG on field 2000: adaptive setup at the lightest mass (not in the
-    rate), then solves at the lightest and the heaviest mass (timed)."""
+    rate), then solves at the lightest and the heaviest mass (timed).  Waits for a
+    line on stdin first, so that it does not share the host with the GPU legs whose
+    rates are the headline; returns None at end of input without one."""
+    if sys.stdin.readline().strip() != "go":
+        return None
     import numpy as np
 
     import synth
@@ -127,9 +131,11 @@ def cpu_baseline_leg():
 
 
 def start_cpu_baseline():
+    # started before anything touches the GPU (a GPU process does not start programs);
+    # it waits for "go" on stdin
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-leg"], env=env,
-                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+                            stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
 
 
 def cpu_model():
@@ -656,6 +662,9 @@ def main():
         dt = time.perf_counter() - t0
         results[name] = dict(seconds=dt, solves=len(systems) * args.steps, records=rec)
         log(f"{name}: {len(systems) * args.steps / dt:.1f} solves/s")
+    if cpu_proc is not None:  # the headline rates are taken: the oracle may use its core now
+        cpu_proc.stdin.write("go\n")
+        cpu_proc.stdin.flush()
 
     # ---- chirality-split aggregates on the same systems: Nv = 6 candidates per level, each
     # block split by chirality, so the coarse levels carry 12 variables per site as above
@@ -753,7 +762,7 @@ def main():
 
     cpu = None
     if cpu_proc is not None:
-        out, err = cpu_proc.communicate(timeout=1800)
+        out, err = cpu_proc.communicate(timeout=1800)  # also closes its stdin
         if cpu_proc.returncode == 0:
             leg = json.loads(out.strip().splitlines()[-1])
             per_solve = sum(leg["solve_s"]) / len(leg["solve_s"])
