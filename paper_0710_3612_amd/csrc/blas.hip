@@ -148,6 +148,23 @@ __global__ void __launch_bounds__(kThreads) k_axpy_update_fold(cpx<R>* __restric
                                                                size_t n, int nb, double* __restrict__ partial) {
   __shared__ double s_alpha;
   const int j = blockIdx.y;
+  const size_t off = (size_t)j * n;
+  // the thread's (at most E) elements are requested before alpha is formed: the loads
+  // do not depend on it (grid-stride order, index clamped, the excess not stored)
+  constexpr int E = 4;
+  const bool pre = n <= (size_t)E * nb * kThreads;
+  const size_t i0 = (size_t)blockIdx.x * kThreads + threadIdx.x, st = (size_t)nb * kThreads;
+  cpx<R> xs[E], rs[E], ps[E], qs[E];
+  if (pre) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t k = off + min(i0 + e * st, n - 1);
+      xs[e] = x[k];
+      rs[e] = r[k];
+      ps[e] = p[k];
+      qs[e] = q[k];
+    }
+  }
   double re = 0, im = 0;
   for (int i = threadIdx.x; i < pnb; i += kThreads) {
     re += ppart[2 * ((size_t)j * pnb + i)];
@@ -179,15 +196,27 @@ __global__ void __launch_bounds__(kThreads) k_axpy_update_fold(cpx<R>* __restric
     s_alpha = al;
   }
   __syncthreads();
-  const size_t off = (size_t)j * n;
   const R a = (R)s_alpha;
   double rr = 0, dummy = 0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)nb * kThreads) {
-    const size_t k = off + i;
-    x[k] = x[k] + a * p[k];
-    const cpx<R> rn = r[k] - a * q[k];
-    r[k] = rn;
-    rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+  if (pre) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t i = i0 + e * st;
+      if (i < n) {
+        x[off + i] = xs[e] + a * ps[e];
+        const cpx<R> rn = rs[e] - a * qs[e];
+        r[off + i] = rn;
+        rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+      }
+    }
+  } else {
+    for (size_t i = i0; i < n; i += st) {
+      const size_t k = off + i;
+      x[k] = x[k] + a * p[k];
+      const cpx<R> rn = r[k] - a * q[k];
+      r[k] = rn;
+      rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+    }
   }
   block_sum2(rr, dummy);
   if (threadIdx.x == 0) {
