@@ -283,7 +283,8 @@ void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red 
 // <r, z>_new per column, then beta = <r,z>_new / <r,z>_old and <r,z>_old <- <r,z>_new (active columns).
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
-                     const int* active, hipStream_t st);  // out[2*rhs] = <a,b> (complex)
+                     const int* active, hipStream_t st);
+// x += alpha p, r -= alpha q and |r|^2 per column into rr (and rr_host when given).
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
                         int nrhs, Red red, double* rr, hipStream_t st,
@@ -294,7 +295,7 @@ void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, 
 // added up by the host after a synchronisation: no second pass)
 void launch_axpy_update_fold(z32* x, z32* r, const z32* p, const z32* q, const double* ppart, int pnb,
                              const double* rz, double* alpha, const int* active, int* bad, int* bad_host, size_t n,
-                             int nrhs, double* rr_part_host, hipStream_t st);  // x+=a p, r-=a q, rr=|r|^2 (also to rr_host if given)
+                             int nrhs, double* rr_part_host, hipStream_t st);
 template <typename R>
 void launch_xpay(const cpx<R>* z, cpx<R>* p, const double* beta, size_t n, int nrhs, hipStream_t st);
 template <typename R>
