@@ -118,6 +118,12 @@ typedef struct {
                                      chi, and P maps chirality to chirality on every level.
                                      Needs nv[l] <= bx * bt * dof / 2 and 2 nv[l] <= 64.
                                      0 (default): one aggregate per block, nv[l] variables. */
+  int32_t coarsest_fp64;          /* mixed precision, dense coarsest solve: 1 (default) = the FP32
+                                     V-cycle applies the FP64 inverse with FP64 sums (its FP32
+                                     input widened exactly, the result rounded to FP32), so the
+                                     coarsest direct solve stays FP64; 0 = it applies an FP32
+                                     copy of the inverse, or an FP16 copy under operator_storage
+                                     SMG_STORE_F16 (a quarter of the bytes per V-cycle) */
 } smg_params;
 
 typedef struct {
@@ -134,7 +140,7 @@ typedef struct {
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
  * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16,
- * operator_storage = SMG_STORE_F32, split_chirality = 0. */
+ * operator_storage = SMG_STORE_F32, split_chirality = 0, coarsest_fp64 = 1. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
@@ -223,9 +229,13 @@ int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* str
 int smg_vcycle_f32(smg_handle h, const float* b, float* x, int32_t nrhs, void* stream);
 
 /* Solve A x = rhs for nrhs independent right-hand sides with MG-CG (Results
- * section).  precision SMG_FP64: FP64 throughout.  SMG_MIXED: FP32 operators,
- * smoother and coarse levels inside FP64 defect correction (the true residual and
- * the solution update are FP64; Gram-Schmidt and the coarsest solve stay FP64).
+ * section).  precision SMG_FP64: FP64 throughout.  SMG_MIXED: an FP32 MG-CG
+ * (FP32 operators, smoother and coarse levels, with the storage that
+ * smoother_storage and operator_storage select) inside FP64 defect correction:
+ * the true residual and the solution update are FP64, and so are Gram-Schmidt
+ * and the factorisation of the coarsest operator (setup); the FP32 V-cycle
+ * applies the coarsest inverse in FP64 when coarsest_fp64 = 1, else from an FP32
+ * or FP16 copy, or runs the coarsest CG in FP32 (SMG_COARSEST_CG).
  * rhs, x: device complex128 [nrhs][lt][lx][2]; x is overwritten (start from 0).
  * stats: host array of nrhs entries or NULL.
  * Returns SMG_OK when every column reached tol, SMG_NOTCONV when some did not,
@@ -318,6 +328,39 @@ void smg_batch_destroy(smg_batch b);
 
 /* Device bytes held by the handle. */
 int smg_memory_bytes(smg_handle h, size_t* bytes);
+
+/* Device memory of the library.  A setup stays resident and is reused for many
+ * right-hand sides and masses (Results section), so a caller that keeps many of
+ * them accounts for their memory itself: every device array that a handle or a
+ * batch owns comes from alloc(bytes, stream, ctx) and goes back through
+ * release(ptr, bytes, stream, ctx), with `stream` the hipStream_t of the call that
+ * allocated it.  alloc returns device memory of the current device aligned to at
+ * least 256 bytes, or NULL (the call then fails with SMG_ENOMEM).  A handle or
+ * batch keeps the allocator that was installed when it was created.  Before it
+ * hands memory to release the library synchronises the device, so no kernel still
+ * uses it.  Both NULL (the default) restore hipMalloc / hipFree.  Pinned host
+ * memory (the convergence mirrors) and rocBLAS's own workspace (blocked
+ * inversion of coarsest operators above 512 variables) are not routed.
+ * Errors: SMG_EINVAL when only one of alloc and release is given. */
+typedef void* (*smg_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*smg_release_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
+int smg_set_allocator(smg_alloc_fn alloc, smg_release_fn release, void* ctx);
+
+/* Device bytes the library will hold for a hierarchy with these parameters,
+ * computed on the host from the allocation plan that the calls themselves follow
+ * (no device call):
+ *   setup_bytes  smg_memory_bytes of a handle right after smg_setup,
+ *                smg_setup_from_vectors or smg_derive;
+ *   solve_bytes  what such a handle adds the first time it runs smg_solve with
+ *                nrhs columns in `precision` (later solves of at most nrhs columns
+ *                in that precision add nothing; smg_cg adds at most the SMG_FP64
+ *                figure);
+ *   batch_bytes  what smg_batch_create(h, max_rhs = nrhs, precision) adds on such
+ *                a handle: the batch's own memory plus the handle's growth.
+ * Any output may be NULL.  Errors: the parameter checks of smg_setup; SMG_EINVAL
+ * for nrhs outside [1, 4096], or above 256 when batch_bytes is asked for. */
+int smg_query_bytes(const smg_params* params, int32_t nrhs, int32_t precision, size_t* setup_bytes,
+                    size_t* solve_bytes, size_t* batch_bytes);
 
 void smg_destroy(smg_handle h);
 const char* smg_strerror(int code);

@@ -32,6 +32,8 @@ __all__ = [
     "STORE_BF16",
     "STORE_F16",
     "library_path",
+    "query_bytes",
+    "use_torch_allocator",
 ]
 
 MAXLEV = 6
@@ -80,6 +82,7 @@ class Params(ctypes.Structure):
         ("mfma_min_rhs", ctypes.c_int32),
         ("operator_storage", ctypes.c_int32),
         ("split_chirality", ctypes.c_int32),
+        ("coarsest_fp64", ctypes.c_int32),
     ]
 
 
@@ -107,6 +110,11 @@ class SmgError(RuntimeError):
 
 
 _lib = None
+
+# smg_alloc_fn / smg_release_fn
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None  # the installed callbacks (kept alive while the library may call them)
 
 
 def load_library():
@@ -148,6 +156,9 @@ def load_library():
         "smg_get_coarse_links": (i32, [h, i32, P, P]),
         "smg_get_smoother_coefs": (i32, [h, i32, ctypes.POINTER(ctypes.c_double)]),
         "smg_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_query_bytes": (i32, [ctypes.POINTER(Params), i32, i32, ctypes.POINTER(ctypes.c_size_t),
+                                  ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "smg_set_allocator": (i32, [_ALLOC_FN, _RELEASE_FN, P]),
         "smg_batch_create": (i32, [h, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(h)]),
         "smg_batch_admit": (i32, [h, P, ctypes.POINTER(i32), P]),
         "smg_batch_step": (i32, [h, i32, P]),
@@ -167,7 +178,54 @@ def load_library():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    use_torch_allocator(True)
     return lib
+
+
+def _torch_alloc(nbytes, stream, _ctx):
+    import torch
+
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # the library reports SMG_ENOMEM
+        return None
+
+
+def _torch_release(ptr, _nbytes, _stream, _ctx):
+    import sys
+
+    if sys.is_finalizing():  # torch may already be gone; the process is ending
+        return
+    import torch
+
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device memory through PyTorch's caching allocator
+    (smg_set_allocator), so that torch accounts for it and can reuse it; with
+    enable=False the library returns to hipMalloc for handles created later.
+    Installed when the library is loaded."""
+    global _allocator
+    lib = _lib
+    if enable:
+        cbs = (_ALLOC_FN(_torch_alloc), _RELEASE_FN(_torch_release))
+        _check(lib.smg_set_allocator(cbs[0], cbs[1], None))
+        # handles created before keep the callbacks they captured: keep every pair alive
+        _allocator = (cbs, _allocator)
+    else:
+        _check(lib.smg_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None))
+
+
+def query_bytes(params: "Params", nrhs: int = 1, precision: int = FP64):
+    """(setup, solve, batch) device bytes that smg_query_bytes plans for these
+    parameters: a handle after setup, what its first solve of nrhs columns adds,
+    and what a batch of nrhs slots adds (None when nrhs > 256)."""
+    lib = load_library()
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    pc = ctypes.byref(c) if nrhs <= 256 else None
+    _check(lib.smg_query_bytes(ctypes.byref(params), int(nrhs), int(precision), ctypes.byref(a), ctypes.byref(b), pc))
+    return a.value, b.value, (c.value if nrhs <= 256 else None)
 
 
 def _check(code: int, allow_notconv: bool = False) -> int:
@@ -183,7 +241,8 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 coarsest_tol: float = 1e-12, coarsest_maxiter: int = 10000, inner_tol: float = 1e-5,
                 seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16,
                 smoother_storage: int = STORE_F32, stop_recursive: bool = False,
-                operator_storage: int = STORE_F32, split_chirality: bool = False) -> Params:
+                operator_storage: int = STORE_F32, split_chirality: bool = False,
+                coarsest_fp64: bool = True) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -206,6 +265,7 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.stop_recursive = int(bool(stop_recursive))
     p.operator_storage = operator_storage
     p.split_chirality = int(bool(split_chirality))
+    p.coarsest_fp64 = int(bool(coarsest_fp64))
     return p
 
 

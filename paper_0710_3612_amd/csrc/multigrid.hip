@@ -1671,7 +1671,7 @@ void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y
                          mscale);
   } else if (n <= kDenseRowsMax) {
     hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale);
-  } else if constexpr (std::is_same<R, float>::value) {
+  } else if constexpr (std::is_same<R, float>::value && !std::is_same<TM, z64>::value) {
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
     hipLaunchKernelGGL((k_dense_mfma<TM>), grid, dim3(256), 0, st, M, x, y, n, nrhs, (float)mscale);
   } else {
@@ -1770,5 +1770,6 @@ INST(float)
 #undef INST
 template void launch_dense_apply<double, double>(const z64*, const z64*, z64*, int, int, hipStream_t);
 template void launch_dense_apply<float, float>(const z32*, const z32*, z32*, int, int, hipStream_t);
+template void launch_dense_apply<double, float>(const z64*, const z32*, z32*, int, int, hipStream_t);
 
 }  // namespace smg

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <limits>
+#include <memory>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -41,26 +43,70 @@ namespace {
 thread_local std::string g_last_error;
 
 // ---------------------------------------------------------------------------
-// Device memory owned by a context; everything is released with the context.
+// Device memory.  Every array a handle or a batch owns comes from the allocator
+// installed by smg_set_allocator (hipMalloc when none is), is counted, and is
+// released when its owner is destroyed.  A dry pool only counts: smg_query_bytes
+// runs the same allocation plan through it without touching the device.
 // ---------------------------------------------------------------------------
+struct Allocator {
+  smg_alloc_fn alloc = nullptr;
+  smg_release_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
 struct Pool {
+  Allocator a = current_allocator();  // the allocator in force when the owner was created
+  bool dry = false;
+  const hipStream_t* stream = nullptr;  // the owner's current stream, handed to the allocator
   std::vector<void*> ptrs;
+  std::vector<size_t> sizes;
+  std::vector<hipStream_t> streams;
   size_t bytes = 0;
+  uintptr_t fake = 4096;  // distinct, never dereferenced addresses of a dry pool
   template <typename T>
   T* alloc(size_t count) {
     if (count == 0) count = 1;
+    const size_t nb = count * sizeof(T);
+    bytes += nb;
+    if (dry) {
+      fake += (nb + 255) & ~(size_t)255;
+      return reinterpret_cast<T*>(fake);
+    }
+    hipStream_t st = stream ? *stream : nullptr;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
+    if (a.alloc) {
+      p = a.alloc(nb, (void*)st, a.ctx);
+      if (!p) {
+        bytes -= nb;
+        throw Error(SMG_ENOMEM, "the installed allocator returned no memory for " + std::to_string(nb) + " bytes");
+      }
+    } else if (hipMalloc(&p, nb) != hipSuccess) {
       (void)hipGetLastError();
-      throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      bytes -= nb;
+      throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed");
     }
     ptrs.push_back(p);
-    bytes += count * sizeof(T);
+    sizes.push_back(nb);
+    streams.push_back(st);
     return static_cast<T*>(p);
   }
   ~Pool() {
-    for (void* p : ptrs) (void)hipFree(p);
+    if (dry || ptrs.empty()) return;
+    if (a.release) {
+      // the callback may hand the memory to other users at once: nothing may still read it
+      (void)hipDeviceSynchronize();
+      for (size_t i = 0; i < ptrs.size(); ++i) a.release(ptrs[i], sizes[i], (void*)streams[i], a.ctx);
+    } else {
+      for (void* p : ptrs) (void)hipFree(p);
+    }
   }
 };
 
@@ -212,6 +258,7 @@ void ensure_scalars(Ctx& c, int nrhs) {
     s.on_host = nullptr;
     s.rr_part_host = nullptr;
     s.rr_part_nb = nb;
+    if (c.pool.dry) continue;
     HIPCHECK(hipHostMalloc((void**)&s.rr_host, sizeof(double) * 2 * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.bad_host, sizeof(int) * cap, hipHostMallocCoherent));
     HIPCHECK(hipHostMalloc((void**)&s.on_host, sizeof(int) * cap, hipHostMallocCoherent));
@@ -220,18 +267,23 @@ void ensure_scalars(Ctx& c, int nrhs) {
   }
   c.dc_down = c.pool.alloc<double>(cap);
   c.dc_up = c.pool.alloc<double>(cap);
+  c.scal_cap = cap;
+  if (c.pool.dry) return;
   if (c.h_scal) (void)hipHostFree(c.h_scal);
   if (c.h_int) (void)hipHostFree(c.h_int);
   c.h_scal = nullptr;
   c.h_int = nullptr;
   HIPCHECK(hipHostMalloc((void**)&c.h_scal, sizeof(double) * 4 * cap, hipHostMallocDefault));
   HIPCHECK(hipHostMalloc((void**)&c.h_int, sizeof(int) * 2 * cap, hipHostMallocDefault));
-  c.scal_cap = cap;
 }
 
 template <typename R>
 void ensure_level_work(Ctx& c, int nrhs) {
-  for (auto& lv : levels_of<R>(c)) {
+  auto& Ls = levels_of<R>(c);
+  if ((int)Ls.size() != c.nlev) throw Error(SMG_EINVAL, "level work requested before the levels exist");
+  for (auto& lv : Ls) {
+    if (&lv != &Ls.back() && !(lv.bx > 0 && lv.nkw() > 0))  // every level but the coarsest transfers
+      throw Error(SMG_EINVAL, "level work requested before the transfer geometry is set");
     if (lv.cap >= nrhs) continue;
     lv.cap = nrhs;
     lv.b = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
@@ -248,15 +300,40 @@ void ensure_level_work(Ctx& c, int nrhs) {
 }
 
 template <typename R>
-void ensure_kvecs(Ctx& c, KVecs<R>& v, size_t elems) {
+void alloc_kvecs(Pool& pool, KVecs<R>& v, size_t elems) {
   if (v.cap >= elems) return;
-  v.r = c.pool.alloc<cpx<R>>(elems);
-  v.p = c.pool.alloc<cpx<R>>(elems);
-  v.q = c.pool.alloc<cpx<R>>(elems);
-  v.z = c.pool.alloc<cpx<R>>(elems);
-  v.t = c.pool.alloc<cpx<R>>(elems);
-  v.p2 = c.pool.alloc<cpx<R>>(elems);
+  v.r = pool.alloc<cpx<R>>(elems);
+  v.p = pool.alloc<cpx<R>>(elems);
+  v.q = pool.alloc<cpx<R>>(elems);
+  v.z = pool.alloc<cpx<R>>(elems);
+  v.t = pool.alloc<cpx<R>>(elems);
+  v.p2 = pool.alloc<cpx<R>>(elems);
   v.cap = elems;
+}
+
+template <typename R>
+void ensure_kvecs(Ctx& c, KVecs<R>& v, size_t elems) {
+  alloc_kvecs<R>(c.pool, v, elems);
+}
+
+// Per-workgroup partial sums of the fused FP32 CG step and of the V-cycle's last
+// fine apply (nrhs columns).
+void ensure_cg_partial(Ctx& c, int nrhs) {
+  const int nb = cg_step_blocks<float>(c.L64[0].lx, c.L64[0].lt);
+  const size_t need = (size_t)2 * nb * nrhs;
+  if (nb == 0 || c.cg_partial_cap >= need) return;
+  c.cg_partial = c.pool.alloc<double>(need);
+  c.rz_partial = c.pool.alloc<double>(need);
+  c.cg_partial_cap = need;
+}
+
+// FP64 residual and FP32 right-hand side and correction of defect correction.
+void ensure_dc(Ctx& c, size_t elems) {
+  if (c.dc_cap >= elems) return;
+  c.r64 = c.pool.alloc<z64>(elems);
+  c.b32 = c.pool.alloc<z32>(elems);
+  c.e32 = c.pool.alloc<z32>(elems);
+  c.dc_cap = elems;
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +424,9 @@ void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool us
   auto& lv = levels_of<R>(c)[l];
   if (!use_cg && c.Minv && l == c.nlev - 1) {
     if constexpr (std::is_same<R, float>::value) {
-      if (c.Minv16)
+      if (c.prm.coarsest_fp64)  // FP64 inverse and FP64 sums, the FP32 input widened exactly
+        launch_dense_apply<double, float>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
+      else if (c.Minv16)
         launch_dense_apply_h16(c.Minv16, c.mscale, b, x, (int)lv.n, nrhs, c.st);
       else
         launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st);
@@ -535,14 +614,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
   int fuse_nb = 0;
   if constexpr (std::is_same<R, float>::value)
     if (lv.fine) fuse_nb = cg_step_blocks<float>(lv.lx, lv.lt);
-  if (fuse_nb > 0) {
-    const size_t need = (size_t)2 * fuse_nb * nrhs;
-    if (c.cg_partial_cap < need) {
-      c.cg_partial = c.pool.alloc<double>(need);
-      c.rz_partial = c.pool.alloc<double>(need);
-      c.cg_partial_cap = need;
-    }
-  }
+  if (fuse_nb > 0) ensure_cg_partial(c, nrhs);
   cpx<R>* p_cur = v.p;
   cpx<R>* p_alt = v.p2;
   // Fused path: <r, z> lives in one of two slots.  When the V-cycle's last fine apply
@@ -883,11 +955,7 @@ void build_coarsest_inverse(Ctx& c) {
   if (c.nlev < 2 || c.prm.coarsest != SMG_COARSEST_DIRECT) return;
   auto& lv = c.L64[c.nlev - 1];
   const int n = (int)lv.n;
-  if (!c.Minv) {
-    c.Minv = c.pool.alloc<z64>((size_t)n * n);
-    c.colk = c.pool.alloc<z64>(n);
-    c.piv = c.pool.alloc<double>(1);
-  }
+  if (!c.Minv) throw Error(SMG_EINVAL, "coarsest inverse not reserved");
   launch_coarse_to_dense(lv.L, c.Minv, lv.lx, lv.lt, lv.dof, c.st);
   zero(c.fail, sizeof(int), c.st);
   if (n <= kGJBlock)
@@ -951,6 +1019,7 @@ void validate(const smg_params& p) {
   if (p.operator_storage != SMG_STORE_F32 && p.operator_storage != SMG_STORE_F16)
     throw Error(SMG_EINVAL, "operator_storage must be SMG_STORE_F32 or SMG_STORE_F16");
   if (p.split_chirality != 0 && p.split_chirality != 1) throw Error(SMG_EINVAL, "split_chirality must be 0 or 1");
+  if (p.coarsest_fp64 != 0 && p.coarsest_fp64 != 1) throw Error(SMG_EINVAL, "coarsest_fp64 must be 0 or 1");
   const int m = p.split_chirality ? 2 : 1;
   if (p.smoother_storage != SMG_STORE_F32 && (p.levels < 2 || !normal_lp_fits(p.lx, p.lt)))
     throw Error(SMG_EINVAL, "BF16/FP16 smoother storage needs levels >= 2, lx % 32 == 0 and lt % 16 == 0");
@@ -971,22 +1040,28 @@ void validate(const smg_params& p) {
 }
 
 // New context with every device array allocated.  The fermion links come from
-// `gauge` (ABI layout) or are copied from `src_links` (already prepared).
-Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z64* src_links = nullptr) {
-  if ((!gauge && !src_links) || !prm) throw Error(SMG_EINVAL, "null gauge or params");
+// `gauge` (ABI layout) or are copied from `src_links` (already prepared).  A dry
+// context only counts the bytes of the same allocations (neither is read).
+Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z64* src_links = nullptr,
+            bool dry = false) {
+  if ((!gauge && !src_links && !dry) || !prm) throw Error(SMG_EINVAL, "null gauge or params");
   validate(*prm);
   Ctx* c = new Ctx();
   try {
+    c->pool.dry = dry;
+    c->pool.stream = &c->st;
     c->prm = *prm;
     c->st = st;
     c->nlev = prm->levels;
     const int lx = prm->lx, lt = prm->lt;
     const size_t V = (size_t)lx * lt;
     c->U64 = c->pool.alloc<z64>(2 * V);
-    if (src_links)
+    if (dry) {
+    } else if (src_links) {
       HIPCHECK(hipMemcpyAsync(c->U64, src_links, 2 * V * sizeof(z64), hipMemcpyDeviceToDevice, st));
-    else
+    } else {
       launch_prepare_links<double>((const z64*)gauge, c->U64, lx, lt, prm->t_antiperiodic, st);
+    }
     c->L64.resize(c->nlev);
     c->L64[0].lx = lx;
     c->L64[0].lt = lt;
@@ -1033,12 +1108,12 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z6
   }
 }
 
-// FP32 copy of the hierarchy for the mixed-precision inner solves.
 // Power-of-two scale s with max|a| / s in [0.5, 1) (1 for an all-zero array): FP16
 // copies store a / s, so every stored entry is at most 1 in magnitude.
+constexpr int kAbsmaxBlocks = 256;
+
 double fp16_scale(Ctx& c, const z64* a, size_t n) {
-  constexpr int kBlocks = 256;
-  if (!c.absmax_part) c.absmax_part = c.pool.alloc<double>(kBlocks);
+  constexpr int kBlocks = kAbsmaxBlocks;
   launch_absmax_partial(a, n, c.absmax_part, kBlocks, c.st);
   double h[kBlocks];
   HIPCHECK(hipMemcpyAsync(h, c.absmax_part, sizeof h, hipMemcpyDeviceToHost, c.st));
@@ -1052,27 +1127,53 @@ double fp16_scale(Ctx& c, const z64* a, size_t n) {
   return std::ldexp(1.0, e);
 }
 
+// FP32 (and FP16) copies of the hierarchy for the mixed-precision solves: the
+// arrays (alloc_f32), then their contents from the FP64 operators (ensure_f32).
+void alloc_f32(Ctx& c) {
+  if (!c.L32.empty()) return;
+  const bool h16 = c.prm.operator_storage == SMG_STORE_F16;
+  c.L32.resize(c.nlev);
+  c.U32 = c.pool.alloc<z32>(c.L64[0].n);  // 2 links per site, as many as vector entries
+  for (int l = 0; l < c.nlev; ++l) {
+    auto& a = c.L64[l];
+    auto& b = c.L32[l];
+    // the shape, transfer geometry included: work buffers are sized from it
+    b.lx = a.lx; b.lt = a.lt; b.dof = a.dof; b.n = a.n; b.fine = a.fine;
+    b.bx = a.bx; b.bt = a.bt; b.nc = a.nc; b.ldk = a.ldk; b.halo = a.halo;
+    if (a.fine) b.U = c.U32;
+    if (a.L) {
+      const size_t nl = 9 * (size_t)a.lx * a.lt * a.dof * a.dof;
+      b.L = c.pool.alloc<z32>(nl);
+      if (h16) b.L16 = c.pool.alloc<hfc>(nl);
+    }
+    if (a.P) {
+      const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * a.halo) * (a.bt + 2 * a.halo) * a.dof;
+      b.P = c.pool.alloc<z32>(np);
+      if (h16) b.P16 = c.pool.alloc<hfc>(np);
+    }
+  }
+  if (c.Minv && !c.prm.coarsest_fp64) {
+    const size_t nn = c.L64[c.nlev - 1].n * c.L64[c.nlev - 1].n;
+    c.Minv32 = c.pool.alloc<z32>(nn);
+    if (h16) c.Minv16 = c.pool.alloc<hfc>(nn);
+  }
+  if (h16) c.absmax_part = c.pool.alloc<double>(kAbsmaxBlocks);
+}
+
 void ensure_f32(Ctx& c) {
   if (c.f32_ready) return;
+  alloc_f32(c);
   const bool h16 = c.prm.operator_storage == SMG_STORE_F16;
-  const bool fresh = c.L32.empty();
-  if (fresh) {
-    c.L32.resize(c.nlev);
-    c.U32 = c.pool.alloc<z32>(c.L64[0].n);  // 2 links per site, as many as vector entries
-  }
   launch_links_convert<float>(c.U64, c.U32, c.L64[0].n, c.st);  // 2V links == n entries
   for (int l = 0; l < c.nlev; ++l) {
     auto& a = c.L64[l];
     auto& b = c.L32[l];
     b.lx = a.lx; b.lt = a.lt; b.dof = a.dof; b.n = a.n; b.fine = a.fine; b.diag = a.diag;
     b.bx = a.bx; b.bt = a.bt; b.nc = a.nc; b.ldk = a.ldk; b.coefs = a.coefs; b.halo = a.halo; b.sa_w = a.sa_w;
-    if (a.fine) b.U = c.U32;
     if (a.L) {
       const size_t nl = 9 * (size_t)a.lx * a.lt * a.dof * a.dof;
-      if (fresh) b.L = c.pool.alloc<z32>(nl);
       launch_links_convert<float>(a.L, b.L, nl, c.st);
       if (h16) {
-        if (!b.L16) b.L16 = c.pool.alloc<hfc>(nl);
         const double sc = fp16_scale(c, a.L, nl);
         b.lscale = (float)sc;
         launch_convert_h16(a.L, b.L16, nl, 1.0 / sc, c.st);
@@ -1080,28 +1181,72 @@ void ensure_f32(Ctx& c) {
     }
     if (a.P) {
       const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * a.halo) * (a.bt + 2 * a.halo) * a.dof;
-      if (fresh) b.P = c.pool.alloc<z32>(np);
       launch_links_convert<float>(a.P, b.P, np, c.st);
       if (h16) {
-        if (!b.P16) b.P16 = c.pool.alloc<hfc>(np);
         const double sc = fp16_scale(c, a.P, np);
         b.pscale = (float)sc;
         launch_convert_h16(a.P, b.P16, np, 1.0 / sc, c.st);
       }
     }
   }
-  if (c.Minv) {
+  if (c.Minv32) {
     const size_t nn = c.L64[c.nlev - 1].n * c.L64[c.nlev - 1].n;
-    if (!c.Minv32) c.Minv32 = c.pool.alloc<z32>(nn);
     launch_links_convert<float>(c.Minv, c.Minv32, nn, c.st);
     if (h16) {
-      if (!c.Minv16) c.Minv16 = c.pool.alloc<hfc>(nn);
       c.mscale = fp16_scale(c, c.Minv, nn);
       launch_convert_h16(c.Minv, c.Minv16, nn, 1.0 / c.mscale, c.st);
     }
   }
   c.f32_ready = true;
   ++c.gen;
+}
+
+// Every allocation a setup makes beyond create(): the calibration start of every
+// coarsening and the dense coarsest inverse with its elimination scratch.
+void reserve_setup(Ctx& c) {
+  c.calib.assign(c.nlev, nullptr);
+  for (int l = 0; l + 1 < c.nlev; ++l) c.calib[l] = c.pool.alloc<z64>(c.L64[l].n);
+  if (c.nlev > 1 && c.prm.coarsest == SMG_COARSEST_DIRECT) {
+    const size_t n = c.L64[c.nlev - 1].n;
+    c.Minv = c.pool.alloc<z64>(n * n);
+    c.colk = c.pool.alloc<z64>(n);
+    c.piv = c.pool.alloc<double>(1);
+  }
+}
+
+// Every allocation of a solve of nrhs columns in `prec` (smg_solve, smg_cg).
+void reserve_solve(Ctx& c, int nrhs, int prec) {
+  const size_t n = c.L64[0].n;
+  const bool cg = c.nlev > 1 && c.prm.coarsest == SMG_COARSEST_CG;
+  ensure_scalars(c, nrhs);
+  ensure_level_work<double>(c, nrhs);
+  if (prec == SMG_FP64) {
+    ensure_kvecs<double>(c, c.f64, (size_t)nrhs * n);
+    if (cg) ensure_kvecs<double>(c, c.c64, (size_t)nrhs * c.L64[c.nlev - 1].n);
+  } else {
+    alloc_f32(c);
+    ensure_level_work<float>(c, nrhs);
+    ensure_kvecs<float>(c, c.f32, (size_t)nrhs * n);
+    ensure_dc(c, (size_t)nrhs * n);
+    ensure_cg_partial(c, nrhs);
+    if (cg) ensure_kvecs<float>(c, c.c32, (size_t)nrhs * c.L64[c.nlev - 1].n);
+  }
+}
+
+// The handle's own growth when a batch of cap slots in `prec` is created on it.
+void reserve_batch_handle(Ctx& c, int cap, int prec) {
+  if (prec == SMG_MIXED) {
+    alloc_f32(c);
+    ensure_level_work<float>(c, cap);
+  }
+  ensure_level_work<double>(c, cap);
+  if (c.nlev > 1 && c.prm.coarsest == SMG_COARSEST_CG) {  // the coarsest CG of the batch's V-cycles
+    ensure_scalars(c, cap);
+    if (prec == SMG_MIXED)
+      ensure_kvecs<float>(c, c.c32, (size_t)cap * c.L64[c.nlev - 1].n);
+    else
+      ensure_kvecs<double>(c, c.c64, (size_t)cap * c.L64[c.nlev - 1].n);
+  }
 }
 
 void finish_setup(Ctx& c) {
@@ -1184,6 +1329,7 @@ struct Batch {
   std::vector<int> used, act, its, stat, bad;
   std::vector<double> bb, rel;
   int64_t applies0 = 0;
+  hipStream_t st0 = nullptr;  // stream of smg_batch_create (handed to the allocator)
   // One captured graph of an iteration's device work per number of leading slots
   // (pointers and coefficients are fixed for a given count); dropped when the
   // handle's operators change.
@@ -1213,6 +1359,34 @@ struct Batch {
     return m;
   }
 };
+
+// Every device array of a batch of B.cap slots (B.n, B.prec set).
+void batch_alloc(Batch& B) {
+  const int cap = B.cap;
+  const size_t e = (size_t)cap * B.n;
+  B.b = B.pool.alloc<z64>(e);
+  B.x = B.pool.alloc<z64>(e);
+  B.r = B.pool.alloc<z64>(e);
+  B.p = B.pool.alloc<z64>(e);
+  B.q = B.pool.alloc<z64>(e);
+  B.z = B.pool.alloc<z64>(e);
+  B.t = B.pool.alloc<z64>(e);
+  if (B.prec == SMG_MIXED) {
+    B.zo = B.pool.alloc<z64>(e);
+    B.r32 = B.pool.alloc<z32>(e);
+    B.z32v = B.pool.alloc<z32>(e);
+    B.rzo = B.pool.alloc<double>(2 * cap);
+  }
+  B.red.partial = B.pool.alloc<double>((size_t)2 * red_blocks(B.n) * cap);
+  B.S.bb = B.pool.alloc<double>(2 * cap);
+  B.S.rz = B.pool.alloc<double>(2 * cap);
+  B.S.pq = B.pool.alloc<double>(2 * cap);
+  B.S.ab = B.pool.alloc<double>(2 * cap);
+  B.S.rr = B.pool.alloc<double>(2 * cap);
+  B.S.tt = B.pool.alloc<double>(2 * cap);
+  B.S.active = B.pool.alloc<int>(cap);
+  B.S.bad = B.pool.alloc<int>(cap);
+}
 
 void batch_upload_active(Batch& B, hipStream_t st) {
   for (int j = 0; j < B.cap; ++j) B.hi_[j] = B.act[j];
@@ -1417,6 +1591,7 @@ void smg_default_params(smg_params* p) {
   p->mfma_min_rhs = 16;
   p->operator_storage = SMG_STORE_F32;
   p->split_chirality = 0;
+  p->coarsest_fp64 = 1;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
@@ -1426,11 +1601,18 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
   hipStream_t st = (hipStream_t)stream;
   Ctx* c = create(gauge, params, st);
   try {
-    c->calib.resize(c->nlev);
+    reserve_setup(*c);
+    // The random starts and the Krylov vectors of the setup cycles' coarse CG live
+    // only while the setup runs (released after its final synchronisation).
+    Pool tmp;
+    tmp.stream = &c->st;
+    size_t cgmax = 0;
+    for (int l = 1; l < c->nlev; ++l) cgmax = std::max(cgmax, c->L64[l].n);
+    if (cgmax) alloc_kvecs<double>(tmp, c->c64, cgmax);
     for (int l = 0; l + 1 < c->nlev; ++l) {
       const size_t n = c->L64[l].n;
       const int nv = c->prm.nv[l];
-      z64* rnd = c->pool.alloc<z64>((1 + (size_t)nv) * n);
+      z64* rnd = tmp.alloc<z64>((1 + (size_t)nv) * n);
       if (randoms) {
         HIPCHECK(hipMemcpyAsync(rnd, (const z64*)randoms + level_offset_randoms(*c, l, true),
                                 (1 + (size_t)nv) * n * sizeof(z64), hipMemcpyDeviceToDevice, st));
@@ -1438,12 +1620,13 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
         for (int row = 0; row <= nv; ++row)
           launch_random_gaussian(rnd + (size_t)row * n, n, c->prm.seed, (uint64_t)l * 4096 + row, st);
       }
-      c->calib[l] = rnd;  // row 0
+      HIPCHECK(hipMemcpyAsync(c->calib[l], rnd, n * sizeof(z64), hipMemcpyDeviceToDevice, st));  // row 0
       calibrate(*c, l);
       sa_weight(*c, l);
       adaptive_level(*c, l, rnd);
     }
     finish_setup(*c);
+    c->c64 = KVecs<double>{};
   } catch (...) {
     delete c;
     throw;
@@ -1460,14 +1643,12 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
   hipStream_t st = (hipStream_t)stream;
   Ctx* c = create(gauge, params, st);
   try {
-    c->calib.resize(c->nlev);
+    reserve_setup(*c);
     for (int l = 0; l + 1 < c->nlev; ++l) {
       const size_t n = c->L64[l].n;
       const int nv = c->prm.nv[l];
-      z64* cb = c->pool.alloc<z64>(n);
-      HIPCHECK(hipMemcpyAsync(cb, (const z64*)calib + level_offset_plain(*c, l), n * sizeof(z64),
+      HIPCHECK(hipMemcpyAsync(c->calib[l], (const z64*)calib + level_offset_plain(*c, l), n * sizeof(z64),
                               hipMemcpyDeviceToDevice, st));
-      c->calib[l] = cb;
       calibrate(*c, l);
       sa_weight(*c, l);
       const z64* vl = (const z64*)vectors + level_offset_randoms(*c, l, false);
@@ -1507,12 +1688,14 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
   if (!out) throw Error(SMG_EINVAL, "null output handle");
   if (!std::isfinite(mass)) throw Error(SMG_EINVAL, "mass must be finite");
   hipStream_t st = (hipStream_t)stream;
-  HIPCHECK(hipStreamSynchronize(src->st));
+  // What is read from src (links, prolongators, calibration starts) is written only
+  // by the setup calls, which synchronise before they return, so src may be in use
+  // on another stream meanwhile; its stream field is not touched.
   smg_params prm = src->prm;
   prm.mass = mass;
   Ctx* c = create(nullptr, &prm, st, src->U64);
   try {
-    c->calib.resize(c->nlev);
+    reserve_setup(*c);
     for (int l = 0; l + 1 < c->nlev; ++l) {
       auto& a = src->L64[l];
       auto& b = c->L64[l];
@@ -1523,9 +1706,7 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
         HIPCHECK(hipMemcpyAsync(b.P, a.P, nw * sizeof(z64), hipMemcpyDeviceToDevice, st));
       }
       b.sa_w = a.sa_w;
-      z64* cb = c->pool.alloc<z64>(a.n);
-      HIPCHECK(hipMemcpyAsync(cb, src->calib[l], a.n * sizeof(z64), hipMemcpyDeviceToDevice, st));
-      c->calib[l] = cb;
+      HIPCHECK(hipMemcpyAsync(c->calib[l], src->calib[l], a.n * sizeof(z64), hipMemcpyDeviceToDevice, st));
     }
     for (int l = 0; l + 1 < c->nlev; ++l) {
       set_nc(*c, l, c->prm.nv[l] * cols_per_vector(c->prm));
@@ -1683,24 +1864,13 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
   const size_t n = lv.n;
   ColStats cs;
   int refinements = 1;
+  reserve_solve(*c, nrhs, precision);
   if (precision == SMG_FP64) {
-    ensure_level_work<double>(*c, nrhs);
-    ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * n);
     pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, mg, c->f64, &cs, 1, 0,
                 c->prm.stop_recursive == 0);
   } else {
     // FP64 defect correction around FP32 MG-CG.
     ensure_f32(*c);
-    ensure_level_work<float>(*c, nrhs);
-    ensure_level_work<double>(*c, nrhs);
-    ensure_kvecs<float>(*c, c->f32, (size_t)nrhs * n);
-    ensure_scalars(*c, nrhs);
-    if (c->dc_cap < (size_t)nrhs * n) {
-      c->r64 = c->pool.alloc<z64>((size_t)nrhs * n);
-      c->b32 = c->pool.alloc<z32>((size_t)nrhs * n);
-      c->e32 = c->pool.alloc<z32>((size_t)nrhs * n);
-      c->dc_cap = (size_t)nrhs * n;
-    }
     const z64* b = (const z64*)rhs;
     z64* xx = (z64*)x;
     launch_dc_start(b, c->r64, xx, (size_t)nrhs * n, c->st);  // r = b, x = 0
@@ -1776,8 +1946,7 @@ int smg_cg(smg_handle h, const double* rhs, double* x, int32_t nrhs, double tol,
   if (!(tol > 0) || maxiter < 1) throw Error(SMG_EINVAL, "tol must be > 0 and maxiter >= 1");
   c->st = (hipStream_t)stream;
   const int64_t fa0 = c->fine_applies;
-  ensure_level_work<double>(*c, nrhs);
-  ensure_kvecs<double>(*c, c->f64, (size_t)nrhs * c->L64[0].n);
+  reserve_solve(*c, nrhs, SMG_FP64);
   ColStats cs;
   pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, false, c->f64, &cs, 1, 0,
               c->prm.stop_recursive == 0);
@@ -1852,6 +2021,53 @@ int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out) {
   API_END
 }
 
+int smg_set_allocator(smg_alloc_fn alloc, smg_release_fn release, void* ctx) {
+  API_BEGIN
+  if (!alloc != !release) throw Error(SMG_EINVAL, "give both alloc and release, or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return SMG_OK;
+  API_END
+}
+
+int smg_query_bytes(const smg_params* params, int32_t nrhs, int32_t precision, size_t* setup_bytes,
+                    size_t* solve_bytes, size_t* batch_bytes) {
+  API_BEGIN
+  if (!params) throw Error(SMG_EINVAL, "null params");
+  check_nrhs(nrhs);
+  if (precision != SMG_FP64 && precision != SMG_MIXED) throw Error(SMG_EINVAL, "bad precision");
+  if (batch_bytes && nrhs > 256) throw Error(SMG_EINVAL, "a batch has at most 256 slots");
+  // the allocation plan of the real calls, run on dry contexts (no device call)
+  auto planned = [&]() {
+    std::unique_ptr<Ctx> c(create(nullptr, params, nullptr, nullptr, true));
+    reserve_setup(*c);
+    return c;
+  };
+  auto c0 = planned();
+  const size_t setup = c0->pool.bytes;
+  if (setup_bytes) *setup_bytes = setup;
+  if (solve_bytes) {
+    reserve_solve(*c0, nrhs, precision);
+    *solve_bytes = c0->pool.bytes - setup;
+  }
+  if (batch_bytes) {
+    auto c1 = planned();
+    Batch B;
+    B.pool.dry = true;
+    B.c = c1.get();
+    B.cap = nrhs;
+    B.prec = precision;
+    B.n = c1->L64[0].n;
+    batch_alloc(B);
+    reserve_batch_handle(*c1, nrhs, precision);
+    *batch_bytes = B.pool.bytes + (c1->pool.bytes - setup);
+  }
+  return SMG_OK;
+  API_END
+}
+
 int smg_memory_bytes(smg_handle h, size_t* bytes) {
   API_BEGIN
   Ctx* c = H(h);
@@ -1880,30 +2096,11 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     B->prec = precision;
     B->n = c->L64[0].n;
     const size_t e = (size_t)max_rhs * B->n;
-    B->b = B->pool.alloc<z64>(e);
-    B->x = B->pool.alloc<z64>(e);
-    B->r = B->pool.alloc<z64>(e);
-    B->p = B->pool.alloc<z64>(e);
-    B->q = B->pool.alloc<z64>(e);
-    B->z = B->pool.alloc<z64>(e);
-    B->t = B->pool.alloc<z64>(e);
-    if (precision == SMG_MIXED) {
-      B->zo = B->pool.alloc<z64>(e);
-      B->r32 = B->pool.alloc<z32>(e);
-      B->z32v = B->pool.alloc<z32>(e);
-      B->rzo = B->pool.alloc<double>(2 * max_rhs);
-      ensure_f32(*c);
-      ensure_level_work<float>(*c, max_rhs);
-    }
-    B->red.partial = B->pool.alloc<double>((size_t)2 * red_blocks(B->n) * max_rhs);
-    B->S.bb = B->pool.alloc<double>(2 * max_rhs);
-    B->S.rz = B->pool.alloc<double>(2 * max_rhs);
-    B->S.pq = B->pool.alloc<double>(2 * max_rhs);
-    B->S.ab = B->pool.alloc<double>(2 * max_rhs);
-    B->S.rr = B->pool.alloc<double>(2 * max_rhs);
-    B->S.tt = B->pool.alloc<double>(2 * max_rhs);
-    B->S.active = B->pool.alloc<int>(max_rhs);
-    B->S.bad = B->pool.alloc<int>(max_rhs);
+    B->pool.stream = &B->st0;
+    B->st0 = st;
+    batch_alloc(*B);
+    reserve_batch_handle(*c, max_rhs, precision);
+    if (precision == SMG_MIXED) ensure_f32(*c);
     HIPCHECK(hipHostMalloc((void**)&B->h, sizeof(double) * 2 * max_rhs, hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&B->hi_, sizeof(int) * max_rhs, hipHostMallocDefault));
     // off by default: each (batch, slot count) pays a capture, and replays do not
@@ -1925,7 +2122,6 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     zero(B->r, e * sizeof(z64), st);
     zero(B->z, e * sizeof(z64), st);
     zero(B->S.rz, sizeof(double) * 2 * max_rhs, st);
-    ensure_level_work<double>(*c, max_rhs);
     batch_upload_active(*B, st);
   } catch (...) {
     delete B;

@@ -58,47 +58,29 @@ def levels_for(l: int, block: int = 4, max_coarse: int = 8) -> int:
     return levels
 
 
-def estimate_bytes(lx: int, lt: int, blocks: Sequence, nv: Sequence[int], capacity: int = 1,
-                   mixed: bool = True, full_setup: bool = True, smoothed: bool = True,
-                   coarsest_direct: bool = True) -> int:
-    """Device bytes of one hierarchy plus one batch of `capacity` slots (an upper
-    estimate of what the library allocates for them)."""
-    shapes = [(lx, lt, 2)]
-    for (bx, bt), k in zip(blocks, nv):
-        cx, ct, _ = shapes[-1]
-        shapes.append((cx // bx, ct // bt, k))
-    n = [a * b * c for a, b, c in shapes]
-    tot = 2 * lx * lt * Z64  # links
-    work = 0
-    for l in range(len(shapes) - 1):
-        bx, bt = blocks[l]
-        cx, ct, k = shapes[l + 1]
-        dof = shapes[l][2]
-        K = cx * ct
-        halo = 1 if (smoothed and bx >= 4 and bt >= 4 and cx >= 2 and ct >= 2) else 0
-        links = 9 * K * k * k
-        pt = K * k * bx * bt * dof
-        pw = K * k * (bx + 2 * halo) * (bt + 2 * halo) * dof
-        tot += (links + pt + (pw if halo else 0)) * Z64
-        tot += n[l] * Z64  # calibration vector
-        if full_setup:
-            tot += (1 + k) * n[l] * Z64  # random starts
-        if mixed:
-            tot += (links + pw) * Z32
-        work += K * (bx + 2 * halo) * (bt + 2 * halo) * dof  # window buffer per column
-    nlev = len(shapes)
-    if nlev > 1:
-        tot += 5 * n[0] * Z64  # setup scratch
-        if coarsest_direct:
-            tot += (n[-1] * n[-1] + n[-1]) * Z64
-    cols = capacity + 1  # level work grows from 1 column to the batch width
-    per_col64 = sum(4 * m for m in n) + n[0] + work
-    tot += cols * per_col64 * Z64
-    if mixed:
-        tot += n[0] * Z32 + cols * per_col64 * Z32
-    # the batch itself: b x r p q z t (+ z_old, FP32 r and z)
-    tot += capacity * n[0] * (7 + (1 if mixed else 0)) * Z64 + (2 * capacity * n[0] * Z32 if mixed else 0)
-    return int(tot * 1.05) + (1 << 20)
+def estimate_bytes(params, capacity: int = 1, mixed: bool = True) -> int:
+    """Device bytes of one hierarchy plus a batch of `capacity` slots, from the
+    library's own allocation plan (smg_query_bytes: no device call)."""
+    from . import FP64, MIXED, query_bytes
+
+    setup, _solve, batch = query_bytes(params, capacity, MIXED if mixed else FP64)
+    return setup + batch
+
+
+# Stack of every thread that calls into the library here (warm-up workers, lanes).
+# A launch from a fresh thread can run deep in the HIP runtime and, under a
+# profiler's tracing callbacks, beyond the 8 MiB that threads get by default.
+THREAD_STACK_BYTES = 64 << 20
+
+
+@contextlib.contextmanager
+def _thread_stack(nbytes: int = THREAD_STACK_BYTES):
+    """Threads started inside the block get `nbytes` of stack."""
+    old = threading.stack_size(nbytes)
+    try:
+        yield
+    finally:
+        threading.stack_size(old)
 
 
 @dataclasses.dataclass
@@ -290,7 +272,8 @@ class _Lane:
         self.cv = threading.Condition()
         self.stop = False
         self.last_busy = time.perf_counter()
-        self.thread = threading.Thread(target=self._run, daemon=True, name=f"lane-{field}-{mass}")
+        with _thread_stack():
+            self.thread = threading.Thread(target=self._run, daemon=True, name=f"lane-{field}-{mass}")
         self.solver = None
         self.batch = None
         self.stream = server._take_stream()
@@ -559,7 +542,8 @@ class Server:
                 with self.lock:
                     self.streams.append(stream)
 
-        threads = [threading.Thread(target=work, args=(i,)) for i in range(min(workers, len(items)))]
+        with _thread_stack():
+            threads = [threading.Thread(target=work, args=(i,)) for i in range(min(workers, len(items)))]
         for t in threads:
             t.start()
         for t in threads:
@@ -675,12 +659,8 @@ class DeviceBackend:
         self.mixed = mixed
 
     def estimate(self, field, capacity: int) -> int:
-        g, p = self.fields[field]
-        blocks = [(p.block[l][0], p.block[l][1]) for l in range(p.levels - 1)]
-        # coarse variables per site: nv, or 2 nv with chirality-split aggregates
-        nv = [p.nv[l] * (2 if p.split_chirality else 1) for l in range(p.levels - 1)]
-        return estimate_bytes(p.lx, p.lt, blocks, nv, capacity, mixed=self.mixed,
-                              smoothed=p.sa_scale > 0, coarsest_direct=p.coarsest == 0)
+        _g, p = self.fields[field]
+        return estimate_bytes(p, capacity, mixed=self.mixed)
 
     def setup(self, field, mass: float, stream):
         g, p = self.fields[field]

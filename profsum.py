@@ -13,7 +13,7 @@ seconds are kept (a program that pauses between its setup and a timed region
 gives the timed region alone); the summary then also reports the wall span of
 those dispatches and the time the device had at least one of them running.
 
-Usage: python -m paper_0710_3612_amd.profsum TRACE.csv [--top N] [--match SUBSTR] [--counters]
+Usage: python profsum.py TRACE.csv [--top N] [--match SUBSTR] [--counters]
        [--after-gap S]
 """
 

@@ -42,7 +42,7 @@ def c_layout():
         "smg_params": ["lx", "lt", "mass", "levels", "block", "nv", "setup_iters", "smoother_steps",
                        "smoother_omega", "t_antiperiodic", "coarsest", "coarsest_tol", "coarsest_maxiter",
                        "inner_tol", "seed", "sa_scale", "smoother_storage", "stop_recursive", "mfma_min_rhs",
-                       "operator_storage", "split_chirality"],
+                       "operator_storage", "split_chirality", "coarsest_fp64"],
         "smg_stats": ["status", "iterations", "refinements", "vcycles", "fine_applies", "true_relres", "seconds"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {", 'printf("{");']
@@ -133,3 +133,43 @@ def test_operator_storage_validation():
         p = smg.make_params(64, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4], operator_storage=bad)
         assert lib.smg_setup(fake, ctypes.byref(p), None, None, ctypes.byref(h)) == -1
         assert "operator_storage" in lib.smg_last_error().decode()
+
+
+def test_query_bytes_plans_without_a_device():
+    """smg_query_bytes runs the allocation plan on the host: it answers without a
+    GPU, grows with the columns and the precision's extra copies, counts the
+    FP16 operator copies, and rejects what smg_setup rejects."""
+    import paper_0710_3612_amd as smg
+
+    p = smg.make_params(64, 64, 0.1, levels=3, blocks=[(4, 4), (4, 4)], nv=[8, 8])
+    s1, f1, b1 = smg.query_bytes(p, 1, smg.FP64)
+    s8, f8, b8 = smg.query_bytes(p, 8, smg.FP64)
+    assert s1 == s8 > 0 and f8 > f1 > 0 and b8 > b1 > 0
+    _, m8, bm8 = smg.query_bytes(p, 8, smg.MIXED)
+    assert m8 > f8 and bm8 > b8  # FP32 copies of the hierarchy and FP32 work vectors
+    # the fine links (32 B per site) and the coarsest inverse (n^2 16 B) are in the setup
+    n_c = 4 * 4 * 8
+    assert s1 > 64 * 64 * 32 + n_c * n_c * 16
+    q = smg.make_params(64, 64, 0.1, levels=3, blocks=[(4, 4), (4, 4)], nv=[8, 8], operator_storage=smg.STORE_F16,
+                        coarsest_fp64=False)
+    _, m16, _ = smg.query_bytes(q, 8, smg.MIXED)
+    assert m16 > m8  # FP16 copies of links, P and the inverse, plus the FP32 inverse
+    bad = smg.make_params(30, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[8])
+    with pytest.raises(smg.SmgError) as e:
+        smg.query_bytes(bad, 1, smg.FP64)
+    assert e.value.code == -2
+    assert smg.query_bytes(p, 300, smg.FP64)[2] is None  # a batch has at most 256 slots
+    with pytest.raises(smg.SmgError):
+        smg.query_bytes(p, 5000, smg.FP64)
+    lib = smg.load_library()
+    a = ctypes.c_size_t()
+    assert lib.smg_query_bytes(ctypes.byref(p), 300, 0, None, None, ctypes.byref(a)) == -1
+
+
+def test_set_allocator_needs_both_callbacks():
+    import paper_0710_3612_amd as smg
+
+    lib = smg.load_library()
+    fn = smg._ALLOC_FN(lambda n, s, c: None)
+    assert lib.smg_set_allocator(fn, smg._RELEASE_FN(), None) == -1
+    smg.use_torch_allocator(True)

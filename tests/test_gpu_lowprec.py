@@ -58,7 +58,8 @@ def lp():
     for st in (smg.STORE_F32, smg.STORE_BF16, smg.STORE_F16):
         p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, smoother_storage=st)
         solvers[st] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
-    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, operator_storage=smg.STORE_F16, mfma_min_rhs=0)
+    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, operator_storage=smg.STORE_F16, mfma_min_rhs=0,
+                        coarsest_fp64=False)
     solvers["op16"] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
     yield dict(U=U, A=A, h=h, m=m, n=2 * lx * lt, s=solvers)
     for s in solvers.values():

@@ -505,10 +505,11 @@ def test_smoother_degrees(nu):
         s.close()
 
 
-@pytest.mark.parametrize("opst", [0, 2])
-def test_fp32_vcycle_large_coarsest_matrix_cores(opst):
+@pytest.mark.parametrize("opst,c64", [(0, False), (2, False), (2, True)])
+def test_fp32_vcycle_large_coarsest_matrix_cores(opst, c64):
     """FP32 V-cycle whose 5120-variable coarsest inverse is applied on the matrix
-    cores (n above the row-kernel limit), with FP32 or FP16 operator storage: within
+    cores from an FP32 or FP16 copy (n above the row-kernel limit), or in FP64 by
+    the tiled kernel (coarsest_fp64), with FP32 or FP16 operator storage: within
     1e-4 (FP32) or 1e-3 (FP16, unit roundoff 2^-11 times 2) of the oracle's FP64
     V-cycle, for 1 and 33 right-hand sides (two column tiles, the second ragged);
     a column's result is bitwise the same alone and inside the batch."""
@@ -520,7 +521,7 @@ def test_fp32_vcycle_large_coarsest_matrix_cores(opst):
     vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, 63)
     A = normal_matrix(U, m)
     h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=4 / 3)
-    p = smg.make_params(lx, lt, m, levels=2, blocks=blocks, nv=nvs, operator_storage=opst)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=blocks, nv=nvs, operator_storage=opst, coarsest_fp64=c64)
     s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])), calib=dev(np.concatenate(calib)))
     try:
         assert s.level_size(1) == 5120

@@ -262,6 +262,73 @@ def test_mass_affinity_of_coarse_operator():
         np.testing.assert_allclose(Ac, C2 + m * C1 + m * m * np.eye(Ac.shape[0]), atol=1e-13)
 
 
+def test_set_mass_rebuilds_every_level_from_the_new_mass():
+    """set_mass on a 3-level hierarchy (smoothed P on the first coarsening): with
+    D(m) = D0 + m and P, P2 kept, level 1 is C2 + m C1 + m^2 C0 (C0 = P^H P, which
+    is not I for a smoothed P) and level 2 is P2^H (C2 + m C1 + m^2 C0) P2.  The C
+    are formed here from D0 at mass 0, never from set_mass's own operators, so a
+    level rebuilt from the old mass, or level 2 from the old level 1, fails."""
+    lx = lt = 16
+    m0, m1 = 0.2, -0.05
+    U = hot_field(lx, lt, seed=71, sweeps=10)
+    blocks, nvs = [(4, 4), (2, 2)], [3, 3]
+    R = synth.setup_randoms(lx, lt, blocks, nvs, 12)
+    h = mg.adaptive_setup(normal_matrix(U, m0), (lx, lt, 2), blocks, nvs, R, nu=2, omega=0.8, setup_iters=2,
+                          sa_scale=4 / 3)
+    assert h.levels[0].sa_weight > 0 and h.levels[1].sa_weight == 0
+    calib = [r[0] for r in R]
+    h1 = mg.set_mass(h, normal_matrix(U, m1), calib, nu=2, omega=0.8)
+    P, P2 = h.levels[0].P.toarray(), h.levels[1].P.toarray()
+    D0 = dirac_matrix(U, 0.0).toarray()
+    C0 = P.conj().T @ P
+    C1 = P.conj().T @ (D0 + D0.conj().T) @ P
+    C2 = P.conj().T @ (D0.conj().T @ D0) @ P
+    assert np.max(np.abs(C0 - np.eye(C0.shape[0]))) > 1e-3  # smoothed: P^H P differs from I
+    A1 = C2 + m1 * C1 + m1 * m1 * C0
+    scale = np.max(np.abs(A1))
+    assert np.max(np.abs(h1.levels[1].A.toarray() - A1)) <= 1e-13 * scale
+    A2 = P2.conj().T @ A1 @ P2
+    assert np.max(np.abs(h1.levels[2].A.toarray() - A2)) <= 1e-13 * scale
+    # the old operators differ by far more than that
+    assert np.max(np.abs(h.levels[1].A.toarray() - A1)) > 1e-3 * scale
+    # prolongators are kept as they are (Results section: vectors reused)
+    assert (h1.levels[0].P != h.levels[0].P).nnz == 0 and (h1.levels[1].P != h.levels[1].P).nnz == 0
+
+
+def test_set_mass_recalibrates_from_closed_form_eigenvectors():
+    """Free field, periodic BC, constant candidates, plain aggregation.  set_mass to m1
+    with the fine calibration start a plane wave (an eigenvector of A(m1) with
+    eigenvalue lam) and the coarse start the coarse constant (A_c(m1) 1 = m1^2 1):
+    every frozen coefficient is then omega / lam on level 0 and omega / m1^2 on
+    level 1 (MR on an eigenvector), and A_c(m1) 1 = m1^2 1."""
+    lx = lt = 16
+    m0, m1, omega, nu = 0.4, 0.25, 0.8, 3
+    U = np.ones((2, lt, lx), dtype=np.complex128)
+    blocks = [(4, 4), (2, 2)]
+    V0 = np.zeros((2, 2 * lx * lt), dtype=np.complex128)
+    V0[0, 0::2] = 1.0
+    V0[1, 1::2] = 1.0
+    n1 = (lx // 4) * (lt // 4) * 2
+    V1 = np.zeros((2, n1), dtype=np.complex128)
+    V1[0, 0::2] = 1.0
+    V1[1, 1::2] = 1.0
+    t, x = np.meshgrid(np.arange(lt), np.arange(lx), indexing="ij")
+    px, pt = 2 * math.pi * 2 / lx, 2 * math.pi * 3 / lt
+    Dp = (2 + m1 - math.cos(px) - math.cos(pt)) * np.eye(2) + 1j * (SIGMA1 * math.sin(px) + SIGMA2 * math.sin(pt))
+    w, vecs = np.linalg.eigh(Dp.conj().T @ Dp)
+    wave = np.kron(np.exp(1j * (px * x + pt * t)).ravel(), vecs[:, 1])
+    ones1 = np.ones(n1, dtype=np.complex128)
+    rnd = [synth.gaussian(2 * lx * lt, 1), synth.gaussian(n1, 2)]
+    h = mg.hierarchy_from_vectors(normal_matrix(U, m0, antiperiodic_t=False), (lx, lt, 2), blocks, [V0, V1], rnd,
+                                  nu, omega)
+    h1 = mg.set_mass(h, normal_matrix(U, m1, antiperiodic_t=False), [wave, ones1], nu, omega)
+    np.testing.assert_allclose(h1.levels[0].coefs, [omega / w[1]] * nu, rtol=1e-12)
+    np.testing.assert_allclose(h1.levels[1].coefs, [omega / m1 ** 2] * nu, rtol=1e-12)
+    np.testing.assert_allclose(h1.levels[1].A @ ones1, m1 ** 2 * ones1, atol=1e-13)
+    n2 = (lx // 8) * (lt // 8) * 2
+    np.testing.assert_allclose(h1.levels[2].A @ np.ones(n2), m1 ** 2 * np.ones(n2), atol=1e-13)
+
+
 # ---------------------------------------------------------------------------
 # Smoother (P11) and V-cycle (P9, P10)
 # ---------------------------------------------------------------------------

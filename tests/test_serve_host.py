@@ -239,9 +239,30 @@ def test_levels_for_and_estimate():
     assert serve.levels_for(128) == 3  # 128 -> 32 -> 8
     assert serve.levels_for(256) == 4  # 256 -> 64 -> 16 -> 4
     assert serve.levels_for(512) == 4  # 512 -> 128 -> 32 -> 8
-    a = serve.estimate_bytes(256, 256, [(4, 4)] * 2, [12, 12], capacity=16)
-    b = serve.estimate_bytes(256, 256, [(4, 4)] * 2, [12, 12], capacity=1)
-    assert a > b > 0
+    import paper_0710_3612_amd as smg
+
+    p = smg.make_params(256, 256, 0.1, levels=3, blocks=[(4, 4)] * 2, nv=[12, 12])
+    a = serve.estimate_bytes(p, capacity=16)
+    b = serve.estimate_bytes(p, capacity=1)
+    c = serve.estimate_bytes(p, capacity=1, mixed=False)
+    assert a > b > c > 0
+    setup, _, batch = smg.query_bytes(p, 16, smg.MIXED)
+    assert a == setup + batch
+
+
+def test_worker_threads_get_large_stacks():
+    """Warm-up workers and lanes start with THREAD_STACK_BYTES of stack, and the
+    process default is restored afterwards."""
+    import threading
+
+    seen = []
+    before = threading.stack_size()
+    with serve._thread_stack():
+        t = threading.Thread(target=lambda: seen.append(threading.stack_size()))
+        t.start()
+        t.join()
+    assert seen == [serve.THREAD_STACK_BYTES]
+    assert threading.stack_size() == before
 
 
 def test_warm_builds_every_key_once():
