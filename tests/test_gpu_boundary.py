@@ -77,21 +77,30 @@ def test_library_memory_is_torch_memory(cuda):
     allocated bytes grow by at least the handle's bytes while it lives and fall
     back when it is destroyed; hipMalloc is restored for later handles when the
     binding turns the allocator off, and the handles made before keep theirs."""
+    import gc
+
     import torch
 
     smg = smg_mod()
     lx = lt = 64
     U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 5, 3))
     p = smg.make_params(lx, lt, 0.1, levels=3, blocks=[(4, 4), (4, 4)], nv=[6, 6])
-    torch.cuda.synchronize()
-    base = torch.cuda.memory_allocated()
-    s = smg.Solver(dev(U), p)
-    used = torch.cuda.memory_allocated() - base
+    g = dev(U)
+    # no collection of earlier tests' tensors may free memory inside the measurement
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        s = smg.Solver(g, p)
+        used = torch.cuda.memory_allocated() - base
+    finally:
+        gc.enable()
     assert used >= s.memory_bytes() > 0
     smg.use_torch_allocator(False)
     try:
         before = torch.cuda.memory_allocated()
-        s2 = smg.Solver(dev(U), p)
+        s2 = smg.Solver(g, p)
         assert torch.cuda.memory_allocated() - before < s2.memory_bytes() // 2
         x = dev(synth.gaussian(2 * lx * lt, 4))
         y1, y2 = s.apply_A(x), s2.apply_A(x)
