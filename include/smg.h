@@ -223,6 +223,22 @@ int smg_smooth(smg_handle h, int32_t level, const double* b, double* x, int32_t 
  * with the sign of its R A R^H term taken from those steps).  FP64.  ASYNC. */
 int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream);
 
+/* x = V b as smg_vcycle, for callers that cannot allocate device memory during the
+ * call: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The call allocates nothing (no hipMalloc, hipFree or allocator
+ * callback): the per-level work vectors of the V-cycle live in one static device
+ * array of 64 MiB per GPU (SMG_NOALLOC_SCRATCH_BYTES), taken when the library is
+ * first used this way on that device and held until the process ends.  Every call
+ * on a GPU shares that GPU's array, so calls that overlap on one GPU (any handle,
+ * any stream) race: serialise them.  Nothing in the array needs to start at zero.
+ * Needs levels >= 2 and SMG_COARSEST_DIRECT (the coarsest CG keeps Krylov vectors
+ * of its own).  b, x: device, complex128 [nrhs][lt][lx][2], must not overlap.
+ * ASYNC.  The result equals smg_vcycle's bit for bit.
+ * Errors: SMG_EINVAL (bad arguments, CG coarsest, or nrhs columns whose work
+ * vectors exceed the array: about 20 MB per column for a 256^2 lattice with Nv = 12). */
+#define SMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int smg_vcycle_noalloc(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream);
+
 /* The FP32 V-cycle of the mixed-precision solve (same steps; FP32 operators, the
  * fine smoother iterates stored as smoother_storage says): x = V b for complex64
  * device vectors [nrhs][n].  Errors: SMG_EINVAL. */

@@ -148,6 +148,7 @@ def load_library():
         "smg_smooth": (i32, [h, i32, P, P, i32, P]),
         "smg_vcycle": (i32, [h, P, P, i32, P]),
         "smg_vcycle_f32": (i32, [h, P, P, i32, P]),
+        "smg_vcycle_noalloc": (i32, [h, P, P, i32, P]),
         "smg_solve": (i32, [h, P, P, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(Stats)]),
         "smg_cg": (i32, [h, P, P, i32, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
         "smg_level_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -440,6 +441,15 @@ class Solver:
         x = self._new(b.shape, b)
         _check(self.lib.smg_vcycle(self.handle, _ptr(b), _ptr(x), nr, _stream(stream)))
         return x
+
+    def vcycle_noalloc(self, b, out, stream=None):
+        """x = V b into `out` without any allocation in the library (smg_vcycle_noalloc)."""
+        b = b.contiguous()
+        nr = self._nrhs(b, self.level_size(0))
+        if out.numel() != b.numel():
+            raise ValueError("out must have as many entries as b")
+        _check(self.lib.smg_vcycle_noalloc(self.handle, _ptr(b), _ptr(out), nr, _stream(stream)))
+        return out
 
     def vcycle_f32(self, b, stream=None):
         """The mixed solve's FP32 V-cycle (complex64 in/out)."""

@@ -1548,6 +1548,62 @@ Batch* BH(smg_batch b) {
   return reinterpret_cast<Batch*>(b);
 }
 
+// ---------------------------------------------------------------------------
+// V-cycle without allocation.  Its per-level work vectors come from one static
+// device array per GPU instead of the handle's pool, so a call allocates nothing.
+// The host never names the array itself: its address on each device is taken once
+// with hipGetSymbolAddress, with that device current, and passed to the kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = SMG_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+unsigned char* scratch_on_current_device() {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) throw Error(SMG_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHECK(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(SMG_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Work vectors of every level for nrhs columns carved out of `base` (256-byte
+// aligned pieces); returns the bytes they take.  With base == nullptr only counts.
+size_t carve_level_work(Ctx& c, int nrhs, unsigned char* base, std::vector<Level<double>>* out) {
+  size_t off = 0;
+  auto take = [&](size_t elems) -> z64* {
+    z64* p = base ? reinterpret_cast<z64*>(base + off) : nullptr;
+    off += (elems * sizeof(z64) + 255) & ~(size_t)255;
+    return p;
+  };
+  for (int l = 0; l < c.nlev; ++l) {
+    Level<double> w = c.L64[l];
+    const size_t n = (size_t)nrhs * w.n;
+    w.b = take(n);
+    w.x = take(n);
+    w.r = take(n);
+    w.t = take(n);
+    w.tmp = w.fine ? take(n) : nullptr;
+    w.wbuf = w.bx ? take((size_t)nrhs * w.nkw()) : nullptr;
+    w.cap = nrhs;
+    if (out) (*out)[l] = w;
+  }
+  return off;
+}
+
 }  // namespace
 }  // namespace smg
 
@@ -1831,6 +1887,46 @@ int smg_vcycle(smg_handle h, const double* b, double* x, int32_t nrhs, void* str
   c->st = (hipStream_t)stream;
   ensure_level_work<double>(*c, nrhs);
   vcycle<double>(*c, 0, c->nlev - 1, (const z64*)b, (z64*)x, nrhs, c->prm.coarsest == SMG_COARSEST_CG);
+  return SMG_OK;
+  API_END
+}
+
+int smg_vcycle_noalloc(smg_handle h, const double* b, double* x, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_nrhs(nrhs);
+  if (!x || !b) throw Error(SMG_EINVAL, "null vector");
+  if (c->nlev < 2 || c->prm.coarsest != SMG_COARSEST_DIRECT)
+    throw Error(SMG_EINVAL, "smg_vcycle_noalloc needs levels >= 2 and the dense coarsest inverse");
+  const size_t need = carve_level_work(*c, nrhs, nullptr, nullptr);
+  if (need > kScratchBytes)
+    throw Error(SMG_EINVAL, "smg_vcycle_noalloc: " + std::to_string(nrhs) + " columns need " + std::to_string(need) +
+                                " bytes of work space, more than the " + std::to_string(kScratchBytes) +
+                                " bytes of the static scratch array");
+  unsigned char* base = scratch_on_current_device();
+  std::vector<Level<double>> work(c->nlev);
+  carve_level_work(*c, nrhs, base, &work);
+  // the handle's own work vectors are swapped out for the call and restored on every exit
+  struct Swap {
+    Ctx& c;
+    std::vector<Level<double>>& w;
+    void flip() {
+      for (int l = 0; l < c.nlev; ++l) {
+        auto& a = c.L64[l];
+        std::swap(a.b, w[l].b);
+        std::swap(a.x, w[l].x);
+        std::swap(a.r, w[l].r);
+        std::swap(a.t, w[l].t);
+        std::swap(a.tmp, w[l].tmp);
+        std::swap(a.wbuf, w[l].wbuf);
+        std::swap(a.cap, w[l].cap);
+      }
+    }
+    ~Swap() { flip(); }
+  } swap{*c, work};
+  swap.flip();
+  c->st = (hipStream_t)stream;
+  vcycle<double>(*c, 0, c->nlev - 1, (const z64*)b, (z64*)x, nrhs, false);
   return SMG_OK;
   API_END
 }
