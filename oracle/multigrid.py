@@ -394,9 +394,26 @@ def _two_level_exact(level: Level, Ac) -> Callable:
     return V
 
 
+def two_level_factor(level: Level, Ac, e0: np.ndarray, iters: int) -> float:
+    """Convergence factor of the current two-level cycle on a start error e0
+    (Adaptive Multigrid section: vectors are added until the V-cycle reduces a random
+    error sufficiently): iters passes of e <- (I - V A) e, then the geometric mean of
+    the A-norm reduction, (||e_iters||_A / ||e_0||_A)^(1 / iters)."""
+    V = _two_level_exact(level, Ac)
+    A = level.A
+    e = np.array(e0, dtype=np.complex128, copy=True)
+    q = A @ e
+    n0 = math.sqrt(dot(e, q).real)
+    for _ in range(iters):
+        e = e - V(q)
+        q = A @ e
+    return (math.sqrt(max(dot(e, q).real, 0.0)) / n0) ** (1.0 / iters)
+
+
 def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_iters: int,
                    coarsest="cholesky", coarsest_tol=1e-12, log: Optional[list] = None,
-                   sa_scale: float = 0.0, split: bool = False) -> Hierarchy:
+                   sa_scale: float = 0.0, split: bool = False, nv_stop_rho: float = 0.0,
+                   nv_stop_iters: int = 3) -> Hierarchy:
     """Adaptive setup (Adaptive Multigrid section), level by level.
 
     For each coarsening l with random starts randoms[l] ([1 + Nv, n_l]):
@@ -410,11 +427,20 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
       * the finished A_c is the next level's operator (the procedure recurses).
     With sa_scale > 0 every prolongator is the smoothed one (see the module notes);
     with split every coarsening uses chirality-split aggregates.
+
+    nv_stop_rho > 0 stops adding vectors early ("repeated as necessary"): after each
+    appended vector (the first included) the two-level cycle's convergence factor on
+    the level's calibration start randoms[l][0] (two_level_factor, nv_stop_iters
+    passes) is measured, and the level keeps the vectors it has once the factor is
+    <= nv_stop_rho; Nv_l is then the most it takes.  The next level's vectors are
+    shorter then: its random rows are still given at full length and their first
+    n_{l+1} entries are used.  Each level's factors go to log[l]["factors"].
     """
     levels = [Level(A=A, shape=tuple(shape))]
     for l, block in enumerate(blocks):
         cur = levels[-1]
-        R = randoms[l]
+        n = cur.A.shape[0]
+        R = np.asarray(randoms[l])[:, :n]
         cur.coefs = mr_coefficients(cur.A, R[0], nu, omega)
         wsa = level_sa_weight(cur, block, R[0], sa_scale)
         e = np.array(R[1], copy=True)
@@ -423,7 +449,16 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
             e = e / norm(e)
         vecs = [e]
         cur, nxt = coarsen(cur, np.array(vecs), block, wsa, split)
-        for k in range(1, nvs[l]):
+        factors = []
+        # at most the variables of an aggregate (the next level may have fewer per site)
+        nmax = min(nvs[l], block[0] * block[1] * cur.shape[2] // (2 if split else 1))
+        for k in range(1, nmax + 1):
+            if nv_stop_rho > 0:
+                factors.append(two_level_factor(cur, nxt.A, R[0], nv_stop_iters))
+                if factors[-1] <= nv_stop_rho:
+                    break
+            if k == nmax:
+                break
             V = _two_level_exact(cur, nxt.A)
             e = np.array(R[1 + k], copy=True)
             for _ in range(setup_iters):
@@ -432,7 +467,7 @@ def adaptive_setup(A, shape, blocks, nvs, randoms, nu: int, omega: float, setup_
             vecs.append(e)
             cur, nxt = coarsen(cur, np.array(vecs), block, wsa, split)
         if log is not None:
-            log.append({"level": l, "coefs": list(cur.coefs)})
+            log.append({"level": l, "coefs": list(cur.coefs), "factors": factors, "nv": len(vecs)})
         levels.append(nxt)
     return Hierarchy(levels, coarsest, coarsest_tol).factor_coarsest()
 

@@ -702,3 +702,101 @@ def test_split_hierarchy_vcycle_identity_and_mgcg(sa_scale):
     x, info = mg.mg_cg(h, b, 1e-12)
     assert info.converged
     np.testing.assert_allclose(x, np.linalg.solve(Ad, b), atol=1e-9 * np.linalg.norm(np.linalg.solve(Ad, b)))
+
+
+# ---------------------------------------------------------------------------
+# Adaptive number of vectors (Adaptive Multigrid section: the procedure is repeated
+# until a V-cycle reduces a random error sufficiently)
+# ---------------------------------------------------------------------------
+
+def test_two_level_factor_matches_dense_error_propagator():
+    """two_level_factor = (||E^s e0||_A / ||e0||_A)^(1/s) with the dense two-level
+    error propagator E = (I - R A)(I - P A_c^{-1} P^H A)(I - R A)."""
+    lx = lt = 8
+    U = hot_field(lx, lt, seed=91, sweeps=10)
+    A = normal_matrix(U, 0.1)
+    R = synth.setup_randoms(lx, lt, [(2, 2)], [3], 4)
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(2, 2)], [3], R, nu=2, omega=0.8, setup_iters=2)
+    lev = h.levels[0]
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    P = lev.P.toarray()
+    Ac = h.levels[1].A.toarray()
+    Rd = mg.smoother_matrix(Ad, lev.coefs)
+    I = np.eye(n)
+    E = (I - Rd @ Ad) @ (I - P @ np.linalg.solve(Ac, P.conj().T @ Ad)) @ (I - Rd @ Ad)
+    e0 = R[0][0]
+    for s in (1, 3):
+        e = np.linalg.matrix_power(E, s) @ e0
+        want = (math.sqrt(np.vdot(e, Ad @ e).real) / math.sqrt(np.vdot(e0, Ad @ e0).real)) ** (1 / s)
+        got = mg.two_level_factor(lev, h.levels[1].A, e0, s)
+        assert abs(got - want) <= 1e-10 * want
+        assert 0 < got < 1
+
+
+def test_nv_stop_off_and_at_one():
+    """nv_stop_rho = 0 keeps Nv vectors and measures nothing; a threshold of 1 stops
+    after the first vector, since a two-level cycle with an exact coarse solve and a
+    convergent smoother contracts the A-norm (factor < 1)."""
+    lx = lt = 16
+    U = hot_field(lx, lt, seed=92, sweeps=10)
+    A = normal_matrix(U, 0.1)
+    R = synth.setup_randoms(lx, lt, [(4, 4)], [5], 5)
+    log = []
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [5], R, nu=2, omega=0.8, setup_iters=2, log=log)
+    assert log[0]["nv"] == 5 and log[0]["factors"] == [] and h.levels[1].shape[2] == 5
+    log = []
+    h = mg.adaptive_setup(A, (lx, lt, 2), [(4, 4)], [5], R, nu=2, omega=0.8, setup_iters=2, log=log,
+                          nv_stop_rho=1.0)
+    assert log[0]["nv"] == 1 and h.levels[1].shape[2] == 1 and 0 < log[0]["factors"][0] < 1
+
+
+def test_nv_stop_full_coarse_space_is_exact():
+    """1x1 aggregates with both spin vectors make P unitary, so the coarse correction
+    is exact and the two-level factor is 0 (to rounding) after the second vector,
+    while one vector leaves a factor in (0, 1)."""
+    lx = lt = 8
+    U = hot_field(lx, lt, seed=93, sweeps=10)
+    A = normal_matrix(U, 0.2)
+    R = synth.setup_randoms(lx, lt, [(1, 1)], [2], 6)
+    log = []
+    mg.adaptive_setup(A, (lx, lt, 2), [(1, 1)], [2], R, nu=2, omega=0.8, setup_iters=2, log=log,
+                      nv_stop_rho=1e-300)
+    f1, f2 = log[0]["factors"]
+    assert 0 < f1 < 1 and f2 <= 1e-7 * f1
+
+
+def test_nv_stop_is_a_prefix_of_the_full_setup_and_shortens_the_next_level():
+    """With a threshold between two consecutive factors of the full setup, the setup
+    keeps exactly the vectors up to the first factor below it: the same vectors and
+    factors as the full run up to there (the rule only truncates), the next level has
+    that many variables per site and is built from the leading part of its random
+    rows, and the resulting 3-level hierarchy satisfies the V-cycle identity."""
+    lx = lt = 32
+    U = hot_field(lx, lt, seed=94, sweeps=20)
+    A = normal_matrix(U, 0.05)
+    blocks, nvs = [(4, 4), (2, 2)], [8, 4]
+    R = synth.setup_randoms(lx, lt, blocks, nvs, 7)
+    full = []
+    mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, nu=2, omega=0.8, setup_iters=3, log=full, nv_stop_rho=1e-300)
+    f = full[0]["factors"]
+    assert len(f) == 8
+    # a threshold halfway (geometrically) across the largest relative drop between vector counts 2..7
+    i = max(range(1, 6), key=lambda j: f[j - 1] / f[j])
+    k = i + 1  # vectors kept: the factor after k vectors is the first below the threshold
+    thr = math.sqrt(f[i] * f[i - 1])
+    assert f[i - 1] / f[i] > 1.01 and all(x > thr for x in f[:i]) and f[i] < thr
+    log = []
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, nu=2, omega=0.8, setup_iters=3, log=log, nv_stop_rho=thr)
+    assert log[0]["nv"] == k and h.levels[1].shape == (8, 8, k)
+    np.testing.assert_allclose(log[0]["factors"], f[:k], rtol=1e-12)
+    Rk = [R[0], R[1][:, :8 * 8 * k]]
+    ref = mg.adaptive_setup(A, (lx, lt, 2), blocks, [k, 4], Rk, nu=2, omega=0.8, setup_iters=3)
+    np.testing.assert_allclose(h.levels[2].A.toarray(), ref.levels[2].A.toarray(), atol=1e-12)
+    b = synth.gaussian(2 * lx * lt, 9)
+    lev = h.levels[0]
+    lhs = b - mg.vcycle(h, 0, A @ b)
+    v1 = b - mg.smoother_apply(A, lev.coefs, A @ b)
+    v2 = v1 - lev.P @ mg.vcycle(h, 1, lev.P.conj().T @ (A @ v1))
+    rhs = v2 - mg.smoother_apply(A, lev.coefs, A @ v2)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.linalg.norm(b))
