@@ -124,6 +124,27 @@ typedef struct {
                                      coarsest direct solve stays FP64; 0 = it applies an FP32
                                      copy of the inverse, or an FP16 copy under operator_storage
                                      SMG_STORE_F16 (a quarter of the bytes per V-cycle) */
+  int32_t remass_affine;          /* 1: smg_setup and smg_setup_from_vectors also keep the mass
+                                     coefficients of every coarse operator, A^(l)(m) = C2 + m C1
+                                     + m^2 C0 with the prolongators fixed (three arrays of the
+                                     level's link size, from the Galerkin operators at m = 0, 1,
+                                     -1), and smg_derive / smg_set_mass form the coarse operators
+                                     of a new mass from them in one pass over the links instead of
+                                     Eq. 2.  Derived handles keep none (they derive by Eq. 2).
+                                     0 (default): every mass change rebuilds by Eq. 2. */
+  double nv_stop_rho;             /* > 0: adaptive number of vectors (Adaptive Multigrid section:
+                                     the procedure is repeated until a V-cycle reduces a random
+                                     error sufficiently).  After each appended vector of coarsening
+                                     l (the first included) smg_setup measures the two-level
+                                     cycle's convergence factor on the level's calibration start,
+                                     (||e||_A / ||e_0||_A)^(1/s) after s = nv_stop_iters passes of
+                                     e <- e - V A e, and stops adding vectors once it is <=
+                                     nv_stop_rho; nv[l] is then the most the level takes and the
+                                     next level carries as many variables per site as were kept
+                                     (smg_level_info).  The random starts keep their full-nv
+                                     layout; a shorter level uses the leading entries of its
+                                     rows.  0 (default): exactly nv[l] vectors. */
+  int32_t nv_stop_iters;          /* passes s of the factor above (default 3) */
 } smg_params;
 
 typedef struct {
@@ -140,7 +161,8 @@ typedef struct {
  * nu = 4, omega = 0.8, antiperiodic t, dense coarsest, coarsest_tol = 1e-12,
  * coarsest_maxiter = 10000, inner_tol = 1e-5, seed = 1, sa_scale = 4/3,
  * smoother_storage = SMG_STORE_F32, stop_recursive = 0, mfma_min_rhs = 16,
- * operator_storage = SMG_STORE_F32, split_chirality = 0, coarsest_fp64 = 1. */
+ * operator_storage = SMG_STORE_F32, split_chirality = 0, coarsest_fp64 = 1,
+ * remass_affine = 0, nv_stop_rho = 0, nv_stop_iters = 3. */
 void smg_default_params(smg_params* p);
 
 /* Adaptive setup (Adaptive Multigrid section; recursion and reuse in Results).
@@ -268,7 +290,8 @@ int smg_level_info(smg_handle h, int32_t level, int32_t* lx, int32_t* lt, int32_
 
 /* Copy out the prolongator of coarsening l (Adaptive Multigrid section).
  * smoothed = 0: the tentative block-orthonormal P_t, device complex128 [J][k][i]
- *   with J the coarse site, k < nv[l] the vector and i = (wy*bx + wx)*dof_l + d for
+ *   with J the coarse site, k < nc the vector (nc = the dof of level l+1 from
+ *   smg_level_info) and i = (wy*bx + wx)*dof_l + d for
  *   the site (Jx*bx + wx, Jt*bt + wy) of the aggregate.
  * smoothed = 1: the prolongator the V-cycle uses, [J][k][i] over the window of
  *   (bx + 2h) x (bt + 2h) sites, i = (wy*(bx+2h) + wx)*dof_l + d for the site
@@ -285,6 +308,12 @@ int smg_transfer_info(smg_handle h, int32_t level, int32_t* halo, double* sa_wei
  * neighbour K + (dx, dt), row = output component: (A v)_K = sum_D L[K][D] v_{K+D}.
  * Synchronous. */
 int smg_get_coarse_links(smg_handle h, int32_t level, double* out, void* stream);
+
+/* The two-level convergence factors that the adaptive stop (nv_stop_rho) measured on
+ * coarsening `level`, one per vector count from 1: up to cap of them into out (host),
+ * their number into *count (0 when the stop was off or the handle was not made by
+ * smg_setup). */
+int smg_get_setup_factors(smg_handle h, int32_t level, double* out, int32_t cap, int32_t* count);
 
 /* Host copy of the nu smoother coefficients c_k of level l. */
 int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out);
@@ -365,8 +394,10 @@ int smg_set_allocator(smg_alloc_fn alloc, smg_release_fn release, void* ctx);
 /* Device bytes the library will hold for a hierarchy with these parameters,
  * computed on the host from the allocation plan that the calls themselves follow
  * (no device call):
- *   setup_bytes  smg_memory_bytes of a handle right after smg_setup,
- *                smg_setup_from_vectors or smg_derive;
+ *   setup_bytes  smg_memory_bytes of a handle right after smg_setup or
+ *                smg_setup_from_vectors (smg_derive: the same, less the mass
+ *                coefficients that remass_affine keeps, 3 x 144 nc^2 bytes per
+ *                coarse site of every coarse level);
  *   solve_bytes  what such a handle adds the first time it runs smg_solve with
  *                nrhs columns in `precision` (later solves of at most nrhs columns
  *                in that precision add nothing; smg_cg adds at most the SMG_FP64

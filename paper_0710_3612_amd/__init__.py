@@ -83,6 +83,9 @@ class Params(ctypes.Structure):
         ("operator_storage", ctypes.c_int32),
         ("split_chirality", ctypes.c_int32),
         ("coarsest_fp64", ctypes.c_int32),
+        ("remass_affine", ctypes.c_int32),
+        ("nv_stop_rho", ctypes.c_double),
+        ("nv_stop_iters", ctypes.c_int32),
     ]
 
 
@@ -156,6 +159,7 @@ def load_library():
         "smg_transfer_info": (i32, [h, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "smg_get_coarse_links": (i32, [h, i32, P, P]),
         "smg_get_smoother_coefs": (i32, [h, i32, ctypes.POINTER(ctypes.c_double)]),
+        "smg_get_setup_factors": (i32, [h, i32, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]),
         "smg_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
         "smg_query_bytes": (i32, [ctypes.POINTER(Params), i32, i32, ctypes.POINTER(ctypes.c_size_t),
                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
@@ -243,7 +247,8 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
                 seed: int = 1, sa_scale: float = 4.0 / 3.0, mfma_min_rhs: int = 16,
                 smoother_storage: int = STORE_F32, stop_recursive: bool = False,
                 operator_storage: int = STORE_F32, split_chirality: bool = False,
-                coarsest_fp64: bool = True) -> Params:
+                coarsest_fp64: bool = True, remass_affine: bool = False, nv_stop_rho: float = 0.0,
+                nv_stop_iters: int = 3) -> Params:
     lib = load_library()
     p = Params()
     lib.smg_default_params(ctypes.byref(p))
@@ -267,6 +272,9 @@ def make_params(lx: int, lt: int, mass: float, levels: int = 2, blocks: Sequence
     p.operator_storage = operator_storage
     p.split_chirality = int(bool(split_chirality))
     p.coarsest_fp64 = int(bool(coarsest_fp64))
+    p.remass_affine = int(bool(remass_affine))
+    p.nv_stop_rho = float(nv_stop_rho)
+    p.nv_stop_iters = int(nv_stop_iters)
     return p
 
 
@@ -519,6 +527,13 @@ class Solver:
         b = ctypes.c_size_t()
         _check(self.lib.smg_memory_bytes(self.handle, ctypes.byref(b)))
         return b.value
+
+    def setup_factors(self, level: int):
+        """Two-level factors the adaptive stop measured on coarsening `level`."""
+        buf = (ctypes.c_double * 64)()
+        cnt = ctypes.c_int32()
+        _check(self.lib.smg_get_setup_factors(self.handle, level, buf, 64, ctypes.byref(cnt)))
+        return [buf[i] for i in range(cnt.value)]
 
 
 class Batch:

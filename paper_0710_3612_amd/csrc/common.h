@@ -341,7 +341,8 @@ void launch_random_gaussian(z64* v, size_t n, uint64_t seed, uint64_t stream_id,
 void launch_links_export(const z64* L, z64* out, int nK, int nc, hipStream_t st);
 template <typename Ro>
 void launch_links_convert(const z64* L, cpx<Ro>* out, size_t n, hipStream_t st);
-// out = C2 + m*C1 + m^2 * I(D = centre)  (mass-affine coarse links)
-void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int nK, int nc, hipStream_t st);
+// out = a X + b Y + c Z elementwise over n complex values (in place allowed)
+void launch_lincomb3(const z64* X, const z64* Y, const z64* Z, z64* out, double a, double b, double c, size_t n,
+                     hipStream_t st);
 
 }  // namespace smg

@@ -954,19 +954,15 @@ __global__ void k_links_export(const z64* __restrict__ L, z64* __restrict__ out,
   out[idx] = L[((size_t)D * nc + col) * n + (size_t)K * nc + row];
 }
 
-__global__ void k_links_affine(const z64* __restrict__ C2, const z64* __restrict__ C1, z64* __restrict__ out,
-                               double m, int nK, int nc) {
-  const size_t n = (size_t)nK * nc;
-  const size_t total = 9 * (size_t)nc * n;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  z64 v = C2[idx] + m * C1[idx];
-  // centre block D = 4, diagonal col == row
-  const size_t Dc = idx / ((size_t)nc * n);
-  const int col = (int)((idx / n) % nc);
-  const int row = (int)(idx % nc);
-  if (Dc == 4 && col == row) v.re += m * m;
-  out[idx] = v;
+// out = a X + b Y + c Z elementwise over complex arrays (real coefficients): the
+// coarse links of a mass from the mass coefficients, and those coefficients from
+// the links at three masses.  In place is allowed (out equal to X, Y or Z).
+__global__ void k_lincomb3(const z64* X, const z64* Y, const z64* Z, z64* out, double a, double b, double c,
+                           size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const z64 x = X[i], y = Y[i], z = Z[i];
+    out[i] = mk(fma(c, z.re, fma(b, y.re, a * x.re)), fma(c, z.im, fma(b, y.im, a * x.im)));
+  }
 }
 
 template <typename Ro>
@@ -1750,10 +1746,11 @@ void launch_convert_h16(const z64* in, hfc* out, size_t n, double inv_scale, hip
   HIPCHECK(hipGetLastError());
 }
 
-void launch_links_affine(const z64* C2, const z64* C1, z64* out, double m, int nK, int nc, hipStream_t st) {
-  const size_t total = 9 * (size_t)nc * nc * nK;
-  hipLaunchKernelGGL(k_links_affine, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, C2,
-                     C1, out, m, nK, nc);
+void launch_lincomb3(const z64* X, const z64* Y, const z64* Z, z64* out, double a, double b, double c, size_t n,
+                     hipStream_t st) {
+  const size_t g = std::min<size_t>((n + kThreads - 1) / kThreads, 8192);
+  if (g == 0) return;
+  hipLaunchKernelGGL(k_lincomb3, dim3((unsigned)g), dim3(kThreads), 0, st, X, Y, Z, out, a, b, c, n);
   HIPCHECK(hipGetLastError());
 }
 

@@ -173,6 +173,11 @@ struct Ctx {
   std::vector<Level<float>> L32;
   bool f32_ready = false;
   std::vector<z64*> calib;          // smoother calibration start per coarsening
+  // mass coefficients of the coarse operators (remass_affine): A^(l)(m) = C2 + m C1 + m^2 C0
+  // for every coarse level l >= 1, the prolongators fixed (empty when not kept)
+  std::vector<z64*> C0, C1, C2;
+  std::vector<size_t> n_plan;       // vector length per level at the full nv (layout of the random starts)
+  std::vector<std::vector<double>> factors;  // two-level factors measured by the adaptive stop, per level
   // dense inverse of the coarsest operator
   z64* Minv = nullptr;
   z32* Minv32 = nullptr;            // FP32 copy for the mixed solve's V-cycles
@@ -971,6 +976,28 @@ void scale_to_unit(Ctx& c, z64* e, size_t n) {
   launch_scale_const<double>(e, 1.0 / nrm, n, 1, c.st);
 }
 
+// Convergence factor of the current two-level cycle on level l (Adaptive Multigrid
+// section: vectors are added until the V-cycle reduces a random error sufficiently):
+// from the level's calibration start e, nv_stop_iters passes of e <- e - V(A e), then
+// (||e||_A / ||e_0||_A)^(1 / passes).  The coarse system is solved by CG to
+// coarsest_tol, as in the setup's cycles.
+double two_level_factor(Ctx& c, int l) {
+  auto& lv = c.L64[l];
+  const size_t n = lv.n;
+  const int it = c.prm.nv_stop_iters;
+  HIPCHECK(hipMemcpyAsync(c.se, c.calib[l], n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  apply_op<double>(c, lv, c.se, c.st_, 1, 0, 0.0, nullptr, nullptr);
+  const double n0 = std::sqrt(dev_dot_re(c, c.se, c.st_, n));
+  for (int i = 0; i < it; ++i) {
+    vcycle<double>(c, l, l + 1, c.st_, c.sz, 1, true);
+    launch_axpy_const<double>(c.se, c.sz, -1.0, n, 1, c.st);
+    apply_op<double>(c, lv, c.se, c.st_, 1, 0, 0.0, nullptr, nullptr);
+  }
+  const double e2 = dev_dot_re(c, c.se, c.st_, n);
+  if (!(n0 > 0) || !std::isfinite(e2)) throw Error(SMG_ESETUP, "two-level factor: the error is not finite");
+  return std::pow(std::sqrt(std::max(e2, 0.0)) / n0, 1.0 / it);
+}
+
 // Adaptive setup of coarsening l (Adaptive Multigrid section).  rnd holds the
 // 1 + nv random starts of this level (row 0 was used for the calibration).
 void adaptive_level(Ctx& c, int l, const z64* rnd) {
@@ -989,8 +1016,16 @@ void adaptive_level(Ctx& c, int l, const z64* rnd) {
   set_nc(c, l, m);
   gs_append(c, l, c.se, 0);
   galerkin(c, l);
-  // further candidates: the current two-level V-cycle as error propagator
-  for (int k = 1; k < nv; ++k) {
+  // at most the variables of an aggregate (fewer per site when the level above stopped early)
+  const int nmax = std::min(nv, lv.bx * lv.bt * lv.dof / m);
+  // further candidates: the current two-level V-cycle as error propagator; with
+  // nv_stop_rho > 0 the level keeps what it has once that cycle's factor is small enough
+  for (int k = 1; k <= nmax; ++k) {
+    if (c.prm.nv_stop_rho > 0) {
+      c.factors[l].push_back(two_level_factor(c, l));
+      if (c.factors[l].back() <= c.prm.nv_stop_rho) break;
+    }
+    if (k == nmax) break;
     HIPCHECK(hipMemcpyAsync(c.se, rnd + (size_t)(1 + k) * n, n * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
     for (int it = 0; it < c.prm.setup_iters; ++it) {
       apply_op<double>(c, lv, c.se, c.st_, 1, 0, 0.0, nullptr, nullptr);
@@ -1020,6 +1055,10 @@ void validate(const smg_params& p) {
     throw Error(SMG_EINVAL, "operator_storage must be SMG_STORE_F32 or SMG_STORE_F16");
   if (p.split_chirality != 0 && p.split_chirality != 1) throw Error(SMG_EINVAL, "split_chirality must be 0 or 1");
   if (p.coarsest_fp64 != 0 && p.coarsest_fp64 != 1) throw Error(SMG_EINVAL, "coarsest_fp64 must be 0 or 1");
+  if (p.remass_affine != 0 && p.remass_affine != 1) throw Error(SMG_EINVAL, "remass_affine must be 0 or 1");
+  if (!(p.nv_stop_rho >= 0) || !std::isfinite(p.nv_stop_rho)) throw Error(SMG_EINVAL, "nv_stop_rho must be >= 0");
+  if (p.nv_stop_rho > 0 && (p.nv_stop_iters < 1 || p.nv_stop_iters > 100))
+    throw Error(SMG_EINVAL, "nv_stop_iters must be in [1, 100]");
   const int m = p.split_chirality ? 2 : 1;
   if (p.smoother_storage != SMG_STORE_F32 && (p.levels < 2 || !normal_lp_fits(p.lx, p.lt)))
     throw Error(SMG_EINVAL, "BF16/FP16 smoother storage needs levels >= 2, lx % 32 == 0 and lt % 16 == 0");
@@ -1091,6 +1130,8 @@ Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z6
       else
         pv.P = pv.Pt;
     }
+    for (auto& lv : c->L64) c->n_plan.push_back(lv.n);
+    c->factors.assign(c->nlev, {});
     c->fail = c->pool.alloc<int>(4);
     ensure_scalars(*c, 1);
     ensure_level_work<double>(*c, 1);
@@ -1203,9 +1244,22 @@ void ensure_f32(Ctx& c) {
 
 // Every allocation a setup makes beyond create(): the calibration start of every
 // coarsening and the dense coarsest inverse with its elimination scratch.
-void reserve_setup(Ctx& c) {
+size_t links_count(const Level<double>& lv) { return 9 * (size_t)lv.lx * lv.lt * lv.dof * lv.dof; }
+
+void reserve_setup(Ctx& c, bool coefficients = true) {
   c.calib.assign(c.nlev, nullptr);
   for (int l = 0; l + 1 < c.nlev; ++l) c.calib[l] = c.pool.alloc<z64>(c.L64[l].n);
+  if (coefficients && c.prm.remass_affine && c.nlev > 1) {
+    c.C0.assign(c.nlev, nullptr);
+    c.C1.assign(c.nlev, nullptr);
+    c.C2.assign(c.nlev, nullptr);
+    for (int l = 1; l < c.nlev; ++l) {
+      const size_t nl = links_count(c.L64[l]);
+      c.C0[l] = c.pool.alloc<z64>(nl);
+      c.C1[l] = c.pool.alloc<z64>(nl);
+      c.C2[l] = c.pool.alloc<z64>(nl);
+    }
+  }
   if (c.nlev > 1 && c.prm.coarsest == SMG_COARSEST_DIRECT) {
     const size_t n = c.L64[c.nlev - 1].n;
     c.Minv = c.pool.alloc<z64>(n * n);
@@ -1249,6 +1303,52 @@ void reserve_batch_handle(Ctx& c, int cap, int prec) {
   }
 }
 
+// Mass coefficients of every coarse operator (Results section: the vectors of one
+// setup serve other masses).  D(m) = D0 + m, so A(m) = D0^H D0 + m (D0 + D0^H) + m^2
+// and, with the prolongators fixed, every Galerkin operator is C2 + m C1 + m^2 C0 on
+// each level.  The three coefficient arrays come from the Galerkin chain at
+// m = 0, +1, -1: C2 = G(0), C1 = (G(1) - G(-1)) / 2, C0 = (G(1) + G(-1)) / 2 - G(0).
+// The links of the setup mass are left as they were.
+void build_mass_coefficients(Ctx& c) {
+  if (c.C0.empty()) return;
+  const int L = c.nlev;
+  Pool keep;  // the setup mass's links, restored at the end
+  keep.stream = &c.st;
+  std::vector<z64*> saved(L, nullptr);
+  for (int l = 1; l < L; ++l) {
+    const size_t nl = links_count(c.L64[l]);
+    saved[l] = keep.alloc<z64>(nl);
+    HIPCHECK(hipMemcpyAsync(saved[l], c.L64[l].L, nl * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  }
+  const double diag0 = c.L64[0].diag;
+  const double masses[3] = {0.0, 1.0, -1.0};
+  z64** dst[3] = {c.C2.data(), c.C1.data(), c.C0.data()};  // G(0), G(1), G(-1) first
+  for (int j = 0; j < 3; ++j) {
+    c.L64[0].diag = 2.0 + masses[j];
+    for (int l = 0; l + 1 < L; ++l) galerkin(c, l);
+    for (int l = 1; l < L; ++l)
+      HIPCHECK(hipMemcpyAsync(dst[j][l], c.L64[l].L, links_count(c.L64[l]) * sizeof(z64), hipMemcpyDeviceToDevice,
+                              c.st));
+  }
+  for (int l = 1; l < L; ++l) {
+    const size_t nl = links_count(c.L64[l]);
+    z64* tmp = c.L64[l].L;  // holds C0 until C1 has been formed in place
+    launch_lincomb3(c.C1[l], c.C0[l], c.C2[l], tmp, 0.5, 0.5, -1.0, nl, c.st);
+    launch_lincomb3(c.C1[l], c.C0[l], c.C0[l], c.C1[l], 0.5, -0.5, 0.0, nl, c.st);
+    HIPCHECK(hipMemcpyAsync(c.C0[l], tmp, nl * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+    HIPCHECK(hipMemcpyAsync(c.L64[l].L, saved[l], nl * sizeof(z64), hipMemcpyDeviceToDevice, c.st));
+  }
+  c.L64[0].diag = diag0;
+  sync(c);  // the saved links are released on return
+}
+
+// Coarse operators of `dst` at its mass from the mass coefficients of `src` (the
+// same prolongators): one pass over the links per level instead of Eq. 2.
+void affine_links(Ctx& dst, const Ctx& src, double m) {
+  for (int l = 1; l < dst.nlev; ++l)
+    launch_lincomb3(src.C2[l], src.C1[l], src.C0[l], dst.L64[l].L, 1.0, m, m * m, links_count(dst.L64[l]), dst.st);
+}
+
 void finish_setup(Ctx& c) {
   build_coarsest_inverse(c);
   c.f32_ready = false;
@@ -1256,15 +1356,17 @@ void finish_setup(Ctx& c) {
   sync(c);
 }
 
+// Offsets into the caller's concatenated per-level blocks, laid out at the full nv of
+// every coarsening (the planned vector lengths).
 size_t level_offset_randoms(const Ctx& c, int l, bool with_calib) {
   size_t off = 0;
-  for (int q = 0; q < l; ++q) off += (size_t)(c.prm.nv[q] + (with_calib ? 1 : 0)) * c.L64[q].n;
+  for (int q = 0; q < l; ++q) off += (size_t)(c.prm.nv[q] + (with_calib ? 1 : 0)) * c.n_plan[q];
   return off;
 }
 
 size_t level_offset_plain(const Ctx& c, int l) {
   size_t off = 0;
-  for (int q = 0; q < l; ++q) off += c.L64[q].n;
+  for (int q = 0; q < l; ++q) off += c.n_plan[q];
   return off;
 }
 
@@ -1648,6 +1750,9 @@ void smg_default_params(smg_params* p) {
   p->operator_storage = SMG_STORE_F32;
   p->split_chirality = 0;
   p->coarsest_fp64 = 1;
+  p->remass_affine = 0;
+  p->nv_stop_rho = 0.0;
+  p->nv_stop_iters = 3;
 }
 
 int smg_setup(const double* gauge, const smg_params* params, const double* randoms, void* stream,
@@ -1666,12 +1771,14 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
     for (int l = 1; l < c->nlev; ++l) cgmax = std::max(cgmax, c->L64[l].n);
     if (cgmax) alloc_kvecs<double>(tmp, c->c64, cgmax);
     for (int l = 0; l + 1 < c->nlev; ++l) {
-      const size_t n = c->L64[l].n;
+      // n is shorter than the planned length when the level above kept fewer vectors
+      // (nv_stop_rho): then the leading n entries of each given row are used
+      const size_t n = c->L64[l].n, np = c->n_plan[l];
       const int nv = c->prm.nv[l];
       z64* rnd = tmp.alloc<z64>((1 + (size_t)nv) * n);
       if (randoms) {
-        HIPCHECK(hipMemcpyAsync(rnd, (const z64*)randoms + level_offset_randoms(*c, l, true),
-                                (1 + (size_t)nv) * n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpy2DAsync(rnd, n * sizeof(z64), (const z64*)randoms + level_offset_randoms(*c, l, true),
+                                  np * sizeof(z64), n * sizeof(z64), 1 + (size_t)nv, hipMemcpyDeviceToDevice, st));
       } else {
         for (int row = 0; row <= nv; ++row)
           launch_random_gaussian(rnd + (size_t)row * n, n, c->prm.seed, (uint64_t)l * 4096 + row, st);
@@ -1681,6 +1788,7 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
       sa_weight(*c, l);
       adaptive_level(*c, l, rnd);
     }
+    build_mass_coefficients(*c);
     finish_setup(*c);
     c->c64 = KVecs<double>{};
   } catch (...) {
@@ -1712,6 +1820,7 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
       set_nc(*c, l, nv * cols_per_vector(c->prm));
       galerkin(*c, l);
     }
+    build_mass_coefficients(*c);
     finish_setup(*c);
   } catch (...) {
     delete c;
@@ -1729,9 +1838,14 @@ int smg_set_mass(smg_handle h, double mass, void* stream) {
   c->st = (hipStream_t)stream;
   c->prm.mass = mass;
   c->L64[0].diag = 2.0 + mass;
-  for (int l = 0; l + 1 < c->nlev; ++l) {
-    calibrate(*c, l);
-    galerkin(*c, l);
+  if (!c->C0.empty()) {
+    affine_links(*c, *c, mass);
+    for (int l = 0; l + 1 < c->nlev; ++l) calibrate(*c, l);
+  } else {
+    for (int l = 0; l + 1 < c->nlev; ++l) {
+      calibrate(*c, l);
+      galerkin(*c, l);
+    }
   }
   finish_setup(*c);
   return SMG_OK;
@@ -1751,7 +1865,7 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
   prm.mass = mass;
   Ctx* c = create(nullptr, &prm, st, src->U64);
   try {
-    reserve_setup(*c);
+    reserve_setup(*c, false);  // a derived handle keeps no mass coefficients of its own
     for (int l = 0; l + 1 < c->nlev; ++l) {
       auto& a = src->L64[l];
       auto& b = c->L64[l];
@@ -1764,10 +1878,15 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
       b.sa_w = a.sa_w;
       HIPCHECK(hipMemcpyAsync(c->calib[l], src->calib[l], a.n * sizeof(z64), hipMemcpyDeviceToDevice, st));
     }
-    for (int l = 0; l + 1 < c->nlev; ++l) {
-      set_nc(*c, l, c->prm.nv[l] * cols_per_vector(c->prm));
-      calibrate(*c, l);
-      galerkin(*c, l);
+    for (int l = 0; l + 1 < c->nlev; ++l) set_nc(*c, l, src->L64[l].nc);  // what the source's setup kept
+    if (!src->C0.empty()) {
+      affine_links(*c, *src, mass);
+      for (int l = 0; l + 1 < c->nlev; ++l) calibrate(*c, l);
+    } else {
+      for (int l = 0; l + 1 < c->nlev; ++l) {
+        calibrate(*c, l);
+        galerkin(*c, l);
+      }
     }
     finish_setup(*c);
   } catch (...) {
@@ -2074,9 +2193,12 @@ int smg_get_prolongator(smg_handle h, int32_t level, int32_t smoothed, double* o
   if (!out) throw Error(SMG_EINVAL, "null output");
   auto& a = c->L64[level];
   const int hh = smoothed ? a.halo : 0;
-  const size_t np = (size_t)(a.lx / a.bx) * (a.lt / a.bt) * a.ldk * (a.bx + 2 * hh) * (a.bt + 2 * hh) * a.dof;
-  HIPCHECK(hipMemcpyAsync(out, smoothed ? a.P : a.Pt, np * sizeof(z64), hipMemcpyDeviceToDevice,
-                          (hipStream_t)stream));
+  // the device keeps ldk column slots per aggregate; the first nc are in use (fewer
+  // than ldk when the adaptive stop kept fewer vectors)
+  const size_t nJ = (size_t)(a.lx / a.bx) * (a.lt / a.bt);
+  const size_t nw = (size_t)(a.bx + 2 * hh) * (a.bt + 2 * hh) * a.dof;
+  HIPCHECK(hipMemcpy2DAsync(out, a.nc * nw * sizeof(z64), smoothed ? a.P : a.Pt, a.ldk * nw * sizeof(z64),
+                            a.nc * nw * sizeof(z64), nJ, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
   return SMG_OK;
   API_END
@@ -2102,6 +2224,18 @@ int smg_get_coarse_links(smg_handle h, int32_t level, double* out, void* stream)
   auto& a = c->L64[level];
   launch_links_export(a.L, (z64*)out, a.lx * a.lt, a.dof, (hipStream_t)stream);
   HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  return SMG_OK;
+  API_END
+}
+
+int smg_get_setup_factors(smg_handle h, int32_t level, double* out, int32_t cap, int32_t* count) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  const auto& f = c->factors[level];
+  if (count) *count = (int32_t)f.size();
+  if (out)
+    for (int k = 0; k < std::min<int>(cap, (int)f.size()); ++k) out[k] = f[k];
   return SMG_OK;
   API_END
 }

@@ -42,7 +42,8 @@ def c_layout():
         "smg_params": ["lx", "lt", "mass", "levels", "block", "nv", "setup_iters", "smoother_steps",
                        "smoother_omega", "t_antiperiodic", "coarsest", "coarsest_tol", "coarsest_maxiter",
                        "inner_tol", "seed", "sa_scale", "smoother_storage", "stop_recursive", "mfma_min_rhs",
-                       "operator_storage", "split_chirality", "coarsest_fp64"],
+                       "operator_storage", "split_chirality", "coarsest_fp64", "remass_affine",
+                       "nv_stop_rho", "nv_stop_iters"],
         "smg_stats": ["status", "iterations", "refinements", "vcycles", "fine_applies", "true_relres", "seconds"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {", 'printf("{");']

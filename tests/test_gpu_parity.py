@@ -289,6 +289,57 @@ def test_set_mass_rebuilds_coarse_operators(pair):
         s.set_mass(pair["m"])
 
 
+@pytest.mark.parametrize("split", [False, True])
+def test_affine_remass_equals_galerkin(cuda, split):
+    """remass_affine: the setup keeps the mass coefficients C0, C1, C2 of every coarse
+    operator (C0 = P^H P is not I for the smoothed P), and smg_derive / smg_set_mass
+    form A^(l)(m) = C2 + m C1 + m^2 C0 in one pass.  Every level equals the oracle's
+    Galerkin rebuild at the new mass (set_mass) and the GPU's own Eq. 2 rebuild within
+    1e-12; the smoothers match; the setup handle's own links are those of a setup
+    without coefficients, bit for bit; MG-CG on the derived handle reaches 1e-10."""
+    smg = smg_mod()
+    lx = lt = 32
+    blocks, nvs, m, m2 = [(4, 4), (2, 2)], [4, 3], 0.05, 0.21
+    U = field(lx, lt, seed=81)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, 82, split)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=SA, split=split)
+    h2 = mg.set_mass(h, normal_matrix(U, m2), calib, 4, 0.8)
+    vv, cc = dev(np.concatenate([v.ravel() for v in vecs])), dev(np.concatenate(calib))
+    out = {}
+    for aff in (True, False):
+        p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, sa_scale=SA, split_chirality=split,
+                            remass_affine=aff)
+        out[aff] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    try:
+        for l in (1, 2):
+            assert np.array_equal(host(out[True].coarse_links(l)), host(out[False].coarse_links(l)))
+        d_aff, d_gal = out[True].derive(m2), out[False].derive(m2)
+        try:
+            for l in (1, 2):
+                cx, ct, nc = d_aff.level_info(l)
+                la, lg = host(d_aff.coarse_links(l)), host(d_gal.coarse_links(l))
+                assert rel_err(la, lg) <= 1e-12
+                assert rel_err(dense_from_links(la, cx, ct, nc), h2.levels[l].A.toarray()) <= 1e-12
+            for l in (0, 1):
+                np.testing.assert_allclose(d_aff.smoother_coefs(l), h2.levels[l].coefs, rtol=1e-12)
+            rhs = dirac_matrix(U, m2).conj().T @ synth.gaussian(2 * lx * lt, 83)
+            x, st, code = d_aff.solve(dev(rhs), tol=1e-10, precision=smg.MIXED)
+            assert code == 0
+            assert np.linalg.norm(rhs - normal_matrix(U, m2) @ host(x)) / np.linalg.norm(rhs) <= 1e-10
+        finally:
+            d_aff.close()
+            d_gal.close()
+        out[True].set_mass(m2)
+        for l in (1, 2):
+            cx, ct, nc = out[True].level_info(l)
+            assert rel_err(dense_from_links(host(out[True].coarse_links(l)), cx, ct, nc),
+                           h2.levels[l].A.toarray()) <= 1e-12
+    finally:
+        for s in out.values():
+            s.close()
+
+
 # ---------------------------------------------------------------------------
 # Adaptive setup and the c1 workload (32^2, beta 3, m 0.1, 2 levels, Nv 8)
 # ---------------------------------------------------------------------------
@@ -377,6 +428,56 @@ def test_adaptive_setup_split_chirality(cuda):
         if prec == smg.FP64:
             assert abs(st[0]["iterations"] - io.iterations) <= 1
     s.close()
+
+
+def test_adaptive_nv_stop_matches_oracle(cuda):
+    """Adaptive number of vectors: the oracle's full setup gives the two-level factor
+    per vector count; with a threshold across its largest drop, the GPU's setup and the
+    oracle's stop at the same count (the next level's variables per site), measure the
+    same factors (within 1e-8: the GPU's coarse solve is CG to 1e-12), build the same
+    per-aggregate projectors on both coarsenings (1e-8), and the MG-CG solve on the
+    shortened hierarchy reaches 1e-10 within one iteration of the oracle's."""
+    smg = smg_mod()
+    lx = lt = 32
+    m = 0.05
+    blocks, nvs = [(4, 4), (2, 2)], [8, 4]
+    U = field(lx, lt, seed=94, sweeps=20)
+    A = normal_matrix(U, m)
+    R = synth.setup_randoms(lx, lt, blocks, nvs, 7)
+    kw = dict(nu=2, omega=0.8, setup_iters=3, sa_scale=SA)
+    full = []
+    mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, log=full, nv_stop_rho=1e-300, **kw)
+    f = full[0]["factors"]
+    i = max(range(1, 6), key=lambda j: f[j - 1] / f[j])
+    thr = math.sqrt(f[i] * f[i - 1])
+    log = []
+    h = mg.adaptive_setup(A, (lx, lt, 2), blocks, nvs, R, log=log, nv_stop_rho=thr, **kw)
+    k = log[0]["nv"]
+    assert k == i + 1 < nvs[0]
+    p = smg.make_params(lx, lt, m, levels=3, blocks=blocks, nv=nvs, setup_iters=3, smoother_steps=2,
+                        sa_scale=SA, nv_stop_rho=thr)
+    with smg.Solver(dev(U), p, randoms=dev(np.concatenate([r.ravel() for r in R]))) as s:
+        assert s.level_info(1) == (8, 8, k)
+        assert s.level_info(2) == h.levels[2].shape
+        for l in range(2):
+            np.testing.assert_allclose(s.setup_factors(l), log[l]["factors"], rtol=1e-8)
+            Pg = host(s.prolongator(l))
+            Po = h.levels[l].U
+            assert Pg.shape == Po.shape
+            proj_g = np.einsum("jki,jkl->jil", Pg, Pg.conj())
+            proj_o = np.einsum("jki,jkl->jil", Po, Po.conj())
+            assert np.max(np.abs(proj_g - proj_o)) <= 1e-8, l
+        rhs = dirac_matrix(U, m).conj().T @ synth.gaussian(2 * lx * lt, 95)
+        _, io = mg.mg_cg(h, rhs, 1e-10)
+        x, st, code = s.solve(dev(rhs), tol=1e-10, precision=smg.FP64)
+        assert code == 0
+        assert np.linalg.norm(rhs - A @ host(x)) / np.linalg.norm(rhs) <= 1e-10
+        assert abs(st[0]["iterations"] - io.iterations) <= 1
+        # a mass derived from the shortened hierarchy keeps its shape
+        with s.derive(m + 0.1) as d:
+            assert d.level_info(1) == (8, 8, k)
+            x, st, code = d.solve(dev(rhs), tol=1e-10, precision=smg.MIXED)
+            assert code == 0
 
 
 def test_batch_invariance_and_edge_cases(cuda):
