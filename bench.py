@@ -54,9 +54,17 @@ SERVE_FIELDS_PER_SIZE = 8
 SERVE_SWEEPS = 200
 SERVE_MASSES = {3.0: [0.02, 0.05, 0.1, 0.2], 6.0: [0.01, 0.03, 0.06, 0.1], 10.0: [0.005, 0.02, 0.05, 0.1]}
 SERVE_NV = 8
-# Mixed solves of every leg store the FP32 V-cycle's operators (coarse links on the
-# vector-ALU path, prolongators, coarsest dense inverse) in FP16 (smg.STORE_F16).
+# Mixed solves of the serving and chirality legs store the FP32 V-cycle's operators
+# (coarse links on the vector-ALU path, prolongators, coarsest dense inverse) in FP16
+# (smg.STORE_F16).
 OPERATOR_STORAGE = 2
+# Mixed-precision variants of the headline, on the same systems:
+# (name, operator_storage, coarsest_fp64).  The first gives `value`.
+VARIANTS = [
+    ("f16_ops_f16_coarsest", 2, False),   # FP16 copies of links, P and the coarsest inverse
+    ("f16_ops_fp64_coarsest", 2, True),   # FP16 links and P, the coarsest inverse applied in FP64
+    ("f32_ops_fp64_coarsest", 0, True),   # FP32 operators, FP64 coarsest solve (the configuration as stated)
+]
 SERVE_BUDGET = 200 * 10**9
 SERVE_CAPACITY = 16
 
@@ -95,45 +103,84 @@ def make_field(seed):
 # CPU baseline: the FP64 oracle on a bounded sample (child process, one thread)
 # ---------------------------------------------------------------------------
 
+C1 = dict(L=32, beta=3.0, sweeps=200, seed=1000, mass=0.1, b_seed=0, blocks=[(4, 4)], nv=[8], rnd_seed=1)
+
+
 def cpu_baseline_leg():
-    """Oracle MG-CG on field 2000: adaptive setup at the lightest mass (not in the
-    rate), then solves at the lightest and the heaviest mass (timed).  Waits for a
-    line on stdin first, so that it does not share the host with the GPU legs whose
-    rates are the headline; returns None at end of input without one."""
+    """The FP64 oracle on the host (child process; it waits for "go" on stdin so that
+    it does not share the host with the GPU legs timed before it).
+
+    * The precision configuration, one field in full (field 2000): the adaptive setup
+      at its lightest mass, then for each of its 5 masses the re-mass (set_mass) and the
+      MG-CG solve, with BLAS on every host core; then the same 5 solves again with BLAS
+      on one thread (threadpoolctl).  The sparse products are single-threaded either way.
+    * The plain-method configuration (32^2, beta 3, m 0.1, 2 levels, CG coarsest):
+      setup and solve.
+    Returns None at end of input without "go"."""
     if sys.stdin.readline().strip() != "go":
         return None
-    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import synth
     from oracle import multigrid as mg
     from oracle.wilson import dirac_matrix, normal_matrix
 
+    out = {}
+    # plain method (c1)
+    U1 = synth.links_from_angles(synth.metropolis_u1(C1["L"], C1["L"], C1["beta"], C1["sweeps"], C1["seed"]))
+    R1 = synth.setup_randoms(C1["L"], C1["L"], C1["blocks"], C1["nv"], C1["rnd_seed"])
+    A1 = normal_matrix(U1, C1["mass"])
+    t0 = time.perf_counter()
+    h1 = mg.adaptive_setup(A1, (C1["L"], C1["L"], 2), C1["blocks"], C1["nv"], R1, nu=NU, omega=OMEGA,
+                           setup_iters=SETUP_ITERS, coarsest="cg", sa_scale=SA_SCALE)
+    s1 = time.perf_counter() - t0
+    rhs1 = dirac_matrix(U1, C1["mass"]).conj().T @ synth.gaussian(2 * C1["L"] ** 2, C1["b_seed"])
+    t0 = time.perf_counter()
+    _, info1 = mg.mg_cg(h1, rhs1, TOL)
+    out["c1"] = dict(setup_s=s1, solve_s=time.perf_counter() - t0, iterations=info1.iterations,
+                     relres=info1.relres)
+    # precision configuration, field SEEDS[0] in full
     seed = SEEDS[0]
-    masses = load_masses()[seed]
+    masses = sorted(load_masses()[seed])
     U = make_field(seed)
-    m_light = min(masses)
+    m_light = masses[0]
     R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
     t0 = time.perf_counter()
     h = mg.adaptive_setup(normal_matrix(U, m_light), (L, L, 2), BLOCKS, NV, R, nu=NU, omega=OMEGA,
                           setup_iters=SETUP_ITERS, sa_scale=SA_SCALE)
     setup_s = time.perf_counter() - t0
     b = synth.gaussian(2 * L * L, 10000 * 2 + 0)
-    solve_s, iters, res = [], [], []
-    for m in (m_light, max(masses)):
+    hs, rhss, remass_s, solve_all, iters, res = [], [], [], [], [], []
+    for m in masses:
+        t0 = time.perf_counter()
         hm = h if m == m_light else mg.set_mass(h, normal_matrix(U, m), [r[0] for r in R], NU, OMEGA)
+        if m != m_light:
+            remass_s.append(time.perf_counter() - t0)
         rhs = dirac_matrix(U, m).conj().T @ b
         t0 = time.perf_counter()
-        x, info = mg.mg_cg(hm, rhs, TOL)
-        solve_s.append(time.perf_counter() - t0)
+        _, info = mg.mg_cg(hm, rhs, TOL)
+        solve_all.append(time.perf_counter() - t0)
         iters.append(info.iterations)
         res.append(info.relres)
-    return dict(setup_s=setup_s, solve_s=solve_s, iterations=iters, relres=res)
+        hs.append(hm)
+        rhss.append(rhs)
+    solve_one = []
+    with threadpool_limits(limits=1):
+        for hm, rhs in zip(hs, rhss):
+            t0 = time.perf_counter()
+            mg.mg_cg(hm, rhs, TOL)
+            solve_one.append(time.perf_counter() - t0)
+    blas_threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    out.update(setup_s=setup_s, remass_s=remass_s, solve_s=solve_all, solve_s_1thread=solve_one, iterations=iters,
+               relres=res, masses=masses, blas_threads=blas_threads, cores=len(os.sched_getaffinity(0)))
+    return out
 
 
 def start_cpu_baseline():
     # started before anything touches the GPU (a GPU process does not start programs);
-    # it waits for "go" on stdin
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    # it waits for "go" on stdin.  BLAS may use every core the process may run on.
+    ncores = str(len(os.sched_getaffinity(0)))
+    env = dict(os.environ, OMP_NUM_THREADS=ncores, OPENBLAS_NUM_THREADS=ncores, MKL_NUM_THREADS=ncores)
     return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-leg"], env=env,
                             stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
 
@@ -243,6 +290,46 @@ def mrhs_leg(args, torch, smg, dev, U):
                           f"and coarsest inverse, coarse links on the matrix cores"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
+
+
+def c1_leg(torch, smg, dev):
+    """The plain-method configuration on the GPU: 32^2, beta 3 (200 sweeps, seed 1000),
+    m = 0.1, b Gaussian (seed 0), rhs = D^H b, 2 levels of 4x4 with Nv = 8 from 5
+    adaptive setup iterations, nu = 4, coarsest CG to 1e-12, FP64 MG-CG to 1e-10.
+    Wall times of the setup and of the solve (the first call of each, and the median
+    of 5 after it)."""
+    import numpy as np
+
+    import synth
+
+    U = synth.links_from_angles(synth.metropolis_u1(C1["L"], C1["L"], C1["beta"], C1["sweeps"], C1["seed"]))
+    R = synth.setup_randoms(C1["L"], C1["L"], C1["blocks"], C1["nv"], C1["rnd_seed"])
+    p = smg.make_params(C1["L"], C1["L"], C1["mass"], levels=2, blocks=C1["blocks"], nv=C1["nv"],
+                        setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, coarsest=smg.COARSEST_CG,
+                        sa_scale=SA_SCALE)
+    g = torch.from_numpy(U).to(dev)
+    rnd = torch.from_numpy(np.concatenate([r.ravel() for r in R])).to(dev)
+    b = torch.from_numpy(synth.gaussian(2 * C1["L"] ** 2, C1["b_seed"])).to(dev)
+    setups, solves, st = [], [], None
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = smg.Solver(g, p, randoms=rnd)
+        torch.cuda.synchronize()
+        setups.append(time.perf_counter() - t0)
+        rhs = s.apply_D(b, dagger=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, code = s.solve(rhs, tol=TOL, maxiter=500, precision=smg.FP64)
+        torch.cuda.synchronize()
+        solves.append(time.perf_counter() - t0)
+        if code != 0:
+            raise RuntimeError(f"c1 solve did not converge: {st[0]}")
+        s.close()
+    return dict(workload="32x32 U(1) beta=3 (200 sweeps, seed 1000), m=0.1, 2 levels 4x4, Nv=8, nu=4, coarsest CG "
+                         "1e-12, FP64 MG-CG to 1e-10, one Gaussian RHS",
+                gpu_setup_s_first=setups[0], gpu_setup_s=sorted(setups[1:])[2], gpu_solve_s_first=solves[0],
+                gpu_solve_s=sorted(solves[1:])[2], iterations=st[0]["iterations"], relres=st[0]["true_relres"])
 
 
 def serving_leg(args, torch, smg, dev):
@@ -415,7 +502,7 @@ def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
     y = torch.empty_like(v)
     px, py = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr())
     dur = timed_graph(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
-    h16 = OPERATOR_STORAGE == smg.STORE_F16
+    h16 = s.params.operator_storage == smg.STORE_F16
     nbytes = 9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8
     gbs = nbytes / dur / 1e9
     q = (nc + 3) // 4
@@ -461,6 +548,39 @@ def kernel_probe(reps):
         torch.add(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(json.dumps(dict(roofline=roof, copy_read_bytes=a.numel() * 4, copy_write_bytes=b.numel() * 4)))
+
+
+def dslash_probe(Ld, reps):
+    """Launch only the fine FP64 A = D^H D at Ld^2 (single RHS) and a plain FP32
+    elementwise kernel reading and writing 64 MiB each (the counters' calibration),
+    for kernel-trace and counter runs; prints the event-timed rate."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_0710_3612_amd as smg
+    import synth
+
+    dev = torch.device("cuda:0")
+    th = np.random.default_rng(5000 + Ld).uniform(-math.pi, math.pi, size=(2, Ld, Ld))
+    s = smg.Solver(torch.from_numpy(np.exp(1j * th)).to(dev), smg.make_params(Ld, Ld, 0.01, levels=1))
+    x = torch.from_numpy(synth.gaussian(2 * Ld * Ld, 6)).to(dev)
+    y = torch.empty_like(x)
+    lib = smg.load_library()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    px, py = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())
+    dur = timed_events(lambda: lib.smg_apply_A(s.handle, px, py, 1, sp), reps, stream)
+    nbytes = Ld * Ld * 96
+    a = torch.ones(16 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.add(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(kernel="k_normal_fused FP64", L=Ld, avg_launch_us=dur * 1e6, bytes_per_launch=nbytes,
+                          achieved_GBps=nbytes / dur / 1e9, copy_read_bytes=a.numel() * 4,
+                          copy_write_bytes=b.numel() * 4)))
 
 
 def mfma_probe(reps):
@@ -514,6 +634,8 @@ def main():
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
     ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
+    ap.add_argument("--dslash-probe", type=int, default=0, metavar="L",
+                    help="only launch the fine FP64 A at L x L and a 64 MiB copy (for profiler runs)")
     ap.add_argument("--solves-only", action="store_true",
                     help="set up the precision workload, pause 1 s, run --steps mixed steps (for kernel traces)")
     ap.add_argument("--kernel-probe", action="store_true",
@@ -524,6 +646,9 @@ def main():
         return 0
     if args.mfma_probe:
         mfma_probe(args.dslash_reps)
+        return 0
+    if args.dslash_probe:
+        dslash_probe(args.dslash_probe, args.dslash_reps)
         return 0
 
     if args.cpu_baseline_leg:
@@ -577,35 +702,47 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(dev)
 
     # ---- setup (timed separately) ---------------------------------------------
-    systems = []     # (solver, rhs tensor)
-    setup_s, remass_s = [], []
-    keep = []
-    for seed, U in zip(SEEDS, fields):
-        ms = masses[seed]
-        m_light = min(ms)
-        p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=NV, setup_iters=SETUP_ITERS,
-                            smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE,
-                            operator_storage=OPERATOR_STORAGE)
-        R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
-        g = T(U)
-        rnd = T(np.concatenate([r.ravel() for r in R]))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s0 = smg.Solver(g, p, randoms=rnd)
-        torch.cuda.synchronize()
-        setup_s.append(time.perf_counter() - t0)
-        b = T(synth.gaussian(2 * L * L, 10000 * 2 + SEEDS.index(seed)))
-        keep.append(s0)
-        for m in ms:
-            t0 = time.perf_counter()
-            s = s0 if m == m_light else s0.derive(m)
+    # One hierarchy per field at its lightest mass (adaptive setup, mass coefficients
+    # kept), the heavier masses derived from it.  Every storage variant gets its own
+    # handles from the same random starts: the FP64 hierarchy is the same.
+    def build_systems(opst, c64, timing):
+        systems, keep = [], []
+        for seed, U in zip(SEEDS, fields):
+            ms = masses[seed]
+            m_light = min(ms)
+            p = smg.make_params(L, L, m_light, levels=3, blocks=BLOCKS, nv=NV, setup_iters=SETUP_ITERS,
+                                smoother_steps=NU, smoother_omega=OMEGA, seed=seed, sa_scale=SA_SCALE,
+                                operator_storage=opst, coarsest_fp64=c64, remass_affine=True)
+            R = synth.setup_randoms(L, L, BLOCKS, NV, seed)
+            g = T(U)
+            rnd = T(np.concatenate([r.ravel() for r in R]))
             torch.cuda.synchronize()
-            if m != m_light:
-                remass_s.append(time.perf_counter() - t0)
-            rhs = s.apply_D(b, dagger=True)
-            systems.append((s, rhs, seed, m))
-            keep.append(s)
-        log(f"field {seed}: setup {setup_s[-1]:.2f}s")
+            t0 = time.perf_counter()
+            s0 = smg.Solver(g, p, randoms=rnd)
+            torch.cuda.synchronize()
+            if timing is not None:
+                timing["setup"].append(time.perf_counter() - t0)
+            b = T(synth.gaussian(2 * L * L, 10000 * 2 + SEEDS.index(seed)))
+            keep.append(s0)
+            for m in ms:
+                t0 = time.perf_counter()
+                s = s0 if m == m_light else s0.derive(m)
+                torch.cuda.synchronize()
+                if m != m_light and timing is not None:
+                    timing["remass"].append(time.perf_counter() - t0)
+                rhs = s.apply_D(b, dagger=True)
+                systems.append((s, rhs, seed, m))
+                if s is not s0:
+                    keep.append(s)
+        return systems, keep
+
+    timing = dict(setup=[], remass=[])
+    variant_systems = {}
+    for name, opst, c64 in VARIANTS:
+        variant_systems[name] = build_systems(opst, c64, timing if not variant_systems else None)
+        log(f"variant {name}: {len(variant_systems[name][0])} systems")
+    systems = variant_systems[VARIANTS[0][0]][0]
+    setup_s, remass_s = timing["setup"], timing["remass"]
     xs = [torch.empty_like(rhs) for _, rhs, _, _ in systems]
 
     # The systems are independent: worker threads, each with its own stream, keep
@@ -616,10 +753,10 @@ def main():
     streams = [torch.cuda.Stream(dev) for _ in range(nwork)]
     torch.cuda.synchronize()
 
-    def run_share(w, prec, rec):
+    def run_share(w, syss, prec, rec):
         with torch.cuda.stream(streams[w]):
-            for k in range(w, len(systems), nwork):
-                s, rhs, seed, m = systems[k]
+            for k in range(w, len(syss), nwork):
+                s, rhs, seed, m = syss[k]
                 x, st, code = s.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=xs[k], stream=streams[w])
                 if code != 0 or st[0]["true_relres"] > TOL:
                     raise RuntimeError(f"solve did not converge: field {seed} mass {m} {st[0]}")
@@ -630,41 +767,51 @@ def main():
 
     pool = ThreadPoolExecutor(max_workers=nwork)
 
-    def step(prec, rec=None):
-        futs = [pool.submit(run_share, w, prec, rec) for w in range(nwork)]
+    def step(syss, prec, rec=None):
+        futs = [pool.submit(run_share, w, syss, prec, rec) for w in range(nwork)]
         for f in futs:
             f.result()
 
     if args.solves_only:
-        step(smg.MIXED)
+        step(systems, smg.MIXED)
         torch.cuda.synchronize()
         time.sleep(1.0)  # an idle gap that separates setup from the steps in a kernel trace
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(smg.MIXED)
+            step(systems, smg.MIXED)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         pool.shutdown()
         print(json.dumps(dict(solves_per_s=len(systems) * args.steps / dt, steps=args.steps, streams=nwork)))
         return 0
 
-    results = {}
-    for name, prec in (("mixed", smg.MIXED), ("fp64", smg.FP64)):
+    def timed(syss, prec):
         rec = []
-        step(prec, rec)                       # also the first warmup
+        step(syss, prec, rec)                       # also the first warmup
         for _ in range(max(args.warmup - 1, 0)):
-            step(prec)
+            step(syss, prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(prec)
+            step(syss, prec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        results[name] = dict(seconds=dt, solves=len(systems) * args.steps, records=rec)
-        log(f"{name}: {len(systems) * args.steps / dt:.1f} solves/s")
-    if cpu_proc is not None:  # the headline rates are taken: the oracle may use its core now
+        return dict(seconds=dt, solves=len(syss) * args.steps, records=rec)
+
+    results = {}
+    for name, _opst, _c64 in VARIANTS:
+        results[name] = timed(variant_systems[name][0], smg.MIXED)
+        log(f"mixed {name}: {results[name]['solves'] / results[name]['seconds']:.1f} solves/s")
+    results["fp64"] = timed(systems, smg.FP64)
+    log(f"fp64: {results['fp64']['solves'] / results['fp64']['seconds']:.1f} solves/s")
+    if cpu_proc is not None:  # the headline rates are taken: the oracle may use the host now
         cpu_proc.stdin.write("go\n")
         cpu_proc.stdin.flush()
+    for name, _opst, _c64 in VARIANTS[1:]:
+        for s_ in variant_systems[name][1]:
+            s_.close()
+        variant_systems[name] = None
+    results["mixed"] = results[VARIANTS[0][0]]
 
     # ---- chirality-split aggregates on the same systems: Nv = 6 candidates per level, each
     # block split by chirality, so the coarse levels carry 12 variables per site as above
@@ -752,31 +899,51 @@ def main():
     dslash_4096 = dslash(2 * DSLASH_L)
     n_systems = len(systems)
     del systems, xs, s
-    for s_ in keep:
+    for s_ in variant_systems[VARIANTS[0][0]][1]:
         s_.close()
-    keep.clear()
+    variant_systems.clear()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    c1 = c1_leg(torch, smg, dev)
     mrhs = None if args.no_mrhs else mrhs_leg(args, torch, smg, dev, mrhs_U)
-    serving = None if args.no_serve else serving_leg(args, torch, smg, dev)
 
     cpu = None
-    if cpu_proc is not None:
+    if cpu_proc is not None:  # waits for the oracle before the serving leg loads the host
         out, err = cpu_proc.communicate(timeout=1800)  # also closes its stdin
         if cpu_proc.returncode == 0:
             leg = json.loads(out.strip().splitlines()[-1])
-            per_solve = sum(leg["solve_s"]) / len(leg["solve_s"])
-            cpu = dict(value=1.0 / per_solve, unit="solves/s", cores=1, kind="oracle",
-                       sample=(f"FP64 oracle (scipy sparse, 1 thread, {cpu_model()}) MG-CG on field {SEEDS[0]} at its "
-                               f"lightest and heaviest mass ({len(leg['solve_s'])} solves, "
-                               f"{sum(leg['solve_s']):.1f}s); its adaptive setup took {leg['setup_s']:.1f}s "
-                               f"(not in the rate); iterations {leg['iterations']}"))
+            n_s = len(leg["solve_s"])
+            cpu = dict(value=n_s / sum(leg["solve_s"]), unit="solves/s", cores=leg["cores"], kind="oracle",
+                       sample=(f"FP64 oracle (numpy/scipy; sparse products single-threaded, BLAS on "
+                               f"{leg['blas_threads']} threads; {cpu_model()}, {leg['cores']} cores): field "
+                               f"{SEEDS[0]} of the precision workload in full, MG-CG at its {n_s} masses "
+                               f"({sum(leg['solve_s']):.1f}s of solves, iterations {leg['iterations']}); the adaptive "
+                               f"setup ({leg['setup_s']:.1f}s) and the {len(leg['remass_s'])} re-masses "
+                               f"({sum(leg['remass_s']):.1f}s) are not in the rate"),
+                       single_thread_solves_per_s=n_s / sum(leg["solve_s_1thread"]),
+                       setup_s=leg["setup_s"], remass_s=leg["remass_s"],
+                       field_s=leg["setup_s"] + sum(leg["remass_s"]) + sum(leg["solve_s"]),
+                       max_relres=max(leg["relres"]), cpu_model=cpu_model(), c1=leg["c1"])
+            if c1 is not None:
+                c1["oracle"] = leg["c1"]
         else:
             log("cpu baseline failed: " + err[-2000:])
+    serving = None if args.no_serve else serving_leg(args, torch, smg, dev)
 
     mixed = results["mixed"]
     fp64 = results["fp64"]
     value = mixed["solves"] / mixed["seconds"]
+
+    def rate(r):
+        return r["solves"] / r["seconds"]
+
+    variants = {name: dict(operator_storage="f16" if opst == 2 else "f32",
+                           coarsest="fp64 inverse" if c64 else ("fp16 copy" if opst == 2 else "fp32 copy"),
+                           solves_per_s=rate(results[name]), over_fp64=rate(results[name]) / rate(fp64),
+                           mean_iterations=sum(q["iterations"] for q in results[name]["records"])
+                           / len(results[name]["records"]),
+                           max_relres=max(q["relres"] for q in results[name]["records"]))
+                for name, opst, c64 in VARIANTS}
     line = {
         "metric": "MG solves/s to 1e-10 residual (mixed vs FP64); D†D HBM GB/s; p99 latency",
         "value": value,
@@ -788,12 +955,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 inner (f16 operator storage) / f64 outer",
+        "dtype": f"f32 inner ({variants[VARIANTS[0][0]]['operator_storage']} operator storage, coarsest "
+                 f"{variants[VARIANTS[0][0]]['coarsest']}) / f64 outer",
         "data": "synthetic",
         "config": {
             "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
-                        "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG with "
-                        "FP16-stored coarse links, prolongators and coarsest inverse inside FP64 defect correction",
+                        "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG inside "
+                        f"FP64 defect correction, variant {VARIANTS[0][0]} (others in mixed_variants)",
+            "mixed_variants": variants,
             "systems_per_step": n_systems,
             "concurrent_streams": nwork,
             "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
@@ -808,6 +977,7 @@ def main():
         "dslash": dslash_2048,
         "dslash_4096": dslash_4096,
         "cpu_baseline": cpu,
+        "plain_method_c1": c1,
         "multi_rhs": mrhs,
         "serving": serving,
         "chirality_split": split,

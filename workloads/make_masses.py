@@ -18,8 +18,8 @@ D takes most of a minute and some near-critical ones far longer), so the target 
 reached from a starting mass by secant steps on sigma_min(D) = sqrt(lambda_min(A)),
 which moves almost linearly with m away from m_crit; m* is not searched there.
 
-Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 128_beta6 | 128_beta10 | 128_beta6_cold |
-       128_beta10_cold]
+Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 512_beta6_s3000 | 128_beta6 | 128_beta10 |
+       128_beta6_cold | 128_beta10_cold]
        (writes workloads/masses_<name>.json)
 """
 
@@ -49,6 +49,8 @@ CONFIGS = {
     "256_beta6": dict(L=256, beta=6.0, sweeps=500, seeds=[2000, 2001, 2002, 2003],
                       ratios=[1e-2, 3e-3, 1e-3, 3e-4, 1e-4]),
     "512_beta6": dict(L=512, beta=6.0, sweeps=500, seeds=[5000], ratios=[1e-3], start=0.065),
+    # the multi-RHS configuration as stated: field seed 3000, ratio 1e-4
+    "512_beta6_s3000": dict(L=512, beta=6.0, sweeps=500, seeds=[3000], ratios=[1e-4], start=0.0),
     # the paper's 128^2 experiment: m_crit (= m*) of candidate fields, picked by topological charge
     "128_beta6": dict(L=128, beta=6.0, sweeps=1000, seeds=list(range(7000, 7008)), ratios=[]),
     "128_beta10": dict(L=128, beta=10.0, sweeps=1000, seeds=list(range(7100, 7108)), ratios=[]),
