@@ -45,15 +45,19 @@ SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
 
-# Serving workload: Poisson stream of requests over 8 seeded fields per lattice size,
-# beta cycling over the fields, 4 masses per beta, 1-16 Gaussian right-hand sides,
-# admission under a 200 GB HBM budget.
+# Serving workload: Poisson streams of 2000 requests over 8 seeded fields per (lattice
+# size, beta), sizes 64..512^2, beta 3, 6, 10 (500 sweeps, beta 10: 1000), masses
+# m_c(beta) + {0.1, 0.05, 0.02, 0.01} with m_c(beta) the median m_crit of sampled 128^2
+# fields of that beta, 1-16 Gaussian right-hand sides per request, every field's
+# hierarchy 3 levels of 4x4 with Nv = 12 (the precision configuration's), admission
+# under a 200 GB HBM budget.
 SERVE_SIZES = [64, 128, 256, 512]
 SERVE_BETAS = [3.0, 6.0, 10.0]
-SERVE_FIELDS_PER_SIZE = 8
-SERVE_SWEEPS = 200
-SERVE_MASSES = {3.0: [0.02, 0.05, 0.1, 0.2], 6.0: [0.01, 0.03, 0.06, 0.1], 10.0: [0.005, 0.02, 0.05, 0.1]}
-SERVE_NV = 8
+SERVE_FIELDS = 8                       # per (size, beta)
+SERVE_SWEEPS = {3.0: 500, 6.0: 500, 10.0: 1000}
+SERVE_GAPS = [0.1, 0.05, 0.02, 0.01]
+SERVE_NV = 12
+SERVE_LOADS = [0.7]                    # offered load / saturation (--serve-full: 0.5, 0.7, 0.9 and a cold run)
 # Mixed solves of the serving and chirality legs store the FP32 V-cycle's operators
 # (coarse links on the vector-ALU path, prolongators, coarsest dense inverse) in FP16
 # (smg.STORE_F16).
@@ -69,12 +73,12 @@ SERVE_BUDGET = 200 * 10**9
 SERVE_CAPACITY = 16
 
 # Multi-RHS workload: 32 Z2-noise sources on one 512x512 field at beta = 6 (500
-# sweeps, seed 5000) at the mass where lambda_min(A)/lambda_max(A) = 1e-3, 3 levels of
+# sweeps, seed 3000) at the mass where lambda_min(A)/lambda_max(A) = 1e-4, 3 levels of
 # 4x4 aggregates with Nv = 16 (coarse links 16x16 on the matrix cores, dense inverse
-# of the 16384-variable coarsest operator, BF16 storage of the fine smoother iterates
-# and FP16 storage of the prolongators and coarsest inverse in the mixed solve).
+# of the 16384-variable coarsest operator applied in FP64, BF16 storage of the fine
+# smoother iterates and FP16 storage of the prolongators in the mixed solve).
 MRHS_L = 512
-MRHS_SEED = 5000
+MRHS_SEED = 3000
 MRHS_NRHS = 32
 MRHS_NV = [16, 16]
 
@@ -199,11 +203,14 @@ def cpu_model():
 # GPU
 # ---------------------------------------------------------------------------
 
-def serve_field(spec):
-    import synth
+def serve_mcrit(beta):
+    """Median m_crit (the mass minimising lambda_min(A)) of the sampled 128^2 fields of
+    this beta (workloads/masses_128_beta*.json, found offline with the oracle)."""
+    import statistics
 
-    L, beta, seed = spec
-    return synth.links_from_angles(synth.metropolis_u1(L, L, beta, SERVE_SWEEPS, seed))
+    with open(os.path.join(ROOT, "workloads", f"masses_128_beta{int(beta)}.json")) as f:
+        data = json.load(f)
+    return statistics.median(fld["m_star"] for fld in data["fields"])
 
 
 def mrhs_field(_=None):
@@ -213,7 +220,7 @@ def mrhs_field(_=None):
 
 
 def mrhs_mass():
-    with open(os.path.join(ROOT, "workloads", "masses_512_beta6.json")) as f:
+    with open(os.path.join(ROOT, "workloads", "masses_512_beta6_s3000.json")) as f:
         data = json.load(f)
     fld = data["fields"][0]
     assert fld["L"] == MRHS_L and fld["seed"] == MRHS_SEED and fld["sweeps"] == SWEEPS
@@ -241,7 +248,7 @@ def mrhs_leg(args, torch, smg, dev, U):
     s = smg.Solver(g, p)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    eta = torch.from_numpy(synth.z2_noise((MRHS_NRHS, n), MRHS_SEED + 1)).to(dev)
+    eta = torch.from_numpy(synth.z2_noise((MRHS_NRHS, n), 10 * MRHS_SEED)).to(dev)
     rhs = s.apply_D(eta, dagger=True)
     x = torch.empty_like(rhs)
     torch.cuda.synchronize()
@@ -286,8 +293,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     return dict(workload=(f"{MRHS_L}x{MRHS_L} U(1) beta={BETA:g} ({SWEEPS} sweeps, seed {MRHS_SEED}), mass {mass:.5f} "
                           f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
                           f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}; mixed: FP32 inner "
-                          f"MG-CG, BF16 storage of the fine smoother iterates, FP16 storage of the prolongators "
-                          f"and coarsest inverse, coarse links on the matrix cores"),
+                          f"MG-CG, BF16 storage of the fine smoother iterates, FP16 storage of the prolongators, "
+                          f"coarse links on the matrix cores, the coarsest inverse applied in FP64"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
 
@@ -333,79 +340,119 @@ def c1_leg(torch, smg, dev):
 
 
 def serving_leg(args, torch, smg, dev):
-    """The request loop on a warm setup cache; returns the serving summary."""
+    """The request loop (continuous batching over a setup cache): fields drawn on the
+    GPU, then a warm cache (every key that fits the budget built before the trace), the
+    saturation throughput (all requests arriving at once), the offered loads of
+    SERVE_LOADS times it, and with --serve-full a cold run (empty cache, setups inside
+    the trace) at 0.7 x saturation."""
     import numpy as np
-    from concurrent.futures import ProcessPoolExecutor
 
     import synth
     from paper_0710_3612_amd import serve
 
-    specs = [(L, SERVE_BETAS[i % len(SERVE_BETAS)], 3000 + 100 * si + i)
-             for si, L in enumerate(SERVE_SIZES) for i in range(SERVE_FIELDS_PER_SIZE)]
-    log(f"serving: generating {len(specs)} gauge fields")
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=16) as ex:
-        links = list(ex.map(serve_field, specs))
-    gen_s = time.perf_counter() - t0
-    fields, masses = {}, {}
-    for (L, beta, seed), U in zip(specs, links):
-        lv = serve.levels_for(L)
-        p = smg.make_params(L, L, 0.0, levels=lv, blocks=[(4, 4)] * (lv - 1), nv=[SERVE_NV] * (lv - 1),
-                            setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA, seed=seed,
-                            sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE)
-        fields[seed] = (torch.from_numpy(np.ascontiguousarray(U)).to(dev), p)
-        masses[seed] = SERVE_MASSES[beta]
+    fields, masses, sizes = {}, {}, {}
+    mc = {b: serve_mcrit(b) for b in SERVE_BETAS}
+    for si, Ls in enumerate(SERVE_SIZES):
+        for bi, beta in enumerate(SERVE_BETAS):
+            th = synth.metropolis_u1_device(Ls, Ls, beta, SERVE_SWEEPS[beta], 4000 + 100 * si + 10 * bi,
+                                            count=SERVE_FIELDS, device=dev)
+            for i in range(SERVE_FIELDS):
+                key = f"L{Ls}_b{int(beta)}_{i}"
+                ms = [round(mc[beta] + g, 6) for g in SERVE_GAPS]
+                p = smg.make_params(Ls, Ls, min(ms), levels=3, blocks=BLOCKS, nv=[SERVE_NV, SERVE_NV],
+                                    setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA,
+                                    seed=4000 + i, sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE,
+                                    remass_affine=True)
+                fields[key] = (torch.polar(torch.ones_like(th[i]), th[i]).contiguous(), p)
+                masses[key] = ms
+                sizes[key] = Ls
+            del th
     torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    log(f"serving: {len(fields)} fields on the GPU in {gen_s:.1f}s; m_c = {mc}")
     backend = serve.DeviceBackend(fields, mixed=True)
-    srv = serve.Server(backend, SERVE_BUDGET, capacity=SERVE_CAPACITY, tol=TOL, maxiter=2000,
-                       precision=smg.MIXED, max_lanes=args.serve_lanes)
     keys = [(f, m) for f in fields for m in masses[f]]
+
+    def run(srv, rate, seed, nreq):
+        trace = serve.poisson_trace(nreq, rate, list(fields), masses, (1, 16), seed=seed)
+        reqs = []
+        for i, (t, f, m, k, sd) in enumerate(trace):
+            n = 2 * sizes[f] ** 2
+            reqs.append(serve.Request(seed * 100000 + i, f, m,
+                                      (lambda n=n, sd=sd, k=k: synth.gaussian_device(n, sd, "cuda", k)), k, t))
+        if rate == math.inf:
+            for r in reqs:
+                r.arrival = 0.0
+        c0 = dict(setups=srv.cache.setups, derives=srv.cache.derives, evictions=srv.cache.evictions)
+        results = srv.run_trace(reqs, timeout=1800)
+        summ = serve.latency_summary(results)
+        bad = [r for r in results if not r.ok or max(r.true_relres) > TOL]
+        by_size = {}
+        for r in results:
+            by_size.setdefault(sizes[r.field], []).append(r)
+        summ.update(offered_rps=None if rate == math.inf else rate, failed=len(bad),
+                    first_failure=(None if not bad else f"{bad[0].error} {bad[0].status} {bad[0].true_relres}"),
+                    setups=srv.cache.setups - c0["setups"], derives=srv.cache.derives - c0["derives"],
+                    evictions=srv.cache.evictions - c0["evictions"], resident_gb=srv.cache.used / 1e9,
+                    mean_iterations=float(np.mean([i for r in results if r.ok for i in r.iterations])),
+                    max_relres=max((max(r.true_relres) for r in results if r.ok), default=None),
+                    p50_ms_by_size={str(k): serve.latency_summary(v)["p50_ms"] for k, v in sorted(by_size.items())},
+                    p99_ms_by_size={str(k): serve.latency_summary(v)["p99_ms"] for k, v in sorted(by_size.items())})
+        return summ
+
+    def server():
+        return serve.Server(backend, SERVE_BUDGET, capacity=SERVE_CAPACITY, tol=TOL, maxiter=2000,
+                            precision=smg.MIXED, max_lanes=args.serve_lanes)
+
+    # warm: the keys that fit the budget, small lattices first, each field's lightest mass first
+    srv = server()
+    order = sorted(keys, key=lambda k: (sizes[k[0]], k[0], k[1]))
+    warm_keys, used = [], 0
+    for f, m in order:
+        need = backend.estimate(f, SERVE_CAPACITY)
+        if used + need > 0.9 * SERVE_BUDGET:
+            break
+        warm_keys.append((f, m))
+        used += need
     t0 = time.perf_counter()
-    srv.warm(keys, workers=8)
+    srv.warm(warm_keys, workers=8)
     torch.cuda.synchronize()
     warm_s = time.perf_counter() - t0
-    log(f"serving: warmed {len(keys)} hierarchies in {warm_s:.1f}s ({srv.cache.used / 1e9:.1f} GB)")
-    trace = serve.poisson_trace(args.serve_requests, args.serve_rate, list(fields), masses, (1, 16), seed=7)
-    reqs = []
-    for i, (t, f, m, k, sd) in enumerate(trace):
-        n = 2 * fields[f][1].lx * fields[f][1].lt
-        reqs.append(serve.Request(i, f, m, (lambda n=n, sd=sd, k=k: synth.gaussian_device(n, sd, "cuda", k)), k, t))
-    results = srv.run_trace(reqs, timeout=1200)
-    summ = serve.latency_summary(results)
-    bad = [r for r in results if not r.ok or max(r.true_relres) > TOL]
-    if bad:
-        raise RuntimeError(f"{len(bad)} served requests failed, first: {bad[0].error} {bad[0].status} "
-                           f"{bad[0].true_relres}")
-    by_size = {}
-    for r in results:
-        L = fields[r.field][1].lx
-        by_size.setdefault(L, []).append(r)
-    iters = [i for r in results for i in r.iterations]
-    summ.update(
-        offered_rate_rps=args.serve_rate,
-        warm_s=warm_s,
-        field_generation_s=gen_s,
-        resident_gb=srv.cache.used / 1e9,
-        hierarchies=len(srv.cache.entries),
-        setups=srv.cache.setups,
-        derives=srv.cache.derives,
-        evictions=srv.cache.evictions,
-        lanes=args.serve_lanes,
-        lanes_started=srv.lanes_started,
-        mean_iterations=float(np.mean(iters)),
-        max_relres=max(max(r.true_relres) for r in results),
-        p50_ms_by_size={str(L): serve.latency_summary(rs)["p50_ms"] for L, rs in sorted(by_size.items())},
-        p99_ms_by_size={str(L): serve.latency_summary(rs)["p99_ms"] for L, rs in sorted(by_size.items())},
-        workload=(f"{args.serve_requests} Poisson requests at {args.serve_rate:g}/s over {len(fields)} fields "
-                  f"({'/'.join(map(str, SERVE_SIZES))}^2 x {SERVE_FIELDS_PER_SIZE}, beta 3/6/10, "
-                  f"{SERVE_SWEEPS} sweeps), 4 masses per beta, 1-16 Gaussian RHS each, 4x4 blocks, "
-                  f"Nv={SERVE_NV}, mixed precision, {SERVE_CAPACITY}-slot batches, "
-                  f"budget {SERVE_BUDGET / 1e9:.0f} GB, tol {TOL:g}"),
-    )
+    log(f"serving: warmed {len(warm_keys)} of {len(keys)} keys in {warm_s:.1f}s ({srv.cache.used / 1e9:.1f} GB)")
+    out = dict(workload=(f"{args.serve_requests} Poisson requests per run over {len(fields)} fields "
+                         f"({'/'.join(map(str, SERVE_SIZES))}^2 x beta 3/6/10 x {SERVE_FIELDS}, 500 sweeps, beta 10: "
+                         f"1000, drawn on the GPU), masses m_c(beta) + {SERVE_GAPS} with m_c = "
+                         f"{ {int(b): round(v, 4) for b, v in mc.items()} }, 1-16 Gaussian RHS each, 3 levels 4x4, "
+                         f"Nv={SERVE_NV}, mixed precision (FP64 flexible CG, FP32 V-cycle, FP16 operator copies), "
+                         f"{SERVE_CAPACITY}-slot batches, {args.serve_lanes} lanes, budget {SERVE_BUDGET / 1e9:.0f} GB, "
+                         f"tol {TOL:g}"),
+               keys=len(keys), warm_keys=len(warm_keys), warm_s=warm_s, field_generation_s=gen_s)
+    sat = run(srv, math.inf, 11, args.serve_requests)
+    sat_rps = sat["requests"] / sat["span_s"]
+    out["saturation"] = sat
+    log(f"serving: saturation {sat['solves_per_s']:.1f} solves/s, {sat_rps:.1f} requests/s")
+    loads = [0.5, 0.7, 0.9] if args.serve_full else SERVE_LOADS
+    for j, frac in enumerate(loads):
+        out[f"load_{frac:g}"] = run(srv, frac * sat_rps, 12 + j, args.serve_requests)
+        q = out[f"load_{frac:g}"]
+        log(f"serving: load {frac:g} x saturation: p50 {q['p50_ms']:.1f} ms, p99 {q['p99_ms']:.1f} ms, "
+            f"{q['solves_per_s']:.1f} solves/s")
     srv.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    return summ
+    if args.serve_full:
+        srv = server()
+        out["cold_0.7"] = run(srv, 0.7 * sat_rps, 13, args.serve_requests)
+        q = out["cold_0.7"]
+        log(f"serving: cold at 0.7 x saturation: p50 {q['p50_ms']:.1f} ms, p99 {q['p99_ms']:.1f} ms")
+        srv.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    main_pt = out[f"load_{0.7:g}"]
+    out.update(p50_ms=main_pt["p50_ms"], p99_ms=main_pt["p99_ms"], solves_per_s=main_pt["solves_per_s"],
+               saturation_solves_per_s=sat["solves_per_s"], saturation_requests_per_s=sat_rps)
+    return out
 
 def timed_graph(fn, reps, stream, per_graph=20):
     """Average duration of fn() with the launches replayed from a HIP graph of
@@ -625,8 +672,9 @@ def main():
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--streams", type=int, default=16, help="concurrent solve streams")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="offered requests/s of the serving trace")
     ap.add_argument("--serve-lanes", type=int, default=8, help="concurrent (field, mass) lanes")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving at 0.5, 0.7 and 0.9 x saturation and a cold run (longer)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
     ap.add_argument("--no-mrhs", action="store_true")

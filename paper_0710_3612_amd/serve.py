@@ -132,6 +132,7 @@ class _Entry:
     bytes: int
     pins: int = 0
     batch: object = None  # the key's slot batch, kept with the hierarchy
+    base: bool = False    # built by the full adaptive setup (it holds the mass coefficients)
     ready: threading.Event = dataclasses.field(default_factory=threading.Event)
     failed: Optional[BaseException] = None
 
@@ -194,8 +195,11 @@ class SetupCache:
                     raise BudgetExceeded(f"{key}: {need} bytes exceed the budget of {self.budget}")
                 if not self._evict_for(need):
                     return None
-                src = next((k for k, v in reversed(self.entries.items())
-                            if k[0] == field and v.ready.is_set() and v.solver is not None), None)
+                # derive from a resident hierarchy of the field, its full setup first
+                same = [(k, v) for k, v in reversed(self.entries.items())
+                        if k[0] == field and v.ready.is_set() and v.solver is not None]
+                same.sort(key=lambda kv: not kv[1].base)
+                src = same[0][0] if same else None
                 if src is not None:
                     self.entries[src].pins += 1
                 e = _Entry(None, need, pins=1)
@@ -230,6 +234,7 @@ class SetupCache:
                 self.entries[src].pins -= 1
                 self.derives += 1
             else:
+                e.base = True
                 self.setups += 1
         e.ready.set()
         return solver

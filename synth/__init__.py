@@ -6,11 +6,13 @@ of the solver's arithmetic (no Dirac operator, no multigrid), so the GPU library
 the CPU oracle can both consume its outputs without sharing any method code.
 """
 
-from .gauge import metropolis_u1, plaquette_angles, mean_plaquette, topological_charge, links_from_angles
+from .gauge import (metropolis_u1, metropolis_u1_device, plaquette_angles, mean_plaquette, topological_charge,
+                    links_from_angles)
 from .vectors import gaussian, gaussian_device, z2_noise, point_source, setup_randoms, level_shapes
 
 __all__ = [
     "metropolis_u1",
+    "metropolis_u1_device",
     "plaquette_angles",
     "mean_plaquette",
     "topological_charge",

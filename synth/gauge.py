@@ -118,3 +118,49 @@ def string_length(beta: float) -> float:
     from scipy.special import i0, i1
 
     return 1.0 / math.sqrt(-math.log(i1(beta) / i0(beta)))
+
+
+def metropolis_u1_device(lx: int, lt: int, beta: float, sweeps: int, seed: int, count: int = 1,
+                         device="cuda"):
+    """`count` fields of link angles [count, 2, lt, lx] from the same checkerboard
+    Metropolis as metropolis_u1 (hot start, the same update order and proposal width),
+    run with torch on `device` for request streams over many large fields.  The random
+    numbers come from torch's generator seeded with `seed`, so the fields differ from
+    metropolis_u1's for the same seed but are reproducible for a device type and seed."""
+    import torch
+
+    if lx % 2 or lt % 2:
+        raise ValueError("checkerboard update needs even extents")
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    theta = (torch.rand((count, 2, lt, lx), generator=g, device=device, dtype=f64) * 2.0 - 1.0) * math.pi
+    delta = math.sqrt(2.0 / beta) if beta > 0 else math.pi
+
+    def plaq(th):
+        return th[:, 0] + torch.roll(th[:, 1], -1, dims=2) - torch.roll(th[:, 0], -1, dims=1) - th[:, 1]
+
+    for _ in range(sweeps):
+        for mu in (0, 1):
+            for parity in (0, 1):
+                p = plaq(theta)
+                if mu == 0:  # x-link at (t, x): + in p[t, x], - in p[t-1, x]
+                    p_plus = p[:, parity::2, :]
+                    p_minus = torch.roll(p, 1, dims=1)[:, parity::2, :]
+                    old = theta[:, 0, parity::2, :]
+                else:  # t-link at (t, x): + in p[t, x-1], - in p[t, x]
+                    p_plus = torch.roll(p, 1, dims=2)[:, :, parity::2]
+                    p_minus = p[:, :, parity::2]
+                    old = theta[:, 1, :, parity::2]
+                u = torch.rand(old.shape, generator=g, device=device, dtype=f64)
+                acc = torch.rand(old.shape, generator=g, device=device, dtype=f64)
+                step = delta * (2.0 * u - 1.0)
+                ds = beta * (torch.cos(p_plus + step) + torch.cos(p_minus - step) - torch.cos(p_plus)
+                             - torch.cos(p_minus))
+                take = acc < torch.exp(torch.clamp(ds, max=0.0))
+                new = torch.where(take, torch.remainder(old + step + math.pi, TWO_PI) - math.pi, old)
+                if mu == 0:
+                    theta[:, 0, parity::2, :] = new
+                else:
+                    theta[:, 1, :, parity::2] = new
+    return theta

@@ -800,3 +800,19 @@ def test_nv_stop_is_a_prefix_of_the_full_setup_and_shortens_the_next_level():
     v2 = v1 - lev.P @ mg.vcycle(h, 1, lev.P.conj().T @ (A @ v1))
     rhs = v2 - mg.smoother_apply(A, lev.coefs, A @ v2)
     np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("beta", [3.0, 10.0])
+def test_device_metropolis_plaquette_and_charge(beta):
+    """The torch copy of the Metropolis update (run here on the CPU) thermalises to the
+    same plaquette, I1(beta)/I0(beta), and gives integer charges, for a batch of fields."""
+    from scipy.special import i0, i1
+
+    th = synth.metropolis_u1_device(32, 32, beta, 300, 5, count=4, device="cpu").numpy()
+    plaq = [synth.mean_plaquette(t) for t in th]
+    target = i1(beta) / i0(beta)
+    # four 32^2 fields: 4096 plaquettes; the spread of cos is below 0.5 at these couplings
+    assert abs(np.mean(plaq) - target) < 3 * 0.5 / math.sqrt(4096)
+    for t in th:
+        q = synth.topological_charge(t)
+        assert abs(q - round(q)) < 1e-9

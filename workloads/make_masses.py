@@ -18,8 +18,8 @@ D takes most of a minute and some near-critical ones far longer), so the target 
 reached from a starting mass by secant steps on sigma_min(D) = sqrt(lambda_min(A)),
 which moves almost linearly with m away from m_crit; m* is not searched there.
 
-Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 512_beta6_s3000 | 128_beta6 | 128_beta10 |
-       128_beta6_cold | 128_beta10_cold]
+Usage: python -m workloads.make_masses [256_beta6 | 512_beta6 | 512_beta6_s3000 | 128_beta3 | 128_beta6 |
+       128_beta10 | 128_beta6_cold | 128_beta10_cold]
        (writes workloads/masses_<name>.json)
 """
 
@@ -54,6 +54,8 @@ CONFIGS = {
     # the paper's 128^2 experiment: m_crit (= m*) of candidate fields, picked by topological charge
     "128_beta6": dict(L=128, beta=6.0, sweeps=1000, seeds=list(range(7000, 7008)), ratios=[]),
     "128_beta10": dict(L=128, beta=10.0, sweeps=1000, seeds=list(range(7100, 7108)), ratios=[]),
+    # the serving workload's beta = 3 fields: m_crit (= m*) of 8 fields, 500 sweeps
+    "128_beta3": dict(L=128, beta=3.0, sweeps=500, seeds=list(range(7200, 7208)), ratios=[]),
     # cold starts; the first seeds whose field keeps topological charge 0 after 1000 sweeps
     "128_beta6_cold": dict(L=128, beta=6.0, sweeps=1000, seeds=[7014], ratios=[], cold=True),
     "128_beta10_cold": dict(L=128, beta=10.0, sweeps=1000, seeds=[7110], ratios=[], cold=True),
