@@ -360,7 +360,8 @@ def serving_leg(args, torch, smg, dev):
             for i in range(SERVE_FIELDS):
                 key = f"L{Ls}_b{int(beta)}_{i}"
                 ms = [round(mc[beta] + g, 6) for g in SERVE_GAPS]
-                p = smg.make_params(Ls, Ls, min(ms), levels=3, blocks=BLOCKS, nv=[SERVE_NV, SERVE_NV],
+                lv = serve.levels_for(Ls, 4, 16)  # coarsest lattice at most 16^2
+                p = smg.make_params(Ls, Ls, min(ms), levels=lv, blocks=[(4, 4)] * (lv - 1), nv=[SERVE_NV] * (lv - 1),
                                     setup_iters=SETUP_ITERS, smoother_steps=NU, smoother_omega=OMEGA,
                                     seed=4000 + i, sa_scale=SA_SCALE, operator_storage=OPERATOR_STORAGE,
                                     remass_affine=True)
@@ -385,7 +386,8 @@ def serving_leg(args, torch, smg, dev):
             for r in reqs:
                 r.arrival = 0.0
         c0 = dict(setups=srv.cache.setups, derives=srv.cache.derives, evictions=srv.cache.evictions)
-        results = srv.run_trace(reqs, timeout=1800)
+        results = srv.run_trace(reqs, timeout=1800,
+                                progress=lambda o, n: log(f"serving: {n - o} of {n} requests done"))
         summ = serve.latency_summary(results)
         bad = [r for r in results if not r.ok or max(r.true_relres) > TOL]
         by_size = {}
@@ -423,7 +425,8 @@ def serving_leg(args, torch, smg, dev):
     out = dict(workload=(f"{args.serve_requests} Poisson requests per run over {len(fields)} fields "
                          f"({'/'.join(map(str, SERVE_SIZES))}^2 x beta 3/6/10 x {SERVE_FIELDS}, 500 sweeps, beta 10: "
                          f"1000, drawn on the GPU), masses m_c(beta) + {SERVE_GAPS} with m_c = "
-                         f"{ {int(b): round(v, 4) for b, v in mc.items()} }, 1-16 Gaussian RHS each, 3 levels 4x4, "
+                         f"{ {int(b): round(v, 4) for b, v in mc.items()} }, 1-16 Gaussian RHS each, 4x4 "
+                         f"aggregates down to a coarsest lattice of at most 16^2 (2/3/3/4 levels), "
                          f"Nv={SERVE_NV}, mixed precision (FP64 flexible CG, FP32 V-cycle, FP16 operator copies), "
                          f"{SERVE_CAPACITY}-slot batches, {args.serve_lanes} lanes, budget {SERVE_BUDGET / 1e9:.0f} GB, "
                          f"tol {TOL:g}"),

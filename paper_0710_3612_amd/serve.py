@@ -160,18 +160,21 @@ class SetupCache:
         self.evictions = 0
 
     def _evict_for(self, need: int) -> bool:
-        for key in list(self.entries.keys()):
-            if self.used + need <= self.budget:
-                break
-            e = self.entries[key]
-            if e.pins == 0 and e.ready.is_set():
-                if e.batch is not None:
-                    e.batch.close()
-                if e.solver is not None:
-                    e.solver.close()
-                self.used -= e.bytes
-                del self.entries[key]
-                self.evictions += 1
+        # least recently used first; hierarchies derived from another mass (cheap to
+        # derive again) before full setups (a field's adaptive setup costs far more)
+        for bases in (False, True):
+            for key in list(self.entries.keys()):
+                if self.used + need <= self.budget:
+                    break
+                e = self.entries[key]
+                if e.pins == 0 and e.ready.is_set() and e.base == bases:
+                    if e.batch is not None:
+                        e.batch.close()
+                    if e.solver is not None:
+                        e.solver.close()
+                    self.used -= e.bytes
+                    del self.entries[key]
+                    self.evictions += 1
         return self.used + need <= self.budget
 
     def entry(self, field, mass: float) -> Optional[_Entry]:
@@ -193,15 +196,18 @@ class SetupCache:
                 need = self.backend.estimate(field, capacity)
                 if need > self.budget:
                     raise BudgetExceeded(f"{key}: {need} bytes exceed the budget of {self.budget}")
-                if not self._evict_for(need):
-                    return None
-                # derive from a resident hierarchy of the field, its full setup first
+                # derive from a resident hierarchy of the field, its full setup first; it is
+                # pinned before room is made, so that the eviction cannot take it
                 same = [(k, v) for k, v in reversed(self.entries.items())
                         if k[0] == field and v.ready.is_set() and v.solver is not None]
                 same.sort(key=lambda kv: not kv[1].base)
                 src = same[0][0] if same else None
                 if src is not None:
                     self.entries[src].pins += 1
+                if not self._evict_for(need):
+                    if src is not None:
+                        self.entries[src].pins -= 1
+                    return None
                 e = _Entry(None, need, pins=1)
                 self.entries[key] = e
                 self.used += need
@@ -557,9 +563,11 @@ class Server:
             raise errors[0]
 
     # -- driving ---------------------------------------------------------------
-    def run_trace(self, requests: Sequence[Request], timeout: float = 600.0) -> List[Result]:
+    def run_trace(self, requests: Sequence[Request], timeout: float = 600.0,
+                  progress: Optional[Callable[[int, int], None]] = None) -> List[Result]:
         """Submit each request at its arrival time (seconds from now) and wait for
-        all of them; returns the results in request order."""
+        all of them; returns the results in request order.  progress(open, total), if
+        given, is called about every 10 s while waiting."""
         self.t0 = time.perf_counter()
         order = sorted(requests, key=lambda r: r.arrival)
         for req in order:
@@ -569,17 +577,22 @@ class Server:
             self.submit(req, arrival=req.arrival)
             with self.lock:
                 self._drain_waiting()
-        self.wait(timeout)
+        self.wait(timeout, progress=(None if progress is None else (lambda o: progress(o, len(order)))))
         return [self.results[r.rid] for r in requests]
 
-    def wait(self, timeout: float = 600.0):
+    def wait(self, timeout: float = 600.0, progress: Optional[Callable[[int], None]] = None):
         end = time.perf_counter() + timeout
+        tick = time.perf_counter() + 10.0
         with self.lock:
             while self.open > 0:
                 self._drain_waiting()
-                left = end - time.perf_counter()
+                now = time.perf_counter()
+                left = end - now
                 if left <= 0:
                     raise TimeoutError(f"{self.open} requests still open")
+                if progress is not None and now >= tick:
+                    progress(self.open)
+                    tick = now + 10.0
                 self.done_cv.wait(timeout=min(left, 0.01))
 
     def close(self):

@@ -276,3 +276,25 @@ def test_warm_builds_every_key_once():
         results = srv.run_trace(reqs, timeout=30)
         assert len(be.setups) == 3 and len(be.derives) == 3  # served from the warm cache
     check_results(reqs, results)
+
+
+def test_eviction_keeps_full_setups_longer():
+    """Derived hierarchies (another mass of a resident field) are evicted before full
+    setups, least recently used first within each kind, and a new mass derives from
+    the field's full setup when it is resident."""
+    be = FakeBackend(est=100)
+    cache = serve.SetupCache(be, budget_bytes=300)
+    for f, m in ((1, 0.1), (1, 0.2), (2, 0.1)):  # setup 1, derive (1, 0.2), setup 2
+        assert cache.acquire(f, m, 4) is not None
+        cache.release(f, m)
+    assert be.setups == [(1, 0.1), (2, 0.1)] and be.derives == [(1, 0.2)]
+    assert cache.entry(1, 0.1).base and not cache.entry(1, 0.2).base
+    # a fourth key needs room: the derived (1, 0.2) goes, although (1, 0.1) is older
+    assert cache.acquire(3, 0.1, 4) is not None
+    cache.release(3, 0.1)
+    assert cache.entry(1, 0.2) is None and cache.entry(1, 0.1) is not None
+    # the next mass of field 1 derives from its full setup, which is kept while room is
+    # made (the least recently used other full setup, field 2's, goes instead)
+    assert cache.acquire(1, 0.3, 4) is not None
+    assert be.derives[-1] == (1, 0.3) and len(be.setups) == 3
+    assert cache.entry(2, 0.1) is None and cache.entry(1, 0.1) is not None
