@@ -191,7 +191,7 @@ class SetupCache:
             if e is not None:
                 self.entries.move_to_end(key)
                 e.pins += 1
-                build = False
+                build = evicted = False
             else:
                 need = self.backend.estimate(field, capacity)
                 if need > self.budget:
@@ -204,14 +204,18 @@ class SetupCache:
                 src = same[0][0] if same else None
                 if src is not None:
                     self.entries[src].pins += 1
+                ev0 = self.evictions
                 if not self._evict_for(need):
                     if src is not None:
                         self.entries[src].pins -= 1
                     return None
+                evicted = self.evictions != ev0
                 e = _Entry(None, need, pins=1)
                 self.entries[key] = e
                 self.used += need
                 build = True
+        if build and evicted and hasattr(self.backend, "trim"):
+            self.backend.trim()  # memory the evicted hierarchies held goes back to the device
         if not build:
             e.ready.wait()
             if e.failed is not None:
@@ -692,6 +696,14 @@ class DeviceBackend:
 
     def new_stream(self):
         return self.torch.cuda.Stream()
+
+    def trim(self, slack: int = 8 << 30):
+        """Return torch's cached free blocks (where the library's evicted arrays went)
+        to the device once they exceed `slack` bytes, so that allocations outside
+        torch's cache (rocBLAS workspaces) still find memory."""
+        t = self.torch
+        if t.cuda.memory_reserved() - t.cuda.memory_allocated() > slack:
+            t.cuda.empty_cache()
 
     def stream_context(self, stream):
         return self.torch.cuda.stream(stream)
