@@ -407,7 +407,7 @@ def serving_leg(args, torch, smg, dev):
 
     def server():
         return serve.Server(backend, SERVE_BUDGET, capacity=SERVE_CAPACITY, tol=TOL, maxiter=2000,
-                            precision=smg.MIXED, max_lanes=args.serve_lanes)
+                            precision=smg.MIXED, max_lanes=args.serve_lanes, keep_solutions=False)
 
     # warm: every field's full setup at its lightest mass (the expensive part), then
     # the other masses, small lattices first, while 90% of the budget holds them
@@ -415,9 +415,11 @@ def serving_leg(args, torch, smg, dev):
     lightest = [(f, min(masses[f])) for f in fields]
     others = sorted([k for k in keys if k not in lightest], key=lambda k: (sizes[k[0]], k[0], k[1]))
     warm_keys, used = [], 0
+    # room for every lane's batch of the largest lattice stays free
+    room = 0.9 * SERVE_BUDGET - args.serve_lanes * max(backend.batch_estimate(f, SERVE_CAPACITY) for f in fields)
     for f, m in sorted(lightest, key=lambda k: sizes[k[0]]) + others:
-        need = backend.estimate(f, SERVE_CAPACITY)
-        if used + need > 0.9 * SERVE_BUDGET:
+        need = backend.estimate(f, 0)
+        if used + need > room:
             continue
         warm_keys.append((f, m))
         used += need

@@ -326,8 +326,10 @@ int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out);
  * finished slots are harvested and reused.  Each slot keeps its own Krylov
  * scalars and is frozen on the device when it converges, so its result is bitwise
  * the same alone and in any mix.  precision SMG_FP64: FP64 MG-CG; SMG_MIXED: FP64
- * flexible CG preconditioned by the FP32 V-cycle.  A batch uses the work buffers
- * of h: while it exists, h must not run other solves concurrently.
+ * flexible CG preconditioned by the FP32 V-cycle.  A batch owns the column work
+ * vectors of its slots (all levels) and lends them to h for the duration of each
+ * smg_batch_step, so that destroying the batch returns them; h must not run other
+ * calls while a step of one of its batches runs.
  * ------------------------------------------------------------------------------ */
 
 /* New batch of max_rhs (1..256) slots with relative tolerance tol (true residual)

@@ -282,27 +282,74 @@ void ensure_scalars(Ctx& c, int nrhs) {
   HIPCHECK(hipHostMalloc((void**)&c.h_int, sizeof(int) * 2 * cap, hipHostMallocDefault));
 }
 
+// Column work vectors of one level for cap right-hand sides from `pool`.
+template <typename R>
+void alloc_level_work(Pool& pool, Level<R>& lv, int cap, int smoother_storage) {
+  lv.cap = cap;
+  lv.b = pool.alloc<cpx<R>>((size_t)cap * lv.n);
+  lv.x = pool.alloc<cpx<R>>((size_t)cap * lv.n);
+  lv.r = pool.alloc<cpx<R>>((size_t)cap * lv.n);
+  lv.t = pool.alloc<cpx<R>>((size_t)cap * lv.n);
+  lv.tmp = lv.fine ? pool.alloc<cpx<R>>((size_t)cap * lv.n) : nullptr;
+  lv.wbuf = lv.bx ? pool.alloc<cpx<R>>((size_t)cap * lv.nkw()) : nullptr;
+  lv.r_lp = lv.t_lp = nullptr;
+  if (std::is_same<R, float>::value && lv.fine && smoother_storage != SMG_STORE_F32) {
+    lv.r_lp = pool.alloc<uint32_t>((size_t)cap * lv.n);  // 4-byte complex entries
+    lv.t_lp = pool.alloc<uint32_t>((size_t)cap * lv.n);
+  }
+}
+
+template <typename R>
+void check_work_geometry(const Ctx& c, const std::vector<Level<R>>& Ls) {
+  if ((int)Ls.size() != c.nlev) throw Error(SMG_EINVAL, "level work requested before the levels exist");
+  for (size_t l = 0; l + 1 < Ls.size(); ++l)  // every level but the coarsest transfers
+    if (!(Ls[l].bx > 0 && Ls[l].nkw() > 0)) throw Error(SMG_EINVAL, "level work requested before the transfer geometry is set");
+}
+
 template <typename R>
 void ensure_level_work(Ctx& c, int nrhs) {
   auto& Ls = levels_of<R>(c);
-  if ((int)Ls.size() != c.nlev) throw Error(SMG_EINVAL, "level work requested before the levels exist");
-  for (auto& lv : Ls) {
-    if (&lv != &Ls.back() && !(lv.bx > 0 && lv.nkw() > 0))  // every level but the coarsest transfers
-      throw Error(SMG_EINVAL, "level work requested before the transfer geometry is set");
-    if (lv.cap >= nrhs) continue;
-    lv.cap = nrhs;
-    lv.b = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
-    lv.x = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
-    lv.r = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
-    lv.t = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
-    if (lv.fine) lv.tmp = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.n);
-    if (lv.bx) lv.wbuf = c.pool.alloc<cpx<R>>((size_t)nrhs * lv.nkw());
-    if (std::is_same<R, float>::value && lv.fine && c.prm.smoother_storage != SMG_STORE_F32) {
-      lv.r_lp = c.pool.alloc<uint32_t>((size_t)nrhs * lv.n);  // 4-byte complex entries
-      lv.t_lp = c.pool.alloc<uint32_t>((size_t)nrhs * lv.n);
+  check_work_geometry(c, Ls);
+  for (auto& lv : Ls)
+    if (lv.cap < nrhs) alloc_level_work<R>(c.pool, lv, nrhs, c.prm.smoother_storage);
+}
+
+// Work vectors of every level for cap columns from `pool`, with the shapes of the
+// handle's levels: a batch owns such a set, so that they go when the batch goes.
+template <typename R>
+std::vector<Level<R>> alloc_work_set(Pool& pool, const Ctx& c, const std::vector<Level<R>>& Ls, int cap) {
+  check_work_geometry(c, Ls);
+  std::vector<Level<R>> w(Ls.begin(), Ls.end());
+  for (auto& lv : w) alloc_level_work<R>(pool, lv, cap, c.prm.smoother_storage);
+  return w;
+}
+
+// Lends the work vectors of `w` to the handle's levels for the lifetime of the loan
+// (the V-cycle code reads them from the levels), swapping the handle's own back after.
+template <typename R>
+struct WorkLoan {
+  std::vector<Level<R>>& Ls;
+  std::vector<Level<R>>& w;
+  void flip() {
+    for (size_t l = 0; l < Ls.size() && l < w.size(); ++l) {
+      auto& a = Ls[l];
+      auto& o = w[l];
+      std::swap(a.b, o.b);
+      std::swap(a.x, o.x);
+      std::swap(a.r, o.r);
+      std::swap(a.t, o.t);
+      std::swap(a.tmp, o.tmp);
+      std::swap(a.wbuf, o.wbuf);
+      std::swap(a.r_lp, o.r_lp);
+      std::swap(a.t_lp, o.t_lp);
+      std::swap(a.cap, o.cap);
     }
   }
-}
+  WorkLoan(std::vector<Level<R>>& L, std::vector<Level<R>>& W) : Ls(L), w(W) { flip(); }
+  ~WorkLoan() { flip(); }
+  WorkLoan(const WorkLoan&) = delete;
+  WorkLoan& operator=(const WorkLoan&) = delete;
+};
 
 template <typename R>
 void alloc_kvecs(Pool& pool, KVecs<R>& v, size_t elems) {
@@ -906,29 +953,31 @@ void sa_weight(Ctx& c, int l) {
 // block k = -C P and B_kk = P.  The three products are plain GEMMs (rocBLAS).
 constexpr int kGJBlock = 512;
 
-struct DevBuf {
-  void* p = nullptr;
-  explicit DevBuf(size_t bytes) {
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    }
-  }
-  ~DevBuf() { (void)hipFree(p); }
-};
-
 void blas_check(rocblas_status s) {
   if (s != rocblas_status_success) throw Error(SMG_EDEVICE, std::string("rocBLAS: ") + rocblas_status_to_string(s));
 }
 
 void blocked_gauss_jordan(Ctx& c, z64* B, int n) {
-  if (!c.blas) blas_check(rocblas_create_handle(&c.blas));
+  // a rocBLAS handle for this inversion only: it holds device workspace of its own
+  struct Blas {
+    rocblas_handle h = nullptr;
+    ~Blas() {
+      if (h) (void)rocblas_destroy_handle(h);
+    }
+  } blas;
+  blas_check(rocblas_create_handle(&blas.h));
+  c.blas = blas.h;
+  struct Forget {
+    Ctx& c;
+    ~Forget() { c.blas = nullptr; }
+  } forget{c};
   blas_check(rocblas_set_stream(c.blas, c.st));
   const int nb = kGJBlock;
-  DevBuf Cb((size_t)n * nb * sizeof(z64)), Rb((size_t)n * nb * sizeof(z64)), Pb((size_t)nb * nb * sizeof(z64));
-  z64* C = static_cast<z64*>(Cb.p);
-  z64* R = static_cast<z64*>(Rb.p);
-  z64* P = static_cast<z64*>(Pb.p);
+  Pool scratch;  // released after the final synchronisation below
+  scratch.stream = &c.st;
+  z64* C = scratch.alloc<z64>((size_t)n * nb);
+  z64* R = scratch.alloc<z64>((size_t)n * nb);
+  z64* P = scratch.alloc<z64>((size_t)nb * nb);
   const size_t zs = sizeof(z64);
   const rocblas_double_complex one = {1.0, 0.0}, mone = {-1.0, 0.0}, zer = {0.0, 0.0};
   auto zc = [](z64* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
@@ -1289,11 +1338,7 @@ void reserve_solve(Ctx& c, int nrhs, int prec) {
 
 // The handle's own growth when a batch of cap slots in `prec` is created on it.
 void reserve_batch_handle(Ctx& c, int cap, int prec) {
-  if (prec == SMG_MIXED) {
-    alloc_f32(c);
-    ensure_level_work<float>(c, cap);
-  }
-  ensure_level_work<double>(c, cap);
+  if (prec == SMG_MIXED) alloc_f32(c);  // the batch brings its own column work vectors
   if (c.nlev > 1 && c.prm.coarsest == SMG_COARSEST_CG) {  // the coarsest CG of the batch's V-cycles
     ensure_scalars(c, cap);
     if (prec == SMG_MIXED)
@@ -1423,6 +1468,8 @@ struct Batch {
   z64 *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *zo = nullptr,
       *t = nullptr;
   z32 *r32 = nullptr, *z32v = nullptr;
+  std::vector<Level<double>> w64;  // the batch's own column work vectors of every level
+  std::vector<Level<float>> w32;
   Red red;
   Scal S;
   double* rzo = nullptr;
@@ -1488,6 +1535,8 @@ void batch_alloc(Batch& B) {
   B.S.tt = B.pool.alloc<double>(2 * cap);
   B.S.active = B.pool.alloc<int>(cap);
   B.S.bad = B.pool.alloc<int>(cap);
+  B.w64 = alloc_work_set<double>(B.pool, *B.c, B.c->L64, cap);
+  if (B.prec == SMG_MIXED) B.w32 = alloc_work_set<float>(B.pool, *B.c, B.c->L32, cap);
 }
 
 void batch_upload_active(Batch& B, hipStream_t st) {
@@ -1561,6 +1610,10 @@ void batch_step(Batch& B, int iters, hipStream_t st) {
   auto& lv = c.L64[0];
   const size_t n = B.n;
   if (B.prec == SMG_MIXED) ensure_f32(c);
+  // the V-cycle and the fine applies run on the batch's own work vectors
+  WorkLoan<double> loan64(c.L64, B.w64);
+  std::vector<Level<float>> none32;
+  WorkLoan<float> loan32(c.L32, B.prec == SMG_MIXED ? B.w32 : none32);
   if (B.graph_gen != c.gen) {
     B.drop_graphs();
     B.graph_gen = c.gen;
@@ -2026,24 +2079,7 @@ int smg_vcycle_noalloc(smg_handle h, const double* b, double* x, int32_t nrhs, v
   std::vector<Level<double>> work(c->nlev);
   carve_level_work(*c, nrhs, base, &work);
   // the handle's own work vectors are swapped out for the call and restored on every exit
-  struct Swap {
-    Ctx& c;
-    std::vector<Level<double>>& w;
-    void flip() {
-      for (int l = 0; l < c.nlev; ++l) {
-        auto& a = c.L64[l];
-        std::swap(a.b, w[l].b);
-        std::swap(a.x, w[l].x);
-        std::swap(a.r, w[l].r);
-        std::swap(a.t, w[l].t);
-        std::swap(a.tmp, w[l].tmp);
-        std::swap(a.wbuf, w[l].wbuf);
-        std::swap(a.cap, w[l].cap);
-      }
-    }
-    ~Swap() { flip(); }
-  } swap{*c, work};
-  swap.flip();
+  WorkLoan<double> loan(c->L64, work);
   c->st = (hipStream_t)stream;
   vcycle<double>(*c, 0, c->nlev - 1, (const z64*)b, (z64*)x, nrhs, false);
   return SMG_OK;
@@ -2290,8 +2326,8 @@ int smg_query_bytes(const smg_params* params, int32_t nrhs, int32_t precision, s
     B.cap = nrhs;
     B.prec = precision;
     B.n = c1->L64[0].n;
-    batch_alloc(B);
     reserve_batch_handle(*c1, nrhs, precision);
+    batch_alloc(B);
     *batch_bytes = B.pool.bytes + (c1->pool.bytes - setup);
   }
   return SMG_OK;
@@ -2328,8 +2364,8 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     const size_t e = (size_t)max_rhs * B->n;
     B->pool.stream = &B->st0;
     B->st0 = st;
-    batch_alloc(*B);
     reserve_batch_handle(*c, max_rhs, precision);
+    batch_alloc(*B);
     if (precision == SMG_MIXED) ensure_f32(*c);
     HIPCHECK(hipHostMalloc((void**)&B->h, sizeof(double) * 2 * max_rhs, hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&B->hi_, sizeof(int) * max_rhs, hipHostMallocDefault));

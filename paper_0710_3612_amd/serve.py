@@ -59,12 +59,12 @@ def levels_for(l: int, block: int = 4, max_coarse: int = 8) -> int:
 
 
 def estimate_bytes(params, capacity: int = 1, mixed: bool = True) -> int:
-    """Device bytes of one hierarchy plus a batch of `capacity` slots, from the
-    library's own allocation plan (smg_query_bytes: no device call)."""
+    """Device bytes of one hierarchy plus a batch of `capacity` slots (none for 0),
+    from the library's own allocation plan (smg_query_bytes: no device call)."""
     from . import FP64, MIXED, query_bytes
 
-    setup, _solve, batch = query_bytes(params, capacity, MIXED if mixed else FP64)
-    return setup + batch
+    setup, _solve, batch = query_bytes(params, max(capacity, 1), MIXED if mixed else FP64)
+    return setup + (batch if capacity > 0 else 0)
 
 
 # Stack of every thread that calls into the library here (warm-up workers, lanes).
@@ -193,8 +193,8 @@ class SetupCache:
                 e.pins += 1
                 build = evicted = False
             else:
-                need = self.backend.estimate(field, capacity)
-                if need > self.budget:
+                need = self.backend.estimate(field, 0)  # the hierarchy; a lane's batch is added by open_batch
+                if need + self.backend.estimate(field, capacity) - need > self.budget:
                     raise BudgetExceeded(f"{key}: {need} bytes exceed the budget of {self.budget}")
                 # derive from a resident hierarchy of the field, its full setup first; it is
                 # pinned before room is made, so that the eviction cannot take it
@@ -248,6 +248,50 @@ class SetupCache:
                 self.setups += 1
         e.ready.set()
         return solver
+
+    def open_batch(self, field, mass: float, capacity: int, make: Callable[[], object]):
+        """The batch of a pinned key, made by make() when the key has none, its bytes
+        counted against the budget; None while the budget cannot make room for it."""
+        key = (field, float(mass))
+        with self.lock:
+            e = self.entries[key]
+            if e.batch is not None:
+                return e.batch
+            need = self.backend.batch_estimate(field, capacity)
+            ev0 = self.evictions
+            if not self._evict_for(need):
+                return None
+            evicted = self.evictions != ev0
+            e.bytes += need
+            self.used += need
+        if evicted and hasattr(self.backend, "trim"):
+            self.backend.trim()
+        try:
+            batch = make()
+        except BaseException:
+            with self.lock:
+                e.bytes -= need
+                self.used -= need
+            raise
+        with self.lock:
+            e.batch = batch
+            actual = e.solver.memory_bytes() + batch.memory_bytes()
+            self.used += actual - e.bytes
+            e.bytes = actual
+        return batch
+
+    def close_batch(self, field, mass: float):
+        """Close a key's batch (its slots are all harvested); the hierarchy stays."""
+        key = (field, float(mass))
+        with self.lock:
+            e = self.entries.get(key)
+            if e is None or e.batch is None:
+                return
+            batch, e.batch = e.batch, None
+            actual = e.solver.memory_bytes()
+            self.used += actual - e.bytes
+            e.bytes = actual
+        batch.close()
 
     def settle(self, field, mass: float, actual: int):
         """Replace the estimate of a resident entry by its measured bytes."""
@@ -337,12 +381,18 @@ class _Lane:
                     if self.stop:
                         return
                     time.sleep(srv.poll_sleep)
-                ent = srv.cache.entry(self.field, self.mass)
-                if ent.batch is None:  # first lane of this key: the batch stays with the hierarchy
-                    ent.batch = be.new_batch(self.solver, srv.capacity, srv.tol, srv.maxiter, srv.precision,
-                                             self.stream)
-                    srv.cache.settle(self.field, self.mass, self.solver.memory_bytes() + ent.batch.memory_bytes())
-                self.batch = ent.batch
+                # the key's batch lives while the lane does: idle keys keep only their hierarchy
+                make = lambda: be.new_batch(self.solver, srv.capacity, srv.tol, srv.maxiter,  # noqa: E731
+                                            srv.precision, self.stream)
+                while True:
+                    self.batch = srv.cache.open_batch(self.field, self.mass, srv.capacity, make)
+                    if self.batch is not None:
+                        break
+                    if self.stop:
+                        srv.cache.release(self.field, self.mass)
+                        self.solver = None
+                        return
+                    time.sleep(srv.poll_sleep)
             except Exception as exc:  # setup failed: fail what is queued here
                 self._fail(f"setup: {exc}")
                 if self.solver is not None:
@@ -354,15 +404,11 @@ class _Lane:
                 self._serve()
             except Exception as exc:
                 self._fail(f"solve: {exc}")
-                # the batch's slots are in an unknown state: drop it with the lane
-                ent = srv.cache.entry(self.field, self.mass)
-                if ent is not None and ent.batch is self.batch:
-                    ent.batch = None
+            finally:
                 try:
-                    self.batch.close()
+                    srv.cache.close_batch(self.field, self.mass)
                 except Exception:
                     pass
-            finally:
                 self.batch = None
                 srv.cache.release(self.field, self.mass)
                 self.solver = None
@@ -426,7 +472,7 @@ class Server:
 
     def __init__(self, backend, budget_bytes: int, capacity: int = 16, tol: float = 1e-10, maxiter: int = 5000,
                  precision: int = 1, max_lanes: int = 8, iters_per_step: int = 1, poll_sleep: float = 0.0005,
-                 linger: float = 0.5):
+                 linger: float = 0.5, keep_solutions: bool = True):
         self.backend = backend
         self.cache = SetupCache(backend, budget_bytes)
         self.capacity = int(capacity)
@@ -446,6 +492,10 @@ class Server:
         self.t0 = time.perf_counter()
         self.lanes_started = 0
         self.streams: list = []
+        # False: a finished request drops its right-hand sides and solutions (its
+        # statistics stay), so that a long trace does not hold them all on the device
+        self.keep_solutions = bool(keep_solutions)
+        self.requests: Dict[int, Request] = {}
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -455,6 +505,7 @@ class Server:
         res = Result(req.rid, req.field, float(req.mass), req.k, self.now() if arrival is None else arrival)
         with self.lock:
             self.results[req.rid] = res
+            self.requests[req.rid] = req
             self.open += 1
             self._route(res, req)
         return res
@@ -522,6 +573,11 @@ class Server:
         with self.lock:
             if math.isnan(res.finished):
                 res.finished = self.now()
+            req = self.requests.pop(res.rid, None)
+            if not self.keep_solutions:
+                res.x = None
+                if req is not None:
+                    req.rhs = None
             self.open -= 1
             self.done_cv.notify_all()
 
@@ -545,11 +601,12 @@ class Server:
                             solver = self.cache.acquire(f, m, self.capacity, stream)
                             if solver is None:
                                 raise BudgetExceeded(f"no room to warm {(f, m)}")
-                            ent = self.cache.entry(f, m)
-                            if ent.batch is None:
-                                ent.batch = self.backend.new_batch(solver, self.capacity, self.tol, self.maxiter,
-                                                                   self.precision, stream)
-                                self.cache.settle(f, m, solver.memory_bytes() + ent.batch.memory_bytes())
+                            # a batch made once readies the operators its precision needs; the
+                            # lanes make their own
+                            b = self.cache.open_batch(f, m, self.capacity, lambda s_=solver: self.backend.new_batch(
+                                s_, self.capacity, self.tol, self.maxiter, self.precision, stream))
+                            if b is not None:
+                                self.cache.close_batch(f, m)
                             self.cache.release(f, m)
             except BaseException as exc:
                 errors.append(exc)
@@ -681,8 +738,13 @@ class DeviceBackend:
         self.mixed = mixed
 
     def estimate(self, field, capacity: int) -> int:
+        """Hierarchy bytes, plus a batch of `capacity` slots when capacity > 0."""
         _g, p = self.fields[field]
         return estimate_bytes(p, capacity, mixed=self.mixed)
+
+    def batch_estimate(self, field, capacity: int) -> int:
+        _g, p = self.fields[field]
+        return estimate_bytes(p, capacity, mixed=self.mixed) - estimate_bytes(p, 0, mixed=self.mixed)
 
     def setup(self, field, mass: float, stream):
         g, p = self.fields[field]

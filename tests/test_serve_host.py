@@ -98,7 +98,10 @@ class FakeBackend:
             self.max_used = max(self.max_used, self.cache_ref.used)
 
     def estimate(self, field, capacity):
-        return self.est
+        return self.est if capacity else self.est - self.bytes_per_batch
+
+    def batch_estimate(self, field, capacity):
+        return self.bytes_per_batch
 
     def setup(self, field, mass, stream):
         time.sleep(self.setup_delay)
@@ -271,7 +274,8 @@ def test_warm_builds_every_key_once():
     with serve.Server(be, budget_bytes=10_000, capacity=4) as srv:
         srv.warm(keys, workers=2)
         assert len(be.setups) == 3 and len(be.derives) == 3
-        assert all(srv.cache.entry(f, m).batch is not None for f, m in keys)
+        # hierarchies stay resident; batches live with the lanes only
+        assert all(srv.cache.entry(f, m) is not None and srv.cache.entry(f, m).batch is None for f, m in keys)
         reqs = make_requests([(f, m, 2, 0.0) for f, m in keys])
         results = srv.run_trace(reqs, timeout=30)
         assert len(be.setups) == 3 and len(be.derives) == 3  # served from the warm cache
@@ -298,3 +302,20 @@ def test_eviction_keeps_full_setups_longer():
     assert cache.acquire(1, 0.3, 4) is not None
     assert be.derives[-1] == (1, 0.3) and len(be.setups) == 3
     assert cache.entry(2, 0.1) is None and cache.entry(1, 0.1) is not None
+
+
+def test_batches_live_with_lanes_and_are_accounted():
+    """A lane opens its key's batch when it starts (its bytes count against the
+    budget) and closes it when it retires; the hierarchy stays resident and only
+    its own bytes remain counted."""
+    be = FakeBackend(est=100, bytes_per_solver=80, bytes_per_batch=20)
+    with serve.Server(be, budget_bytes=10_000, capacity=4, linger=0.0) as srv:
+        reqs = make_requests([(1, 0.1, 2, 0.0), (2, 0.1, 3, 0.0)])
+        results = srv.run_trace(reqs, timeout=30)
+        deadline = time.time() + 10
+        while srv.lanes and time.time() < deadline:
+            time.sleep(0.01)
+        assert not srv.lanes
+        assert srv.cache.used == 2 * 80
+        assert all(e.batch is None for e in srv.cache.entries.values())
+    check_results(reqs, results)
