@@ -423,8 +423,15 @@ def serving_leg(args, torch, smg, dev):
             continue
         warm_keys.append((f, m))
         used += need
+    # one field of each lattice size first, built alone (every kernel instantiation a
+    # size uses is launched once before eight threads build the others)
+    firsts = []
+    for f, m in warm_keys:
+        if sizes[f] not in {sizes[g] for g in firsts}:
+            firsts.append(f)
+    warm_keys = [k for f in firsts for k in warm_keys if k[0] == f] + [k for k in warm_keys if k[0] not in firsts]
     t0 = time.perf_counter()
-    srv.warm(warm_keys, workers=8)
+    srv.warm(warm_keys, workers=8, serial=len(firsts))
     torch.cuda.synchronize()
     warm_s = time.perf_counter() - t0
     log(f"serving: warmed {len(warm_keys)} of {len(keys)} keys in {warm_s:.1f}s ({srv.cache.used / 1e9:.1f} GB)")

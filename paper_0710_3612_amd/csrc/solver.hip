@@ -164,7 +164,7 @@ struct Ctx {
   int nlev = 0;
   int mfma_pin = -1;                // -1: by mfma_min_rhs; 0 / 1: vector ALU / matrix cores
   uint64_t gen = 0;                 // bumped whenever operators or coefficients change (captured graphs)
-  rocblas_handle blas = nullptr;    // GEMMs of the blocked coarsest inversion (setup only)
+  rocblas_handle blas = nullptr;    // the calling thread's handle during a blocked coarsest inversion
   hipStream_t st = nullptr;
   Pool pool;
   z64* U64 = nullptr;
@@ -215,7 +215,6 @@ struct Ctx {
   int64_t vcycles = 0;
 
   ~Ctx() {
-    if (blas) (void)rocblas_destroy_handle(blas);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_int) (void)hipHostFree(h_int);
     for (auto& s : sc) {
@@ -953,24 +952,37 @@ void sa_weight(Ctx& c, int l) {
 // block k = -C P and B_kk = P.  The three products are plain GEMMs (rocBLAS).
 constexpr int kGJBlock = 512;
 
+std::mutex g_blas_mu;
+std::vector<rocblas_handle> g_blas_free;
+
 void blas_check(rocblas_status s) {
   if (s != rocblas_status_success) throw Error(SMG_EDEVICE, std::string("rocBLAS: ") + rocblas_status_to_string(s));
 }
 
 void blocked_gauss_jordan(Ctx& c, z64* B, int n) {
-  // a rocBLAS handle for this inversion only: it holds device workspace of its own
-  struct Blas {
-    rocblas_handle h = nullptr;
-    ~Blas() {
-      if (h) (void)rocblas_destroy_handle(h);
-    }
-  } blas;
-  blas_check(rocblas_create_handle(&blas.h));
-  c.blas = blas.h;
-  struct Forget {
+  // a rocBLAS handle from a process-wide pool (a handle holds device workspace of its
+  // own and serves one thread at a time): as many handles as inversions ever ran at
+  // once, kept until the process ends, instead of one per hierarchy
+  struct Lease {
     Ctx& c;
-    ~Forget() { c.blas = nullptr; }
-  } forget{c};
+    rocblas_handle h = nullptr;
+    explicit Lease(Ctx& cc) : c(cc) {
+      {
+        std::lock_guard<std::mutex> lk(g_blas_mu);
+        if (!g_blas_free.empty()) {
+          h = g_blas_free.back();
+          g_blas_free.pop_back();
+        }
+      }
+      if (!h) blas_check(rocblas_create_handle(&h));
+      c.blas = h;
+    }
+    ~Lease() {
+      c.blas = nullptr;
+      std::lock_guard<std::mutex> lk(g_blas_mu);
+      g_blas_free.push_back(h);
+    }
+  } lease{c};
   blas_check(rocblas_set_stream(c.blas, c.st));
   const int nb = kGJBlock;
   Pool scratch;  // released after the final synchronisation below
@@ -2372,8 +2384,6 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     // off by default: each (batch, slot count) pays a capture, and replays do not
     // shorten the iteration where the device front end bounds it (smg_batch_use_graphs)
     B->use_graphs = false;
-    HIPCHECK(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
-    HIPCHECK(hipEventCreateWithFlags(&B->ev, hipEventDisableTiming));
     B->graphs.assign(max_rhs + 1, nullptr);
     B->graph_gen = c->gen;
     B->used.assign(max_rhs, 0);
@@ -2520,6 +2530,10 @@ int smg_batch_use_graphs(smg_batch b, int32_t enable) {
   const bool can = c.nlev < 2 || c.prm.coarsest == SMG_COARSEST_DIRECT;
   if (enable && !can) throw Error(SMG_EINVAL, "graphs need a direct coarsest solve");
   B->drop_graphs();
+  if (enable && !B->gs) {  // the batch's own stream, made when graphs are first wanted
+    HIPCHECK(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&B->ev, hipEventDisableTiming));
+  }
   B->use_graphs = enable != 0;
   return SMG_OK;
   API_END

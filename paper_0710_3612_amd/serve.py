@@ -582,10 +582,12 @@ class Server:
             self.done_cv.notify_all()
 
     # -- warm-up -----------------------------------------------------------------
-    def warm(self, keys: Sequence[Tuple], workers: int = 4):
-        """Build the hierarchy and batch of each (field, mass) key before serving
-        (fields in parallel; the masses of one field in order, so that the first
-        one runs the adaptive setup and the others derive from it)."""
+    def warm(self, keys: Sequence[Tuple], workers: int = 4, serial: int = 1):
+        """Build the hierarchy of each (field, mass) key before serving (the masses of
+        one field in order, so that the first one runs the adaptive setup and the
+        others derive from it).  The first `serial` fields are built on this thread
+        alone, so that the kernels they use have all been launched once before several
+        threads launch them at the same time; the other fields in parallel."""
         by_field: Dict = collections.OrderedDict()
         for f, m in keys:
             by_field.setdefault(f, []).append(float(m))
@@ -597,23 +599,35 @@ class Server:
             try:
                 with self.backend.stream_context(stream):
                     for f, ms in items[i::workers]:
-                        for m in ms:
-                            solver = self.cache.acquire(f, m, self.capacity, stream)
-                            if solver is None:
-                                raise BudgetExceeded(f"no room to warm {(f, m)}")
-                            # a batch made once readies the operators its precision needs; the
-                            # lanes make their own
-                            b = self.cache.open_batch(f, m, self.capacity, lambda s_=solver: self.backend.new_batch(
-                                s_, self.capacity, self.tol, self.maxiter, self.precision, stream))
-                            if b is not None:
-                                self.cache.close_batch(f, m)
-                            self.cache.release(f, m)
+                        build(f, ms, stream)
             except BaseException as exc:
                 errors.append(exc)
             finally:
                 with self.lock:
                     self.streams.append(stream)
 
+        def build(f, ms, stream):
+            for m in ms:
+                solver = self.cache.acquire(f, m, self.capacity, stream)
+                if solver is None:
+                    raise BudgetExceeded(f"no room to warm {(f, m)}")
+                # a batch made once readies the operators its precision needs; the lanes make their own
+                b = self.cache.open_batch(f, m, self.capacity, lambda s_=solver: self.backend.new_batch(
+                    s_, self.capacity, self.tol, self.maxiter, self.precision, stream))
+                if b is not None:
+                    self.cache.close_batch(f, m)
+                self.cache.release(f, m)
+
+        if serial > 0 and items:
+            stream = self._take_stream()
+            try:
+                with self.backend.stream_context(stream):
+                    for f, ms in items[:serial]:
+                        build(f, ms, stream)
+            finally:
+                with self.lock:
+                    self.streams.append(stream)
+            items = items[serial:]
         with _thread_stack():
             threads = [threading.Thread(target=work, args=(i,)) for i in range(min(workers, len(items)))]
         for t in threads:
