@@ -84,6 +84,20 @@ MRHS_SEED = 3000
 MRHS_NRHS = 32
 MRHS_NV = [16, 16]
 
+# Large single field: 2048x2048 at beta = 10 (1000 sweeps, seed 5000), 4 levels
+# 2048^2 -> (4x4) 512^2 -> (2x2) 256^2 -> (2x2) 128^2 with Nv = 16, the coarsest
+# level (262144 variables, a dense inverse would take 1.1 TB) solved by CG, 64
+# Gaussian right-hand sides; the mass puts lambda_min(A)/lambda_max(A) near 1e-5 on
+# this field (measured in the run by block inverse iteration).
+C5_L = 2048
+C5_BETA = 10.0
+C5_SWEEPS = 1000
+C5_SEED = 5000
+C5_NRHS = 64
+C5_MASS = -0.03
+C5_BLOCKS = [(4, 4), (2, 2), (2, 2)]
+C5_NV = [16, 16, 16]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -299,6 +313,130 @@ def mrhs_leg(args, torch, smg, dev, U):
                           f"coarse links on the matrix cores, the coarsest inverse applied in FP64"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
+
+
+def c5_leg(args, torch, smg, dev):
+    """The large single field: adaptive setup at 2048^2, then 64 right-hand sides
+    solved by plain FP64 MG-CG and by the mixed solver (FP32 MG-CG with BF16 storage
+    of the fine smoother iterates and the coarse links on the FP32 matrix cores,
+    coarsest CG in FP32 inside the V-cycle, FP64 defect correction) to 1e-10."""
+    import ctypes
+
+    import numpy as np
+
+    import synth
+
+    t_start = time.perf_counter()
+    last = [0.0]
+
+    def progress(stage, level, step, total, value):
+        now = time.perf_counter()
+        if stage in ("calibrate", "coarsest", "refinement") or now - last[0] > 10.0:
+            last[0] = now
+            log(f"c5 {stage} level {level}: {step}/{total} ({value:.2e}) at {now - t_start:.0f} s")
+
+    smg.set_progress(progress)
+    n = 2 * C5_L * C5_L
+    th = synth.metropolis_u1_device(C5_L, C5_L, C5_BETA, C5_SWEEPS, C5_SEED, device=dev)[0]
+    plaq = torch.cos(th[0] + torch.roll(th[1], -1, 1) - torch.roll(th[0], -1, 0) - th[1]).mean().item()
+    U = torch.exp(1j * th).contiguous()
+    del th
+    torch.cuda.synchronize()
+    field_s = time.perf_counter() - t_start
+    log(f"c5 field {C5_L}^2 beta {C5_BETA:g}: {field_s:.1f} s, plaquette {plaq:.5f}")
+    p = smg.make_params(C5_L, C5_L, C5_MASS, levels=4, blocks=C5_BLOCKS, nv=C5_NV, setup_iters=SETUP_ITERS,
+                        smoother_steps=NU, smoother_omega=OMEGA, seed=C5_SEED, sa_scale=SA_SCALE,
+                        coarsest=smg.COARSEST_CG, mfma_min_rhs=16, smoother_storage=smg.STORE_BF16)
+    plan = {name: smg.query_bytes(p, C5_NRHS, prec) for name, prec in (("fp64", smg.FP64), ("mixed", smg.MIXED))}
+    t0 = time.perf_counter()
+    s = smg.Solver(U, p)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"c5 setup {setup_s:.1f} s, {s.memory_bytes() / 1e9:.1f} GB")
+    b = synth.gaussian_device(n, 10000 * 5, device=dev, count=C5_NRHS)
+    rhs = s.apply_D(b, dagger=True)
+    del b
+    x = torch.empty_like(rhs)
+    out = {}
+
+    def run(solver, name, prec):
+        # a first pass of one iteration allocates the solve's work vectors
+        solver.solve(rhs, tol=TOL, maxiter=1, precision=prec, out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, code = solver.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        worst = max(q["true_relres"] for q in st)
+        if code != 0 or worst > TOL:
+            raise RuntimeError(f"2048^2 {name} solve did not converge: {st[0]}")
+        out[name] = dict(solves_per_s=C5_NRHS / dt, seconds=dt,
+                         mean_iterations=float(np.mean([q["iterations"] for q in st])),
+                         max_relres=worst, vcycles=int(st[0]["vcycles"]), memory_gb=solver.memory_bytes() / 1e9)
+        log(f"c5 {name}: {dt:.2f} s for {C5_NRHS} RHS ({C5_NRHS / dt:.2f} solves/s), "
+            f"{out[name]['mean_iterations']:.1f} iterations, max relres {worst:.2e}")
+
+    # FP64 on a second handle with the same hierarchy (smg_derive at the same mass), so
+    # that the two solves' work vectors are not held at once
+    d = s.derive(C5_MASS)
+    run(d, "fp64", smg.FP64)
+    # fine A = D^H D on the 64 right-hand sides (FP64; 64 B per site and RHS plus the links)
+    stream = torch.cuda.current_stream()
+    lib = smg.load_library()
+    px, py = ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(x.data_ptr())
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    dur = timed_events(lambda: lib.smg_apply_level(d.handle, 0, px, py, C5_NRHS, sp), 10, stream)
+    abytes = C5_L * C5_L * (64.0 * C5_NRHS + 32.0)
+    fineA = dict(kernel=f"k_normal_fused, {C5_L}^2, {C5_NRHS} RHS, FP64", avg_launch_ms=dur * 1e3,
+                 algorithmic_gb=abytes / 1e9, achieved_tb_s=abytes / dur / 1e12, frac=abytes / dur / 8e12)
+    log(f"c5 fine A, {C5_NRHS} RHS: {dur * 1e3:.2f} ms, {abytes / dur / 1e12:.2f} TB/s")
+    # spectral ratio: lambda_max by power iteration, lambda_min (an upper bound) by
+    # block inverse iteration with Rayleigh-Ritz on 8 vectors
+    v = synth.gaussian_device(n, 7, device=dev)
+    for _ in range(50):
+        w = d.apply_A(v)
+        lmax = (torch.vdot(v[0], w[0]).real / torch.vdot(v[0], v[0]).real).item()
+        v = w / torch.linalg.vector_norm(w)
+    k = 8
+    X = synth.gaussian_device(n, 11, device=dev, count=k)
+
+    def orth(X):
+        for i in range(k):
+            for _ in range(2):
+                for j in range(i):
+                    X[i] -= torch.vdot(X[j], X[i]) * X[j]
+            X[i] /= torch.linalg.vector_norm(X[i])
+        return X
+
+    X = orth(X)
+    ritz, Y = [], None
+    for _ in range(args.c5_inverse_iters):
+        Y, _, _ = d.solve(X, tol=1e-8, maxiter=2000, precision=smg.FP64)
+        X = orth(Y)
+        H = (X.conj() @ d.apply_A(X).T).cpu().numpy()
+        ritz = np.linalg.eigvalsh(0.5 * (H + H.conj().T)).tolist()
+        log(f"c5 lowest Ritz values {ritz[0]:.4e} .. {ritz[-1]:.4e}, ratio {ritz[0] / lmax:.2e}")
+    d.close()
+    del X, Y, v, w
+    run(s, "mixed", smg.MIXED)
+    s.close()
+    smg.set_progress(None)
+    del U, rhs, x
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return dict(workload=(f"{C5_L}x{C5_L} U(1) beta={C5_BETA:g} ({C5_SWEEPS} sweeps, seed {C5_SEED}, torch device "
+                          f"generator), mass {C5_MASS:g}, {C5_NRHS} Gaussian right-hand sides (rhs = D^H b), 4 levels "
+                          f"4x4, 2x2, 2x2, Nv=16, nu={NU}, coarsest (128^2 x 16 = 262144 variables) by CG to 1e-12 "
+                          f"(FP64) / 1e-6 (inside the FP32 V-cycle), tol {TOL:g}; mixed: FP32 inner MG-CG, BF16 "
+                          f"storage of the fine smoother iterates, coarse links on the FP32 matrix cores; FP64: coarse "
+                          f"links on the FP64 matrix cores"),
+                plaquette=plaq, field_s=field_s, setup_s=setup_s, setup_gb=plan["fp64"][0] / 1e9,
+                solve_gb={k_: v_[1] / 1e9 for k_, v_ in plan.items()}, lambda_max=lmax,
+                lambda_min_ritz=ritz[0] if ritz else None,
+                ratio_upper_bound=(ritz[0] / lmax) if ritz else None, lowest_ritz=ritz,
+                fp64=out["fp64"], mixed=out["mixed"],
+                mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], fine_A=fineA,
+                seconds=time.perf_counter() - t_start)
 
 
 def c1_leg(torch, smg, dev):
@@ -699,6 +837,10 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the chirality-split comparison")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
+    ap.add_argument("--c5", action="store_true",
+                    help="only the 2048^2 four-level leg, 64 right-hand sides (prints its summary)")
+    ap.add_argument("--c5-inverse-iters", type=int, default=6,
+                    help="block inverse iterations for the 2048^2 leg's spectral ratio")
     ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
     ap.add_argument("--dslash-probe", type=int, default=0, metavar="L",
                     help="only launch the fine FP64 A at L x L and a 64 MiB copy (for profiler runs)")
@@ -731,6 +873,14 @@ def main():
         import paper_0710_3612_amd as smg
 
         print(json.dumps(serving_leg(args, torch, smg, torch.device("cuda:0"))))
+        return 0
+
+    if args.c5:
+        import torch
+
+        import paper_0710_3612_amd as smg
+
+        print(json.dumps(c5_leg(args, torch, smg, torch.device("cuda:0"))))
         return 0
 
     if args.mrhs_only:

@@ -213,6 +213,14 @@ int smg_apply_A(smg_handle h, const double* x, double* y, int32_t nrhs, void* st
 int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int32_t nrhs,
                     void* stream);
 
+/* FP64 operator of level `level` with the epilogues the V-cycle uses (Multigrid
+ * section, steps 1-5; Results for the smoother), the modes of smg_level_op_f32
+ * below.  Vectors are complex128 device arrays [nrhs][n_l] (xacc, aux may be
+ * NULL where unused).  Coarse levels with nc <= 16 and nrhs >= mfma_min_rhs run
+ * on the matrix cores (FP64 MFMA).  Errors: SMG_EINVAL.  ASYNC. */
+int smg_level_op(smg_handle h, int32_t level, int32_t mode, double coef, const double* x, double* y, double* xacc,
+                 const double* aux, int32_t nrhs, void* stream);
+
 /* y = A^(l) x with the FP32 copy of the level-l operator that the mixed-precision
  * solves use (the same operator as smg_apply_level, links rounded to FP32).
  * x, y: device, complex64 (interleaved float) level-l batches.  ASYNC. */
@@ -392,6 +400,31 @@ int smg_memory_bytes(smg_handle h, size_t* bytes);
 typedef void* (*smg_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*smg_release_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
 int smg_set_allocator(smg_alloc_fn alloc, smg_release_fn release, void* ctx);
+
+/* Progress of long calls.  A setup of a large lattice runs for minutes inside one
+ * call (the adaptive setup builds each level one near-null vector at a time,
+ * Adaptive Multigrid section), so the library reports its steps as they finish:
+ *   "calibrate"   level `level`'s smoother is calibrated (step 0, total = nv[level]);
+ *   "candidate"   level `level` holds `step` of at most `total` near-null vectors
+ *                 (value: the two-level factor that decided to go on when
+ *                 nv_stop_rho > 0, else 0);
+ *   "coarsest"    the setup is complete (level = levels - 1);
+ *   "iteration"   an outer MG-CG (smg_solve, smg_cg; in SMG_MIXED the FP32 inner
+ *                 solve) checked convergence after `step` of at most `total`
+ *                 iterations (value: the largest recursive relative residual of the
+ *                 columns still running);
+ *   "refinement"  a SMG_MIXED solve finished defect-correction pass `step` (value:
+ *                 the largest true relative residual after it);
+ *   "coarsest-cg" a CG solve of the coarsest level (SMG_COARSEST_CG, or a setup
+ *                 cycle's coarse system) took `step` iterations (most over the
+ *                 columns; value: the largest relative residual reached).
+ * The callback runs on the thread that made the call, between device
+ * synchronisations, with no library lock held; calls on several threads may
+ * report at the same time.  It must not call the library.  fn = NULL (the
+ * default) turns reporting off.  Never fails. */
+typedef void (*smg_progress_fn)(const char* stage, int32_t level, int32_t step, int32_t total, double value,
+                                void* ctx);
+int smg_set_progress(smg_progress_fn fn, void* ctx);
 
 /* Device bytes the library will hold for a hierarchy with these parameters,
  * computed on the host from the allocation plan that the calls themselves follow

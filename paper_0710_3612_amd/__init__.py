@@ -12,8 +12,10 @@ Multigrid sections; Results for the smoother, the 4x4 blocks and MG-CG).
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from pathlib import Path
 from typing import Optional, Sequence
 
@@ -118,6 +120,24 @@ _lib = None
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _allocator = None  # the installed callbacks (kept alive while the library may call them)
+# smg_progress_fn
+_PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_double, ctypes.c_void_p)
+_progress = None  # every installed callback (kept alive while the library may call them)
+
+
+# Handles and batches still open, closed at interpreter exit while the allocator
+# callbacks and torch are still alive (a handle freed during module teardown would
+# call a release callback that may already be gone).
+_live_solvers = weakref.WeakSet()
+_live_batches = weakref.WeakSet()
+
+
+def _close_all():
+    for b in list(_live_batches):
+        b.close()
+    for s in list(_live_solvers):
+        s.close()
 
 
 def load_library():
@@ -145,6 +165,7 @@ def load_library():
         "smg_apply_A": (i32, [h, P, P, i32, P]),
         "smg_apply_level": (i32, [h, i32, P, P, i32, P]),
         "smg_apply_level_f32": (i32, [h, i32, P, P, i32, P]),
+        "smg_level_op": (i32, [h, i32, i32, ctypes.c_double, P, P, P, P, i32, P]),
         "smg_level_op_f32": (i32, [h, i32, i32, ctypes.c_double, P, P, P, P, i32, P]),
         "smg_restrict": (i32, [h, i32, P, P, i32, P]),
         "smg_prolong": (i32, [h, i32, P, P, i32, P]),
@@ -164,6 +185,7 @@ def load_library():
         "smg_query_bytes": (i32, [ctypes.POINTER(Params), i32, i32, ctypes.POINTER(ctypes.c_size_t),
                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "smg_set_allocator": (i32, [_ALLOC_FN, _RELEASE_FN, P]),
+        "smg_set_progress": (i32, [_PROGRESS_FN, P]),
         "smg_batch_create": (i32, [h, i32, ctypes.c_double, i32, i32, P, ctypes.POINTER(h)]),
         "smg_batch_admit": (i32, [h, P, ctypes.POINTER(i32), P]),
         "smg_batch_step": (i32, [h, i32, P]),
@@ -184,6 +206,7 @@ def load_library():
         fn.argtypes = args
     _lib = lib
     use_torch_allocator(True)
+    atexit.register(_close_all)  # runs before torch's own exit handlers, registered earlier
     return lib
 
 
@@ -220,6 +243,26 @@ def use_torch_allocator(enable: bool = True):
         _allocator = (cbs, _allocator)
     else:
         _check(lib.smg_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None))
+
+
+def set_progress(fn=None):
+    """Install fn(stage, level, step, total, value) as the library's progress
+    callback (smg_set_progress: setup levels and vectors, outer iterations,
+    defect-correction passes), or turn reporting off with None.  fn runs on the
+    thread that made the library call and must not call the library."""
+    global _progress
+    lib = load_library()
+    if fn is None:
+        _check(lib.smg_set_progress(_PROGRESS_FN(), None))
+        return
+
+    def cb(stage, level, step, total, value, _ctx):
+        fn(stage.decode(), level, step, total, value)
+
+    c = _PROGRESS_FN(cb)
+    _check(lib.smg_set_progress(c, None))
+    # a call on another thread may still be inside an earlier callback: keep every one alive
+    _progress = (c, _progress)
 
 
 def query_bytes(params: "Params", nrhs: int = 1, precision: int = FP64):
@@ -320,6 +363,7 @@ class Solver:
             code = self.lib.smg_setup(_ptr(g), ctypes.byref(params), rp, st, ctypes.byref(self.handle))
         _check(code)
         self._torch = torch
+        _live_solvers.add(self)
 
     # -- lifetime ---------------------------------------------------------------
     def close(self):
@@ -328,6 +372,10 @@ class Solver:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
+        import sys
+
+        if sys.is_finalizing():  # closed at exit already, or the process is ending
+            return
         try:
             self.close()
         except Exception:
@@ -374,6 +422,7 @@ class Solver:
         other.handle = ctypes.c_void_p()
         other._torch = self._torch
         _check(self.lib.smg_derive(self.handle, float(mass), _stream(stream), ctypes.byref(other.handle)))
+        _live_solvers.add(other)
         return other
 
     def apply_D(self, x, dagger: bool = False, stream=None):
@@ -404,6 +453,22 @@ class Solver:
         y = torch.empty_like(x)
         _check(self.lib.smg_apply_level_f32(self.handle, level, ctypes.c_void_p(x.data_ptr()),
                                             ctypes.c_void_p(y.data_ptr()), nr, _stream(stream)))
+        return y
+
+    def level_op(self, level: int, x, mode: int = 0, coef: float = 0.0, xacc=None, aux=None, stream=None):
+        """FP64 level operator with the V-cycle's epilogues (smg_level_op);
+        complex128 tensors; returns y (xacc is updated in place for modes 1 and 3)."""
+        def p64(t):
+            if t is None:
+                return ctypes.c_void_p()
+            if not t.is_cuda or t.dtype != self._torch.complex128 or not t.is_contiguous():
+                raise TypeError("expected a contiguous complex128 CUDA tensor")
+            return ctypes.c_void_p(t.data_ptr())
+
+        nr = self._nrhs(x, self.level_size(level))
+        y = self._torch.empty_like(x)
+        _check(self.lib.smg_level_op(self.handle, level, int(mode), float(coef), p64(x), p64(y), p64(xacc),
+                                     p64(aux), nr, _stream(stream)))
         return y
 
     def level_op_f32(self, level: int, x, mode: int = 0, coef: float = 0.0, xacc=None, aux=None, stream=None):
@@ -556,6 +621,7 @@ class Batch:
                                          _stream(stream), ctypes.byref(self.handle)))
         self._stats = (Stats * self.capacity)()
         self._done = (ctypes.c_uint8 * self.capacity)()
+        _live_batches.add(self)
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -563,6 +629,10 @@ class Batch:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
+        import sys
+
+        if sys.is_finalizing():  # closed at exit already, or the process is ending
+            return
         try:
             self.close()
         except Exception:

@@ -844,77 +844,6 @@ __global__ void k_gj_update(z64* __restrict__ M, int n, int k, const z64* __rest
   }
 }
 
-// Y = M X for nrhs columns (M dense row-major n x n, X and Y [nrhs][n]): the
-// coarsest solve with the explicit inverse.  A workgroup computes a 64-row x
-// 32-column tile; tiles of M (64 x 16) and X (32 x 16) pass through LDS, so M is
-// read once per 32 columns and X once per 64 rows.  Every output accumulates its
-// products in the order j = 0, 1, ..., n-1 with explicit FMAs, so a column's
-// result does not depend on nrhs or on the other columns.
-constexpr int kGemmTR = 64, kGemmTC = 32, kGemmTJ = 16;
-
-template <typename RM, typename R, typename TM = cpx<RM>>
-__global__ void __launch_bounds__(kThreads) k_dense_gemm(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                         cpx<R>* __restrict__ y, int n, int nrhs, double mscale) {
-  __shared__ cpx<RM> Ms[kGemmTJ][kGemmTR + 1];
-  __shared__ cpx<RM> Xs[kGemmTJ][kGemmTC + 1];
-  const int r0 = blockIdx.x * kGemmTR, c0 = blockIdx.y * kGemmTC;
-  const int t = threadIdx.x;
-  const int tr = t & 31, tc = t >> 5;  // rows tr, tr + 32; columns tc + 8k
-  RM are[2][4], aim[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) are[a][k] = aim[a][k] = 0;
-  for (int j0 = 0; j0 < n; j0 += kGemmTJ) {
-#pragma unroll
-    for (int q = 0; q < kGemmTR * kGemmTJ / kThreads; ++q) {
-      const int e = t + q * kThreads;
-      const int row = e / kGemmTJ, jj = e % kGemmTJ;
-      const int gr = r0 + row, gj = j0 + jj;
-      Ms[jj][row] = (gr < n && gj < n) ? widen(M[(size_t)gr * n + gj]) : mk<RM>(0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < kGemmTC * kGemmTJ / kThreads; ++q) {
-      const int e = t + q * kThreads;
-      const int col = e / kGemmTJ, jj = e % kGemmTJ;
-      const int gc = c0 + col, gj = j0 + jj;
-      cpx<RM> v = mk<RM>(0, 0);
-      if (gc < nrhs && gj < n) {
-        const cpx<R> u = x[(size_t)gc * n + gj];
-        v = mk<RM>((RM)u.re, (RM)u.im);
-      }
-      Xs[jj][col] = v;
-    }
-    __syncthreads();
-    const int jn = min(kGemmTJ, n - j0);
-    for (int jj = 0; jj < jn; ++jj) {
-      cpx<RM> m[2], v[4];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) m[a] = Ms[jj][tr + 32 * a];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = Xs[jj][tc + 8 * k];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          are[a][k] = fma(m[a].re, v[k].re, are[a][k]);
-          are[a][k] = fma(-m[a].im, v[k].im, are[a][k]);
-          aim[a][k] = fma(m[a].re, v[k].im, aim[a][k]);
-          aim[a][k] = fma(m[a].im, v[k].re, aim[a][k]);
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int gr = r0 + tr + 32 * a, gc = c0 + tc + 8 * k;
-      if (gr < n && gc < nrhs)
-        y[(size_t)gc * n + gr] = mk<R>((R)(mscale * are[a][k]), (R)(mscale * aim[a][k]));
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Utilities.
 // ---------------------------------------------------------------------------
@@ -1377,6 +1306,139 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
     launch_coarse_mfma_s<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-RHS FP64 coarse operator on the matrix cores (Eq. 2 for the FP64 solves
+// of many right-hand sides).  One wave computes one coarse site K for 16 RT
+// right-hand sides.  For each link direction D the complex product
+// Y += L_{K,D} V_{K+D} is the real GEMM [Yr; Yi] += [[Lr, -Li], [Li, Lr]] [Vr; Vi]
+// done with v_mfma_f64_16x16x4f64: the output rows are the nc <= 16 variables
+// (one tile for Re, one for Im), the columns 16 right-hand sides, and K-step s
+// covers link columns 4s..4s+3, against Vr and then against Vi.  Lane layout:
+// A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, accumulator r of lane l
+// holds row 4r + l/16, column l%16 (checked on the device).  Every link is loaded once per 16 RT
+// right-hand sides; the neighbours' vector entries are read straight from memory
+// (the eight other sites that read them run close by, so they come from L2), the
+// next direction's operands while this direction's MFMAs run.  FP64 MFMA has the
+// FP64 vector peak of this chip; what the matrix cores save is the broadcast of
+// link and vector entries across lanes that a vector-ALU kernel needs.
+// ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int MODE, int RT>
+__global__ void __launch_bounds__(256) k_coarse_mfma64(const z64* __restrict__ L, const z64* __restrict__ v,
+                                                       z64* __restrict__ y, int cx, int ct, int nc, int nrhs,
+                                                       double c, double c2, z64* __restrict__ xacc,
+                                                       const z64* __restrict__ aux) {
+  const int nK = cx * ct;
+  const size_t n = (size_t)nK * nc;
+  const int K = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (K >= nK) return;  // wave-uniform, and no barrier follows
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const int rhs0 = blockIdx.y * 16 * RT;
+  const int kx = K % cx, kt = K / cx;
+  const int irow = i < nc ? i : nc - 1;  // clamped: every lane loads a valid address, masked after
+  const bool row_ok = i < nc;
+  int rj[RT];
+  bool rj_ok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = rhs0 + 16 * rt + i;
+    rj_ok[rt] = r < nrhs;
+    rj[rt] = r < nrhs ? r : nrhs - 1;
+  }
+  auto load = [&](int D, z64 (&l)[4], z64 (&b)[RT][4]) {
+    const int dt = D / 3 - 1, dx = D % 3 - 1;
+    const int gx = ((kx + dx) % cx + cx) % cx, gt = ((kt + dt) % ct + ct) % ct;
+    const size_t nb = (size_t)(gt * cx + gx) * nc;
+    const z64* LD = L + (size_t)D * nc * n + (size_t)K * nc + irow;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = 4 * s + kq;
+      const z64 t = LD[(size_t)(col < nc ? col : nc - 1) * n];
+      const bool ok = row_ok && col < nc;
+      l[s] = mk<double>(ok ? t.re : 0.0, ok ? t.im : 0.0);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const z64 u = v[(size_t)rj[rt] * n + nb + (col < nc ? col : nc - 1)];
+        const bool uok = rj_ok[rt] && col < nc;
+        b[rt][s] = mk<double>(uok ? u.re : 0.0, uok ? u.im : 0.0);
+      }
+    }
+  };
+  doublex4 accR[RT], accI[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      accR[rt][r] = 0.0;
+      accI[rt][r] = 0.0;
+    }
+  z64 la[4], lb[4], ba[RT][4], bb[RT][4];
+  load(0, la, ba);
+#pragma unroll
+  for (int D = 0; D < 9; ++D) {
+    z64(&l)[4] = (D & 1) ? lb : la;
+    z64(&b)[RT][4] = (D & 1) ? bb : ba;
+    if (D < 8) load(D + 1, (D & 1) ? la : lb, (D & 1) ? ba : bb);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[s].re, b[rt][s].re, accR[rt], 0, 0, 0);
+        accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l[s].im, b[rt][s].im, accR[rt], 0, 0, 0);
+        accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[s].im, b[rt][s].re, accI[rt], 0, 0, 0);
+        accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[s].re, b[rt][s].im, accI[rt], 0, 0, 0);
+      }
+  }
+  // ---- epilogue: lane holds right-hand side rhs0 + 16 rt + i, variables 4 r + kq
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    if (!rj_ok[rt]) continue;
+    const size_t ob = (size_t)rj[rt] * n + (size_t)K * nc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int dof = 4 * r + kq;
+      if (dof >= nc) continue;
+      const z64 sum = mk<double>(accR[rt][r], accI[rt][r]);
+      const size_t o = ob + dof;
+      if (MODE == 0) {
+        y[o] = sum;
+      } else if (MODE == 1 || MODE == 3) {
+        const z64 vi = v[o];
+        xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
+        y[o] = vi - c * sum;
+      } else if (MODE == 4 || MODE == 5) {
+        const z64 vi = v[o];
+        const z64 a = MODE == 5 ? c * vi : xacc[o] + c * vi;
+        xacc[o] = a + c2 * (vi - c * sum);
+      } else {
+        y[o] = aux[o] - sum;
+      }
+    }
+  }
+}
+
+// 16, 32 or 64 right-hand sides per wave (one link load each), by the column count.
+void launch_coarse_mfma64(const z64* L, const z64* x, z64* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                          z64* xacc, const z64* aux, hipStream_t st, double c2) {
+  if (nc < 1 || nc > 16) throw Error(-1, "FP64 matrix-core coarse apply needs 1 <= nc <= 16");
+  if (nrhs < 1) return;
+  const long nK = (long)cx * ct;
+  const int rt = nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+  const dim3 grid((unsigned)((nK + 3) / 4), (unsigned)((nrhs + 16 * rt - 1) / (16 * rt)));
+  with_mode(mode, [&](auto m) {
+    constexpr int M = decltype(m)::v;
+    if (rt == 1)
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 1>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+    else if (rt == 2)
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 2>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+    else
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 4>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename R, typename TL>
 void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
                      double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
@@ -1646,6 +1708,93 @@ __global__ void __launch_bounds__(256) k_dense_mfma(const TM* __restrict__ M, co
   }
 }
 
+// Y = M X in FP64 on the matrix cores for the large coarsest inverses (n >
+// kDenseRowsMax), the FP64 counterpart of k_dense_mfma.  A workgroup owns 32 rows x
+// 32 right-hand sides as 2 x 2 tiles of v_mfma_f64_16x16x4f64 (layout of
+// k_coarse_mfma64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// accumulator r of lane l is row 4r + l/16, column l%16); per step of 4 complex k
+// the real embedding takes four instructions per tile: Mr Xr and -Mi Xi into Re Y,
+// Mi Xr and Mr Xi into Im Y.  The four waves each take a quarter of the k range (a
+// multiple of 4, set by n alone) and meet in LDS in a fixed order, so a column's
+// result does not depend on nrhs.  Operands of a step are loaded three steps ahead.
+// The vectors are FP64, or FP32 (the FP64 inverse inside the FP32 V-cycle), widened
+// on load and rounded on store.
+template <typename R>
+__global__ void __launch_bounds__(256) k_dense_mfma64(const z64* __restrict__ M, const cpx<R>* __restrict__ x,
+                                                      cpx<R>* __restrict__ y, int n, int nrhs) {
+  __shared__ double red[3][8][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const z64* Mr[2] = {M + (size_t)min(r0 + i, n - 1) * n, M + (size_t)min(r0 + 16 + i, n - 1) * n};
+  const cpx<R>* Xc[2] = {x + (size_t)min(c0 + i, nrhs - 1) * n, x + (size_t)min(c0 + 16 + i, nrhs - 1) * n};
+  const int kw = ((n + 15) / 16) * 4;  // k per wave, a multiple of 4
+  const int kb = w * kw, ke = min(n, kb + kw);
+  doublex4 acc[2][2][2];  // [row tile][rhs tile][Re, Im]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][0][r] = acc[a][b][1][r] = 0.0;
+  constexpr int D = 4;  // ring of steps in flight
+  z64 mb[D][2];
+  cpx<R> vb[D][2];
+  auto load = [&](int d, int k0) {
+    const int k = min(k0 + kq, n - 1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      mb[d][t] = Mr[t][k];
+      vb[d][t] = Xc[t][k];
+    }
+  };
+#pragma unroll
+  for (int d = 0; d + 1 < D; ++d) load(d, kb + 4 * d);
+  for (int k4 = kb; k4 < ke; k4 += 4 * D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      load((d + D - 1) % D, k4 + 4 * (d + D - 1));
+      __builtin_amdgcn_sched_barrier(0);  // keep the refill where it is issued
+      const double am = (k4 + 4 * d + kq < ke) ? 1.0 : 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double mre = am * mb[d][a].re, mim = am * mb[d][a].im;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const z64 v = mk<double>((double)vb[d][b].re, (double)vb[d][b].im);
+          acc[a][b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(mre, v.re, acc[a][b][0], 0, 0, 0);
+          acc[a][b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-mim, v.im, acc[a][b][0], 0, 0, 0);
+          acc[a][b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(mim, v.re, acc[a][b][1], 0, 0, 0);
+          acc[a][b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(mre, v.im, acc[a][b][1], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[w - 1][q][r][lane] = acc[q >> 2][(q >> 1) & 1][q & 1][r];
+  }
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = c0 + 16 * b + i;
+      const int q = 4 * a + 2 * b;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 16 * a + 4 * r + kq;
+        const double re = ((acc[a][b][0][r] + red[0][q][r][lane]) + red[1][q][r][lane]) + red[2][q][r][lane];
+        const double im =
+            ((acc[a][b][1][r] + red[0][q + 1][r][lane]) + red[1][q + 1][r][lane]) + red[2][q + 1][r][lane];
+        if (row < n && col < nrhs) y[(size_t)col * n + row] = mk<R>((R)re, (R)im);
+      }
+    }
+}
+
 // mscale: power-of-two scale of a reduced-precision M (1 otherwise), applied exactly.
 template <typename RM, typename R, typename TM>
 void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
@@ -1671,8 +1820,10 @@ void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
     hipLaunchKernelGGL((k_dense_mfma<TM>), grid, dim3(256), 0, st, M, x, y, n, nrhs, (float)mscale);
   } else {
-    dim3 grid((unsigned)((n + kGemmTR - 1) / kGemmTR), (unsigned)((nrhs + kGemmTC - 1) / kGemmTC));
-    hipLaunchKernelGGL((k_dense_gemm<RM, R, TM>), grid, dim3(kThreads), 0, st, M, x, y, n, nrhs, mscale);
+    static_assert(std::is_same<TM, z64>::value || std::is_same<R, float>::value,
+                  "an FP32 or FP16 inverse is applied to FP32 vectors only");
+    dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
+    hipLaunchKernelGGL((k_dense_mfma64<R>), grid, dim3(256), 0, st, M, x, y, n, nrhs);
   }
   HIPCHECK(hipGetLastError());
 }

@@ -62,6 +62,23 @@ Allocator current_allocator() {
   return g_alloc;
 }
 
+// Progress reporting of long calls (smg_set_progress).  The callback is read under
+// the lock and called outside it, on the calling thread.
+std::mutex g_progress_mu;
+smg_progress_fn g_progress = nullptr;
+void* g_progress_ctx = nullptr;
+
+void report(const char* stage, int level, int step, int total, double value) {
+  smg_progress_fn fn;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_progress_mu);
+    fn = g_progress;
+    ctx = g_progress_ctx;
+  }
+  if (fn) fn(stage, level, step, total, value, ctx);
+}
+
 struct Pool {
   Allocator a = current_allocator();  // the allocator in force when the owner was created
   bool dry = false;
@@ -390,9 +407,9 @@ void ensure_dc(Ctx& c, size_t elems) {
 // ---------------------------------------------------------------------------
 // Operators.
 // ---------------------------------------------------------------------------
-// FP32 coarse applies of many right-hand sides go to the matrix cores.  A batch
-// pins the choice for all its V-cycles (mfma_pin), so that a column's rounding
-// does not depend on how many other columns run beside it.
+// Coarse applies of many right-hand sides (FP32 and FP64) go to the matrix cores.
+// A batch pins the choice for all its V-cycles (mfma_pin), so that a column's
+// rounding does not depend on how many other columns run beside it.
 bool use_mfma(const Ctx& c, int nc, int nrhs) {
   if (nc > 16) return false;
   if (c.mfma_pin >= 0) return c.mfma_pin == 1;
@@ -414,6 +431,11 @@ void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mo
     }
     if (lv.L16) {
       launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
+      return;
+    }
+  } else {
+    if (use_mfma(c, lv.dof, nrhs)) {
+      launch_coarse_mfma64(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
       return;
     }
   }
@@ -734,6 +756,12 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
           S.rr_host[2 * j + 1] = 0;
         }
       }
+      if (depth == 0) {  // the outer solve: largest recursive relative residual of the running columns
+        double worst = 0;
+        for (int j = 0; j < nrhs; ++j)
+          if (act[j] && hbb[j] > 0) worst = std::max(worst, std::sqrt(std::max(S.rr_host[2 * j], 0.0) / hbb[j]));
+        report("iteration", l, it, maxiter, worst);
+      }
       std::vector<int> cand(nrhs, 0);
       bool any_cand = false;
       for (int j = 0; j < nrhs; ++j) {
@@ -834,6 +862,13 @@ void coarse_cg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, 
   } else {
     pcg<R>(c, l, b, x, nrhs, tol, maxiter, false, v, &cs, 8, 1);
   }
+  int most = 0;
+  double worst = 0;
+  for (int j = 0; j < nrhs; ++j) {
+    most = std::max(most, cs.iters[j]);
+    worst = std::max(worst, cs.relres[j]);
+  }
+  report("coarsest-cg", l, most, maxiter, worst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1077,6 +1112,7 @@ void adaptive_level(Ctx& c, int l, const z64* rnd) {
   set_nc(c, l, m);
   gs_append(c, l, c.se, 0);
   galerkin(c, l);
+  report("candidate", l, 1, nv, 0.0);
   // at most the variables of an aggregate (fewer per site when the level above stopped early)
   const int nmax = std::min(nv, lv.bx * lv.bt * lv.dof / m);
   // further candidates: the current two-level V-cycle as error propagator; with
@@ -1097,6 +1133,7 @@ void adaptive_level(Ctx& c, int l, const z64* rnd) {
     gs_append(c, l, c.se, k);
     set_nc(c, l, m * (k + 1));
     galerkin(c, l);
+    report("candidate", l, k + 1, nv, c.factors[l].empty() ? 0.0 : c.factors[l].back());
   }
 }
 
@@ -1567,14 +1604,14 @@ void batch_precondition(Batch& B, int j0, int cnt, hipStream_t st) {
     return;
   }
   const bool cg = c.prm.coarsest == SMG_COARSEST_CG;
+  struct Pin {  // restored on every exit path
+    Ctx& c;
+    ~Pin() { c.mfma_pin = -1; }
+  } pin{c};
+  c.mfma_pin = (c.prm.mfma_min_rhs > 0 && B.cap >= c.prm.mfma_min_rhs) ? 1 : 0;
   if (B.prec == SMG_FP64) {
     vcycle<double>(c, 0, c.nlev - 1, B.r + off, B.z + off, cnt, cg);
   } else {
-    struct Pin {  // restored on every exit path
-      Ctx& c;
-      ~Pin() { c.mfma_pin = -1; }
-    } pin{c};
-    c.mfma_pin = (c.prm.mfma_min_rhs > 0 && B.cap >= c.prm.mfma_min_rhs) ? 1 : 0;
     launch_convert<float, double>(B.r + off, B.r32 + off, (size_t)cnt * B.n, st);
     vcycle<float>(c, 0, c.nlev - 1, B.r32 + off, B.z32v + off, cnt, cg);
     launch_convert<double, float>(B.z32v + off, B.z + off, (size_t)cnt * B.n, st);
@@ -1850,11 +1887,13 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
       }
       HIPCHECK(hipMemcpyAsync(c->calib[l], rnd, n * sizeof(z64), hipMemcpyDeviceToDevice, st));  // row 0
       calibrate(*c, l);
+      report("calibrate", l, 0, nv, 0.0);
       sa_weight(*c, l);
       adaptive_level(*c, l, rnd);
     }
     build_mass_coefficients(*c);
     finish_setup(*c);
+    report("coarsest", c->nlev - 1, 0, 0, 0.0);
     c->c64 = KVecs<double>{};
   } catch (...) {
     delete c;
@@ -1983,6 +2022,22 @@ int smg_apply_level(smg_handle h, int32_t level, const double* x, double* y, int
   c->st = (hipStream_t)stream;
   ensure_level_work<double>(*c, nrhs);
   apply_op<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs, 0, 0.0, nullptr, nullptr);
+  return SMG_OK;
+  API_END
+}
+
+int smg_level_op(smg_handle h, int32_t level, int32_t mode, double coef, const double* x, double* y, double* xacc,
+                 const double* aux, int32_t nrhs, void* stream) {
+  API_BEGIN
+  Ctx* c = H(h);
+  check_level(c, level);
+  check_nrhs(nrhs);
+  if (mode < 0 || mode > 3) throw Error(SMG_EINVAL, "mode must be 0, 1, 2 or 3");
+  if (!x || !y || ((mode == 1 || mode == 3) && !xacc) || (mode == 2 && !aux)) throw Error(SMG_EINVAL, "null vector");
+  if (!std::isfinite(coef)) throw Error(SMG_EINVAL, "coef must be finite");
+  c->st = (hipStream_t)stream;
+  ensure_level_work<double>(*c, nrhs);
+  apply_op<double>(*c, c->L64[level], (const z64*)x, (z64*)y, nrhs, mode, coef, (z64*)xacc, (const z64*)aux);
   return SMG_OK;
   API_END
 }
@@ -2165,6 +2220,11 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
         up[j] = std::sqrt(rr);
         ++nact;
       }
+      if (refinements > 0) {  // true relative residual after this many passes (largest column)
+        double worst = 0;
+        for (int j = 0; j < nrhs; ++j) worst = std::max(worst, rel[j]);
+        report("refinement", 0, refinements, maxiter, worst);
+      }
       if (nact == 0 || used >= maxiter) break;
       // the same scales on the device, from the same |r|^2 and this decision (no copy)
       for (int j = 0; j < nrhs; ++j) c->sc[1].on_host[j] = down[j] != 0 ? 1 : 0;
@@ -2306,6 +2366,15 @@ int smg_set_allocator(smg_alloc_fn alloc, smg_release_fn release, void* ctx) {
   g_alloc.alloc = alloc;
   g_alloc.release = release;
   g_alloc.ctx = alloc ? ctx : nullptr;
+  return SMG_OK;
+  API_END
+}
+
+int smg_set_progress(smg_progress_fn fn, void* ctx) {
+  API_BEGIN
+  std::lock_guard<std::mutex> lk(g_progress_mu);
+  g_progress = fn;
+  g_progress_ctx = ctx;
   return SMG_OK;
   API_END
 }

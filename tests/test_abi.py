@@ -174,3 +174,13 @@ def test_set_allocator_needs_both_callbacks():
     fn = smg._ALLOC_FN(lambda n, s, c: None)
     assert lib.smg_set_allocator(fn, smg._RELEASE_FN(), None) == -1
     smg.use_torch_allocator(True)
+
+
+def test_set_progress_installs_and_clears():
+    """smg_set_progress takes a callback and NULL; installing one calls nothing."""
+    import paper_0710_3612_amd as smg
+
+    seen = []
+    smg.set_progress(lambda *a: seen.append(a))
+    smg.set_progress(None)
+    assert seen == []

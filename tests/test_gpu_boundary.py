@@ -118,3 +118,67 @@ def test_library_memory_is_torch_memory(cuda):
     s.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() - base < used // 2
+
+
+def test_progress_reports_setup_and_solve(cuda):
+    """The progress callback sees every level's calibration, each near-null vector as
+    it is added (1..nv in order), the end of the setup, the outer iterations with
+    their largest relative residual, and the defect-correction passes of a mixed
+    solve; with reporting off it sees nothing."""
+    smg = smg_mod()
+    lx = lt = 64
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 5, 9))
+    p = smg.make_params(lx, lt, 0.1, levels=3, blocks=[(4, 4), (4, 4)], nv=[5, 4])
+    ev = []
+    smg.set_progress(lambda *a: ev.append(a))
+    try:
+        with smg.Solver(dev(U), p) as s:
+            setup = list(ev)
+            ev.clear()
+            b = dev(synth.gaussian((2, 2 * lx * lt), 6))
+            _, st, _ = s.solve(b, tol=1e-10, maxiter=200, precision=0)
+            fp64 = list(ev)
+            ev.clear()
+            s.solve(b, tol=1e-10, maxiter=200, precision=1)
+            mixed = list(ev)
+            ev.clear()
+            smg.set_progress(None)
+            s.solve(b, tol=1e-10, maxiter=200, precision=0)
+            assert ev == []
+    finally:
+        smg.set_progress(None)
+    for l, nv in enumerate([5, 4]):
+        assert ("calibrate", l, 0, nv, 0.0) in setup
+        assert [e[2] for e in setup if e[0] == "candidate" and e[1] == l] == list(range(1, nv + 1))
+    assert setup[-1][0] == "coarsest"
+    its = [e for e in fp64 if e[0] == "iteration"]
+    assert [e[2] for e in its] == list(range(1, len(its) + 1))
+    assert len(its) == max(int(x["iterations"]) for x in st)
+    assert its[-1][4] < its[0][4]
+    ref = [e for e in mixed if e[0] == "refinement"]
+    assert ref and [e[2] for e in ref] == list(range(1, len(ref) + 1))
+    assert ref[-1][4] <= 1e-10
+
+
+def test_open_handles_at_exit(cuda, tmp_path):
+    """A program that ends with a handle and a batch still open exits cleanly: the
+    binding closes them at exit, while the allocator callbacks that release their
+    memory are still alive (module teardown would free those callbacks first)."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    prog = (
+        "import numpy as np, torch, synth, paper_0710_3612_amd as smg\n"
+        "U = synth.links_from_angles(synth.metropolis_u1(32, 32, 3.0, 5, 1))\n"
+        "p = smg.make_params(32, 32, 0.1, levels=2, blocks=[(4, 4)], nv=[4])\n"
+        "s = smg.Solver(torch.from_numpy(U).to('cuda'), p)\n"
+        "d = s.derive(0.2)\n"
+        "b = smg.Batch(s, 2)\n"
+        "smg.set_progress(lambda *a: None)\n"
+        "print('ok', flush=True)\n"
+    )
+    r = subprocess.run([sys.executable, "-c", prog], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip() == "ok"

@@ -1,4 +1,4 @@
-"""GPU: the matrix-core (MFMA FP32) coarse operator against the FP64 oracle.
+"""GPU: the matrix-core coarse operators (MFMA FP32 and FP64) against the FP64 oracle.
 
 The coarse operator of Eq. 2 applied to many right-hand sides runs on
 v_mfma_f32_32x32x2f32 for levels with nc <= 16.  Each mode (plain apply, one
@@ -9,7 +9,9 @@ most 9 * 16 complex products, so 2e-5 of the column's largest entry bounds the
 difference with a wide margin.  Cases cover nc = 16, 12 and an odd nc = 5, tiles
 cut by the lattice edge (coarse extents not multiples of the tile), both tile
 shapes (2x2 on small coarse lattices, 4x4 from 64x64 sites), and right-hand-side
-counts that are not multiples of 32.
+counts that are not multiples of 32.  The FP64 operator of many right-hand sides
+runs on v_mfma_f64_16x16x4f64; its modes are held to 1e-12 of the column's largest
+entry (FP64 inputs and links, the same sums).
 """
 
 import numpy as np
@@ -171,3 +173,67 @@ def test_fp16_link_coarse_modes(hier, nrhs):
         assert colerr(y1, x64 - coef * Ax) <= TOL16, (level, "mode 1")
         assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (level, "mode 1 acc")
         assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL16, (level, "mode 2")
+
+
+TOL64 = 1e-12  # FP64 inputs and links; sums of at most 9 * 16 complex products
+
+
+@pytest.mark.parametrize("nrhs", [16, 33, 64, 70, 1])
+def test_mfma64_coarse_modes(hier, nrhs):
+    """FP64 coarse operator on the matrix cores (v_mfma_f64_16x16x4f64, 16, 32 or
+    64 right-hand sides per wave) against the oracle's sparse coarse matrix for
+    every mode, and against the vector-ALU FP64 kernel; counts that are not
+    multiples of 16 leave masked columns in the last wave."""
+    import torch
+
+    for level in range(1, hier["nlev"]):
+        Ac = hier["h"].levels[level].A
+        n = Ac.shape[0]
+        rng = np.random.default_rng(level * 300 + nrhs)
+        x = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+        aux = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+        acc0 = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
+        coef = 0.37
+        Ax = np.stack([Ac @ x[j] for j in range(nrhs)])
+        got = {}
+        for name in ("mfma", "valu"):
+            s = hier[name]
+            xt = dev(x)
+            y0 = host(s.level_op(level, xt, mode=0)).reshape(nrhs, n)
+            xacc = dev(acc0)
+            y1 = host(s.level_op(level, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
+            a1 = host(xacc).reshape(nrhs, n)
+            y2 = host(s.level_op(level, xt, mode=2, aux=dev(aux))).reshape(nrhs, n)
+            xacc3 = dev(acc0)
+            y3 = host(s.level_op(level, xt, mode=3, coef=coef, xacc=xacc3)).reshape(nrhs, n)
+            a3 = host(xacc3).reshape(nrhs, n)
+            torch.cuda.synchronize()
+            assert colerr(y0, Ax) <= TOL64, (name, level, "mode 0")
+            assert colerr(y1, x - coef * Ax) <= TOL64, (name, level, "mode 1")
+            assert colerr(a1, acc0 + coef * x) <= TOL64, (name, level, "mode 1 acc")
+            assert colerr(y2, aux - Ax) <= TOL64, (name, level, "mode 2")
+            assert colerr(y3, x - coef * Ax) <= TOL64, (name, level, "mode 3")
+            assert colerr(a3, coef * x) <= TOL64, (name, level, "mode 3 acc")
+            got[name] = y0
+        assert colerr(got["mfma"], got["valu"]) <= TOL64
+
+
+def test_mfma64_fp64_solve_many_rhs(hier):
+    """FP64 MG-CG of 40 right-hand sides whose coarse levels run on the FP64 matrix
+    cores: every sampled column reaches 1e-10 against the oracle's A, and the
+    solutions agree with the vector-ALU path to the accuracy both reached."""
+    import paper_0710_3612_amd as smg
+
+    A = hier["A"]
+    n = A.shape[0]
+    B = synth.gaussian((40, n), 4343)
+    xs = {}
+    for name in ("mfma", "valu"):
+        x, st, code = hier[name].solve(dev(B), tol=1e-10, maxiter=500, precision=smg.FP64)
+        assert code == 0
+        xh = host(x).reshape(40, n)
+        for j in range(0, 40, 7):
+            assert np.linalg.norm(B[j] - A @ xh[j]) / np.linalg.norm(B[j]) <= 1e-10
+        xs[name] = xh
+    d = np.linalg.norm(xs["mfma"] - xs["valu"], axis=1) / np.linalg.norm(xs["valu"], axis=1)
+    assert d.max() < 1e-6

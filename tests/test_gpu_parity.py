@@ -637,3 +637,32 @@ def test_fp32_vcycle_large_coarsest_matrix_cores(opst, c64):
             assert rel_err(xb[j], ref) <= bound, (j, rel_err(xb[j], ref))
     finally:
         s.close()
+
+
+def test_fp64_vcycle_large_coarsest_matrix_cores():
+    """FP64 V-cycle whose 5120-variable coarsest inverse is applied on the FP64
+    matrix cores (n above the row-kernel limit): within 1e-11 of the oracle's
+    V-cycle for 1 and 33 right-hand sides (two column tiles, the second ragged), and
+    a column's result is bitwise the same alone and inside the batch."""
+    import torch
+
+    smg = smg_mod()
+    lx, lt, blocks, nvs, m = 64, 64, [(2, 2)], [5], 0.1
+    U = field(lx, lt, seed=61)
+    vecs, calib = hierarchy_inputs(lx, lt, blocks, nvs, 63)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, vecs, calib, nu=4, omega=0.8, sa_scale=4 / 3)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=blocks, nv=nvs)
+    s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])), calib=dev(np.concatenate(calib)))
+    try:
+        assert s.level_size(1) == 5120
+        n = s.level_size(0)
+        b = synth.gaussian((33, n), 68)
+        xa = host(s.vcycle(torch.from_numpy(b[:1].copy()).to("cuda"))).reshape(1, -1)
+        xb = host(s.vcycle(torch.from_numpy(b).to("cuda"))).reshape(33, -1)
+        assert np.array_equal(xa[0], xb[0])
+        for j in (0, 17, 32):
+            ref = mg.vcycle(h, 0, b[j])
+            assert rel_err(xb[j], ref) <= 1e-11, (j, rel_err(xb[j], ref))
+    finally:
+        s.close()
