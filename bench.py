@@ -94,7 +94,7 @@ C5_BETA = 10.0
 C5_SWEEPS = 1000
 C5_SEED = 5000
 C5_NRHS = 64
-C5_MASS = -0.03
+C5_MASS = -0.027
 C5_BLOCKS = [(4, 4), (2, 2), (2, 2)]
 C5_NV = [16, 16, 16]
 
@@ -302,6 +302,15 @@ def mrhs_leg(args, torch, smg, dev, U):
     mfma = dict(kernel=f"coarse operator on the matrix cores (k_coarse_mfma), {cx}x{ct} sites, nc={nc}, "
                        f"{MRHS_NRHS} RHS, FP32", bound="mfma", achieved=flops / dur / 1e12, peak=157.3,
                 unit="TFLOP/s", frac=flops / dur / 1e12 / 157.3, avg_launch_us=dur * 1e6, flops_per_launch=flops)
+    # the same operator in FP64 (the plain solve's) on the FP64 matrix cores
+    v64 = torch.randn(MRHS_NRHS * nl, dtype=torch.complex128, device=dev)
+    y64 = torch.empty_like(v64)
+    qx, qy = ctypes.c_void_p(v64.data_ptr()), ctypes.c_void_p(y64.data_ptr())
+    dur64 = timed_events(lambda: lib.smg_level_op(h, 1, 0, 0.0, qx, qy, nul, nul, MRHS_NRHS, sp), 50, stream)
+    mfma64 = dict(kernel=f"k_coarse_mfma64, {cx}x{ct} sites, nc={nc}, {MRHS_NRHS} RHS, FP64", bound="mfma",
+                  achieved=flops / dur64 / 1e12, peak=78.6, unit="TFLOP/s", frac=flops / dur64 / 1e12 / 78.6,
+                  avg_launch_us=dur64 * 1e6)
+    del v64, y64
     s.close()
     del g, eta, rhs, x, v32, y32
     torch.cuda.synchronize()
@@ -310,9 +319,11 @@ def mrhs_leg(args, torch, smg, dev, U):
                           f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
                           f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}; mixed: FP32 inner "
                           f"MG-CG, BF16 storage of the fine smoother iterates, FP16 storage of the prolongators, "
-                          f"coarse links on the matrix cores, the coarsest inverse applied in FP64"),
+                          f"coarse links on the FP32 matrix cores, the coarsest inverse applied in FP64; FP64: "
+                          f"coarse links and the coarsest inverse on the FP64 matrix cores"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
-                mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma)
+                mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma,
+                mfma64=mfma64)
 
 
 def c5_leg(args, torch, smg, dev):
@@ -328,9 +339,12 @@ def c5_leg(args, torch, smg, dev):
 
     t_start = time.perf_counter()
     last = [0.0]
+    coarse_its = []  # iterations of every coarsest CG solve of the current timed solve
 
     def progress(stage, level, step, total, value):
         now = time.perf_counter()
+        if stage == "coarsest-cg":
+            coarse_its.append(step)
         if stage in ("calibrate", "coarsest", "refinement") or now - last[0] > 10.0:
             last[0] = now
             log(f"c5 {stage} level {level}: {step}/{total} ({value:.2e}) at {now - t_start:.0f} s")
@@ -363,18 +377,23 @@ def c5_leg(args, torch, smg, dev):
         # a first pass of one iteration allocates the solve's work vectors
         solver.solve(rhs, tol=TOL, maxiter=1, precision=prec, out=x)
         torch.cuda.synchronize()
+        coarse_its.clear()
         t0 = time.perf_counter()
         _, st, code = solver.solve(rhs, tol=TOL, maxiter=2000, precision=prec, out=x)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        cits = list(coarse_its)
         worst = max(q["true_relres"] for q in st)
         if code != 0 or worst > TOL:
             raise RuntimeError(f"2048^2 {name} solve did not converge: {st[0]}")
         out[name] = dict(solves_per_s=C5_NRHS / dt, seconds=dt,
                          mean_iterations=float(np.mean([q["iterations"] for q in st])),
-                         max_relres=worst, vcycles=int(st[0]["vcycles"]), memory_gb=solver.memory_bytes() / 1e9)
+                         max_relres=worst, vcycles=int(st[0]["vcycles"]), memory_gb=solver.memory_bytes() / 1e9,
+                         coarsest_cg_solves=len(cits), coarsest_cg_iterations=sum(cits),
+                         coarsest_cg_mean=float(np.mean(cits)) if cits else 0.0)
         log(f"c5 {name}: {dt:.2f} s for {C5_NRHS} RHS ({C5_NRHS / dt:.2f} solves/s), "
-            f"{out[name]['mean_iterations']:.1f} iterations, max relres {worst:.2e}")
+            f"{out[name]['mean_iterations']:.1f} iterations, max relres {worst:.2e}, "
+            f"{len(cits)} coarsest CG solves of {out[name]['coarsest_cg_mean']:.0f} iterations on average")
 
     # FP64 on a second handle with the same hierarchy (smg_derive at the same mass), so
     # that the two solves' work vectors are not held at once
@@ -390,6 +409,22 @@ def c5_leg(args, torch, smg, dev):
     fineA = dict(kernel=f"k_normal_fused, {C5_L}^2, {C5_NRHS} RHS, FP64", avg_launch_ms=dur * 1e3,
                  algorithmic_gb=abytes / 1e9, achieved_tb_s=abytes / dur / 1e12, frac=abytes / dur / 8e12)
     log(f"c5 fine A, {C5_NRHS} RHS: {dur * 1e3:.2f} ms, {abytes / dur / 1e12:.2f} TB/s")
+    # the coarse operators of 64 right-hand sides on the FP64 matrix cores (levels 1 and 3)
+    coarse = {}
+    for lev in (1, 3):
+        cx, ct, nc = d.level_info(lev)
+        nl = cx * ct * nc
+        vl = synth.gaussian_device(nl, 13, device=dev, count=C5_NRHS)
+        yl = torch.empty_like(vl)
+        pv, pw = ctypes.c_void_p(vl.data_ptr()), ctypes.c_void_p(yl.data_ptr())
+        nul = ctypes.c_void_p()
+        dl = timed_events(lambda: lib.smg_level_op(d.handle, lev, 0, 0.0, pv, pw, nul, nul, C5_NRHS, sp), 10, stream)
+        fl = 72.0 * nc * nc * C5_NRHS * cx * ct
+        coarse[f"level{lev}"] = dict(kernel=f"k_coarse_mfma64, {cx}x{ct} sites, nc={nc}, {C5_NRHS} RHS, FP64",
+                                     avg_launch_ms=dl * 1e3, tflops=fl / dl / 1e12, frac=fl / dl / 1e12 / 78.6)
+        log(f"c5 level {lev} coarse operator, {C5_NRHS} RHS, FP64 matrix cores: {dl * 1e3:.3f} ms, "
+            f"{fl / dl / 1e12:.1f} TFLOP/s")
+        del vl, yl
     # spectral ratio: lambda_max by power iteration, lambda_min (an upper bound) by
     # block inverse iteration with Rayleigh-Ritz on 8 vectors
     v = synth.gaussian_device(n, 7, device=dev)
@@ -436,7 +471,36 @@ def c5_leg(args, torch, smg, dev):
                 ratio_upper_bound=(ritz[0] / lmax) if ritz else None, lowest_ritz=ritz,
                 fp64=out["fp64"], mixed=out["mixed"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], fine_A=fineA,
+                coarse_fp64=coarse,
                 seconds=time.perf_counter() - t_start)
+
+
+def legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu):
+    """The other legs' headline figures in a few numbers (their full records follow
+    the config in the same line)."""
+    def r(x, nd=4):
+        return None if x is None else float(f"{x:.{nd}g}")
+
+    out = {"fine_A_fp64_tb_s": {"2048": r(dslash_2048["achieved"] / 1e3), "4096": r(dslash_4096["achieved"] / 1e3)},
+           "fine_A_fp64_frac": {"2048": r(dslash_2048["frac"], 3), "4096": r(dslash_4096["frac"], 3)}}
+    if c1:
+        out["plain_32"] = {"gpu_solve_s": r(c1["gpu_solve_s"]), "iterations": c1["iterations"],
+                           "relres": r(c1["relres"], 3)}
+    if mrhs:
+        out["multi_rhs_512"] = {"mixed_solves_per_s": r(mrhs["mixed"]["solves_per_s"]),
+                                "fp64_solves_per_s": r(mrhs["fp64"]["solves_per_s"]),
+                                "mixed_over_fp64": r(mrhs["mixed_over_fp64"], 3),
+                                "mfma_fp32_frac": r(mrhs["mfma"]["frac"], 3),
+                                "mfma_fp64_frac": r(mrhs.get("mfma64", {}).get("frac"), 3)}
+    if serving:
+        out["serving"] = {"saturation_solves_per_s": r(serving["saturation_solves_per_s"]),
+                          "solves_per_s_0.7": r(serving["solves_per_s"]), "p50_ms_0.7": r(serving["p50_ms"]),
+                          "p99_ms_0.7": r(serving["p99_ms"])}
+    if split:
+        out["chirality_split_solves_per_s"] = r(split["mixed_solves_per_s"])
+    if cpu:
+        out["cpu_oracle_solves_per_s"] = r(cpu.get("value"))
+    return out
 
 
 def c1_leg(torch, smg, dev):
@@ -1188,6 +1252,7 @@ def main():
             "mean_iterations_mixed": sum(r["iterations"] for r in mixed["records"]) / len(mixed["records"]),
             "mean_iterations_fp64": sum(r["iterations"] for r in fp64["records"]) / len(fp64["records"]),
             "max_relres": max(r["relres"] for r in mixed["records"] + fp64["records"]),
+            "legs": legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu),
         },
         "roofline": roof,
         "dslash": dslash_2048,

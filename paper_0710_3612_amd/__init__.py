@@ -15,6 +15,7 @@ from __future__ import annotations
 import atexit
 import ctypes
 import os
+import sys
 import weakref
 from pathlib import Path
 from typing import Optional, Sequence
@@ -219,10 +220,8 @@ def _torch_alloc(nbytes, stream, _ctx):
         return None
 
 
-def _torch_release(ptr, _nbytes, _stream, _ctx):
-    import sys
-
-    if sys.is_finalizing():  # torch may already be gone; the process is ending
+def _torch_release(ptr, _nbytes, _stream, _ctx, _finalizing=sys.is_finalizing):
+    if _finalizing():  # torch may already be gone; the process is ending
         return
     import torch
 
@@ -371,10 +370,8 @@ class Solver:
             self.lib.smg_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
-    def __del__(self):
-        import sys
-
-        if sys.is_finalizing():  # closed at exit already, or the process is ending
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # closed at exit already, or the process is ending
             return
         try:
             self.close()
@@ -628,10 +625,8 @@ class Batch:
             self.lib.smg_batch_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
-    def __del__(self):
-        import sys
-
-        if sys.is_finalizing():  # closed at exit already, or the process is ending
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # closed at exit already, or the process is ending
             return
         try:
             self.close()

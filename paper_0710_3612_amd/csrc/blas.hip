@@ -430,6 +430,16 @@ void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red r
   HIPCHECK(hipGetLastError());
 }
 
+// beta = |r|^2 / <r, z>_old for an unpreconditioned CG (z = r), from the partial sums
+// of |r|^2 that the last k_axpy_update left in red.partial (no pass over r).
+void launch_beta_partials(size_t n, int nrhs, Red red, double* rz, double* beta, const int* active,
+                          hipStream_t st) {
+  const int nb = red_blocks(n);
+  hipLaunchKernelGGL((k_reduce_final<2>), dim3(nrhs), dim3(kThreads), 0, st, red.partial, nb, beta, rz, active,
+                     nullptr, nullptr, nullptr);
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,
                         int nrhs, Red red, double* rr, hipStream_t st, double* rr_host) {

@@ -287,6 +287,10 @@ void launch_dot_alpha(const cpx<R>* p, const cpx<R>* q, size_t n, int nrhs, Red 
 template <typename R>
 void launch_dot_beta(const cpx<R>* r, const cpx<R>* z, size_t n, int nrhs, Red red, double* rz, double* beta,
                      const int* active, hipStream_t st);
+// beta and <r, r> of an unpreconditioned CG from the |r|^2 partial sums that the last
+// launch_axpy_update of the same length left in red.
+void launch_beta_partials(size_t n, int nrhs, Red red, double* rz, double* beta, const int* active,
+                          hipStream_t st);
 // x += alpha p, r -= alpha q and |r|^2 per column into rr (and rr_host when given).
 template <typename R>
 void launch_axpy_update(cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* q, const double* alpha, size_t n,

@@ -1318,9 +1318,15 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
 // holds row 4r + l/16, column l%16 (checked on the device).  Every link is loaded once per 16 RT
 // right-hand sides; the neighbours' vector entries are read straight from memory
 // (the eight other sites that read them run close by, so they come from L2), the
-// next direction's operands while this direction's MFMAs run.  FP64 MFMA has the
+// next direction's operands while this direction's MFMAs run (a deeper ring pinned
+// by sched_barrier measured 20-45% slower: fewer waves per SIMD).  FP64 MFMA has the
 // FP64 vector peak of this chip; what the matrix cores save is the broadcast of
 // link and vector entries across lanes that a vector-ALU kernel needs.
+// Site order: each XCD takes a band of ct/8 rows (its blocks are contiguous after
+// xcd_tile) and walks it in strips `strip` sites wide, row by row within a strip, so
+// that the rows above and below the sites in flight are still in that XCD's L2 when
+// their entries are read again (in plain row order a row of 64-RHS entries, 16 KB
+// per site, outgrows the L2 before the next row needs it).  strip = 0: row order.
 // ---------------------------------------------------------------------------
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -1328,15 +1334,26 @@ template <int MODE, int RT>
 __global__ void __launch_bounds__(256) k_coarse_mfma64(const z64* __restrict__ L, const z64* __restrict__ v,
                                                        z64* __restrict__ y, int cx, int ct, int nc, int nrhs,
                                                        double c, double c2, z64* __restrict__ xacc,
-                                                       const z64* __restrict__ aux) {
+                                                       const z64* __restrict__ aux, int strip) {
   const int nK = cx * ct;
   const size_t n = (size_t)nK * nc;
-  const int K = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-  if (K >= nK) return;  // wave-uniform, and no barrier follows
+  const int g = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (g >= nK) return;  // wave-uniform, and no barrier follows
+  int kx, kt;
+  if (strip > 0) {
+    const int H = ct / 8, chunk = H * cx;
+    const int band = g / chunk, q = g - band * chunk;
+    const int sidx = q / (strip * H), r = q - sidx * (strip * H);
+    kt = band * H + r / strip;
+    kx = sidx * strip + r % strip;
+  } else {
+    kx = g % cx;
+    kt = g / cx;
+  }
+  const int K = kt * cx + kx;
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, kq = lane >> 4;
   const int rhs0 = blockIdx.y * 16 * RT;
-  const int kx = K % cx, kt = K / cx;
   const int irow = i < nc ? i : nc - 1;  // clamped: every lane loads a valid address, masked after
   const bool row_ok = i < nc;
   int rj[RT];
@@ -1427,14 +1444,21 @@ void launch_coarse_mfma64(const z64* L, const z64* x, z64* y, int cx, int ct, in
   const long nK = (long)cx * ct;
   const int rt = nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
   const dim3 grid((unsigned)((nK + 3) / 4), (unsigned)((nrhs + 16 * rt - 1) / (16 * rt)));
+  // strips of 16 sites where the bands and strips tile the lattice exactly (every
+  // block's four sites inside one band, the bands one per XCD)
+  constexpr int kStrip = 16;
+  const int strip = (nK % 32 == 0 && (nK / 4) % 8 == 0 && ct % 8 == 0 && cx % kStrip == 0) ? kStrip : 0;
   with_mode(mode, [&](auto m) {
     constexpr int M = decltype(m)::v;
     if (rt == 1)
-      hipLaunchKernelGGL((k_coarse_mfma64<M, 1>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 1>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux,
+                         strip);
     else if (rt == 2)
-      hipLaunchKernelGGL((k_coarse_mfma64<M, 2>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 2>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux,
+                         strip);
     else
-      hipLaunchKernelGGL((k_coarse_mfma64<M, 4>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux);
+      hipLaunchKernelGGL((k_coarse_mfma64<M, 4>), grid, dim3(256), 0, st, L, x, y, cx, ct, nc, nrhs, c, c2, xacc, aux,
+                         strip);
   });
   HIPCHECK(hipGetLastError());
 }

@@ -725,6 +725,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     }
   }
   for (int it = 1; it <= maxiter && nact > 0; ++it) {
+    bool partials_kept = true;  // red still holds this iteration's |r|^2 partial sums
     if (fuse_nb > 0) {
       if constexpr (std::is_same<R, float>::value) {
         BetaFold bf;
@@ -788,6 +789,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         if (nact == 0) break;
       } else if (any_cand) {
         // confirm on the true residual t = b - A x
+        partials_kept = false;
         apply_op<R>(c, lv, x, v.t, nrhs, 2, 0.0, nullptr, b);
         launch_dot<R>(v.t, v.t, n, nrhs, c.red, S.tt, c.st);
         HIPCHECK(hipMemcpyAsync(c.h_scal, S.tt, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, c.st));
@@ -817,6 +819,10 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
     if (fuse_nb > 0) {  // the V-cycle's last fine apply also forms the partial sums of <r, z>
       folded = precondition_fold(v.r, v.z);
       if (!folded) launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, rz_cur, S.ab, S.active, c.st);
+    } else if (!precond && partials_kept) {
+      // plain CG: z = r, and <r, r> is in the update's partial sums (no copy, no pass over r)
+      launch_beta_partials(n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
+      launch_xpay<R>(v.r, p_cur, S.ab, n, nrhs, c.st);
     } else {
       precondition(v.r, v.z);
       launch_dot_beta<R>(v.r, v.z, n, nrhs, c.red, S.rz, S.ab, S.active, c.st);
