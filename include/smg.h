@@ -99,10 +99,13 @@ typedef struct {
   int32_t stop_recursive;         /* FP64 MG-CG and CG: 0 (default) = converged when the recomputed
                                      residual ||rhs - A x|| / ||rhs|| reaches tol; 1 = when CG's
                                      recursive residual does (the true one is still reported) */
-  int32_t mfma_min_rhs;           /* FP32 coarse applies of at least this many right-hand
-                                     sides run on the matrix cores (MFMA FP32, levels with
-                                     nc <= 16); 1 = always, 0 = never.  Results differ from
-                                     the vector-ALU path by FP32 rounding only. */
+  int32_t mfma_min_rhs;           /* coarse applies of at least this many right-hand sides run
+                                     on the matrix cores (levels with nc <= 16: MFMA FP32 in
+                                     the FP32 V-cycle; MFMA FP64, with the FP64 restriction and
+                                     prolongation, in FP64); 1 = always, 0 = never.  Results
+                                     differ from the vector-ALU path by rounding only, so a
+                                     column's rounding in smg_solve / smg_vcycle can depend on
+                                     nrhs; batches pin the choice by their capacity. */
   int32_t operator_storage;       /* mixed precision: storage of the FP32 V-cycle's coarse
                                      links (vector-ALU path; the matrix-core path keeps FP32),
                                      prolongators and coarsest dense inverse, SMG_STORE_F32 or

@@ -233,10 +233,14 @@ void launch_coarse_mfma64(const z64* L, const z64* x, z64* y, int cx, int ct, in
 template <typename R>
 void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                      int nc, int ldk, int nrhs, hipStream_t st);
+// FP64 restriction of many right-hand sides on the matrix cores (1 <= nc <= 16).
+void launch_restrict_mfma64(const z64* P, const z64* x, z64* y, int lx, int lt, int dof, int bx, int bt, int h,
+                            int nc, int ldk, int nrhs, hipStream_t st);
 // mode 0: y = P e ; mode 1: y += P e.  wbuf holds nrhs * nK * nw scratch values.
+// mfma (FP64 only, nc <= 16): the window phase on the matrix cores.
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false);
 
 // FP32 prolongation with P stored in FP16 scaled by 1 / ps.
 void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,

@@ -33,6 +33,9 @@ __device__ inline T wave_sum(T v) {
 // (halo h = 0, the tentative P) or on the block plus a one-site ring (h = 1, the
 // smoothed P).  Window variable i = ((wy * (bx + 2h)) + wx) * dof + d with
 // wx in [0, bx + 2h) standing for x = Jx * bx + wx - h (periodic).
+// accumulator of v_mfma_f64_16x16x4f64 (four FP64 values per lane)
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 __device__ inline int win_index(int J, int i, int lx, int lt, int dof, int bx, int bt, int cx, int h) {
   const int Jt = J / cx, Jx = J - Jt * cx;
   const int wxw = bx + 2 * h;
@@ -979,6 +982,103 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
   HIPCHECK(hipGetLastError());
 }
 
+// FP64 restriction of many right-hand sides on the matrix cores (V-cycle step 2):
+// per aggregate K, Y_K = P_K^H X_K with X_K the nw window variables of each
+// right-hand side, a (nc x nw) x (nw x nrhs) product.  One wave owns one aggregate
+// and 16 RT right-hand sides; K-step s takes window variables 4s..4s+3 through
+// v_mfma_f64_16x16x4f64 (layout of k_coarse_mfma64), the conjugate transpose in the
+// real embedding: Pr Xr + Pi Xi into Re Y, Pr Xi - Pi Xr into Im Y.  P_K is read
+// once per 16 RT columns instead of once per column group of the vector-ALU kernel;
+// the next step's operands are loaded while this step's instructions run.
+template <int RT>
+__global__ void __launch_bounds__(256) k_restrict_mfma64(const z64* __restrict__ P, const z64* __restrict__ x,
+                                                         z64* __restrict__ y, int lx, int lt, int dof, int bx, int bt,
+                                                         int h, int nc, int ldk, int nrhs) {
+  const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= nK) return;  // wave-uniform, and no barrier follows
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const size_t n = (size_t)lx * lt * dof;
+  const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
+  const int rhs0 = blockIdx.y * 16 * RT;
+  const z64* PK = P + (size_t)K * ldk * nw + (size_t)(i < nc ? i : nc - 1) * nw;
+  const bool row_ok = i < nc;
+  int rj[RT];
+  bool rj_ok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = rhs0 + 16 * rt + i;
+    rj_ok[rt] = r < nrhs;
+    rj[rt] = r < nrhs ? r : nrhs - 1;
+  }
+  auto load = [&](int st, double& pr, double& pi, z64 (&xv)[RT]) {
+    const int w = 4 * st + kq;
+    const bool wok = w < nw;
+    const int wc = wok ? w : nw - 1;
+    const z64 pv = PK[wc];
+    pr = (row_ok && wok) ? pv.re : 0.0;
+    pi = (row_ok && wok) ? pv.im : 0.0;
+    const int wi = win_index(K, wc, lx, lt, dof, bx, bt, cx, h);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const z64 u = x[(size_t)rj[rt] * n + wi];
+      const bool ok = rj_ok[rt] && wok;
+      xv[rt] = mk<double>(ok ? u.re : 0.0, ok ? u.im : 0.0);
+    }
+  };
+  doublex4 accR[RT], accI[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) accR[rt][r] = accI[rt][r] = 0.0;
+  const int steps = (nw + 3) / 4;
+  double pr, pi, pr2, pi2;
+  z64 xv[RT], xv2[RT];
+  load(0, pr, pi, xv);
+  for (int st = 0; st < steps; ++st) {
+    if (st + 1 < steps) load(st + 1, pr2, pi2, xv2);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, xv[rt].re, accR[rt], 0, 0, 0);
+      accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, xv[rt].im, accI[rt], 0, 0, 0);
+      accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, xv[rt].im, accR[rt], 0, 0, 0);
+      accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi, xv[rt].re, accI[rt], 0, 0, 0);
+    }
+    pr = pr2;
+    pi = pi2;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) xv[rt] = xv2[rt];
+  }
+  // lane holds right-hand side rhs0 + 16 rt + i, coarse variables 4 r + kq
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    if (!rj_ok[rt]) continue;
+    z64* yr = y + ((size_t)rj[rt] * nK + K) * nc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * r + kq;
+      if (k < nc) yr[k] = mk<double>(accR[rt][r], accI[rt][r]);
+    }
+  }
+}
+
+void launch_restrict_mfma64(const z64* P, const z64* x, z64* y, int lx, int lt, int dof, int bx, int bt, int h,
+                            int nc, int ldk, int nrhs, hipStream_t st) {
+  if (nc < 1 || nc > 16) throw Error(-1, "FP64 matrix-core restriction needs 1 <= nc <= 16");
+  if (nrhs < 1) return;
+  const int nK = (lx / bx) * (lt / bt);
+  const int rt = nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+  const dim3 grid((unsigned)((nK + 3) / 4), (unsigned)((nrhs + 16 * rt - 1) / (16 * rt)));
+  if (rt == 1)
+    hipLaunchKernelGGL((k_restrict_mfma64<1>), grid, dim3(256), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs);
+  else if (rt == 2)
+    hipLaunchKernelGGL((k_restrict_mfma64<2>), grid, dim3(256), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs);
+  else
+    hipLaunchKernelGGL((k_restrict_mfma64<4>), grid, dim3(256), 0, st, P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs);
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename R>
 void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
                      int nc, int ldk, int nrhs, hipStream_t st) {
@@ -1001,18 +1101,103 @@ INST_RS(hfc, bfc)
 INST_RS(hfc, hfc)
 #undef INST_RS
 
+// Phase 1 of the FP64 prolongation of many right-hand sides on the matrix cores:
+// per aggregate K, W_K = P_K E_K (nw x nc times nc x nrhs).  One wave owns 16 window
+// variables of one aggregate and 16 RT right-hand sides; K-step s takes coarse
+// variables 4s..4s+3 through v_mfma_f64_16x16x4f64 (layout of k_coarse_mfma64):
+// Pr Er - Pi Ei into Re W, Pr Ei + Pi Er into Im W.  W has the layout of
+// k_prolong_win's, so the gather phase is shared.
+template <int RT>
+__global__ void __launch_bounds__(256) k_prolong_win_mfma64(const z64* __restrict__ P, const z64* __restrict__ e,
+                                                            z64* __restrict__ wbuf, int nK, int nw, int nc, int ldk,
+                                                            int nrhs) {
+  const int ntile = (nw + 15) / 16;
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= nK * ntile) return;  // wave-uniform, and no barrier follows
+  const int K = g / ntile, tile = g - K * ntile;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const int w = 16 * tile + i;
+  const bool w_ok = w < nw;
+  const z64* PK = P + (size_t)K * ldk * nw + (w_ok ? w : nw - 1);
+  const int rhs0 = blockIdx.y * 16 * RT;
+  int rj[RT];
+  bool rj_ok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = rhs0 + 16 * rt + i;
+    rj_ok[rt] = r < nrhs;
+    rj[rt] = r < nrhs ? r : nrhs - 1;
+  }
+  doublex4 accR[RT], accI[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) accR[rt][r] = accI[rt][r] = 0.0;
+  for (int s = 0; s < (nc + 3) / 4; ++s) {
+    const int k = 4 * s + kq;
+    const bool k_ok = k < nc;
+    const int kc = k_ok ? k : nc - 1;
+    const z64 pv = PK[(size_t)kc * nw];
+    const double pr = (w_ok && k_ok) ? pv.re : 0.0, pi = (w_ok && k_ok) ? pv.im : 0.0;
+    z64 ev[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const z64 u = e[((size_t)rj[rt] * nK + K) * nc + kc];
+      const bool ok = rj_ok[rt] && k_ok;
+      ev[rt] = mk<double>(ok ? u.re : 0.0, ok ? u.im : 0.0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, ev[rt].re, accR[rt], 0, 0, 0);
+      accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, ev[rt].im, accI[rt], 0, 0, 0);
+      accR[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi, ev[rt].im, accR[rt], 0, 0, 0);
+      accI[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, ev[rt].re, accI[rt], 0, 0, 0);
+    }
+  }
+  // lane holds right-hand side rhs0 + 16 rt + i, window variables 16 tile + 4 r + kq
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    if (!rj_ok[rt]) continue;
+    z64* wr = wbuf + ((size_t)rj[rt] * nK + K) * nw;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int wv = 16 * tile + 4 * r + kq;
+      if (wv < nw) wr[wv] = mk<double>(accR[rt][r], accI[rt][r]);
+    }
+  }
+}
+
 template <typename R, typename TP>
 void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                      int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
+                      int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   const size_t nkw = (size_t)nK * nw;
-  if (nrhs >= 8)  // eight right-hand sides per thread share its P entries
+  bool win_done = false;
+  if constexpr (std::is_same<R, double>::value && std::is_same<TP, z64>::value) {
+    if (mfma) {  // FP64, many right-hand sides: phase 1 on the matrix cores
+      if (nc < 1 || nc > 16) throw Error(-1, "FP64 matrix-core prolongation needs 1 <= nc <= 16");
+      const int rt = nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+      const long waves = (long)nK * ((nw + 15) / 16);
+      const dim3 g((unsigned)((waves + 3) / 4), (unsigned)((nrhs + 16 * rt - 1) / (16 * rt)));
+      if (rt == 1)
+        hipLaunchKernelGGL((k_prolong_win_mfma64<1>), g, dim3(256), 0, st, P, e, wbuf, nK, nw, nc, ldk, nrhs);
+      else if (rt == 2)
+        hipLaunchKernelGGL((k_prolong_win_mfma64<2>), g, dim3(256), 0, st, P, e, wbuf, nK, nw, nc, ldk, nrhs);
+      else
+        hipLaunchKernelGGL((k_prolong_win_mfma64<4>), g, dim3(256), 0, st, P, e, wbuf, nK, nw, nc, ldk, nrhs);
+      win_done = true;
+    }
+  }
+  if (win_done) {
+  } else if (nrhs >= 8) {  // eight right-hand sides per thread share its P entries
     hipLaunchKernelGGL((k_prolong_win<R, TP, 8>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), (nrhs + 7) / 8),
                        dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
-  else
+  } else {
     hipLaunchKernelGGL((k_prolong_win<R, TP, 1>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs),
                        dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
+  }
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
   // h = 1 needs both coarse extents >= 2 (then no window covers a site twice) and blocks
@@ -1036,8 +1221,8 @@ void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbu
 
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
-  launch_prolong_t<R, cpx<R>>(P, (R)1, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st);
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma) {
+  launch_prolong_t<R, cpx<R>>(P, (R)1, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st, mfma);
 }
 
 void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,
@@ -1328,8 +1513,6 @@ void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int 
 // their entries are read again (in plain row order a row of 64-RHS entries, 16 KB
 // per site, outgrows the L2 before the next row needs it).  strip = 0: row order.
 // ---------------------------------------------------------------------------
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
 template <int MODE, int RT>
 __global__ void __launch_bounds__(256) k_coarse_mfma64(const z64* __restrict__ L, const z64* __restrict__ v,
                                                        z64* __restrict__ y, int cx, int ct, int nc, int nrhs,
@@ -1933,7 +2116,7 @@ void launch_lincomb3(const z64* X, const z64* Y, const z64* Z, z64* out, double 
   template void launch_restrict<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int, \
                                    int, hipStream_t);                                                            \
   template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int, int, int, int, int,  \
-                                  int, int, int, int, hipStream_t);                                              \
+                                  int, int, int, int, hipStream_t, bool);                                        \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
                                  const cpx<R>*, hipStream_t, double);                                            \
   template void launch_links_convert<R>(const z64*, cpx<R>*, size_t, hipStream_t);

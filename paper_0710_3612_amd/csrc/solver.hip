@@ -450,6 +450,11 @@ void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
                                   nrhs, c.st);
       return;
     }
+  } else {
+    if (use_mfma(c, lv.nc, nrhs)) {
+      launch_restrict_mfma64(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
+      return;
+    }
   }
   launch_restrict<R>(lv.P, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, c.st);
 }
@@ -463,7 +468,8 @@ void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, in
       return;
     }
   }
-  launch_prolong<R>(lv.P, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st);
+  launch_prolong<R>(lv.P, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs, mode, c.st,
+                    std::is_same<R, double>::value && use_mfma(c, lv.nc, nrhs));
 }
 
 // x = R b for the frozen MR polynomial, from x = 0 (lv.r / lv.t are ping-pong buffers).

@@ -220,6 +220,26 @@ def test_coarse_links(pair):
         assert rel_err(dense_from_links(links, cx, ct, nc), h.levels[l].A.toarray()) <= 1e-12
 
 
+@pytest.mark.parametrize("nrhs", [16, 20, 33])
+def test_transfer_many_rhs_matrix_cores(pair, nrhs):
+    """FP64 restriction and prolongation of at least mfma_min_rhs right-hand sides
+    (the FP64 matrix-core kernels, 16, 32 or 64 columns per wave with masked columns)
+    equal P^H x and P e of the oracle's sparse P column by column, on every case's
+    levels (smoothed windows, blocks of unequal extents, odd and chirality-split nc)."""
+    h, s = pair["h"], pair["s"]
+    for l in range(len(pair["blocks"])):
+        n = s.level_size(l)
+        nc = s.level_size(l + 1)
+        P = h.levels[l].P
+        x = synth.gaussian((nrhs, n), 17 + l + nrhs)
+        e = synth.gaussian((nrhs, nc), 19 + l + nrhs)
+        r = host(s.restrict(l, dev(x))).reshape(nrhs, -1)
+        pe = host(s.prolong(l, dev(e))).reshape(nrhs, -1)
+        for j in range(nrhs):
+            assert rel_err(r[j], P.conj().T @ x[j]) <= 1e-12, (l, j)
+            assert rel_err(pe[j], P @ e[j]) <= 1e-12, (l, j)
+
+
 def test_transfer_and_coarse_apply(pair):
     h, s = pair["h"], pair["s"]
     for l in range(len(pair["blocks"])):
@@ -642,8 +662,10 @@ def test_fp32_vcycle_large_coarsest_matrix_cores(opst, c64):
 def test_fp64_vcycle_large_coarsest_matrix_cores():
     """FP64 V-cycle whose 5120-variable coarsest inverse is applied on the FP64
     matrix cores (n above the row-kernel limit): within 1e-11 of the oracle's
-    V-cycle for 1 and 33 right-hand sides (two column tiles, the second ragged), and
-    a column's result is bitwise the same alone and inside the batch."""
+    V-cycle for 1, 16 and 33 right-hand sides (two column tiles, the second ragged).
+    A column's result is bitwise the same in a call of 16 and of 33 columns (both at
+    or above mfma_min_rhs, so the transfers also run on the matrix cores; below it
+    they take the vector-ALU kernels, which round differently)."""
     import torch
 
     smg = smg_mod()
@@ -658,9 +680,11 @@ def test_fp64_vcycle_large_coarsest_matrix_cores():
         assert s.level_size(1) == 5120
         n = s.level_size(0)
         b = synth.gaussian((33, n), 68)
-        xa = host(s.vcycle(torch.from_numpy(b[:1].copy()).to("cuda"))).reshape(1, -1)
+        x1 = host(s.vcycle(torch.from_numpy(b[:1].copy()).to("cuda"))).reshape(1, -1)
+        xa = host(s.vcycle(torch.from_numpy(b[:16].copy()).to("cuda"))).reshape(16, -1)
         xb = host(s.vcycle(torch.from_numpy(b).to("cuda"))).reshape(33, -1)
-        assert np.array_equal(xa[0], xb[0])
+        assert np.array_equal(xa[0], xb[0]) and np.array_equal(xa[15], xb[15])
+        assert rel_err(x1[0], mg.vcycle(h, 0, b[0])) <= 1e-11
         for j in (0, 17, 32):
             ref = mg.vcycle(h, 0, b[j])
             assert rel_err(xb[j], ref) <= 1e-11, (j, rel_err(xb[j], ref))
