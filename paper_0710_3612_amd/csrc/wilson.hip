@@ -176,14 +176,14 @@ __device__ inline int fused_tile(int b, int nb) {
 // MODE 7 ends a V-cycle: the last two smoother steps of MODE 4 (xacc becomes the
 // V-cycle's output z) and the workgroup's share of <r, z> with r = aux, the V-cycle's
 // input, into partial[rhs][block].
-template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>>
+template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>, int NRB = 1>
 __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
                                                            TO* __restrict__ y, int lx, int lt, R diag, R c, R c2,
                                                            cpx<R>* __restrict__ xacc,
                                                            const cpx<R>* __restrict__ aux,
                                                            const double* __restrict__ beta = nullptr,
                                                            double* __restrict__ partial = nullptr,
-                                                           BetaFold bf = BetaFold{}) {
+                                                           BetaFold bf = BetaFold{}, int nrhs = 0) {
   constexpr int HX = TX + 2, HT = TT + 2;
   constexpr int RG = kThreads / TX;          // row groups
   constexpr int PER = TX * TT / kThreads;    // sites per thread
@@ -196,8 +196,8 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const int ntx = lx / TX;
   const int tile = fused_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
-  const size_t off = (size_t)blockIdx.y * 2 * V;
-  const TI* __restrict__ xb = x + off;
+  static_assert(NRB == 1 || MODE <= 5, "several right-hand sides per workgroup: epilogues 0-5 only");
+  const int nr = nrhs > 0 ? nrhs : (int)gridDim.y * NRB;
   constexpr int NRING = 2 * TX + 2 * TT;
   static_assert(NRING <= kThreads, "one ring site per thread");
 
@@ -228,16 +228,6 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
     ku0m[k] = U[gt * lx + (gx == 0 ? lx - 1 : gx - 1)];
     ku1m[k] = U[V + (gt == 0 ? lt - 1 : gt - 1) * lx + gx];
   }
-  // the epilogue's other operand (xacc for a smoother step, aux for a residual), also early
-  cpx<R> ep0[PER], ep1[PER];
-  cpx<R> ea0[MODE == 7 ? PER : 1], ea1[MODE == 7 ? PER : 1];  // MODE 7: the V-cycle's input r
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const size_t i0 = off + 2 * (size_t)((t0 + lti + k * RG) * lx + x0 + lxi);
-    if (MODE == 1 || MODE == 4 || MODE == 7) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
-    if (MODE == 2) { ep0[k] = aux[i0]; ep1[k] = aux[i0 + 1]; }
-    if (MODE == 7) { ea0[k] = aux[i0]; ea1[k] = aux[i0 + 1]; }
-  }
   // ring site of this thread (threads 0 .. NRING-1): halo coordinates, the hop it skips, its links
   int rhx = 0, rht = 0, rskip = kSkipNone;
   cpx<R> ru0 = mk<R>(0, 0), ru1 = ru0, ru0m = ru0, ru1m = ru0;
@@ -257,223 +247,243 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
     if (rskip != kSkipTm) ru1m = U[V + (gt == 0 ? lt - 1 : gt - 1) * lx + gx];
   }
 
-  // ---- stage psi (tile + halo): every load is issued before the first LDS write,
-  // so a workgroup waits for one memory latency, not one per pass
-  constexpr int NSP = HT * HX * 2, NPASS = (NSP + kThreads - 1) / kThreads;
-  TI stage[NPASS];  // raw stored values: widened only after every load has been issued
-  cpx<R> stage2[MODE == 6 ? NPASS : 1];
+  // NRB right-hand sides per workgroup reuse the links loaded above (their psi
+  // staging, D and D^H run once per right-hand side, as with NRB = 1)
+#pragma unroll 1
+  for (int q = 0; q < NRB; ++q) {
+    const int rhs = (int)blockIdx.y * NRB + q;
+    if (rhs >= nr) break;  // uniform over the workgroup
+    const size_t off = (size_t)rhs * 2 * V;
+    const TI* __restrict__ xb = x + off;
+    // the epilogue's other operand (xacc for a smoother step, aux for a residual), also early
+    cpx<R> ep0[PER], ep1[PER];
+    cpx<R> ea0[MODE == 7 ? PER : 1], ea1[MODE == 7 ? PER : 1];  // MODE 7: the V-cycle's input r
 #pragma unroll
-  for (int j = 0; j < NPASS; ++j) {
-    const int i = threadIdx.x + j * kThreads;
-    if (i < NSP) {
-      const int comp = i & 1, site = i >> 1;
-      const int ht = site / HX, hx = site - ht * HX;
-      int gx = x0 + hx - 1, gt = t0 + ht - 1;
-      gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
-      gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
-      stage[j] = xb[2 * (gt * lx + gx) + comp];
-      if constexpr (MODE == 6) stage2[j] = aux[off + 2 * (gt * lx + gx) + comp];
+    for (int k = 0; k < PER; ++k) {
+      const size_t i0 = off + 2 * (size_t)((t0 + lti + k * RG) * lx + x0 + lxi);
+      if (MODE == 1 || MODE == 4 || MODE == 7) { ep0[k] = xacc[i0]; ep1[k] = xacc[i0 + 1]; }
+      if (MODE == 2) { ep0[k] = aux[i0]; ep1[k] = aux[i0 + 1]; }
+      if (MODE == 7) { ea0[k] = aux[i0]; ea1[k] = aux[i0 + 1]; }
     }
-  }
-  R bt = 0;
-  if constexpr (MODE == 6) {
-    if (bf.part) {  // beta from the partial sums of <r, z>, in the order of the separate pass
-      __shared__ double sb[2 * (kThreads / 64)];
-      const int j = blockIdx.y;
-      double re = 0, im = 0;
+    // ---- stage psi (tile + halo): every load is issued before the first LDS write,
+    // so a workgroup waits for one memory latency, not one per pass
+    constexpr int NSP = HT * HX * 2, NPASS = (NSP + kThreads - 1) / kThreads;
+    TI stage[NPASS];  // raw stored values: widened only after every load has been issued
+    cpx<R> stage2[MODE == 6 ? NPASS : 1];
 #pragma unroll
-      for (int u = 0; u < NBF; ++u) {
-        if ((int)threadIdx.x + u * kThreads < bf.nb) {
-          re += bre[u];
-          im += bim[u];
-        }
+    for (int j = 0; j < NPASS; ++j) {
+      const int i = threadIdx.x + j * kThreads;
+      if (i < NSP) {
+        const int comp = i & 1, site = i >> 1;
+        const int ht = site / HX, hx = site - ht * HX;
+        int gx = x0 + hx - 1, gt = t0 + ht - 1;
+        gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
+        gt = gt < 0 ? gt + lt : (gt >= lt ? gt - lt : gt);
+        stage[j] = xb[2 * (gt * lx + gx) + comp];
+        if constexpr (MODE == 6) stage2[j] = aux[off + 2 * (gt * lx + gx) + comp];
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_xor(re, o, 64);
-        im += __shfl_xor(im, o, 64);
-      }
-      if ((threadIdx.x & 63) == 0) {
-        sb[2 * (threadIdx.x >> 6)] = re;
-        sb[2 * (threadIdx.x >> 6) + 1] = im;
-      }
-      __syncthreads();
-      re = 0;
-      im = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        re += sb[2 * w];
-        im += sb[2 * w + 1];
-      }
-      double be = 0;
-      if (bf.rz_old && bf.active[j] && bf.rz_old[2 * j] != 0) be = re / bf.rz_old[2 * j];
-      bt = (R)be;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const bool keep = bf.rz_old && !bf.active[j];
-        bf.rz_new[2 * j] = keep ? bf.rz_old[2 * j] : re;
-        bf.rz_new[2 * j + 1] = keep ? bf.rz_old[2 * j + 1] : im;
-      }
-    } else {
-      bt = (R)beta[blockIdx.y];
     }
-  }
-#pragma unroll
-  for (int j = 0; j < NPASS; ++j) {
-    const int i = threadIdx.x + j * kThreads;
+    R bt = 0;
     if constexpr (MODE == 6) {
-      // p = z + beta p_old; p = z where beta = 0 (p_old is not read into the sum then)
-      if (i < NSP) sp[i] = bt != (R)0 ? widen(stage[j]) + bt * stage2[j] : widen(stage[j]);
-    } else {
-      if (i < NSP) sp[i] = widen(stage[j]);
-    }
-  }
-  __syncthreads();
-
-  auto P = [&](int ht, int hx, int comp) -> cpx<R> { return sp[(ht * HX + hx) * 2 + comp]; };
-  const R half = (R)0.5;
-
-  // D (or a projection of it) at halo coordinates (hx, ht), global (gx, gt).
-  auto d_at = [&](int hx, int ht, cpx<R> u0, cpx<R> u1, cpx<R> u0m, cpx<R> u1m, int skip, cpx<R>& o0,
-                  cpx<R>& o1) {
-    cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
-    if (skip != kSkipXp) hop_acc<R, false>(s0, s1, 0, u0, P(ht, hx + 1, 0), P(ht, hx + 1, 1));
-    if (skip != kSkipXm) hop_acc<R, false>(s0, s1, 1, cj(u0m), P(ht, hx - 1, 0), P(ht, hx - 1, 1));
-    if (skip != kSkipTp) hop_acc<R, false>(s0, s1, 2, u1, P(ht + 1, hx, 0), P(ht + 1, hx, 1));
-    if (skip != kSkipTm) hop_acc<R, false>(s0, s1, 3, cj(u1m), P(ht - 1, hx, 0), P(ht - 1, hx, 1));
-    o0 = diag * P(ht, hx, 0) - half * s0;
-    o1 = diag * P(ht, hx, 1) - half * s1;
-  };
-
-  // ---- phase 1: phi on the tile ------------------------------------------------
+      if (bf.part) {  // beta from the partial sums of <r, z>, in the order of the separate pass
+        __shared__ double sb[2 * (kThreads / 64)];
+        const int j = blockIdx.y;
+        double re = 0, im = 0;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int r = lti + k * RG;
-    d_at(lxi + 1, r + 1, ku0[k], ku1[k], ku0m[k], ku1m[k], kSkipNone, f0[k], f1[k]);
-    sf[(r * TX + lxi) * 2] = f0[k];
-    sf[(r * TX + lxi) * 2 + 1] = f1[k];
-  }
-  // ---- phase 1b: projected phi on the ring -------------------------------------
-  if (threadIdx.x < NRING) {
-    cpx<R> o0, o1;
-    d_at(rhx, rht, ru0, ru1, ru0m, ru1m, rskip, o0, o1);
-    // D^H at the neighbouring tile site uses: from x0-1 (its -x hop) (1 - s1) -> o0 - o1;
-    // from x0+TX (+x hop) (1 + s1) -> o0 + o1; from t0-1 (1 - s2) -> o0 + i o1;
-    // from t0+TT (1 + s2) -> o0 - i o1.
-    cpx<R> h;
-    if (rskip == kSkipXm) h = o0 - o1;
-    else if (rskip == kSkipXp) h = o0 + o1;
-    else if (rskip == kSkipTm) h = o0 + imul(o1);
-    else h = o0 - imul(o1);
-    sr[threadIdx.x] = h;
-  }
-  __syncthreads();
-
-  // ---- phase 2: D^H phi on the tile ---------------------------------------------
-  double dre = 0, dim = 0;  // MODE 6: this thread's share of <p, A p>
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int r = lti + k * RG;
-    const int gx = x0 + lxi, gt = t0 + r;
-    const int s = gt * lx + gx;
-    cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
-    // +x neighbour: (1 + s1) U0_s phi_{s+x}
-    {
-      cpx<R> h;
-      if (lxi + 1 < TX) h = sf[(r * TX + lxi + 1) * 2] + sf[(r * TX + lxi + 1) * 2 + 1];
-      else h = sr[TT + r];
-      h = ku0[k] * h;
-      s0 = s0 + h; s1 = s1 + h;
-    }
-    // -x neighbour: (1 - s1) conj(U0_{s-x}) phi_{s-x}
-    {
-      cpx<R> h;
-      if (lxi > 0) h = sf[(r * TX + lxi - 1) * 2] - sf[(r * TX + lxi - 1) * 2 + 1];
-      else h = sr[r];
-      h = cj(ku0m[k]) * h;
-      s0 = s0 + h; s1 = s1 - h;
-    }
-    // +t neighbour: (1 + s2) U1_s phi_{s+t}: h = phi0 - i phi1, spread (1, i)
-    {
-      cpx<R> h;
-      if (r + 1 < TT) h = sf[((r + 1) * TX + lxi) * 2] - imul(sf[((r + 1) * TX + lxi) * 2 + 1]);
-      else h = sr[2 * TT + TX + lxi];
-      h = ku1[k] * h;
-      s0 = s0 + h; s1 = s1 + imul(h);
-    }
-    // -t neighbour: (1 - s2) conj(U1_{s-t}) phi_{s-t}: h = phi0 + i phi1, spread (1, -i)
-    {
-      cpx<R> h;
-      if (r > 0) h = sf[((r - 1) * TX + lxi) * 2] + imul(sf[((r - 1) * TX + lxi) * 2 + 1]);
-      else h = sr[2 * TT + lxi];
-      h = cj(ku1m[k]) * h;
-      s0 = s0 + h; s1 = s1 - imul(h);
-    }
-    const cpx<R> o0 = diag * f0[k] - half * s0;
-    const cpx<R> o1 = diag * f1[k] - half * s1;
-    const size_t i0 = off + 2 * (size_t)s, i1 = i0 + 1;
-    if (MODE == 0) {
-      if constexpr (NT && std::is_same<TO, cpx<R>>::value) {  // streaming output: keep it out of the caches
-        __builtin_nontemporal_store(o0.re, &y[i0].re);
-        __builtin_nontemporal_store(o0.im, &y[i0].im);
-        __builtin_nontemporal_store(o1.re, &y[i1].re);
-        __builtin_nontemporal_store(o1.im, &y[i1].im);
+        for (int u = 0; u < NBF; ++u) {
+          if ((int)threadIdx.x + u * kThreads < bf.nb) {
+            re += bre[u];
+            im += bim[u];
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          re += __shfl_xor(re, o, 64);
+          im += __shfl_xor(im, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+          sb[2 * (threadIdx.x >> 6)] = re;
+          sb[2 * (threadIdx.x >> 6) + 1] = im;
+        }
+        __syncthreads();
+        re = 0;
+        im = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          re += sb[2 * w];
+          im += sb[2 * w + 1];
+        }
+        double be = 0;
+        if (bf.rz_old && bf.active[j] && bf.rz_old[2 * j] != 0) be = re / bf.rz_old[2 * j];
+        bt = (R)be;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          const bool keep = bf.rz_old && !bf.active[j];
+          bf.rz_new[2 * j] = keep ? bf.rz_old[2 * j] : re;
+          bf.rz_new[2 * j + 1] = keep ? bf.rz_old[2 * j + 1] : im;
+        }
       } else {
-        stv(y, i0, o0);
-        stv(y, i1, o1);
+        bt = (R)beta[blockIdx.y];
       }
-    } else if (MODE == 1 || MODE == 3) {
-      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      xacc[i0] = MODE == 3 ? c * v0 : ep0[k] + c * v0;
-      xacc[i1] = MODE == 3 ? c * v1 : ep1[k] + c * v1;
-      stv(y, i0, v0 - c * o0);
-      stv(y, i1, v1 - c * o1);
-    } else if (MODE == 4 || MODE == 5) {
-      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      const cpx<R> a0 = MODE == 5 ? c * v0 : ep0[k] + c * v0;
-      const cpx<R> a1 = MODE == 5 ? c * v1 : ep1[k] + c * v1;
-      xacc[i0] = a0 + c2 * (v0 - c * o0);
-      xacc[i1] = a1 + c2 * (v1 - c * o1);
-    } else if (MODE == 7) {
-      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      const cpx<R> z0 = ep0[k] + c * v0 + c2 * (v0 - c * o0);
-      const cpx<R> z1 = ep1[k] + c * v1 + c2 * (v1 - c * o1);
-      xacc[i0] = z0;
-      xacc[i1] = z1;
-      const cpx<R> a0 = ea0[k], a1 = ea1[k];
-      dre += (double)a0.re * z0.re + (double)a0.im * z0.im + (double)a1.re * z1.re + (double)a1.im * z1.im;
-      dim += (double)a0.re * z0.im - (double)a0.im * z0.re + (double)a1.re * z1.im - (double)a1.im * z1.re;
-    } else if (MODE == 6) {
-      const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
-      xacc[i0] = v0;
-      xacc[i1] = v1;
-      stv(y, i0, o0);
-      stv(y, i1, o1);
-      dre += (double)v0.re * o0.re + (double)v0.im * o0.im + (double)v1.re * o1.re + (double)v1.im * o1.im;
-      dim += (double)v0.re * o0.im - (double)v0.im * o0.re + (double)v1.re * o1.im - (double)v1.im * o1.re;
-    } else {
-      stv(y, i0, ep0[k] - o0);
-      stv(y, i1, ep1[k] - o1);
     }
-  }
-  if constexpr (MODE == 6 || MODE == 7) {
-    __shared__ double sred[2 * (kThreads / 64)];
-    for (int o = 32; o > 0; o >>= 1) {
-      dre += __shfl_xor(dre, o, 64);
-      dim += __shfl_xor(dim, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      sred[2 * (threadIdx.x >> 6)] = dre;
-      sred[2 * (threadIdx.x >> 6) + 1] = dim;
+#pragma unroll
+    for (int j = 0; j < NPASS; ++j) {
+      const int i = threadIdx.x + j * kThreads;
+      if constexpr (MODE == 6) {
+        // p = z + beta p_old; p = z where beta = 0 (p_old is not read into the sum then)
+        if (i < NSP) sp[i] = bt != (R)0 ? widen(stage[j]) + bt * stage2[j] : widen(stage[j]);
+      } else {
+        if (i < NSP) sp[i] = widen(stage[j]);
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0, b = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        a += sred[2 * w];
-        b += sred[2 * w + 1];
-      }
-      const size_t pi = 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x);
-      partial[pi] = a;
-      partial[pi + 1] = b;
+
+    auto P = [&](int ht, int hx, int comp) -> cpx<R> { return sp[(ht * HX + hx) * 2 + comp]; };
+    const R half = (R)0.5;
+
+    // D (or a projection of it) at halo coordinates (hx, ht), global (gx, gt).
+    auto d_at = [&](int hx, int ht, cpx<R> u0, cpx<R> u1, cpx<R> u0m, cpx<R> u1m, int skip, cpx<R>& o0,
+                    cpx<R>& o1) {
+      cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
+      if (skip != kSkipXp) hop_acc<R, false>(s0, s1, 0, u0, P(ht, hx + 1, 0), P(ht, hx + 1, 1));
+      if (skip != kSkipXm) hop_acc<R, false>(s0, s1, 1, cj(u0m), P(ht, hx - 1, 0), P(ht, hx - 1, 1));
+      if (skip != kSkipTp) hop_acc<R, false>(s0, s1, 2, u1, P(ht + 1, hx, 0), P(ht + 1, hx, 1));
+      if (skip != kSkipTm) hop_acc<R, false>(s0, s1, 3, cj(u1m), P(ht - 1, hx, 0), P(ht - 1, hx, 1));
+      o0 = diag * P(ht, hx, 0) - half * s0;
+      o1 = diag * P(ht, hx, 1) - half * s1;
+    };
+
+    // ---- phase 1: phi on the tile ------------------------------------------------
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int r = lti + k * RG;
+      d_at(lxi + 1, r + 1, ku0[k], ku1[k], ku0m[k], ku1m[k], kSkipNone, f0[k], f1[k]);
+      sf[(r * TX + lxi) * 2] = f0[k];
+      sf[(r * TX + lxi) * 2 + 1] = f1[k];
     }
+    // ---- phase 1b: projected phi on the ring -------------------------------------
+    if (threadIdx.x < NRING) {
+      cpx<R> o0, o1;
+      d_at(rhx, rht, ru0, ru1, ru0m, ru1m, rskip, o0, o1);
+      // D^H at the neighbouring tile site uses: from x0-1 (its -x hop) (1 - s1) -> o0 - o1;
+      // from x0+TX (+x hop) (1 + s1) -> o0 + o1; from t0-1 (1 - s2) -> o0 + i o1;
+      // from t0+TT (1 + s2) -> o0 - i o1.
+      cpx<R> h;
+      if (rskip == kSkipXm) h = o0 - o1;
+      else if (rskip == kSkipXp) h = o0 + o1;
+      else if (rskip == kSkipTm) h = o0 + imul(o1);
+      else h = o0 - imul(o1);
+      sr[threadIdx.x] = h;
+    }
+    __syncthreads();
+
+    // ---- phase 2: D^H phi on the tile ---------------------------------------------
+    double dre = 0, dim = 0;  // MODE 6: this thread's share of <p, A p>
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int r = lti + k * RG;
+      const int gx = x0 + lxi, gt = t0 + r;
+      const int s = gt * lx + gx;
+      cpx<R> s0 = mk<R>(0, 0), s1 = mk<R>(0, 0);
+      // +x neighbour: (1 + s1) U0_s phi_{s+x}
+      {
+        cpx<R> h;
+        if (lxi + 1 < TX) h = sf[(r * TX + lxi + 1) * 2] + sf[(r * TX + lxi + 1) * 2 + 1];
+        else h = sr[TT + r];
+        h = ku0[k] * h;
+        s0 = s0 + h; s1 = s1 + h;
+      }
+      // -x neighbour: (1 - s1) conj(U0_{s-x}) phi_{s-x}
+      {
+        cpx<R> h;
+        if (lxi > 0) h = sf[(r * TX + lxi - 1) * 2] - sf[(r * TX + lxi - 1) * 2 + 1];
+        else h = sr[r];
+        h = cj(ku0m[k]) * h;
+        s0 = s0 + h; s1 = s1 - h;
+      }
+      // +t neighbour: (1 + s2) U1_s phi_{s+t}: h = phi0 - i phi1, spread (1, i)
+      {
+        cpx<R> h;
+        if (r + 1 < TT) h = sf[((r + 1) * TX + lxi) * 2] - imul(sf[((r + 1) * TX + lxi) * 2 + 1]);
+        else h = sr[2 * TT + TX + lxi];
+        h = ku1[k] * h;
+        s0 = s0 + h; s1 = s1 + imul(h);
+      }
+      // -t neighbour: (1 - s2) conj(U1_{s-t}) phi_{s-t}: h = phi0 + i phi1, spread (1, -i)
+      {
+        cpx<R> h;
+        if (r > 0) h = sf[((r - 1) * TX + lxi) * 2] + imul(sf[((r - 1) * TX + lxi) * 2 + 1]);
+        else h = sr[2 * TT + lxi];
+        h = cj(ku1m[k]) * h;
+        s0 = s0 + h; s1 = s1 - imul(h);
+      }
+      const cpx<R> o0 = diag * f0[k] - half * s0;
+      const cpx<R> o1 = diag * f1[k] - half * s1;
+      const size_t i0 = off + 2 * (size_t)s, i1 = i0 + 1;
+      if (MODE == 0) {
+        if constexpr (NT && std::is_same<TO, cpx<R>>::value) {  // streaming output: keep it out of the caches
+          __builtin_nontemporal_store(o0.re, &y[i0].re);
+          __builtin_nontemporal_store(o0.im, &y[i0].im);
+          __builtin_nontemporal_store(o1.re, &y[i1].re);
+          __builtin_nontemporal_store(o1.im, &y[i1].im);
+        } else {
+          stv(y, i0, o0);
+          stv(y, i1, o1);
+        }
+      } else if (MODE == 1 || MODE == 3) {
+        const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+        xacc[i0] = MODE == 3 ? c * v0 : ep0[k] + c * v0;
+        xacc[i1] = MODE == 3 ? c * v1 : ep1[k] + c * v1;
+        stv(y, i0, v0 - c * o0);
+        stv(y, i1, v1 - c * o1);
+      } else if (MODE == 4 || MODE == 5) {
+        const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+        const cpx<R> a0 = MODE == 5 ? c * v0 : ep0[k] + c * v0;
+        const cpx<R> a1 = MODE == 5 ? c * v1 : ep1[k] + c * v1;
+        xacc[i0] = a0 + c2 * (v0 - c * o0);
+        xacc[i1] = a1 + c2 * (v1 - c * o1);
+      } else if (MODE == 7) {
+        const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+        const cpx<R> z0 = ep0[k] + c * v0 + c2 * (v0 - c * o0);
+        const cpx<R> z1 = ep1[k] + c * v1 + c2 * (v1 - c * o1);
+        xacc[i0] = z0;
+        xacc[i1] = z1;
+        const cpx<R> a0 = ea0[k], a1 = ea1[k];
+        dre += (double)a0.re * z0.re + (double)a0.im * z0.im + (double)a1.re * z1.re + (double)a1.im * z1.im;
+        dim += (double)a0.re * z0.im - (double)a0.im * z0.re + (double)a1.re * z1.im - (double)a1.im * z1.re;
+      } else if (MODE == 6) {
+        const cpx<R> v0 = P(r + 1, lxi + 1, 0), v1 = P(r + 1, lxi + 1, 1);
+        xacc[i0] = v0;
+        xacc[i1] = v1;
+        stv(y, i0, o0);
+        stv(y, i1, o1);
+        dre += (double)v0.re * o0.re + (double)v0.im * o0.im + (double)v1.re * o1.re + (double)v1.im * o1.im;
+        dim += (double)v0.re * o0.im - (double)v0.im * o0.re + (double)v1.re * o1.im - (double)v1.im * o1.re;
+      } else {
+        stv(y, i0, ep0[k] - o0);
+        stv(y, i1, ep1[k] - o1);
+      }
+    }
+    if constexpr (MODE == 6 || MODE == 7) {
+      __shared__ double sred[2 * (kThreads / 64)];
+      for (int o = 32; o > 0; o >>= 1) {
+        dre += __shfl_xor(dre, o, 64);
+        dim += __shfl_xor(dim, o, 64);
+      }
+      if ((threadIdx.x & 63) == 0) {
+        sred[2 * (threadIdx.x >> 6)] = dre;
+        sred[2 * (threadIdx.x >> 6) + 1] = dim;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          a += sred[2 * w];
+          b += sred[2 * w + 1];
+        }
+        const size_t pi = 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x);
+        partial[pi] = a;
+        partial[pi + 1] = b;
+      }
+    }
+    if (NRB > 1) __syncthreads();  // the next right-hand side overwrites sp, sf and sr
   }
 }
 
@@ -502,13 +512,31 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
   HIPCHECK(hipGetLastError());
 }
 
+// With at least kFusedNRB right-hand sides on a lattice of at least kFusedNRBSites
+// sites a workgroup takes kFusedNRB of them in turn and loads its links once (96 ->
+// 64 + 32 / kFusedNRB bytes per site and right-hand side in FP64); each column's
+// arithmetic is the same either way.  Measured on MI355X: 2048^2, 64 RHS: FP64 4.29
+// -> 3.82 ms, FP32 2.24 -> 1.87 ms; at 512^2 (cache-resident, and the loop halves the
+// waves per SIMD) FP64 32 RHS ran 0.099 -> 0.112 ms, so small lattices keep one
+// right-hand side per workgroup.  Dispatching a tile's right-hand sides next to each
+// other instead (links from L2, one per workgroup) was slower at both sizes.
+constexpr int kFusedNRB = 4;
+constexpr long kFusedNRBSites = 1L << 20;
+
 template <typename R, int TX, int TT, bool NT>
 void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs, int mode,
                   double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
-  dim3 grid((lx / TX) * (lt / TT), nrhs);
+  const int tiles = (lx / TX) * (lt / TT);
   with_mode(mode, [&](auto m) {
-    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, decltype(m)::v, NT>), grid, dim3(kThreads), 0, st, U, x, y, lx, lt,
-                       (R)diag, (R)c, (R)c2, xacc, aux);
+    constexpr int M = decltype(m)::v;
+    if (nrhs >= kFusedNRB && (long)lx * lt >= kFusedNRBSites) {
+      dim3 grid(tiles, (nrhs + kFusedNRB - 1) / kFusedNRB);
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT, cpx<R>, cpx<R>, kFusedNRB>), grid, dim3(kThreads), 0, st,
+                         U, x, y, lx, lt, (R)diag, (R)c, (R)c2, xacc, aux, nullptr, nullptr, BetaFold{}, nrhs);
+    } else {
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT>), dim3(tiles, nrhs), dim3(kThreads), 0, st, U, x, y, lx,
+                         lt, (R)diag, (R)c, (R)c2, xacc, aux);
+    }
   });
   HIPCHECK(hipGetLastError());
 }

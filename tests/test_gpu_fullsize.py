@@ -369,3 +369,58 @@ def test_paper_experiment_setting(cuda):
         assert code == 0
         assert np.linalg.norm(rhs - A @ host(x)) / np.linalg.norm(rhs) <= 1e-12
         assert abs(st[0]["iterations"] - io.iterations) <= max(1, io.iterations // 10), (st[0], io.iterations)
+
+
+# ---------------------------------------------------------------------------
+# Several right-hand sides per workgroup (lattices of at least 2^20 sites)
+# ---------------------------------------------------------------------------
+
+def test_fused_rhs_groups_equal_single_columns(cuda):
+    """On a 1024x1024 lattice a fused-A workgroup takes four right-hand sides in turn
+    (the links loaded once for them). Every column of a 6-column call (a group of 4
+    and a ragged group of 2) equals the same column applied alone, bit for bit, for
+    the plain operator, the MR steps from zero and accumulating, the residual (FP64
+    and FP32), and the fused smoother; one column of A x matches the oracle's D^H D."""
+    import torch
+
+    smg = smg_mod()
+    lx = lt = 1024
+    m = 0.07
+    U = field(lx, lt, seed=1024)
+    n = 2 * lx * lt
+    vecs, calib = vectors_for(lx, lt, [(8, 8)], [2], 3)
+    p = smg.make_params(lx, lt, m, levels=2, blocks=[(8, 8)], nv=[2], coarsest=smg.COARSEST_CG)
+    s = smg.Solver(dev(U), p, vectors=dev(np.concatenate([v.ravel() for v in vecs])), calib=dev(np.concatenate(calib)))
+    try:
+        nr = 6
+        x = synth.gaussian((nr, n), 1025)
+        aux = synth.gaussian((nr, n), 1026)
+        acc = synth.gaussian((nr, n), 1027)
+        coef = 0.31
+
+        def ops(level_op, conv, cols):
+            xt = conv(x[cols])
+            out = [host(level_op(0, xt, mode=0))]
+            xa = conv(acc[cols])
+            out.append(host(level_op(0, xt, mode=1, coef=coef, xacc=xa)))
+            out.append(host(xa))
+            out.append(host(level_op(0, xt, mode=2, aux=conv(aux[cols]))))
+            xa3 = conv(acc[cols])
+            out.append(host(level_op(0, xt, mode=3, coef=coef, xacc=xa3)))
+            out.append(host(xa3))
+            torch.cuda.synchronize()
+            return [o.reshape(-1, n) for o in out]
+
+        for level_op, conv in ((s.level_op, dev), (s.level_op_f32, dev32)):
+            many = ops(level_op, conv, slice(0, nr))
+            for j in range(nr):
+                one = ops(level_op, conv, slice(j, j + 1))
+                for a, b in zip(many, one):
+                    assert np.array_equal(a[j], b[0]), j
+        sm = host(s.smooth(0, dev(x))).reshape(nr, n)
+        for j in (0, 5):
+            assert np.array_equal(sm[j], host(s.smooth(0, dev(x[j:j + 1]))).reshape(n))
+        D = dirac_matrix(U, m)
+        assert rel_err(host(s.apply_A(dev(x))).reshape(nr, n)[5], D.conj().T @ (D @ x[5])) <= 1e-12
+    finally:
+        s.close()
