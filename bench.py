@@ -475,6 +475,47 @@ def c5_leg(args, torch, smg, dev):
                 seconds=time.perf_counter() - t_start)
 
 
+def grouped_leg(args, torch, smg, syss, xs_single, streams):
+    """The same mixed solves as grouped solves (smg_group_solve): the systems split
+    into args.groups groups of one hierarchy shape, each group on its own stream and
+    host thread, every launch serving all systems of its group.  The solutions are
+    compared bit for bit with the single solves' (xs_single)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    ng = max(1, min(args.groups, len(syss), len(streams)))
+    parts = [list(range(k, len(syss), ng)) for k in range(ng)]
+    groups = [smg.Group([syss[j][0] for j in part], stream=streams[k]) for k, part in enumerate(parts)]
+    rhs = [torch.stack([syss[j][1].reshape(-1) for j in part]) for part in parts]
+    outs = [torch.empty_like(r) for r in rhs]
+    recs = []
+
+    def run(k, rec):
+        with torch.cuda.stream(streams[k]):
+            _, st, code = groups[k].solve(rhs[k], tol=TOL, maxiter=2000, out=outs[k], stream=streams[k])
+            if code != 0 or max(q["true_relres"] for q in st) > TOL:
+                raise RuntimeError(f"grouped solve did not converge: {st}")
+            if rec is not None:
+                rec.extend(q["iterations"] for q in st)
+
+    pool = ThreadPoolExecutor(max_workers=ng)
+    for f in [pool.submit(run, k, recs) for k in range(ng)]:
+        f.result()
+    torch.cuda.synchronize()
+    equal = all(torch.equal(outs[k][i], xs_single[j].reshape(-1)) for k, part in enumerate(parts)
+                for i, j in enumerate(part))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for f in [pool.submit(run, k, None) for k in range(ng)]:
+            f.result()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pool.shutdown()
+    for g in groups:
+        g.close()
+    return dict(solves_per_s=len(syss) * args.steps / dt, groups=ng, systems_per_group=[len(p) for p in parts],
+                mean_iterations=sum(recs) / len(recs), equal_to_single=bool(equal))
+
+
 def legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu):
     """The other legs' headline figures in a few numbers (their full records follow
     the config in the same line)."""
@@ -898,6 +939,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
     ap.add_argument("--no-mrhs", action="store_true")
+    ap.add_argument("--no-group", action="store_true", help="skip the grouped solves of the headline systems")
+    ap.add_argument("--groups", type=int, default=4, help="groups (streams) of the grouped headline solves")
     ap.add_argument("--no-split", action="store_true", help="skip the chirality-split comparison")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
@@ -1079,9 +1122,14 @@ def main():
         return dict(seconds=dt, solves=len(syss) * args.steps, records=rec)
 
     results = {}
-    for name, _opst, _c64 in VARIANTS:
+    grouped = None
+    for vi, (name, _opst, _c64) in enumerate(VARIANTS):
         results[name] = timed(variant_systems[name][0], smg.MIXED)
         log(f"mixed {name}: {results[name]['solves'] / results[name]['seconds']:.1f} solves/s")
+        if vi == 0 and not args.no_group:
+            grouped = grouped_leg(args, torch, smg, variant_systems[name][0], xs, streams)
+            log(f"grouped {name}: {grouped['solves_per_s']:.1f} solves/s ({grouped['groups']} groups, "
+                f"bitwise equal to the single solves: {grouped['equal_to_single']})")
     results["fp64"] = timed(systems, smg.FP64)
     log(f"fp64: {results['fp64']['solves'] / results['fp64']['seconds']:.1f} solves/s")
     if cpu_proc is not None:  # the headline rates are taken: the oracle may use the host now
@@ -1252,6 +1300,7 @@ def main():
             "mean_iterations_mixed": sum(r["iterations"] for r in mixed["records"]) / len(mixed["records"]),
             "mean_iterations_fp64": sum(r["iterations"] for r in fp64["records"]) / len(fp64["records"]),
             "max_relres": max(r["relres"] for r in mixed["records"] + fp64["records"]),
+            "grouped": grouped,
             "legs": legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu),
         },
         "roofline": roof,

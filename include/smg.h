@@ -71,6 +71,7 @@ enum { SMG_STORE_F32 = 0, SMG_STORE_BF16 = 1, SMG_STORE_F16 = 2 };
 
 typedef struct smg_ctx* smg_handle;
 typedef struct smg_batch_s* smg_batch;
+typedef struct smg_group_s* smg_group;
 
 typedef struct {
   int32_t lx, lt;                 /* fine extents, even, divisible by the product of blocks */
@@ -378,6 +379,29 @@ int smg_batch_cancel(smg_batch b, int32_t slot, void* stream);
  * are bitwise identical either way.  Errors: SMG_EINVAL (graphs with a CG coarsest
  * solve, which synchronises with the host). */
 int smg_batch_use_graphs(smg_batch b, int32_t enable);
+
+/* Grouped solves (Results section: many solves amortise one setup; here many
+ * systems also share each launch).  A group binds nsys handles whose hierarchies
+ * have one shape: the same lattice, levels, blocks, vectors per level (after an
+ * adaptive stop, the counts that were kept), smoother steps (>= 2) and storage,
+ * smoother_storage F32, a dense coarsest inverse of at most 4096 variables and
+ * 4 <= nc <= 16 on the intermediate levels.  Masses, fields and setups may differ.
+ * smg_group_solve solves A_j x_j = rhs_j for every system j with the SMG_MIXED solve,
+ * system j in column j of every launch, so one launch per step serves all of them;
+ * column j's arithmetic is that of smg_solve on handle j with one right-hand side,
+ * so x_j equals that solve's result bit for bit.
+ * rhs, x: device complex128 [nsys][lt][lx][2]; stats: host array of nsys or NULL.
+ * The group runs on the first handle's context (its work vectors for nsys columns,
+ * kept like a solve's) and reads every handle's operators in place: while the group
+ * is used, no other call may use the first handle, and a re-mass of any handle is
+ * picked up by the next group solve.  The group holds only its small tables of
+ * per-system pointers, scales and smoother coefficients; destroy it before its handles.
+ * Errors: SMG_EINVAL (shapes or options not supported, null arguments); the codes of
+ * smg_solve.  Returns SMG_NOTCONV when some system did not reach tol. */
+int smg_group_create(const smg_handle* hs, int32_t nsys, void* stream, smg_group* out);
+int smg_group_solve(smg_group g, const double* rhs, double* x, double tol, int32_t maxiter, void* stream,
+                    smg_stats* stats);
+void smg_group_destroy(smg_group g);
 
 /* Device bytes held by the batch (in addition to its handle). */
 int smg_batch_memory_bytes(smg_batch b, size_t* bytes);

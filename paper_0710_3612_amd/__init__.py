@@ -132,11 +132,14 @@ _progress = None  # every installed callback (kept alive while the library may c
 # call a release callback that may already be gone).
 _live_solvers = weakref.WeakSet()
 _live_batches = weakref.WeakSet()
+_live_groups = weakref.WeakSet()
 
 
 def _close_all():
     for b in list(_live_batches):
         b.close()
+    for g in list(_live_groups):
+        g.close()
     for s in list(_live_solvers):
         s.close()
 
@@ -197,6 +200,9 @@ def load_library():
         "smg_batch_memory_bytes": (i32, [h, ctypes.POINTER(ctypes.c_size_t)]),
         "smg_batch_use_graphs": (i32, [h, i32]),
         "smg_batch_destroy": (None, [h]),
+        "smg_group_create": (i32, [ctypes.POINTER(h), i32, P, ctypes.POINTER(h)]),
+        "smg_group_solve": (i32, [h, P, P, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
+        "smg_group_destroy": (None, [h]),
         "smg_destroy": (None, [h]),
         "smg_strerror": (ctypes.c_char_p, [i32]),
         "smg_last_error": (ctypes.c_char_p, []),
@@ -596,6 +602,56 @@ class Solver:
         cnt = ctypes.c_int32()
         _check(self.lib.smg_get_setup_factors(self.handle, level, buf, 64, ctypes.byref(cnt)))
         return [buf[i] for i in range(cnt.value)]
+
+
+class Group:
+    """Several independent systems of one hierarchy shape solved together
+    (smg_group_*): system j is column j of every launch of the mixed-precision
+    solve, so one launch per step serves all of them, and x_j equals Solver j's own
+    one-column solve bit for bit.  The first solver runs the group: no other call
+    may use it while the group is in use."""
+
+    def __init__(self, solvers, stream=None):
+        self.lib = solvers[0].lib
+        self.solvers = list(solvers)
+        self.n = solvers[0].level_size(0)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.smg_group_create(arr, len(self.solvers), _stream(stream), ctypes.byref(self.handle)))
+        self._torch = solvers[0]._torch
+        _live_groups.add(self)
+
+    def solve(self, rhs, tol: float = 1e-10, maxiter: int = 10000, out=None, stream=None):
+        """rhs: [nsys, n] complex128 CUDA tensor; returns (x, [per-system stats], status)."""
+        rhs = rhs.contiguous()
+        G = len(self.solvers)
+        if tuple(rhs.shape) != (G, self.n) or rhs.dtype != self._torch.complex128 or not rhs.is_cuda:
+            raise ValueError(f"rhs must be a complex128 CUDA tensor of shape ({G}, {self.n})")
+        x = out if out is not None else self._torch.empty_like(rhs)
+        st = (Stats * G)()
+        code = self.lib.smg_group_solve(self.handle, _ptr(rhs), _ptr(x), float(tol), int(maxiter), _stream(stream),
+                                        st)
+        _check(code, allow_notconv=True)
+        return x, [q.as_dict() for q in st], code
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.smg_group_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Batch:

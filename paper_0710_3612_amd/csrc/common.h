@@ -158,6 +158,20 @@ template <typename R>
 void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs,
                    bool dagger, hipStream_t st);
 
+// Per-column operators of a grouped solve: several independent systems of one shape
+// advanced together, system j in column j of every launch.  Column j reads op[j] (its
+// links, prolongator or coarsest inverse) and s[j] (their power-of-two scale, or the
+// fine diagonal 2 + m) in place of the launch's own, and c[j], c2[j] (its smoother
+// coefficients) where non-null.  op = nullptr: an ordinary launch.  Grouped launches
+// take one column per workgroup, the kernels a single system uses, so column j's
+// arithmetic is that of system j solved alone.
+struct Grp {
+  const void* const* op = nullptr;
+  const double* s = nullptr;
+  const double* c = nullptr;
+  const double* c2 = nullptr;
+};
+
 // Fine normal operator with an epilogue.  mode:
 //   0: y = A x
 //   1: smoother step   xacc += c * x ;  y = x - c * A x
@@ -165,7 +179,8 @@ void launch_wilson(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, 
 // A x = D^H (D x); `tmp` holds D x ([nrhs][V][2]).
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
-                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
+                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0,
+                   const Grp& g = Grp{});
 
 // beta of the fused CG step formed inside the kernel (part == nullptr: read beta[rhs]).
 // Every workgroup sums the nb partials of <r, z> per column in the order of the
@@ -189,13 +204,13 @@ int cg_step_blocks(int lx, int lt);
 template <typename R>
 void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
                     double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
-                    const BetaFold& bf = BetaFold{});
+                    const BetaFold& bf = BetaFold{}, const Grp& g = Grp{});
 // The last fine apply of a V-cycle with the CG dot folded in: z += c v + c2 (v - c A v)
 // (the last two smoother steps) and per workgroup <r, z> into partial[rhs][block]
 // (cg_step_blocks(lx, lt) blocks).
 template <typename R>
 void launch_vcycle_end(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
-                       int nrhs, double c, double c2, double* partial, hipStream_t st);
+                       int nrhs, double c, double c2, double* partial, hipStream_t st, const Grp& g = Grp{});
 // FP32 fine A with x and y stored as TI / TO (z32, bfc or hfc); fused kernel only
 // (lx and lt multiples of 16).
 template <typename TI, typename TO>
@@ -206,7 +221,7 @@ bool normal_lp_fits(int lx, int lt);
 // (z32, bfc or hfc).
 template <typename TP, typename TI>
 void launch_restrict_s(const TP* P, float ps, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h,
-                       int nc, int ldk, int nrhs, hipStream_t st);
+                       int nc, int ldk, int nrhs, hipStream_t st, const Grp& g = Grp{});
 // x += a y for y stored as TI.
 template <typename TI>
 void launch_axpy_const_lp(z32* y, const TI* x, double a, size_t n, int nrhs, hipStream_t st);
@@ -216,10 +231,10 @@ void launch_zero(void* p, size_t bytes, hipStream_t st);
 // Coarse 9-point operator on level with extents (cx, ct), nc dof; links [9][nc][K][nc].
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                   double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0);
+                   double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2 = 0, const Grp& g = Grp{});
 // The same with the links stored in FP16 scaled by 1 / lscale (a power of two).
 void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
-                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
+                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2 = 0, const Grp& g = Grp{});
 // Matrix-core (MFMA FP32) coarse apply for 1 <= nc <= 16, any number of right-hand sides.
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                         z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
@@ -240,11 +255,12 @@ void launch_restrict_mfma64(const z64* P, const z64* x, z64* y, int lx, int lt, 
 // mfma (FP64 only, nc <= 16): the window phase on the matrix cores.
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false);
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false,
+                    const Grp& g = Grp{});
 
 // FP32 prolongation with P stored in FP16 scaled by 1 / ps.
 void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,
-                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st);
+                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, const Grp& g = Grp{});
 
 // Block Gram-Schmidt of candidate `v` as vector k of every aggregate (FP64).
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int m,
@@ -266,9 +282,11 @@ void launch_coarse_to_dense(const z64* L, z64* M, int cx, int ct, int nc, hipStr
 void launch_gj_step(z64* M, int n, int k, z64* colk, double* piv, int* fail, hipStream_t st);
 // Y = M X, M dense row-major n x n in precision RM, X and Y [nrhs][n].
 template <typename RM, typename R>
-void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st);
+void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st,
+                        const Grp& g = Grp{});
 // FP32 y = M x with M stored in FP16 scaled by 1 / mscale (a power of two).
-void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st);
+void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st,
+                            const Grp& g = Grp{});
 // Per-block maxima of max(|re|, |im|) over n values into part[0 .. blocks).
 void launch_absmax_partial(const z64* a, size_t n, double* part, int blocks, hipStream_t st);
 // out = FP16(in * inv_scale).

@@ -211,7 +211,11 @@ __device__ inline float butterfly_sum(float (&v)[2 * NCOL], int lane) {
 template <int NCOL, int NCH, typename TX, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__ P, const TX* __restrict__ x,
                                                           z32* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                          int bt, int h, int nc, int ldk, float ps, int nrhs) {
+                                                          int bt, int h, int nc, int ldk, float ps, int nrhs, Grp g) {
+  if (g.op) {  // grouped (NRB = 1): this column's system
+    P = static_cast<const TP*>(g.op[blockIdx.y]);
+    ps = (float)g.s[blockIdx.y];
+  }
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
   const int K = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (K >= nK) return;  // whole wavefronts; the kernel has no barrier
@@ -275,7 +279,12 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bf(const TP* __restrict__
 template <int NCOL, int CPW, typename TX, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict__ P, const TX* __restrict__ x,
                                                            z32* __restrict__ y, int lx, int lt, int dof, int bx,
-                                                           int bt, int h, int nc, int ldk, float ps, int nrhs) {
+                                                           int bt, int h, int nc, int ldk, float ps, int nrhs,
+                                                           Grp g) {
+  if (g.op) {  // grouped (NRB = 1): this column's system
+    P = static_cast<const TP*>(g.op[blockIdx.y]);
+    ps = (float)g.s[blockIdx.y];
+  }
   constexpr int NW = kThreads / 64, V = 2 * NCOL, LOGV = V == 8 ? 3 : V == 16 ? 4 : 5;
   __shared__ float part[NRB][NW][V];
   const int cx = lx / bx, ct = lt / bt, nK = cx * ct;
@@ -338,7 +347,11 @@ __global__ void __launch_bounds__(kThreads) k_restrict_bfw(const TP* __restrict_
 template <typename R, typename TP, int NRB>
 __global__ void __launch_bounds__(kThreads) k_prolong_win(const TP* __restrict__ P, const cpx<R>* __restrict__ e,
                                                           cpx<R>* __restrict__ wbuf, int nK, int nw, int nc, int ldk,
-                                                          R ps, int nrhs) {
+                                                          R ps, int nrhs, Grp g) {
+  if (g.op) {  // grouped (NRB = 1): this column's system
+    P = static_cast<const TP*>(g.op[blockIdx.y]);
+    ps = (R)g.s[blockIdx.y];
+  }
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nK * nw) return;
   const int K = (int)(idx / nw), i = (int)(idx - (size_t)K * nw);
@@ -548,9 +561,15 @@ template <typename R, int MODE, int Q, typename TL>
 __global__ void __launch_bounds__(kThreads) k_coarse_sv(const TL* __restrict__ L, const cpx<R>* __restrict__ v,
                                                         cpx<R>* __restrict__ y, int cx, int ct, int nc, R c, R c2,
                                                         cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux,
-                                                        R lscale) {
+                                                        R lscale, Grp g) {
   __shared__ cpx<R> part[3][64];
   __shared__ cpx<R> sv[kCoarseSvMax];
+  if (g.op) {  // grouped: this column's system
+    L = static_cast<const TL*>(g.op[blockIdx.y]);
+    lscale = (R)g.s[blockIdx.y];
+    if (g.c) c = (R)g.c[blockIdx.y];
+    if (g.c2) c2 = (R)g.c2[blockIdx.y];
+  }
   const int nK = cx * ct;
   const size_t n = (size_t)nK * nc;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -921,7 +940,7 @@ int colors_along(int extent) { return extent < 3 ? extent : 3 + (extent - 3 * (e
 
 template <typename R, typename TP, typename TX>
 void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt, int dof, int bx, int bt, int h,
-                       int nc, int ldk, int nrhs, hipStream_t st) {
+                       int nc, int ldk, int nrhs, hipStream_t st, const Grp& grp = Grp{}) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   if constexpr (std::is_same<R, float>::value) {
@@ -929,15 +948,16 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
     const int nch = (nw + 63) / 64, ncol = nc <= 4 ? 4 : nc <= 8 ? 8 : 16;
     if (nc <= 16 && nch <= 2 && ncol * nch * (int)(sizeof(TP) / 4) <= 64) {
       // eight right-hand sides per wavefront share its P rows once there are that many
-      const int nrb = nrhs >= 8 ? 8 : 1;
+      // (grouped: one per wavefront, each column its own P)
+      const int nrb = nrhs >= 8 && !grp.op ? 8 : 1;
       dim3 g((nK + kThreads / 64 - 1) / (kThreads / 64), (nrhs + nrb - 1) / nrb);
       auto go = [&](auto ncl, auto ch) {
         if (nrb == 8)
           hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP, 8>), g, dim3(kThreads), 0, st,
-                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs, Grp{});
         else
           hipLaunchKernelGGL((k_restrict_bf<decltype(ncl)::v, decltype(ch)::v, TX, TP, 1>), g, dim3(kThreads), 0, st,
-                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs, grp);
       };
       auto by_ch = [&](auto ncl) {
         if (nch == 1) go(ncl, IntC<1>{});
@@ -953,15 +973,15 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
     const int cpw = (nch + kThreads / 64 - 1) / (kThreads / 64);
     if (nc <= 16 && cpw <= 3 && ncol * cpw * (int)(sizeof(TP) / 4) <= 64) {
       // four right-hand sides per workgroup share its P rows once there are that many
-      const int nrb = nrhs >= 4 ? 4 : 1;
+      const int nrb = nrhs >= 4 && !grp.op ? 4 : 1;
       dim3 g(nK, (nrhs + nrb - 1) / nrb);
       auto go = [&](auto ncl, auto cw) {
         if (nrb == 4)
           hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP, 4>), g, dim3(kThreads), 0, st,
-                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs, Grp{});
         else
           hipLaunchKernelGGL((k_restrict_bfw<decltype(ncl)::v, decltype(cw)::v, TX, TP, 1>), g, dim3(kThreads), 0, st,
-                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs);
+                             P, x, y, lx, lt, dof, bx, bt, h, nc, ldk, ps, nrhs, grp);
       };
       auto by_cw = [&](auto ncl) {
         if (cpw == 1) go(ncl, IntC<1>{});
@@ -975,6 +995,7 @@ void launch_restrict_t(const TP* P, R ps, const TX* x, cpx<R>* y, int lx, int lt
       return;
     }
   }
+  if (grp.op) throw Error(-1, "grouped restriction needs the one-wavefront or one-workgroup kernel");
   dim3 grid(nK, nrhs);
   dispatch_chunks((nw + 63) / 64, [&](auto c) {
     launch_restrict_kw<R, decltype(c)::v, TX, TP>(grid, st, P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs);
@@ -1087,12 +1108,12 @@ void launch_restrict(const cpx<R>* P, const cpx<R>* x, cpx<R>* y, int lx, int lt
 
 template <typename TP, typename TI>
 void launch_restrict_s(const TP* P, float ps, const TI* x, z32* y, int lx, int lt, int dof, int bx, int bt, int h,
-                       int nc, int ldk, int nrhs, hipStream_t st) {
-  launch_restrict_t<float, TP, TI>(P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, st);
+                       int nc, int ldk, int nrhs, hipStream_t st, const Grp& g) {
+  launch_restrict_t<float, TP, TI>(P, ps, x, y, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, st, g);
 }
 #define INST_RS(TP, TI)                                                                                         \
   template void launch_restrict_s<TP, TI>(const TP*, float, const TI*, z32*, int, int, int, int, int, int, int, \
-                                          int, int, hipStream_t);
+                                          int, int, hipStream_t, const Grp&);
 INST_RS(z32, z32)
 INST_RS(z32, bfc)
 INST_RS(z32, hfc)
@@ -1170,7 +1191,8 @@ __global__ void __launch_bounds__(256) k_prolong_win_mfma64(const z64* __restric
 
 template <typename R, typename TP>
 void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                      int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false) {
+                      int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma = false,
+                      const Grp& grp = Grp{}) {
   const int nK = (lx / bx) * (lt / bt);
   const int nw = (bx + 2 * h) * (bt + 2 * h) * dof;
   const size_t nkw = (size_t)nK * nw;
@@ -1191,12 +1213,12 @@ void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbu
     }
   }
   if (win_done) {
-  } else if (nrhs >= 8) {  // eight right-hand sides per thread share its P entries
+  } else if (nrhs >= 8 && !grp.op) {  // eight right-hand sides per thread share its P entries
     hipLaunchKernelGGL((k_prolong_win<R, TP, 8>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), (nrhs + 7) / 8),
-                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
-  } else {
+                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs, Grp{});
+  } else {  // one right-hand side per thread (grouped: each column its own P)
     hipLaunchKernelGGL((k_prolong_win<R, TP, 1>), dim3((unsigned)((nkw + kThreads - 1) / kThreads), nrhs),
-                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs);
+                       dim3(kThreads), 0, st, P, e, wbuf, nK, nw, nc, ldk, ps, nrhs, grp);
   }
   const size_t total = (size_t)lx * lt * dof;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), nrhs);
@@ -1221,13 +1243,13 @@ void launch_prolong_t(const TP* P, R ps, const cpx<R>* e, cpx<R>* y, cpx<R>* wbu
 
 template <typename R>
 void launch_prolong(const cpx<R>* P, const cpx<R>* e, cpx<R>* y, cpx<R>* wbuf, int lx, int lt, int dof, int bx,
-                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma) {
-  launch_prolong_t<R, cpx<R>>(P, (R)1, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st, mfma);
+                    int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, bool mfma, const Grp& g) {
+  launch_prolong_t<R, cpx<R>>(P, (R)1, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st, mfma, g);
 }
 
 void launch_prolong_h16(const hfc* P, float ps, const z32* e, z32* y, z32* wbuf, int lx, int lt, int dof, int bx,
-                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st) {
-  launch_prolong_t<float, hfc>(P, ps, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st);
+                        int bt, int h, int nc, int ldk, int nrhs, int mode, hipStream_t st, const Grp& g) {
+  launch_prolong_t<float, hfc>(P, ps, e, y, wbuf, lx, lt, dof, bx, bt, h, nc, ldk, nrhs, mode, st, false, g);
 }
 
 template <typename R, int NR, int Q, typename TL>
@@ -1648,33 +1670,35 @@ void launch_coarse_mfma64(const z64* L, const z64* x, z64* y, int cx, int ct, in
 
 template <typename R, typename TL>
 void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode,
-                     double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                     double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, const Grp& g = Grp{}) {
   // one FP32 right-hand side: vector entries staged in LDS (in FP64 the 27 link loads and
-  // the staged entries need twice the registers, and the plain kernel is faster)
+  // the staged entries need twice the registers, and the plain kernel is faster); a
+  // grouped launch takes it for every column, each with its own links
   if constexpr (std::is_same<R, float>::value) {
-    if (nrhs == 1 && nc >= 4 && nc <= 16) {
+    if ((nrhs == 1 || g.op) && nc >= 4 && nc <= 16) {
       const size_t total = (size_t)cx * ct * nc;
-      const dim3 grid((unsigned)((total + 63) / 64), 1);
+      const dim3 grid((unsigned)((total + 63) / 64), nrhs);
       const int q = (nc + 3) / 4;
       with_mode(mode, [&](auto m) {
         constexpr int M = decltype(m)::v;
         if (q == 1)
           hipLaunchKernelGGL((k_coarse_sv<R, M, 1, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale);
+                             xacc, aux, lscale, g);
         else if (q == 2)
           hipLaunchKernelGGL((k_coarse_sv<R, M, 2, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale);
+                             xacc, aux, lscale, g);
         else if (q == 3)
           hipLaunchKernelGGL((k_coarse_sv<R, M, 3, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale);
+                             xacc, aux, lscale, g);
         else
           hipLaunchKernelGGL((k_coarse_sv<R, M, 4, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale);
+                             xacc, aux, lscale, g);
       });
       HIPCHECK(hipGetLastError());
       return;
     }
   }
+  if (g.op) throw Error(-1, "grouped coarse operator needs FP32 and 4 <= nc <= 16");
   if (nrhs == 1)
     launch_coarse_nr<R, 1, TL>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else if (nrhs <= 2)
@@ -1687,13 +1711,13 @@ void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, 
 
 template <typename R>
 void launch_coarse(const cpx<R>* L, const cpx<R>* x, cpx<R>* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                   cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2) {
-  launch_coarse_t<R, cpx<R>>(L, (R)1, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
+                   cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2, const Grp& g) {
+  launch_coarse_t<R, cpx<R>>(L, (R)1, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, g);
 }
 
 void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
-                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
-  launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
+                       double c, z32* xacc, const z32* aux, hipStream_t st, double c2, const Grp& g) {
+  launch_coarse_t<float, hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, g);
 }
 
 void launch_gs_append(double* P, const z64* v, int lx, int lt, int dof, int bx, int bt, int k, int ldk, int m,
@@ -1760,7 +1784,11 @@ constexpr int kDenseRowsMax = 4096;
 
 template <typename RM, typename R, typename TM = cpx<RM>>
 __global__ void __launch_bounds__(kThreads) k_dense_rows(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                         cpx<R>* __restrict__ y, int n, double mscale) {
+                                                         cpx<R>* __restrict__ y, int n, double mscale, Grp g) {
+  if (g.op) {  // grouped: this column's system
+    M = static_cast<const TM*>(g.op[blockIdx.y]);
+    mscale = g.s[blockIdx.y];
+  }
   const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
@@ -1801,7 +1829,11 @@ struct alignas(4 * sizeof(T)) Quad {
 
 template <typename RM, typename R, typename TM, int G>
 __global__ void __launch_bounds__(kThreads) k_dense_rows4(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
-                                                          cpx<R>* __restrict__ y, int n, double mscale) {
+                                                          cpx<R>* __restrict__ y, int n, double mscale, Grp g) {
+  if (g.op) {  // grouped: this column's system
+    M = static_cast<const TM*>(g.op[blockIdx.y]);
+    mscale = g.s[blockIdx.y];
+  }
   const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
@@ -2004,7 +2036,9 @@ __global__ void __launch_bounds__(256) k_dense_mfma64(const z64* __restrict__ M,
 
 // mscale: power-of-two scale of a reduced-precision M (1 otherwise), applied exactly.
 template <typename RM, typename R, typename TM>
-void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
+void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st,
+                          const Grp& grp = Grp{}) {
+  if (grp.op && n > kDenseRowsMax) throw Error(-1, "grouped coarsest apply needs n <= 4096");
   if (n <= kDenseRowsMax && n % 4 == 0) {
     // quads in flight per lane: all of a row of n <= 4096 in one group where registers allow
     constexpr int W = (int)((sizeof(TM) + sizeof(cpx<R>)) / 4);  // registers per entry pair
@@ -2012,17 +2046,17 @@ void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y
     const int want = (n / 4 + 63) / 64;
     const dim3 g((n + 3) / 4, nrhs);
     if (want <= 4 || GMAX == 4)
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4>), g, dim3(kThreads), 0, st, M, x, y, n, mscale);
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
     else if (want <= 8 || GMAX == 8)
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 8>), g, dim3(kThreads), 0, st, M, x, y, n, mscale);
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 8>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
     else if (want <= 12)
       hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 12 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
-                         mscale);
+                         mscale, grp);
     else
       hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 16 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
-                         mscale);
+                         mscale, grp);
   } else if (n <= kDenseRowsMax) {
-    hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale);
+    hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
   } else if constexpr (std::is_same<R, float>::value && !std::is_same<TM, z64>::value) {
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((nrhs + 31) / 32));
     hipLaunchKernelGGL((k_dense_mfma<TM>), grid, dim3(256), 0, st, M, x, y, n, nrhs, (float)mscale);
@@ -2036,12 +2070,14 @@ void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y
 }
 
 template <typename RM, typename R>
-void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st) {
-  launch_dense_apply_t<RM, R, cpx<RM>>(M, 1.0, x, y, n, nrhs, st);
+void launch_dense_apply(const cpx<RM>* M, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st,
+                        const Grp& g) {
+  launch_dense_apply_t<RM, R, cpx<RM>>(M, 1.0, x, y, n, nrhs, st, g);
 }
 
-void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st) {
-  launch_dense_apply_t<float, float, hfc>(M, mscale, x, y, n, nrhs, st);
+void launch_dense_apply_h16(const hfc* M, double mscale, const z32* x, z32* y, int n, int nrhs, hipStream_t st,
+                            const Grp& g) {
+  launch_dense_apply_t<float, float, hfc>(M, mscale, x, y, n, nrhs, st, g);
 }
 
 void launch_random_gaussian(z64* v, size_t n, uint64_t seed, uint64_t stream_id, hipStream_t st) {
@@ -2116,15 +2152,15 @@ void launch_lincomb3(const z64* X, const z64* Y, const z64* Z, z64* out, double 
   template void launch_restrict<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, int, int, int, \
                                    int, hipStream_t);                                                            \
   template void launch_prolong<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, cpx<R>*, int, int, int, int, int, int,  \
-                                  int, int, int, int, hipStream_t, bool);                                        \
+                                  int, int, int, int, hipStream_t, bool, const Grp&);                            \
   template void launch_coarse<R>(const cpx<R>*, const cpx<R>*, cpx<R>*, int, int, int, int, int, double, cpx<R>*, \
-                                 const cpx<R>*, hipStream_t, double);                                            \
+                                 const cpx<R>*, hipStream_t, double, const Grp&);                                \
   template void launch_links_convert<R>(const z64*, cpx<R>*, size_t, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
-template void launch_dense_apply<double, double>(const z64*, const z64*, z64*, int, int, hipStream_t);
-template void launch_dense_apply<float, float>(const z32*, const z32*, z32*, int, int, hipStream_t);
-template void launch_dense_apply<double, float>(const z64*, const z32*, z32*, int, int, hipStream_t);
+template void launch_dense_apply<double, double>(const z64*, const z64*, z64*, int, int, hipStream_t, const Grp&);
+template void launch_dense_apply<float, float>(const z32*, const z32*, z32*, int, int, hipStream_t, const Grp&);
+template void launch_dense_apply<double, float>(const z64*, const z32*, z32*, int, int, hipStream_t, const Grp&);
 
 }  // namespace smg

@@ -176,10 +176,23 @@ struct KVecs {
   size_t cap = 0;                   // elements per vector
 };
 
+// Per-column operators of a grouped solve (smg_group_*), device arrays of G entries in
+// the order of the group's handles: FP32 fine links and diagonals, FP64 fine links and
+// diagonals (the defect correction's residual), coarse links and prolongators per
+// level of the FP32 V-cycle, the smoother coefficients per level as [nu][G], and the
+// coarsest inverse.
+struct GroupTab {
+  int G = 0;
+  Grp U32, U64, M;
+  std::vector<Grp> L, P;
+  std::vector<const double*> coef;
+};
+
 struct Ctx {
   smg_params prm{};
   int nlev = 0;
   int mfma_pin = -1;                // -1: by mfma_min_rhs; 0 / 1: vector ALU / matrix cores
+  const GroupTab* grp = nullptr;    // while a grouped solve runs on this context: its systems
   uint64_t gen = 0;                 // bumped whenever operators or coefficients change (captured graphs)
   rocblas_handle blas = nullptr;    // the calling thread's handle during a blocked coarsest inversion
   hipStream_t st = nullptr;
@@ -416,21 +429,45 @@ bool use_mfma(const Ctx& c, int nc, int nrhs) {
   return c.prm.mfma_min_rhs > 0 && nrhs >= c.prm.mfma_min_rhs;
 }
 
+// The operators of level lv in a grouped solve, with the smoother coefficients of
+// step `step` (and step + 1 for the fused last two steps, modes 4 and 5).
+template <typename R>
+Grp group_ops(const Ctx& c, const Level<R>& lv, int mode, int step) {
+  const GroupTab& t = *c.grp;
+  const int l = (int)(&lv - levels_of<R>(const_cast<Ctx&>(c)).data());
+  Grp g;
+  if constexpr (std::is_same<R, float>::value) {
+    g = lv.fine ? t.U32 : t.L[l];
+  } else {
+    if (!lv.fine) throw Error(SMG_EINVAL, "grouped solve: FP64 coarse levels are not grouped");
+    g = t.U64;
+  }
+  if (mode == 1 || mode == 3 || mode == 4 || mode == 5) {
+    if (step < 0 || (size_t)l >= t.coef.size()) throw Error(SMG_EINVAL, "grouped solve: smoother step not given");
+    g.c = t.coef[l] + (size_t)step * t.G;
+    if (mode == 4 || mode == 5) g.c2 = t.coef[l] + (size_t)(step + 1) * t.G;
+  }
+  return g;
+}
+
+// step: which smoother coefficient `coef` is (needed by grouped solves, whose systems
+// each have their own), or -1.
 template <typename R>
 void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mode, double coef, cpx<R>* xacc,
-              const cpx<R>* aux, double coef2 = 0) {
+              const cpx<R>* aux, double coef2 = 0, int step = -1) {
+  const Grp g = c.grp ? group_ops<R>(c, lv, mode, step) : Grp{};
   if (lv.fine) {
-    launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st, coef2);
+    launch_normal<R>(lv.U, x, y, lv.tmp, lv.lx, lv.lt, lv.diag, nrhs, mode, coef, xacc, aux, c.st, coef2, g);
     c.fine_applies += nrhs;
     return;
   }
   if constexpr (std::is_same<R, float>::value) {
-    if (use_mfma(c, lv.dof, nrhs)) {
+    if (!c.grp && use_mfma(c, lv.dof, nrhs)) {
       launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
       return;
     }
     if (lv.L16) {
-      launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
+      launch_coarse_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2, g);
       return;
     }
   } else {
@@ -439,12 +476,22 @@ void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mo
       return;
     }
   }
-  launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
+  launch_coarse<R>(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2, g);
 }
 
 template <typename R>
 void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
   if constexpr (std::is_same<R, float>::value) {
+    if (c.grp) {
+      const Grp& g = c.grp->P[&lv - c.L32.data()];
+      if (lv.P16)
+        launch_restrict_s<hfc, z32>(lv.P16, lv.pscale, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc,
+                                    lv.ldk, nrhs, c.st, g);
+      else
+        launch_restrict_s<z32, z32>(lv.P, 1.0f, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk,
+                                    nrhs, c.st, g);
+      return;
+    }
     if (lv.P16) {
       launch_restrict_s<hfc, z32>(lv.P16, lv.pscale, x, y, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk,
                                   nrhs, c.st);
@@ -462,6 +509,16 @@ void restrict_to(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs) {
 template <typename R>
 void prolong_from(Ctx& c, Level<R>& lv, const cpx<R>* e, cpx<R>* y, int nrhs, int mode) {
   if constexpr (std::is_same<R, float>::value) {
+    if (c.grp) {
+      const Grp& g = c.grp->P[&lv - c.L32.data()];
+      if (lv.P16)
+        launch_prolong_h16(lv.P16, lv.pscale, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc,
+                           lv.ldk, nrhs, mode, c.st, g);
+      else
+        launch_prolong<float>(lv.P, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk, nrhs,
+                              mode, c.st, false, g);
+      return;
+    }
     if (lv.P16) {
       launch_prolong_h16(lv.P16, lv.pscale, e, y, lv.wbuf, lv.lx, lv.lt, lv.dof, lv.bx, lv.bt, lv.halo, lv.nc, lv.ldk,
                          nrhs, mode, c.st);
@@ -489,7 +546,7 @@ void smooth(Ctx& c, Level<R>& lv, const cpx<R>* b, cpx<R>* x, int nrhs) {
     const bool last = k + 2 == nu;
     const int mode = last ? (k == 0 ? 5 : 4) : (k == 0 ? 3 : 1);
     cpx<R>* nxt = bufs[k & 1];
-    apply_op<R>(c, lv, cur, nxt, nrhs, mode, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0);
+    apply_op<R>(c, lv, cur, nxt, nrhs, mode, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0, k);
     cur = nxt;
   }
 }
@@ -503,12 +560,13 @@ void coarsest_solve(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, bool us
   auto& lv = levels_of<R>(c)[l];
   if (!use_cg && c.Minv && l == c.nlev - 1) {
     if constexpr (std::is_same<R, float>::value) {
+      const Grp g = c.grp ? c.grp->M : Grp{};
       if (c.prm.coarsest_fp64)  // FP64 inverse and FP64 sums, the FP32 input widened exactly
-        launch_dense_apply<double, float>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
+        launch_dense_apply<double, float>(c.Minv, b, x, (int)lv.n, nrhs, c.st, g);
       else if (c.Minv16)
-        launch_dense_apply_h16(c.Minv16, c.mscale, b, x, (int)lv.n, nrhs, c.st);
+        launch_dense_apply_h16(c.Minv16, c.mscale, b, x, (int)lv.n, nrhs, c.st, g);
       else
-        launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st);
+        launch_dense_apply<float, float>(c.Minv32, b, x, (int)lv.n, nrhs, c.st, g);
     }
     else
       launch_dense_apply<double, double>(c.Minv, b, x, (int)lv.n, nrhs, c.st);
@@ -547,7 +605,7 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
   cpx<R>* bufs[2] = {lv.r, lv.t};
   for (int k = 0; k < nu; ++k) {
     cpx<R>* nxt = bufs[k & 1];
-    apply_op<R>(c, lv, cur, nxt, nrhs, k == 0 ? 3 : 1, lv.coefs[k], x, nullptr);
+    apply_op<R>(c, lv, cur, nxt, nrhs, k == 0 ? 3 : 1, lv.coefs[k], x, nullptr, 0.0, k);
     cur = nxt;
   }
   // 2. r_c = P^H (b - A x)
@@ -568,13 +626,13 @@ void vcycle(Ctx& c, int l, int last, const cpx<R>* b, cpx<R>* x, int nrhs, bool 
     if constexpr (std::is_same<R, float>::value) {
       if (last && l == 0 && lv.fine && c.vend_partial) {
         launch_vcycle_end<float>(lv.U, cur, x, b, lv.lx, lv.lt, lv.diag, nrhs, lv.coefs[k], lv.coefs[k + 1],
-                                 c.vend_partial, c.st);
+                                 c.vend_partial, c.st, c.grp ? group_ops<float>(c, lv, 4, k) : Grp{});
         c.fine_applies += nrhs;
         c.vend_done = true;
         break;
       }
     }
-    apply_op<R>(c, lv, cur, nxt, nrhs, last ? 4 : 1, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0);
+    apply_op<R>(c, lv, cur, nxt, nrhs, last ? 4 : 1, lv.coefs[k], x, nullptr, last ? lv.coefs[k + 1] : 0.0, k);
     cur = nxt;
   }
   if (l == 0) c.vcycles += nrhs;
@@ -737,7 +795,7 @@ void pcg(Ctx& c, int l, const cpx<R>* b, cpx<R>* x, int nrhs, double tol, int ma
         BetaFold bf;
         if (folded) bf = BetaFold{c.rz_partial, fuse_nb, first ? nullptr : rz_cur, rz_nxt, S.active};
         launch_cg_step<float>(lv.U, v.z, p_cur, p_alt, v.q, lv.lx, lv.lt, lv.diag, nrhs, S.ab, c.cg_partial, c.st,
-                              bf);
+                              bf, c.grp ? group_ops<float>(c, lv, 0, -1) : Grp{});
         c.fine_applies += nrhs;
         std::swap(p_cur, p_alt);
         if (folded) std::swap(rz_cur, rz_nxt);
@@ -1836,6 +1894,182 @@ using namespace smg;
     return SMG_EINVAL;                            \
   }
 
+// FP64 defect correction around FP32 MG-CG (smg_solve with SMG_MIXED, and grouped
+// solves): rhs, x complex128 [nrhs][n] on the fine level; per-column results in cs.
+void solve_mixed(Ctx* c, const double* rhs, double* x, int nrhs, double tol, int maxiter, ColStats& cs,
+                 int& refinements) {
+  const bool mg = c->nlev > 1;
+  auto& lv = c->L64[0];
+  const size_t n = lv.n;
+  ensure_f32(*c);
+  const z64* b = (const z64*)rhs;
+  z64* xx = (z64*)x;
+  launch_dc_start(b, c->r64, xx, (size_t)nrhs * n, c->st);  // r = b, x = 0
+  std::vector<double> hbb(nrhs), rel(nrhs, 0.0), down(nrhs), up(nrhs);
+  std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
+  refinements = 0;
+  int used = 0;
+  std::vector<double> bb_inner(nrhs);
+  bool first = true;
+  while (true) {
+    launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st, c->sc[1].rr_host);
+    sync(*c);
+    if (first) {  // r = b: the first norms are |b|^2
+      first = false;
+      for (int j = 0; j < nrhs; ++j) {
+        hbb[j] = c->sc[1].rr_host[2 * j];
+        if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
+        if (!(hbb[j] > 0)) { act[j] = 0; stat[j] = SMG_OK; }
+      }
+    }
+    int nact = 0;
+    for (int j = 0; j < nrhs; ++j) {
+      if (!act[j]) { down[j] = 0; up[j] = 0; continue; }
+      const double rr = c->sc[1].rr_host[2 * j];
+      if (!std::isfinite(rr)) throw Error(SMG_EBREAKDOWN, "defect correction residual is NaN/Inf");
+      rel[j] = std::sqrt(rr / hbb[j]);
+      if (rel[j] <= tol) { act[j] = 0; stat[j] = SMG_OK; down[j] = 0; up[j] = 0; continue; }
+      down[j] = 1.0 / std::sqrt(rr);
+      up[j] = std::sqrt(rr);
+      ++nact;
+    }
+    if (refinements > 0) {  // true relative residual after this many passes (largest column)
+      double worst = 0;
+      for (int j = 0; j < nrhs; ++j) worst = std::max(worst, rel[j]);
+      report("refinement", 0, refinements, maxiter, worst);
+    }
+    if (nact == 0 || used >= maxiter) break;
+    // the same scales on the device, from the same |r|^2 and this decision (no copy)
+    for (int j = 0; j < nrhs; ++j) c->sc[1].on_host[j] = down[j] != 0 ? 1 : 0;
+    launch_dc_scales(c->sc[1].rr, c->sc[1].on_host, c->dc_down, c->dc_up, nrhs, c->st);
+    launch_scale_down_start(c->r64, c->b32, c->f32.r, c->e32, c->dc_down, n, nrhs, c->st);
+    ColStats inner;
+    // The inner solve's own convergence test uses inner_tol; its limit is what is
+    // left of maxiter.  Its right-hand side has unit norm in every running column.
+    for (int j = 0; j < nrhs; ++j) bb_inner[j] = down[j] != 0 ? 1.0 : 0.0;
+    pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0,
+               false, bb_inner.data(), true);
+    int maxit = 0;
+    for (int j = 0; j < nrhs; ++j) {
+      if (down[j] != 0) its[j] += inner.iters[j];
+      maxit = std::max(maxit, inner.iters[j]);
+    }
+    used += std::max(maxit, 1);
+    launch_scale_up_add(xx, c->e32, c->dc_up, n, nrhs, c->st);
+    apply_op<double>(*c, lv, xx, c->r64, nrhs, 2, 0.0, nullptr, b);
+    ++refinements;
+  }
+  cs.iters = its;
+  cs.status = stat;
+  cs.relres = rel;
+}
+
+// A grouped solve: independent systems of one shape (lattice, levels, vectors per
+// level, storage) solved together, system j in column j of every launch of the mixed
+// solve, so each launch does the work of all of them.  The first handle's context
+// runs the solve (its work vectors for G columns, its stream); the per-column
+// operator tables point into every handle's own arrays.
+struct Group {
+  std::vector<Ctx*> cs;
+  std::vector<uint64_t> gens;  // each handle's operator generation when the tables were filled
+  Pool pool;                   // the tables
+  GroupTab tab;
+  // host copies of the tables, uploaded after each fill
+  std::vector<const void*> h_ptr;
+  std::vector<double> h_val;
+  const void** d_ptr = nullptr;
+  double* d_val = nullptr;
+};
+
+Group* GH(smg_group g) {
+  if (!g) throw Error(SMG_EINVAL, "null group");
+  return reinterpret_cast<Group*>(g);
+}
+
+// The shape and storage a grouped solve needs every system to share.
+void group_check(const Ctx& a, const Ctx& b) {
+  const smg_params &p = a.prm, &q = b.prm;
+  bool same = p.lx == q.lx && p.lt == q.lt && a.nlev == b.nlev && p.smoother_steps == q.smoother_steps &&
+              p.operator_storage == q.operator_storage && p.smoother_storage == q.smoother_storage &&
+              p.coarsest == q.coarsest && p.coarsest_fp64 == q.coarsest_fp64 && p.split_chirality == q.split_chirality;
+  for (int l = 0; same && l < a.nlev; ++l) {
+    const auto &x = a.L32[l], &y = b.L32[l];
+    same = x.lx == y.lx && x.lt == y.lt && x.dof == y.dof && x.nc == y.nc && x.ldk == y.ldk && x.halo == y.halo &&
+           x.bx == y.bx && x.bt == y.bt && x.coefs.size() == y.coefs.size() && (x.L16 == nullptr) == (y.L16 == nullptr) &&
+           (x.P16 == nullptr) == (y.P16 == nullptr);
+  }
+  if (!same) throw Error(SMG_EINVAL, "grouped systems differ in shape, levels, vectors per level or storage");
+}
+
+// Fill the per-column tables from every handle's current operators (FP32 copies
+// brought up to date first).
+void group_fill(Group& g, hipStream_t st) {
+  const int G = (int)g.cs.size();
+  for (Ctx* c : g.cs) {
+    c->st = st;
+    ensure_f32(*c);
+  }
+  Ctx& c0 = *g.cs[0];
+  const int nl = c0.nlev;
+  for (Ctx* c : g.cs) group_check(c0, *c);
+  // layout of the pointer table: U32, U64, M, then L per level, then P per level (G each);
+  // of the value table: diag32, diag64, mscale, lscale per level, pscale per level, then
+  // the coefficients of every level ([nu][G])
+  const int nptr = 3 + 2 * nl, nu = (int)c0.L32[0].coefs.size();
+  const int nval = 3 + 2 * nl + nl * nu;
+  g.h_ptr.assign((size_t)nptr * G, nullptr);
+  g.h_val.assign((size_t)nval * G, 0.0);
+  auto P = [&](int slot, int j) -> const void*& { return g.h_ptr[(size_t)slot * G + j]; };
+  auto V = [&](int slot, int j) -> double& { return g.h_val[(size_t)slot * G + j]; };
+  for (int j = 0; j < G; ++j) {
+    Ctx& c = *g.cs[j];
+    P(0, j) = c.L32[0].U;
+    V(0, j) = c.L32[0].diag;
+    P(1, j) = c.L64[0].U;
+    V(1, j) = c.L64[0].diag;
+    const bool m16 = !c.prm.coarsest_fp64 && c.Minv16;
+    P(2, j) = c.prm.coarsest_fp64 ? (const void*)c.Minv : (m16 ? (const void*)c.Minv16 : (const void*)c.Minv32);
+    V(2, j) = m16 ? c.mscale : 1.0;
+    for (int l = 0; l < nl; ++l) {
+      const auto& lv = c.L32[l];
+      P(3 + l, j) = lv.L16 ? (const void*)lv.L16 : (const void*)lv.L;
+      V(3 + l, j) = lv.L16 ? lv.lscale : 1.0;
+      P(3 + nl + l, j) = lv.P16 ? (const void*)lv.P16 : (const void*)lv.P;
+      V(3 + nl + l, j) = lv.P16 ? lv.pscale : 1.0;
+      for (int k = 0; k < (int)lv.coefs.size(); ++k) V(3 + 2 * nl + l * nu + k, j) = lv.coefs[k];
+    }
+  }
+  if (!g.d_ptr) {
+    g.pool.stream = &c0.st;
+    g.d_ptr = reinterpret_cast<const void**>(g.pool.alloc<uint64_t>((size_t)nptr * G));
+    g.d_val = g.pool.alloc<double>((size_t)nval * G);
+  }
+  HIPCHECK(hipMemcpyAsync(g.d_ptr, g.h_ptr.data(), g.h_ptr.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(g.d_val, g.h_val.data(), g.h_val.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));  // the host copies may change at the next fill
+  auto grp = [&](int pslot, int vslot) {
+    Grp r;
+    r.op = g.d_ptr + (size_t)pslot * G;
+    r.s = g.d_val + (size_t)vslot * G;
+    return r;
+  };
+  GroupTab& t = g.tab;
+  t.G = G;
+  t.U32 = grp(0, 0);
+  t.U64 = grp(1, 1);
+  t.M = grp(2, 2);
+  t.L.assign(nl, Grp{});
+  t.P.assign(nl, Grp{});
+  t.coef.assign(nl, nullptr);
+  for (int l = 0; l < nl; ++l) {
+    t.L[l] = grp(3 + l, 3 + l);
+    t.P[l] = grp(3 + nl + l, 3 + nl + l);
+    t.coef[l] = g.d_val + (size_t)(3 + 2 * nl + l * nu) * G;
+  }
+  g.gens.resize(G);
+  for (int j = 0; j < G; ++j) g.gens[j] = g.cs[j]->gen;
+}
+
 extern "C" {
 
 void smg_default_params(smg_params* p) {
@@ -2199,68 +2433,7 @@ int smg_solve(smg_handle h, const double* rhs, double* x, int32_t nrhs, double t
     pcg<double>(*c, 0, (const z64*)rhs, (z64*)x, nrhs, tol, maxiter, mg, c->f64, &cs, 1, 0,
                 c->prm.stop_recursive == 0);
   } else {
-    // FP64 defect correction around FP32 MG-CG.
-    ensure_f32(*c);
-    const z64* b = (const z64*)rhs;
-    z64* xx = (z64*)x;
-    launch_dc_start(b, c->r64, xx, (size_t)nrhs * n, c->st);  // r = b, x = 0
-    std::vector<double> hbb(nrhs), rel(nrhs, 0.0), down(nrhs), up(nrhs);
-    std::vector<int> act(nrhs, 1), its(nrhs, 0), stat(nrhs, SMG_NOTCONV);
-    refinements = 0;
-    int used = 0;
-    std::vector<double> bb_inner(nrhs);
-    bool first = true;
-    while (true) {
-      launch_dot<double>(c->r64, c->r64, n, nrhs, c->red, c->sc[1].rr, c->st, c->sc[1].rr_host);
-      sync(*c);
-      if (first) {  // r = b: the first norms are |b|^2
-        first = false;
-        for (int j = 0; j < nrhs; ++j) {
-          hbb[j] = c->sc[1].rr_host[2 * j];
-          if (!std::isfinite(hbb[j])) throw Error(SMG_EBREAKDOWN, "right-hand side contains NaN/Inf");
-          if (!(hbb[j] > 0)) { act[j] = 0; stat[j] = SMG_OK; }
-        }
-      }
-      int nact = 0;
-      for (int j = 0; j < nrhs; ++j) {
-        if (!act[j]) { down[j] = 0; up[j] = 0; continue; }
-        const double rr = c->sc[1].rr_host[2 * j];
-        if (!std::isfinite(rr)) throw Error(SMG_EBREAKDOWN, "defect correction residual is NaN/Inf");
-        rel[j] = std::sqrt(rr / hbb[j]);
-        if (rel[j] <= tol) { act[j] = 0; stat[j] = SMG_OK; down[j] = 0; up[j] = 0; continue; }
-        down[j] = 1.0 / std::sqrt(rr);
-        up[j] = std::sqrt(rr);
-        ++nact;
-      }
-      if (refinements > 0) {  // true relative residual after this many passes (largest column)
-        double worst = 0;
-        for (int j = 0; j < nrhs; ++j) worst = std::max(worst, rel[j]);
-        report("refinement", 0, refinements, maxiter, worst);
-      }
-      if (nact == 0 || used >= maxiter) break;
-      // the same scales on the device, from the same |r|^2 and this decision (no copy)
-      for (int j = 0; j < nrhs; ++j) c->sc[1].on_host[j] = down[j] != 0 ? 1 : 0;
-      launch_dc_scales(c->sc[1].rr, c->sc[1].on_host, c->dc_down, c->dc_up, nrhs, c->st);
-      launch_scale_down_start(c->r64, c->b32, c->f32.r, c->e32, c->dc_down, n, nrhs, c->st);
-      ColStats inner;
-      // The inner solve's own convergence test uses inner_tol; its limit is what is
-      // left of maxiter.  Its right-hand side has unit norm in every running column.
-      for (int j = 0; j < nrhs; ++j) bb_inner[j] = down[j] != 0 ? 1.0 : 0.0;
-      pcg<float>(*c, 0, c->b32, c->e32, nrhs, c->prm.inner_tol, std::max(1, maxiter - used), mg, c->f32, &inner, 1, 0,
-                 false, bb_inner.data(), true);
-      int maxit = 0;
-      for (int j = 0; j < nrhs; ++j) {
-        if (down[j] != 0) its[j] += inner.iters[j];
-        maxit = std::max(maxit, inner.iters[j]);
-      }
-      used += std::max(maxit, 1);
-      launch_scale_up_add(xx, c->e32, c->dc_up, n, nrhs, c->st);
-      apply_op<double>(*c, lv, xx, c->r64, nrhs, 2, 0.0, nullptr, b);
-      ++refinements;
-    }
-    cs.iters = its;
-    cs.status = stat;
-    cs.relres = rel;
+    solve_mixed(c, rhs, x, nrhs, tol, maxiter, cs, refinements);
   }
   sync(*c);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2434,6 +2607,64 @@ int smg_memory_bytes(smg_handle h, size_t* bytes) {
   *bytes = c->pool.bytes;
   return SMG_OK;
   API_END
+}
+
+int smg_group_create(const smg_handle* hs, int32_t nsys, void* stream, smg_group* out) {
+  API_BEGIN
+  if (!hs || !out) throw Error(SMG_EINVAL, "null handles or output");
+  if (nsys < 1 || nsys > 4096) throw Error(SMG_EINVAL, "nsys must be in [1, 4096]");
+  std::unique_ptr<Group> g(new Group());
+  for (int j = 0; j < nsys; ++j) g->cs.push_back(H(hs[j]));
+  const Ctx& c0 = *g->cs[0];
+  if (c0.nlev < 2) throw Error(SMG_EINVAL, "a grouped solve needs levels >= 2");
+  if (c0.prm.coarsest != SMG_COARSEST_DIRECT) throw Error(SMG_EINVAL, "a grouped solve needs the dense coarsest inverse");
+  if (c0.prm.smoother_storage != SMG_STORE_F32) throw Error(SMG_EINVAL, "a grouped solve needs smoother_storage F32");
+  if (c0.prm.smoother_steps < 2) throw Error(SMG_EINVAL, "a grouped solve needs smoother_steps >= 2");
+  if (c0.L64[c0.nlev - 1].n > 4096) throw Error(SMG_EINVAL, "a grouped solve needs a coarsest level of <= 4096 variables");
+  for (int l = 1; l + 1 < c0.nlev; ++l)
+    if (c0.L64[l].dof < 4 || c0.L64[l].dof > 16) throw Error(SMG_EINVAL, "a grouped solve needs 4 <= nc <= 16");
+  group_fill(*g, (hipStream_t)stream);
+  *out = reinterpret_cast<smg_group>(g.release());
+  return SMG_OK;
+  API_END
+}
+
+int smg_group_solve(smg_group gh, const double* rhs, double* x, double tol, int32_t maxiter, void* stream,
+                    smg_stats* stats) {
+  API_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
+  Group& g = *GH(gh);
+  if (!rhs || !x) throw Error(SMG_EINVAL, "null vector");
+  if (!(tol > 0) || maxiter < 1) throw Error(SMG_EINVAL, "tol must be > 0 and maxiter >= 1");
+  const int G = (int)g.cs.size();
+  hipStream_t st = (hipStream_t)stream;
+  bool stale = false;
+  for (int j = 0; j < G; ++j) stale = stale || g.cs[j]->gen != g.gens[j] || !g.cs[j]->f32_ready;
+  if (stale) group_fill(g, st);
+  Ctx* c = g.cs[0];
+  c->st = st;
+  const int64_t fa0 = c->fine_applies, vc0 = c->vcycles;
+  reserve_solve(*c, G, SMG_MIXED);
+  struct Bind {  // the context runs ungrouped again on every exit path
+    Ctx* c;
+    ~Bind() { c->grp = nullptr; }
+  } bind{c};
+  c->grp = &g.tab;
+  ColStats cs;
+  int refinements = 0;
+  solve_mixed(c, rhs, x, G, tol, maxiter, cs, refinements);
+  sync(*c);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(stats, G, cs, refinements, c->fine_applies - fa0, c->vcycles - vc0, secs);
+  for (int j = 0; j < G; ++j)
+    if (cs.status[j] != SMG_OK) return SMG_NOTCONV;
+  return SMG_OK;
+  API_END
+}
+
+void smg_group_destroy(smg_group g) {
+  if (!g) return;
+  delete reinterpret_cast<Group*>(g);
 }
 
 int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter, int32_t precision, void* stream,

@@ -183,7 +183,8 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
                                                            const cpx<R>* __restrict__ aux,
                                                            const double* __restrict__ beta = nullptr,
                                                            double* __restrict__ partial = nullptr,
-                                                           BetaFold bf = BetaFold{}, int nrhs = 0) {
+                                                           BetaFold bf = BetaFold{}, int nrhs = 0,
+                                                           Grp g = Grp{}) {
   constexpr int HX = TX + 2, HT = TT + 2;
   constexpr int RG = kThreads / TX;          // row groups
   constexpr int PER = TX * TT / kThreads;    // sites per thread
@@ -198,6 +199,13 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
   static_assert(NRB == 1 || MODE <= 5, "several right-hand sides per workgroup: epilogues 0-5 only");
   const int nr = nrhs > 0 ? nrhs : (int)gridDim.y * NRB;
+  if (g.op) {  // grouped (NRB = 1): this column's system
+    const int col = blockIdx.y;
+    U = static_cast<const cpx<R>*>(g.op[col]);
+    diag = (R)g.s[col];
+    if (g.c) c = (R)g.c[col];
+    if (g.c2) c2 = (R)g.c2[col];
+  }
   constexpr int NRING = 2 * TX + 2 * TT;
   static_assert(NRING <= kThreads, "one ring site per thread");
 
@@ -525,11 +533,14 @@ constexpr long kFusedNRBSites = 1L << 20;
 
 template <typename R, int TX, int TT, bool NT>
 void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, double diag, int nrhs, int mode,
-                  double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st) {
+                  double c, double c2, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, const Grp& g) {
   const int tiles = (lx / TX) * (lt / TT);
   with_mode(mode, [&](auto m) {
     constexpr int M = decltype(m)::v;
-    if (nrhs >= kFusedNRB && (long)lx * lt >= kFusedNRBSites) {
+    if (g.op) {
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT>), dim3(tiles, nrhs), dim3(kThreads), 0, st, U, x, y, lx,
+                         lt, (R)diag, (R)c, (R)c2, xacc, aux, nullptr, nullptr, BetaFold{}, 0, g);
+    } else if (nrhs >= kFusedNRB && (long)lx * lt >= kFusedNRBSites) {
       dim3 grid(tiles, (nrhs + kFusedNRB - 1) / kFusedNRB);
       hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT, cpx<R>, cpx<R>, kFusedNRB>), grid, dim3(kThreads), 0, st,
                          U, x, y, lx, lt, (R)diag, (R)c, (R)c2, xacc, aux, nullptr, nullptr, BetaFold{}, nrhs);
@@ -544,10 +555,10 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
 template <typename R, int TX, int TT, bool NT>
 void launch_cg_step_t(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
                       double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
-                      const BetaFold& bf) {
+                      const BetaFold& bf, const Grp& g) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
   hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT>), grid, dim3(kThreads), 0, st, U, z, q, lx, lt, (R)diag,
-                     (R)0, (R)0, p, p_old, beta, partial, bf);
+                     (R)0, (R)0, p, p_old, beta, partial, bf, 0, g);
   HIPCHECK(hipGetLastError());
 }
 
@@ -587,15 +598,17 @@ int fused_shape(int lx, int lt) {
 
 template <typename R>
 void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int lx, int lt, double diag,
-                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2) {
+                   int nrhs, int mode, double c, cpx<R>* xacc, const cpx<R>* aux, hipStream_t st, double c2,
+                   const Grp& g) {
   switch (fused_shape<R>(lx, lt)) {
-    case kT64x4: launch_fused<R, 64, 4, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
-    case kT64x8nt: launch_fused<R, 64, 8, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
-    case kT32x16nt: launch_fused<R, 32, 16, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
-    case kT32x8: launch_fused<R, 32, 8, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
-    case kT16x16: launch_fused<R, 16, 16, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st); return;
+    case kT64x4: launch_fused<R, 64, 4, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st, g); return;
+    case kT64x8nt: launch_fused<R, 64, 8, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st, g); return;
+    case kT32x16nt: launch_fused<R, 32, 16, true>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st, g); return;
+    case kT32x8: launch_fused<R, 32, 8, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st, g); return;
+    case kT16x16: launch_fused<R, 16, 16, false>(U, x, y, lx, lt, diag, nrhs, mode, c, c2, xacc, aux, st, g); return;
     default: break;
   }
+  if (g.op) throw Error(-1, "grouped fine operator needs a fused tile shape");
   launch_wilson<R>(U, x, tmp, lx, lt, diag, nrhs, false, st);
   const int V = lx * lt;
   dim3 grid((V + kThreads - 1) / kThreads, nrhs);
@@ -608,27 +621,28 @@ void launch_normal(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, cpx<R>* tmp, int
 
 template <typename R, int TX, int TT, bool NT>
 void launch_vcycle_end_t(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
-                         int nrhs, double c, double c2, double* partial, hipStream_t st) {
+                         int nrhs, double c, double c2, double* partial, hipStream_t st, const Grp& g) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
-  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT>), grid, dim3(kThreads), 0, st, U, v, static_cast<cpx<R>*>(nullptr),
-                     lx, lt, (R)diag, (R)c, (R)c2, z, r, static_cast<const double*>(nullptr), partial);
+  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT>), grid, dim3(kThreads), 0, st, U, v,
+                     static_cast<cpx<R>*>(nullptr), lx, lt, (R)diag, (R)c, (R)c2, z, r,
+                     static_cast<const double*>(nullptr), partial, BetaFold{}, 0, g);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename R>
 void launch_vcycle_end(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
-                       int nrhs, double c, double c2, double* partial, hipStream_t st) {
+                       int nrhs, double c, double c2, double* partial, hipStream_t st, const Grp& g) {
   switch (fused_shape<R>(lx, lt)) {
-    case kT64x4: launch_vcycle_end_t<R, 64, 4, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
-    case kT64x8nt: launch_vcycle_end_t<R, 64, 8, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
-    case kT32x16nt: launch_vcycle_end_t<R, 32, 16, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
-    case kT32x8: launch_vcycle_end_t<R, 32, 8, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
-    case kT16x16: launch_vcycle_end_t<R, 16, 16, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st); return;
+    case kT64x4: launch_vcycle_end_t<R, 64, 4, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st, g); return;
+    case kT64x8nt: launch_vcycle_end_t<R, 64, 8, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st, g); return;
+    case kT32x16nt: launch_vcycle_end_t<R, 32, 16, true>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st, g); return;
+    case kT32x8: launch_vcycle_end_t<R, 32, 8, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st, g); return;
+    case kT16x16: launch_vcycle_end_t<R, 16, 16, false>(U, v, z, r, lx, lt, diag, nrhs, c, c2, partial, st, g); return;
     default: throw Error(-1, "V-cycle end kernel needs a fused tile shape");
   }
 }
 template void launch_vcycle_end<float>(const z32*, const z32*, z32*, const z32*, int, int, double, int, double, double,
-                                       double*, hipStream_t);
+                                       double*, hipStream_t, const Grp&);
 
 template <typename R>
 int cg_step_blocks(int lx, int lt) {
@@ -645,29 +659,29 @@ int cg_step_blocks(int lx, int lt) {
 template <typename R>
 void launch_cg_step(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx<R>* p, cpx<R>* q, int lx, int lt,
                     double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
-                    const BetaFold& bf) {
+                    const BetaFold& bf, const Grp& g) {
   switch (fused_shape<R>(lx, lt)) {
     case kT64x4:
-      launch_cg_step_t<R, 64, 4, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      launch_cg_step_t<R, 64, 4, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf, g);
       return;
     case kT64x8nt:
-      launch_cg_step_t<R, 64, 8, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      launch_cg_step_t<R, 64, 8, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf, g);
       return;
     case kT32x16nt:
-      launch_cg_step_t<R, 32, 16, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      launch_cg_step_t<R, 32, 16, true>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf, g);
       return;
     case kT32x8:
-      launch_cg_step_t<R, 32, 8, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      launch_cg_step_t<R, 32, 8, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf, g);
       return;
     case kT16x16:
-      launch_cg_step_t<R, 16, 16, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf);
+      launch_cg_step_t<R, 16, 16, false>(U, z, p_old, p, q, lx, lt, diag, nrhs, beta, partial, st, bf, g);
       return;
     default: throw Error(-1, "CG step kernel needs a fused tile shape");
   }
 }
 template int cg_step_blocks<float>(int, int);
 template void launch_cg_step<float>(const z32*, const z32*, const z32*, z32*, z32*, int, int, double, int,
-                                    const double*, double*, hipStream_t, const BetaFold&);
+                                    const double*, double*, hipStream_t, const BetaFold&, const Grp&);
 
 template <int TX, int TT, typename TI, typename TO>
 void launch_fused_lp(const z32* U, const TI* x, TO* y, int lx, int lt, double diag, int nrhs, int mode, double c,
@@ -709,9 +723,9 @@ void launch_prepare_links(const z64* gauge, cpx<R>* U, int lx, int lt, int antip
 template void launch_wilson<double>(const z64*, const z64*, z64*, int, int, double, int, bool, hipStream_t);
 template void launch_wilson<float>(const z32*, const z32*, z32*, int, int, double, int, bool, hipStream_t);
 template void launch_normal<double>(const z64*, const z64*, z64*, z64*, int, int, double, int, int, double, z64*,
-                                    const z64*, hipStream_t, double);
+                                    const z64*, hipStream_t, double, const Grp&);
 template void launch_normal<float>(const z32*, const z32*, z32*, z32*, int, int, double, int, int, double, z32*,
-                                   const z32*, hipStream_t, double);
+                                   const z32*, hipStream_t, double, const Grp&);
 template void launch_prepare_links<double>(const z64*, z64*, int, int, int, hipStream_t);
 template void launch_prepare_links<float>(const z64*, z32*, int, int, int, hipStream_t);
 
