@@ -770,7 +770,7 @@ def kernel_source_digest():
 
     text = open(KERNEL_SOURCE).read()
     parts = []
-    for start in ("template <typename R, int MODE, int Q, typename TL>\n"
+    for start in ("template <typename R, int MODE, int Q, typename TL, bool GRP = false>\n"
                   "__global__ void __launch_bounds__(kThreads) k_coarse_sv(",
                   "void launch_coarse_t(", "void launch_coarse_h16("):
         i = text.index(start)
@@ -1132,9 +1132,6 @@ def main():
                 f"bitwise equal to the single solves: {grouped['equal_to_single']})")
     results["fp64"] = timed(systems, smg.FP64)
     log(f"fp64: {results['fp64']['solves'] / results['fp64']['seconds']:.1f} solves/s")
-    if cpu_proc is not None:  # the headline rates are taken: the oracle may use the host now
-        cpu_proc.stdin.write("go\n")
-        cpu_proc.stdin.flush()
     for name, _opst, _c64 in VARIANTS[1:]:
         for s_ in variant_systems[name][1]:
             s_.close()
@@ -1236,7 +1233,11 @@ def main():
     mrhs = None if args.no_mrhs else mrhs_leg(args, torch, smg, dev, mrhs_U)
 
     cpu = None
-    if cpu_proc is not None:  # waits for the oracle before the serving leg loads the host
+    if cpu_proc is not None:
+        # every GPU leg that times host-driven solves is done: the oracle may use the host
+        # now, and the serving leg waits for it
+        cpu_proc.stdin.write("go\n")
+        cpu_proc.stdin.flush()
         out, err = cpu_proc.communicate(timeout=1800)  # also closes its stdin
         if cpu_proc.returncode == 0:
             leg = json.loads(out.strip().splitlines()[-1])

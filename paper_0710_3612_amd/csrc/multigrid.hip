@@ -557,14 +557,14 @@ __global__ void __launch_bounds__(kThreads) k_coarse(const TL* __restrict__ L, c
 // order and the reduction over the waves are those of k_coarse.
 constexpr int kCoarseSvMax = 9 * (64 + 2 * 16);  // 9 (64 / nc + 2) nc entries at most (4 <= nc <= 16)
 
-template <typename R, int MODE, int Q, typename TL>
+template <typename R, int MODE, int Q, typename TL, bool GRP = false>
 __global__ void __launch_bounds__(kThreads) k_coarse_sv(const TL* __restrict__ L, const cpx<R>* __restrict__ v,
                                                         cpx<R>* __restrict__ y, int cx, int ct, int nc, R c, R c2,
                                                         cpx<R>* __restrict__ xacc, const cpx<R>* __restrict__ aux,
                                                         R lscale, Grp g) {
   __shared__ cpx<R> part[3][64];
   __shared__ cpx<R> sv[kCoarseSvMax];
-  if (g.op) {  // grouped: this column's system
+  if constexpr (GRP) {  // grouped: this column's system
     L = static_cast<const TL*>(g.op[blockIdx.y]);
     lscale = (R)g.s[blockIdx.y];
     if (g.c) c = (R)g.c[blockIdx.y];
@@ -1681,18 +1681,18 @@ void launch_coarse_t(const TL* L, R lscale, const cpx<R>* x, cpx<R>* y, int cx, 
       const int q = (nc + 3) / 4;
       with_mode(mode, [&](auto m) {
         constexpr int M = decltype(m)::v;
-        if (q == 1)
-          hipLaunchKernelGGL((k_coarse_sv<R, M, 1, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale, g);
-        else if (q == 2)
-          hipLaunchKernelGGL((k_coarse_sv<R, M, 2, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale, g);
-        else if (q == 3)
-          hipLaunchKernelGGL((k_coarse_sv<R, M, 3, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale, g);
-        else
-          hipLaunchKernelGGL((k_coarse_sv<R, M, 4, TL>), grid, dim3(kThreads), 0, st, L, x, y, cx, ct, nc, (R)c, (R)c2,
-                             xacc, aux, lscale, g);
+        auto go = [&](auto qq, auto gg) {  // the grouped variant is its own instantiation
+          hipLaunchKernelGGL((k_coarse_sv<R, M, decltype(qq)::v, TL, decltype(gg)::v == 1>), grid, dim3(kThreads), 0,
+                             st, L, x, y, cx, ct, nc, (R)c, (R)c2, xacc, aux, lscale, g);
+        };
+        auto by_g = [&](auto qq) {
+          if (g.op) go(qq, IntC<1>{});
+          else go(qq, IntC<0>{});
+        };
+        if (q == 1) by_g(IntC<1>{});
+        else if (q == 2) by_g(IntC<2>{});
+        else if (q == 3) by_g(IntC<3>{});
+        else by_g(IntC<4>{});
       });
       HIPCHECK(hipGetLastError());
       return;

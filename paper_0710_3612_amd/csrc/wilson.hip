@@ -176,7 +176,8 @@ __device__ inline int fused_tile(int b, int nb) {
 // MODE 7 ends a V-cycle: the last two smoother steps of MODE 4 (xacc becomes the
 // V-cycle's output z) and the workgroup's share of <r, z> with r = aux, the V-cycle's
 // input, into partial[rhs][block].
-template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>, int NRB = 1>
+template <typename R, int TX, int TT, int MODE, bool NT, typename TI = cpx<R>, typename TO = cpx<R>, int NRB = 1,
+          bool GRP = false>
 __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restrict__ U, const TI* __restrict__ x,
                                                            TO* __restrict__ y, int lx, int lt, R diag, R c, R c2,
                                                            cpx<R>* __restrict__ xacc,
@@ -199,7 +200,8 @@ __global__ void __launch_bounds__(kThreads) k_normal_fused(const cpx<R>* __restr
   const int x0 = (tile % ntx) * TX, t0 = (tile / ntx) * TT;
   static_assert(NRB == 1 || MODE <= 5, "several right-hand sides per workgroup: epilogues 0-5 only");
   const int nr = nrhs > 0 ? nrhs : (int)gridDim.y * NRB;
-  if (g.op) {  // grouped (NRB = 1): this column's system
+  static_assert(!GRP || NRB == 1, "grouped launches take one right-hand side per workgroup");
+  if constexpr (GRP) {  // grouped: this column's system
     const int col = blockIdx.y;
     U = static_cast<const cpx<R>*>(g.op[col]);
     diag = (R)g.s[col];
@@ -538,8 +540,9 @@ void launch_fused(const cpx<R>* U, const cpx<R>* x, cpx<R>* y, int lx, int lt, d
   with_mode(mode, [&](auto m) {
     constexpr int M = decltype(m)::v;
     if (g.op) {
-      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT>), dim3(tiles, nrhs), dim3(kThreads), 0, st, U, x, y, lx,
-                         lt, (R)diag, (R)c, (R)c2, xacc, aux, nullptr, nullptr, BetaFold{}, 0, g);
+      hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT, cpx<R>, cpx<R>, 1, true>), dim3(tiles, nrhs),
+                         dim3(kThreads), 0, st, U, x, y, lx, lt, (R)diag, (R)c, (R)c2, xacc, aux, nullptr, nullptr,
+                         BetaFold{}, 0, g);
     } else if (nrhs >= kFusedNRB && (long)lx * lt >= kFusedNRBSites) {
       dim3 grid(tiles, (nrhs + kFusedNRB - 1) / kFusedNRB);
       hipLaunchKernelGGL((k_normal_fused<R, TX, TT, M, NT, cpx<R>, cpx<R>, kFusedNRB>), grid, dim3(kThreads), 0, st,
@@ -557,8 +560,12 @@ void launch_cg_step_t(const cpx<R>* U, const cpx<R>* z, const cpx<R>* p_old, cpx
                       double diag, int nrhs, const double* beta, double* partial, hipStream_t st,
                       const BetaFold& bf, const Grp& g) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
-  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT>), grid, dim3(kThreads), 0, st, U, z, q, lx, lt, (R)diag,
-                     (R)0, (R)0, p, p_old, beta, partial, bf, 0, g);
+  if (g.op)
+    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT, cpx<R>, cpx<R>, 1, true>), grid, dim3(kThreads), 0, st, U, z,
+                       q, lx, lt, (R)diag, (R)0, (R)0, p, p_old, beta, partial, bf, 0, g);
+  else
+    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 6, NT>), grid, dim3(kThreads), 0, st, U, z, q, lx, lt, (R)diag,
+                       (R)0, (R)0, p, p_old, beta, partial, bf, 0, g);
   HIPCHECK(hipGetLastError());
 }
 
@@ -623,9 +630,14 @@ template <typename R, int TX, int TT, bool NT>
 void launch_vcycle_end_t(const cpx<R>* U, const cpx<R>* v, cpx<R>* z, const cpx<R>* r, int lx, int lt, double diag,
                          int nrhs, double c, double c2, double* partial, hipStream_t st, const Grp& g) {
   dim3 grid((lx / TX) * (lt / TT), nrhs);
-  hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT>), grid, dim3(kThreads), 0, st, U, v,
-                     static_cast<cpx<R>*>(nullptr), lx, lt, (R)diag, (R)c, (R)c2, z, r,
-                     static_cast<const double*>(nullptr), partial, BetaFold{}, 0, g);
+  if (g.op)
+    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT, cpx<R>, cpx<R>, 1, true>), grid, dim3(kThreads), 0, st, U, v,
+                       static_cast<cpx<R>*>(nullptr), lx, lt, (R)diag, (R)c, (R)c2, z, r,
+                       static_cast<const double*>(nullptr), partial, BetaFold{}, 0, g);
+  else
+    hipLaunchKernelGGL((k_normal_fused<R, TX, TT, 7, NT>), grid, dim3(kThreads), 0, st, U, v,
+                       static_cast<cpx<R>*>(nullptr), lx, lt, (R)diag, (R)c, (R)c2, z, r,
+                       static_cast<const double*>(nullptr), partial, BetaFold{}, 0, g);
   HIPCHECK(hipGetLastError());
 }
 
