@@ -44,6 +44,8 @@ SETUP_ITERS = 5
 SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
+GROUPS = 4               # the 20 systems of the precision workload solve as 4 grouped solves ...
+GROUP_SIZE = 5           # ... of 5 systems each (every launch of a grouped solve serves its 5 systems)
 
 # Serving workload: Poisson streams of requests over 8 seeded fields per (lattice size,
 # beta), sizes 64..512^2, beta 3, 6, 10 (500 sweeps, beta 10: 1000), masses
@@ -501,8 +503,9 @@ def grouped_leg(args, torch, smg, syss, xs_single, streams):
     for f in [pool.submit(run, k, recs) for k in range(ng)]:
         f.result()
     torch.cuda.synchronize()
-    equal = all(torch.equal(outs[k][i], xs_single[j].reshape(-1)) for k, part in enumerate(parts)
-                for i, j in enumerate(part))
+    equal = None if xs_single is None else all(torch.equal(outs[k][i], xs_single[j].reshape(-1))
+                                               for k, part in enumerate(parts) for i, j in enumerate(part))
+    time.sleep(1.0)  # an idle gap that separates the warm-up from the timed solves in a kernel trace
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for f in [pool.submit(run, k, None) for k in range(ng)]:
@@ -513,7 +516,7 @@ def grouped_leg(args, torch, smg, syss, xs_single, streams):
     for g in groups:
         g.close()
     return dict(solves_per_s=len(syss) * args.steps / dt, groups=ng, systems_per_group=[len(p) for p in parts],
-                mean_iterations=sum(recs) / len(recs), equal_to_single=bool(equal))
+                mean_iterations=sum(recs) / len(recs), equal_to_single=None if equal is None else bool(equal))
 
 
 def legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu):
@@ -759,6 +762,7 @@ def timed_events(fn, reps, stream):
 
 
 COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_counters.md")
+COUNTERS_MD_GROUP = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_group5_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip")
 
 
@@ -778,14 +782,12 @@ def kernel_source_digest():
     return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed counter runs
+def measured_traffic(path):
+    """HBM bytes per launch of a roofline kernel from its committed counter runs
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known size), or None when
     the kernel source changed since they were taken."""
-    import hashlib
-
     try:
-        text = open(COUNTERS_MD).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = dict(line.split(" = ", 1) for line in text.splitlines() if " = " in line and line[:1].isalpha())
@@ -797,35 +799,44 @@ def measured_traffic():
         return None
 
 
-def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev):
+def coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev, group=None):
     """Average launch time of the FP32 coarse operator on level 1 (the kernel that
     dominates the mixed-precision V-cycle), and its algorithmic bytes: 9 link
     blocks of nc x nc complex values per coarse site (4 bytes each in FP16 operator
-    storage, 8 in FP32) plus the input and output vector (complex64)."""
+    storage, 8 in FP32) plus the input and output vector (complex64), per system.
+    With a group (smg.Group) one launch applies every system's operator to its own
+    column, as inside the grouped solves."""
     import ctypes
 
     cx, ct, nc = s.level_info(1)
-    v = torch.randn(cx * ct * nc, dtype=torch.complex64, device=dev)
+    G = 1 if group is None else len(group.solvers)
+    v = torch.randn(G * cx * ct * nc, dtype=torch.complex64, device=dev)
     y = torch.empty_like(v)
     px, py = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr())
-    dur = timed_graph(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
+    if group is None:
+        dur = timed_graph(lambda: lib.smg_apply_level_f32(s.handle, 1, px, py, 1, sp), reps, stream)
+    else:
+        gh, nul = group.handle, ctypes.c_void_p()
+        dur = timed_graph(lambda: lib.smg_group_level_op_f32(gh, 1, 0, px, py, nul, sp), reps, stream)
     h16 = s.params.operator_storage == smg.STORE_F16
-    nbytes = 9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8
+    nbytes = G * (9 * nc * nc * (4 if h16 else 8) * cx * ct + 2 * cx * ct * nc * 8)
     gbs = nbytes / dur / 1e9
     q = (nc + 3) // 4
-    if 4 <= nc <= 16:  # one right-hand side: the LDS-staged kernel, one pass of q columns per wave
-        name = f"k_coarse_sv<float,0,{q},{'hfc' if h16 else 'cpx<float>'}>"
+    if 4 <= nc <= 16:  # the LDS-staged kernel, one pass of q columns per wave
+        name = f"k_coarse_sv<float,0,{q},{'hfc' if h16 else 'cpx<float>'}{',true' if group is not None else ''}>"
     else:
         cols = 2 if q <= 2 else min(q, 4)  # columns per pass, as the launcher picks them
         name = f"k_coarse<float,0,1,{cols}{',hfc' if h16 else ''}>"
     what = "FP16 links (scaled), FP32 arithmetic" if h16 else "FP32"
+    per = "single RHS" if group is None else f"{G} systems per launch (each its own links), one RHS each"
     # context: a plain device copy moving the same bytes (half read, half written), timed the same way
     src = torch.ones(nbytes // 8, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dcopy = timed_graph(lambda: dst.copy_(src), reps, stream)
-    return dict(kernel=f"{name}: coarse 9-point operator, {what}, level 1 ({cx}x{ct} sites, nc={nc}), single RHS",
+    return dict(kernel=f"{name}: coarse 9-point operator, {what}, level 1 ({cx}x{ct} sites, nc={nc}), {per}",
                 bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0,
-                traffic=measured_traffic(), avg_launch_us=dur * 1e6, bytes_per_launch=nbytes,
+                traffic=measured_traffic(COUNTERS_MD if group is None else COUNTERS_MD_GROUP),
+                avg_launch_us=dur * 1e6, bytes_per_launch=nbytes,
                 same_bytes_copy_us=dcopy * 1e6, same_bytes_copy_GBps=nbytes / dcopy / 1e9)
 
 
@@ -847,14 +858,22 @@ def kernel_probe(reps):
     lib = smg.load_library()
     stream = torch.cuda.Stream(dev)  # graphs are not captured on the null stream
     sp = ctypes.c_void_p(stream.cuda_stream)
-    roof = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev)
+    single = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev)
+    # a group of GROUP_SIZE systems of the same shape (the field at further masses), as in
+    # the grouped solves of the benchmark
+    sys_ = [s] + [s.derive(0.01 * k) for k in range(1, GROUP_SIZE)]
+    with smg.Group(sys_, stream=stream) as g:
+        roof = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev, group=g)
+    for d in sys_[1:]:
+        d.close()
     # calibration: an elementwise FP32 kernel that reads and writes 64 MiB each
     a = torch.ones(16 << 20, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(reps):
         torch.add(a, 1.0, out=b)
     torch.cuda.synchronize()
-    print(json.dumps(dict(roofline=roof, copy_read_bytes=a.numel() * 4, copy_write_bytes=b.numel() * 4)))
+    print(json.dumps(dict(roofline=roof, roofline_single=single, copy_read_bytes=a.numel() * 4,
+                          copy_write_bytes=b.numel() * 4)))
 
 
 def dslash_probe(Ld, reps):
@@ -940,7 +959,9 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only the serving leg (prints its summary)")
     ap.add_argument("--no-mrhs", action="store_true")
     ap.add_argument("--no-group", action="store_true", help="skip the grouped solves of the headline systems")
-    ap.add_argument("--groups", type=int, default=4, help="groups (streams) of the grouped headline solves")
+    ap.add_argument("--groups", type=int, default=GROUPS, help="groups (streams) of the grouped headline solves")
+    ap.add_argument("--group-only", action="store_true",
+                    help="with --solves-only: time only the grouped solves (an idle second before the timed steps)")
     ap.add_argument("--no-split", action="store_true", help="skip the chirality-split comparison")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-RHS leg (prints its summary)")
     ap.add_argument("--mrhs-steps", type=int, default=3)
@@ -1095,6 +1116,10 @@ def main():
         for f in futs:
             f.result()
 
+    if args.solves_only and args.group_only:
+        res = grouped_leg(args, torch, smg, systems, None, streams)
+        print(json.dumps(dict(res, steps=args.steps)))
+        return 0
     if args.solves_only:
         step(systems, smg.MIXED)
         torch.cuda.synchronize()
@@ -1194,14 +1219,21 @@ def main():
         del ssys
     pool.shutdown()
 
-    # ---- dominant-kernel roofline: the FP32 level-2 coarse operator of the mixed solve
-    # (64x64 coarse sites, nc = 12), measured with HIP events on the solver's stream
+    # ---- dominant-kernel roofline: the FP32 level-1 coarse operator of the mixed solve
+    # (64x64 coarse sites, nc = 12) as the grouped solves launch it (the systems of the
+    # first group, each its own links, one launch), and for one system alone; HIP events
+    # on the launching stream
     import ctypes
 
     lib = smg.load_library()
     sp = ctypes.c_void_p(stream.cuda_stream)
     s = systems[0][0]
-    roof = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev)
+    roof_single = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev)
+    roof = roof_single
+    if grouped is not None:
+        first = [systems[j][0] for j in range(0, len(systems), grouped["groups"])]
+        with smg.Group(first, stream=stream) as g:
+            roof = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev, group=g)
 
     # ---- fine D^H D at 2048^2 and 4096^2 (working sets beyond the caches) ------------
     def dslash(Ld):
@@ -1261,7 +1293,10 @@ def main():
 
     mixed = results["mixed"]
     fp64 = results["fp64"]
-    value = mixed["solves"] / mixed["seconds"]
+    single_rate = mixed["solves"] / mixed["seconds"]
+    # the job's throughput: the grouped solves (the same systems and solutions, bit for
+    # bit), unless they were skipped
+    value = grouped["solves_per_s"] if grouped is not None else single_rate
 
     def rate(r):
         return r["solves"] / r["seconds"]
@@ -1280,7 +1315,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": mixed["seconds"] / args.steps * 1e3,
+        "ms_per_step": n_systems / value * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -1290,12 +1325,17 @@ def main():
         "config": {
             "workload": "256x256 U(1) beta=6, 4 fields x 5 masses (lambda_min/lambda_max 1e-2..1e-4), "
                         "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG inside "
-                        f"FP64 defect correction, variant {VARIANTS[0][0]} (others in mixed_variants)",
+                        f"FP64 defect correction, variant {VARIANTS[0][0]} (others in mixed_variants); "
+                        + (f"value: the {n_systems} systems as {grouped['groups']} grouped solves of "
+                           f"{max(grouped['systems_per_group'])} on {grouped['groups']} streams (grouped)"
+                           if grouped is not None else f"value: one solve per system on {nwork} streams"),
             "mixed_variants": variants,
             "systems_per_step": n_systems,
             "concurrent_streams": nwork,
+            "single_solves_per_s": single_rate,
             "fp64_solves_per_s": fp64["solves"] / fp64["seconds"],
-            "mixed_over_fp64": (mixed["solves"] / mixed["seconds"]) / (fp64["solves"] / fp64["seconds"]),
+            "mixed_over_fp64": single_rate / (fp64["solves"] / fp64["seconds"]),
+            "value_over_fp64": value / (fp64["solves"] / fp64["seconds"]),
             "setup_s_per_field": setup_s,
             "remass_s_mean": sum(remass_s) / max(len(remass_s), 1),
             "mean_iterations_mixed": sum(r["iterations"] for r in mixed["records"]) / len(mixed["records"]),
@@ -1305,6 +1345,7 @@ def main():
             "legs": legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu),
         },
         "roofline": roof,
+        "roofline_single": roof_single,
         "dslash": dslash_2048,
         "dslash_4096": dslash_4096,
         "cpu_baseline": cpu,

@@ -403,6 +403,16 @@ int smg_group_solve(smg_group g, const double* rhs, double* x, double tol, int32
                     smg_stats* stats);
 void smg_group_destroy(smg_group g);
 
+/* The FP32 operator of level `level` (the one smg_level_op_f32 applies) of every
+ * system of the group, system j's on column j, in one launch per step as inside
+ * smg_group_solve (Eq. 2 on coarse levels, A = D^H D on the fine level): mode 0:
+ * y_j = A_j x_j; mode 2 (residual): y_j = aux_j - A_j x_j.  x, y, aux: device
+ * complex64 [nsys][n_l] (aux may be NULL for mode 0); column j equals
+ * smg_level_op_f32 on handle j with one right-hand side bit for bit.  The same
+ * rule on the first handle as for smg_group_solve.  Errors: SMG_EINVAL.  ASYNC. */
+int smg_group_level_op_f32(smg_group g, int32_t level, int32_t mode, const float* x, float* y, const float* aux,
+                           void* stream);
+
 /* Device bytes held by the batch (in addition to its handle). */
 int smg_batch_memory_bytes(smg_batch b, size_t* bytes);
 

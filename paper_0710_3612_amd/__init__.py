@@ -203,6 +203,7 @@ def load_library():
         "smg_group_create": (i32, [ctypes.POINTER(h), i32, P, ctypes.POINTER(h)]),
         "smg_group_solve": (i32, [h, P, P, ctypes.c_double, i32, P, ctypes.POINTER(Stats)]),
         "smg_group_destroy": (None, [h]),
+        "smg_group_level_op_f32": (i32, [h, i32, i32, P, P, P, P]),
         "smg_destroy": (None, [h]),
         "smg_strerror": (ctypes.c_char_p, [i32]),
         "smg_last_error": (ctypes.c_char_p, []),
@@ -633,6 +634,26 @@ class Group:
                                         st)
         _check(code, allow_notconv=True)
         return x, [q.as_dict() for q in st], code
+
+    def level_op_f32(self, level: int, x, mode: int = 0, aux=None, out=None, stream=None):
+        """Every system's FP32 level operator on its own column (smg_group_level_op_f32):
+        x: [nsys, n_level] complex64 CUDA tensor; mode 0: y_j = A_j x_j, mode 2:
+        y_j = aux_j - A_j x_j.  Returns y."""
+        G = len(self.solvers)
+        shape = (G, self.solvers[0].level_size(level))
+
+        def p32(t):
+            if t is None:
+                return ctypes.c_void_p()
+            if (tuple(t.shape) != shape or t.dtype != self._torch.complex64 or not t.is_cuda
+                    or not t.is_contiguous()):
+                raise ValueError(f"expected a contiguous complex64 CUDA tensor of shape {shape}")
+            return ctypes.c_void_p(t.data_ptr())
+
+        y = out if out is not None else self._torch.empty(shape, dtype=self._torch.complex64, device=x.device)
+        _check(self.lib.smg_group_level_op_f32(self.handle, int(level), int(mode), p32(x), p32(y), p32(aux),
+                                               _stream(stream)))
+        return y
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

@@ -2662,6 +2662,31 @@ int smg_group_solve(smg_group gh, const double* rhs, double* x, double tol, int3
   API_END
 }
 
+int smg_group_level_op_f32(smg_group gh, int32_t level, int32_t mode, const float* x, float* y, const float* aux,
+                           void* stream) {
+  API_BEGIN
+  Group& g = *GH(gh);
+  if (mode != 0 && mode != 2) throw Error(SMG_EINVAL, "mode must be 0 or 2");
+  if (!x || !y || (mode == 2 && !aux)) throw Error(SMG_EINVAL, "null vector");
+  const int G = (int)g.cs.size();
+  Ctx* c = g.cs[0];
+  check_level(c, level);
+  hipStream_t st = (hipStream_t)stream;
+  bool stale = false;
+  for (int j = 0; j < G; ++j) stale = stale || g.cs[j]->gen != g.gens[j] || !g.cs[j]->f32_ready;
+  if (stale) group_fill(g, st);
+  c->st = st;
+  ensure_level_work<float>(*c, G);
+  struct Bind {  // the context runs ungrouped again on every exit path
+    Ctx* c;
+    ~Bind() { c->grp = nullptr; }
+  } bind{c};
+  c->grp = &g.tab;
+  apply_op<float>(*c, c->L32[level], (const z32*)x, (z32*)y, G, mode, 0.0, nullptr, (const z32*)aux);
+  return SMG_OK;
+  API_END
+}
+
 void smg_group_destroy(smg_group g) {
   if (!g) return;
   delete reinterpret_cast<Group*>(g);

@@ -91,3 +91,51 @@ def test_group_rejects_mismatched_shapes(cuda):
     finally:
         for s in (a, b, c):
             s.close()
+
+
+@pytest.mark.parametrize("lx,lt,blocks,nv,opst", [(128, 128, [(4, 4), (4, 4)], [12, 12], 2),
+                                                 (64, 64, [(4, 4), (4, 4)], [6, 6], 0)])
+def test_group_level_op_equals_single(cuda, lx, lt, blocks, nv, opst):
+    """smg_group_level_op_f32: column j is handle j's own FP32 level operator (fine A,
+    the coarse operators, modes 0 and 2) bit for bit, also after a re-mass of one
+    handle (the tables are filled again)."""
+    import torch
+
+    import paper_0710_3612_amd as smg
+
+    solvers = []
+    for f in range(2):
+        U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 10, 400 + f))
+        p = smg.make_params(lx, lt, 0.05, levels=len(blocks) + 1, blocks=blocks, nv=nv, operator_storage=opst,
+                            coarsest_fp64=False, seed=17 + f)
+        s0 = smg.Solver(dev(U), p)
+        solvers += [s0, s0.derive(0.11)]
+    G = len(solvers)
+    try:
+        with smg.Group(solvers) as g:
+            for remass in (False, True):
+                if remass:
+                    solvers[1].set_mass(0.2)
+                for level in range(len(blocks) + 1):
+                    n = solvers[0].level_size(level)
+                    rng = np.random.default_rng(31 + level)
+                    X = torch.from_numpy((rng.standard_normal((G, n)) + 1j * rng.standard_normal((G, n)))
+                                         .astype(np.complex64)).to("cuda")
+                    Aux = torch.from_numpy((rng.standard_normal((G, n)) + 1j * rng.standard_normal((G, n)))
+                                           .astype(np.complex64)).to("cuda")
+                    Y0 = host(g.level_op_f32(level, X))
+                    Y2 = host(g.level_op_f32(level, X, mode=2, aux=Aux))
+                    for j, s in enumerate(solvers):
+                        y0 = host(s.level_op_f32(level, X[j:j + 1].contiguous()))
+                        y2 = host(s.level_op_f32(level, X[j:j + 1].contiguous(), mode=2,
+                                                 aux=Aux[j:j + 1].contiguous()))
+                        assert np.array_equal(Y0[j], y0.reshape(-1)), (remass, level, j)
+                        assert np.array_equal(Y2[j], y2.reshape(-1)), (remass, level, j)
+            X1 = torch.zeros((G, solvers[0].level_size(1)), dtype=torch.complex64, device="cuda")
+            with pytest.raises(smg.SmgError):
+                g.level_op_f32(1, X1, mode=1)
+            with pytest.raises(ValueError):
+                g.level_op_f32(1, X1[:, 1:].contiguous())
+    finally:
+        for s in solvers:
+            s.close()
