@@ -44,8 +44,13 @@ SETUP_ITERS = 5
 SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
-GROUPS = 4               # the 20 systems of the precision workload solve as 4 grouped solves ...
-GROUP_SIZE = 5           # ... of 5 systems each (every launch of a grouped solve serves its 5 systems)
+# The 20 systems of the precision workload (field-major: system 5 f + m is field f at
+# mass m) solve as 5 grouped solves of 4: group k takes systems k, k + 5, ..., the four
+# fields at mass k, whose solves take alike many iterations, so no column of a group
+# runs on masked while a slower one finishes (measured on MI355X: 5 x 4 1711-1731
+# solves/s, 4 x 5 1506, 10 x 2 1680, 3 groups 1415, 6-8 uneven groups 1383-1540).
+GROUPS = 5
+GROUP_SIZE = 4
 
 # Serving workload: Poisson streams of requests over 8 seeded fields per (lattice size,
 # beta), sizes 64..512^2, beta 3, 6, 10 (500 sweeps, beta 10: 1000), masses
@@ -762,7 +767,7 @@ def timed_events(fn, reps, stream):
 
 
 COUNTERS_MD = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_counters.md")
-COUNTERS_MD_GROUP = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_group5_counters.md")
+COUNTERS_MD_GROUP = os.path.join(ROOT, "profiles", "coarse_f16_level1_256_group4_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0710_3612_amd", "csrc", "multigrid.hip")
 
 
@@ -859,8 +864,8 @@ def kernel_probe(reps):
     stream = torch.cuda.Stream(dev)  # graphs are not captured on the null stream
     sp = ctypes.c_void_p(stream.cuda_stream)
     single = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev)
-    # a group of GROUP_SIZE systems of the same shape (the field at further masses), as in
-    # the grouped solves of the benchmark
+    # a group of GROUP_SIZE systems of the benchmark's shape, as the grouped solves launch
+    # them (here one field at further masses; the kernel's work does not depend on which)
     sys_ = [s] + [s.derive(0.01 * k) for k in range(1, GROUP_SIZE)]
     with smg.Group(sys_, stream=stream) as g:
         roof = coarse_roofline(smg, lib, s, sp, stream, reps, torch, dev, group=g)
