@@ -44,11 +44,12 @@ SETUP_ITERS = 5
 SA_SCALE = 4.0 / 3.0     # smoothed aggregation weight scale
 TOL = 1e-10
 DSLASH_L = 2048          # fine D^H D bandwidth lattice (working set far beyond the caches)
-# The 20 systems of the precision workload (field-major: system 5 f + m is field f at
-# mass m) solve as 5 grouped solves of 4: group k takes systems k, k + 5, ..., the four
-# fields at mass k, whose solves take alike many iterations, so no column of a group
-# runs on masked while a slower one finishes (measured on MI355X: 5 x 4 1711-1731
-# solves/s, 4 x 5 1506, 10 x 2 1680, 3 groups 1415, 6-8 uneven groups 1383-1540).
+# The 20 systems of the precision workload (4 fields x 5 masses) solve as 5 grouped
+# solves of 4: group k holds the four fields at their k-th mass, whose solves take
+# alike many iterations, so no column of a group runs on masked while a slower one
+# finishes (group_parts; measured on MI355X with that grouping: 5 x 4 1711-1731
+# solves/s, 10 x 2 1680; with masses mixed in a group: 4 x 5 1506, 3 groups 1415,
+# 6-8 uneven groups 1383-1540).
 GROUPS = 5
 GROUP_SIZE = 4
 
@@ -482,6 +483,25 @@ def c5_leg(args, torch, smg, dev):
                 seconds=time.perf_counter() - t_start)
 
 
+def group_parts(syss, ng):
+    """Indices of the systems of each of ng groups.  A group's solve runs until its
+    slowest system converges, so systems that take alike many iterations share a
+    group: the k-th mass of every field (each field's masses target the same spectral
+    ratios), in consecutive chunks of near-equal size."""
+    seen, rank = {}, []
+    for _, _, seed, _ in syss:
+        rank.append(seen.get(seed, 0))
+        seen[seed] = rank[-1] + 1
+    order = sorted(range(len(syss)), key=lambda j: (rank[j], j))
+    base, extra = divmod(len(syss), ng)
+    parts, at = [], 0
+    for k in range(ng):
+        size = base + (1 if k < extra else 0)
+        parts.append(order[at:at + size])
+        at += size
+    return parts
+
+
 def grouped_leg(args, torch, smg, syss, xs_single, streams):
     """The same mixed solves as grouped solves (smg_group_solve): the systems split
     into args.groups groups of one hierarchy shape, each group on its own stream and
@@ -490,7 +510,7 @@ def grouped_leg(args, torch, smg, syss, xs_single, streams):
     from concurrent.futures import ThreadPoolExecutor
 
     ng = max(1, min(args.groups, len(syss), len(streams)))
-    parts = [list(range(k, len(syss), ng)) for k in range(ng)]
+    parts = group_parts(syss, ng)
     groups = [smg.Group([syss[j][0] for j in part], stream=streams[k]) for k, part in enumerate(parts)]
     rhs = [torch.stack([syss[j][1].reshape(-1) for j in part]) for part in parts]
     outs = [torch.empty_like(r) for r in rhs]
@@ -521,7 +541,8 @@ def grouped_leg(args, torch, smg, syss, xs_single, streams):
     for g in groups:
         g.close()
     return dict(solves_per_s=len(syss) * args.steps / dt, groups=ng, systems_per_group=[len(p) for p in parts],
-                mean_iterations=sum(recs) / len(recs), equal_to_single=None if equal is None else bool(equal))
+                members=parts, mean_iterations=sum(recs) / len(recs),
+                equal_to_single=None if equal is None else bool(equal))
 
 
 def legs_summary(dslash_2048, dslash_4096, c1, mrhs, serving, split, cpu):
@@ -1236,7 +1257,7 @@ def main():
     roof_single = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev)
     roof = roof_single
     if grouped is not None:
-        first = [systems[j][0] for j in range(0, len(systems), grouped["groups"])]
+        first = [systems[j][0] for j in grouped["members"][0]]
         with smg.Group(first, stream=stream) as g:
             roof = coarse_roofline(smg, lib, s, sp, stream, args.dslash_reps, torch, dev, group=g)
 
