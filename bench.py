@@ -1320,9 +1320,12 @@ def main():
     mixed = results["mixed"]
     fp64 = results["fp64"]
     single_rate = mixed["solves"] / mixed["seconds"]
-    # the job's throughput: the grouped solves (the same systems and solutions, bit for
-    # bit), unless they were skipped
-    value = grouped["solves_per_s"] if grouped is not None else single_rate
+    # the job's throughput: the grouped solves, when their solutions equal the single
+    # solves' bit for bit (checked in this run); otherwise the single solves
+    use_grouped = grouped is not None and grouped["equal_to_single"] is True
+    if grouped is not None and not use_grouped:
+        log("grouped solutions differ from the single solves: the value is the single-solve rate")
+    value = grouped["solves_per_s"] if use_grouped else single_rate
 
     def rate(r):
         return r["solves"] / r["seconds"]
@@ -1353,8 +1356,9 @@ def main():
                         "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG inside "
                         f"FP64 defect correction, variant {VARIANTS[0][0]} (others in mixed_variants); "
                         + (f"value: the {n_systems} systems as {grouped['groups']} grouped solves of "
-                           f"{max(grouped['systems_per_group'])} on {grouped['groups']} streams (grouped)"
-                           if grouped is not None else f"value: one solve per system on {nwork} streams"),
+                           f"{max(grouped['systems_per_group'])} (systems of like mass together) on {grouped['groups']} "
+                           "streams (grouped)"
+                           if use_grouped else f"value: one solve per system on {nwork} streams"),
             "mixed_variants": variants,
             "systems_per_step": n_systems,
             "concurrent_streams": nwork,
