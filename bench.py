@@ -1356,8 +1356,8 @@ def main():
                         "3 levels 4x4, Nv=12, nu=4, 1 Gaussian RHS per system, tol 1e-10; mixed: FP32 MG-CG inside "
                         f"FP64 defect correction, variant {VARIANTS[0][0]} (others in mixed_variants); "
                         + (f"value: the {n_systems} systems as {grouped['groups']} grouped solves of "
-                           f"{max(grouped['systems_per_group'])} (systems of like mass together) on {grouped['groups']} "
-                           "streams (grouped)"
+                           f"{max(grouped['systems_per_group'])} (systems of like mass together) on "
+                           f"{grouped['groups']} streams (grouped)"
                            if use_grouped else f"value: one solve per system on {nwork} streams"),
             "mixed_variants": variants,
             "systems_per_step": n_systems,
