@@ -660,6 +660,7 @@ def serving_leg(args, torch, smg, dev):
             for r in reqs:
                 r.arrival = 0.0
         c0 = dict(setups=srv.cache.setups, derives=srv.cache.derives, evictions=srv.cache.evictions)
+        ph0 = srv.phase_times()
         results = srv.run_trace(reqs, timeout=1800,
                                 progress=lambda o, n: log(f"serving: {n - o} of {n} requests done"))
         summ = serve.latency_summary(results)
@@ -667,6 +668,8 @@ def serving_leg(args, torch, smg, dev):
         by_size = {}
         for r in results:
             by_size.setdefault(sizes[r.field], []).append(r)
+        ph1 = srv.phase_times()
+        summ.update(phase_s={k: round(ph1[k] - ph0.get(k, 0.0), 3) for k in sorted(ph1)})
         summ.update(offered_rps=None if rate == math.inf else rate, failed=len(bad),
                     first_failure=(None if not bad else f"{bad[0].error} {bad[0].status} {bad[0].true_relres}"),
                     setups=srv.cache.setups - c0["setups"], derives=srv.cache.derives - c0["derives"],
@@ -679,7 +682,8 @@ def serving_leg(args, torch, smg, dev):
 
     def server():
         return serve.Server(backend, SERVE_BUDGET, capacity=SERVE_CAPACITY, tol=TOL, maxiter=2000,
-                            precision=smg.MIXED, max_lanes=args.serve_lanes, keep_solutions=False)
+                            precision=smg.MIXED, max_lanes=args.serve_lanes, keep_solutions=False,
+                            fit_capacity=not args.serve_fixed_batches)
 
     # warm: every field's full setup at its lightest mass (the expensive part), then
     # the other masses, small lattices first, while 90% of the budget holds them
@@ -714,7 +718,8 @@ def serving_leg(args, torch, smg, dev):
                          f"1-16 Gaussian RHS each, 4x4 "
                          f"aggregates down to a coarsest lattice of at most 16^2 (2/3/3/4 levels), "
                          f"Nv={SERVE_NV}, mixed precision (FP64 flexible CG, FP32 V-cycle, FP16 operator copies), "
-                         f"{SERVE_CAPACITY}-slot batches, {args.serve_lanes} lanes, budget {SERVE_BUDGET / 1e9:.0f} GB, "
+                         f"{'' if args.serve_fixed_batches else '4-'}{SERVE_CAPACITY}-slot batches, {args.serve_lanes} lanes, "
+                         f"budget {SERVE_BUDGET / 1e9:.0f} GB, "
                          f"tol {TOL:g}"),
                keys=len(keys), warm_keys=len(warm_keys), warm_s=warm_s, field_generation_s=gen_s)
     sat = run(srv, math.inf, 11, nreq)
@@ -979,6 +984,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per serving run (--serve-full: 2000)")
     ap.add_argument("--serve-lanes", type=int, default=8, help="concurrent (field, mass) lanes")
+    ap.add_argument("--serve-fixed-batches", action="store_true",
+                    help="every lane's batch has 16 slots (default: sized to the right-hand sides queued for its "
+                         "key, 4-16 slots)")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving at 0.5, 0.7 and 0.9 x saturation and a cold run (longer)")
     ap.add_argument("--no-serve", action="store_true")

@@ -345,7 +345,10 @@ int smg_get_smoother_coefs(smg_handle h, int32_t level, double* out);
  * ------------------------------------------------------------------------------ */
 
 /* New batch of max_rhs (1..256) slots with relative tolerance tol (true residual)
- * and per-slot iteration cap maxiter.  Errors: SMG_EINVAL, SMG_ENOMEM. */
+ * and per-slot iteration cap maxiter.  Every device array of the batch is carved
+ * from one allocation (each array rounded to 256 bytes), so creating and
+ * destroying a batch costs one call of the installed allocator each way.
+ * Errors: SMG_EINVAL, SMG_ENOMEM. */
 int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter, int32_t precision, void* stream,
                      smg_batch* out);
 
@@ -416,6 +419,8 @@ int smg_group_level_op_f32(smg_group g, int32_t level, int32_t mode, const float
 /* Device bytes held by the batch (in addition to its handle). */
 int smg_batch_memory_bytes(smg_batch b, size_t* bytes);
 
+/* Synchronises every stream that a call of the batch used (not the whole device),
+ * then returns the batch's memory. */
 void smg_batch_destroy(smg_batch b);
 
 /* Device bytes held by the handle. */
@@ -429,10 +434,12 @@ int smg_memory_bytes(smg_handle h, size_t* bytes);
  * allocated it.  alloc returns device memory of the current device aligned to at
  * least 256 bytes, or NULL (the call then fails with SMG_ENOMEM).  A handle or
  * batch keeps the allocator that was installed when it was created.  Before it
- * hands memory to release the library synchronises the device, so no kernel still
- * uses it.  Both NULL (the default) restore hipMalloc / hipFree.  Pinned host
- * memory (the convergence mirrors) and rocBLAS's own workspace (blocked
- * inversion of coarsest operators above 512 variables) are not routed.
+ * hands memory to release the library synchronises the device (a batch: the
+ * streams its calls used), so no kernel still uses it.  Both NULL (the default)
+ * restore hipMalloc / hipFree.  Pinned host memory (the convergence mirrors, and
+ * a batch's read-back scratch, kept in a process-wide cache for reuse) and
+ * rocBLAS's own workspace (blocked inversion of coarsest operators above 512
+ * variables) are not routed.
  * Errors: SMG_EINVAL when only one of alloc and release is given. */
 typedef void* (*smg_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*smg_release_fn)(void* ptr, size_t bytes, void* stream, void* ctx);

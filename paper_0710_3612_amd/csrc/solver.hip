@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <limits>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <cstdio>
@@ -88,44 +89,99 @@ struct Pool {
   std::vector<hipStream_t> streams;
   size_t bytes = 0;
   uintptr_t fake = 4096;  // distinct, never dereferenced addresses of a dry pool
-  template <typename T>
-  T* alloc(size_t count) {
-    if (count == 0) count = 1;
-    const size_t nb = count * sizeof(T);
-    bytes += nb;
-    if (dry) {
-      fake += (nb + 255) & ~(size_t)255;
-      return reinterpret_cast<T*>(fake);
-    }
+  // Arena pools (batches): every array is rounded to 256 bytes and carved from one
+  // block that open_arena takes from the allocator, so that a batch costs one
+  // allocation and one release instead of one per array.  A dry pool with the same
+  // granularity counts the same bytes.
+  size_t gran = 1;
+  char* arena = nullptr;
+  size_t arena_size = 0, arena_off = 0;
+  // The owner has synchronised every stream that used the memory, so the release
+  // needs no device-wide synchronisation.
+  bool owner_synced = false;
+  void* raw(size_t nb) {
     hipStream_t st = stream ? *stream : nullptr;
     void* p = nullptr;
     if (a.alloc) {
       p = a.alloc(nb, (void*)st, a.ctx);
-      if (!p) {
-        bytes -= nb;
-        throw Error(SMG_ENOMEM, "the installed allocator returned no memory for " + std::to_string(nb) + " bytes");
-      }
+      if (!p) throw Error(SMG_ENOMEM, "the installed allocator returned no memory for " + std::to_string(nb) + " bytes");
     } else if (hipMalloc(&p, nb) != hipSuccess) {
       (void)hipGetLastError();
-      bytes -= nb;
       throw Error(SMG_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed");
     }
     ptrs.push_back(p);
     sizes.push_back(nb);
     streams.push_back(st);
+    return p;
+  }
+  void open_arena(size_t total) {
+    gran = 256;
+    if (dry || total == 0) return;
+    arena = static_cast<char*>(raw(total));
+    arena_size = total;
+    arena_off = 0;
+  }
+  template <typename T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    const size_t nb = (count * sizeof(T) + gran - 1) / gran * gran;
+    if (dry) {
+      bytes += nb;
+      fake += (nb + 255) & ~(size_t)255;
+      return reinterpret_cast<T*>(fake);
+    }
+    if (arena && arena_off + nb <= arena_size) {
+      T* p = reinterpret_cast<T*>(arena + arena_off);
+      arena_off += nb;
+      bytes += nb;
+      return p;
+    }
+    void* p = raw(nb);  // beyond the arena (or none): an array of its own
+    bytes += nb;
     return static_cast<T*>(p);
   }
   ~Pool() {
     if (dry || ptrs.empty()) return;
     if (a.release) {
       // the callback may hand the memory to other users at once: nothing may still read it
-      (void)hipDeviceSynchronize();
+      if (!owner_synced) (void)hipDeviceSynchronize();
       for (size_t i = 0; i < ptrs.size(); ++i) a.release(ptrs[i], sizes[i], (void*)streams[i], a.ctx);
     } else {
-      for (void* p : ptrs) (void)hipFree(p);
+      for (void* p : ptrs) (void)hipFree(p);  // hipFree waits for the device itself
     }
   }
 };
+
+// Small pinned host blocks of the batches (read-back scratch), kept for reuse: a
+// pinned allocation and its release each cost a round trip to the driver, and a
+// serving loop opens and closes batches all the time.  Bounded by the largest
+// number of batches alive at once.
+struct PinnedCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_;
+  void* get(size_t nb) {
+    nb = (nb + 4095) & ~(size_t)4095;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = free_.find(nb);
+      if (it != free_.end()) {
+        void* p = it->second;
+        free_.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    HIPCHECK(hipHostMalloc(&p, nb, hipHostMallocDefault));
+    return p;
+  }
+  void put(void* p, size_t nb) {
+    if (!p) return;
+    nb = (nb + 4095) & ~(size_t)4095;
+    std::lock_guard<std::mutex> lk(mu);
+    free_.emplace(nb, p);
+  }
+};
+PinnedCache g_pinned;  // never freed: the blocks live until the process ends
 
 // One grid level in one precision.
 template <typename R>
@@ -1606,6 +1662,10 @@ struct Batch {
   uint64_t graph_gen = 0;
   hipStream_t gs = nullptr;  // the batch's own stream: graphs cannot be captured on the null stream
   hipEvent_t ev = nullptr;
+  std::vector<hipStream_t> seen;  // every stream a call of the batch enqueued work on
+  void note(hipStream_t s) {
+    if (std::find(seen.begin(), seen.end(), s) == seen.end()) seen.push_back(s);
+  }
   void drop_graphs() {
     for (auto& g : graphs)
       if (g) {
@@ -1617,8 +1677,8 @@ struct Batch {
     drop_graphs();
     if (ev) (void)hipEventDestroy(ev);
     if (gs) (void)hipStreamDestroy(gs);
-    if (h) (void)hipHostFree(h);
-    if (hi_) (void)hipHostFree(hi_);
+    g_pinned.put(h, sizeof(double) * 2 * cap);
+    g_pinned.put(hi_, sizeof(int) * cap);
   }
   int hi() const {
     int m = 0;
@@ -2588,6 +2648,7 @@ int smg_query_bytes(const smg_params* params, int32_t nrhs, int32_t precision, s
     auto c1 = planned();
     Batch B;
     B.pool.dry = true;
+    B.pool.gran = 256;  // the arena's granularity (smg_batch_create)
     B.c = c1.get();
     B.cap = nrhs;
     B.prec = precision;
@@ -2713,11 +2774,23 @@ int smg_batch_create(smg_handle h, int32_t max_rhs, double tol, int32_t maxiter,
     const size_t e = (size_t)max_rhs * B->n;
     B->pool.stream = &B->st0;
     B->st0 = st;
+    B->note(st);
     reserve_batch_handle(*c, max_rhs, precision);
+    {  // every array of the batch in one block, sized by the same plan on a dry pool
+      Batch plan;
+      plan.pool.dry = true;
+      plan.pool.gran = 256;
+      plan.c = c;
+      plan.cap = max_rhs;
+      plan.prec = precision;
+      plan.n = B->n;
+      batch_alloc(plan);
+      B->pool.open_arena(plan.pool.bytes);
+    }
     batch_alloc(*B);
     if (precision == SMG_MIXED) ensure_f32(*c);
-    HIPCHECK(hipHostMalloc((void**)&B->h, sizeof(double) * 2 * max_rhs, hipHostMallocDefault));
-    HIPCHECK(hipHostMalloc((void**)&B->hi_, sizeof(int) * max_rhs, hipHostMallocDefault));
+    B->h = static_cast<double*>(g_pinned.get(sizeof(double) * 2 * max_rhs));
+    B->hi_ = static_cast<int*>(g_pinned.get(sizeof(int) * max_rhs));
     // off by default: each (batch, slot count) pays a capture, and replays do not
     // shorten the iteration where the device front end bounds it (smg_batch_use_graphs)
     B->use_graphs = false;
@@ -2750,6 +2823,7 @@ int smg_batch_admit(smg_batch b, const double* rhs, int32_t* slot, void* stream)
   Batch* B = BH(b);
   if (!rhs || !slot) throw Error(SMG_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
+  B->note(st);
   int s = -1;
   for (int j = 0; j < B->cap; ++j)
     if (!B->used[j]) {
@@ -2795,6 +2869,7 @@ int smg_batch_step(smg_batch b, int32_t iters, void* stream) {
   API_BEGIN
   Batch* B = BH(b);
   if (iters < 1) throw Error(SMG_EINVAL, "iters must be >= 1");
+  B->note((hipStream_t)stream);
   batch_step(*B, iters, (hipStream_t)stream);
   return SMG_OK;
   API_END
@@ -2839,6 +2914,7 @@ int smg_batch_harvest(smg_batch b, int32_t slot, double* x, void* stream) {
   if (slot < 0 || slot >= B->cap || !B->used[slot]) throw Error(SMG_EINVAL, "slot is not in use");
   if (B->act[slot]) throw Error(SMG_EINVAL, "slot is still running");
   hipStream_t st = (hipStream_t)stream;
+  B->note(st);
   if (x)
     HIPCHECK(hipMemcpyAsync(x, B->x + (size_t)slot * B->n, B->n * sizeof(z64), hipMemcpyDeviceToDevice, st));
   batch_clear(*B, slot, st);
@@ -2854,6 +2930,7 @@ int smg_batch_cancel(smg_batch b, int32_t slot, void* stream) {
   if (slot < 0 || slot >= B->cap || !B->used[slot]) throw Error(SMG_EINVAL, "slot is not in use");
   B->used[slot] = 0;
   B->act[slot] = 0;
+  B->note((hipStream_t)stream);
   batch_clear(*B, slot, (hipStream_t)stream);
   batch_upload_active(*B, (hipStream_t)stream);
   return SMG_OK;
@@ -2888,7 +2965,11 @@ int smg_batch_memory_bytes(smg_batch b, size_t* bytes) {
 void smg_batch_destroy(smg_batch b) {
   if (!b) return;
   Batch* B = reinterpret_cast<Batch*>(b);
-  (void)hipStreamSynchronize(B->c->st);
+  // only the batch's own calls touched its memory: once their streams are idle the
+  // arena can go back to the allocator without waiting for the rest of the device
+  for (hipStream_t s : B->seen) (void)hipStreamSynchronize(s);
+  if (B->gs) (void)hipStreamSynchronize(B->gs);
+  B->pool.owner_synced = true;
   delete B;
 }
 

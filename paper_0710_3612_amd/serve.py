@@ -158,10 +158,25 @@ class SetupCache:
         self.setups = 0
         self.derives = 0
         self.evictions = 0
+        # seconds spent in setups, derives, evictions (closing hierarchies and batches)
+        # and trims, summed over the threads that ran them
+        self.times = collections.Counter()
+
+    def _time(self, name: str, t0: float):
+        dt = time.perf_counter() - t0
+        with self.lock:
+            self.times[name] += dt
 
     def _evict_for(self, need: int) -> bool:
         # least recently used first; hierarchies derived from another mass (cheap to
         # derive again) before full setups (a field's adaptive setup costs far more)
+        t0 = time.perf_counter()
+        try:
+            return self._evict_lru(need)
+        finally:
+            self.times["evict_s"] += time.perf_counter() - t0  # called under the lock
+
+    def _evict_lru(self, need: int) -> bool:
         for bases in (False, True):
             for key in list(self.entries.keys()):
                 if self.used + need <= self.budget:
@@ -215,18 +230,22 @@ class SetupCache:
                 self.used += need
                 build = True
         if build and evicted and hasattr(self.backend, "trim"):
+            t0 = time.perf_counter()
             self.backend.trim()  # memory the evicted hierarchies held goes back to the device
+            self._time("trim_s", t0)
         if not build:
             e.ready.wait()
             if e.failed is not None:
                 self.release(field, mass)
                 raise e.failed
             return e.solver
+        t0 = time.perf_counter()
         try:
             if src is not None:
                 solver = self.backend.derive(self.entries[src].solver, float(mass), stream)
             else:
                 solver = self.backend.setup(field, float(mass), stream)
+            self._time("derive_s" if src is not None else "setup_s", t0)
         except BaseException as exc:
             with self.lock:
                 e.failed = exc
@@ -265,7 +284,10 @@ class SetupCache:
             e.bytes += need
             self.used += need
         if evicted and hasattr(self.backend, "trim"):
+            t0 = time.perf_counter()
             self.backend.trim()
+            self._time("trim_s", t0)
+        t0 = time.perf_counter()
         try:
             batch = make()
         except BaseException:
@@ -273,6 +295,7 @@ class SetupCache:
                 e.bytes -= need
                 self.used -= need
             raise
+        self._time("batch_create_s", t0)
         with self.lock:
             e.batch = batch
             actual = e.solver.memory_bytes() + batch.memory_bytes()
@@ -291,7 +314,9 @@ class SetupCache:
             actual = e.solver.memory_bytes()
             self.used += actual - e.bytes
             e.bytes = actual
+        t0 = time.perf_counter()
         batch.close()
+        self._time("batch_close_s", t0)
 
     def settle(self, field, mass: float, actual: int):
         """Replace the estimate of a resident entry by its measured bytes."""
@@ -335,6 +360,7 @@ class _Lane:
             self.thread = threading.Thread(target=self._run, daemon=True, name=f"lane-{field}-{mass}")
         self.solver = None
         self.batch = None
+        self.cap = server.capacity  # slots of this lane's batch (Server.batch_capacity)
         self.stream = server._take_stream()
 
     def push(self, res: Result, req: Request):
@@ -372,6 +398,7 @@ class _Lane:
         srv = self.server
         be = srv.backend
         ctx = be.stream_context(self.stream)
+        t_start = time.perf_counter()
         with ctx:
             try:
                 while True:
@@ -381,11 +408,16 @@ class _Lane:
                     if self.stop:
                         return
                     time.sleep(srv.poll_sleep)
+                t_acq = time.perf_counter()
+                srv._lane_time("acquire_s", t_acq - t_start)
                 # the key's batch lives while the lane does: idle keys keep only their hierarchy
-                make = lambda: be.new_batch(self.solver, srv.capacity, srv.tol, srv.maxiter,  # noqa: E731
+                with self.cv:
+                    want = len(self.pending)
+                self.cap = srv.batch_capacity(want)
+                make = lambda: be.new_batch(self.solver, self.cap, srv.tol, srv.maxiter,  # noqa: E731
                                             srv.precision, self.stream)
                 while True:
-                    self.batch = srv.cache.open_batch(self.field, self.mass, srv.capacity, make)
+                    self.batch = srv.cache.open_batch(self.field, self.mass, self.cap, make)
                     if self.batch is not None:
                         break
                     if self.stop:
@@ -393,6 +425,7 @@ class _Lane:
                         self.solver = None
                         return
                     time.sleep(srv.poll_sleep)
+                srv._lane_time("open_batch_s", time.perf_counter() - t_acq)
             except Exception as exc:  # setup failed: fail what is queued here
                 self._fail(f"setup: {exc}")
                 if self.solver is not None:
@@ -400,11 +433,14 @@ class _Lane:
                     self.solver = None
                 srv._lane_done(self)
                 return
+            t_serve = time.perf_counter()
             try:
                 self._serve()
             except Exception as exc:
                 self._fail(f"solve: {exc}")
             finally:
+                t_end = time.perf_counter()
+                srv._lane_time("serve_s", t_end - t_serve)
                 try:
                     srv.cache.close_batch(self.field, self.mass)
                 except Exception:
@@ -413,20 +449,27 @@ class _Lane:
                 srv.cache.release(self.field, self.mass)
                 self.solver = None
                 srv._lane_done(self)
+                srv._lane_time("close_s", time.perf_counter() - t_end)
+                srv._lane_time("lanes", 1)
 
     def _serve(self):
         srv = self.server
         be = srv.backend
         while True:
+            idle = 0.0
             with self.cv:
                 if not self.pending and not self.slots and not self.stop:
+                    t_idle = time.perf_counter()
                     self.cv.wait(timeout=srv.poll_sleep * 10)
+                    idle = time.perf_counter() - t_idle
                 has_work = bool(self.pending or self.slots)
                 stop = self.stop
                 todo = []
-                free = srv.capacity - len(self.slots)
+                free = self.cap - len(self.slots)
                 while self.pending and len(todo) < free:
                     todo.append(self.pending.popleft())
+            if idle:
+                srv._lane_time("idle_s", idle)  # takes the server lock: never under self.cv
             if not has_work:
                 if stop or srv._want_retire(self):  # takes the server lock: never under self.cv
                     return
@@ -448,8 +491,11 @@ class _Lane:
                     break
                 self.slots[slot] = (res, j)
             if self.slots:
+                t_step = time.perf_counter()
                 self.batch.step(srv.iters_per_step, self.stream)
-                for slot, st in self.batch.poll():
+                polled = self.batch.poll()
+                srv._lane_time("step_poll_s", time.perf_counter() - t_step)
+                for slot, st in polled:
                     res, j = self.slots.pop(slot)
                     self.batch.harvest(slot, res.x[j], self.stream)
                     res.status[j] = st["status"]
@@ -472,10 +518,16 @@ class Server:
 
     def __init__(self, backend, budget_bytes: int, capacity: int = 16, tol: float = 1e-10, maxiter: int = 5000,
                  precision: int = 1, max_lanes: int = 8, iters_per_step: int = 1, poll_sleep: float = 0.0005,
-                 linger: float = 0.5, keep_solutions: bool = True):
+                 linger: float = 0.5, keep_solutions: bool = True, fit_capacity: bool = False,
+                 min_capacity: int = 4):
         self.backend = backend
         self.cache = SetupCache(backend, budget_bytes)
         self.capacity = int(capacity)
+        # fit_capacity: a lane's batch gets the smallest power of two >= min_capacity
+        # that holds the right-hand sides queued for its key when it opens (at most
+        # `capacity`), so that small requests do not hold a full batch of memory
+        self.fit_capacity = bool(fit_capacity)
+        self.min_capacity = max(1, int(min_capacity))
         self.tol = float(tol)
         self.maxiter = int(maxiter)
         self.precision = int(precision)
@@ -491,6 +543,9 @@ class Server:
         self.open = 0
         self.t0 = time.perf_counter()
         self.lanes_started = 0
+        # lane seconds by phase (acquire, open_batch, serve with its idle_s part, close)
+        # and the number of lanes that ended, summed over the lanes
+        self.lane_times = collections.Counter()
         self.streams: list = []
         # False: a finished request drops its right-hand sides and solutions (its
         # statistics stay), so that a long trace does not hold them all on the device
@@ -499,6 +554,28 @@ class Server:
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
+
+    def batch_capacity(self, want: int) -> int:
+        """Slots of a lane's batch when `want` right-hand sides wait for its key."""
+        if not self.fit_capacity:
+            return self.capacity
+        c = min(self.min_capacity, self.capacity)
+        while c < want and c < self.capacity:
+            c *= 2
+        return min(c, self.capacity)
+
+    def _lane_time(self, name: str, value: float):
+        with self.lock:
+            self.lane_times[name] += value
+
+    def phase_times(self) -> dict:
+        """Lane phases and cache work so far (seconds summed over threads; `lanes`
+        counts the lanes that ended)."""
+        with self.lock:
+            out = dict(self.lane_times)
+        with self.cache.lock:
+            out.update(self.cache.times)
+        return out
 
     # -- routing ---------------------------------------------------------------
     def submit(self, req: Request, arrival: Optional[float] = None) -> Result:

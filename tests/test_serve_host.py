@@ -319,3 +319,29 @@ def test_batches_live_with_lanes_and_are_accounted():
         assert srv.cache.used == 2 * 80
         assert all(e.batch is None for e in srv.cache.entries.values())
     check_results(reqs, results)
+
+
+def test_fitted_batch_capacity():
+    """With fit_capacity a lane's batch has the smallest power of two >= the minimum
+    that holds the right-hand sides queued for its key, at most `capacity`; a request
+    wider than that streams through the slots and every result is still right."""
+    be = FakeBackend()
+    caps = []
+    make = be.new_batch
+
+    def recording(solver, capacity, *a):
+        caps.append((solver.field, capacity))
+        return make(solver, capacity, *a)
+
+    be.new_batch = recording
+    srv = serve.Server(be, budget_bytes=10_000, capacity=16, fit_capacity=True, min_capacity=4)
+    assert [srv.batch_capacity(w) for w in (0, 1, 4, 5, 8, 9, 16, 40)] == [4, 4, 4, 8, 8, 16, 16, 16]
+    assert serve.Server(be, 10_000, capacity=16).batch_capacity(1) == 16  # fixed by default
+    assert serve.Server(be, 10_000, capacity=2, fit_capacity=True).batch_capacity(1) == 2
+    with srv:
+        reqs = make_requests([(1, 0.1, 1, 0.0), (2, 0.1, 6, 0.0), (3, 0.1, 13, 0.0), (4, 0.1, 30, 0.0)])
+        results = srv.run_trace(reqs, timeout=30)
+    check_results(reqs, results)
+    assert sorted(caps) == [(1, 4), (2, 8), (3, 16), (4, 16)]
+    times = srv.phase_times()
+    assert times["lanes"] == 4 and times["serve_s"] > 0 and times["batch_create_s"] >= 0
