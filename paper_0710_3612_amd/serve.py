@@ -269,13 +269,14 @@ class SetupCache:
         return solver
 
     def open_batch(self, field, mass: float, capacity: int, make: Callable[[], object]):
-        """The batch of a pinned key, made by make() when the key has none, its bytes
-        counted against the budget; None while the budget cannot make room for it."""
+        """A new batch for a pinned key, made by make(), its bytes counted against the
+        budget; None while the budget cannot make room for it, or while the key's
+        previous batch (another caller's) is not closed yet."""
         key = (field, float(mass))
         with self.lock:
             e = self.entries[key]
             if e.batch is not None:
-                return e.batch
+                return None
             need = self.backend.batch_estimate(field, capacity)
             ev0 = self.evictions
             if not self._evict_for(need):
@@ -603,16 +604,14 @@ class Server:
         lane.push(res, req)
 
     def _want_retire(self, lane: _Lane) -> bool:
-        """An idle lane leaves when others wait for a lane or it lingered long."""
+        """An idle lane leaves when others wait for a lane or it lingered long.  It
+        stays the key's lane until its batch is closed (_lane_done): a request for the
+        key that arrives meanwhile is queued on it and goes back to the waiting queue
+        then, so that no second lane of the key can reach the batch being closed."""
         with self.lock:
             if lane.pending or lane.slots:
                 return False
-            if self.waiting or time.perf_counter() - lane.last_busy > self.linger:
-                key = (lane.field, lane.mass)
-                if self.lanes.get(key) is lane:
-                    del self.lanes[key]
-                return True
-            return False
+            return bool(self.waiting) or time.perf_counter() - lane.last_busy > self.linger
 
     def _take_stream(self):
         with self.lock:

@@ -44,6 +44,7 @@ class FakeBatch:
 
     def admit(self, rhs, stream=None):
         assert not self.solver.closed
+        assert not self.closed, "batch used after close"
         for j in range(self.cap):
             if self.slots[j] is None:
                 steps = 1 + int(abs(rhs[0].real) * 3) % 4
@@ -52,6 +53,7 @@ class FakeBatch:
         return None
 
     def step(self, iters=1, stream=None):
+        assert not self.closed, "batch used after close"
         with self.be.lock:
             self.be.stepping += 1
             self.be.max_stepping = max(self.be.max_stepping, self.be.stepping)
@@ -74,6 +76,7 @@ class FakeBatch:
         self.slots[slot] = None
 
     def close(self):
+        time.sleep(self.be.batch_close_delay)
         self.closed = True
 
 
@@ -92,6 +95,7 @@ class FakeBackend:
         self.max_stepping = 0
         self.cache_ref = None
         self.max_used = 0
+        self.batch_close_delay = 0.0
 
     def _watch(self):
         if self.cache_ref is not None:
@@ -345,3 +349,35 @@ def test_fitted_batch_capacity():
     assert sorted(caps) == [(1, 4), (2, 8), (3, 16), (4, 16)]
     times = srv.phase_times()
     assert times["lanes"] == 4 and times["serve_s"] > 0 and times["batch_create_s"] >= 0
+
+
+def test_retiring_lane_keeps_its_key_until_its_batch_is_closed():
+    """A request for a key whose lane is retiring (between its decision to retire and
+    the close of its batch) waits for that lane to finish and then gets a lane and a
+    batch of its own: it never reaches the batch that is being closed."""
+    be = FakeBackend()
+    made = []
+    make = be.new_batch
+
+    def recording(solver, capacity, *a):
+        b = make(solver, capacity, *a)
+        made.append(b)
+        return b
+
+    be.new_batch = recording
+    with serve.Server(be, budget_bytes=10_000, capacity=4, linger=0.0) as srv:
+        close = srv.cache.close_batch
+
+        def slow_close(field, mass):  # the retiring lane is slow to reach the close
+            time.sleep(0.3)
+            close(field, mass)
+
+        srv.cache.close_batch = slow_close
+        first = make_requests([(1, 0.1, 2, 0.0)], seed=1)
+        check_results(first, srv.run_trace(first, timeout=30))
+        time.sleep(0.1)  # the idle lane (linger 0) has decided to retire and is not done
+        second = make_requests([(1, 0.1, 3, 0.0)], seed=2)
+        second[0].rid = 99
+        check_results(second, srv.run_trace(second, timeout=30))
+    assert len(made) == 2 and made[1] is not made[0]
+    assert all(b.closed for b in made)
