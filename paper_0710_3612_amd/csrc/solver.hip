@@ -1175,6 +1175,7 @@ void blocked_gauss_jordan(Ctx& c, z64* B, int n) {
                               c.st));
   }
   HIPCHECK(hipStreamSynchronize(c.st));  // the scratch buffers are freed on return
+  scratch.owner_synced = true;           // only this stream used them
 }
 
 // Dense inverse of the coarsest operator by Gauss-Jordan elimination (FP64).
@@ -1305,16 +1306,22 @@ void validate(const smg_params& p) {
 // New context with every device array allocated.  The fermion links come from
 // `gauge` (ABI layout) or are copied from `src_links` (already prepared).  A dry
 // context only counts the bytes of the same allocations (neither is read).
+// arena: bytes of the block that create and reserve_setup carve their arrays from
+// (setup_arena_bytes), so that building a hierarchy costs one allocator call for
+// them; 0: one allocation per array.  Arrays are rounded to 256 bytes either way, in
+// dry (planning) contexts too.
 Ctx* create(const double* gauge, const smg_params* prm, hipStream_t st, const z64* src_links = nullptr,
-            bool dry = false) {
+            bool dry = false, size_t arena = 0) {
   if ((!gauge && !src_links && !dry) || !prm) throw Error(SMG_EINVAL, "null gauge or params");
   validate(*prm);
   Ctx* c = new Ctx();
   try {
     c->pool.dry = dry;
     c->pool.stream = &c->st;
+    c->pool.gran = 256;
     c->prm = *prm;
     c->st = st;
+    if (!dry && arena) c->pool.open_arena(arena);
     c->nlev = prm->levels;
     const int lx = prm->lx, lt = prm->lt;
     const size_t V = (size_t)lx * lt;
@@ -1490,6 +1497,14 @@ void reserve_setup(Ctx& c, bool coefficients = true) {
     c.colk = c.pool.alloc<z64>(n);
     c.piv = c.pool.alloc<double>(1);
   }
+}
+
+// Bytes that create and reserve_setup(coefficients) allocate for these parameters,
+// from the same calls on a dry context.
+size_t setup_arena_bytes(const smg_params* prm, bool coefficients) {
+  std::unique_ptr<Ctx> d(create(nullptr, prm, nullptr, nullptr, true));
+  reserve_setup(*d, coefficients);
+  return d->pool.bytes;
 }
 
 // Every allocation of a solve of nrhs columns in `prec` (smg_solve, smg_cg).
@@ -2168,7 +2183,7 @@ int smg_setup(const double* gauge, const smg_params* params, const double* rando
   API_BEGIN
   if (!out) throw Error(SMG_EINVAL, "null output handle");
   hipStream_t st = (hipStream_t)stream;
-  Ctx* c = create(gauge, params, st);
+  Ctx* c = create(gauge, params, st, nullptr, false, params ? setup_arena_bytes(params, true) : 0);
   try {
     reserve_setup(*c);
     // The random starts and the Krylov vectors of the setup cycles' coarse CG live
@@ -2215,7 +2230,7 @@ int smg_setup_from_vectors(const double* gauge, const smg_params* params, const 
   API_BEGIN
   if (!out || !vectors || !calib) throw Error(SMG_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  Ctx* c = create(gauge, params, st);
+  Ctx* c = create(gauge, params, st, nullptr, false, params ? setup_arena_bytes(params, true) : 0);
   try {
     reserve_setup(*c);
     for (int l = 0; l + 1 < c->nlev; ++l) {
@@ -2273,7 +2288,7 @@ int smg_derive(smg_handle h, double mass, void* stream, smg_handle* out) {
   // on another stream meanwhile; its stream field is not touched.
   smg_params prm = src->prm;
   prm.mass = mass;
-  Ctx* c = create(nullptr, &prm, st, src->U64);
+  Ctx* c = create(nullptr, &prm, st, src->U64, false, setup_arena_bytes(&prm, false));
   try {
     reserve_setup(*c, false);  // a derived handle keeps no mass coefficients of its own
     for (int l = 0; l + 1 < c->nlev; ++l) {
