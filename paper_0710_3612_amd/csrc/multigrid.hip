@@ -1820,35 +1820,42 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows(const TM* __restrict__ 
 }
 
 // k_dense_rows for n % 4 == 0: each lane reads four consecutive entries of the row
-// (and of x) per load, and up to G such quads per lane are in flight together, so a
-// row of n <= 4096 FP16 entries takes at most two round trips instead of six.
+// (and of x) per load, and up to G such quads per lane are in flight together.  A
+// wave takes RW consecutive rows and loads each quad of x once for all of them.
+// Every lane adds its entries of a row in increasing order and masked (clamped)
+// entries add an exact zero, so a row's result does not depend on G or RW.
 template <typename T>
 struct alignas(4 * sizeof(T)) Quad {
   T e[4];
 };
 
-template <typename RM, typename R, typename TM, int G>
+template <typename RM, typename R, typename TM, int G, int RW>
 __global__ void __launch_bounds__(kThreads) k_dense_rows4(const TM* __restrict__ M, const cpx<R>* __restrict__ x,
                                                           cpx<R>* __restrict__ y, int n, double mscale, Grp g) {
   if (g.op) {  // grouped: this column's system
     M = static_cast<const TM*>(g.op[blockIdx.y]);
     mscale = g.s[blockIdx.y];
   }
-  const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int row0 = (blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * RW;
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  if (row0 >= n) return;
   const int nq = n / 4;
-  const Quad<TM>* Mr = reinterpret_cast<const Quad<TM>*>(M + (size_t)row * n);
+  const Quad<TM>* Mr[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) Mr[r] = reinterpret_cast<const Quad<TM>*>(M + (size_t)min(row0 + r, n - 1) * n);
   const Quad<cpx<R>>* xb = reinterpret_cast<const Quad<cpx<R>>*>(x + (size_t)blockIdx.y * n);
-  double re = 0, im = 0;
+  double re[RW], im[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) re[r] = im[r] = 0;
   for (int q0 = lane; q0 < nq; q0 += 64 * G) {
-    Quad<TM> m[G];
+    Quad<TM> m[RW][G];
     Quad<cpx<R>> v[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       const int q = min(q0 + 64 * u, nq - 1);  // clamped: all loads of the group in flight together
-      m[u] = Mr[q];
       v[u] = xb[q];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) m[r][u] = Mr[r][q];
     }
     __builtin_amdgcn_sched_barrier(0);  // keeps every load of the group ahead of the first product
 #pragma unroll
@@ -1856,18 +1863,23 @@ __global__ void __launch_bounds__(kThreads) k_dense_rows4(const TM* __restrict__
       const bool dup = q0 + 64 * u >= nq;  // a clamped duplicate contributes nothing
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const cpx<RM> a = widen(m[u].e[e]);
         const cpx<R> b = dup ? mk<R>(0, 0) : v[u].e[e];
-        re = fma((double)a.re, (double)b.re, re);
-        re = fma(-(double)a.im, (double)b.im, re);
-        im = fma((double)a.re, (double)b.im, im);
-        im = fma((double)a.im, (double)b.re, im);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          const cpx<RM> a = widen(m[r][u].e[e]);
+          re[r] = fma((double)a.re, (double)b.re, re[r]);
+          re[r] = fma(-(double)a.im, (double)b.im, re[r]);
+          im[r] = fma((double)a.re, (double)b.im, im[r]);
+          im[r] = fma((double)a.im, (double)b.re, im[r]);
+        }
       }
     }
   }
-  re = wave_sum(re);
-  im = wave_sum(im);
-  if (lane == 0) y[(size_t)blockIdx.y * n + row] = mk<R>((R)(mscale * re), (R)(mscale * im));
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const double sr = wave_sum(re[r]), si = wave_sum(im[r]);
+    if (lane == 0 && row0 + r < n) y[(size_t)blockIdx.y * n + row0 + r] = mk<R>((R)(mscale * sr), (R)(mscale * si));
+  }
 }
 
 // The kernel is chosen by n alone, so a column's result never depends on nrhs.
@@ -2039,21 +2051,32 @@ template <typename RM, typename R, typename TM>
 void launch_dense_apply_t(const TM* M, double mscale, const cpx<R>* x, cpx<R>* y, int n, int nrhs, hipStream_t st,
                           const Grp& grp = Grp{}) {
   if (grp.op && n > kDenseRowsMax) throw Error(-1, "grouped coarsest apply needs n <= 4096");
-  if (n <= kDenseRowsMax && n % 4 == 0) {
+  if (n <= kDenseRowsMax && n % 4 == 0 && sizeof(TM) <= sizeof(z32)) {
+    // FP16 or FP32 M: two rows per wave share the loads of x; groups of up to six
+    // quads per row keep both rows' loads in flight (about 120 registers, four waves
+    // per SIMD)
+    const int want = (n / 4 + 63) / 64;
+    const dim3 g((n + 7) / 8, nrhs);
+    if (want <= 4)
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4, 2>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
+    else
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (sizeof(TM) <= sizeof(hfc) ? 6 : 4), 2>), g, dim3(kThreads), 0,
+                         st, M, x, y, n, mscale, grp);
+  } else if (n <= kDenseRowsMax && n % 4 == 0) {
     // quads in flight per lane: all of a row of n <= 4096 in one group where registers allow
     constexpr int W = (int)((sizeof(TM) + sizeof(cpx<R>)) / 4);  // registers per entry pair
     constexpr int GMAX = W <= 3 ? 16 : (W <= 4 ? 8 : 4);
     const int want = (n / 4 + 63) / 64;
     const dim3 g((n + 3) / 4, nrhs);
     if (want <= 4 || GMAX == 4)
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 4, 1>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
     else if (want <= 8 || GMAX == 8)
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 8>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, 8, 1>), g, dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
     else if (want <= 12)
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 12 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 12 : 8), 1>), g, dim3(kThreads), 0, st, M, x, y, n,
                          mscale, grp);
     else
-      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 16 : 8)>), g, dim3(kThreads), 0, st, M, x, y, n,
+      hipLaunchKernelGGL((k_dense_rows4<RM, R, TM, (GMAX > 8 ? 16 : 8), 1>), g, dim3(kThreads), 0, st, M, x, y, n,
                          mscale, grp);
   } else if (n <= kDenseRowsMax) {
     hipLaunchKernelGGL((k_dense_rows<RM, R, TM>), dim3((n + 3) / 4, nrhs), dim3(kThreads), 0, st, M, x, y, n, mscale, grp);
