@@ -308,7 +308,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), 100, stream)
     flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
     mfma = dict(kernel=f"coarse operator on the matrix cores (k_coarse_mfma), {cx}x{ct} sites, nc={nc}, "
-                       f"{MRHS_NRHS} RHS, FP32", bound="mfma", achieved=flops / dur / 1e12, peak=157.3,
+                       f"{MRHS_NRHS} RHS, FP32 arithmetic on the FP16 copy of the links (power-of-two scale)",
+                bound="mfma", achieved=flops / dur / 1e12, peak=157.3,
                 unit="TFLOP/s", frac=flops / dur / 1e12 / 157.3, avg_launch_us=dur * 1e6, flops_per_launch=flops)
     # the same operator in FP64 (the plain solve's) on the FP64 matrix cores
     v64 = torch.randn(MRHS_NRHS * nl, dtype=torch.complex128, device=dev)
@@ -327,7 +328,7 @@ def mrhs_leg(args, torch, smg, dev, U):
                           f"(lambda_min/lambda_max {ratio:.1e}), {MRHS_NRHS} Z2-noise sources (rhs = D^H eta), "
                           f"3 levels 4x4, Nv=16, nu={NU}, dense coarsest inverse, tol {TOL:g}; mixed: FP32 inner "
                           f"MG-CG, BF16 storage of the fine smoother iterates, FP16 storage of the prolongators, "
-                          f"coarse links on the FP32 matrix cores, the coarsest inverse applied in FP64; FP64: "
+                          f"FP16-stored coarse links on the FP32 matrix cores, the coarsest inverse applied in FP64; FP64: "
                           f"coarse links and the coarsest inverse on the FP64 matrix cores"),
                 setup_s=setup_s, mixed=out["mixed"], fp64=out["fp64"],
                 mixed_over_fp64=out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], mfma=mfma,
@@ -940,9 +941,10 @@ def dslash_probe(Ld, reps):
                           copy_write_bytes=b.numel() * 4)))
 
 
-def mfma_probe(reps):
+def mfma_probe(reps, f16=False):
     """Launch only the matrix-core coarse operator (512^2 hierarchy, level 1: 128^2 sites,
-    nc = 16, 32 RHS) for profiler runs; prints its event-timed rate."""
+    nc = 16, 32 RHS; FP32 links, or with f16 the FP16 copy of the links) for profiler
+    runs; prints its event-timed rate."""
     import ctypes
 
     import numpy as np
@@ -955,7 +957,8 @@ def mfma_probe(reps):
     U = synth.links_from_angles(synth.metropolis_u1(MRHS_L, MRHS_L, BETA, 20, MRHS_SEED))
     p = smg.make_params(MRHS_L, MRHS_L, 0.0, levels=3, blocks=[(4, 4), (4, 4)], nv=MRHS_NV, setup_iters=0,
                         smoother_steps=NU, smoother_omega=OMEGA, seed=MRHS_SEED, sa_scale=SA_SCALE,
-                        coarsest=smg.COARSEST_CG, mfma_min_rhs=16)
+                        coarsest=smg.COARSEST_CG, mfma_min_rhs=16,
+                        operator_storage=smg.STORE_F16 if f16 else smg.STORE_F32)
     s = smg.Solver(torch.from_numpy(np.ascontiguousarray(U)).to(dev), p)
     cx, ct, nc = s.level_info(1)
     v = torch.randn(MRHS_NRHS * cx * ct * nc, dtype=torch.complex64, device=dev)
@@ -967,9 +970,10 @@ def mfma_probe(reps):
     px, py, nul = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p()
     dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), reps, stream)
     flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
-    print(json.dumps(dict(kernel="k_coarse_mfma", sites=cx * ct, nc=nc, nrhs=MRHS_NRHS, avg_launch_us=dur * 1e6,
+    print(json.dumps(dict(kernel="k_coarse_mfma", links="FP16 (scaled)" if f16 else "FP32", sites=cx * ct, nc=nc,
+                          nrhs=MRHS_NRHS, avg_launch_us=dur * 1e6,
                           tflops=flops / dur / 1e12, frac=flops / dur / 1e12 / 157.3,
-                          link_bytes=9 * nc * nc * 8 * cx * ct)))
+                          link_bytes=9 * nc * nc * (4 if f16 else 8) * cx * ct)))
 
 
 def main():
@@ -1004,6 +1008,7 @@ def main():
     ap.add_argument("--c5-inverse-iters", type=int, default=6,
                     help="block inverse iterations for the 2048^2 leg's spectral ratio")
     ap.add_argument("--mfma-probe", action="store_true", help="only launch the matrix-core coarse operator")
+    ap.add_argument("--probe-f16", action="store_true", help="--mfma-probe on the FP16 copy of the links")
     ap.add_argument("--dslash-probe", type=int, default=0, metavar="L",
                     help="only launch the fine FP64 A at L x L and a 64 MiB copy (for profiler runs)")
     ap.add_argument("--solves-only", action="store_true",
@@ -1015,7 +1020,7 @@ def main():
         kernel_probe(args.dslash_reps)
         return 0
     if args.mfma_probe:
-        mfma_probe(args.dslash_reps)
+        mfma_probe(args.dslash_reps, args.probe_f16)
         return 0
     if args.dslash_probe:
         dslash_probe(args.dslash_probe, args.dslash_reps)

@@ -238,6 +238,9 @@ void launch_coarse_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx,
 // Matrix-core (MFMA FP32) coarse apply for 1 <= nc <= 16, any number of right-hand sides.
 void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                         z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
+// The same reading links stored in FP16 scaled by 1 / lscale (FP32 arithmetic).
+void launch_coarse_mfma_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs,
+                            int mode, double c, z32* xacc, const z32* aux, hipStream_t st, double c2 = 0);
 // FP64 multi-RHS coarse operator on the matrix cores (1 <= nc <= 16).
 void launch_coarse_mfma64(const z64* L, const z64* x, z64* y, int cx, int ct, int nc, int nrhs, int mode, double c,
                           z64* xacc, const z64* aux, hipStream_t st, double c2 = 0);

@@ -1305,11 +1305,14 @@ __device__ inline int xcd_tile(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <int MODE, int TX, int TT, int NW, int S>
-__global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__ L, const z32* __restrict__ v,
+// TL: link storage, z32, or hfc (FP16 scaled by 1 / lscale, a power of two: the
+// links widen to FP32 exactly in registers and the sums are scaled exactly at the
+// end, so the arithmetic is FP32 in both cases and the link stream is halved).
+template <int MODE, int TX, int TT, int NW, int S, typename TL = z32>
+__global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const TL* __restrict__ L, const z32* __restrict__ v,
                                                         z32* __restrict__ y, int cx, int ct, int nc, int nrhs,
                                                         float c, float c2, z32* __restrict__ xacc,
-                                                        const z32* __restrict__ aux, int pairs) {
+                                                        const z32* __restrict__ aux, int pairs, float lscale) {
   // S = ceil(nc / 2): MFMA pairs per link direction and staged column pairs.  It is
   // a compile-time constant so that the loads below are straight-line code (loads
   // under branches make the compiler drain every outstanding load before an MFMA).
@@ -1380,10 +1383,10 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   const int nvalid = vx * vt;
   const int mine = nvalid > w ? (nvalid - w + NW - 1) / NW : 0;
   if (mine == 0) return;  // wave-uniform, and no barrier follows
-  auto load_links = [&](int k, int D, z32* dst) {
+  auto load_links = [&](int k, int D, TL* dst) {
     const int idx = w + k * NW;
     const int ox = idx % vx, ot = idx / vx;
-    const z32* LD = L + (size_t)D * nc * n + (size_t)((t0 + ot) * cx + x0 + ox) * nc + rowc;
+    const TL* LD = L + (size_t)D * nc * n + (size_t)((t0 + ot) * cx + x0 + ox) * nc + rowc;
 #pragma unroll
     for (int sp = 0; sp < S; ++sp) {
       const int cc = 2 * sp + h;
@@ -1398,11 +1401,11 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   // exactly the loads each step needs.
   constexpr int MAXS = (TX * TT + NW - 1) / NW;
   const int last = 9 * mine - 1;
-  auto load_step = [&](int q, z32* dst) {
+  auto load_step = [&](int q, TL* dst) {
     q = min(q, last);
     load_links(q / 9, q - 9 * (q / 9), dst);
   };
-  z32 lb[3][S];
+  TL lb[3][S];
   load_step(0, lb[0]);
   load_step(1, lb[1]);
   load_step(2, lb[2]);
@@ -1424,7 +1427,7 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
       for (int sp = 0; sp < S; ++sp) b[sp] = VB[(2 * sp + h) * kMfmaRS];
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
-        const z32 l = lb[D % 3][sp];
+        const z32 l = widen(lb[D % 3][sp]);
         const bool ok = row_ok && (2 * sp + h < nc);
         const float a_re = ok ? (upper ? l.im : l.re) : 0.f;
         const float a_im = ok ? (upper ? l.re : -l.im) : 0.f;
@@ -1450,7 +1453,7 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
     for (int r = 0; r < 8; ++r) {
       const int dof = 8 * (r >> 2) + 4 * h + (r & 3);
       if (dof >= nc) continue;
-      const z32 sum = mk<float>(acc[k][r], acc[k][r + 8]);
+      const z32 sum = lscale * mk<float>(acc[k][r], acc[k][r + 8]);  // exact: a power of two
       const size_t o = ob + dof;
       if (MODE == 0) {
         y[o] = sum;
@@ -1471,46 +1474,57 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const z32* __restrict__
   }
 }
 
-template <int TX, int TT, int NW, int S>
-void launch_coarse_mfma_t(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                          double c2, z32* xacc, const z32* aux, hipStream_t st) {
+template <int TX, int TT, int NW, int S, typename TL>
+void launch_coarse_mfma_t(const TL* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs,
+                          int mode, double c, double c2, z32* xacc, const z32* aux, hipStream_t st) {
   const int tiles = ((cx + TX - 1) / TX) * ((ct + TT - 1) / TT);
   dim3 grid((unsigned)tiles, (unsigned)((nrhs + 31) / 32));
   // 16-byte loads of column pairs need an even nc and a 16-byte aligned input
   const int pairs = (nc % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
   with_mode(mode, [&](auto m) {
-    hipLaunchKernelGGL((k_coarse_mfma<decltype(m)::v, TX, TT, NW, S>), grid, dim3(NW * 64), 0, st, L, x, y, cx, ct,
-                       nc, nrhs, (float)c, (float)c2, xacc, aux, pairs);
+    hipLaunchKernelGGL((k_coarse_mfma<decltype(m)::v, TX, TT, NW, S, TL>), grid, dim3(NW * 64), 0, st, L, x, y, cx,
+                       ct, nc, nrhs, (float)c, (float)c2, xacc, aux, pairs, lscale);
   });
   HIPCHECK(hipGetLastError());
 }
 
-template <int TX, int TT, int NW>
-void launch_coarse_mfma_s(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                          double c2, z32* xacc, const z32* aux, hipStream_t st) {
+template <int TX, int TT, int NW, typename TL>
+void launch_coarse_mfma_s(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
+                          double c, double c2, z32* xacc, const z32* aux, hipStream_t st) {
   switch ((nc + 1) / 2) {
-    case 1: launch_coarse_mfma_t<TX, TT, NW, 1>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 2: launch_coarse_mfma_t<TX, TT, NW, 2>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 3: launch_coarse_mfma_t<TX, TT, NW, 3>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 4: launch_coarse_mfma_t<TX, TT, NW, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 5: launch_coarse_mfma_t<TX, TT, NW, 5>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 6: launch_coarse_mfma_t<TX, TT, NW, 6>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    case 7: launch_coarse_mfma_t<TX, TT, NW, 7>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
-    default: launch_coarse_mfma_t<TX, TT, NW, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 1: launch_coarse_mfma_t<TX, TT, NW, 1>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 2: launch_coarse_mfma_t<TX, TT, NW, 2>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 3: launch_coarse_mfma_t<TX, TT, NW, 3>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 4: launch_coarse_mfma_t<TX, TT, NW, 4>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 5: launch_coarse_mfma_t<TX, TT, NW, 5>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 6: launch_coarse_mfma_t<TX, TT, NW, 6>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    case 7: launch_coarse_mfma_t<TX, TT, NW, 7>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
+    default: launch_coarse_mfma_t<TX, TT, NW, 8>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st); break;
   }
 }
 
 // 4x4 tiles (8 waves, 152 KB of LDS) where they fill the chip; on small coarse
 // lattices 2x2 tiles (4 waves, 68 KB) give four times the workgroups (measured on
 // MI355X: 32^2 sites, 32 RHS: 14 us vs 35 us; 128^2 sites: 4x4 ahead by 9%).
-void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
-                        z32* xacc, const z32* aux, hipStream_t st, double c2) {
+template <typename TL>
+void launch_coarse_mfma_l(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
+                          double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
   if (nc < 1 || nc > 16) throw Error(-1, "matrix-core coarse apply needs 1 <= nc <= 16");
   const long tiles44 = (long)((cx + 3) / 4) * ((ct + 3) / 4);
   if (tiles44 < 256)
-    launch_coarse_mfma_s<2, 2, 4>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
+    launch_coarse_mfma_s<2, 2, 4>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else
-    launch_coarse_mfma_s<4, 4, 8>(L, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
+    launch_coarse_mfma_s<4, 4, 8>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
+}
+
+void launch_coarse_mfma(const z32* L, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode, double c,
+                        z32* xacc, const z32* aux, hipStream_t st, double c2) {
+  launch_coarse_mfma_l<z32>(L, 1.0f, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st, c2);
+}
+
+void launch_coarse_mfma_h16(const hfc* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs,
+                            int mode, double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
+  launch_coarse_mfma_l<hfc>(L, lscale, x, y, cx, ct, nc, nrhs, mode, c, xacc, aux, st, c2);
 }
 
 // ---------------------------------------------------------------------------

@@ -519,7 +519,11 @@ void apply_op(Ctx& c, Level<R>& lv, const cpx<R>* x, cpx<R>* y, int nrhs, int mo
   }
   if constexpr (std::is_same<R, float>::value) {
     if (!c.grp && use_mfma(c, lv.dof, nrhs)) {
-      launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
+      if (lv.L16)
+        launch_coarse_mfma_h16(lv.L16, lv.lscale, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st,
+                               coef2);
+      else
+        launch_coarse_mfma(lv.L, x, y, lv.lx, lv.lt, lv.dof, nrhs, mode, coef, xacc, aux, c.st, coef2);
       return;
     }
     if (lv.L16) {

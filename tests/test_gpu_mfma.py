@@ -81,6 +81,9 @@ def hier(request):
     p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, mfma_min_rhs=0,
                         operator_storage=smg.STORE_F16)
     out["h16"] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
+    p = smg.make_params(lx, lt, m, levels=len(blocks) + 1, blocks=blocks, nv=nvs, mfma_min_rhs=1,
+                        operator_storage=smg.STORE_F16)
+    out["mfma16"] = smg.Solver(dev(U), p, vectors=vv, calib=cc)
     yield dict(h=h, A=A, U=U, m=m, nlev=len(blocks) + 1, **out)
     for s in out.values():
         s.close()
@@ -173,6 +176,45 @@ def test_fp16_link_coarse_modes(hier, nrhs):
         assert colerr(y1, x64 - coef * Ax) <= TOL16, (level, "mode 1")
         assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (level, "mode 1 acc")
         assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL16, (level, "mode 2")
+
+
+@pytest.mark.parametrize("nrhs", [32, 45])
+def test_fp16_link_mfma_coarse_modes(hier, nrhs):
+    """Matrix-core coarse operator reading the FP16 links (scaled by a power of two,
+    FP32 arithmetic): every mode within TOL16 of the oracle's FP64 operator, and
+    within TOL32 of the vector-ALU kernel that reads the same FP16 links (so a wrong
+    scale, layout or column pairing of the FP16 stream cannot hide in TOL16)."""
+    import torch
+
+    for level in range(1, hier["nlev"]):
+        Ac = hier["h"].levels[level].A
+        n = Ac.shape[0]
+        rng = np.random.default_rng(level * 2000 + nrhs)
+        x = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        aux = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        acc0 = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+        coef = 0.37
+        x64 = x.astype(np.complex128)
+        Ax = np.stack([Ac @ x64[j] for j in range(nrhs)])
+        s = hier["mfma16"]
+        xt = dev(x, np.complex64)
+        y0 = host(s.level_op_f32(level, xt, mode=0)).reshape(nrhs, n)
+        xacc = dev(acc0, np.complex64)
+        y1 = host(s.level_op_f32(level, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
+        a1 = host(xacc).reshape(nrhs, n)
+        y2 = host(s.level_op_f32(level, xt, mode=2, aux=dev(aux, np.complex64))).reshape(nrhs, n)
+        xacc3 = dev(acc0, np.complex64)
+        y3 = host(s.level_op_f32(level, xt, mode=3, coef=coef, xacc=xacc3)).reshape(nrhs, n)
+        a3 = host(xacc3).reshape(nrhs, n)
+        v0 = host(hier["h16"].level_op_f32(level, xt, mode=0)).reshape(nrhs, n)
+        torch.cuda.synchronize()
+        assert colerr(y0, Ax) <= TOL16, (level, "mode 0")
+        assert colerr(y1, x64 - coef * Ax) <= TOL16, (level, "mode 1")
+        assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (level, "mode 1 acc")
+        assert colerr(y2, aux.astype(np.complex128) - Ax) <= TOL16, (level, "mode 2")
+        assert colerr(y3, x64 - coef * Ax) <= TOL16, (level, "mode 3")
+        assert colerr(a3, coef * x64) <= TOL32, (level, "mode 3 acc")
+        assert colerr(y0, v0.astype(np.complex128)) <= TOL32, (level, "against the vector-ALU FP16 kernel")
 
 
 TOL64 = 1e-12  # FP64 inputs and links; sums of at most 9 * 16 complex products
