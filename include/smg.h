@@ -472,7 +472,7 @@ int smg_set_progress(smg_progress_fn fn, void* ctx);
 
 /* Device bytes the library will hold for a hierarchy with these parameters,
  * computed on the host from the allocation plan that the calls themselves follow
- * (no device call):
+ * (no device call; every array counted rounded up to 256 bytes, as allocated):
  *   setup_bytes  smg_memory_bytes of a handle right after smg_setup or
  *                smg_setup_from_vectors (smg_derive: the same, less the mass
  *                coefficients that remass_affine keeps, 3 x 144 nc^2 bytes per
