@@ -1474,6 +1474,183 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const TL* __restrict__ 
   }
 }
 
+// The same operator for large coarse lattices, walking down strips of rows: a
+// workgroup owns a strip 4 sites wide and `seg` rows of it and keeps a rolling window
+// of four rows of V (the two rows it computes and the rows above and below, 4 x 6
+// sites with the ring, 101 KB of LDS) as [row slot][site][c][rhs].  Each step computes
+// two rows (one site per wave) while the next two rows are requested into registers
+// (24 per thread), and writes them over the two rows no longer needed between two
+// barriers, so the staging of V runs under the MFMAs instead of before them.  The
+// link ring continues from step to step.  A site's products, their order and the
+// epilogue are those of k_coarse_mfma, so the results are bitwise the same.
+constexpr int kTwRows = 2;  // rows per step
+
+template <int MODE, int S, typename TL>
+__global__ void __launch_bounds__(512) k_coarse_mfma_tw(const TL* __restrict__ L, const z32* __restrict__ v,
+                                                        z32* __restrict__ y, int cx, int ct, int nc, int nrhs,
+                                                        float c, float c2, z32* __restrict__ xacc,
+                                                        const z32* __restrict__ aux, int pairs, float lscale,
+                                                        int seg) {
+  constexpr int NW = 8, TXW = 4, HX = TXW + 2, NSLOT = kTwRows + 2, NT = NW * 64;
+  __shared__ float2 vs[NSLOT * HX * 16 * kMfmaRS];
+  const int nK = cx * ct;
+  const size_t n = (size_t)nK * nc;
+  const int rhs0 = blockIdx.y * 32;
+  const int ns = (cx + TXW - 1) / TXW;
+  // XCD k takes a contiguous band of segments (xcd_tile), so that the strips beside a
+  // strip, which read the same halo columns, run in the same L2
+  const int tl = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = tl % ns, segi = tl / ns;
+  const int x0 = strip * TXW;
+  const int r0 = segi * seg, r1 = min(ct, r0 + seg);
+  const int jmax = nrhs - rhs0 - 1;
+  // ---- staging of whole window rows: item = (rhs, row of the step, site in row, column
+  // pair); ROWS rows are one pass of ROWS * U1 loads per thread
+  constexpr int ITEMS_ROW = 32 * HX * S;
+  constexpr int U1 = (ITEMS_ROW + NT - 1) / NT;  // loads per thread and row (3 for nc = 16)
+  auto row_load = [&](int r, int u0, float4* buf) {  // unwrapped row r >= -1
+    const int gt = ((r % ct) + ct) % ct;
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int e0 = threadIdx.x + u * NT;
+      const int e = e0 < ITEMS_ROW ? e0 : ITEMS_ROW - 1;
+      const int pr = e % S;
+      const int rest = e / S;
+      const int hx = rest % HX, j = rest / HX;
+      const int gx = ((x0 + hx - 1) % cx + cx) % cx;
+      const int jc = j <= jmax ? j : jmax;
+      const z32* src = v + (size_t)(rhs0 + jc) * n + (size_t)(gt * cx + gx) * nc;
+      float4 t;
+      if (pairs) {
+        t = *reinterpret_cast<const float4*>(src + 2 * pr);
+      } else {
+        const z32 a0 = src[2 * pr];
+        const z32 a1 = src[min(2 * pr + 1, nc - 1)];
+        t = make_float4(a0.re, a0.im, a1.re, a1.im);
+      }
+      const bool live = j <= jmax;
+      const bool hi_ok = live && (2 * pr + 1 < nc);
+      buf[u0 + u] = make_float4(live ? t.x : 0.f, live ? t.y : 0.f, hi_ok ? t.z : 0.f, hi_ok ? t.w : 0.f);
+    }
+  };
+  auto row_store = [&](int r, int u0, const float4* buf) {
+    const int slot = (r + NSLOT) % NSLOT;
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int e0 = threadIdx.x + u * NT;
+      if (e0 >= ITEMS_ROW) continue;
+      const int pr = e0 % S;
+      const int rest = e0 / S;
+      const int hx = rest % HX, j = rest / HX;
+      const int d = ((slot * HX + hx) * 16 + 2 * pr) * kMfmaRS + j;
+      vs[d] = make_float2(buf[u0 + u].x, buf[u0 + u].y);
+      vs[d + kMfmaRS] = make_float2(buf[u0 + u].z, buf[u0 + u].w);
+    }
+  };
+  if (r0 >= ct) return;  // workgroup-uniform, before any barrier
+  {  // the first window: rows r0 - 1 .. r0 + 2
+    float4 fb[NSLOT * U1];
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) row_load(r0 - 1 + q, q * U1, fb);
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) row_store(r0 - 1 + q, q * U1, fb);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 31, h = lane >> 5;
+  const int row = i & 15;
+  const bool upper = i >= 16;
+  const int rowc = row < nc ? row : nc - 1;  // clamped: every lane loads a valid address
+  const bool row_ok = row < nc;
+  const int ox = w % TXW, orow = w / TXW;  // this wave's site in every step
+  const bool col_ok = x0 + ox < cx;
+  const int gxs = col_ok ? x0 + ox : cx - 1;
+  const int nsteps = (r1 - r0 + kTwRows - 1) / kTwRows;
+  // link loads of step q / 9, direction q % 9 (rows and columns clamped to valid sites)
+  auto load_step = [&](int q, TL* dst) {
+    const int st = q / 9, D = q - 9 * st;
+    const int gr = min(r0 + kTwRows * min(st, nsteps - 1) + orow, ct - 1);
+    const TL* LD = L + (size_t)D * nc * n + (size_t)(gr * cx + gxs) * nc + rowc;
+#pragma unroll
+    for (int sp = 0; sp < S; ++sp) {
+      const int cc = 2 * sp + h;
+      dst[sp] = LD[(size_t)(cc < nc ? cc : nc - 1) * n];  // masked where used, not here
+    }
+  };
+  TL lb[3][S];
+  load_step(0, lb[0]);
+  load_step(1, lb[1]);
+  load_step(2, lb[2]);
+  float4 nb[kTwRows * U1];
+  for (int stp = 0; stp < nsteps; ++stp) {
+    const int rs = r0 + kTwRows * stp;
+    const bool has_next = stp + 1 < nsteps;  // uniform over the workgroup
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < kTwRows; ++q) row_load(rs + 2 + q + 1, q * U1, nb);  // rows rs + 3, rs + 4
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int trow = rs + orow;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int D = 0; D < 9; ++D) {
+      const int dt = D / 3 - 1, dx = D % 3 - 1;
+      const int slot = (trow + dt + NSLOT) % NSLOT;
+      const float2* VB = vs + (size_t)(slot * HX + ox + 1 + dx) * 16 * kMfmaRS + i;
+      float2 bb[S];
+#pragma unroll
+      for (int sp = 0; sp < S; ++sp) bb[sp] = VB[(2 * sp + h) * kMfmaRS];
+#pragma unroll
+      for (int sp = 0; sp < S; ++sp) {
+        const z32 l = widen(lb[D % 3][sp]);
+        const bool ok = row_ok && (2 * sp + h < nc);
+        const float a_re = ok ? (upper ? l.im : l.re) : 0.f;
+        const float a_im = ok ? (upper ? l.re : -l.im) : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, bb[sp].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, bb[sp].y, acc, 0, 0, 0);
+      }
+      load_step(9 * stp + D + 3, lb[D % 3]);  // refill the slot just consumed (the next step's from D = 6)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // ---- epilogue: lane holds rhs j = i, dofs 8(r/4) + 4h + r%4 (Re in r, Im in r + 8)
+    const int j = i;
+    if (col_ok && trow < r1 && rhs0 + j < nrhs) {
+      const size_t ob = (size_t)(rhs0 + j) * n + (size_t)(trow * cx + x0 + ox) * nc;
+      const int lsc = ((trow + NSLOT) % NSLOT) * HX + ox + 1;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int dof = 8 * (r >> 2) + 4 * h + (r & 3);
+        if (dof >= nc) continue;
+        const z32 sum = lscale * mk<float>(acc[r], acc[r + 8]);  // exact: a power of two
+        const size_t o = ob + dof;
+        if (MODE == 0) {
+          y[o] = sum;
+        } else if (MODE == 1 || MODE == 3) {
+          const float2 t = vs[(lsc * 16 + dof) * kMfmaRS + j];
+          const z32 vi = mk<float>(t.x, t.y);
+          xacc[o] = MODE == 3 ? c * vi : xacc[o] + c * vi;
+          y[o] = vi - c * sum;
+        } else if (MODE == 4 || MODE == 5) {
+          const float2 t = vs[(lsc * 16 + dof) * kMfmaRS + j];
+          const z32 vi = mk<float>(t.x, t.y);
+          const z32 a = MODE == 5 ? c * vi : xacc[o] + c * vi;
+          xacc[o] = a + c2 * (vi - c * sum);
+        } else {
+          y[o] = aux[o] - sum;
+        }
+      }
+    }
+    if (!has_next) break;
+    __syncthreads();  // every wave is done with rows rs - 1 and rs
+#pragma unroll
+    for (int q = 0; q < kTwRows; ++q) row_store(rs + 3 + q, q * U1, nb);
+    __syncthreads();
+  }
+}
+
 template <int TX, int TT, int NW, int S, typename TL>
 void launch_coarse_mfma_t(const TL* L, float lscale, const z32* x, z32* y, int cx, int ct, int nc, int nrhs,
                           int mode, double c, double c2, z32* xacc, const z32* aux, hipStream_t st) {
@@ -1506,12 +1683,49 @@ void launch_coarse_mfma_s(const TL* L, float ls, const z32* x, z32* y, int cx, i
 // 4x4 tiles (8 waves, 152 KB of LDS) where they fill the chip; on small coarse
 // lattices 2x2 tiles (4 waves, 68 KB) give four times the workgroups (measured on
 // MI355X: 32^2 sites, 32 RHS: 14 us vs 35 us; 128^2 sites: 4x4 ahead by 9%).
+template <int S, typename TL>
+void launch_coarse_mfma_tw_s(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
+                             double c, double c2, z32* xacc, const z32* aux, hipStream_t st, int ns, int seg) {
+  const int nseg = (ct + seg - 1) / seg;
+  dim3 grid((unsigned)(ns * nseg), (unsigned)((nrhs + 31) / 32));
+  const int pairs = (nc % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0) ? 1 : 0;
+  with_mode(mode, [&](auto m) {
+    hipLaunchKernelGGL((k_coarse_mfma_tw<decltype(m)::v, S, TL>), grid, dim3(512), 0, st, L, x, y, cx, ct, nc, nrhs,
+                       (float)c, (float)c2, xacc, aux, pairs, ls, seg);
+  });
+  HIPCHECK(hipGetLastError());
+}
+
+// Rows per workgroup of the strip-walking kernel: about one workgroup per CU (256),
+// an even number; 0 when that leaves fewer than 8 rows per workgroup (the window's
+// two extra rows would then cost more than the overlap saves).
+int mfma_tw_seg(int cx, int ct) {
+  const int ns = (cx + 3) / 4;
+  const int nseg = std::max(1, 256 / ns);
+  int seg = (ct + nseg - 1) / nseg;
+  seg += seg & 1;
+  return seg >= 8 ? seg : 0;
+}
+
 template <typename TL>
 void launch_coarse_mfma_l(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
                           double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
   if (nc < 1 || nc > 16) throw Error(-1, "matrix-core coarse apply needs 1 <= nc <= 16");
   const long tiles44 = (long)((cx + 3) / 4) * ((ct + 3) / 4);
-  if (tiles44 < 256)
+  const int seg = tiles44 >= 256 ? mfma_tw_seg(cx, ct) : 0;
+  if (seg > 0) {
+    const int ns = (cx + 3) / 4;
+    switch ((nc + 1) / 2) {
+      case 1: launch_coarse_mfma_tw_s<1>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 2: launch_coarse_mfma_tw_s<2>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 3: launch_coarse_mfma_tw_s<3>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 4: launch_coarse_mfma_tw_s<4>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 5: launch_coarse_mfma_tw_s<5>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 6: launch_coarse_mfma_tw_s<6>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      case 7: launch_coarse_mfma_tw_s<7>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+      default: launch_coarse_mfma_tw_s<8>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st, ns, seg); break;
+    }
+  } else if (tiles44 < 256)
     launch_coarse_mfma_s<2, 2, 4>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);
   else
     launch_coarse_mfma_s<4, 4, 8>(L, ls, x, y, cx, ct, nc, nrhs, mode, c, c2, xacc, aux, st);

@@ -279,3 +279,74 @@ def test_mfma64_fp64_solve_many_rhs(hier):
         xs[name] = xh
     d = np.linalg.norm(xs["mfma"] - xs["valu"], axis=1) / np.linalg.norm(xs["valu"], axis=1)
     assert d.max() < 1e-6
+
+
+TW_CASES = [
+    # lx, lt, blocks, nvs, mass: level 1 large enough for the strip-walking kernel
+    (512, 256, [(4, 4)], [16], 0.05),  # 128x64x16: 32 strips, segments of 8 rows
+    (520, 264, [(4, 4)], [16], 0.05),  # 130x66x16: a last strip of 2 columns, segments of 10 rows, the last of 6
+]
+
+
+@pytest.mark.parametrize("case", range(len(TW_CASES)))
+def test_strip_walking_mfma_coarse_modes(case):
+    """The strip-walking matrix-core kernel (coarse lattices with at least 8 rows per
+    workgroup, rows of V staged under the MFMAs of the rows before) in every mode, on
+    FP32 and on FP16 links, against the oracle's Galerkin operator, and against the
+    vector-ALU kernels on the same links; 32 and 40 right-hand sides (a partial
+    second block of columns)."""
+    import torch
+
+    import paper_0710_3612_amd as smg
+
+    lx, lt, blocks, nvs, m = TW_CASES[case]
+    U = synth.links_from_angles(synth.metropolis_u1(lx, lt, 3.0, 5, 170 + case))
+    shapes = synth.level_shapes(lx, lt, blocks, nvs)
+    n0 = shapes[0][0] * shapes[0][1] * shapes[0][2]
+    vecs = synth.gaussian((nvs[0], n0), 1900 + case)
+    calib = synth.gaussian(n0, 1950 + case)
+    A = normal_matrix(U, m)
+    h = mg.hierarchy_from_vectors(A, (lx, lt, 2), blocks, [vecs], [calib], nu=4, omega=0.8, sa_scale=4 / 3,
+                                  coarsest="cg")
+    Ac = h.levels[1].A
+    n = Ac.shape[0]
+    sol = {}
+    try:
+        for name, mmin, store in (("tw", 1, smg.STORE_F32), ("tw16", 1, smg.STORE_F16), ("valu", 0, smg.STORE_F32),
+                                  ("valu16", 0, smg.STORE_F16)):
+            p = smg.make_params(lx, lt, m, levels=2, blocks=blocks, nv=nvs, mfma_min_rhs=mmin, operator_storage=store,
+                                coarsest=smg.COARSEST_CG)
+            sol[name] = smg.Solver(dev(U), p, vectors=dev(vecs.ravel()), calib=dev(calib))
+        for nrhs in (32, 40):
+            rng = np.random.default_rng(7000 + 10 * case + nrhs)
+            x = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+            aux = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+            acc0 = (rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))).astype(np.complex64)
+            coef = 0.37
+            x64 = x.astype(np.complex128)
+            Ax = (Ac @ x64.T).T
+            y0 = {}
+            for name in sol:
+                y0[name] = host(sol[name].level_op_f32(1, dev(x, np.complex64), mode=0)).reshape(nrhs, n)
+            for name, tol in (("tw", TOL32), ("tw16", TOL16)):
+                s = sol[name]
+                xt = dev(x, np.complex64)
+                xacc = dev(acc0, np.complex64)
+                y1 = host(s.level_op_f32(1, xt, mode=1, coef=coef, xacc=xacc)).reshape(nrhs, n)
+                a1 = host(xacc).reshape(nrhs, n)
+                y2 = host(s.level_op_f32(1, xt, mode=2, aux=dev(aux, np.complex64))).reshape(nrhs, n)
+                xacc3 = dev(acc0, np.complex64)
+                y3 = host(s.level_op_f32(1, xt, mode=3, coef=coef, xacc=xacc3)).reshape(nrhs, n)
+                a3 = host(xacc3).reshape(nrhs, n)
+                torch.cuda.synchronize()
+                assert colerr(y0[name], Ax) <= tol, (name, nrhs, "mode 0")
+                assert colerr(y1, x64 - coef * Ax) <= tol, (name, nrhs, "mode 1")
+                assert colerr(a1, acc0.astype(np.complex128) + coef * x64) <= TOL32, (name, nrhs, "mode 1 acc")
+                assert colerr(y2, aux.astype(np.complex128) - Ax) <= tol, (name, nrhs, "mode 2")
+                assert colerr(y3, x64 - coef * Ax) <= tol, (name, nrhs, "mode 3")
+                assert colerr(a3, coef * x64) <= TOL32, (name, nrhs, "mode 3 acc")
+            assert colerr(y0["tw"], y0["valu"].astype(np.complex128)) <= TOL32, nrhs
+            assert colerr(y0["tw16"], y0["valu16"].astype(np.complex128)) <= TOL32, nrhs
+    finally:
+        for s in sol.values():
+            s.close()
