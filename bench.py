@@ -307,7 +307,8 @@ def mrhs_leg(args, torch, smg, dev, U):
     nul = ctypes.c_void_p()
     dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), 100, stream)
     flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
-    mfma = dict(kernel=f"coarse operator on the matrix cores (k_coarse_mfma), {cx}x{ct} sites, nc={nc}, "
+    mfma = dict(kernel=f"coarse operator on the matrix cores (k_coarse_mfma_tw: strips of 4 sites, rows of V staged "
+                       f"under the MFMAs), {cx}x{ct} sites, nc={nc}, "
                        f"{MRHS_NRHS} RHS, FP32 arithmetic on the FP16 copy of the links (power-of-two scale)",
                 bound="mfma", achieved=flops / dur / 1e12, peak=157.3,
                 unit="TFLOP/s", frac=flops / dur / 1e12 / 157.3, avg_launch_us=dur * 1e6, flops_per_launch=flops)
@@ -970,7 +971,7 @@ def mfma_probe(reps, f16=False):
     px, py, nul = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p()
     dur = timed_events(lambda: lib.smg_level_op_f32(h, 1, 0, 0.0, px, py, nul, nul, MRHS_NRHS, sp), reps, stream)
     flops = 72.0 * nc * nc * MRHS_NRHS * cx * ct
-    print(json.dumps(dict(kernel="k_coarse_mfma", links="FP16 (scaled)" if f16 else "FP32", sites=cx * ct, nc=nc,
+    print(json.dumps(dict(kernel="k_coarse_mfma_tw", links="FP16 (scaled)" if f16 else "FP32", sites=cx * ct, nc=nc,
                           nrhs=MRHS_NRHS, avg_launch_us=dur * 1e6,
                           tflops=flops / dur / 1e12, frac=flops / dur / 1e12 / 157.3,
                           link_bytes=9 * nc * nc * (4 if f16 else 8) * cx * ct)))
