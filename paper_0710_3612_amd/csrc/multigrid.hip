@@ -1595,22 +1595,28 @@ __global__ void __launch_bounds__(512) k_coarse_mfma_tw(const TL* __restrict__ L
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-#pragma unroll
-    for (int D = 0; D < 9; ++D) {
+    // B operands of direction D from the window (read one direction ahead, so that the
+    // LDS round trip of the next direction runs under this direction's MFMAs)
+    auto read_b = [&](int D, float2* bb) {
       const int dt = D / 3 - 1, dx = D % 3 - 1;
       const int slot = (trow + dt + NSLOT) % NSLOT;
       const float2* VB = vs + (size_t)(slot * HX + ox + 1 + dx) * 16 * kMfmaRS + i;
-      float2 bb[S];
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) bb[sp] = VB[(2 * sp + h) * kMfmaRS];
+    };
+    float2 bb[2][S];
+    read_b(0, bb[0]);
+#pragma unroll
+    for (int D = 0; D < 9; ++D) {
+      if (D + 1 < 9) read_b(D + 1, bb[(D + 1) % 2]);
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
         const z32 l = widen(lb[D % 3][sp]);
         const bool ok = row_ok && (2 * sp + h < nc);
         const float a_re = ok ? (upper ? l.im : l.re) : 0.f;
         const float a_im = ok ? (upper ? l.re : -l.im) : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, bb[sp].x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, bb[sp].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, bb[D % 2][sp].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, bb[D % 2][sp].y, acc, 0, 0, 0);
       }
       load_step(9 * stp + D + 3, lb[D % 3]);  // refill the slot just consumed (the next step's from D = 6)
       __builtin_amdgcn_sched_barrier(0);
