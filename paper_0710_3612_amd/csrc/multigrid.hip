@@ -1417,22 +1417,28 @@ __global__ void __launch_bounds__(NW * 64) k_coarse_mfma(const TL* __restrict__ 
     if (k >= mine) continue;  // wave-uniform
     const int idx = w + k * NW;
     const int ox = idx % vx, ot = idx / vx;
-#pragma unroll
-    for (int D = 0; D < 9; ++D) {
+    // B operands of direction D, read one direction ahead (their LDS round trip runs
+    // under the previous direction's MFMAs)
+    auto read_b = [&](int D, float2* bo) {
       const int dt = D / 3 - 1, dx = D % 3 - 1;
       const int ls = (ot + 1 + dt) * HX + (ox + 1 + dx);
       const float2* VB = vs + (size_t)ls * 16 * kMfmaRS + i;
-      float2 b[S];
 #pragma unroll
-      for (int sp = 0; sp < S; ++sp) b[sp] = VB[(2 * sp + h) * kMfmaRS];
+      for (int sp = 0; sp < S; ++sp) bo[sp] = VB[(2 * sp + h) * kMfmaRS];
+    };
+    float2 b[2][S];
+    read_b(0, b[0]);
+#pragma unroll
+    for (int D = 0; D < 9; ++D) {
+      if (D + 1 < 9) read_b(D + 1, b[(D + 1) % 2]);
 #pragma unroll
       for (int sp = 0; sp < S; ++sp) {
         const z32 l = widen(lb[D % 3][sp]);
         const bool ok = row_ok && (2 * sp + h < nc);
         const float a_re = ok ? (upper ? l.im : l.re) : 0.f;
         const float a_im = ok ? (upper ? l.re : -l.im) : 0.f;
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b[sp].x, acc[k], 0, 0, 0);
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b[sp].y, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_re, b[D % 2][sp].x, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_im, b[D % 2][sp].y, acc[k], 0, 0, 0);
       }
       load_step(9 * k + D + 3, lb[D % 3]);  // refill the slot just consumed
       // keep the refill here: the scheduler would otherwise sink it next to its use
