@@ -1692,9 +1692,6 @@ void launch_coarse_mfma_s(const TL* L, float ls, const z32* x, z32* y, int cx, i
   }
 }
 
-// 4x4 tiles (8 waves, 152 KB of LDS) where they fill the chip; on small coarse
-// lattices 2x2 tiles (4 waves, 68 KB) give four times the workgroups (measured on
-// MI355X: 32^2 sites, 32 RHS: 14 us vs 35 us; 128^2 sites: 4x4 ahead by 9%).
 template <int S, typename TL>
 void launch_coarse_mfma_tw_s(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
                              double c, double c2, z32* xacc, const z32* aux, hipStream_t st, int ns, int seg) {
@@ -1719,6 +1716,12 @@ int mfma_tw_seg(int cx, int ct) {
   return seg >= 8 ? seg : 0;
 }
 
+// Strips (k_coarse_mfma_tw) where every workgroup gets at least 8 rows (128^2 coarse
+// sites and up: the staging of V runs under the MFMAs; 128^2 sites, 32 RHS, FP16
+// links: 142 us vs 167 us for 4x4 tiles); otherwise 4x4 tiles (8 waves, 152 KB of
+// LDS) where they fill the chip, and on small coarse lattices 2x2 tiles (4 waves,
+// 68 KB), which give four times the workgroups (32^2 sites, 32 RHS: 14 us vs 35 us).
+// All three give bitwise the same results.
 template <typename TL>
 void launch_coarse_mfma_l(const TL* L, float ls, const z32* x, z32* y, int cx, int ct, int nc, int nrhs, int mode,
                           double c, z32* xacc, const z32* aux, hipStream_t st, double c2) {
